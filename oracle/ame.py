@@ -1,0 +1,217 @@
+"""Density-matrix solvers of the adiabatic master equation (FP64 oracle).
+
+TEST INFRASTRUCTURE: only tests/, the smoke check and the bench's cpu_baseline
+leg may import anything under oracle/.
+
+Three independent routes to the AME of Sec. II (eqs. ME2-H, ME2-L, Lindblad2,
+dissdiag) with the Lamb shift set to zero (the paper gives no S(w)):
+
+split_step   -- the exact mean of the trajectory process on the same grid:
+                rho <- O_g rho O_g^T, then rho <- exp(L_g dt) rho with L_g the
+                Lindbladian frozen at s_g, written in the eigenbasis where it
+                decouples: populations evolve with the rate matrix
+                W[a, b] = sum_i R[i, b, a] (b -> a), coherences a != b decay as
+                exp(-i(e_a - e_b) dt - (Gamma_a + Gamma_b) dt / 2
+                    + gamma(0) sum_i z_i[a,a] z_i[b,b] dt).
+                (Averaging trajectories gives the master equation, App. B.)
+liouvillian  -- the Lindbladian as an explicit n^2 x n^2 matrix built from the
+                operators L_{i,w} of eq. Lindblad2 grouped by Bohr frequency
+                (pairs a != b kept as separate operators, the a == b terms
+                of each qubit form one w = 0 operator) for small checks.
+continuous   -- the lab-frame N x N equation integrated with an adaptive
+                Runge-Kutta (DOP853), rebuilding the eigenbasis and the jump
+                operators from numpy eigh at every right-hand-side call.
+"""
+from __future__ import annotations
+
+import numpy as np
+import scipy.linalg as sla
+from scipy.integrate import solve_ivp
+
+from . import model
+
+
+def rate_matrix(T) -> np.ndarray:
+    """W[a, b]: transition rate b -> a (a != b); columns sum to zero."""
+    W = T.R.sum(axis=0).T.copy()
+    np.fill_diagonal(W, 0.0)
+    W -= np.diag(W.sum(axis=0))
+    return W
+
+
+def coherence_factor(T, inst, dt: float) -> np.ndarray:
+    g0 = float(model.gamma_ohmic(0.0, inst.eta, inst.omega_c, inst.T))
+    E, Gam, zd = T.E, T.Gamma, T.zdiag
+    cross = g0 * (zd.T @ zd)                      # gamma(0) sum_i z_aa z_bb
+    rate = (-1j * (E[:, None] - E[None, :]) - 0.5 * (Gam[:, None] + Gam[None, :]) + cross)
+    return np.exp(rate * dt)
+
+
+def step_map(rho: np.ndarray, T, inst, dt: float) -> np.ndarray:
+    """exp(L_g dt) applied to rho in the eigenbasis of grid g."""
+    p = np.real(np.diag(rho)).copy()
+    p = sla.expm(rate_matrix(T) * dt) @ p
+    out = rho * coherence_factor(T, inst, dt)
+    out[np.diag_indices_from(out)] = p
+    return out
+
+
+def split_step(tables, inst, n_grid=None, keep_rho=False):
+    """P_GS(s_g) for g = 0..M-1 (and optionally the final rho) of the split-step AME."""
+    M = n_grid or inst.n_grid
+    dt = inst.t_f / (M - 1)
+    P = np.zeros(M)
+    P[0] = 1.0
+    rho = None
+    for T in tables:
+        if T.g == 1:
+            rho = np.outer(T.cinit, T.cinit).astype(np.complex128)
+        else:
+            rho = T.O @ rho @ T.O.T
+        rho = step_map(rho, T, inst, dt)
+        P[T.g] = float(np.real(np.trace(rho[:T.gs, :T.gs])))
+    return (P, rho) if keep_rho else P
+
+
+def expected_jumps(tables, inst, n_grid=None):
+    """Mean number of jumps per trajectory by kind (relax, excite, omega = 0).
+
+    Sec. III: E[dN_i] = <A_i^dag A_i> dt, so the expected count of a channel is
+    the time integral of tr(A_i rho A_i^dag).  For a != b channels that is
+    R[i, b, a] rho_bb; for the omega = 0 operator of qubit i it is
+    gamma(0) sum_b z_i[b, b]^2 rho_bb.  Within a step the populations follow
+    expm(W tau) p, integrated exactly with an augmented matrix exponential.
+    """
+    M = n_grid or inst.n_grid
+    dt = inst.t_f / (M - 1)
+    out = np.zeros(3)
+    rho = None
+    for T in tables:
+        if T.g == 1:
+            rho = np.outer(T.cinit, T.cinit).astype(np.complex128)
+        else:
+            rho = T.O @ rho @ T.O.T
+        n = len(T.E)
+        p = np.real(np.diag(rho))
+        aug = np.zeros((n + 1, n + 1))
+        aug[:n, :n] = rate_matrix(T)
+        aug[:n, n] = p
+        ip = sla.expm(aug * dt)[:n, n]            # integral over the step of p(tau)
+        off = T.R.copy()
+        for i in range(off.shape[0]):
+            np.fill_diagonal(off[i], 0.0)
+        flow = off.sum(axis=0) * ip[:, None]        # [b, a] expected b -> a jumps
+        lower = T.E[None, :] <= T.E[:, None]        # target energy <= source energy
+        out[0] += flow[lower].sum()
+        out[1] += flow[~lower].sum()
+        out[2] += sum(T.R[i].diagonal() @ ip for i in range(T.R.shape[0]))
+        rho = step_map(rho, T, inst, dt)
+    return out
+
+
+def lindblad_operators(T, inst, tol: float = 1e-9):
+    """Jump operators (already scaled by sqrt(gamma)) in the eigenbasis of grid g.
+
+    eq. Lindblad2 with A_alpha = sz_alpha: for each qubit, terms with equal
+    Bohr frequency belong to one operator.  Distinct a != b pairs are kept
+    apart (generic spectra never share a non-zero Bohr frequency); the a == b
+    terms share w = 0 and are summed into one diagonal operator.
+    """
+    n = len(T.E)
+    ops = []
+    g0 = float(model.gamma_ohmic(0.0, inst.eta, inst.omega_c, inst.T))
+    for i in range(inst.n_qubits):
+        z = T.z[i]
+        for a in range(n):
+            for b in range(n):
+                if a == b:
+                    continue
+                w = T.E[b] - T.E[a]
+                gam = float(model.gamma_ohmic(w, inst.eta, inst.omega_c, inst.T))
+                L = np.zeros((n, n))
+                L[a, b] = z[a, b]
+                ops.append(np.sqrt(gam) * L)
+        ops.append(np.sqrt(g0) * np.diag(np.diag(z)))
+    return ops
+
+
+def liouvillian(T, inst) -> np.ndarray:
+    """Superoperator of drho/dt = -i[H, rho] + sum_k (L rho L^+ - {L^+L, rho}/2), column-stacked."""
+    n = len(T.E)
+    I = np.eye(n)
+    H = np.diag(T.E).astype(np.complex128)
+    Lsup = -1j * (np.kron(I, H) - np.kron(H.T, I))
+    for L in lindblad_operators(T, inst):
+        LdL = L.conj().T @ L
+        Lsup += np.kron(L.conj(), L) - 0.5 * (np.kron(I, LdL) + np.kron(LdL.T, I))
+    return Lsup
+
+
+def continuous(inst, s_eval, rtol=1e-10, atol=1e-12):
+    """Lab-frame AME integrated in t; returns instantaneous ground-state populations at s_eval."""
+    nq, N = inst.n_qubits, inst.dim
+    HX = model.hx_dense(nq)
+    HZ = model.hz_dense(inst.h, inst.J)
+    SZ = [model.sz_diag(i, nq) for i in range(nq)]
+    g0 = float(model.gamma_ohmic(0.0, inst.eta, inst.omega_c, inst.T))
+
+    def H_at(t):
+        a, b = model.schedule(inst.A_ctrl, inst.B_ctrl, t / inst.t_f)
+        return a * HX + b * HZ
+
+    def rhs(t, y):
+        rho = y.reshape(N, N)
+        E, V = np.linalg.eigh(H_at(t))
+        rt = V.T @ rho @ V                      # eigenbasis
+        d = -1j * (E[:, None] - E[None, :]) * rt
+        omega = E[None, :] - E[:, None]
+        gam = model.gamma_ohmic(omega, inst.eta, inst.omega_c, inst.T)
+        np.fill_diagonal(gam, g0)
+        p = np.real(np.diag(rt))
+        for i in range(nq):
+            z = V.T @ (SZ[i][:, None] * V)
+            R = gam * z * z                      # R[a, b]: rate b -> a (diag: g0 z_bb^2)
+            zd = np.diag(z)
+            # pair channels a != b: A = sqrt(R_ab)|a><b|
+            Roff = R.copy()
+            np.fill_diagonal(Roff, 0.0)
+            gain = Roff @ p
+            loss = Roff.sum(axis=0)              # sum_a R[a, b] for each b
+            d += np.diag(gain)
+            d -= 0.5 * (loss[:, None] + loss[None, :]) * rt
+            # omega = 0 channel: D = sqrt(g0) diag(z)
+            d += g0 * (zd[:, None] * rt * zd[None, :]) - 0.5 * g0 * (zd[:, None] ** 2 + zd[None, :] ** 2) * rt
+        return (V @ d @ V.T).ravel()
+
+    E0, V0 = np.linalg.eigh(H_at(0.0))
+    psi0 = V0[:, 0].astype(np.complex128)
+    y0 = np.outer(psi0, psi0.conj()).ravel()
+    t_eval = np.asarray(s_eval) * inst.t_f
+    sol = solve_ivp(rhs, (0.0, inst.t_f), y0, method="DOP853", t_eval=t_eval, rtol=rtol, atol=atol)
+    out = []
+    for t, y in zip(sol.t, sol.y.T):
+        E, V = np.linalg.eigh(H_at(t))
+        rho = y.reshape(N, N)
+        out.append(float(np.real(V[:, 0] @ rho @ V[:, 0])))
+    return np.array(out)
+
+
+def closed_system_lab(inst, s_eval, rtol=1e-11, atol=1e-13):
+    """Schrodinger evolution in the lab frame; instantaneous ground-state population at s_eval."""
+    nq = inst.n_qubits
+    HX = model.hx_dense(nq)
+    HZ = model.hz_dense(inst.h, inst.J)
+
+    def H_at(t):
+        a, b = model.schedule(inst.A_ctrl, inst.B_ctrl, t / inst.t_f)
+        return a * HX + b * HZ
+
+    E0, V0 = np.linalg.eigh(H_at(0.0))
+    psi0 = V0[:, 0].astype(np.complex128)
+    sol = solve_ivp(lambda t, y: -1j * (H_at(t) @ y), (0.0, inst.t_f), psi0, method="DOP853",
+                    t_eval=np.asarray(s_eval) * inst.t_f, rtol=rtol, atol=atol)
+    out = []
+    for t, y in zip(sol.t, sol.y.T):
+        E, V = np.linalg.eigh(H_at(t))
+        out.append(float(np.abs(V[:, 0] @ y) ** 2))
+    return np.array(out)

@@ -1,0 +1,100 @@
+"""Model layer of the FP64 oracle: Ising Hamiltonian, schedule, Ohmic bath.
+
+TEST INFRASTRUCTURE: only tests/, the smoke check and the bench's cpu_baseline
+leg may import anything under oracle/.
+
+Sources in the paper:
+  * transverse-field Ising Hamiltonian H_S = A H_X + B H_Z  (Sec. V, eq. H_S)
+  * independent bosonic baths coupled through sz_i          (Sec. V, eq. SBm)
+  * Ohmic rates gamma(w) = 2 pi g^2 w e^{-|w|/wc} / (1 - e^{-beta w})  (Sec. V)
+  * KMS detailed balance gamma(-w) = e^{-beta w} gamma(w)   (Sec. II, eq. KMS)
+Field-sign reading: H_Z = +sum h_i sz_i + sum_{i<j} J_ij sz_i sz_j (the paper
+writes -sum h sz; the two differ by h -> -h).
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+import scipy.sparse as sp
+
+SX = np.array([[0.0, 1.0], [1.0, 0.0]])
+SZ = np.array([[1.0, 0.0], [0.0, -1.0]])
+I2 = np.eye(2)
+
+
+def pauli_on(op: np.ndarray, i: int, n: int) -> np.ndarray:
+    """Dense 2^n x 2^n operator acting with `op` on qubit i (bit i of the index)."""
+    # np.kron puts its first factor on the most significant bits.
+    return np.kron(np.kron(np.eye(1 << (n - 1 - i)), op), np.eye(1 << i))
+
+
+def pauli_on_sparse(op: np.ndarray, i: int, n: int):
+    return sp.kron(sp.kron(sp.identity(1 << (n - 1 - i), format="csr"), sp.csr_matrix(op)),
+                   sp.identity(1 << i, format="csr"), format="csr")
+
+
+def hx_dense(n: int) -> np.ndarray:
+    return -sum(pauli_on(SX, i, n) for i in range(n))
+
+
+def hz_dense(h: np.ndarray, J: np.ndarray) -> np.ndarray:
+    n = len(h)
+    H = sum(h[i] * pauli_on(SZ, i, n) for i in range(n))
+    for i in range(n):
+        for j in range(i + 1, n):
+            if J[i, j] != 0.0:
+                H = H + J[i, j] * (pauli_on(SZ, i, n) @ pauli_on(SZ, j, n))
+    return H
+
+
+def hx_sparse(n: int):
+    return -sum(pauli_on_sparse(SX, i, n) for i in range(n))
+
+
+def hz_diag(h: np.ndarray, J: np.ndarray) -> np.ndarray:
+    """Diagonal of H_Z in the computational basis (sz eigenvalue +1 for bit 0)."""
+    n = len(h)
+    x = np.arange(1 << n)
+    sig = 1.0 - 2.0 * ((x[None, :] >> np.arange(n)[:, None]) & 1)   # [n, N]
+    e = (h[:, None] * sig).sum(axis=0)
+    for i in range(n):
+        for j in range(i + 1, n):
+            if J[i, j] != 0.0:
+                e = e + J[i, j] * sig[i] * sig[j]
+    return e
+
+
+def sz_diag(i: int, n: int) -> np.ndarray:
+    x = np.arange(1 << n)
+    return 1.0 - 2.0 * ((x >> i) & 1)
+
+
+def schedule(A_ctrl: np.ndarray, B_ctrl: np.ndarray, s):
+    """Piecewise-linear A(s), B(s) through control points at s_j = j/(n_ctrl - 1)."""
+    A_ctrl = np.asarray(A_ctrl, dtype=np.float64)
+    B_ctrl = np.asarray(B_ctrl, dtype=np.float64)
+    knots = np.linspace(0.0, 1.0, len(A_ctrl))
+    return np.interp(s, knots, A_ctrl), np.interp(s, knots, B_ctrl)
+
+
+def hamiltonian_dense(inst, s: float) -> np.ndarray:
+    a, b = schedule(inst.A_ctrl, inst.B_ctrl, s)
+    return a * hx_dense(inst.n_qubits) + b * hz_dense(inst.h, inst.J)
+
+
+def hamiltonian_sparse(inst, s: float):
+    a, b = schedule(inst.A_ctrl, inst.B_ctrl, s)
+    return (a * hx_sparse(inst.n_qubits) + sp.diags(b * hz_diag(inst.h, inst.J))).tocsr()
+
+
+def gamma_ohmic(omega, eta: float, omega_c: float, T: float):
+    """Ohmic bath correlation function (Sec. V) with g^2 = eta; gamma(0) is its limit 2 pi eta T."""
+    omega = np.asarray(omega, dtype=np.float64)
+    beta = 1.0 / T
+    out = np.empty_like(omega)
+    nz = omega != 0.0
+    w = omega[nz]
+    out[nz] = 2.0 * math.pi * eta * w * np.exp(-np.abs(w) / omega_c) / (-np.expm1(-beta * w))
+    out[~nz] = 2.0 * math.pi * eta / beta
+    return out

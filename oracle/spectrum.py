@@ -1,0 +1,180 @@
+"""Spectral layer of the FP64 oracle: instantaneous eigenbasis and AME tables.
+
+TEST INFRASTRUCTURE: only tests/, the smoke check and the bench's cpu_baseline
+leg may import anything under oracle/.
+
+What is computed, per grid point s_g = g/(M-1), g = 0..M-1, t = s t_f:
+
+* eigenpairs of H(s_g) in ascending order (numpy eigh for dense sizes, scipy
+  eigsh for the 2^16 gadget), the "instantaneous energy eigenstates" of
+  Sec. II (eq. Lindblad2);
+* clusters: maximal runs of consecutive levels whose gaps are below deg_tol.
+  Inside a cluster the basis is rotated to the eigenbasis of the projected
+  diagonal operator W = diag(x) (x = computational basis index), ordered by
+  its eigenvalue, and the energies become Rayleigh quotients.  This makes the
+  basis reproducible when levels are (numerically) degenerate; at s = 1 it is
+  the computational basis.  Reading of the paper's Kronecker delta over Bohr
+  frequencies: a != b pairs are separate channels, the a == b terms of each
+  qubit form the single omega = 0 operator;
+* column signs: the first component whose magnitude is within 1e-9 of the
+  column maximum is made positive (a gauge choice; no physical result
+  depends on it);
+* truncation to the n lowest levels;
+* per grid g >= 1 the tables used by the step that ends at s_g (generator
+  frozen at the right end point):
+    O_g     = polar factor of V_g^T V_{g-1}     (basis change, g >= 2)
+    c_init  = V_1^T psi_0 / |V_1^T psi_0|      (g = 1; psi_0 = ground state of H(s_0))
+    z_g[i,a,b] = <a| sz_i |b>                   (eq. Lindblad2 matrix elements)
+    R_g[i,b,a] = gamma(e_b - e_a) z^2 (a != b), gamma(0) z_bb^2 (a == b)
+                 = |A_i psi|^2 per unit population of level b (eq. Aired, eq. 12)
+    Gamma_g[b] = sum_{i,a} R_g[i,b,a]          (diagonal of sum_i A_i^dag A_i, eq. Heff)
+    d_g[b]     = exp(-i e_b dt - Gamma_b dt / 2)
+    leak_g     = 1 - sigma_min(V_g^T V_{g-1})^2  (diagnostic of truncation)
+"""
+from __future__ import annotations
+
+import dataclasses
+from typing import Iterator, Optional
+
+import numpy as np
+import scipy.sparse.linalg as spla
+
+from . import model
+
+
+@dataclasses.dataclass
+class GridTables:
+    g: int
+    s: float
+    E: np.ndarray            # [n]
+    gs: int                  # size of the ground cluster
+    O: Optional[np.ndarray]  # [n, n] (None at g = 1)
+    cinit: Optional[np.ndarray]  # [n] (g = 1 only)
+    z: np.ndarray            # [nq, n, n]
+    R: np.ndarray            # [nq, n(b), n(a)]
+    Gamma: np.ndarray        # [n]
+    zdiag: np.ndarray        # [nq, n]
+    d: np.ndarray            # [n] complex
+    leak: float
+    V: Optional[np.ndarray] = None   # [N, n] (kept only on request)
+
+
+def clusters(E: np.ndarray, deg_tol: float):
+    """List of (start, stop) index ranges of consecutive levels closer than deg_tol."""
+    out = []
+    a0 = 0
+    for a in range(1, len(E) + 1):
+        if a == len(E) or E[a] - E[a - 1] >= deg_tol:
+            out.append((a0, a))
+            a0 = a
+    return out
+
+
+def canonicalize(E: np.ndarray, V: np.ndarray, deg_tol: float):
+    """Rotate degenerate clusters to the W = diag(x) eigenbasis; fix column signs.
+
+    Returns (E, V, clusters) with the clusters found before the rotation.
+    """
+    E = E.copy()
+    V = V.copy()
+    w = np.arange(V.shape[0], dtype=np.float64)
+    cl = clusters(E, deg_tol)
+    for a0, a1 in cl:
+        if a1 - a0 < 2:
+            continue
+        Vc = V[:, a0:a1]
+        G = Vc.T @ (w[:, None] * Vc)
+        _, Q = np.linalg.eigh(0.5 * (G + G.T))
+        V[:, a0:a1] = Vc @ Q
+        E[a0:a1] = (Q * Q).T @ E[a0:a1]
+    mags = np.abs(V)
+    mx = mags.max(axis=0)
+    first = np.argmax(mags >= (1.0 - 1e-9) * mx[None, :], axis=0)
+    sgn = np.sign(V[first, np.arange(V.shape[1])])
+    sgn[sgn == 0] = 1.0
+    return E, V * sgn[None, :], cl
+
+
+def eigen(inst, s: float, n_keep: int, deg_tol: float, guard: int = 16):
+    """Lowest n_keep canonical eigenpairs of H(s) plus the ground-cluster size."""
+    N = inst.dim
+    if N <= 4096:
+        E, V = np.linalg.eigh(model.hamiltonian_dense(inst, s))
+    else:
+        k = min(N - 2, n_keep + guard)
+        H = model.hamiltonian_sparse(inst, s)
+        E, V = spla.eigsh(H, k=k, which="SA", tol=1e-13, v0=np.ones(N) / np.sqrt(N))
+        o = np.argsort(E)
+        E, V = E[o], V[:, o]
+    E, V, cl = canonicalize(E, V, deg_tol)
+    gs = cl[0][1] - cl[0][0]
+    return E[:n_keep], V[:, :n_keep], gs
+
+
+def polar(M: np.ndarray):
+    U, S, Wt = np.linalg.svd(M)
+    return U @ Wt, S
+
+
+def grid_tables(inst, E: np.ndarray, V: np.ndarray, dt: float):
+    nq = inst.n_qubits
+    n = len(E)
+    z = np.empty((nq, n, n))
+    for i in range(nq):
+        z[i] = V.T @ (model.sz_diag(i, nq)[:, None] * V)
+    omega = E[None, :] - E[:, None]                      # omega[a, b] = E_b - E_a
+    gam = model.gamma_ohmic(omega, inst.eta, inst.omega_c, inst.T)
+    np.fill_diagonal(gam, model.gamma_ohmic(0.0, inst.eta, inst.omega_c, inst.T))
+    R = np.empty((nq, n, n))
+    for i in range(nq):
+        R[i] = (gam * z[i] ** 2).T                        # R[i, b, a]
+    Gamma = R.sum(axis=(0, 2))
+    zdiag = np.stack([np.diag(z[i]) for i in range(nq)])
+    d = np.exp(-1j * E * dt - 0.5 * Gamma * dt)
+    return z, R, Gamma, zdiag, d
+
+
+def n_steps_dt(inst, n_grid: int):
+    return n_grid - 1, inst.t_f / (n_grid - 1)
+
+
+def table_stream(inst, n_grid: Optional[int] = None, n_levels: Optional[int] = None,
+                 deg_tol: float = 1e-8, keep_V: bool = False,
+                 grids: Optional[set] = None) -> Iterator[GridTables]:
+    """Yield GridTables for g = 1..M-1 in order (or only those in `grids`, still in order)."""
+    M = n_grid or inst.n_grid
+    n = n_levels or inst.levels
+    dt = inst.t_f / (M - 1)
+    E0, V0, gs0 = eigen(inst, 0.0, max(n, 1), deg_tol)
+    if gs0 != 1:
+        raise ValueError("ground state of H(s=0) is degenerate; initial state undefined")
+    psi0 = V0[:, 0]
+    Vprev = None
+    for g in range(1, M):
+        s = g / (M - 1)
+        need_prev = grids is not None and (g + 1) in grids
+        if grids is not None and g not in grids and not need_prev:
+            Vprev = None
+            continue
+        E, V, gs = eigen(inst, s, n, deg_tol)
+        if g == 1:
+            c = V.T @ psi0
+            leak = 1.0 - float(c @ c)
+            cinit, O = c / np.linalg.norm(c), None
+        else:
+            if Vprev is None:
+                _, Vp, _ = eigen(inst, (g - 1) / (M - 1), n, deg_tol)
+            else:
+                Vp = Vprev
+            O, S = polar(V.T @ Vp)
+            leak = 1.0 - float(S.min()) ** 2
+            cinit = None
+        z, R, Gamma, zdiag, d = grid_tables(inst, E, V, dt)
+        Vprev = V
+        if grids is None or g in grids:
+            yield GridTables(g=g, s=s, E=E, gs=gs, O=O, cinit=cinit, z=z, R=R, Gamma=Gamma,
+                             zdiag=zdiag, d=d, leak=leak, V=V if keep_V else None)
+
+
+def all_tables(inst, **kw):
+    return list(table_stream(inst, **kw))
