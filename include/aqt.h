@@ -1,0 +1,164 @@
+/*
+ * aqt.h -- C ABI of libaqt, an MI355X (gfx950) engine for quantum-jump
+ * trajectories of the adiabatic master equation (AME).
+ *
+ * Method: Yip, Albash, Lidar, "Quantum trajectories for time-dependent
+ * adiabatic master equations".  The AME in Lindblad form with operators in the
+ * instantaneous eigenbasis (Sec. II, eqs. ME2-H, ME2-L, Lindblad2) is unravelled
+ * into jump trajectories (Sec. III, eqs. Heff, sse, jump) and simulated with the
+ * waiting-time procedure (Sec. IV; validity App. C).  Model: transverse-field
+ * Ising system with independent Ohmic baths coupled through sz_i (Sec. V).
+ *
+ * Conventions (all calls):
+ *   - Units: hbar = k_B = 1; energies, rates, temperature in rad/ns; time in ns.
+ *   - H(s) = A(s) (-sum_i sx_i) + B(s) (sum_i h_i sz_i + sum_{i<j} J_ij sz_i sz_j),
+ *     bit i of a basis index is qubit i, sz_i|x> = (1 - 2 bit_i(x)) |x>.
+ *     (The paper's field term is -sum h sz; pass -h for that convention.)
+ *   - Ohmic rates gamma(w) = 2 pi eta w e^{-|w|/wc} / (1 - e^{-w/T}), gamma(0) = 2 pi eta T.
+ *   - Grid s_g = g/(M-1), g = 0..M-1, t = s t_f, dt = t_f/(M-1).  The step from
+ *     s_{g-1} to s_g uses the generator frozen at s_g; the basis change between
+ *     grid points is the polar factor of V_g^T V_{g-1}.
+ *   - Errors: a negative aqt_status; aqt_last_error() returns a message that
+ *     stays valid until the next call on the same context.  On AQT_EINVAL and
+ *     AQT_ESTATE nothing is written to outputs.
+ *   - Ownership: the library owns the context and every precomputed table; the
+ *     caller owns every output buffer.  Host input arrays are copied during the
+ *     call.  Device pointers must be on the context's device.
+ *   - Stream order: device work is enqueued on the context's stream and the
+ *     calls return without synchronising unless stated; the caller synchronises.
+ *   - One context per host thread at a time; contexts are independent.
+ */
+#ifndef AQT_H
+#define AQT_H
+
+#include <stdint.h>
+
+#if defined(__GNUC__) || defined(__clang__)
+#define AQT_API __attribute__((visibility("default")))
+#else
+#define AQT_API
+#endif
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct aqt_ctx aqt_ctx;
+
+typedef enum {
+  AQT_OK = 0,
+  AQT_EINVAL = -1,     /* an argument is out of range or a pointer is NULL          */
+  AQT_ENOMEM = -2,     /* device or host allocation failed                          */
+  AQT_ESTATE = -3,     /* call order: set_* -> precompute (or set_tables) -> run     */
+  AQT_EHIP = -4,       /* a HIP runtime call failed                                 */
+  AQT_ENUMERIC = -5,   /* eigensolver did not converge, degenerate initial state... */
+  AQT_ECAPACITY = -6   /* jump records overflowed; observables are still valid      */
+} aqt_status;
+
+typedef enum {
+  AQT_FP64 = 0,        /* FP64 state, FP64 MFMA overlap GEMM                        */
+  AQT_FP32 = 1,        /* FP32 state, FP32 MFMA, FP32 accumulate                    */
+  AQT_BF16 = 2         /* FP32 state; overlap GEMM on BF16 MFMA with hi/lo splits of
+                          both operands (three products) and the identity split
+                          O = I + Delta; FP32 accumulate                             */
+} aqt_precision;
+
+enum { AQT_KIND_RELAX = 0, AQT_KIND_EXCITE = 1, AQT_KIND_DEPHASE = 2 };
+
+/* One recorded jump (24 bytes).  from_level b -> to_level a in the eigenbasis of
+ * grid step+1; a == b is the omega = 0 operator of `qubit`.  kind: relax if
+ * e_a <= e_b, excite otherwise, dephase for a == b. */
+typedef struct {
+  double t;            /* ns */
+  int32_t step;        /* step index k: the step from s_k to s_{k+1} */
+  int16_t qubit;
+  int16_t kind;
+  int32_t from_level;
+  int32_t to_level;
+} aqt_jump;
+
+typedef struct {
+  int32_t precision;        /* aqt_precision */
+  int32_t record_capacity;  /* jump records kept per trajectory (0: none)            */
+  int64_t n_traj;           /* K >= 1                                               */
+  uint64_t seed;            /* Philox key word 0                                    */
+  uint64_t instance_id;     /* Philox key word 1                                    */
+  uint64_t traj_offset;     /* trajectory ids are traj_offset .. traj_offset+K-1     */
+  int32_t tile;             /* trajectories per workgroup, multiple of 16 (0: auto)  */
+  int32_t reserved;
+} aqt_run_params;
+
+/* Device output buffers of aqt_run (any pointer may be NULL to skip it). */
+typedef struct {
+  double* pgs_sum;          /* [M] sum over trajectories of the ground-cluster population
+                               after each grid point (index 0 = initial state)        */
+  double* pgs_sumsq;        /* [M] sum of squares (standard error, Sec. VI eq. stderror) */
+  int64_t* jump_totals;     /* [3] relax, excite, dephase; accumulated (+=)            */
+  int32_t* jump_count;      /* [K] jumps per trajectory (may exceed record_capacity)   */
+  aqt_jump* jumps;          /* [K * record_capacity], trajectory-major                 */
+  int32_t* net_gs;          /* [K] jumps into minus jumps out of the ground cluster    */
+  int64_t* net_hist;        /* [hist_hi - hist_lo + 1] histogram of net_gs; accumulated,
+                               values outside the range are clamped to the end bins   */
+  int32_t hist_lo, hist_hi;
+  double* final_state;      /* [K * n * 2] final amplitudes (re, im), trajectory-major  */
+} aqt_outputs;
+
+/* Create a context on HIP device `device`; `hip_stream` is a hipStream_t or NULL
+ * for the default stream.  *out receives the context (NULL on failure). */
+AQT_API aqt_status aqt_create(aqt_ctx** out, int device, void* hip_stream);
+AQT_API void aqt_destroy(aqt_ctx* ctx);
+AQT_API const char* aqt_last_error(const aqt_ctx* ctx);
+AQT_API int aqt_version(void);
+
+/* Sec. V, eq. H_S: n_qubits in [1, 16]; h[n_qubits]; J[n_qubits * n_qubits] row-major,
+ * only entries with i < j are read.  Host arrays. */
+AQT_API aqt_status aqt_set_hamiltonian(aqt_ctx* ctx, int n_qubits, const double* h, const double* J);
+
+/* Annealing schedule: t_f > 0 ns; A(s), B(s) piecewise linear through n_ctrl >= 2
+ * control points at s_j = j/(n_ctrl-1), rad/ns.  Host arrays. */
+AQT_API aqt_status aqt_set_schedule(aqt_ctx* ctx, double t_f, int n_ctrl, const double* A_ctrl,
+                            const double* B_ctrl);
+
+/* Ohmic bath (Sec. V): eta >= 0 (the paper's g^2), omega_c > 0, T > 0, rad/ns. */
+AQT_API aqt_status aqt_set_bath(aqt_ctx* ctx, double eta, double omega_c, double T);
+
+/* FP64 eigensystem and AME tables on the GPU for grid points g = 0..n_grid-1
+ * (Sec. II eq. Lindblad2, Sec. III eqs. Aired, Heff): lowest n_levels eigenpairs
+ * (n_levels <= 256; == 2^n_qubits for the full spectrum), clusters closer than
+ * deg_tol rotated to a canonical basis, overlaps, sz matrix elements, rates,
+ * decay and phases.  Synchronises the stream.  AQT_ENUMERIC if the ground state
+ * of H(0) is degenerate or the eigensolver fails. */
+AQT_API aqt_status aqt_precompute(aqt_ctx* ctx, int n_grid, int n_levels, double deg_tol);
+
+/* Load externally computed tables instead of aqt_precompute (same meaning as the
+ * tables aqt_precompute builds; host arrays, FP64, row-major):
+ *   E[n_grid*n]; gs[n_grid] ground-cluster sizes; O[n_grid*n*n] with O[g] the
+ *   polar overlap into grid g (g >= 2, others ignored); cinit[n] initial state in
+ *   the grid-1 basis; R[n_grid*nq*n*n] as R[g][i][b][a] (rate of b -> a through
+ *   qubit i, a == b the omega = 0 weight gamma(0) z_bb^2); zdiag[n_grid*nq*n].
+ * Decay rates and phases are derived from them on the GPU.  Synchronises. */
+AQT_API aqt_status aqt_set_tables(aqt_ctx* ctx, int n_grid, int n_levels, const double* E,
+                          const int32_t* gs, const double* O, const double* cinit,
+                          const double* R, const double* zdiag);
+
+/* Copy tables back to host arrays (any may be NULL): E[M*n], gs[M], O[M*n*n],
+ * cinit[n], R[M*nq*n*n], zdiag[M*nq*n], Gamma[M*n], leak[M].  Synchronises. */
+AQT_API aqt_status aqt_get_tables(aqt_ctx* ctx, double* E, int32_t* gs, double* O, double* cinit,
+                          double* R, double* zdiag, double* Gamma, double* leak);
+
+/* Sizes of the loaded tables: n_grid, n_levels, n_qubits (any may be NULL). */
+AQT_API aqt_status aqt_get_dims(aqt_ctx* ctx, int32_t* n_grid, int32_t* n_levels, int32_t* n_qubits);
+
+/* Run K trajectories (Sec. IV waiting-time procedure, App. B jump-type law
+ * eq. Pi(t)) through all grid points; stream-ordered.  Random draws: Philox4x64-10
+ * with key (seed, instance_id) and counter (trajectory id, draw >> 2, 0, 0);
+ * draw 0 is the first threshold, jump m uses 3m+1, 3m+2, 3m+3.
+ * Never synchronises.  Records beyond record_capacity are dropped; jump_count
+ * still holds the true number of jumps of each trajectory. */
+AQT_API aqt_status aqt_run(aqt_ctx* ctx, const aqt_run_params* params, const aqt_outputs* out);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* AQT_H */

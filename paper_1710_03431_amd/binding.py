@@ -1,0 +1,244 @@
+"""ctypes binding of libaqt (include/aqt.h): argument marshalling only.
+
+Every numerical step runs in the HIP library; PyTorch supplies device memory
+and the stream.  Importing this module loads the in-tree libaqt.so and raises
+if it is missing -- there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Optional
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libaqt.so")
+
+AQT_OK, AQT_EINVAL, AQT_ENOMEM, AQT_ESTATE, AQT_EHIP, AQT_ENUMERIC, AQT_ECAPACITY = 0, -1, -2, -3, -4, -5, -6
+FP64, FP32, BF16 = 0, 1, 2
+PRECISIONS = {"fp64": FP64, "fp32": FP32, "bf16": BF16}
+KIND_NAMES = ("relax", "excite", "dephase")
+
+EXPORTED = ("aqt_create", "aqt_destroy", "aqt_last_error", "aqt_version", "aqt_set_hamiltonian",
+            "aqt_set_schedule", "aqt_set_bath", "aqt_precompute", "aqt_set_tables", "aqt_get_tables",
+            "aqt_get_dims", "aqt_run")
+
+
+class Jump(C.Structure):
+    _fields_ = [("t", C.c_double), ("step", C.c_int32), ("qubit", C.c_int16), ("kind", C.c_int16),
+                ("from_level", C.c_int32), ("to_level", C.c_int32)]
+
+
+class RunParams(C.Structure):
+    _fields_ = [("precision", C.c_int32), ("record_capacity", C.c_int32), ("n_traj", C.c_int64),
+                ("seed", C.c_uint64), ("instance_id", C.c_uint64), ("traj_offset", C.c_uint64),
+                ("tile", C.c_int32), ("reserved", C.c_int32)]
+
+
+class Outputs(C.Structure):
+    _fields_ = [("pgs_sum", C.c_void_p), ("pgs_sumsq", C.c_void_p), ("jump_totals", C.c_void_p),
+                ("jump_count", C.c_void_p), ("jumps", C.c_void_p), ("net_gs", C.c_void_p),
+                ("net_hist", C.c_void_p), ("hist_lo", C.c_int32), ("hist_hi", C.c_int32),
+                ("final_state", C.c_void_p)]
+
+
+JUMP_DTYPE = np.dtype([("t", "<f8"), ("step", "<i4"), ("qubit", "<i2"), ("kind", "<i2"),
+                       ("from_level", "<i4"), ("to_level", "<i4")])
+assert JUMP_DTYPE.itemsize == C.sizeof(Jump) == 24
+
+
+class AqtError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"libaqt status {status}: {msg}")
+        self.status = status
+
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Load libaqt.so and declare the C signatures (no GPU work happens here)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError(f"{path} is missing: build it with `python -m paper_1710_03431_amd.build`")
+    lib = C.CDLL(path)
+    dp = C.POINTER(C.c_double)
+    ip = C.POINTER(C.c_int32)
+    ctx = C.c_void_p
+    lib.aqt_create.argtypes = [C.POINTER(C.c_void_p), C.c_int, C.c_void_p]
+    lib.aqt_destroy.argtypes = [ctx]
+    lib.aqt_destroy.restype = None
+    lib.aqt_last_error.argtypes = [ctx]
+    lib.aqt_last_error.restype = C.c_char_p
+    lib.aqt_version.argtypes = []
+    lib.aqt_set_hamiltonian.argtypes = [ctx, C.c_int, dp, dp]
+    lib.aqt_set_schedule.argtypes = [ctx, C.c_double, C.c_int, dp, dp]
+    lib.aqt_set_bath.argtypes = [ctx, C.c_double, C.c_double, C.c_double]
+    lib.aqt_precompute.argtypes = [ctx, C.c_int, C.c_int, C.c_double]
+    lib.aqt_set_tables.argtypes = [ctx, C.c_int, C.c_int, dp, ip, dp, dp, dp, dp]
+    lib.aqt_get_tables.argtypes = [ctx, dp, ip, dp, dp, dp, dp, dp, dp]
+    lib.aqt_get_dims.argtypes = [ctx, ip, ip, ip]
+    lib.aqt_run.argtypes = [ctx, C.POINTER(RunParams), C.POINTER(Outputs)]
+    for name in EXPORTED:
+        if name not in ("aqt_destroy", "aqt_last_error"):
+            getattr(lib, name).restype = C.c_int
+    _lib = lib
+    return lib
+
+
+def _dptr(a: Optional[np.ndarray]):
+    if a is None:
+        return None
+    return a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+def _iptr(a: Optional[np.ndarray]):
+    if a is None:
+        return None
+    return a.ctypes.data_as(C.POINTER(C.c_int32))
+
+
+def _f64(a) -> np.ndarray:
+    return np.ascontiguousarray(np.asarray(a, dtype=np.float64))
+
+
+class Engine:
+    """One libaqt context bound to a GPU and a stream."""
+
+    def __init__(self, device: int = 0, stream=None):
+        import torch
+        self.torch = torch
+        self.lib = load_library()
+        self.device = device
+        if stream is None:
+            stream = torch.cuda.current_stream(device)
+        self.stream = stream
+        h = C.c_void_p()
+        st = self.lib.aqt_create(C.byref(h), device, C.c_void_p(stream.cuda_stream))
+        if st != AQT_OK:
+            raise AqtError(st, "aqt_create failed")
+        self.ctx = h
+        self.n_grid = self.n_levels = self.n_qubits = None
+
+    def close(self):
+        if getattr(self, "ctx", None):
+            self.lib.aqt_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, st):
+        if st != AQT_OK:
+            raise AqtError(st, self.lib.aqt_last_error(self.ctx).decode())
+
+    # ---------------------------------------------------------------- inputs
+    def set_hamiltonian(self, h, J):
+        h = _f64(h)
+        J = _f64(J)
+        self._check(self.lib.aqt_set_hamiltonian(self.ctx, len(h), _dptr(h), _dptr(J)))
+
+    def set_schedule(self, t_f, A_ctrl, B_ctrl):
+        A = _f64(A_ctrl)
+        B = _f64(B_ctrl)
+        self._check(self.lib.aqt_set_schedule(self.ctx, float(t_f), len(A), _dptr(A), _dptr(B)))
+
+    def set_bath(self, eta, omega_c, T):
+        self._check(self.lib.aqt_set_bath(self.ctx, float(eta), float(omega_c), float(T)))
+
+    def set_instance(self, inst):
+        """Hamiltonian, schedule and bath of a workloads.Instance."""
+        self.set_hamiltonian(inst.h, inst.J)
+        self.set_schedule(inst.t_f, inst.A_ctrl, inst.B_ctrl)
+        self.set_bath(inst.eta, inst.omega_c, inst.T)
+
+    def precompute(self, n_grid: int, n_levels: int, deg_tol: float = 1e-8):
+        self._check(self.lib.aqt_precompute(self.ctx, int(n_grid), int(n_levels), float(deg_tol)))
+        self._dims()
+
+    def set_tables(self, E, gs, O, cinit, R, zdiag):
+        E = _f64(E)
+        M, n = E.shape
+        gs = np.ascontiguousarray(np.asarray(gs, dtype=np.int32))
+        O = _f64(O)
+        cinit = _f64(cinit)
+        R = _f64(R)
+        zdiag = _f64(zdiag)
+        self._check(self.lib.aqt_set_tables(self.ctx, M, n, _dptr(E), _iptr(gs), _dptr(O), _dptr(cinit),
+                                            _dptr(R), _dptr(zdiag)))
+        self._dims()
+
+    def _dims(self):
+        a, b, c = C.c_int32(), C.c_int32(), C.c_int32()
+        self._check(self.lib.aqt_get_dims(self.ctx, C.byref(a), C.byref(b), C.byref(c)))
+        self.n_grid, self.n_levels, self.n_qubits = a.value, b.value, c.value
+
+    def get_tables(self, want=("E", "gs", "O", "cinit", "R", "zdiag", "Gamma", "leak")):
+        M, n, nq = self.n_grid, self.n_levels, self.n_qubits
+        shapes = {"E": (M, n), "gs": (M,), "O": (M, n, n), "cinit": (n,), "R": (M, nq, n, n),
+                  "zdiag": (M, nq, n), "Gamma": (M, n), "leak": (M,)}
+        out = {k: (np.zeros(shapes[k], dtype=np.int32 if k == "gs" else np.float64) if k in want else None)
+               for k in shapes}
+        self._check(self.lib.aqt_get_tables(self.ctx, _dptr(out["E"]), _iptr(out["gs"]), _dptr(out["O"]),
+                                            _dptr(out["cinit"]), _dptr(out["R"]), _dptr(out["zdiag"]),
+                                            _dptr(out["Gamma"]), _dptr(out["leak"])))
+        return {k: v for k, v in out.items() if v is not None}
+
+    # ---------------------------------------------------------------- run
+    def alloc_outputs(self, n_traj: int, record_capacity: int = 0, hist=(-64, 64), final_state=False,
+                      per_trajectory=True):
+        t = self.torch
+        dev = t.device("cuda", self.device)
+        M, n = self.n_grid, self.n_levels
+        o = {"pgs_sum": t.zeros(M, dtype=t.float64, device=dev),
+             "pgs_sumsq": t.zeros(M, dtype=t.float64, device=dev),
+             "jump_totals": t.zeros(3, dtype=t.int64, device=dev),
+             "net_hist": t.zeros(hist[1] - hist[0] + 1, dtype=t.int64, device=dev),
+             "hist": hist}
+        if per_trajectory:
+            o["jump_count"] = t.zeros(n_traj, dtype=t.int32, device=dev)
+            o["net_gs"] = t.zeros(n_traj, dtype=t.int32, device=dev)
+        if record_capacity:
+            o["jumps"] = t.zeros(n_traj * record_capacity * 24, dtype=t.uint8, device=dev)
+        if final_state:
+            o["final_state"] = t.zeros(n_traj * n * 2, dtype=t.float64, device=dev)
+        return o
+
+    def run_into(self, outs: dict, n_traj: int, precision="fp64", seed=0, instance_id=0, traj_offset=0,
+                 record_capacity=0, tile=0):
+        """Enqueue one run writing into pre-allocated outputs (no synchronisation)."""
+        prec = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+        p = RunParams(precision=prec, record_capacity=int(record_capacity), n_traj=int(n_traj),
+                      seed=int(seed), instance_id=int(instance_id), traj_offset=int(traj_offset),
+                      tile=int(tile), reserved=0)
+
+        def ptr(k):
+            v = outs.get(k)
+            return None if v is None else v.data_ptr()
+
+        o = Outputs(pgs_sum=ptr("pgs_sum"), pgs_sumsq=ptr("pgs_sumsq"), jump_totals=ptr("jump_totals"),
+                    jump_count=ptr("jump_count"), jumps=ptr("jumps"), net_gs=ptr("net_gs"),
+                    net_hist=ptr("net_hist"), hist_lo=int(outs["hist"][0]), hist_hi=int(outs["hist"][1]),
+                    final_state=ptr("final_state"))
+        self._check(self.lib.aqt_run(self.ctx, C.byref(p), C.byref(o)))
+
+    def run(self, n_traj: int, precision="fp64", seed=0, instance_id=0, traj_offset=0, record_capacity=0,
+            tile=0, final_state=False, hist=(-64, 64)):
+        """Run K trajectories and return host numpy results (synchronises)."""
+        outs = self.alloc_outputs(n_traj, record_capacity, hist, final_state)
+        self.run_into(outs, n_traj, precision, seed, instance_id, traj_offset, record_capacity, tile)
+        self.stream.synchronize()
+        res = {k: v.cpu().numpy() for k, v in outs.items() if k not in ("hist", "jumps")}
+        res["hist_lo"] = hist[0]
+        if record_capacity:
+            raw = outs["jumps"].cpu().numpy().view(JUMP_DTYPE).reshape(n_traj, record_capacity)
+            res["jumps"] = raw
+        if final_state:
+            res["final_state"] = res["final_state"].reshape(n_traj, self.n_levels, 2)
+        return res

@@ -1,0 +1,251 @@
+// C-ABI entry points of libaqt (declared and documented in include/aqt.h).
+// Argument validation, host->device staging and call-order checks live here;
+// the numerical work is in tables.hip, step.hip and precompute.hip.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "aqt.h"
+#include "ctx.hpp"
+
+using aqt::DevBuf;
+
+namespace {
+
+aqt_status set_device(aqt_ctx* ctx) {
+  hipError_t e = hipSetDevice(ctx->device);
+  if (e != hipSuccess) return ctx->fail(AQT_EHIP, std::string("hipSetDevice: ") + hipGetErrorString(e));
+  return AQT_OK;
+}
+
+bool finite_all(const double* p, size_t n) {
+  for (size_t i = 0; i < n; ++i)
+    if (!std::isfinite(p[i])) return false;
+  return true;
+}
+
+// Copies a [rows][n][n]-shaped host array into a zero-padded [rows][NP][NP] device buffer.
+aqt_status upload_padded(aqt_ctx* ctx, DevBuf& dst, const double* src, size_t rows, int n, int NP, bool square) {
+  const size_t inner_src = square ? static_cast<size_t>(n) * n : n;
+  const size_t inner_dst = square ? static_cast<size_t>(NP) * NP : NP;
+  std::vector<double> host(rows * inner_dst, 0.0);
+  for (size_t r = 0; r < rows; ++r) {
+    if (square) {
+      for (int a = 0; a < n; ++a)
+        std::memcpy(&host[r * inner_dst + static_cast<size_t>(a) * NP], &src[r * inner_src + static_cast<size_t>(a) * n],
+                    n * sizeof(double));
+    } else {
+      std::memcpy(&host[r * inner_dst], &src[r * inner_src], n * sizeof(double));
+    }
+  }
+  if (dst.reserve(host.size() * sizeof(double)) != hipSuccess) return ctx->fail(AQT_ENOMEM, "table allocation failed");
+  AQT_HIP(ctx, hipMemcpy(dst.p, host.data(), host.size() * sizeof(double), hipMemcpyHostToDevice));
+  return AQT_OK;
+}
+
+aqt_status download_unpadded(aqt_ctx* ctx, double* dst, const DevBuf& src, size_t rows, int n, int NP, bool square) {
+  const size_t inner_src = square ? static_cast<size_t>(NP) * NP : NP;
+  const size_t inner_dst = square ? static_cast<size_t>(n) * n : n;
+  std::vector<double> host(rows * inner_src);
+  AQT_HIP(ctx, hipMemcpy(host.data(), src.p, host.size() * sizeof(double), hipMemcpyDeviceToHost));
+  for (size_t r = 0; r < rows; ++r) {
+    if (square) {
+      for (int a = 0; a < n; ++a)
+        std::memcpy(&dst[r * inner_dst + static_cast<size_t>(a) * n], &host[r * inner_src + static_cast<size_t>(a) * NP],
+                    n * sizeof(double));
+    } else {
+      std::memcpy(&dst[r * inner_dst], &host[r * inner_src], n * sizeof(double));
+    }
+  }
+  return AQT_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int aqt_version(void) { return 10000; }
+
+aqt_status aqt_create(aqt_ctx** out, int device, void* hip_stream) {
+  if (!out) return AQT_EINVAL;
+  *out = nullptr;
+  int count = 0;
+  if (hipGetDeviceCount(&count) != hipSuccess || count <= 0) return AQT_EHIP;
+  if (device < 0 || device >= count) return AQT_EINVAL;
+  aqt_ctx* ctx = new (std::nothrow) aqt_ctx();
+  if (!ctx) return AQT_ENOMEM;
+  ctx->device = device;
+  ctx->stream = static_cast<hipStream_t>(hip_stream);
+  if (set_device(ctx) != AQT_OK) {
+    delete ctx;
+    return AQT_EHIP;
+  }
+  *out = ctx;
+  return AQT_OK;
+}
+
+void aqt_destroy(aqt_ctx* ctx) {
+  if (!ctx) return;
+  (void)hipSetDevice(ctx->device);
+  if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
+  else (void)hipDeviceSynchronize();
+  delete ctx;
+}
+
+const char* aqt_last_error(const aqt_ctx* ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+
+aqt_status aqt_set_hamiltonian(aqt_ctx* ctx, int n_qubits, const double* h, const double* J) {
+  if (!ctx) return AQT_EINVAL;
+  if (n_qubits < 1 || n_qubits > 16) return ctx->fail(AQT_EINVAL, "n_qubits must be in [1, 16]");
+  if (!h || !J) return ctx->fail(AQT_EINVAL, "h and J must be non-null");
+  if (!finite_all(h, n_qubits) || !finite_all(J, static_cast<size_t>(n_qubits) * n_qubits))
+    return ctx->fail(AQT_EINVAL, "h and J must be finite");
+  ctx->nq = n_qubits;
+  ctx->h.assign(h, h + n_qubits);
+  ctx->J.assign(J, J + static_cast<size_t>(n_qubits) * n_qubits);
+  ctx->have_h = true;
+  ctx->have_tables = false;
+  return AQT_OK;
+}
+
+aqt_status aqt_set_schedule(aqt_ctx* ctx, double t_f, int n_ctrl, const double* A_ctrl, const double* B_ctrl) {
+  if (!ctx) return AQT_EINVAL;
+  if (!(t_f > 0.0) || !std::isfinite(t_f)) return ctx->fail(AQT_EINVAL, "t_f must be positive");
+  if (n_ctrl < 2 || !A_ctrl || !B_ctrl) return ctx->fail(AQT_EINVAL, "need n_ctrl >= 2 control points");
+  if (!finite_all(A_ctrl, n_ctrl) || !finite_all(B_ctrl, n_ctrl))
+    return ctx->fail(AQT_EINVAL, "schedule must be finite");
+  ctx->t_f = t_f;
+  ctx->A_ctrl.assign(A_ctrl, A_ctrl + n_ctrl);
+  ctx->B_ctrl.assign(B_ctrl, B_ctrl + n_ctrl);
+  ctx->have_sched = true;
+  ctx->have_tables = false;
+  return AQT_OK;
+}
+
+aqt_status aqt_set_bath(aqt_ctx* ctx, double eta, double omega_c, double T) {
+  if (!ctx) return AQT_EINVAL;
+  if (!(eta >= 0.0) || !(omega_c > 0.0) || !(T > 0.0) || !std::isfinite(eta) || !std::isfinite(omega_c) ||
+      !std::isfinite(T))
+    return ctx->fail(AQT_EINVAL, "need eta >= 0, omega_c > 0, T > 0");
+  ctx->eta = eta;
+  ctx->omega_c = omega_c;
+  ctx->T = T;
+  ctx->have_bath = true;
+  ctx->have_tables = false;
+  return AQT_OK;
+}
+
+aqt_status aqt_precompute(aqt_ctx* ctx, int n_grid, int n_levels, double deg_tol) {
+  if (!ctx) return AQT_EINVAL;
+  if (!ctx->have_h || !ctx->have_sched || !ctx->have_bath)
+    return ctx->fail(AQT_ESTATE, "set_hamiltonian, set_schedule and set_bath must come first");
+  const int N = 1 << ctx->nq;
+  if (n_grid < 2) return ctx->fail(AQT_EINVAL, "n_grid must be >= 2");
+  if (n_levels < 1 || n_levels > 256 || n_levels > N) return ctx->fail(AQT_EINVAL, "n_levels must be in [1, min(256, 2^nq)]");
+  if (!(deg_tol >= 0.0)) return ctx->fail(AQT_EINVAL, "deg_tol must be >= 0");
+  aqt_status s = set_device(ctx);
+  if (s != AQT_OK) return s;
+  ctx->have_tables = false;
+  s = aqt::precompute_tables(ctx, n_grid, n_levels, deg_tol);
+  if (s != AQT_OK) return s;
+  s = aqt::finish_tables(ctx);
+  if (s != AQT_OK) return s;
+  AQT_HIP(ctx, hipStreamSynchronize(ctx->stream));
+  ctx->have_tables = true;
+  return AQT_OK;
+}
+
+aqt_status aqt_set_tables(aqt_ctx* ctx, int n_grid, int n_levels, const double* E, const int32_t* gs,
+                          const double* O, const double* cinit, const double* R, const double* zdiag) {
+  if (!ctx) return AQT_EINVAL;
+  if (!ctx->have_h || !ctx->have_sched)
+    return ctx->fail(AQT_ESTATE, "set_hamiltonian and set_schedule must come first");
+  if (n_grid < 2 || n_levels < 1 || n_levels > 256) return ctx->fail(AQT_EINVAL, "bad n_grid or n_levels");
+  if (!E || !gs || !O || !cinit || !R || !zdiag) return ctx->fail(AQT_EINVAL, "all table pointers are required");
+  for (int g = 0; g < n_grid; ++g)
+    if (gs[g] < 1 || gs[g] > n_levels) return ctx->fail(AQT_EINVAL, "ground-cluster size out of range");
+  aqt_status s = set_device(ctx);
+  if (s != AQT_OK) return s;
+  const int n = n_levels, NP = aqt::padded_levels(n), nq = ctx->nq;
+  ctx->have_tables = false;
+  ctx->M = n_grid;
+  ctx->n = n;
+  ctx->NP = NP;
+  ctx->dt = ctx->t_f / (n_grid - 1);
+  if ((s = upload_padded(ctx, ctx->E, E, n_grid, n, NP, false)) != AQT_OK) return s;
+  // Delta = O - I on the n x n block, zero elsewhere
+  {
+    std::vector<double> dl(static_cast<size_t>(n_grid) * n * n);
+    for (int g = 0; g < n_grid; ++g)
+      for (int a = 0; a < n; ++a)
+        for (int b = 0; b < n; ++b) {
+          const size_t k = (static_cast<size_t>(g) * n + a) * n + b;
+          dl[k] = (g >= 2) ? O[k] - (a == b ? 1.0 : 0.0) : 0.0;
+        }
+    if ((s = upload_padded(ctx, ctx->dlt, dl.data(), n_grid, n, NP, true)) != AQT_OK) return s;
+  }
+  if ((s = upload_padded(ctx, ctx->cinit, cinit, 1, n, NP, false)) != AQT_OK) return s;
+  if ((s = upload_padded(ctx, ctx->R, R, static_cast<size_t>(n_grid) * nq, n, NP, true)) != AQT_OK) return s;
+  if ((s = upload_padded(ctx, ctx->zdiag, zdiag, static_cast<size_t>(n_grid) * nq, n, NP, false)) != AQT_OK) return s;
+  if (ctx->gs.reserve(n_grid * sizeof(int32_t)) != hipSuccess) return ctx->fail(AQT_ENOMEM, "table allocation failed");
+  AQT_HIP(ctx, hipMemcpy(ctx->gs.p, gs, n_grid * sizeof(int32_t), hipMemcpyHostToDevice));
+  if (ctx->leak.reserve(n_grid * sizeof(double)) != hipSuccess) return ctx->fail(AQT_ENOMEM, "table allocation failed");
+  AQT_HIP(ctx, hipMemset(ctx->leak.p, 0, n_grid * sizeof(double)));
+  if ((s = aqt::finish_tables(ctx)) != AQT_OK) return s;
+  AQT_HIP(ctx, hipStreamSynchronize(ctx->stream));
+  ctx->have_tables = true;
+  return AQT_OK;
+}
+
+aqt_status aqt_get_dims(aqt_ctx* ctx, int32_t* n_grid, int32_t* n_levels, int32_t* n_qubits) {
+  if (!ctx) return AQT_EINVAL;
+  if (!ctx->have_tables) return ctx->fail(AQT_ESTATE, "no tables loaded");
+  if (n_grid) *n_grid = ctx->M;
+  if (n_levels) *n_levels = ctx->n;
+  if (n_qubits) *n_qubits = ctx->nq;
+  return AQT_OK;
+}
+
+aqt_status aqt_get_tables(aqt_ctx* ctx, double* E, int32_t* gs, double* O, double* cinit, double* R, double* zdiag,
+                          double* Gamma, double* leak) {
+  if (!ctx) return AQT_EINVAL;
+  if (!ctx->have_tables) return ctx->fail(AQT_ESTATE, "no tables loaded");
+  aqt_status s = set_device(ctx);
+  if (s != AQT_OK) return s;
+  AQT_HIP(ctx, hipStreamSynchronize(ctx->stream));
+  const int M = ctx->M, n = ctx->n, NP = ctx->NP, nq = ctx->nq;
+  if (E && (s = download_unpadded(ctx, E, ctx->E, M, n, NP, false)) != AQT_OK) return s;
+  if (gs) AQT_HIP(ctx, hipMemcpy(gs, ctx->gs.p, M * sizeof(int32_t), hipMemcpyDeviceToHost));
+  if (O) {
+    if ((s = download_unpadded(ctx, O, ctx->dlt, M, n, NP, true)) != AQT_OK) return s;
+    for (int g = 0; g < M; ++g)
+      for (int a = 0; a < n; ++a) O[(static_cast<size_t>(g) * n + a) * n + a] += 1.0;
+  }
+  if (cinit && (s = download_unpadded(ctx, cinit, ctx->cinit, 1, n, NP, false)) != AQT_OK) return s;
+  if (R && (s = download_unpadded(ctx, R, ctx->R, static_cast<size_t>(M) * nq, n, NP, true)) != AQT_OK) return s;
+  if (zdiag && (s = download_unpadded(ctx, zdiag, ctx->zdiag, static_cast<size_t>(M) * nq, n, NP, false)) != AQT_OK)
+    return s;
+  if (Gamma && (s = download_unpadded(ctx, Gamma, ctx->Gamma, M, n, NP, false)) != AQT_OK) return s;
+  if (leak) AQT_HIP(ctx, hipMemcpy(leak, ctx->leak.p, M * sizeof(double), hipMemcpyDeviceToHost));
+  return AQT_OK;
+}
+
+aqt_status aqt_run(aqt_ctx* ctx, const aqt_run_params* p, const aqt_outputs* o) {
+  if (!ctx) return AQT_EINVAL;
+  if (!p || !o) return ctx->fail(AQT_EINVAL, "params and outputs are required");
+  if (!ctx->have_tables) return ctx->fail(AQT_ESTATE, "precompute or set_tables must come first");
+  if (p->n_traj < 1) return ctx->fail(AQT_EINVAL, "n_traj must be >= 1");
+  if (p->precision < AQT_FP64 || p->precision > AQT_BF16) return ctx->fail(AQT_EINVAL, "unknown precision");
+  if (p->record_capacity < 0) return ctx->fail(AQT_EINVAL, "record_capacity must be >= 0");
+  if (p->record_capacity > 0 && !o->jumps) return ctx->fail(AQT_EINVAL, "record_capacity > 0 needs a jumps buffer");
+  if (o->net_hist && o->hist_hi < o->hist_lo) return ctx->fail(AQT_EINVAL, "hist_hi < hist_lo");
+  aqt_status s = set_device(ctx);
+  if (s != AQT_OK) return s;
+  return aqt::launch_run(ctx, p, o);
+}
+
+}  // extern "C"

@@ -1,0 +1,83 @@
+// Internal state of an aqt_ctx and the host-side launchers shared between the
+// C-ABI layer (api.hip) and the kernel translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <string>
+#include <vector>
+
+#include "aqt.h"
+#include "common.hpp"
+
+struct aqt_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  std::string err;
+
+  // ---- problem definition (host copies)
+  int nq = 0;
+  std::vector<double> h, J;   // J: nq*nq row-major, i<j used
+  bool have_h = false;
+  double t_f = 0.0;
+  std::vector<double> A_ctrl, B_ctrl;
+  bool have_sched = false;
+  double eta = 0.0, omega_c = 0.0, T = 0.0;
+  bool have_bath = false;
+
+  // ---- tables (device, FP64 masters; rows padded to NP with zeros)
+  bool have_tables = false;
+  int M = 0;        // grid points
+  int n = 0;        // retained levels
+  int NP = 0;       // padded level count: 16, 32, 64, 128 or 256
+  double dt = 0.0;
+  aqt::DevBuf E;        // [M][NP]
+  aqt::DevBuf gs;       // [M] int32
+  aqt::DevBuf dlt;      // [M][NP][NP]  Delta = O - I (row-major), zero padded; g < 2 unused
+  aqt::DevBuf cinit;    // [NP]
+  aqt::DevBuf R;        // [M][nq][NP(b)][NP(a)]
+  aqt::DevBuf zdiag;    // [M][nq][NP]
+  aqt::DevBuf Gamma;    // [M][NP]
+  aqt::DevBuf dre, dim; // [M][NP] FP64 exp(-i e dt - Gamma dt / 2)
+  aqt::DevBuf leak;     // [M]
+
+  // ---- per-precision packed operands of the step kernel (built lazily)
+  int packed_for = -1;      // aqt_precision the packs below hold, -1 = none
+  aqt::DevBuf pk_a, pk_b;   // Delta fragments (hi / lo for BF16)
+  aqt::DevBuf pk_dre, pk_dim;  // d in the state precision
+
+  // ---- run workspace
+  aqt::DevBuf partial;      // [tiles][M][2] per-tile observable sums
+
+  aqt_status fail(aqt_status s, const std::string& msg) {
+    err = msg;
+    return s;
+  }
+};
+
+namespace aqt {
+
+#define AQT_HIP(ctx, expr)                                                              \
+  do {                                                                                  \
+    hipError_t _e = (expr);                                                             \
+    if (_e != hipSuccess)                                                               \
+      return (ctx)->fail(AQT_EHIP, std::string(#expr) + ": " + hipGetErrorString(_e));  \
+  } while (0)
+
+// tables.hip: derive Gamma and d from E and R; pack the step operands.
+aqt_status finish_tables(aqt_ctx* ctx);
+aqt_status pack_for_precision(aqt_ctx* ctx, int precision);
+
+// step.hip: enqueue the trajectory kernel and the observable reduction.
+aqt_status launch_run(aqt_ctx* ctx, const aqt_run_params* p, const aqt_outputs* o);
+
+// precompute.hip: GPU eigensystem and tables.
+aqt_status precompute_tables(aqt_ctx* ctx, int n_grid, int n_levels, double deg_tol);
+
+inline int padded_levels(int n) {
+  int np = 16;
+  while (np < n) np *= 2;
+  return np;
+}
+
+}  // namespace aqt

@@ -1,0 +1,243 @@
+// Workgroup-level FP64 dense symmetric eigensolver (device functions).
+//
+// A symmetric N x N matrix in global memory is reduced to tridiagonal form by
+// Householder reflections (each reflection maps the part of a row right of
+// the diagonal onto a multiple of the first unit vector, applied from both
+// sides to the trailing block as a rank-2 update), the tridiagonal matrix is
+// diagonalised by implicit symmetric QR steps with the Wilkinson shift (a
+// Givens rotation seeded by the shifted leading column, then chased down the
+// band), and the eigenvectors are obtained by applying the reflections to the
+// accumulated rotations.  Textbook algorithms (Householder 1958; Francis QR
+// with Wilkinson's shift), restated for a 256-thread workgroup:
+//   * the reflection is built with two block reductions, the trailing block
+//     is updated by all threads with accesses contiguous along rows;
+//   * one thread computes the rotation sequence of a QR sweep on the band
+//     (O(N) scalar work) and publishes it in LDS, then every thread applies
+//     the whole sequence to its own rows of Z (column-major, so the updates
+//     of a column pair are contiguous across threads);
+//   * eigenvalues are ranked in parallel into a stable ascending order.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "common.hpp"
+
+namespace aqt {
+
+constexpr int kEigThreads = 256;
+constexpr int kEigMaxN = 1024;
+
+struct EigShared {
+  double v[kEigMaxN];     // Householder vector / scratch
+  double w[kEigMaxN];     // p, then w
+  double d[kEigMaxN];     // band diagonal
+  double e[kEigMaxN];     // band off-diagonal
+  double beta[kEigMaxN];  // reflection coefficients
+  double c[kEigMaxN];     // rotation cosines of one sweep
+  double s[kEigMaxN];     // rotation sines of one sweep
+  double red[kEigThreads / kWave];
+  int lo, hi, done, fail;
+};
+
+__device__ __forceinline__ double block_sum(double v, double* red) {
+  const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x >> 6;
+  v = wave_sum(v);
+  __syncthreads();
+  if (lane == 0) red[wave] = v;
+  __syncthreads();
+  double t = 0.0;
+#pragma unroll
+  for (int i = 0; i < kEigThreads / kWave; ++i) t += red[i];
+  return t;
+}
+
+// Reduce symmetric A (row-major, leading dimension lda) to tridiagonal form.
+// On exit sh.d/sh.e hold the band, sh.beta the reflection coefficients and row
+// j of A, right of the diagonal, the Householder vector of step j.
+__device__ void wg_tridiagonalize(double* A, int N, int lda, EigShared& sh) {
+  const int tid = threadIdx.x;
+  const int lane = tid & (kWave - 1), wave = tid >> 6;
+  for (int j = 0; j + 2 < N; ++j) {
+    const int L = N - j - 1;
+    double* row = A + static_cast<size_t>(j) * lda + j + 1;
+    double part = 0.0;
+    for (int i = tid + 1; i < L; i += kEigThreads) part += row[i] * row[i];
+    const double tail = block_sum(part, sh.red);
+    const double x0 = row[0];
+    if (tid == 0) sh.d[j] = A[static_cast<size_t>(j) * lda + j];
+    if (tail == 0.0) {
+      if (tid == 0) {
+        sh.e[j] = x0;
+        sh.beta[j] = 0.0;
+      }
+      __syncthreads();
+      continue;
+    }
+    const double sigma = sqrt(x0 * x0 + tail);
+    const double alpha = (x0 >= 0.0) ? -sigma : sigma;
+    const double v0 = x0 - alpha;
+    const double beta = 2.0 / (v0 * v0 + tail);
+    for (int i = tid; i < L; i += kEigThreads) sh.v[i] = (i == 0) ? v0 : row[i];
+    __syncthreads();
+    // p = beta * S v, S the trailing block; one wavefront per row
+    for (int i = wave; i < L; i += kEigThreads / kWave) {
+      const double* Si = A + static_cast<size_t>(j + 1 + i) * lda + j + 1;
+      double acc = 0.0;
+      for (int k = lane; k < L; k += kWave) acc += Si[k] * sh.v[k];
+      acc = wave_sum(acc);
+      if (lane == 0) sh.w[i] = beta * acc;
+    }
+    __syncthreads();
+    part = 0.0;
+    for (int i = tid; i < L; i += kEigThreads) part += sh.v[i] * sh.w[i];
+    const double Kc = 0.5 * beta * block_sum(part, sh.red);
+    for (int i = tid; i < L; i += kEigThreads) sh.w[i] -= Kc * sh.v[i];
+    __syncthreads();
+    const size_t tot = static_cast<size_t>(L) * L;
+    for (size_t f = tid; f < tot; f += kEigThreads) {
+      const int i = static_cast<int>(f / L), k = static_cast<int>(f - static_cast<size_t>(i) * L);
+      A[static_cast<size_t>(j + 1 + i) * lda + j + 1 + k] -= sh.v[i] * sh.w[k] + sh.w[i] * sh.v[k];
+    }
+    for (int i = tid; i < L; i += kEigThreads) row[i] = sh.v[i];
+    if (tid == 0) {
+      sh.e[j] = alpha;
+      sh.beta[j] = beta;
+    }
+    __syncthreads();
+  }
+  if (tid == 0) {
+    if (N >= 2) {
+      sh.d[N - 2] = A[static_cast<size_t>(N - 2) * lda + N - 2];
+      sh.e[N - 2] = A[static_cast<size_t>(N - 2) * lda + N - 1];
+      sh.beta[N - 2] = 0.0;
+    }
+    sh.d[N - 1] = A[static_cast<size_t>(N - 1) * lda + N - 1];
+    sh.e[N - 1] = 0.0;
+    sh.beta[N - 1] = 0.0;
+  }
+  __syncthreads();
+}
+
+// Implicit symmetric QR on the band in sh.d/sh.e; rotations accumulated into
+// Z (column-major N x N, leading dimension ldz, initialised to I here).
+// Returns false if the iteration budget is exhausted.
+__device__ bool wg_band_qr(double* Z, int N, int ldz, EigShared& sh) {
+  const int tid = threadIdx.x;
+  for (int c = 0; c < N; ++c)
+    for (int r = tid; r < N; r += kEigThreads) Z[static_cast<size_t>(c) * ldz + r] = (r == c) ? 1.0 : 0.0;
+  if (tid == 0) {
+    sh.done = 0;
+    sh.fail = 0;
+    sh.hi = N - 1;
+  }
+  __syncthreads();
+  const long budget = 64L * N + 64;
+  for (long sweep = 0;; ++sweep) {
+    if (tid == 0) {
+      int m = sh.hi;
+      int l = 0;
+      bool have = false;
+      while (m > 0) {
+        for (int k = 0; k < m; ++k)
+          if (fabs(sh.e[k]) <= 2.220446049250313e-16 * (fabs(sh.d[k]) + fabs(sh.d[k + 1]))) sh.e[k] = 0.0;
+        if (sh.e[m - 1] == 0.0) {
+          --m;
+          continue;
+        }
+        l = m - 1;
+        while (l > 0 && sh.e[l - 1] != 0.0) --l;
+        have = true;
+        break;
+      }
+      sh.hi = m;
+      if (!have || sweep >= budget) {
+        sh.done = 1;
+        sh.fail = have ? 1 : 0;
+      } else {
+        // Wilkinson shift from the trailing 2x2 block of the window [l, m]
+        const double delta = 0.5 * (sh.d[m - 1] - sh.d[m]);
+        const double bb = sh.e[m - 1];
+        const double den = delta + copysign(hypot(delta, bb), delta >= 0.0 ? 1.0 : -1.0);
+        const double mu = sh.d[m] - bb * bb / den;
+        double x = sh.d[l] - mu, z = sh.e[l];
+        for (int k = l; k < m; ++k) {
+          const double r = hypot(x, z);
+          const double c = x / r, s = z / r;
+          if (k > l) sh.e[k - 1] = r;
+          const double a = sh.d[k], b = sh.e[k], cc = sh.d[k + 1];
+          sh.d[k] = c * c * a + 2.0 * c * s * b + s * s * cc;
+          sh.d[k + 1] = s * s * a - 2.0 * c * s * b + c * c * cc;
+          sh.e[k] = c * s * (cc - a) + (c * c - s * s) * b;
+          if (k + 1 < m) {
+            z = s * sh.e[k + 1];
+            sh.e[k + 1] *= c;
+          }
+          x = sh.e[k];
+          sh.c[k] = c;
+          sh.s[k] = s;
+        }
+        sh.lo = l;
+      }
+    }
+    __syncthreads();
+    if (sh.done) break;
+    const int l = sh.lo, m = sh.hi;
+    for (int r = tid; r < N; r += kEigThreads) {
+      double zk = Z[static_cast<size_t>(l) * ldz + r];
+      for (int k = l; k < m; ++k) {
+        const double zk1 = Z[static_cast<size_t>(k + 1) * ldz + r];
+        const double c = sh.c[k], s = sh.s[k];
+        Z[static_cast<size_t>(k) * ldz + r] = c * zk + s * zk1;
+        zk = -s * zk + c * zk1;
+      }
+      Z[static_cast<size_t>(m) * ldz + r] = zk;
+    }
+    __syncthreads();
+  }
+  const bool ok = !sh.fail;
+  __syncthreads();
+  return ok;
+}
+
+// Apply the stored reflections to the columns of Z listed in cols[0..ncols-1]
+// (column-major), turning band eigenvectors into eigenvectors of A.
+__device__ void wg_back_transform(const double* A, int N, int lda, double* Z, int ldz, const int* cols, int ncols,
+                                  EigShared& sh) {
+  const int tid = threadIdx.x;
+  const int lane = tid & (kWave - 1), wave = tid >> 6;
+  for (int j = N - 3; j >= 0; --j) {
+    const double beta = sh.beta[j];
+    if (beta == 0.0) continue;
+    const int L = N - j - 1;
+    const double* vrow = A + static_cast<size_t>(j) * lda + j + 1;
+    for (int i = tid; i < L; i += kEigThreads) sh.v[i] = vrow[i];
+    __syncthreads();
+    for (int q = wave; q < ncols; q += kEigThreads / kWave) {
+      const double* zc = Z + static_cast<size_t>(cols[q]) * ldz + j + 1;
+      double acc = 0.0;
+      for (int i = lane; i < L; i += kWave) acc += sh.v[i] * zc[i];
+      acc = wave_sum(acc);
+      if (lane == 0) sh.w[q] = beta * acc;
+    }
+    __syncthreads();
+    const size_t tot = static_cast<size_t>(ncols) * L;
+    for (size_t f = tid; f < tot; f += kEigThreads) {
+      const int q = static_cast<int>(f / L), i = static_cast<int>(f - static_cast<size_t>(q) * L);
+      Z[static_cast<size_t>(cols[q]) * ldz + j + 1 + i] -= sh.w[q] * sh.v[i];
+    }
+    __syncthreads();
+  }
+}
+
+// Stable ascending rank of the eigenvalues: perm[rank] = index.
+__device__ void wg_rank_ascending(const double* d, int N, int* perm) {
+  for (int i = threadIdx.x; i < N; i += kEigThreads) {
+    const double di = d[i];
+    int rank = 0;
+    for (int j = 0; j < N; ++j) rank += (d[j] < di) || (d[j] == di && j < i);
+    perm[rank] = i;
+  }
+  __syncthreads();
+}
+
+}  // namespace aqt

@@ -1,0 +1,551 @@
+// GPU precompute of the instantaneous eigensystem and the AME tables (FP64).
+//
+// Per grid point s_g (Sec. II eq. Lindblad2 needs the eigenpairs of H_S(t)):
+//   k_build_dense  H(s_g) = A(s_g) H_X + B(s_g) diag(e_Z)  (Sec. V eq. H_S)
+//   k_dense_eig    workgroup eigensolver (eigen.hpp), eigenvalues ranked
+//   k_canon        clusters of levels closer than deg_tol rotated to the
+//                  eigenbasis of the projected diagonal operator diag(x)
+//                  (energies become Rayleigh quotients); column signs fixed
+//                  so that the first entry within 1e-9 of the column's largest
+//                  magnitude is positive; truncation to the n lowest levels
+//   k_gemm_f64     MFMA (16x16x4 FP64) products V_g V_{g-1}^T (overlaps) and
+//                  V_g diag(sz_i) V_g^T (matrix elements <a|sz_i|b>)
+//   k_polar        polar factor of the truncated overlap via the eigen-
+//                  decomposition of M^T M; leakage 1 - sigma_min^2
+//   k_rates        R[i][b][a] = gamma(e_b - e_a) z_ab^2 (a != b),
+//                  gamma(0) z_bb^2 (a == b), Ohmic gamma (Sec. V), and zdiag
+// The ground state of H(s_0) (must be non-degenerate) is expressed in the
+// grid-1 basis and normalised: the initial state of every trajectory.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <vector>
+
+#include "common.hpp"
+#include "ctx.hpp"
+#include "eigen.hpp"
+
+namespace aqt {
+namespace {
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+
+inline unsigned nblk(int64_t count, int threads = 256) {
+  return static_cast<unsigned>((count + threads - 1) / threads);
+}
+
+__global__ void k_ising_diag(const double* __restrict__ h, const double* __restrict__ J, int nq,
+                             double* __restrict__ eZ) {
+  const int x = blockIdx.x * blockDim.x + threadIdx.x;
+  if (x >= (1 << nq)) return;
+  double e = 0.0;
+  for (int i = 0; i < nq; ++i) {
+    const double si = ((x >> i) & 1) ? -1.0 : 1.0;
+    e += h[i] * si;
+    for (int j = i + 1; j < nq; ++j) {
+      const double sj = ((x >> j) & 1) ? -1.0 : 1.0;
+      e += J[i * nq + j] * si * sj;
+    }
+  }
+  eZ[x] = e;
+}
+
+__global__ void k_build_dense(const double* __restrict__ eZ, int nq, const double* __restrict__ Ag,
+                              const double* __restrict__ Bg, int g0, int count, double* __restrict__ H) {
+  const int N = 1 << nq;
+  const int64_t per = static_cast<int64_t>(N) * N;
+  const int64_t idx = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (idx >= per * count) return;
+  const int c = static_cast<int>(idx / per);
+  const int64_t r = idx - c * per;
+  const int x = static_cast<int>(r / N), y = static_cast<int>(r - static_cast<int64_t>(x) * N);
+  const int g = g0 + c;
+  double v = 0.0;
+  if (x == y) v = Bg[g] * eZ[x];
+  else if (__popc(static_cast<unsigned>(x ^ y)) == 1) v = -Ag[g];
+  H[idx] = v;
+}
+
+// One workgroup per matrix: eigenvalues (ascending, stable) and eigenvectors.
+// Z is column-major: Z[col * N + row]; perm[a] is the column of level a.
+__global__ __launch_bounds__(kEigThreads) void k_dense_eig(double* H, double* Z, int N, int ncols,
+                                                           double* __restrict__ Eraw, int* __restrict__ perm,
+                                                           int* __restrict__ status) {
+  __shared__ EigShared sh;
+  __shared__ int s_perm[kEigMaxN];
+  const int c = blockIdx.x;
+  double* A = H + static_cast<size_t>(c) * N * N;
+  double* Zc = Z + static_cast<size_t>(c) * N * N;
+  wg_tridiagonalize(A, N, N, sh);
+  const bool ok = wg_band_qr(Zc, N, N, sh);
+  wg_rank_ascending(sh.d, N, s_perm);
+  wg_back_transform(A, N, N, Zc, N, s_perm, ncols, sh);
+  for (int a = threadIdx.x; a < N; a += blockDim.x) {
+    perm[static_cast<size_t>(c) * N + a] = s_perm[a];
+    Eraw[static_cast<size_t>(c) * N + a] = sh.d[s_perm[a]];
+  }
+  if (threadIdx.x == 0) status[c] = ok ? 0 : 1;
+}
+
+// Canonical basis, signs and truncation.  Reads level a (< ncols) as column
+// perm[a] of Z; writes V[a][x] (a < n) row-major, E[g][a] (padded to NP), gs[g].
+// Workspace per matrix: G and its eigenvectors (ncols^2 each), and ncols*N
+// doubles holding the cluster's old vectors.
+__global__ __launch_bounds__(kEigThreads) void k_canon(const double* __restrict__ Z, const int* __restrict__ perm,
+                                                       const double* __restrict__ Eraw, int N, int ncols, int n,
+                                                       int NP, double tol, int g0, double* __restrict__ Vout,
+                                                       double* __restrict__ Etab, int* __restrict__ gstab,
+                                                       double* __restrict__ ws, int* __restrict__ status) {
+  __shared__ EigShared sh;
+  __shared__ double s_E[kEigMaxN];
+  __shared__ int s_cs[kEigMaxN + 1];
+  __shared__ int s_ncl;
+  __shared__ int s_perm2[kEigMaxN];
+  const int c = blockIdx.x;
+  const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid >> 6;
+  const double* Zc = Z + static_cast<size_t>(c) * N * N;
+  const int* pc = perm + static_cast<size_t>(c) * N;
+  double* V = Vout + static_cast<size_t>(c) * ncols * N;   // canonical vectors, ncols rows
+  double* G = ws + static_cast<size_t>(c) * (2 * static_cast<size_t>(ncols) * ncols + static_cast<size_t>(ncols) * N);
+  double* ZG = G + static_cast<size_t>(ncols) * ncols;
+  double* old = ZG + static_cast<size_t>(ncols) * ncols;
+  for (int a = tid; a < ncols; a += blockDim.x) s_E[a] = Eraw[static_cast<size_t>(c) * N + a];
+  for (size_t f = tid; f < static_cast<size_t>(ncols) * N; f += blockDim.x) {
+    const int a = static_cast<int>(f / N), x = static_cast<int>(f - static_cast<size_t>(a) * N);
+    V[f] = Zc[static_cast<size_t>(pc[a]) * N + x];
+  }
+  __syncthreads();
+  if (tid == 0) {
+    int k = 0;
+    s_cs[k++] = 0;
+    for (int a = 1; a < ncols; ++a)
+      if (s_E[a] - s_E[a - 1] >= tol) s_cs[k++] = a;
+    s_cs[k] = ncols;
+    s_ncl = k;
+  }
+  __syncthreads();
+  const int ncl = s_ncl;
+  bool ok = true;
+  for (int q = 0; q < ncl; ++q) {
+    const int a0 = s_cs[q], a1 = s_cs[q + 1], cs = a1 - a0;
+    if (cs < 2) continue;
+    // G[i][j] = sum_x x V[a0+i][x] V[a0+j][x]
+    for (int p = wave; p < cs * cs; p += kEigThreads / kWave) {
+      const int i = p / cs, j = p - i * cs;
+      const double* vi = V + static_cast<size_t>(a0 + i) * N;
+      const double* vj = V + static_cast<size_t>(a0 + j) * N;
+      double acc = 0.0;
+      for (int x = lane; x < N; x += kWave) acc += static_cast<double>(x) * vi[x] * vj[x];
+      acc = wave_sum(acc);
+      if (lane == 0) G[i * cs + j] = acc;
+    }
+    __syncthreads();
+    wg_tridiagonalize(G, cs, cs, sh);
+    ok = wg_band_qr(ZG, cs, cs, sh) && ok;
+    wg_rank_ascending(sh.d, cs, s_perm2);
+    wg_back_transform(G, cs, cs, ZG, cs, s_perm2, cs, sh);
+    // rotate: new_j = sum_i Q[i][j] old_i, Q[i][j] = ZG[perm2[j]][i]
+    for (size_t f = tid; f < static_cast<size_t>(cs) * N; f += blockDim.x) old[f] = V[static_cast<size_t>(a0) * N + f];
+    __syncthreads();
+    for (size_t f = tid; f < static_cast<size_t>(cs) * N; f += blockDim.x) {
+      const int j = static_cast<int>(f / N), x = static_cast<int>(f - static_cast<size_t>(j) * N);
+      const double* qj = ZG + static_cast<size_t>(s_perm2[j]) * cs;
+      double acc = 0.0;
+      for (int i = 0; i < cs; ++i) acc += qj[i] * old[static_cast<size_t>(i) * N + x];
+      V[static_cast<size_t>(a0 + j) * N + x] = acc;
+    }
+    for (int j = tid; j < cs; j += blockDim.x) {
+      const double* qj = ZG + static_cast<size_t>(s_perm2[j]) * cs;
+      double e = 0.0;
+      for (int i = 0; i < cs; ++i) e += qj[i] * qj[i] * s_E[a0 + i];
+      sh.w[j] = e;
+    }
+    __syncthreads();
+    for (int j = tid; j < cs; j += blockDim.x) s_E[a0 + j] = sh.w[j];
+    __syncthreads();
+  }
+  // signs: first entry within 1e-9 of the largest magnitude is made positive
+  for (int a = wave; a < n; a += kEigThreads / kWave) {
+    double* va = V + static_cast<size_t>(a) * N;
+    double mx = 0.0;
+    for (int x = lane; x < N; x += kWave) mx = fmax(mx, fabs(va[x]));
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) mx = fmax(mx, __shfl_xor(mx, o, kWave));
+    int first = N;
+    for (int x = lane; x < N; x += kWave)
+      if (fabs(va[x]) >= (1.0 - 1e-9) * mx) {
+        first = x;
+        break;
+      }
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) first = min(first, __shfl_xor(first, o, kWave));
+    const bool flip = va[first] < 0.0;
+    if (flip)
+      for (int x = lane; x < N; x += kWave) va[x] = -va[x];
+  }
+  __syncthreads();
+  const int g = g0 + c;
+  for (int a = tid; a < NP; a += blockDim.x) Etab[static_cast<size_t>(g) * NP + a] = (a < n) ? s_E[a] : 0.0;
+  if (tid == 0) {
+    gstab[g] = min(n, ncl > 1 ? s_cs[1] : ncols);
+    if (!ok) status[c] |= 2;
+  }
+}
+
+// C[b][i][j] (+)= sum_x w(x) A[i][x] B[j][x] for rows i < ra, j < rb: 64x64 tile
+// per workgroup, x staged through LDS in chunks of 32, 16x16x4 FP64 MFMAs.
+// wmode 0: w = 1; 1: w = sz of qubit (bz % nq) (operands of batch bz / nq).
+// sub_eye: subtract the identity (stores O - I).
+struct GemmArgs {
+  const double* A;
+  const double* B;
+  double* C;
+  int64_t sA, sB, sC;
+  int ra, rb, K, lda, ldb, ldc;
+  int wmode, nq, sub_eye;
+};
+
+__global__ __launch_bounds__(256) void k_gemm_f64(GemmArgs p) {
+  __shared__ double As[64][33];
+  __shared__ double Bs[64][33];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int bz = blockIdx.z;
+  const int opb = (p.wmode == 1) ? bz / p.nq : bz;
+  const int qubit = (p.wmode == 1) ? bz % p.nq : 0;
+  const double* A = p.A + p.sA * opb;
+  const double* B = p.B + p.sB * opb;
+  double* C = p.C + p.sC * bz;
+  const int i0 = blockIdx.y * 64, j0 = blockIdx.x * 64;
+  const int wi = (wave >> 1) * 32, wj = (wave & 1) * 32;
+  d4 acc[2][2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) acc[a][b] = d4{0.0, 0.0, 0.0, 0.0};
+  for (int x0 = 0; x0 < p.K; x0 += 32) {
+    for (int f = tid; f < 64 * 32; f += 256) {
+      const int r = f >> 5, k = f & 31, x = x0 + k;
+      double w = 1.0;
+      if (p.wmode == 1) w = ((x >> qubit) & 1) ? -1.0 : 1.0;
+      As[r][k] = (i0 + r < p.ra && x < p.K) ? w * A[static_cast<size_t>(i0 + r) * p.lda + x] : 0.0;
+      Bs[r][k] = (j0 + r < p.rb && x < p.K) ? B[static_cast<size_t>(j0 + r) * p.ldb + x] : 0.0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < 8; ++kk) {
+      const int k = 4 * kk + (lane >> 4);
+      double av[2], bv[2];
+#pragma unroll
+      for (int a = 0; a < 2; ++a) av[a] = As[wi + 16 * a + (lane & 15)][k];
+#pragma unroll
+      for (int b = 0; b < 2; ++b) bv[b] = Bs[wj + 16 * b + (lane & 15)][k];
+#pragma unroll
+      for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[a], bv[b], acc[a][b], 0, 0, 0);
+    }
+    __syncthreads();
+  }
+  // FP64 16x16x4 accumulator: lane l, element e holds row l/16 + 4e, column l%16
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int i = i0 + wi + 16 * a + (lane >> 4) + 4 * e;
+        const int j = j0 + wj + 16 * b + (lane & 15);
+        if (i < p.ra && j < p.rb) {
+          double v = acc[a][b][e];
+          if (p.sub_eye && i == j) v -= 1.0;
+          C[static_cast<size_t>(i) * p.ldc + j] = v;
+        }
+      }
+}
+
+// Polar factor of the truncated overlap M = O (stored as Delta = M - I in dlt):
+// M^T M = U S^2 U^T, polar(M) = M U S^-1 U^T; leakage 1 - min S^2.
+__global__ __launch_bounds__(kEigThreads) void k_polar(double* dlt, int NP, int n, int g0, double* leak,
+                                                       double* ws, int* status) {
+  __shared__ EigShared sh;
+  __shared__ int s_perm[kEigMaxN];
+  const int c = blockIdx.x;
+  const int g = g0 + c;
+  const int tid = threadIdx.x;
+  double* D = dlt + static_cast<size_t>(g) * NP * NP;
+  double* Mm = ws + static_cast<size_t>(c) * 4 * n * n;   // M
+  double* Gm = Mm + static_cast<size_t>(n) * n;           // M^T M, then reflectors
+  double* U = Gm + static_cast<size_t>(n) * n;            // eigenvectors (column-major)
+  double* T = U + static_cast<size_t>(n) * n;             // M U S^-1
+  for (int f = tid; f < n * n; f += blockDim.x) {
+    const int i = f / n, j = f - i * n;
+    Mm[f] = D[static_cast<size_t>(i) * NP + j] + (i == j ? 1.0 : 0.0);
+  }
+  __syncthreads();
+  for (int f = tid; f < n * n; f += blockDim.x) {
+    const int i = f / n, j = f - i * n;
+    double acc = 0.0;
+    for (int k = 0; k < n; ++k) acc += Mm[k * n + i] * Mm[k * n + j];
+    Gm[f] = acc;
+  }
+  __syncthreads();
+  wg_tridiagonalize(Gm, n, n, sh);
+  const bool ok = wg_band_qr(U, n, n, sh);
+  for (int a = tid; a < n; a += blockDim.x) s_perm[a] = a;   // all columns, any order
+  __syncthreads();
+  wg_back_transform(Gm, n, n, U, n, s_perm, n, sh);
+  double smin = 1e300;
+  for (int a = 0; a < n; ++a) smin = fmin(smin, sh.d[a]);
+  // T = M U S^-1 (column a scaled by 1/sqrt(sigma_a^2))
+  for (int f = tid; f < n * n; f += blockDim.x) {
+    const int i = f / n, a = f - i * n;
+    double acc = 0.0;
+    for (int k = 0; k < n; ++k) acc += Mm[i * n + k] * U[static_cast<size_t>(a) * n + k];
+    T[f] = acc / sqrt(fmax(sh.d[a], 1e-300));
+  }
+  __syncthreads();
+  for (int f = tid; f < n * n; f += blockDim.x) {
+    const int i = f / n, j = f - i * n;
+    double acc = 0.0;
+    for (int a = 0; a < n; ++a) acc += T[i * n + a] * U[static_cast<size_t>(a) * n + j];
+    D[static_cast<size_t>(i) * NP + j] = acc - (i == j ? 1.0 : 0.0);
+  }
+  if (tid == 0) {
+    leak[g] = 1.0 - smin;
+    if (!ok) status[c] |= 4;
+  }
+}
+
+// Full spectrum: M is orthogonal up to rounding; leakage from column norms.
+__global__ void k_leak_columns(const double* dlt, int NP, int n, int g0, int count, double* leak) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= count) return;
+  const int g = g0 + c;
+  const double* D = dlt + static_cast<size_t>(g) * NP * NP;
+  double worst = 0.0;
+  for (int b = 0; b < n; ++b) {
+    double s = 0.0;
+    for (int a = 0; a < n; ++a) {
+      const double o = D[static_cast<size_t>(a) * NP + b] + (a == b ? 1.0 : 0.0);
+      s += o * o;
+    }
+    worst = fmax(worst, 1.0 - s);
+  }
+  leak[g] = worst;
+}
+
+__device__ double gamma_ohmic(double w, double eta, double wc, double T) {
+  if (w == 0.0) return 2.0 * M_PI * eta * T;
+  return 2.0 * M_PI * eta * w * exp(-fabs(w) / wc) / (-expm1(-w / T));
+}
+
+// R[g][i][b][a] and zdiag[g][i][b] from z (row-major [g-local][i][a][b], ld n).
+__global__ void k_rates(const double* __restrict__ z, const double* __restrict__ E, int n, int NP, int nq, int g0,
+                        int count, double eta, double wc, double T, double* __restrict__ R,
+                        double* __restrict__ zdiag) {
+  const int64_t per = static_cast<int64_t>(nq) * NP * NP;
+  const int64_t idx = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (idx >= per * count) return;
+  const int c = static_cast<int>(idx / per);
+  int64_t r = idx - c * per;
+  const int i = static_cast<int>(r / (static_cast<int64_t>(NP) * NP));
+  r -= static_cast<int64_t>(i) * NP * NP;
+  const int b = static_cast<int>(r / NP), a = static_cast<int>(r - static_cast<int64_t>(b) * NP);
+  const int g = g0 + c;
+  double val = 0.0;
+  if (a < n && b < n) {
+    const double zab = z[((static_cast<size_t>(c) * nq + i) * n + a) * n + b];
+    const double w = (a == b) ? 0.0 : E[static_cast<size_t>(g) * NP + b] - E[static_cast<size_t>(g) * NP + a];
+    val = gamma_ohmic(w, eta, wc, T) * zab * zab;
+    if (a == b) zdiag[(static_cast<size_t>(g) * nq + i) * NP + b] = zab;
+  } else if (a == b) {
+    zdiag[(static_cast<size_t>(g) * nq + i) * NP + b] = 0.0;
+  }
+  R[((static_cast<size_t>(g) * nq + i) * NP + b) * NP + a] = val;
+}
+
+// Initial state: ground state of H(s_0) (row 0 of V0) in the grid-1 basis.
+__global__ void k_cinit(const double* __restrict__ V0, const double* __restrict__ V1, int N, int n, int NP,
+                        double* __restrict__ cinit, double* __restrict__ leak) {
+  __shared__ double s_c[kEigMaxN];
+  __shared__ double red[4];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  for (int a = wave; a < n; a += 4) {
+    double acc = 0.0;
+    for (int x = lane; x < N; x += 64) acc += V1[static_cast<size_t>(a) * N + x] * V0[x];
+    acc = wave_sum(acc);
+    if (lane == 0) s_c[a] = acc;
+  }
+  __syncthreads();
+  double part = 0.0;
+  for (int a = tid; a < n; a += blockDim.x) part += s_c[a] * s_c[a];
+  part = wave_sum(part);
+  if (lane == 0) red[wave] = part;
+  __syncthreads();
+  const double nn = red[0] + red[1] + red[2] + red[3];
+  const double inv = 1.0 / sqrt(nn);
+  for (int a = tid; a < NP; a += blockDim.x) cinit[a] = (a < n) ? s_c[a] * inv : 0.0;
+  if (tid == 0) leak[1] = 1.0 - nn;
+}
+
+aqt_status launch_gemm(aqt_ctx* ctx, const GemmArgs& g, int batch) {
+  dim3 grid(static_cast<unsigned>((g.rb + 63) / 64), static_cast<unsigned>((g.ra + 63) / 64),
+            static_cast<unsigned>(batch));
+  hipLaunchKernelGGL(k_gemm_f64, grid, dim3(256), 0, ctx->stream, g);
+  AQT_HIP(ctx, hipGetLastError());
+  return AQT_OK;
+}
+
+}  // namespace
+
+aqt_status precompute_tables(aqt_ctx* ctx, int M, int n, double tol) {
+  const int nq = ctx->nq;
+  const int N = 1 << nq;
+  if (N > kEigMaxN) return ctx->fail(AQT_EINVAL, "dense eigensolver path needs 2^n_qubits <= 1024");
+  if (n < N && n > 128) return ctx->fail(AQT_EINVAL, "truncated spectra are limited to n <= 128 levels");
+  const int NP = padded_levels(n);
+  const int ncols = std::min(N, n + 16);
+  hipStream_t st = ctx->stream;
+
+  // ---- schedule samples and Ising diagonal
+  std::vector<double> Ag(M), Bg(M);
+  const int nc = static_cast<int>(ctx->A_ctrl.size());
+  for (int g = 0; g < M; ++g) {
+    const double s = static_cast<double>(g) / (M - 1);
+    const double u = s * (nc - 1);
+    int j = std::min(static_cast<int>(std::floor(u)), nc - 2);
+    const double f = u - j;
+    Ag[g] = ctx->A_ctrl[j] * (1.0 - f) + ctx->A_ctrl[j + 1] * f;
+    Bg[g] = ctx->B_ctrl[j] * (1.0 - f) + ctx->B_ctrl[j + 1] * f;
+  }
+  DevBuf dA, dB, dh, dJ, eZ;
+  if (dA.reserve(M * 8) || dB.reserve(M * 8) || dh.reserve(nq * 8) || dJ.reserve(nq * nq * 8) || eZ.reserve(N * 8))
+    return ctx->fail(AQT_ENOMEM, "precompute allocation failed");
+  AQT_HIP(ctx, hipMemcpyAsync(dA.p, Ag.data(), M * 8, hipMemcpyHostToDevice, st));
+  AQT_HIP(ctx, hipMemcpyAsync(dB.p, Bg.data(), M * 8, hipMemcpyHostToDevice, st));
+  AQT_HIP(ctx, hipMemcpyAsync(dh.p, ctx->h.data(), nq * 8, hipMemcpyHostToDevice, st));
+  AQT_HIP(ctx, hipMemcpyAsync(dJ.p, ctx->J.data(), nq * nq * 8, hipMemcpyHostToDevice, st));
+  hipLaunchKernelGGL(k_ising_diag, dim3(nblk(N)), dim3(256), 0, st, dh.as<double>(), dJ.as<double>(), nq,
+                     eZ.as<double>());
+  AQT_HIP(ctx, hipGetLastError());
+
+  // ---- tables
+  ctx->M = M;
+  ctx->n = n;
+  ctx->NP = NP;
+  ctx->dt = ctx->t_f / (M - 1);
+  const size_t sNP = static_cast<size_t>(NP);
+  if (ctx->E.reserve(M * sNP * 8) || ctx->gs.reserve(M * 4) || ctx->dlt.reserve(M * sNP * sNP * 8) ||
+      ctx->cinit.reserve(sNP * 8) || ctx->R.reserve(static_cast<size_t>(M) * nq * sNP * sNP * 8) ||
+      ctx->zdiag.reserve(static_cast<size_t>(M) * nq * sNP * 8) || ctx->leak.reserve(M * 8))
+    return ctx->fail(AQT_ENOMEM, "table allocation failed");
+  AQT_HIP(ctx, hipMemsetAsync(ctx->dlt.p, 0, M * sNP * sNP * 8, st));
+  AQT_HIP(ctx, hipMemsetAsync(ctx->R.p, 0, static_cast<size_t>(sNP) * sNP * nq * 8, st));       // g = 0 unused
+  AQT_HIP(ctx, hipMemsetAsync(ctx->zdiag.p, 0, static_cast<size_t>(sNP) * nq * 8, st));
+  AQT_HIP(ctx, hipMemsetAsync(ctx->leak.p, 0, M * 8, st));
+
+  // ---- chunked workspace
+  const size_t per_grid = 2 * static_cast<size_t>(N) * N            // H, Z
+                          + static_cast<size_t>(ncols) * N            // canonical V
+                          + 2 * static_cast<size_t>(ncols) * ncols + static_cast<size_t>(ncols) * N  // canon ws
+                          + static_cast<size_t>(nq) * n * n           // z
+                          + 4 * static_cast<size_t>(n) * n            // polar ws
+                          + N;                                        // Eraw
+  const size_t budget = size_t(2) << 30;
+  int Gc = static_cast<int>(std::max<size_t>(1, std::min<size_t>(M, budget / (per_grid * 8))));
+  DevBuf H, Z, Vc, Vprev, cws, zws, pws, Eraw, perm, status;
+  if (H.reserve(static_cast<size_t>(Gc) * N * N * 8) || Z.reserve(static_cast<size_t>(Gc) * N * N * 8) ||
+      Vc.reserve(static_cast<size_t>(Gc) * ncols * N * 8) || Vprev.reserve(static_cast<size_t>(ncols) * N * 8) ||
+      cws.reserve(static_cast<size_t>(Gc) * (2 * static_cast<size_t>(ncols) * ncols + static_cast<size_t>(ncols) * N) * 8) ||
+      zws.reserve(static_cast<size_t>(Gc) * nq * n * n * 8) || pws.reserve(static_cast<size_t>(Gc) * 4 * n * n * 8) ||
+      Eraw.reserve(static_cast<size_t>(Gc) * N * 8) || perm.reserve(static_cast<size_t>(Gc) * N * 4) ||
+      status.reserve(static_cast<size_t>(Gc) * 4))
+    return ctx->fail(AQT_ENOMEM, "precompute workspace allocation failed");
+  std::vector<int> hstat(Gc);
+  const size_t Vstride = static_cast<size_t>(ncols) * N;
+
+  for (int g0 = 0; g0 < M; g0 += Gc) {
+    const int cnt = std::min(Gc, M - g0);
+    hipLaunchKernelGGL(k_build_dense, dim3(nblk(static_cast<int64_t>(N) * N * cnt)), dim3(256), 0, st,
+                       eZ.as<double>(), nq, dA.as<double>(), dB.as<double>(), g0, cnt, H.as<double>());
+    AQT_HIP(ctx, hipGetLastError());
+    hipLaunchKernelGGL(k_dense_eig, dim3(cnt), dim3(kEigThreads), 0, st, H.as<double>(), Z.as<double>(), N, ncols,
+                       Eraw.as<double>(), perm.as<int>(), status.as<int>());
+    AQT_HIP(ctx, hipGetLastError());
+    hipLaunchKernelGGL(k_canon, dim3(cnt), dim3(kEigThreads), 0, st, Z.as<double>(), perm.as<int>(),
+                       Eraw.as<double>(), N, ncols, n, NP, tol, g0, Vc.as<double>(), ctx->E.as<double>(),
+                       ctx->gs.as<int>(), cws.as<double>(), status.as<int>());
+    AQT_HIP(ctx, hipGetLastError());
+    AQT_HIP(ctx, hipMemcpyAsync(hstat.data(), status.p, cnt * 4, hipMemcpyDeviceToHost, st));
+    AQT_HIP(ctx, hipStreamSynchronize(st));
+    for (int c = 0; c < cnt; ++c)
+      if (hstat[c]) return ctx->fail(AQT_ENUMERIC, "eigensolver did not converge at grid point " + std::to_string(g0 + c));
+    if (g0 == 0) {
+      int gs0 = 0;
+      AQT_HIP(ctx, hipMemcpy(&gs0, ctx->gs.p, 4, hipMemcpyDeviceToHost));
+      if (gs0 != 1) return ctx->fail(AQT_ENUMERIC, "ground state of H(s=0) is degenerate; initial state undefined");
+    }
+    // overlaps into grid g from g-1 (g >= 2); the first grid of a chunk pairs with Vprev
+    for (int c = 0; c < cnt; ++c) {
+      const int g = g0 + c;
+      const double* Vg = Vc.as<double>() + c * Vstride;
+      const double* Vp = (c == 0) ? Vprev.as<double>() : Vc.as<double>() + (c - 1) * Vstride;
+      if (g == 1) {
+        hipLaunchKernelGGL(k_cinit, dim3(1), dim3(256), 0, st, Vp, Vg, N, n, NP, ctx->cinit.as<double>(),
+                           ctx->leak.as<double>());
+        AQT_HIP(ctx, hipGetLastError());
+      }
+      if (g >= 2 && c == 0) {
+        GemmArgs ga{Vg, Vp, ctx->dlt.as<double>() + static_cast<size_t>(g) * NP * NP, 0, 0, 0, n, n, N, N, N, NP, 0, nq, 1};
+        aqt_status s = launch_gemm(ctx, ga, 1);
+        if (s != AQT_OK) return s;
+      }
+    }
+    {
+      // batched overlaps for the grid points whose predecessor is in the chunk
+      const int first = std::max(1, (g0 == 0) ? 2 : 1);   // chunk-local index
+      const int count = cnt - first;
+      if (count > 0) {
+        GemmArgs ga{Vc.as<double>() + first * Vstride, Vc.as<double>() + (first - 1) * Vstride,
+                    ctx->dlt.as<double>() + static_cast<size_t>(g0 + first) * NP * NP, static_cast<int64_t>(Vstride),
+                    static_cast<int64_t>(Vstride), static_cast<int64_t>(NP) * NP, n, n, N, N, N, NP, 0, nq, 1};
+        aqt_status s = launch_gemm(ctx, ga, count);
+        if (s != AQT_OK) return s;
+      }
+    }
+    const int pg0 = std::max(g0, 2), pcnt = g0 + cnt - pg0;
+    if (pcnt > 0) {
+      if (n < N) {
+        hipLaunchKernelGGL(k_polar, dim3(pcnt), dim3(kEigThreads), 0, st, ctx->dlt.as<double>(), NP, n, pg0,
+                           ctx->leak.as<double>(), pws.as<double>(), status.as<int>() + (pg0 - g0));
+      } else {
+        hipLaunchKernelGGL(k_leak_columns, dim3(nblk(pcnt, 64)), dim3(64), 0, st, ctx->dlt.as<double>(), NP, n,
+                           pg0, pcnt, ctx->leak.as<double>());
+      }
+      AQT_HIP(ctx, hipGetLastError());
+    }
+    // matrix elements z_i = V diag(sz_i) V^T and rate tables for g >= 1
+    const int zg0 = std::max(g0, 1), zcnt = g0 + cnt - zg0;
+    if (zcnt > 0) {
+      const int off = zg0 - g0;
+      GemmArgs ga{Vc.as<double>() + off * Vstride, Vc.as<double>() + off * Vstride, zws.as<double>(),
+                  static_cast<int64_t>(Vstride), static_cast<int64_t>(Vstride), static_cast<int64_t>(n) * n,
+                  n, n, N, N, N, n, 1, nq, 0};
+      aqt_status s = launch_gemm(ctx, ga, zcnt * nq);
+      if (s != AQT_OK) return s;
+      hipLaunchKernelGGL(k_rates, dim3(nblk(static_cast<int64_t>(nq) * NP * NP * zcnt)), dim3(256), 0, st,
+                         zws.as<double>(), ctx->E.as<double>(), n, NP, nq, zg0, zcnt, ctx->eta, ctx->omega_c, ctx->T,
+                         ctx->R.as<double>(), ctx->zdiag.as<double>());
+      AQT_HIP(ctx, hipGetLastError());
+    }
+    AQT_HIP(ctx, hipMemcpyAsync(Vprev.p, Vc.as<double>() + (cnt - 1) * Vstride, Vstride * 8, hipMemcpyDeviceToDevice, st));
+    AQT_HIP(ctx, hipMemcpyAsync(hstat.data(), status.p, cnt * 4, hipMemcpyDeviceToHost, st));
+    AQT_HIP(ctx, hipStreamSynchronize(st));
+    for (int c = 0; c < cnt; ++c)
+      if (hstat[c]) return ctx->fail(AQT_ENUMERIC, "polar factor eigensolver failed at grid " + std::to_string(g0 + c));
+  }
+  return AQT_OK;
+}
+
+}  // namespace aqt

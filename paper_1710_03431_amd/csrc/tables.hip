@@ -1,0 +1,168 @@
+// Derived tables and MFMA operand packing for the trajectory kernel.
+//
+// finish_tables: Gamma_b = sum_{i,a} R[i][b][a], the diagonal of
+//   sum_i A_i^dag A_i (Sec. III eq. Heff with the rates absorbed, eq. Aired),
+//   and d_b = exp(-i e_b dt - Gamma_b dt / 2), the no-jump propagator over one
+//   step of the diagonal effective Hamiltonian (Sec. III eq. detun).
+// pack_for_precision: Delta = O - I rearranged into 16x16 MFMA A-operand
+//   fragments (64 lanes contiguous) in the state precision; for BF16 two
+//   fragment sets (hi, lo) with Delta ~ hi + lo.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+
+#include "common.hpp"
+#include "ctx.hpp"
+
+namespace aqt {
+namespace {
+
+__global__ void k_gamma_phase(const double* __restrict__ E, const double* __restrict__ R, int M, int NP, int n,
+                              int nq, double dt, double* __restrict__ Gamma, double* __restrict__ dre,
+                              double* __restrict__ dim) {
+  const int64_t idx = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (idx >= static_cast<int64_t>(M) * NP) return;
+  const int g = static_cast<int>(idx / NP);
+  const int b = static_cast<int>(idx - static_cast<int64_t>(g) * NP);
+  double G = 0.0;
+  if (b < n) {
+    for (int i = 0; i < nq; ++i) {
+      const double* row = R + ((static_cast<size_t>(g) * nq + i) * NP + b) * NP;
+      for (int a = 0; a < n; ++a) G += row[a];
+    }
+  }
+  Gamma[idx] = G;
+  if (b < n) {
+    double sn, cs;
+    sincos(E[idx] * dt, &sn, &cs);
+    const double mag = exp(-0.5 * G * dt);
+    dre[idx] = mag * cs;
+    dim[idx] = -mag * sn;
+  } else {
+    dre[idx] = 0.0;
+    dim[idx] = 0.0;
+  }
+}
+
+template <class T>
+__global__ void k_pack_k4(const double* __restrict__ dlt, int M, int NP, T* __restrict__ out) {
+  // out[((g*NRT + rt)*(NP/4) + kc)*64 + l] = Delta[g][16 rt + l%16][4 kc + l/16]
+  const int64_t idx = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  const int64_t per_g = static_cast<int64_t>(NP) * NP;
+  if (idx >= per_g * M) return;
+  const int g = static_cast<int>(idx / per_g);
+  int64_t r = idx - g * per_g;
+  const int l = static_cast<int>(r & 63);
+  r >>= 6;
+  const int kc = static_cast<int>(r % (NP / 4));
+  const int rt = static_cast<int>(r / (NP / 4));
+  const int row = 16 * rt + (l & 15);
+  const int col = 4 * kc + (l >> 4);
+  out[idx] = static_cast<T>(dlt[(static_cast<size_t>(g) * NP + row) * NP + col]);
+}
+
+__device__ __forceinline__ uint32_t bf16_rne_bits(float x) {
+  uint32_t u = __float_as_uint(x);
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return u >> 16;
+}
+
+__global__ void k_pack_bf16(const double* __restrict__ dlt, int M, int NP, uint4* __restrict__ hi,
+                            uint4* __restrict__ lo) {
+  // fragment (g, rt, kc, l) holds Delta[g][16 rt + l%16][32 kc + 8 (l/16) + j], j = 0..7
+  const int64_t idx = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  const int64_t per_g = static_cast<int64_t>(NP) * NP / 8;
+  if (idx >= per_g * M) return;
+  const int g = static_cast<int>(idx / per_g);
+  int64_t r = idx - g * per_g;
+  const int l = static_cast<int>(r & 63);
+  r >>= 6;
+  const int kc = static_cast<int>(r % (NP / 32));
+  const int rt = static_cast<int>(r / (NP / 32));
+  const int row = 16 * rt + (l & 15);
+  const int col0 = 32 * kc + 8 * (l >> 4);
+  uint32_t h[4], w[4];
+  for (int j = 0; j < 4; ++j) {
+    uint32_t hb[2], lb[2];
+    for (int e = 0; e < 2; ++e) {
+      const double x = dlt[(static_cast<size_t>(g) * NP + row) * NP + col0 + 2 * j + e];
+      const uint32_t hh = bf16_rne_bits(static_cast<float>(x));
+      const double rest = x - static_cast<double>(__uint_as_float(hh << 16));
+      hb[e] = hh;
+      lb[e] = bf16_rne_bits(static_cast<float>(rest));
+    }
+    h[j] = hb[0] | (hb[1] << 16);
+    w[j] = lb[0] | (lb[1] << 16);
+  }
+  hi[idx] = make_uint4(h[0], h[1], h[2], h[3]);
+  lo[idx] = make_uint4(w[0], w[1], w[2], w[3]);
+}
+
+__global__ void k_to_f32(const double* __restrict__ in, float* __restrict__ out, int64_t count) {
+  const int64_t idx = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (idx < count) out[idx] = static_cast<float>(in[idx]);
+}
+
+inline unsigned blocks_for(int64_t count, int threads = 256) {
+  return static_cast<unsigned>((count + threads - 1) / threads);
+}
+
+}  // namespace
+
+aqt_status finish_tables(aqt_ctx* ctx) {
+  const int64_t cnt = static_cast<int64_t>(ctx->M) * ctx->NP;
+  if (ctx->Gamma.reserve(cnt * sizeof(double)) != hipSuccess || ctx->dre.reserve(cnt * sizeof(double)) != hipSuccess ||
+      ctx->dim.reserve(cnt * sizeof(double)) != hipSuccess)
+    return ctx->fail(AQT_ENOMEM, "table allocation failed");
+  hipLaunchKernelGGL(k_gamma_phase, dim3(blocks_for(cnt)), dim3(256), 0, ctx->stream, ctx->E.as<double>(),
+                     ctx->R.as<double>(), ctx->M, ctx->NP, ctx->n, ctx->nq, ctx->dt, ctx->Gamma.as<double>(),
+                     ctx->dre.as<double>(), ctx->dim.as<double>());
+  AQT_HIP(ctx, hipGetLastError());
+  ctx->packed_for = -1;
+  return AQT_OK;
+}
+
+aqt_status pack_for_precision(aqt_ctx* ctx, int precision) {
+  if (ctx->packed_for == precision) return AQT_OK;
+  const int64_t nd = static_cast<int64_t>(ctx->M) * ctx->NP * ctx->NP;
+  const int64_t nv = static_cast<int64_t>(ctx->M) * ctx->NP;
+  ctx->pk_a.release();
+  ctx->pk_b.release();
+  ctx->pk_dre.release();
+  ctx->pk_dim.release();
+  if (precision == AQT_FP64) {
+    if (ctx->pk_a.reserve(nd * 8) != hipSuccess || ctx->pk_dre.reserve(nv * 8) != hipSuccess ||
+        ctx->pk_dim.reserve(nv * 8) != hipSuccess)
+      return ctx->fail(AQT_ENOMEM, "operand allocation failed");
+    hipLaunchKernelGGL(k_pack_k4<double>, dim3(blocks_for(nd)), dim3(256), 0, ctx->stream, ctx->dlt.as<double>(),
+                       ctx->M, ctx->NP, ctx->pk_a.as<double>());
+    AQT_HIP(ctx, hipMemcpyAsync(ctx->pk_dre.p, ctx->dre.p, nv * 8, hipMemcpyDeviceToDevice, ctx->stream));
+    AQT_HIP(ctx, hipMemcpyAsync(ctx->pk_dim.p, ctx->dim.p, nv * 8, hipMemcpyDeviceToDevice, ctx->stream));
+  } else {
+    if (ctx->pk_dre.reserve(nv * 4) != hipSuccess || ctx->pk_dim.reserve(nv * 4) != hipSuccess)
+      return ctx->fail(AQT_ENOMEM, "operand allocation failed");
+    if (precision == AQT_FP32) {
+      if (ctx->pk_a.reserve(nd * 4) != hipSuccess) return ctx->fail(AQT_ENOMEM, "operand allocation failed");
+      hipLaunchKernelGGL(k_pack_k4<float>, dim3(blocks_for(nd)), dim3(256), 0, ctx->stream, ctx->dlt.as<double>(),
+                         ctx->M, ctx->NP, ctx->pk_a.as<float>());
+    } else if (precision == AQT_BF16) {
+      if (ctx->NP < 32) return ctx->fail(AQT_EINVAL, "BF16 stepping needs n > 16");
+      if (ctx->pk_a.reserve(nd * 2) != hipSuccess || ctx->pk_b.reserve(nd * 2) != hipSuccess)
+        return ctx->fail(AQT_ENOMEM, "operand allocation failed");
+      hipLaunchKernelGGL(k_pack_bf16, dim3(blocks_for(nd / 8)), dim3(256), 0, ctx->stream, ctx->dlt.as<double>(),
+                         ctx->M, ctx->NP, ctx->pk_a.as<uint4>(), ctx->pk_b.as<uint4>());
+    } else {
+      return ctx->fail(AQT_EINVAL, "unknown precision");
+    }
+    AQT_HIP(ctx, hipGetLastError());
+    hipLaunchKernelGGL(k_to_f32, dim3(blocks_for(nv)), dim3(256), 0, ctx->stream, ctx->dre.as<double>(),
+                       ctx->pk_dre.as<float>(), nv);
+    hipLaunchKernelGGL(k_to_f32, dim3(blocks_for(nv)), dim3(256), 0, ctx->stream, ctx->dim.as<double>(),
+                       ctx->pk_dim.as<float>(), nv);
+  }
+  AQT_HIP(ctx, hipGetLastError());
+  ctx->packed_for = precision;
+  return AQT_OK;
+}
+
+}  // namespace aqt
