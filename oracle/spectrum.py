@@ -22,7 +22,9 @@ What is computed, per grid point s_g = g/(M-1), g = 0..M-1, t = s t_f:
 * truncation to the n lowest levels;
 * per grid g >= 1 the tables used by the step that ends at s_g (generator
   frozen at the right end point):
-    O_g     = polar factor of V_g^T V_{g-1}     (basis change, g >= 2)
+    O_g     = polar factor of V_g^T V_{g-1}     (basis change, g >= 2; directions
+              with singular value <= 1e-4, lost by the truncation, are completed
+              in a canonical basis so that O_g stays orthogonal)
     c_init  = V_1^T psi_0 / |V_1^T psi_0|      (g = 1; psi_0 = ground state of H(s_0))
     z_g[i,a,b] = <a| sz_i |b>                   (eq. Lindblad2 matrix elements)
     R_g[i,b,a] = gamma(e_b - e_a) z^2 (a != b), gamma(0) z_bb^2 (a == b)
@@ -111,9 +113,37 @@ def eigen(inst, s: float, n_keep: int, deg_tol: float, guard: int = 16):
     return E[:n_keep], V[:, :n_keep], gs
 
 
-def polar(M: np.ndarray):
+def _sign_fixed(v: np.ndarray) -> np.ndarray:
+    mags = np.abs(v)
+    first = int(np.argmax(mags >= (1.0 - 1e-9) * mags.max()))
+    return v if v[first] >= 0 else -v
+
+
+def _canonical_basis(P: np.ndarray, k: int) -> np.ndarray:
+    """k orthonormal columns spanning the range of the projector P, made unique by
+    diagonalising P diag(1..n) P (generic weights) and the column sign rule."""
+    n = P.shape[0]
+    K = P @ np.diag(np.arange(1.0, n + 1.0)) @ P
+    w, Q = np.linalg.eigh(0.5 * (K + K.T))
+    cols = [_sign_fixed(Q[:, j]) for j in range(n - k, n)]   # the k non-zero eigenvalues, ascending
+    return np.stack(cols, axis=1)
+
+
+def polar(M: np.ndarray, tau: float = 1e-4):
+    """Polar factor U W^T of M (SVD).  Directions with singular value <= tau carry no
+    overlap (the retained subspace lost them); they are mapped onto the left directions
+    not reached by the others, both taken in the canonical basis above, so the factor
+    stays orthogonal and reproducible."""
     U, S, Wt = np.linalg.svd(M)
-    return U @ Wt, S
+    good = S > tau
+    P = U[:, good] @ Wt[good]
+    k = int((~good).sum())
+    if k:
+        n = M.shape[0]
+        right = _canonical_basis(Wt[~good].T @ Wt[~good], k)
+        left = _canonical_basis(np.eye(n) - U[:, good] @ U[:, good].T, k)
+        P = P + left @ right.T
+    return P, S
 
 
 def grid_tables(inst, E: np.ndarray, V: np.ndarray, dt: float):
