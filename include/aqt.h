@@ -84,7 +84,7 @@ typedef struct {
   uint64_t seed;            /* Philox key word 0                                    */
   uint64_t instance_id;     /* Philox key word 1                                    */
   uint64_t traj_offset;     /* trajectory ids are traj_offset .. traj_offset+K-1     */
-  int32_t tile;             /* trajectories per workgroup, multiple of 16 (0: auto)  */
+  int32_t tile;             /* trajectories per workgroup: 8, 16, 32, 40 or 64 (0: auto) */
   int32_t reserved;
 } aqt_run_params;
 
@@ -156,6 +156,28 @@ AQT_API aqt_status aqt_get_dims(aqt_ctx* ctx, int32_t* n_grid, int32_t* n_levels
  * Never synchronises.  Records beyond record_capacity are dropped; jump_count
  * still holds the true number of jumps of each trajectory. */
 AQT_API aqt_status aqt_run(aqt_ctx* ctx, const aqt_run_params* params, const aqt_outputs* out);
+
+/* ---- Batched runs: many instances in one persistent launch --------------------------
+ * Each context (with tables loaded) is one instance with its own run parameters and
+ * output buffers.  One kernel launch runs every (instance, tile) work item from an
+ * atomic queue, longest items first, then one fixed-order reduction writes every
+ * instance's observable sums.  All contexts must be on one device and use one
+ * precision.  flags: AQT_BATCH_GRAPH captures the launch sequence once into a HIP
+ * graph (replayed by aqt_batch_launch); AQT_BATCH_AUTOTUNE times the supported tile
+ * sizes per level count on a shortened anneal and keeps the fastest (instances
+ * with a non-zero params[i].tile keep theirs).  Output pointers are bound at
+ * creation.  On failure *out may still receive a batch whose aqt_batch_last_error
+ * explains the failure; it must be destroyed.  Launches on the first context's
+ * stream; jump_totals and net_hist accumulate across launches. */
+typedef struct aqt_batch aqt_batch;
+enum { AQT_BATCH_GRAPH = 1, AQT_BATCH_AUTOTUNE = 2 };
+AQT_API aqt_status aqt_batch_create(aqt_batch** out, aqt_ctx* const* ctxs, int n, const aqt_run_params* params,
+                                    const aqt_outputs* outs, int flags);
+AQT_API aqt_status aqt_batch_launch(aqt_batch* batch);
+/* Trajectories per workgroup tile chosen for each instance (host array [n]). */
+AQT_API aqt_status aqt_batch_tiles(const aqt_batch* batch, int32_t* tile_per_instance);
+AQT_API const char* aqt_batch_last_error(const aqt_batch* batch);
+AQT_API void aqt_batch_destroy(aqt_batch* batch);
 
 #ifdef __cplusplus
 }

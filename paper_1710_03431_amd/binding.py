@@ -22,7 +22,9 @@ KIND_NAMES = ("relax", "excite", "dephase")
 
 EXPORTED = ("aqt_create", "aqt_destroy", "aqt_last_error", "aqt_version", "aqt_set_hamiltonian",
             "aqt_set_schedule", "aqt_set_bath", "aqt_precompute", "aqt_set_tables", "aqt_get_tables",
-            "aqt_get_dims", "aqt_run")
+            "aqt_get_dims", "aqt_run", "aqt_batch_create", "aqt_batch_launch", "aqt_batch_tiles",
+            "aqt_batch_last_error", "aqt_batch_destroy")
+BATCH_GRAPH, BATCH_AUTOTUNE = 1, 2
 
 
 class Jump(C.Structure):
@@ -64,6 +66,9 @@ def load_library(path: str = LIB_PATH):
         return _lib
     if not os.path.exists(path):
         raise ImportError(f"{path} is missing: build it with `python -m paper_1710_03431_amd.build`")
+    # torch bundles its own HIP runtime under the same soname as /opt/rocm's; load it
+    # first so that libaqt and torch share one runtime (streams, allocations).
+    import torch  # noqa: F401
     lib = C.CDLL(path)
     dp = C.POINTER(C.c_double)
     ip = C.POINTER(C.c_int32)
@@ -82,8 +87,16 @@ def load_library(path: str = LIB_PATH):
     lib.aqt_get_tables.argtypes = [ctx, dp, ip, dp, dp, dp, dp, dp, dp]
     lib.aqt_get_dims.argtypes = [ctx, ip, ip, ip]
     lib.aqt_run.argtypes = [ctx, C.POINTER(RunParams), C.POINTER(Outputs)]
+    lib.aqt_batch_create.argtypes = [C.POINTER(C.c_void_p), C.POINTER(C.c_void_p), C.c_int,
+                                     C.POINTER(RunParams), C.POINTER(Outputs), C.c_int]
+    lib.aqt_batch_launch.argtypes = [C.c_void_p]
+    lib.aqt_batch_tiles.argtypes = [C.c_void_p, ip]
+    lib.aqt_batch_last_error.argtypes = [C.c_void_p]
+    lib.aqt_batch_last_error.restype = C.c_char_p
+    lib.aqt_batch_destroy.argtypes = [C.c_void_p]
+    lib.aqt_batch_destroy.restype = None
     for name in EXPORTED:
-        if name not in ("aqt_destroy", "aqt_last_error"):
+        if name not in ("aqt_destroy", "aqt_last_error", "aqt_batch_last_error", "aqt_batch_destroy"):
             getattr(lib, name).restype = C.c_int
     _lib = lib
     return lib
@@ -119,7 +132,7 @@ class Engine:
         h = C.c_void_p()
         st = self.lib.aqt_create(C.byref(h), device, C.c_void_p(stream.cuda_stream))
         if st != AQT_OK:
-            raise AqtError(st, "aqt_create failed")
+            raise AqtError(st, f"aqt_create failed on device {device} (no usable HIP device?)")
         self.ctx = h
         self.n_grid = self.n_levels = self.n_qubits = None
 
@@ -242,3 +255,83 @@ class Engine:
         if final_state:
             res["final_state"] = res["final_state"].reshape(n_traj, self.n_levels, 2)
         return res
+
+
+def _params(n_traj, precision, seed, instance_id, traj_offset, record_capacity, tile):
+    prec = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+    return RunParams(precision=prec, record_capacity=int(record_capacity), n_traj=int(n_traj), seed=int(seed),
+                     instance_id=int(instance_id), traj_offset=int(traj_offset), tile=int(tile), reserved=0)
+
+
+def _outputs(outs):
+    def ptr(k):
+        v = outs.get(k)
+        return None if v is None else v.data_ptr()
+    return Outputs(pgs_sum=ptr("pgs_sum"), pgs_sumsq=ptr("pgs_sumsq"), jump_totals=ptr("jump_totals"),
+                   jump_count=ptr("jump_count"), jumps=ptr("jumps"), net_gs=ptr("net_gs"),
+                   net_hist=ptr("net_hist"), hist_lo=int(outs["hist"][0]), hist_hi=int(outs["hist"][1]),
+                   final_state=ptr("final_state"))
+
+
+class Batch:
+    """Many instances (Engines with tables) run by one persistent launch (aqt_batch_*).
+
+    runs: list of dicts with keys n_traj, seed, instance_id, traj_offset, record_capacity, tile.
+    Output buffers are allocated here and bound at creation; launch() replays them.
+    """
+
+    def __init__(self, engines, runs, precision="bf16", graph=True, autotune=True, hist=(-64, 64)):
+        self.engines = list(engines)
+        self.lib = load_library()
+        n = len(self.engines)
+        self.outs = []
+        params = (RunParams * n)()
+        outs = (Outputs * n)()
+        ctxs = (C.c_void_p * n)()
+        for i, (eng, r) in enumerate(zip(self.engines, runs)):
+            o = eng.alloc_outputs(r["n_traj"], r.get("record_capacity", 0), hist)
+            self.outs.append(o)
+            params[i] = _params(r["n_traj"], precision, r.get("seed", 0), r.get("instance_id", i),
+                                r.get("traj_offset", 0), r.get("record_capacity", 0), r.get("tile", 0))
+            outs[i] = _outputs(o)
+            ctxs[i] = eng.ctx
+        self.runs = list(runs)
+        h = C.c_void_p()
+        flags = (BATCH_GRAPH if graph else 0) | (BATCH_AUTOTUNE if autotune else 0)
+        st = self.lib.aqt_batch_create(C.byref(h), ctxs, n, params, outs, flags)
+        if st != AQT_OK:
+            msg = self.lib.aqt_batch_last_error(h).decode() if h.value else "aqt_batch_create failed"
+            if h.value:
+                self.lib.aqt_batch_destroy(h)
+            raise AqtError(st, msg)
+        self.handle = h
+        t = (C.c_int32 * n)()
+        self.lib.aqt_batch_tiles(h, t)
+        self.tiles = list(t)
+
+    def launch(self):
+        st = self.lib.aqt_batch_launch(self.handle)
+        if st != AQT_OK:
+            raise AqtError(st, self.lib.aqt_batch_last_error(self.handle).decode())
+
+    def results(self):
+        """Host copies of every instance's outputs (synchronises the first engine's stream)."""
+        self.engines[0].stream.synchronize()
+        res = []
+        for o, r in zip(self.outs, self.runs):
+            d = {k: v.cpu().numpy() for k, v in o.items() if k not in ("hist", "jumps")}
+            if r.get("record_capacity", 0):
+                d["jumps"] = o["jumps"].cpu().numpy().view(JUMP_DTYPE).reshape(r["n_traj"], r["record_capacity"])
+            res.append(d)
+        return res
+
+    def close(self):
+        if getattr(self, "handle", None):
+            self.lib.aqt_batch_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -38,6 +38,7 @@ struct aqt_ctx {
   aqt::DevBuf R;        // [M][nq][NP(b)][NP(a)]
   aqt::DevBuf zdiag;    // [M][nq][NP]
   aqt::DevBuf Gamma;    // [M][NP]
+  aqt::DevBuf Rq;       // [M][nq][NP] row sums sum_a R[i][b][a] (qubit draw of a jump)
   aqt::DevBuf dre, dim; // [M][NP] FP64 exp(-i e dt - Gamma dt / 2)
   aqt::DevBuf leak;     // [M]
 

@@ -35,7 +35,7 @@ __host__ __device__ __forceinline__ Philox4 philox4x64_10(uint64_t c0, uint64_t 
   constexpr uint64_t kM1 = 0xCA5A826395121157ull;
   constexpr uint64_t kW0 = 0x9E3779B97F4A7C15ull;
   constexpr uint64_t kW1 = 0xBB67AE8584CAA73Bull;
-#pragma unroll
+#pragma unroll 1
   for (int r = 0; r < 10; ++r) {
     if (r) {
       k0 += kW0;

@@ -204,18 +204,23 @@ struct GemmArgs {
   int64_t sA, sB, sC;
   int ra, rb, K, lda, ldb, ldc;
   int wmode, nq, sub_eye;
+  int ksplit = 1;   // > 1: blockIdx.z = batch * ksplit + part, each part sums x in its
+  int kspan = 0;    // span of kspan and writes a compact [ra][rb] partial at C + sC * blockIdx.z
 };
 
 __global__ __launch_bounds__(256) void k_gemm_f64(GemmArgs p) {
   __shared__ double As[64][33];
   __shared__ double Bs[64][33];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int bz = blockIdx.z;
+  const int bz = blockIdx.z / p.ksplit;
+  const int kpart = blockIdx.z - bz * p.ksplit;
+  const int xbeg = (p.ksplit > 1) ? kpart * p.kspan : 0;
+  const int xend = (p.ksplit > 1) ? min(p.K, xbeg + p.kspan) : p.K;
   const int opb = (p.wmode == 1) ? bz / p.nq : bz;
   const int qubit = (p.wmode == 1) ? bz % p.nq : 0;
   const double* A = p.A + p.sA * opb;
   const double* B = p.B + p.sB * opb;
-  double* C = p.C + p.sC * bz;
+  double* C = p.C + p.sC * blockIdx.z;
   const int i0 = blockIdx.y * 64, j0 = blockIdx.x * 64;
   const int wi = (wave >> 1) * 32, wj = (wave & 1) * 32;
   d4 acc[2][2];
@@ -223,13 +228,13 @@ __global__ __launch_bounds__(256) void k_gemm_f64(GemmArgs p) {
   for (int a = 0; a < 2; ++a)
 #pragma unroll
     for (int b = 0; b < 2; ++b) acc[a][b] = d4{0.0, 0.0, 0.0, 0.0};
-  for (int x0 = 0; x0 < p.K; x0 += 32) {
+  for (int x0 = xbeg; x0 < xend; x0 += 32) {
     for (int f = tid; f < 64 * 32; f += 256) {
       const int r = f >> 5, k = f & 31, x = x0 + k;
       double w = 1.0;
       if (p.wmode == 1) w = ((x >> qubit) & 1) ? -1.0 : 1.0;
-      As[r][k] = (i0 + r < p.ra && x < p.K) ? w * A[static_cast<size_t>(i0 + r) * p.lda + x] : 0.0;
-      Bs[r][k] = (j0 + r < p.rb && x < p.K) ? B[static_cast<size_t>(j0 + r) * p.ldb + x] : 0.0;
+      As[r][k] = (i0 + r < p.ra && x < xend) ? w * A[static_cast<size_t>(i0 + r) * p.lda + x] : 0.0;
+      Bs[r][k] = (j0 + r < p.rb && x < xend) ? B[static_cast<size_t>(j0 + r) * p.ldb + x] : 0.0;
     }
     __syncthreads();
 #pragma unroll
@@ -258,33 +263,100 @@ __global__ __launch_bounds__(256) void k_gemm_f64(GemmArgs p) {
         const int j = j0 + wj + 16 * b + (lane & 15);
         if (i < p.ra && j < p.rb) {
           double v = acc[a][b][e];
-          if (p.sub_eye && i == j) v -= 1.0;
-          C[static_cast<size_t>(i) * p.ldc + j] = v;
+          if (p.ksplit > 1) {
+            C[static_cast<size_t>(i) * p.rb + j] = v;   // compact partial
+          } else {
+            if (p.sub_eye && i == j) v -= 1.0;
+            C[static_cast<size_t>(i) * p.ldc + j] = v;
+          }
         }
       }
 }
 
+// out[b][i][j] (ld ldo) = sum over parts of partial[b * ksplit + part][i][j] (- I if sub_eye).
+__global__ void k_splitk_reduce(const double* __restrict__ part, int ksplit, int ra, int rb, int nbatch,
+                                double* __restrict__ out, int64_t s_out, int ldo, int sub_eye) {
+  const int64_t idx = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  const int64_t per = static_cast<int64_t>(ra) * rb;
+  if (idx >= per * nbatch) return;
+  const int b = static_cast<int>(idx / per);
+  const int64_t e = idx - b * per;
+  const int i = static_cast<int>(e / rb), j = static_cast<int>(e - static_cast<int64_t>(i) * rb);
+  double acc = 0.0;
+  for (int k = 0; k < ksplit; ++k) acc += part[(static_cast<int64_t>(b) * ksplit + k) * per + e];
+  if (sub_eye && i == j) acc -= 1.0;
+  out[b * s_out + static_cast<int64_t>(i) * ldo + j] = acc;
+}
+
+// Canonical orthonormal basis of the range of the projector P (n x n, rank k):
+// eigenvectors of P diag(1..n) P for its k largest eigenvalues (ascending), each
+// with the column sign rule.  Writes k columns into out (column-major, ld n).
+__device__ void wg_canonical_range(const double* P, int n, int k, double* K, double* Z, int* perm, double* out,
+                                   EigShared& sh) {
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  for (int f = tid; f < n * n; f += blockDim.x) {
+    const int i = f / n, j = f - i * n;
+    double acc = 0.0;
+    for (int m = 0; m < n; ++m) acc += P[i * n + m] * static_cast<double>(m + 1) * P[m * n + j];
+    K[f] = acc;
+  }
+  __syncthreads();
+  wg_tridiagonalize(K, n, n, sh);
+  wg_band_qr(Z, n, n, sh);
+  wg_rank_ascending(sh.d, n, perm);
+  wg_back_transform(K, n, n, Z, n, perm, n, sh);
+  for (int q = wave; q < k; q += kEigThreads / kWave) {
+    const double* v = Z + static_cast<size_t>(perm[n - k + q]) * n;
+    double mx = 0.0;
+    for (int x = lane; x < n; x += kWave) mx = fmax(mx, fabs(v[x]));
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) mx = fmax(mx, __shfl_xor(mx, o, kWave));
+    int first = n;
+    for (int x = lane; x < n; x += kWave)
+      if (fabs(v[x]) >= (1.0 - 1e-9) * mx) {
+        first = x;
+        break;
+      }
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) first = min(first, __shfl_xor(first, o, kWave));
+    const double sgn = (v[first] < 0.0) ? -1.0 : 1.0;
+    for (int x = lane; x < n; x += kWave) out[static_cast<size_t>(q) * n + x] = sgn * v[x];
+  }
+  __syncthreads();
+}
+
 // Polar factor of the truncated overlap M = O (stored as Delta = M - I in dlt):
-// M^T M = U S^2 U^T, polar(M) = M U S^-1 U^T; leakage 1 - min S^2.
+// M^T M = U S^2 U^T, polar(M) = sum_{s_a > tau} (M u_a / s_a) u_a^T.  Directions
+// with s_a <= tau = 1e-4 (lost by the truncation) are mapped onto the left
+// directions that the others leave free, both in the canonical basis of
+// wg_canonical_range, so the factor stays orthogonal.  Leakage 1 - min S^2.
 __global__ __launch_bounds__(kEigThreads) void k_polar(double* dlt, int NP, int n, int g0, double* leak,
                                                        double* ws, int* status) {
   __shared__ EigShared sh;
   __shared__ int s_perm[kEigMaxN];
+  __shared__ int s_bad[kEigMaxN];
+  __shared__ int s_nbad;
   const int c = blockIdx.x;
   const int g = g0 + c;
   const int tid = threadIdx.x;
+  const size_t nn = static_cast<size_t>(n) * n;
   double* D = dlt + static_cast<size_t>(g) * NP * NP;
-  double* Mm = ws + static_cast<size_t>(c) * 4 * n * n;   // M
-  double* Gm = Mm + static_cast<size_t>(n) * n;           // M^T M, then reflectors
-  double* U = Gm + static_cast<size_t>(n) * n;            // eigenvectors (column-major)
-  double* T = U + static_cast<size_t>(n) * n;             // M U S^-1
-  for (int f = tid; f < n * n; f += blockDim.x) {
-    const int i = f / n, j = f - i * n;
+  double* Mm = ws + static_cast<size_t>(c) * 9 * nn;   // M
+  double* Gm = Mm + nn;                                 // M^T M, then reflectors
+  double* U = Gm + nn;                                  // eigenvectors (column-major)
+  double* T = U + nn;                                   // M U S^-1 (row-major [i][a])
+  double* P = T + nn;                                   // projector scratch
+  double* K = P + nn;                                   // canonical-range scratch
+  double* ZK = K + nn;
+  double* Rb = ZK + nn;                                 // right lost basis (column-major)
+  double* Lb = Rb + nn;                                 // left completion (column-major)
+  for (size_t f = tid; f < nn; f += blockDim.x) {
+    const int i = static_cast<int>(f / n), j = static_cast<int>(f - static_cast<size_t>(i) * n);
     Mm[f] = D[static_cast<size_t>(i) * NP + j] + (i == j ? 1.0 : 0.0);
   }
   __syncthreads();
-  for (int f = tid; f < n * n; f += blockDim.x) {
-    const int i = f / n, j = f - i * n;
+  for (size_t f = tid; f < nn; f += blockDim.x) {
+    const int i = static_cast<int>(f / n), j = static_cast<int>(f - static_cast<size_t>(i) * n);
     double acc = 0.0;
     for (int k = 0; k < n; ++k) acc += Mm[k * n + i] * Mm[k * n + j];
     Gm[f] = acc;
@@ -295,20 +367,56 @@ __global__ __launch_bounds__(kEigThreads) void k_polar(double* dlt, int NP, int 
   for (int a = tid; a < n; a += blockDim.x) s_perm[a] = a;   // all columns, any order
   __syncthreads();
   wg_back_transform(Gm, n, n, U, n, s_perm, n, sh);
-  double smin = 1e300;
-  for (int a = 0; a < n; ++a) smin = fmin(smin, sh.d[a]);
-  // T = M U S^-1 (column a scaled by 1/sqrt(sigma_a^2))
-  for (int f = tid; f < n * n; f += blockDim.x) {
-    const int i = f / n, a = f - i * n;
-    double acc = 0.0;
-    for (int k = 0; k < n; ++k) acc += Mm[i * n + k] * U[static_cast<size_t>(a) * n + k];
-    T[f] = acc / sqrt(fmax(sh.d[a], 1e-300));
+  const double tau2 = 1e-8;   // tau^2
+  if (tid == 0) {
+    int k = 0;
+    for (int a = 0; a < n; ++a)
+      if (!(sh.d[a] > tau2)) s_bad[k++] = a;
+    s_nbad = k;
   }
   __syncthreads();
-  for (int f = tid; f < n * n; f += blockDim.x) {
-    const int i = f / n, j = f - i * n;
+  const int nbad = s_nbad;
+  double smin = 1e300;
+  for (int a = 0; a < n; ++a) smin = fmin(smin, sh.d[a]);
+  // T[:, a] = M u_a / s_a for the kept directions, 0 for the lost ones
+  for (size_t f = tid; f < nn; f += blockDim.x) {
+    const int i = static_cast<int>(f / n), a = static_cast<int>(f - static_cast<size_t>(i) * n);
+    double acc = 0.0;
+    if (sh.d[a] > tau2) {
+      for (int k = 0; k < n; ++k) acc += Mm[i * n + k] * U[static_cast<size_t>(a) * n + k];
+      acc /= sqrt(sh.d[a]);
+    }
+    T[f] = acc;
+  }
+  __syncthreads();
+  if (nbad > 0) {
+    // right: projector onto the lost right directions
+    for (size_t f = tid; f < nn; f += blockDim.x) {
+      const int i = static_cast<int>(f / n), j = static_cast<int>(f - static_cast<size_t>(i) * n);
+      double acc = 0.0;
+      for (int q = 0; q < nbad; ++q) {
+        const double* u = U + static_cast<size_t>(s_bad[q]) * n;
+        acc += u[i] * u[j];
+      }
+      P[f] = acc;
+    }
+    __syncthreads();
+    wg_canonical_range(P, n, nbad, K, ZK, s_perm, Rb, sh);
+    // left: complement of the kept left directions
+    for (size_t f = tid; f < nn; f += blockDim.x) {
+      const int i = static_cast<int>(f / n), j = static_cast<int>(f - static_cast<size_t>(i) * n);
+      double acc = (i == j) ? 1.0 : 0.0;
+      for (int a = 0; a < n; ++a) acc -= T[i * n + a] * T[j * n + a];
+      P[f] = acc;
+    }
+    __syncthreads();
+    wg_canonical_range(P, n, nbad, K, ZK, s_perm, Lb, sh);
+  }
+  for (size_t f = tid; f < nn; f += blockDim.x) {
+    const int i = static_cast<int>(f / n), j = static_cast<int>(f - static_cast<size_t>(i) * n);
     double acc = 0.0;
     for (int a = 0; a < n; ++a) acc += T[i * n + a] * U[static_cast<size_t>(a) * n + j];
+    for (int q = 0; q < nbad; ++q) acc += Lb[static_cast<size_t>(q) * n + i] * Rb[static_cast<size_t>(q) * n + j];
     D[static_cast<size_t>(i) * NP + j] = acc - (i == j ? 1.0 : 0.0);
   }
   if (tid == 0) {
@@ -450,7 +558,7 @@ aqt_status precompute_tables(aqt_ctx* ctx, int M, int n, double tol) {
                           + static_cast<size_t>(ncols) * N            // canonical V
                           + 2 * static_cast<size_t>(ncols) * ncols + static_cast<size_t>(ncols) * N  // canon ws
                           + static_cast<size_t>(nq) * n * n           // z
-                          + 4 * static_cast<size_t>(n) * n            // polar ws
+                          + 9 * static_cast<size_t>(n) * n            // polar ws
                           + N;                                        // Eraw
   const size_t budget = size_t(2) << 30;
   int Gc = static_cast<int>(std::max<size_t>(1, std::min<size_t>(M, budget / (per_grid * 8))));
@@ -458,7 +566,7 @@ aqt_status precompute_tables(aqt_ctx* ctx, int M, int n, double tol) {
   if (H.reserve(static_cast<size_t>(Gc) * N * N * 8) || Z.reserve(static_cast<size_t>(Gc) * N * N * 8) ||
       Vc.reserve(static_cast<size_t>(Gc) * ncols * N * 8) || Vprev.reserve(static_cast<size_t>(ncols) * N * 8) ||
       cws.reserve(static_cast<size_t>(Gc) * (2 * static_cast<size_t>(ncols) * ncols + static_cast<size_t>(ncols) * N) * 8) ||
-      zws.reserve(static_cast<size_t>(Gc) * nq * n * n * 8) || pws.reserve(static_cast<size_t>(Gc) * 4 * n * n * 8) ||
+      zws.reserve(static_cast<size_t>(Gc) * nq * n * n * 8) || pws.reserve(static_cast<size_t>(Gc) * 9 * n * n * 8) ||
       Eraw.reserve(static_cast<size_t>(Gc) * N * 8) || perm.reserve(static_cast<size_t>(Gc) * N * 4) ||
       status.reserve(static_cast<size_t>(Gc) * 4))
     return ctx->fail(AQT_ENOMEM, "precompute workspace allocation failed");

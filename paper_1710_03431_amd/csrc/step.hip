@@ -25,6 +25,11 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <type_traits>
+#include <algorithm>
+#include <new>
+#include <string>
+#include <vector>
 
 #include "common.hpp"
 #include "ctx.hpp"
@@ -58,9 +63,22 @@ struct ModeBF16 {
   static constexpr int KC = 32;
   __device__ static constexpr int row(int lane, int i) { return 4 * (lane >> 4) + i; }
 };
+// 16-level instances: BF16 16x16x16 MFMA (four BF16 per lane and operand).
+struct ModeBF16K16 {
+  using T = float;
+  using Acc = f4;
+  static constexpr int KC = 16;
+  __device__ static constexpr int row(int lane, int i) { return 4 * (lane >> 4) + i; }
+};
+typedef short s16x4 __attribute__((ext_vector_type(4)));
 
 struct StepArgs {
   int M, n, nq;
+  int M_run;             // grid points processed (M, or fewer when autotuning)
+  int NP, TQ;            // padded levels and column tiles of this instance (batched runs)
+  int64_t tiles;         // workgroup tiles of this instance
+  double* pgs_sum;       // [M] (batched runs reduce into these)
+  double* pgs_sumsq;
   double dt;
   int64_t K;
   uint64_t seed, iid, traj0;
@@ -74,6 +92,7 @@ struct StepArgs {
   const double* d64re;   // [M][NP]
   const double* d64im;
   const double* R;       // [M][nq][NP][NP]
+  const double* Rq;      // [M][nq][NP] row sums of R over the target level
   const double* zdiag;   // [M][nq][NP]
   const double* E;       // [M][NP]
   const int* gs;         // [M]
@@ -118,16 +137,38 @@ __device__ __forceinline__ void split8(const float* x, bf16x8& hi, bf16x8& lo) {
   lo = __builtin_bit_cast(bf16x8, lv);
 }
 
+// hi/lo BF16 split of 4 floats, packed as two 64-bit words.
+__device__ __forceinline__ void split4(const float* x, s16x4& hi, s16x4& lo) {
+  uint32_t h[2], l[2];
+#pragma unroll
+  for (int j = 0; j < 2; ++j) {
+    uint32_t h0 = bf16_bits(x[2 * j]), h1 = bf16_bits(x[2 * j + 1]);
+    float r0 = x[2 * j] - __uint_as_float(h0 << 16);
+    float r1 = x[2 * j + 1] - __uint_as_float(h1 << 16);
+    h[j] = h0 | (h1 << 16);
+    l[j] = bf16_bits(r0) | (bf16_bits(r1) << 16);
+  }
+  hi = __builtin_bit_cast(s16x4, make_uint2(h[0], h[1]));
+  lo = __builtin_bit_cast(s16x4, make_uint2(l[0], l[1]));
+}
+
 // ----------------------------------------------------------- jump handler --
-// One wavefront finishes step g for trajectory column t of the tile whose
-// amplitudes after step 2 are in S.  Works in FP64.
-template <int NP, int TQ, class T>
-__device__ void finish_crossing(const StepArgs& a, int g, int t, int64_t jloc, T (*S)[TQ][NP][16],
+// Tile layout in LDS: S[q][row][c] holds column tile q (8 trajectories); column
+// c = (t & 7) + 8 * part carries the real (part 0) or imaginary (part 1) part of
+// local trajectory t = 8 q + (c & 7).
+template <int NP, class T>
+__device__ __forceinline__ T& amp(T (*S)[NP][16], int t, int part, int row) {
+  return S[t >> 3][row][(t & 7) + 8 * part];
+}
+
+// One wavefront finishes step g for local trajectory t whose amplitudes after
+// the fused propagator are in S.  Works in FP64.
+template <int NP, class T>
+__device__ void finish_crossing(const StepArgs& a, int g, int t, int64_t jloc, T (*S)[NP][16],
                                 double* s_r, int* s_m, int* s_cnt, int* s_net, double* s_p,
                                 int* s_kind) {
   constexpr int PL = (NP + kWave - 1) / kWave;
   const int lane = threadIdx.x & (kWave - 1);
-  const int q = t >> 4, col = t & 15;
   const double dt = a.dt;
   const uint64_t traj = a.traj0 + static_cast<uint64_t>(jloc);   // Philox counter word 0
   const double* Gam = a.Gamma + static_cast<size_t>(g) * NP;
@@ -137,10 +178,10 @@ __device__ void finish_crossing(const StepArgs& a, int g, int t, int64_t jloc, T
     const int x = lane + kWave * j;
     if (x < NP) {
       G[j] = Gam[x];
-      // undo the full-step decay of step 2: keep the phases, restore magnitudes
+      // undo the full-step decay of the fused propagator: keep phases, restore magnitudes
       const double up = exp(fmin(0.5 * G[j] * dt, 700.0));
-      cr[j] = static_cast<double>(S[0][q][x][col]) * up;
-      ci[j] = static_cast<double>(S[1][q][x][col]) * up;
+      cr[j] = static_cast<double>(amp<NP, T>(S, t, 0, x)) * up;
+      ci[j] = static_cast<double>(amp<NP, T>(S, t, 1, x)) * up;
     } else {
       G[j] = 0.0;
       cr[j] = ci[j] = 0.0;
@@ -242,41 +283,40 @@ __device__ void finish_crossing(const StepArgs& a, int g, int t, int64_t jloc, T
       }
       break;
     }
-    // qubit i and target a: running sum over R[g][i][b][a], i-major, a-minor
+    // qubit i and target a: inverse CDF over R[g][i][b][a] in i-major, a-minor order,
+    // taken in two stages -- the qubit from the row sums, then the target within
+    // that row -- which selects the same (i, a) as one pass over the whole list.
     int qi = 0, ta = b;
     {
-      const int nf = a.nq * NP;
-      const double* Rg = a.R + static_cast<size_t>(g) * a.nq * NP * NP;
-      double tot = 0.0;
-      for (int f = lane; f < nf; f += kWave) {
-        const int i = f / NP, x = f - i * NP;
-        tot += Rg[(static_cast<size_t>(i) * NP + b) * NP + x];
-      }
-      tot = wave_sum(tot);
+      const double* Rqg = a.Rq + static_cast<size_t>(g) * a.nq * NP;
+      const double rs = (lane < a.nq) ? Rqg[static_cast<size_t>(lane) * NP + b] : 0.0;
+      const double cum_i = wave_inclusive_scan(rs);
+      const double tot = __shfl(cum_i, kWave - 1, kWave);
       const double thr = u2 * tot;
-      double carry = 0.0;
-      int hitf = -1, lastpos = -1;
-      for (int f0 = 0; f0 < nf; f0 += kWave) {
-        const int f = f0 + lane;
-        double v = 0.0;
-        if (f < nf) {
-          const int i = f / NP, x = f - i * NP;
-          v = Rg[(static_cast<size_t>(i) * NP + b) * NP + x];
-        }
-        const double cum = wave_inclusive_scan(v) + carry;
-        carry = __shfl(cum, kWave - 1, kWave);
-        const uint64_t pos = __ballot(v > 0.0);
-        if (pos) lastpos = f0 + last_set_lane(pos);
-        const uint64_t hit = __ballot(cum > thr);
-        if (hit) {
-          hitf = f0 + first_set_lane(hit);
-          break;
-        }
+      const uint64_t hit_i = __ballot(cum_i > thr && lane < a.nq);
+      const uint64_t pos_i = __ballot(rs > 0.0);
+      qi = hit_i ? first_set_lane(hit_i) : last_set_lane(pos_i);
+      if (qi < 0) qi = 0;
+      const double before = (qi > 0) ? __shfl(cum_i, qi - 1, kWave) : 0.0;
+      const double* row = a.R + ((static_cast<size_t>(g) * a.nq + qi) * NP + b) * NP;
+      double v[PL];
+#pragma unroll
+      for (int j = 0; j < PL; ++j) {
+        const int x = lane + kWave * j;
+        v[j] = (x < NP) ? row[x] : 0.0;
       }
-      if (hitf < 0) hitf = lastpos;
-      if (hitf < 0) hitf = b;   // empty row cannot happen when q_b Gamma_b > 0; stay in range anyway
-      qi = hitf / NP;
-      ta = hitf - qi * NP;
+      double carry = before;
+      int hit = -1, lastpos = -1;
+#pragma unroll
+      for (int j = 0; j < PL; ++j) {
+        const double cum = wave_inclusive_scan(v[j]) + carry;
+        carry = __shfl(cum, kWave - 1, kWave);
+        const uint64_t h = __ballot(cum > thr);
+        if (hit < 0 && h) hit = first_set_lane(h) + kWave * j;
+        const uint64_t pz = __ballot(v[j] > 0.0);
+        if (pz) lastpos = last_set_lane(pz) + kWave * j;
+      }
+      ta = (hit >= 0) ? hit : (lastpos >= 0 ? lastpos : b);
     }
     int kind;
     if (ta != b) {
@@ -340,8 +380,8 @@ __device__ void finish_crossing(const StepArgs& a, int g, int t, int64_t jloc, T
     pt += w2;
     if (x < gsz) pg += w2;
     if (x < NP) {
-      S[0][q][x][col] = static_cast<T>(cr[j]);
-      S[1][q][x][col] = static_cast<T>(ci[j]);
+      amp<NP, T>(S, t, 0, x) = static_cast<T>(cr[j]);
+      amp<NP, T>(S, t, 1, x) = static_cast<T>(ci[j]);
     }
   }
   pg = wave_sum(pg);
@@ -356,32 +396,56 @@ __device__ void finish_crossing(const StepArgs& a, int g, int t, int64_t jloc, T
 }
 
 // --------------------------------------------------------------- kernel ----
+// Work split of the overlap GEMM over the four waves: with four or more row
+// tiles each wave owns the row tiles rt = wave (mod 4) for every column tile
+// (one A fragment feeds TQ MFMAs); with fewer, waves take (row tile, column
+// tile) pairs.  The k loop is outermost so each wave keeps UPW*QG independent
+// accumulator chains in flight.
+template <int NP, int TQ, class T>
+struct TileShared {
+  static constexpr int NRT = NP / 16;
+  static constexpr int TT = 8 * TQ;
+  T S[TQ][NP][16];
+  T nu[NRT][TT];
+  T gw[NRT][TT];
+  double r[TT];
+  double p[TT];
+  int m[TT], cnt[TT], net[TT];
+  int list[TT];
+  int nlist;
+  int kind[3];
+};
+
 template <int NP, int TQ, class Mode>
-__global__ __launch_bounds__(256) void k_trajectories(StepArgs a) {
+__device__ void run_tile(const StepArgs& a, int64_t tile, TileShared<NP, TQ, typename Mode::T>& sh) {
   using T = typename Mode::T;
   using Acc = typename Mode::Acc;
   constexpr int NRT = NP / 16;
-  constexpr int TT = 16 * TQ;
-  constexpr int QG = (NRT >= 4) ? TQ : 1;          // column groups per work unit
+  constexpr int TT = 8 * TQ;
+  constexpr int QG = (NRT >= 4) ? TQ : 1;          // column tiles per work unit
   constexpr int NUNITS = NRT * (TQ / QG);
   constexpr int UPW = (NUNITS + 3) / 4;            // units per wave
+  constexpr int NKC = NP / Mode::KC;
   static_assert(TT <= kWave, "tile must fit one wavefront for the decision pass");
 
-  __shared__ T S[2][TQ][NP][16];
-  __shared__ T s_nu[NRT][TT];
-  __shared__ T s_gw[NRT][TT];
-  __shared__ double s_r[TT];
-  __shared__ double s_p[TT];
-  __shared__ int s_m[TT], s_cnt[TT], s_net[TT];
-  __shared__ int s_list[TT];
-  __shared__ int s_nlist;
-  __shared__ int s_kind[3];
+  auto& S = sh.S;
+  auto& s_nu = sh.nu;
+  auto& s_gw = sh.gw;
+  double* s_r = sh.r;
+  double* s_p = sh.p;
+  int* s_m = sh.m;
+  int* s_cnt = sh.cnt;
+  int* s_net = sh.net;
+  int* s_list = sh.list;
+  int& s_nlist = sh.nlist;
+  int* s_kind = sh.kind;
 
   const int tid = threadIdx.x;
   const int lane = tid & (kWave - 1);
   const int wave = tid >> 6;
-  const int64_t tile = blockIdx.x;
   const int64_t tb = tile * TT;
+  const int lc = lane & 15;          // MFMA output column
+  const int part = (lane >> 3) & 1;  // 0: real part, 1: imaginary part
 
   if (tid < TT) {
     const int64_t j = tb + tid;
@@ -392,71 +456,112 @@ __global__ __launch_bounds__(256) void k_trajectories(StepArgs a) {
   }
   if (tid < 3) s_kind[tid] = 0;
 
-  Acc acc[UPW][QG][2];
-  const int lc = lane & 15;         // output column (trajectory) within a column tile
+  int rt_u[UPW], q0_u[UPW];
+  bool ok_u[UPW];
+#pragma unroll
+  for (int u = 0; u < UPW; ++u) {
+    const int unit = wave + 4 * u;
+    ok_u[u] = unit < NUNITS;
+    rt_u[u] = unit % NRT;
+    q0_u[u] = (unit / NRT) * QG;
+  }
+  Acc acc[UPW][QG];
 
-  for (int g = 1; g < a.M; ++g) {
+  for (int g = 1; g < a.M_run; ++g) {
     const int gsz = a.gs[g];
     // ---- 1. C + Delta C (or the initial state at g = 1)
 #pragma unroll
     for (int u = 0; u < UPW; ++u) {
-      const int unit = wave + 4 * u;
-      if (unit >= NUNITS) break;
-      const int rt = unit % NRT;
-      const int q0 = (unit / NRT) * QG;
+      if (!ok_u[u]) continue;
 #pragma unroll
-      for (int qq = 0; qq < QG; ++qq) {
+      for (int qq = 0; qq < QG; ++qq)
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
-          const int row = rt * 16 + Mode::row(lane, i);
-          if (g == 1) {
-            acc[u][qq][0][i] = static_cast<T>(a.cinit[row]);
-            acc[u][qq][1][i] = T(0);
-          } else {
-            acc[u][qq][0][i] = S[0][q0 + qq][row][lc];
-            acc[u][qq][1][i] = S[1][q0 + qq][row][lc];
-          }
+          const int row = rt_u[u] * 16 + Mode::row(lane, i);
+          acc[u][qq][i] = (g == 1) ? (part ? T(0) : static_cast<T>(a.cinit[row])) : S[q0_u[u] + qq][row][lc];
         }
-      }
-      if (g > 1) {
-        if constexpr (Mode::KC == 4) {
-          const T* A = static_cast<const T*>(a.dlt_a) +
-                       ((static_cast<size_t>(g) * NRT + rt) * (NP / 4)) * kWave + lane;
-#pragma unroll 4
-          for (int kc = 0; kc < NP / 4; ++kc) {
-            const T av = A[kc * kWave];
-            const int krow = 4 * kc + (lane >> 4);
+    }
+    if (g > 1) {
+      if constexpr (Mode::KC == 4) {
+        // A fragments are prefetched two k chunks ahead (two register sets) so the
+        // global-load latency hides behind the MFMAs of the chunk in flight.
+        const T* A = static_cast<const T*>(a.dlt_a) + static_cast<size_t>(g) * NRT * NKC * kWave + lane;
+        T pa[2][UPW];
 #pragma unroll
-            for (int qq = 0; qq < QG; ++qq) {
-              acc[u][qq][0] = mfma_k4(av, S[0][q0 + qq][krow][lc], acc[u][qq][0]);
-              acc[u][qq][1] = mfma_k4(av, S[1][q0 + qq][krow][lc], acc[u][qq][1]);
+        for (int s2 = 0; s2 < 2; ++s2)
+#pragma unroll
+          for (int u = 0; u < UPW; ++u)
+            pa[s2][u] = ok_u[u] ? A[(static_cast<size_t>(rt_u[u]) * NKC + s2) * kWave] : T(0);
+        for (int kc = 0; kc < NKC; kc += 2) {
+#pragma unroll
+          for (int s2 = 0; s2 < 2; ++s2) {
+            const int k = kc + s2;
+            T av[UPW];
+#pragma unroll
+            for (int u = 0; u < UPW; ++u) av[u] = pa[s2][u];
+            if (k + 2 < NKC) {
+#pragma unroll
+              for (int u = 0; u < UPW; ++u)
+                pa[s2][u] = ok_u[u] ? A[(static_cast<size_t>(rt_u[u]) * NKC + k + 2) * kWave] : T(0);
+            }
+            const int krow = 4 * k + (lane >> 4);
+#pragma unroll
+            for (int u = 0; u < UPW; ++u) {
+              if (!ok_u[u]) continue;
+#pragma unroll
+              for (int qq = 0; qq < QG; ++qq) acc[u][qq] = mfma_k4(av[u], S[q0_u[u] + qq][krow][lc], acc[u][qq]);
             }
           }
-        } else {
-          const uint4* Ah = static_cast<const uint4*>(a.dlt_a) +
-                            ((static_cast<size_t>(g) * NRT + rt) * (NP / 32)) * kWave + lane;
-          const uint4* Al = static_cast<const uint4*>(a.dlt_b) +
-                            ((static_cast<size_t>(g) * NRT + rt) * (NP / 32)) * kWave + lane;
-#pragma unroll 2
-          for (int kc = 0; kc < NP / 32; ++kc) {
-            const bf16x8 ah = __builtin_bit_cast(bf16x8, Ah[kc * kWave]);
-            const bf16x8 al = __builtin_bit_cast(bf16x8, Al[kc * kWave]);
-            const int k0 = 32 * kc + 8 * (lane >> 4);
+        }
+      } else if constexpr (Mode::KC == 16) {
+        const uint2* Ah = static_cast<const uint2*>(a.dlt_a) + static_cast<size_t>(g) * NRT * NKC * kWave + lane;
+        const uint2* Al = static_cast<const uint2*>(a.dlt_b) + static_cast<size_t>(g) * NRT * NKC * kWave + lane;
+        for (int kc = 0; kc < NKC; ++kc) {
+          const int k0 = 16 * kc + 4 * (lane >> 4);
+#pragma unroll
+          for (int u = 0; u < UPW; ++u) {
+            if (!ok_u[u]) continue;
+            const size_t off = (static_cast<size_t>(rt_u[u]) * NKC + kc) * kWave;
+            const s16x4 ah = __builtin_bit_cast(s16x4, Ah[off]);
+            const s16x4 al = __builtin_bit_cast(s16x4, Al[off]);
 #pragma unroll
             for (int qq = 0; qq < QG; ++qq) {
+              float xv[4];
 #pragma unroll
-              for (int part = 0; part < 2; ++part) {
-                float xv[8];
+              for (int j = 0; j < 4; ++j) xv[j] = S[q0_u[u] + qq][k0 + j][lc];
+              s16x4 bh, bl;
+              split4(xv, bh, bl);
+              Acc c = acc[u][qq];
+              c = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah, bh, c, 0, 0, 0);
+              c = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah, bl, c, 0, 0, 0);
+              c = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(al, bh, c, 0, 0, 0);
+              acc[u][qq] = c;
+            }
+          }
+        }
+      } else {
+        const uint4* Ah = static_cast<const uint4*>(a.dlt_a) + static_cast<size_t>(g) * NRT * NKC * kWave + lane;
+        const uint4* Al = static_cast<const uint4*>(a.dlt_b) + static_cast<size_t>(g) * NRT * NKC * kWave + lane;
+        for (int kc = 0; kc < NKC; ++kc) {
+          const int k0 = 32 * kc + 8 * (lane >> 4);
 #pragma unroll
-                for (int j = 0; j < 8; ++j) xv[j] = S[part][q0 + qq][k0 + j][lc];
-                bf16x8 bh, bl;
-                split8(xv, bh, bl);
-                Acc c = acc[u][qq][part];
-                c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh, c, 0, 0, 0);
-                c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl, c, 0, 0, 0);
-                c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh, c, 0, 0, 0);
-                acc[u][qq][part] = c;
-              }
+          for (int u = 0; u < UPW; ++u) {
+            if (!ok_u[u]) continue;
+            const size_t off = (static_cast<size_t>(rt_u[u]) * NKC + kc) * kWave;
+            const bf16x8 ah = __builtin_bit_cast(bf16x8, Ah[off]);
+            const bf16x8 al = __builtin_bit_cast(bf16x8, Al[off]);
+#pragma unroll
+            for (int qq = 0; qq < QG; ++qq) {
+              float xv[8];
+#pragma unroll
+              for (int j = 0; j < 8; ++j) xv[j] = S[q0_u[u] + qq][k0 + j][lc];
+              bf16x8 bh, bl;
+              split8(xv, bh, bl);
+              Acc c = acc[u][qq];
+              c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh, c, 0, 0, 0);
+              c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl, c, 0, 0, 0);
+              c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh, c, 0, 0, 0);
+              acc[u][qq] = c;
             }
           }
         }
@@ -469,10 +574,8 @@ __global__ __launch_bounds__(256) void k_trajectories(StepArgs a) {
       const T* di = static_cast<const T*>(a.dim) + static_cast<size_t>(g) * NP;
 #pragma unroll
       for (int u = 0; u < UPW; ++u) {
-        const int unit = wave + 4 * u;
-        if (unit >= NUNITS) break;
-        const int rt = unit % NRT;
-        const int q0 = (unit / NRT) * QG;
+        if (!ok_u[u]) continue;
+        const int rt = rt_u[u];
         T drv[4], div[4];
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
@@ -485,22 +588,23 @@ __global__ __launch_bounds__(256) void k_trajectories(StepArgs a) {
 #pragma unroll
           for (int i = 0; i < 4; ++i) {
             const int row = rt * 16 + Mode::row(lane, i);
-            const T yr = acc[u][qq][0][i], yi = acc[u][qq][1][i];
-            const T cr = drv[i] * yr - div[i] * yi;
-            const T ci = drv[i] * yi + div[i] * yr;
-            S[0][q0 + qq][row][lc] = cr;
-            S[1][q0 + qq][row][lc] = ci;
-            const T w2 = cr * cr + ci * ci;
-            nrm += w2;
-            if (row < gsz) gw += w2;
+            const T y = acc[u][qq][i];
+            const T yp = __shfl_xor(y, 8, kWave);       // the other part of the same amplitude
+            const T yr = part ? yp : y, yi = part ? y : yp;
+            const T c = part ? (drv[i] * yi + div[i] * yr) : (drv[i] * yr - div[i] * yi);
+            S[q0_u[u] + qq][row][lc] = c;
+            nrm += c * c;
+            if (row < gsz) gw += c * c;
           }
+          nrm += __shfl_xor(nrm, 8, kWave);
           nrm += __shfl_xor(nrm, 16, kWave);
           nrm += __shfl_xor(nrm, 32, kWave);
+          gw += __shfl_xor(gw, 8, kWave);
           gw += __shfl_xor(gw, 16, kWave);
           gw += __shfl_xor(gw, 32, kWave);
-          if (lane < 16) {
-            s_nu[rt][(q0 + qq) * 16 + lane] = nrm;
-            s_gw[rt][(q0 + qq) * 16 + lane] = gw;
+          if (lane < 8) {
+            s_nu[rt][(q0_u[u] + qq) * 8 + lane] = nrm;
+            s_gw[rt][(q0_u[u] + qq) * 8 + lane] = gw;
           }
         }
       }
@@ -530,7 +634,7 @@ __global__ __launch_bounds__(256) void k_trajectories(StepArgs a) {
     const int ncross = s_nlist;
     for (int e = wave; e < ncross; e += 4) {
       const int t = s_list[e];
-      finish_crossing<NP, TQ, T>(a, g, t, tb + t, S, s_r, s_m, s_cnt, s_net, s_p, s_kind);
+      finish_crossing<NP, T>(a, g, t, tb + t, S, s_r, s_m, s_cnt, s_net, s_p, s_kind);
     }
     __syncthreads();
     // ---- 4. per-tile observable sums (wave 0)
@@ -561,14 +665,21 @@ __global__ __launch_bounds__(256) void k_trajectories(StepArgs a) {
       const int t = e / a.n, x = e - t * a.n;
       const int64_t j = tb + t;
       if (j < a.K) {
-        a.final_state[(j * a.n + x) * 2 + 0] = static_cast<double>(S[0][t >> 4][x][t & 15]);
-        a.final_state[(j * a.n + x) * 2 + 1] = static_cast<double>(S[1][t >> 4][x][t & 15]);
+        a.final_state[(j * a.n + x) * 2 + 0] = static_cast<double>(amp<NP, T>(S, t, 0, x));
+        a.final_state[(j * a.n + x) * 2 + 1] = static_cast<double>(amp<NP, T>(S, t, 1, x));
       }
     }
   }
   if (a.jump_totals && tid < 3 && s_kind[tid])
     atomicAdd(reinterpret_cast<unsigned long long*>(&a.jump_totals[tid]),
               static_cast<unsigned long long>(s_kind[tid]));
+  __syncthreads();   // the shared tile state may be reused by the caller
+}
+
+template <int NP, int TQ, class Mode>
+__global__ __launch_bounds__(256) void k_trajectories(StepArgs a) {
+  __shared__ TileShared<NP, TQ, typename Mode::T> sh;
+  run_tile<NP, TQ, Mode>(a, blockIdx.x, sh);
 }
 
 __global__ void k_reduce_partials(const double* __restrict__ partial, int64_t tiles, int M, double K,
@@ -589,54 +700,189 @@ __global__ void k_reduce_partials(const double* __restrict__ partial, int64_t ti
   if (sumsq) sumsq[g] = q;
 }
 
-template <int NP, int TQ, class Mode>
-hipError_t launch_np(const StepArgs& a, int64_t tiles, hipStream_t st) {
-  hipLaunchKernelGGL((k_trajectories<NP, TQ, Mode>), dim3(static_cast<unsigned>(tiles)), dim3(256), 0, st, a);
-  return hipGetLastError();
+// Column-tile counts instantiated per level count and precision.
+constexpr int kTQ[] = {1, 2, 4, 5, 8};
+
+__host__ __device__ constexpr bool tq_allowed(int NP, int TQ, bool f64) {
+  return (NP <= 64) ? (TQ != 5 && !(f64 && NP == 64 && TQ == 8))
+                    : (TQ <= 5 && !(f64 && TQ > 2));
 }
 
-template <class Mode>
-hipError_t launch_mode(int NP, int TQ, const StepArgs& a, int64_t tiles, hipStream_t st) {
-#define AQT_CASE(np, tq) \
-  if (NP == np && TQ == tq) return launch_np<np, tq, Mode>(a, tiles, st);
-  if constexpr (Mode::KC == 4) {
-    AQT_CASE(16, 1) AQT_CASE(16, 2) AQT_CASE(16, 4)
+// ------------------------------------------------------------- batched ----
+// Many instances in one persistent launch: workgroups pull (instance, tile)
+// items from an atomic queue (items sorted longest first) and run each with
+// the same per-tile body; the LDS tile state is one raw buffer sized for the
+// largest (levels, tile) combination of the launch.
+struct BatchItem {
+  int inst;
+  int tile;
+};
+
+__global__ void k_batch_reset(int* counter) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) *counter = 0;
+}
+
+template <int NP, int TQ, class Mode>
+__device__ constexpr size_t tile_lds() {
+  return sizeof(TileShared<NP, TQ, typename Mode::T>);
+}
+
+template <int MaxNP, class Mode>
+__device__ constexpr size_t batch_lds() {
+  size_t m = 0;
+  constexpr bool f64 = sizeof(typename Mode::T) == 8;
+  if constexpr (tq_allowed(16, 8, f64)) m = m > tile_lds<16, 8, Mode>() ? m : tile_lds<16, 8, Mode>();
+  if constexpr (tq_allowed(32, 8, f64)) m = m > tile_lds<32, 8, Mode>() ? m : tile_lds<32, 8, Mode>();
+  if constexpr (MaxNP >= 64) {
+    if constexpr (tq_allowed(64, 8, f64)) m = m > tile_lds<64, 8, Mode>() ? m : tile_lds<64, 8, Mode>();
+    m = m > tile_lds<64, 4, Mode>() ? m : tile_lds<64, 4, Mode>();
   }
-  AQT_CASE(32, 1) AQT_CASE(32, 2) AQT_CASE(32, 4)
-  AQT_CASE(64, 1) AQT_CASE(64, 2) AQT_CASE(64, 4)
-  AQT_CASE(128, 1) AQT_CASE(128, 2)
-  AQT_CASE(256, 1) AQT_CASE(256, 2)
+  if constexpr (MaxNP >= 128) m = m > tile_lds<128, 2, Mode>() ? m : tile_lds<128, 2, Mode>();
+  if constexpr (MaxNP >= 256) m = m > tile_lds<256, 2, Mode>() ? m : tile_lds<256, 2, Mode>();
+  return m;
+}
+
+template <int NP, int TQ, class Mode, class BufT>
+__device__ __forceinline__ bool try_tile(const StepArgs& a, int tile, BufT* raw) {
+  constexpr bool f64 = sizeof(typename Mode::T) == 8;
+  if constexpr (tq_allowed(NP, TQ, f64) && (NP != 16 || Mode::KC != 32)) {
+    if (a.NP == NP && a.TQ == TQ) {
+      run_tile<NP, TQ, Mode>(a, tile, *reinterpret_cast<TileShared<NP, TQ, typename Mode::T>*>(raw));
+      return true;
+    }
+  }
+  return false;
+}
+
+template <int MaxNP, class Mode>
+__global__ __launch_bounds__(256) void k_batch(const StepArgs* __restrict__ args, const BatchItem* __restrict__ items,
+                                              int n_items, int* counter) {
+  __shared__ __align__(16) unsigned char raw[batch_lds<MaxNP, Mode>()];
+  __shared__ int s_item;
+  // BF16 runs of 16-level instances use the K = 16 MFMA
+  using M16 = typename std::conditional<Mode::KC == 32, ModeBF16K16, Mode>::type;
+  for (;;) {
+    if (threadIdx.x == 0) s_item = atomicAdd(counter, 1);
+    __syncthreads();
+    const int it = __builtin_amdgcn_readfirstlane(s_item);
+    __syncthreads();
+    if (it >= n_items) break;
+    const BatchItem item{__builtin_amdgcn_readfirstlane(items[it].inst), __builtin_amdgcn_readfirstlane(items[it].tile)};
+    const StepArgs& a = args[item.inst];
+    bool done = try_tile<16, 1, M16>(a, item.tile, raw) || try_tile<16, 2, M16>(a, item.tile, raw) ||
+                try_tile<16, 4, M16>(a, item.tile, raw) || try_tile<16, 8, M16>(a, item.tile, raw) ||
+                try_tile<32, 1, Mode>(a, item.tile, raw) || try_tile<32, 2, Mode>(a, item.tile, raw) ||
+                try_tile<32, 4, Mode>(a, item.tile, raw) || try_tile<32, 8, Mode>(a, item.tile, raw);
+    if constexpr (MaxNP >= 64)
+      done = done || try_tile<64, 1, Mode>(a, item.tile, raw) || try_tile<64, 2, Mode>(a, item.tile, raw) ||
+             try_tile<64, 4, Mode>(a, item.tile, raw) || try_tile<64, 8, Mode>(a, item.tile, raw);
+    if constexpr (MaxNP >= 128)
+      done = done || try_tile<128, 1, Mode>(a, item.tile, raw) || try_tile<128, 2, Mode>(a, item.tile, raw);
+    if constexpr (MaxNP >= 256)
+      done = done || try_tile<256, 1, Mode>(a, item.tile, raw) || try_tile<256, 2, Mode>(a, item.tile, raw);
+    (void)done;
+  }
+}
+
+// Fixed-order reduction of every instance's per-tile sums (blockIdx.y = instance).
+__global__ void k_reduce_batch(const StepArgs* __restrict__ args) {
+  const StepArgs& a = args[blockIdx.y];
+  const int g = blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= a.M) return;
+  double s = 0.0, q = 0.0;
+  if (g == 0) {
+    s = static_cast<double>(a.K);
+    q = s;
+  } else {
+    for (int64_t t = 0; t < a.tiles; ++t) {
+      s += a.partial[(t * a.M + g) * 2];
+      q += a.partial[(t * a.M + g) * 2 + 1];
+    }
+  }
+  if (a.pgs_sum) a.pgs_sum[g] = s;
+  if (a.pgs_sumsq) a.pgs_sumsq[g] = q;
+}
+
+template <class Mode, int NP>
+hipError_t launch_tq(int TQ, const StepArgs& a, int64_t blocks, hipStream_t st) {
+  constexpr bool f64 = sizeof(typename Mode::T) == 8;
+#define AQT_CASE(tq)                                                                          \
+  if constexpr (tq_allowed(NP, tq, f64)) {                                                    \
+    if (TQ == tq) {                                                                           \
+      hipLaunchKernelGGL((k_trajectories<NP, tq, Mode>), dim3(static_cast<unsigned>(blocks)), \
+                         dim3(256), 0, st, a);                                                \
+      return hipGetLastError();                                                               \
+    }                                                                                         \
+  }
+  AQT_CASE(1) AQT_CASE(2) AQT_CASE(4) AQT_CASE(5) AQT_CASE(8)
 #undef AQT_CASE
   return hipErrorInvalidValue;
 }
 
+template <class Mode>
+hipError_t launch_mode(int NP, int TQ, const StepArgs& a, int64_t blocks, hipStream_t st) {
+  switch (NP) {
+    case 16:
+      if constexpr (Mode::KC == 4) return launch_tq<Mode, 16>(TQ, a, blocks, st);
+      else return launch_tq<ModeBF16K16, 16>(TQ, a, blocks, st);
+    case 32: return launch_tq<Mode, 32>(TQ, a, blocks, st);
+    case 64: return launch_tq<Mode, 64>(TQ, a, blocks, st);
+    case 128: return launch_tq<Mode, 128>(TQ, a, blocks, st);
+    case 256: return launch_tq<Mode, 256>(TQ, a, blocks, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
 }  // namespace
 
-int default_tq(int NP, int precision, int64_t K) {
-  // Largest column-group count that still spreads the tiles over the chip.
-  int tq = (NP >= 128) ? 2 : 4;
-  if (precision == AQT_FP64 && NP >= 256) tq = 1;
-  while (tq > 1 && (K + 16 * tq - 1) / (16 * tq) < 512) tq >>= 1;
-  return tq;
+// Column tiles per workgroup: minimise the largest per-CU load
+// ceil(workgroups / CUs) * TQ (every workgroup does the same work per
+// trajectory-step), preferring larger tiles on ties (fewer overlap re-reads).
+int choose_tq(int NP, int precision, int64_t K, int cus) {
+  const int64_t tiles8 = (K + 7) / 8;
+  int best = 1;
+  int64_t best_cost = INT64_MAX;
+  for (int tq : kTQ) {
+    if (!tq_allowed(NP, tq, precision == AQT_FP64)) continue;
+    const int64_t wgs = (tiles8 + tq - 1) / tq;
+    const int64_t cost = ((wgs + cus - 1) / cus) * tq;
+    if (cost < best_cost || (cost == best_cost && tq > best)) {
+      best = tq;
+      best_cost = cost;
+    }
+  }
+  return best;
 }
 
 aqt_status launch_run(aqt_ctx* ctx, const aqt_run_params* p, const aqt_outputs* o) {
   const int prec = p->precision;
-  const int NP_run = (prec == AQT_BF16 && ctx->NP < 32) ? 32 : ctx->NP;
-  if (NP_run != ctx->NP) return ctx->fail(AQT_EINVAL, "BF16 stepping needs at least 17 levels (pad n to 32)");
   aqt_status s = pack_for_precision(ctx, prec);
   if (s != AQT_OK) return s;
-  int tq = p->tile ? p->tile / 16 : default_tq(ctx->NP, prec, p->n_traj);
-  if (p->tile && (p->tile % 16 || tq < 1 || tq > 4 || (tq == 3)))
-    return ctx->fail(AQT_EINVAL, "tile must be 16, 32 or 64 trajectories");
-  if (ctx->NP >= 128 && tq > 2) return ctx->fail(AQT_EINVAL, "tile of 64 needs n <= 64");
-  const int64_t TT = 16 * tq;
+  int cus = 256;
+  {
+    int dev = 0;
+    hipDeviceProp_t prop;
+    if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess &&
+        prop.multiProcessorCount > 0)
+      cus = prop.multiProcessorCount;
+  }
+  const int tq = p->tile ? p->tile / 8 : choose_tq(ctx->NP, prec, p->n_traj, cus);
+  if (p->tile && (p->tile % 8 || !(tq == 1 || tq == 2 || tq == 4 || tq == 5 || tq == 8) ||
+                  !tq_allowed(ctx->NP, tq, prec == AQT_FP64)))
+    return ctx->fail(AQT_EINVAL, "unsupported tile size for this level count and precision");
+  const int64_t TT = 8 * tq;
   const int64_t tiles = (p->n_traj + TT - 1) / TT;
   const size_t need = static_cast<size_t>(tiles) * ctx->M * 2 * sizeof(double);
   if (ctx->partial.reserve(need) != hipSuccess) return ctx->fail(AQT_ENOMEM, "workspace allocation failed");
 
   StepArgs a{};
   a.M = ctx->M;
+  a.M_run = ctx->M;
+  a.NP = ctx->NP;
+  a.TQ = tq;
+  a.tiles = tiles;
+  a.pgs_sum = o->pgs_sum;
+  a.pgs_sumsq = o->pgs_sumsq;
   a.n = ctx->n;
   a.nq = ctx->nq;
   a.dt = ctx->dt;
@@ -654,6 +900,7 @@ aqt_status launch_run(aqt_ctx* ctx, const aqt_run_params* p, const aqt_outputs* 
   a.d64re = ctx->dre.as<double>();
   a.d64im = ctx->dim.as<double>();
   a.R = ctx->R.as<double>();
+  a.Rq = ctx->Rq.as<double>();
   a.zdiag = ctx->zdiag.as<double>();
   a.E = ctx->E.as<double>();
   a.gs = ctx->gs.as<int>();
@@ -683,3 +930,356 @@ aqt_status launch_run(aqt_ctx* ctx, const aqt_run_params* p, const aqt_outputs* 
 }
 
 }  // namespace aqt
+
+// ================================================================ batches ===
+struct aqt_batch {
+  int device = 0;
+  hipStream_t capture_stream = nullptr;   // private stream used only for graph capture
+  hipStream_t stream = nullptr;           // launch stream (the first context's)
+  std::string err;
+  int precision = AQT_FP32;
+  int max_np = 16;
+  int n = 0;
+  std::vector<aqt_ctx*> ctxs;
+  std::vector<aqt::StepArgs> hargs;
+  std::vector<int> tiles_per_inst;        // trajectories per workgroup tile chosen per instance
+  aqt::DevBuf dargs, ditems, dcounter;
+  int n_items = 0;
+  int grid = 0;
+  bool use_graph = false;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  aqt_status fail(aqt_status s, const std::string& m) {
+    err = m;
+    return s;
+  }
+};
+
+namespace aqt {
+namespace {
+
+template <int MaxNP, class Mode>
+hipError_t enqueue_batch_kernel(const aqt_batch* b, const StepArgs* dargs, const BatchItem* items, int n_items,
+                                int* counter, int grid, hipStream_t st) {
+  hipLaunchKernelGGL(k_batch_reset, dim3(1), dim3(64), 0, st, counter);
+  hipLaunchKernelGGL((k_batch<MaxNP, Mode>), dim3(grid), dim3(256), 0, st, dargs, items, n_items, counter);
+  return hipGetLastError();
+}
+
+hipError_t enqueue_batch(const aqt_batch* b, const StepArgs* dargs, const BatchItem* items, int n_items,
+                         int* counter, hipStream_t st) {
+  const bool big = b->max_np > 64;
+  if (b->precision == AQT_FP64)
+    return big ? enqueue_batch_kernel<256, ModeF64>(b, dargs, items, n_items, counter, b->grid, st)
+               : enqueue_batch_kernel<64, ModeF64>(b, dargs, items, n_items, counter, b->grid, st);
+  if (b->precision == AQT_FP32)
+    return big ? enqueue_batch_kernel<256, ModeF32>(b, dargs, items, n_items, counter, b->grid, st)
+               : enqueue_batch_kernel<64, ModeF32>(b, dargs, items, n_items, counter, b->grid, st);
+  return big ? enqueue_batch_kernel<256, ModeBF16>(b, dargs, items, n_items, counter, b->grid, st)
+             : enqueue_batch_kernel<64, ModeBF16>(b, dargs, items, n_items, counter, b->grid, st);
+}
+
+template <int MaxNP, class Mode>
+int batch_occupancy() {
+  int blocks = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_batch<MaxNP, Mode>, 256, 0) != hipSuccess) return 1;
+  return blocks > 0 ? blocks : 1;
+}
+
+bool batch_tq_ok(int NP, int tq, int precision) {
+  if (!tq_allowed(NP, tq, precision == AQT_FP64)) return false;
+  if (NP <= 64) return tq == 1 || tq == 2 || tq == 4 || tq == 8;
+  return tq == 1 || tq == 2;
+}
+
+// Items of all instances, longest first (work per item ~ TQ * (M-1) * NP^2).
+std::vector<BatchItem> build_items(const std::vector<StepArgs>& args) {
+  std::vector<std::pair<double, BatchItem>> v;
+  for (int i = 0; i < static_cast<int>(args.size()); ++i) {
+    const StepArgs& a = args[i];
+    const double w = static_cast<double>(a.TQ) * (a.M_run - 1) * (64.0 + static_cast<double>(a.NP) * a.NP);
+    for (int64_t t = 0; t < a.tiles; ++t) v.push_back({w, BatchItem{i, static_cast<int>(t)}});
+  }
+  std::stable_sort(v.begin(), v.end(), [](const auto& x, const auto& y) { return x.first > y.first; });
+  std::vector<BatchItem> out;
+  out.reserve(v.size());
+  for (auto& p : v) out.push_back(p.second);
+  return out;
+}
+
+// Time each allowed tile size per level count on a shortened anneal (outputs
+// discarded) and keep the fastest per trajectory-step.
+aqt_status autotune(aqt_batch* b) {
+  const int tune_steps = 24;
+  std::vector<int> nps;
+  for (auto& a : b->hargs)
+    if (std::find(nps.begin(), nps.end(), a.NP) == nps.end()) nps.push_back(a.NP);
+  hipEvent_t e0, e1;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
+    return b->fail(AQT_EHIP, "event creation failed");
+  aqt_status st = AQT_OK;
+  DevBuf dargs, ditems, dctr, scratch;
+  if (dctr.reserve(sizeof(int)) != hipSuccess) st = b->fail(AQT_ENOMEM, "tuning allocation failed");
+  for (int np : nps) {
+    if (st != AQT_OK) break;
+    double best_t = 1e300;
+    int best_tq = 1;
+    for (int tq : kTQ) {
+      if (!batch_tq_ok(np, tq, b->precision)) continue;
+      std::vector<StepArgs> ta;
+      size_t scratch_need = 0;
+      double traj_steps = 0.0;
+      for (size_t i = 0; i < b->hargs.size(); ++i) {
+        StepArgs a = b->hargs[i];
+        if (a.NP != np) continue;
+        a.TQ = tq;
+        a.M_run = std::min(a.M, tune_steps + 1);
+        a.tiles = (a.K + 8 * tq - 1) / (8 * tq);
+        a.jump_totals = nullptr;
+        a.jump_count = nullptr;
+        a.jumps = nullptr;
+        a.cap = 0;
+        a.net_gs = nullptr;
+        a.net_hist = nullptr;
+        a.final_state = nullptr;
+        a.pgs_sum = a.pgs_sumsq = nullptr;
+        scratch_need = std::max(scratch_need, static_cast<size_t>(a.tiles) * a.M * 2 * sizeof(double));
+        traj_steps += static_cast<double>(a.K) * (a.M_run - 1);
+        ta.push_back(a);
+      }
+      if (scratch.reserve(scratch_need) != hipSuccess) {
+        st = b->fail(AQT_ENOMEM, "tuning allocation failed");
+        break;
+      }
+      for (auto& a : ta) a.partial = scratch.as<double>();   // shared scratch, contents discarded
+      std::vector<BatchItem> items = build_items(ta);
+      if (dargs.reserve(ta.size() * sizeof(StepArgs)) != hipSuccess ||
+          ditems.reserve(items.size() * sizeof(BatchItem)) != hipSuccess) {
+        st = b->fail(AQT_ENOMEM, "tuning allocation failed");
+        break;
+      }
+      (void)hipMemcpyAsync(dargs.p, ta.data(), ta.size() * sizeof(StepArgs), hipMemcpyHostToDevice, b->stream);
+      (void)hipMemcpyAsync(ditems.p, items.data(), items.size() * sizeof(BatchItem), hipMemcpyHostToDevice, b->stream);
+      double t_ms = 1e300;
+      for (int rep = 0; rep < 2; ++rep) {
+        (void)hipEventRecord(e0, b->stream);
+        if (enqueue_batch(b, dargs.as<StepArgs>(), ditems.as<BatchItem>(), static_cast<int>(items.size()),
+                          dctr.as<int>(), b->stream) != hipSuccess) {
+          st = b->fail(AQT_EHIP, "tuning launch failed");
+          break;
+        }
+        (void)hipEventRecord(e1, b->stream);
+        if (hipEventSynchronize(e1) != hipSuccess) {
+          st = b->fail(AQT_EHIP, "tuning run failed");
+          break;
+        }
+        float ms = 0.f;
+        (void)hipEventElapsedTime(&ms, e0, e1);
+        if (rep) t_ms = std::min(t_ms, static_cast<double>(ms));   // first repetition warms up
+      }
+      if (st != AQT_OK) break;
+      const double per = t_ms / traj_steps;
+      if (per < best_t) {
+        best_t = per;
+        best_tq = tq;
+      }
+    }
+    for (size_t i = 0; i < b->hargs.size(); ++i)
+      if (b->hargs[i].NP == np && b->tiles_per_inst[i] == 0) b->tiles_per_inst[i] = 8 * best_tq;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  return st;
+}
+
+}  // namespace
+}  // namespace aqt
+
+extern "C" {
+
+aqt_status aqt_batch_create(aqt_batch** out, aqt_ctx* const* ctxs, int n, const aqt_run_params* params,
+                            const aqt_outputs* outs, int flags) {
+  using namespace aqt;
+  if (!out) return AQT_EINVAL;
+  *out = nullptr;
+  if (!ctxs || !params || !outs || n < 1) return AQT_EINVAL;
+  aqt_batch* b = new (std::nothrow) aqt_batch();
+  if (!b) return AQT_ENOMEM;
+  auto bail = [&](aqt_status s) {
+    if (s != AQT_OK) {
+      // keep the object so the caller can read the message, then destroy it
+      *out = b;
+      return s;
+    }
+    return s;
+  };
+  b->n = n;
+  b->ctxs.assign(ctxs, ctxs + n);
+  b->device = ctxs[0] ? ctxs[0]->device : 0;
+  b->stream = ctxs[0] ? ctxs[0]->stream : nullptr;
+  b->precision = params[0].precision;
+  b->use_graph = (flags & 1) != 0;
+  const bool tune = (flags & 2) != 0;
+  if (hipSetDevice(b->device) != hipSuccess) return bail(b->fail(AQT_EHIP, "hipSetDevice failed"));
+  for (int i = 0; i < n; ++i) {
+    aqt_ctx* c = ctxs[i];
+    if (!c) return bail(b->fail(AQT_EINVAL, "null context in batch"));
+    if (!c->have_tables) return bail(b->fail(AQT_ESTATE, "every context needs tables before batching"));
+    if (c->device != b->device) return bail(b->fail(AQT_EINVAL, "all contexts must be on one device"));
+    if (params[i].precision != b->precision) return bail(b->fail(AQT_EINVAL, "one precision per batch"));
+    if (params[i].n_traj < 1) return bail(b->fail(AQT_EINVAL, "n_traj must be >= 1"));
+    if (params[i].record_capacity > 0 && !outs[i].jumps)
+      return bail(b->fail(AQT_EINVAL, "record_capacity > 0 needs a jumps buffer"));
+    if (outs[i].net_hist && outs[i].hist_hi < outs[i].hist_lo) return bail(b->fail(AQT_EINVAL, "hist_hi < hist_lo"));
+    if (params[i].tile && (params[i].tile % 8 || !batch_tq_ok(c->NP, params[i].tile / 8, b->precision)))
+      return bail(b->fail(AQT_EINVAL, "unsupported tile size in batch"));
+    b->max_np = std::max(b->max_np, c->NP);
+    aqt_status s = pack_for_precision(c, b->precision);
+    if (s != AQT_OK) return bail(b->fail(s, c->err));
+  }
+  if (hipStreamSynchronize(b->stream) != hipSuccess) return bail(b->fail(AQT_EHIP, "packing failed"));
+  b->tiles_per_inst.assign(n, 0);
+  for (int i = 0; i < n; ++i) b->tiles_per_inst[i] = params[i].tile;
+  // provisional args (TQ fixed below)
+  b->hargs.resize(n);
+  for (int i = 0; i < n; ++i) {
+    aqt_ctx* c = ctxs[i];
+    StepArgs a{};
+    a.M = c->M;
+    a.M_run = c->M;
+    a.n = c->n;
+    a.nq = c->nq;
+    a.NP = c->NP;
+    a.dt = c->dt;
+    a.K = params[i].n_traj;
+    a.seed = params[i].seed;
+    a.iid = params[i].instance_id;
+    a.traj0 = params[i].traj_offset;
+    a.cap = params[i].record_capacity;
+    a.dlt_a = c->pk_a.p;
+    a.dlt_b = c->pk_b.p;
+    a.dre = c->pk_dre.p;
+    a.dim = c->pk_dim.p;
+    a.cinit = c->cinit.as<double>();
+    a.Gamma = c->Gamma.as<double>();
+    a.d64re = c->dre.as<double>();
+    a.d64im = c->dim.as<double>();
+    a.R = c->R.as<double>();
+    a.Rq = c->Rq.as<double>();
+    a.zdiag = c->zdiag.as<double>();
+    a.E = c->E.as<double>();
+    a.gs = c->gs.as<int>();
+    a.jump_totals = outs[i].jump_totals;
+    a.jump_count = outs[i].jump_count;
+    a.jumps = outs[i].jumps;
+    a.net_gs = outs[i].net_gs;
+    a.net_hist = outs[i].net_hist;
+    a.hist_lo = outs[i].hist_lo;
+    a.hist_hi = outs[i].hist_hi;
+    a.final_state = outs[i].final_state;
+    a.pgs_sum = outs[i].pgs_sum;
+    a.pgs_sumsq = outs[i].pgs_sumsq;
+    a.TQ = 1;
+    a.tiles = (a.K + 7) / 8;
+    b->hargs[i] = a;
+  }
+  int cus = 256;
+  {
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, b->device) == hipSuccess && prop.multiProcessorCount > 0)
+      cus = prop.multiProcessorCount;
+  }
+  int occ = 1;
+  const bool big = b->max_np > 64;
+  if (b->precision == AQT_FP64) occ = big ? batch_occupancy<256, ModeF64>() : batch_occupancy<64, ModeF64>();
+  else if (b->precision == AQT_FP32) occ = big ? batch_occupancy<256, ModeF32>() : batch_occupancy<64, ModeF32>();
+  else occ = big ? batch_occupancy<256, ModeBF16>() : batch_occupancy<64, ModeBF16>();
+  b->grid = cus * occ;
+  if (tune) {
+    aqt_status s = autotune(b);
+    if (s != AQT_OK) return bail(s);
+  }
+  for (int i = 0; i < n; ++i) {
+    if (b->tiles_per_inst[i] == 0) {
+      // heuristic: the largest allowed tile that still gives every CU several items
+      int best = 1;
+      for (int tq : kTQ)
+        if (batch_tq_ok(b->hargs[i].NP, tq, b->precision)) best = tq;
+      b->tiles_per_inst[i] = 8 * std::min(best, 4);
+    }
+    StepArgs& a = b->hargs[i];
+    a.TQ = b->tiles_per_inst[i] / 8;
+    a.tiles = (a.K + 8 * a.TQ - 1) / (8 * a.TQ);
+    aqt_ctx* c = ctxs[i];
+    const size_t need = static_cast<size_t>(a.tiles) * a.M * 2 * sizeof(double);
+    if (c->partial.reserve(need) != hipSuccess) return bail(b->fail(AQT_ENOMEM, "workspace allocation failed"));
+    a.partial = c->partial.as<double>();
+  }
+  std::vector<BatchItem> items = build_items(b->hargs);
+  b->n_items = static_cast<int>(items.size());
+  if (b->dargs.reserve(n * sizeof(StepArgs)) != hipSuccess ||
+      b->ditems.reserve(items.size() * sizeof(BatchItem)) != hipSuccess || b->dcounter.reserve(sizeof(int)) != hipSuccess)
+    return bail(b->fail(AQT_ENOMEM, "batch allocation failed"));
+  if (hipMemcpy(b->dargs.p, b->hargs.data(), n * sizeof(StepArgs), hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(b->ditems.p, items.data(), items.size() * sizeof(BatchItem), hipMemcpyHostToDevice) != hipSuccess)
+    return bail(b->fail(AQT_EHIP, "batch upload failed"));
+  if (b->use_graph) {
+    if (hipStreamCreate(&b->capture_stream) != hipSuccess) return bail(b->fail(AQT_EHIP, "stream creation failed"));
+    if (hipStreamBeginCapture(b->capture_stream, hipStreamCaptureModeThreadLocal) != hipSuccess)
+      return bail(b->fail(AQT_EHIP, "graph capture failed to start"));
+    hipError_t e = enqueue_batch(b, b->dargs.as<StepArgs>(), b->ditems.as<BatchItem>(), b->n_items,
+                                 b->dcounter.as<int>(), b->capture_stream);
+    int maxM = 0;
+    for (auto& a : b->hargs) maxM = std::max(maxM, a.M);
+    hipLaunchKernelGGL(k_reduce_batch, dim3((maxM + 255) / 256, n), dim3(256), 0, b->capture_stream,
+                       b->dargs.as<StepArgs>());
+    hipGraph_t g = nullptr;
+    hipError_t e2 = hipStreamEndCapture(b->capture_stream, &g);
+    if (e != hipSuccess || e2 != hipSuccess || !g) return bail(b->fail(AQT_EHIP, "graph capture failed"));
+    b->graph = g;
+    if (hipGraphInstantiate(&b->exec, g, nullptr, nullptr, 0) != hipSuccess)
+      return bail(b->fail(AQT_EHIP, "graph instantiation failed"));
+  }
+  *out = b;
+  return AQT_OK;
+}
+
+aqt_status aqt_batch_launch(aqt_batch* b) {
+  using namespace aqt;
+  if (!b) return AQT_EINVAL;
+  if (!b->dargs.p) return b->fail(AQT_ESTATE, "batch was not created successfully");
+  if (hipSetDevice(b->device) != hipSuccess) return b->fail(AQT_EHIP, "hipSetDevice failed");
+  if (b->use_graph) {
+    if (hipGraphLaunch(b->exec, b->stream) != hipSuccess) return b->fail(AQT_EHIP, "graph launch failed");
+    return AQT_OK;
+  }
+  if (enqueue_batch(b, b->dargs.as<StepArgs>(), b->ditems.as<BatchItem>(), b->n_items, b->dcounter.as<int>(),
+                    b->stream) != hipSuccess)
+    return b->fail(AQT_EHIP, "batch launch failed");
+  int maxM = 0;
+  for (auto& a : b->hargs) maxM = std::max(maxM, a.M);
+  hipLaunchKernelGGL(k_reduce_batch, dim3((maxM + 255) / 256, b->n), dim3(256), 0, b->stream, b->dargs.as<StepArgs>());
+  if (hipGetLastError() != hipSuccess) return b->fail(AQT_EHIP, "batch reduction launch failed");
+  return AQT_OK;
+}
+
+aqt_status aqt_batch_tiles(const aqt_batch* b, int32_t* tile_per_instance) {
+  if (!b || !tile_per_instance) return AQT_EINVAL;
+  for (int i = 0; i < b->n; ++i) tile_per_instance[i] = b->tiles_per_inst.empty() ? 0 : b->tiles_per_inst[i];
+  return AQT_OK;
+}
+
+const char* aqt_batch_last_error(const aqt_batch* b) { return b ? b->err.c_str() : "null batch"; }
+
+void aqt_batch_destroy(aqt_batch* b) {
+  if (!b) return;
+  (void)hipSetDevice(b->device);
+  if (b->stream) (void)hipStreamSynchronize(b->stream);
+  else (void)hipDeviceSynchronize();
+  if (b->exec) (void)hipGraphExecDestroy(b->exec);
+  if (b->graph) (void)hipGraphDestroy(b->graph);
+  if (b->capture_stream) (void)hipStreamDestroy(b->capture_stream);
+  delete b;
+}
+
+}  // extern "C"

@@ -2,11 +2,13 @@
 //
 // finish_tables: Gamma_b = sum_{i,a} R[i][b][a], the diagonal of
 //   sum_i A_i^dag A_i (Sec. III eq. Heff with the rates absorbed, eq. Aired),
+//   with the per-qubit row sums kept for the two-stage channel draw,
 //   and d_b = exp(-i e_b dt - Gamma_b dt / 2), the no-jump propagator over one
 //   step of the diagonal effective Hamiltonian (Sec. III eq. detun).
 // pack_for_precision: Delta = O - I rearranged into 16x16 MFMA A-operand
 //   fragments (64 lanes contiguous) in the state precision; for BF16 two
-//   fragment sets (hi, lo) with Delta ~ hi + lo.
+//   fragment sets (hi, lo) with Delta ~ hi + lo (K = 32 fragments, or K = 16
+//   fragments when only 16 levels are kept).
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -18,18 +20,21 @@ namespace aqt {
 namespace {
 
 __global__ void k_gamma_phase(const double* __restrict__ E, const double* __restrict__ R, int M, int NP, int n,
-                              int nq, double dt, double* __restrict__ Gamma, double* __restrict__ dre,
-                              double* __restrict__ dim) {
+                              int nq, double dt, double* __restrict__ Gamma, double* __restrict__ Rq,
+                              double* __restrict__ dre, double* __restrict__ dim) {
   const int64_t idx = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
   if (idx >= static_cast<int64_t>(M) * NP) return;
   const int g = static_cast<int>(idx / NP);
   const int b = static_cast<int>(idx - static_cast<int64_t>(g) * NP);
   double G = 0.0;
-  if (b < n) {
-    for (int i = 0; i < nq; ++i) {
+  for (int i = 0; i < nq; ++i) {
+    double rs = 0.0;
+    if (b < n) {
       const double* row = R + ((static_cast<size_t>(g) * nq + i) * NP + b) * NP;
-      for (int a = 0; a < n; ++a) G += row[a];
+      for (int a = 0; a < n; ++a) rs += row[a];
     }
+    Rq[(static_cast<size_t>(g) * nq + i) * NP + b] = rs;
+    G += rs;
   }
   Gamma[idx] = G;
   if (b < n) {
@@ -98,6 +103,37 @@ __global__ void k_pack_bf16(const double* __restrict__ dlt, int M, int NP, uint4
   lo[idx] = make_uint4(w[0], w[1], w[2], w[3]);
 }
 
+__global__ void k_pack_bf16_k16(const double* __restrict__ dlt, int M, int NP, uint2* __restrict__ hi,
+                                uint2* __restrict__ lo) {
+  // fragment (g, rt, kc, l) holds Delta[g][16 rt + l%16][16 kc + 4 (l/16) + j], j = 0..3
+  const int64_t idx = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  const int64_t per_g = static_cast<int64_t>(NP) * NP / 4;
+  if (idx >= per_g * M) return;
+  const int g = static_cast<int>(idx / per_g);
+  int64_t r = idx - g * per_g;
+  const int l = static_cast<int>(r & 63);
+  r >>= 6;
+  const int kc = static_cast<int>(r % (NP / 16));
+  const int rt = static_cast<int>(r / (NP / 16));
+  const int row = 16 * rt + (l & 15);
+  const int col0 = 16 * kc + 4 * (l >> 4);
+  uint32_t h[2], w[2];
+  for (int j = 0; j < 2; ++j) {
+    uint32_t hb[2], lb[2];
+    for (int e = 0; e < 2; ++e) {
+      const double x = dlt[(static_cast<size_t>(g) * NP + row) * NP + col0 + 2 * j + e];
+      const uint32_t hh = bf16_rne_bits(static_cast<float>(x));
+      const double rest = x - static_cast<double>(__uint_as_float(hh << 16));
+      hb[e] = hh;
+      lb[e] = bf16_rne_bits(static_cast<float>(rest));
+    }
+    h[j] = hb[0] | (hb[1] << 16);
+    w[j] = lb[0] | (lb[1] << 16);
+  }
+  hi[idx] = make_uint2(h[0], h[1]);
+  lo[idx] = make_uint2(w[0], w[1]);
+}
+
 __global__ void k_to_f32(const double* __restrict__ in, float* __restrict__ out, int64_t count) {
   const int64_t idx = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
   if (idx < count) out[idx] = static_cast<float>(in[idx]);
@@ -112,11 +148,12 @@ inline unsigned blocks_for(int64_t count, int threads = 256) {
 aqt_status finish_tables(aqt_ctx* ctx) {
   const int64_t cnt = static_cast<int64_t>(ctx->M) * ctx->NP;
   if (ctx->Gamma.reserve(cnt * sizeof(double)) != hipSuccess || ctx->dre.reserve(cnt * sizeof(double)) != hipSuccess ||
-      ctx->dim.reserve(cnt * sizeof(double)) != hipSuccess)
+      ctx->dim.reserve(cnt * sizeof(double)) != hipSuccess ||
+      ctx->Rq.reserve(cnt * ctx->nq * sizeof(double)) != hipSuccess)
     return ctx->fail(AQT_ENOMEM, "table allocation failed");
   hipLaunchKernelGGL(k_gamma_phase, dim3(blocks_for(cnt)), dim3(256), 0, ctx->stream, ctx->E.as<double>(),
                      ctx->R.as<double>(), ctx->M, ctx->NP, ctx->n, ctx->nq, ctx->dt, ctx->Gamma.as<double>(),
-                     ctx->dre.as<double>(), ctx->dim.as<double>());
+                     ctx->Rq.as<double>(), ctx->dre.as<double>(), ctx->dim.as<double>());
   AQT_HIP(ctx, hipGetLastError());
   ctx->packed_for = -1;
   return AQT_OK;
@@ -146,11 +183,14 @@ aqt_status pack_for_precision(aqt_ctx* ctx, int precision) {
       hipLaunchKernelGGL(k_pack_k4<float>, dim3(blocks_for(nd)), dim3(256), 0, ctx->stream, ctx->dlt.as<double>(),
                          ctx->M, ctx->NP, ctx->pk_a.as<float>());
     } else if (precision == AQT_BF16) {
-      if (ctx->NP < 32) return ctx->fail(AQT_EINVAL, "BF16 stepping needs n > 16");
       if (ctx->pk_a.reserve(nd * 2) != hipSuccess || ctx->pk_b.reserve(nd * 2) != hipSuccess)
         return ctx->fail(AQT_ENOMEM, "operand allocation failed");
-      hipLaunchKernelGGL(k_pack_bf16, dim3(blocks_for(nd / 8)), dim3(256), 0, ctx->stream, ctx->dlt.as<double>(),
-                         ctx->M, ctx->NP, ctx->pk_a.as<uint4>(), ctx->pk_b.as<uint4>());
+      if (ctx->NP == 16)
+        hipLaunchKernelGGL(k_pack_bf16_k16, dim3(blocks_for(nd / 4)), dim3(256), 0, ctx->stream,
+                           ctx->dlt.as<double>(), ctx->M, ctx->NP, ctx->pk_a.as<uint2>(), ctx->pk_b.as<uint2>());
+      else
+        hipLaunchKernelGGL(k_pack_bf16, dim3(blocks_for(nd / 8)), dim3(256), 0, ctx->stream,
+                           ctx->dlt.as<double>(), ctx->M, ctx->NP, ctx->pk_a.as<uint4>(), ctx->pk_b.as<uint4>());
     } else {
       return ctx->fail(AQT_EINVAL, "unknown precision");
     }

@@ -1,0 +1,93 @@
+"""Batched persistent launch (aqt_batch_*): many instances of different sizes in one
+launch reproduce their individual runs, with and without graph capture.
+
+The batched kernel is a separate instantiation of the same tile code, so the compiler
+may contract or order floating-point operations differently: jump channels must agree
+trajectory by trajectory (up to rare mixed-precision threshold ties), jump times to
+the precision of the state arithmetic.  Replays of one batch are bit-identical."""
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import ame, spectrum, trajectories
+
+from gpu_common import sigma_bound
+
+pytestmark = pytest.mark.gpu
+
+
+def make_engine(inst):
+    from paper_1710_03431_amd.binding import Engine
+    eng = Engine(0)
+    eng.set_instance(inst)
+    eng.precompute(inst.n_grid, inst.levels)
+    return eng
+
+
+def same_records(a, b, t_f, t_rel):
+    """Fraction of trajectories with equal jump counts, channels and times within t_rel."""
+    K = len(a["jump_count"])
+    cap = a["jumps"].shape[1]
+    ok = 0
+    for j in range(K):
+        n = int(a["jump_count"][j])
+        if n != int(b["jump_count"][j]):
+            continue
+        m = min(n, cap)
+        x, y = a["jumps"][j, :m], b["jumps"][j, :m]
+        if any(not np.array_equal(x[f], y[f]) for f in ("step", "qubit", "kind", "from_level", "to_level")):
+            continue
+        if np.all(np.abs(x["t"] - y["t"]) <= t_rel * np.abs(y["t"]) + 1e-12 * t_f):
+            ok += 1
+    return ok / K
+
+
+@pytest.fixture(scope="module")
+def instances():
+    insts = [W.pm1_all_to_all(6, 11, t_f=1500.0, n_grid=120, n_levels=16),
+             W.pm1_all_to_all(7, 12, t_f=3000.0, n_grid=150, n_levels=32),
+             W.pm1_all_to_all(6, 13, t_f=800.0, n_grid=100, n_levels=64),
+             W.ring_instance(4, 1001, n_grid=200)]
+    return insts, [make_engine(i) for i in insts]
+
+
+@pytest.mark.parametrize("prec,graph,autotune", [("fp64", False, False), ("fp32", True, True),
+                                                  ("bf16", True, True)])
+def test_batch_equals_individual_runs(instances, prec, graph, autotune):
+    from paper_1710_03431_amd.binding import Batch
+    insts, engines = instances
+    if prec == "bf16":
+        keep = [k for k in range(len(insts)) if insts[k].levels >= 16]
+    else:
+        keep = list(range(len(insts)))
+    runs = [dict(n_traj=300 + 37 * k, seed=5 + k, instance_id=k, record_capacity=32) for k in keep]
+    b = Batch([engines[k] for k in keep], runs, precision=prec, graph=graph, autotune=autotune)
+    b.launch()
+    got = b.results()
+    b.launch()          # a replay overwrites the sums and gives the same numbers
+    again = b.results()
+    t_rel, need = {"fp64": (1e-9, 0.999), "fp32": (1e-4, 0.98), "bf16": (1e-3, 0.97)}[prec]
+    for k, r, g, g2, tile in zip(keep, runs, got, again, b.tiles):
+        K = r["n_traj"]
+        ref = engines[k].run(K, prec, seed=r["seed"], instance_id=k, record_capacity=32, tile=tile)
+        frac = same_records(g, ref, insts[k].t_f, t_rel)
+        assert frac >= need, (k, frac)
+        # a trajectory that diverges moves each per-grid P_GS sum by at most 1
+        diff = np.abs(g["pgs_sum"] - ref["pgs_sum"]).max()
+        assert diff <= (1.0 - frac) * K + 1e-6 * K, (k, diff)
+        np.testing.assert_array_equal(g2["pgs_sum"], g["pgs_sum"])
+        np.testing.assert_array_equal(g2["jumps"], g["jumps"])
+        np.testing.assert_array_equal(g2["jump_totals"], 2 * g["jump_totals"])   # accumulated
+    b.close()
+
+
+def test_bf16_sixteen_levels_matches_ame():
+    """16 retained levels use the BF16 16x16x16 MFMA; the mean follows the split-step AME."""
+    inst = W.pm1_all_to_all(5, 21, t_f=2000.0, n_grid=400, n_levels=16)
+    tabs = spectrum.all_tables(inst)
+    P = ame.split_step(tabs, inst)
+    eng = make_engine(inst)
+    K = 4000
+    res = eng.run(K, "bf16", seed=3)
+    m, se = trajectories.mean_and_stderr(res["pgs_sum"], res["pgs_sumsq"], K)
+    assert np.all(np.abs(m - P) <= 3 * sigma_bound(P, se, K) + 1e-4)

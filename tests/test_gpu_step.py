@@ -88,7 +88,7 @@ def test_ragged_and_offset_tiles(small, K, offset):
     np.testing.assert_allclose(res["pgs_sum"], ref.pgs_sum, rtol=1e-9, atol=1e-9)
 
 
-@pytest.mark.parametrize("tile", [16, 32, 64])
+@pytest.mark.parametrize("tile", [8, 16, 32, 64])
 def test_tile_shape_does_not_change_results(small, tile):
     inst, tabs = small
     eng = engine_with_oracle_tables(inst, tabs)
