@@ -2,7 +2,7 @@
 // instantaneous eigenbasis (Sec. IV waiting-time procedure; App. C validity;
 // jump-type law App. B eq. Pi(t); jump update Sec. III eq. jump).
 //
-// One workgroup (4 waves) owns a tile of TT = 16*TQ trajectories for the whole
+// One workgroup (4 waves) owns a tile of TT = 8*TQ trajectories for the whole
 // anneal; their amplitudes stay in LDS.  Per grid step g (from s_{g-1} to s_g):
 //   1. C <- O_g C on MFMA, written as C + Delta_g C (identity split) so the
 //      accumulator starts from C.  Real Delta times complex C is one real GEMM
@@ -150,6 +150,46 @@ __device__ __forceinline__ void split4(const float* x, s16x4& hi, s16x4& lo) {
   }
   hi = __builtin_bit_cast(s16x4, make_uint2(h[0], h[1]));
   lo = __builtin_bit_cast(s16x4, make_uint2(l[0], l[1]));
+}
+
+// One A-operand fragment of Delta (per lane): a value for the K = 4 MFMAs,
+// hi/lo BF16 words for the K = 16 and K = 32 ones.
+template <class Mode>
+struct Frag {
+  typename Mode::T v;
+};
+template <>
+struct Frag<ModeBF16K16> {
+  uint2 h, l;
+};
+template <>
+struct Frag<ModeBF16> {
+  uint4 h, l;
+};
+
+template <class Mode>
+__device__ __forceinline__ Frag<Mode> load_frag(const StepArgs& a, size_t idx) {
+  Frag<Mode> f;
+  if constexpr (Mode::KC == 4) {
+    f.v = static_cast<const typename Mode::T*>(a.dlt_a)[idx];
+  } else if constexpr (Mode::KC == 16) {
+    f.h = static_cast<const uint2*>(a.dlt_a)[idx];
+    f.l = static_cast<const uint2*>(a.dlt_b)[idx];
+  } else {
+    f.h = static_cast<const uint4*>(a.dlt_a)[idx];
+    f.l = static_cast<const uint4*>(a.dlt_b)[idx];
+  }
+  return f;
+}
+
+// Chunks of A fragments kept in flight: a ring of PF chunks per unit, refilled
+// PF chunks ahead and, at the end of a step, with the first chunks of the next
+// step, so the loads overlap the epilogue and the jump handler.
+template <class Mode, int NP>
+constexpr int prefetch_depth() {
+  constexpr int NKC = NP / Mode::KC;
+  constexpr int want = (Mode::KC == 4) ? 8 : 2;
+  return NKC < want ? NKC : want;
 }
 
 // ----------------------------------------------------------- jump handler --
@@ -442,7 +482,7 @@ __device__ void run_tile(const StepArgs& a, int64_t tile, TileShared<NP, TQ, typ
 
   const int tid = threadIdx.x;
   const int lane = tid & (kWave - 1);
-  const int wave = tid >> 6;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);   // uniform per wave
   const int64_t tb = tile * TT;
   const int lc = lane & 15;          // MFMA output column
   const int part = (lane >> 3) & 1;  // 0: real part, 1: imaginary part
@@ -461,11 +501,30 @@ __device__ void run_tile(const StepArgs& a, int64_t tile, TileShared<NP, TQ, typ
 #pragma unroll
   for (int u = 0; u < UPW; ++u) {
     const int unit = wave + 4 * u;
-    ok_u[u] = unit < NUNITS;
+    ok_u[u] = (NUNITS % 4 == 0) || unit < NUNITS;   // 4 waves per workgroup
     rt_u[u] = unit % NRT;
     q0_u[u] = (unit / NRT) * QG;
   }
   Acc acc[UPW][QG];
+  // every unit covers all column tiles (q0 = 0) when there are >= 4 row tiles
+  constexpr bool kSharedQ = (QG == TQ);
+#define q0(u) (kSharedQ ? 0 : q0_u[u])
+  // fragment (g, row tile, k chunk) lives at ((g * NRT + rt) * NKC + k) * 64 + lane
+  size_t fbase[UPW];
+#pragma unroll
+  for (int u = 0; u < UPW; ++u) fbase[u] = static_cast<size_t>(rt_u[u]) * NKC * kWave + lane;
+#define frag_index(gg, u, k) \
+  (static_cast<size_t>(gg) * (NRT * NKC * kWave) + fbase[u] + static_cast<size_t>(k) * kWave)
+  constexpr int PF = prefetch_depth<Mode, NP>();
+  static_assert(NKC % PF == 0, "prefetch depth must divide the k chunks");
+  Frag<Mode> ring[PF][UPW];
+  if (a.M_run > 2) {
+#pragma unroll
+    for (int s2 = 0; s2 < PF; ++s2)
+#pragma unroll
+      for (int u = 0; u < UPW; ++u)
+        if (ok_u[u]) ring[s2][u] = load_frag<Mode>(a, frag_index(2, u, s2));
+  }
 
   for (int g = 1; g < a.M_run; ++g) {
     const int gsz = a.gs[g];
@@ -478,90 +537,96 @@ __device__ void run_tile(const StepArgs& a, int64_t tile, TileShared<NP, TQ, typ
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
           const int row = rt_u[u] * 16 + Mode::row(lane, i);
-          acc[u][qq][i] = (g == 1) ? (part ? T(0) : static_cast<T>(a.cinit[row])) : S[q0_u[u] + qq][row][lc];
+          acc[u][qq][i] = (g == 1) ? (part ? T(0) : static_cast<T>(a.cinit[row])) : S[q0(u) + qq][row][lc];
         }
     }
     if (g > 1) {
-      if constexpr (Mode::KC == 4) {
-        // A fragments are prefetched two k chunks ahead (two register sets) so the
-        // global-load latency hides behind the MFMAs of the chunk in flight.
-        const T* A = static_cast<const T*>(a.dlt_a) + static_cast<size_t>(g) * NRT * NKC * kWave + lane;
-        T pa[2][UPW];
+      for (int kc = 0; kc < NKC; kc += PF) {
 #pragma unroll
-        for (int s2 = 0; s2 < 2; ++s2)
+        for (int s2 = 0; s2 < PF; ++s2) {
+          const int k = kc + s2;
+          Frag<Mode> av[UPW];
+#pragma unroll
+          for (int u = 0; u < UPW; ++u) av[u] = ring[s2][u];
+          // refill this slot PF chunks ahead (next step's first chunks at the end)
+          // (after the last step the slot reloads grid M_run - 1: in bounds, unused)
+          const int kn = k + PF;
+          const int gn = min(kn < NKC ? g : g + 1, a.M_run - 1);
+          const int kk = kn < NKC ? kn : kn - NKC;
 #pragma unroll
           for (int u = 0; u < UPW; ++u)
-            pa[s2][u] = ok_u[u] ? A[(static_cast<size_t>(rt_u[u]) * NKC + s2) * kWave] : T(0);
-        for (int kc = 0; kc < NKC; kc += 2) {
-#pragma unroll
-          for (int s2 = 0; s2 < 2; ++s2) {
-            const int k = kc + s2;
-            T av[UPW];
-#pragma unroll
-            for (int u = 0; u < UPW; ++u) av[u] = pa[s2][u];
-            if (k + 2 < NKC) {
-#pragma unroll
-              for (int u = 0; u < UPW; ++u)
-                pa[s2][u] = ok_u[u] ? A[(static_cast<size_t>(rt_u[u]) * NKC + k + 2) * kWave] : T(0);
-            }
+            if (ok_u[u]) ring[s2][u] = load_frag<Mode>(a, frag_index(gn, u, kk));
+          if constexpr (Mode::KC == 4) {
             const int krow = 4 * k + (lane >> 4);
+            T bv[UPW][QG];
+#pragma unroll
+            for (int u = 0; u < UPW; ++u)
+#pragma unroll
+              for (int qq = 0; qq < QG; ++qq)
+                bv[u][qq] = (u == 0 || !kSharedQ) ? S[q0(u) + qq][krow][lc] : bv[0][qq];
 #pragma unroll
             for (int u = 0; u < UPW; ++u) {
               if (!ok_u[u]) continue;
 #pragma unroll
-              for (int qq = 0; qq < QG; ++qq) acc[u][qq] = mfma_k4(av[u], S[q0_u[u] + qq][krow][lc], acc[u][qq]);
+              for (int qq = 0; qq < QG; ++qq) acc[u][qq] = mfma_k4(av[u].v, bv[u][qq], acc[u][qq]);
             }
-          }
-        }
-      } else if constexpr (Mode::KC == 16) {
-        const uint2* Ah = static_cast<const uint2*>(a.dlt_a) + static_cast<size_t>(g) * NRT * NKC * kWave + lane;
-        const uint2* Al = static_cast<const uint2*>(a.dlt_b) + static_cast<size_t>(g) * NRT * NKC * kWave + lane;
-        for (int kc = 0; kc < NKC; ++kc) {
-          const int k0 = 16 * kc + 4 * (lane >> 4);
+          } else if constexpr (Mode::KC == 16) {
+            const int k0 = 16 * k + 4 * (lane >> 4);
 #pragma unroll
-          for (int u = 0; u < UPW; ++u) {
-            if (!ok_u[u]) continue;
-            const size_t off = (static_cast<size_t>(rt_u[u]) * NKC + kc) * kWave;
-            const s16x4 ah = __builtin_bit_cast(s16x4, Ah[off]);
-            const s16x4 al = __builtin_bit_cast(s16x4, Al[off]);
+            for (int u = 0; u < UPW; ++u) {
+              if (!ok_u[u]) continue;
+              const s16x4 ah = __builtin_bit_cast(s16x4, av[u].h);
+              const s16x4 al = __builtin_bit_cast(s16x4, av[u].l);
 #pragma unroll
-            for (int qq = 0; qq < QG; ++qq) {
-              float xv[4];
+              for (int qq = 0; qq < QG; ++qq) {
+                float xv[4];
 #pragma unroll
-              for (int j = 0; j < 4; ++j) xv[j] = S[q0_u[u] + qq][k0 + j][lc];
-              s16x4 bh, bl;
-              split4(xv, bh, bl);
-              Acc c = acc[u][qq];
-              c = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah, bh, c, 0, 0, 0);
-              c = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah, bl, c, 0, 0, 0);
-              c = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(al, bh, c, 0, 0, 0);
-              acc[u][qq] = c;
+                for (int j = 0; j < 4; ++j) xv[j] = S[q0(u) + qq][k0 + j][lc];
+                s16x4 bh, bl;
+                split4(xv, bh, bl);
+                Acc c = acc[u][qq];
+                c = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah, bh, c, 0, 0, 0);
+                c = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah, bl, c, 0, 0, 0);
+                c = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(al, bh, c, 0, 0, 0);
+                acc[u][qq] = c;
+              }
             }
-          }
-        }
-      } else {
-        const uint4* Ah = static_cast<const uint4*>(a.dlt_a) + static_cast<size_t>(g) * NRT * NKC * kWave + lane;
-        const uint4* Al = static_cast<const uint4*>(a.dlt_b) + static_cast<size_t>(g) * NRT * NKC * kWave + lane;
-        for (int kc = 0; kc < NKC; ++kc) {
-          const int k0 = 32 * kc + 8 * (lane >> 4);
+          } else {
+            const int k0 = 32 * k + 8 * (lane >> 4);
+            // B split once per column tile when every unit shares the column tiles
+            bf16x8 bh[kSharedQ ? QG : 1], bl[kSharedQ ? QG : 1];
+            if constexpr (kSharedQ) {
 #pragma unroll
-          for (int u = 0; u < UPW; ++u) {
-            if (!ok_u[u]) continue;
-            const size_t off = (static_cast<size_t>(rt_u[u]) * NKC + kc) * kWave;
-            const bf16x8 ah = __builtin_bit_cast(bf16x8, Ah[off]);
-            const bf16x8 al = __builtin_bit_cast(bf16x8, Al[off]);
+              for (int qq = 0; qq < QG; ++qq) {
+                float xv[8];
 #pragma unroll
-            for (int qq = 0; qq < QG; ++qq) {
-              float xv[8];
+                for (int j = 0; j < 8; ++j) xv[j] = S[qq][k0 + j][lc];
+                split8(xv, bh[qq], bl[qq]);
+              }
+            }
 #pragma unroll
-              for (int j = 0; j < 8; ++j) xv[j] = S[q0_u[u] + qq][k0 + j][lc];
-              bf16x8 bh, bl;
-              split8(xv, bh, bl);
-              Acc c = acc[u][qq];
-              c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh, c, 0, 0, 0);
-              c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl, c, 0, 0, 0);
-              c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh, c, 0, 0, 0);
-              acc[u][qq] = c;
+            for (int u = 0; u < UPW; ++u) {
+              if (!ok_u[u]) continue;
+              const bf16x8 ah = __builtin_bit_cast(bf16x8, av[u].h);
+              const bf16x8 al = __builtin_bit_cast(bf16x8, av[u].l);
+#pragma unroll
+              for (int qq = 0; qq < QG; ++qq) {
+                bf16x8 h, l;
+                if constexpr (kSharedQ) {
+                  h = bh[qq];
+                  l = bl[qq];
+                } else {
+                  float xv[8];
+#pragma unroll
+                  for (int j = 0; j < 8; ++j) xv[j] = S[q0(u) + qq][k0 + j][lc];
+                  split8(xv, h, l);
+                }
+                Acc c = acc[u][qq];
+                c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, h, c, 0, 0, 0);
+                c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, l, c, 0, 0, 0);
+                c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, h, c, 0, 0, 0);
+                acc[u][qq] = c;
+              }
             }
           }
         }
@@ -592,7 +657,7 @@ __device__ void run_tile(const StepArgs& a, int64_t tile, TileShared<NP, TQ, typ
             const T yp = __shfl_xor(y, 8, kWave);       // the other part of the same amplitude
             const T yr = part ? yp : y, yi = part ? y : yp;
             const T c = part ? (drv[i] * yi + div[i] * yr) : (drv[i] * yr - div[i] * yi);
-            S[q0_u[u] + qq][row][lc] = c;
+            S[q0(u) + qq][row][lc] = c;
             nrm += c * c;
             if (row < gsz) gw += c * c;
           }
@@ -603,8 +668,8 @@ __device__ void run_tile(const StepArgs& a, int64_t tile, TileShared<NP, TQ, typ
           gw += __shfl_xor(gw, 16, kWave);
           gw += __shfl_xor(gw, 32, kWave);
           if (lane < 8) {
-            s_nu[rt][(q0_u[u] + qq) * 8 + lane] = nrm;
-            s_gw[rt][(q0_u[u] + qq) * 8 + lane] = gw;
+            s_nu[rt][(q0(u) + qq) * 8 + lane] = nrm;
+            s_gw[rt][(q0(u) + qq) * 8 + lane] = gw;
           }
         }
       }
@@ -674,6 +739,8 @@ __device__ void run_tile(const StepArgs& a, int64_t tile, TileShared<NP, TQ, typ
     atomicAdd(reinterpret_cast<unsigned long long*>(&a.jump_totals[tid]),
               static_cast<unsigned long long>(s_kind[tid]));
   __syncthreads();   // the shared tile state may be reused by the caller
+#undef q0
+#undef frag_index
 }
 
 template <int NP, int TQ, class Mode>
