@@ -193,18 +193,35 @@ constexpr int prefetch_depth() {
 }
 
 // ----------------------------------------------------------- jump handler --
-// Tile layout in LDS: S[q][row][c] holds column tile q (8 trajectories); column
-// c = (t & 7) + 8 * part carries the real (part 0) or imaginary (part 1) part of
-// local trajectory t = 8 q + (c & 7).
+// Tile layout in LDS: S[q][c][row] holds column tile q (8 trajectories) column-
+// major; column c = (t & 7) + 8 * part carries the real (part 0) or imaginary
+// (part 1) part of local trajectory t = 8 q + (c & 7).  Columns are padded to
+// NP + kPad elements so the 16 columns of an MFMA operand fall in distinct banks.
+constexpr int kPad = 4;
 template <int NP, class T>
-__device__ __forceinline__ T& amp(T (*S)[NP][16], int t, int part, int row) {
-  return S[t >> 3][row][(t & 7) + 8 * part];
+using TileCols = T[16][NP + kPad];
+
+template <int NP, class T>
+__device__ __forceinline__ T& amp(TileCols<NP, T>* S, int t, int part, int row) {
+  return S[t >> 3][(t & 7) + 8 * part][row];
+}
+
+// Exchange with lane ^ 8 (the other part of the same amplitude) by DPP row
+// rotation: within each row of 16 lanes, rotating by 8 maps lane i to i ^ 8.
+__device__ __forceinline__ float xor8(float v) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x128, 0xf, 0xf, false));
+}
+__device__ __forceinline__ double xor8(double v) {
+  const uint64_t u = __builtin_bit_cast(uint64_t, v);
+  const int lo = __builtin_amdgcn_update_dpp(0, static_cast<int>(u & 0xffffffffu), 0x128, 0xf, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, static_cast<int>(u >> 32), 0x128, 0xf, 0xf, false);
+  return __builtin_bit_cast(double, (static_cast<uint64_t>(static_cast<uint32_t>(hi)) << 32) | static_cast<uint32_t>(lo));
 }
 
 // One wavefront finishes step g for local trajectory t whose amplitudes after
 // the fused propagator are in S.  Works in FP64.
 template <int NP, class T>
-__device__ void finish_crossing(const StepArgs& a, int g, int t, int64_t jloc, T (*S)[NP][16],
+__device__ void finish_crossing(const StepArgs& a, int g, int t, int64_t jloc, TileCols<NP, T>* S,
                                 double* s_r, int* s_m, int* s_cnt, int* s_net, double* s_p,
                                 int* s_kind) {
   constexpr int PL = (NP + kWave - 1) / kWave;
@@ -445,9 +462,9 @@ template <int NP, int TQ, class T>
 struct TileShared {
   static constexpr int NRT = NP / 16;
   static constexpr int TT = 8 * TQ;
-  T S[TQ][NP][16];
-  T nu[NRT][TT];
-  T gw[NRT][TT];
+  static constexpr int NSLOT = (NRT >= 4) ? 4 : NRT;   // partial squared norms per trajectory
+  TileCols<NP, T> S[TQ];
+  T nu[NSLOT][TT];
   double r[TT];
   double p[TT];
   int m[TT], cnt[TT], net[TT];
@@ -470,7 +487,7 @@ __device__ void run_tile(const StepArgs& a, int64_t tile, TileShared<NP, TQ, typ
 
   auto& S = sh.S;
   auto& s_nu = sh.nu;
-  auto& s_gw = sh.gw;
+  constexpr int NSLOT = TileShared<NP, TQ, T>::NSLOT;
   double* s_r = sh.r;
   double* s_p = sh.p;
   int* s_m = sh.m;
@@ -506,8 +523,11 @@ __device__ void run_tile(const StepArgs& a, int64_t tile, TileShared<NP, TQ, typ
     q0_u[u] = (unit / NRT) * QG;
   }
   Acc acc[UPW][QG];
-  // every unit covers all column tiles (q0 = 0) when there are >= 4 row tiles
-  constexpr bool kSharedQ = (QG == TQ);
+  // with >= 4 row tiles every unit covers all column tiles (q0 = 0) and each wave
+  // keeps one norm partial per trajectory (NSLOT = 4); otherwise units are
+  // (row tile, column tile) pairs and the partials are per row tile
+  constexpr bool kSharedQ = (NRT >= 4);
+  static_assert(NSLOT == (kSharedQ ? 4 : NRT), "norm slots follow the work split");
 #define q0(u) (kSharedQ ? 0 : q0_u[u])
   // fragment (g, row tile, k chunk) lives at ((g * NRT + rt) * NKC + k) * 64 + lane
   size_t fbase[UPW];
@@ -526,19 +546,51 @@ __device__ void run_tile(const StepArgs& a, int64_t tile, TileShared<NP, TQ, typ
         if (ok_u[u]) ring[s2][u] = load_frag<Mode>(a, frag_index(2, u, s2));
   }
 
+  // Accumulator <-> LDS: four rows of one column per lane (consecutive rows in
+  // the FP32 layouts, one 16-byte access).
+  auto acc_load = [&](int q, int rt, Acc& v) {
+    if constexpr (sizeof(T) == 4) {
+      v = *reinterpret_cast<const Acc*>(&S[q][lc][rt * 16 + 4 * (lane >> 4)]);
+    } else {
+#pragma unroll
+      for (int i = 0; i < 4; ++i) v[i] = S[q][lc][rt * 16 + Mode::row(lane, i)];
+    }
+  };
+  auto acc_store = [&](int q, int rt, const Acc& v) {
+    if constexpr (sizeof(T) == 4) {
+      *reinterpret_cast<Acc*>(&S[q][lc][rt * 16 + 4 * (lane >> 4)]) = v;
+    } else {
+#pragma unroll
+      for (int i = 0; i < 4; ++i) S[q][lc][rt * 16 + Mode::row(lane, i)] = v[i];
+    }
+  };
+  // The accumulators keep C between steps (the identity split starts from C);
+  // only column tiles touched by the jump handler are reloaded from LDS.
+  unsigned dirty = 0;
+
   for (int g = 1; g < a.M_run; ++g) {
     const int gsz = a.gs[g];
     // ---- 1. C + Delta C (or the initial state at g = 1)
+    if (g == 1) {
 #pragma unroll
-    for (int u = 0; u < UPW; ++u) {
-      if (!ok_u[u]) continue;
+      for (int u = 0; u < UPW; ++u) {
+        if (!ok_u[u]) continue;
 #pragma unroll
-      for (int qq = 0; qq < QG; ++qq)
+        for (int qq = 0; qq < QG; ++qq)
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-          const int row = rt_u[u] * 16 + Mode::row(lane, i);
-          acc[u][qq][i] = (g == 1) ? (part ? T(0) : static_cast<T>(a.cinit[row])) : S[q0(u) + qq][row][lc];
-        }
+          for (int i = 0; i < 4; ++i) {
+            const int row = rt_u[u] * 16 + Mode::row(lane, i);
+            acc[u][qq][i] = part ? T(0) : static_cast<T>(a.cinit[row]);
+          }
+      }
+    } else if (dirty) {
+#pragma unroll
+      for (int u = 0; u < UPW; ++u) {
+        if (!ok_u[u]) continue;
+#pragma unroll
+        for (int qq = 0; qq < QG; ++qq)
+          if ((dirty >> (q0(u) + qq)) & 1u) acc_load(q0(u) + qq, rt_u[u], acc[u][qq]);
+      }
     }
     if (g > 1) {
       for (int kc = 0; kc < NKC; kc += PF) {
@@ -563,7 +615,7 @@ __device__ void run_tile(const StepArgs& a, int64_t tile, TileShared<NP, TQ, typ
             for (int u = 0; u < UPW; ++u)
 #pragma unroll
               for (int qq = 0; qq < QG; ++qq)
-                bv[u][qq] = (u == 0 || !kSharedQ) ? S[q0(u) + qq][krow][lc] : bv[0][qq];
+                bv[u][qq] = (u == 0 || !kSharedQ) ? S[q0(u) + qq][lc][krow] : bv[0][qq];
 #pragma unroll
             for (int u = 0; u < UPW; ++u) {
               if (!ok_u[u]) continue;
@@ -580,8 +632,7 @@ __device__ void run_tile(const StepArgs& a, int64_t tile, TileShared<NP, TQ, typ
 #pragma unroll
               for (int qq = 0; qq < QG; ++qq) {
                 float xv[4];
-#pragma unroll
-                for (int j = 0; j < 4; ++j) xv[j] = S[q0(u) + qq][k0 + j][lc];
+                *reinterpret_cast<float4*>(xv) = *reinterpret_cast<const float4*>(&S[q0(u) + qq][lc][k0]);
                 s16x4 bh, bl;
                 split4(xv, bh, bl);
                 Acc c = acc[u][qq];
@@ -599,8 +650,8 @@ __device__ void run_tile(const StepArgs& a, int64_t tile, TileShared<NP, TQ, typ
 #pragma unroll
               for (int qq = 0; qq < QG; ++qq) {
                 float xv[8];
-#pragma unroll
-                for (int j = 0; j < 8; ++j) xv[j] = S[qq][k0 + j][lc];
+                *reinterpret_cast<float4*>(xv) = *reinterpret_cast<const float4*>(&S[qq][lc][k0]);
+                *reinterpret_cast<float4*>(xv + 4) = *reinterpret_cast<const float4*>(&S[qq][lc][k0 + 4]);
                 split8(xv, bh[qq], bl[qq]);
               }
             }
@@ -617,8 +668,8 @@ __device__ void run_tile(const StepArgs& a, int64_t tile, TileShared<NP, TQ, typ
                   l = bl[qq];
                 } else {
                   float xv[8];
-#pragma unroll
-                  for (int j = 0; j < 8; ++j) xv[j] = S[q0(u) + qq][k0 + j][lc];
+                  *reinterpret_cast<float4*>(xv) = *reinterpret_cast<const float4*>(&S[q0(u) + qq][lc][k0]);
+                  *reinterpret_cast<float4*>(xv + 4) = *reinterpret_cast<const float4*>(&S[q0(u) + qq][lc][k0 + 4]);
                   split8(xv, h, l);
                 }
                 Acc c = acc[u][qq];
@@ -633,10 +684,13 @@ __device__ void run_tile(const StepArgs& a, int64_t tile, TileShared<NP, TQ, typ
       }
     }
     __syncthreads();   // every wave has finished reading S
-    // ---- 2. C' = d o C, squared norms and ground-cluster weights per row tile
+    // ---- 2. C' = d o C and the squared norms (partial sums per wave or row tile)
     {
       const T* dr = static_cast<const T*>(a.dre) + static_cast<size_t>(g) * NP;
       const T* di = static_cast<const T*>(a.dim) + static_cast<size_t>(g) * NP;
+      T nacc[QG];
+#pragma unroll
+      for (int qq = 0; qq < QG; ++qq) nacc[qq] = T(0);
 #pragma unroll
       for (int u = 0; u < UPW; ++u) {
         if (!ok_u[u]) continue;
@@ -649,28 +703,35 @@ __device__ void run_tile(const StepArgs& a, int64_t tile, TileShared<NP, TQ, typ
         }
 #pragma unroll
         for (int qq = 0; qq < QG; ++qq) {
-          T nrm = T(0), gw = T(0);
+          T nrm = T(0);
 #pragma unroll
           for (int i = 0; i < 4; ++i) {
-            const int row = rt * 16 + Mode::row(lane, i);
             const T y = acc[u][qq][i];
-            const T yp = __shfl_xor(y, 8, kWave);       // the other part of the same amplitude
+            const T yp = xor8(y);       // the other part of the same amplitude
             const T yr = part ? yp : y, yi = part ? y : yp;
             const T c = part ? (drv[i] * yi + div[i] * yr) : (drv[i] * yr - div[i] * yi);
-            S[q0(u) + qq][row][lc] = c;
+            acc[u][qq][i] = c;
             nrm += c * c;
-            if (row < gsz) gw += c * c;
           }
-          nrm += __shfl_xor(nrm, 8, kWave);
+          acc_store(q0(u) + qq, rt, acc[u][qq]);
+          if constexpr (kSharedQ) {
+            nacc[qq] += nrm;
+          } else {
+            nrm += xor8(nrm);
+            nrm += __shfl_xor(nrm, 16, kWave);
+            nrm += __shfl_xor(nrm, 32, kWave);
+            if (lane < 8) s_nu[rt][(q0(u) + qq) * 8 + lane] = nrm;
+          }
+        }
+      }
+      if constexpr (kSharedQ) {
+#pragma unroll
+        for (int qq = 0; qq < QG; ++qq) {
+          T nrm = nacc[qq];
+          nrm += xor8(nrm);
           nrm += __shfl_xor(nrm, 16, kWave);
           nrm += __shfl_xor(nrm, 32, kWave);
-          gw += __shfl_xor(gw, 8, kWave);
-          gw += __shfl_xor(gw, 16, kWave);
-          gw += __shfl_xor(gw, 32, kWave);
-          if (lane < 8) {
-            s_nu[rt][(q0(u) + qq) * 8 + lane] = nrm;
-            s_gw[rt][(q0(u) + qq) * 8 + lane] = gw;
-          }
+          if (lane < 8) s_nu[wave][qq * 8 + lane] = nrm;
         }
       }
     }
@@ -679,16 +740,20 @@ __device__ void run_tile(const StepArgs& a, int64_t tile, TileShared<NP, TQ, typ
     // ---- 3. threshold test
     if (tid < TT) {
       const bool valid = tb + tid < a.K;
-      double nu = 0.0, gw = 0.0;
+      double nu = 0.0;
 #pragma unroll
-      for (int rt = 0; rt < NRT; ++rt) {
-        nu += static_cast<double>(s_nu[rt][tid]);
-        gw += static_cast<double>(s_gw[rt][tid]);
-      }
+      for (int sl = 0; sl < NSLOT; ++sl) nu += static_cast<double>(s_nu[sl][tid]);
       if (valid) {
         if (nu <= s_r[tid]) {
           s_list[atomicAdd(&s_nlist, 1)] = tid;
         } else {
+          // ground-cluster weight: the (few) lowest rows of this trajectory
+          double gw = 0.0;
+          for (int row = 0; row < gsz; ++row) {
+            const double re = static_cast<double>(amp<NP, T>(S, tid, 0, row));
+            const double im = static_cast<double>(amp<NP, T>(S, tid, 1, row));
+            gw += re * re + im * im;
+          }
           s_p[tid] = gw / nu;
         }
       } else {
@@ -696,12 +761,15 @@ __device__ void run_tile(const StepArgs& a, int64_t tile, TileShared<NP, TQ, typ
       }
     }
     __syncthreads();
-    const int ncross = s_nlist;
+    const int ncross = __builtin_amdgcn_readfirstlane(s_nlist);
     for (int e = wave; e < ncross; e += 4) {
       const int t = s_list[e];
       finish_crossing<NP, T>(a, g, t, tb + t, S, s_r, s_m, s_cnt, s_net, s_p, s_kind);
     }
     __syncthreads();
+    // column tiles whose amplitudes the handler rewrote
+    dirty = 0;
+    for (int e = 0; e < ncross; ++e) dirty |= 1u << (__builtin_amdgcn_readfirstlane(s_list[e]) >> 3);
     // ---- 4. per-tile observable sums (wave 0)
     if (wave == 0) {
       const double p = (lane < TT) ? s_p[lane] : 0.0;
