@@ -38,7 +38,8 @@ struct aqt_ctx {
   aqt::DevBuf R;        // [M][nq][NP(b)][NP(a)]
   aqt::DevBuf zdiag;    // [M][nq][NP]
   aqt::DevBuf Gamma;    // [M][NP]
-  aqt::DevBuf Rq;       // [M][nq][NP] row sums sum_a R[i][b][a] (qubit draw of a jump)
+  aqt::DevBuf Rcol;     // [M][nq][NP][4]: sum_a R[i][b][a], sum_{a<b} R[i][b][a], R[i][b][b], 0
+  aqt::DevBuf ehalf;    // [M][NP] exp(+Gamma dt / 2), undoes the step's decay
   aqt::DevBuf dre, dim; // [M][NP] FP64 exp(-i e dt - Gamma dt / 2)
   aqt::DevBuf leak;     // [M]
 

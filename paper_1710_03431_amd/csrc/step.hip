@@ -92,7 +92,8 @@ struct StepArgs {
   const double* d64re;   // [M][NP]
   const double* d64im;
   const double* R;       // [M][nq][NP][NP]
-  const double* Rq;      // [M][nq][NP] row sums of R over the target level
+  const double* Rcol;    // [M][nq][NP][4] row sum, sum below the diagonal, diagonal of R
+  const double* ehalf;   // [M][NP] exp(+Gamma dt / 2)
   const double* zdiag;   // [M][nq][NP]
   const double* E;       // [M][NP]
   const int* gs;         // [M]
@@ -218,8 +219,40 @@ __device__ __forceinline__ double xor8(double v) {
   return __builtin_bit_cast(double, (static_cast<uint64_t>(static_cast<uint32_t>(hi)) << 32) | static_cast<uint32_t>(lo));
 }
 
+// Uniform draws of one trajectory served from Philox blocks computed in parallel:
+// lane l holds block B0 + l (four words), so one generator evaluation covers the
+// next 256 draws; later draws (more than about 80 jumps in one step) fall back
+// to a direct evaluation.
+struct DrawCache {
+  uint64_t B0;
+  uint64_t w0, w1, w2, w3;
+  uint64_t seed, iid, traj;
+  __device__ void fill(uint64_t seed_, uint64_t iid_, uint64_t traj_, uint64_t first_draw) {
+    seed = seed_;
+    iid = iid_;
+    traj = traj_;
+    B0 = first_draw >> 2;
+    const Philox4 r = philox4x64_10(traj, B0 + (threadIdx.x & (kWave - 1)), 0, 0, seed, iid);
+    w0 = r.w[0];
+    w1 = r.w[1];
+    w2 = r.w[2];
+    w3 = r.w[3];
+  }
+  __device__ double operator()(uint64_t d) const {
+    const uint64_t rel = (d >> 2) - B0;
+    if (rel >= static_cast<uint64_t>(kWave)) return draw_uniform(seed, iid, traj, d);
+    const unsigned k = static_cast<unsigned>(d & 3);
+    const uint64_t mine = k == 0 ? w0 : (k == 1 ? w1 : (k == 2 ? w2 : w3));
+    const int src = static_cast<int>(rel);
+    const uint32_t lo = __shfl(static_cast<uint32_t>(mine & 0xffffffffu), src, kWave);
+    const uint32_t hi = __shfl(static_cast<uint32_t>(mine >> 32), src, kWave);
+    return uniform_open01((static_cast<uint64_t>(hi) << 32) | lo);
+  }
+};
+
 // One wavefront finishes step g for local trajectory t whose amplitudes after
-// the fused propagator are in S.  Works in FP64.
+// the fused propagator are in S (the threshold pass found sum |S|^2 <= r in the
+// state precision).  Works in FP64.
 template <int NP, class T>
 __device__ void finish_crossing(const StepArgs& a, int g, int t, int64_t jloc, TileCols<NP, T>* S,
                                 double* s_r, int* s_m, int* s_cnt, int* s_net, double* s_p,
@@ -229,20 +262,16 @@ __device__ void finish_crossing(const StepArgs& a, int g, int t, int64_t jloc, T
   const double dt = a.dt;
   const uint64_t traj = a.traj0 + static_cast<uint64_t>(jloc);   // Philox counter word 0
   const double* Gam = a.Gamma + static_cast<size_t>(g) * NP;
-  double cr[PL], ci[PL], G[PL];
+  const double* Eh = a.ehalf + static_cast<size_t>(g) * NP;
+  double sr[PL], si[PL], G[PL], up[PL];
 #pragma unroll
   for (int j = 0; j < PL; ++j) {
     const int x = lane + kWave * j;
-    if (x < NP) {
-      G[j] = Gam[x];
-      // undo the full-step decay of the fused propagator: keep phases, restore magnitudes
-      const double up = exp(fmin(0.5 * G[j] * dt, 700.0));
-      cr[j] = static_cast<double>(amp<NP, T>(S, t, 0, x)) * up;
-      ci[j] = static_cast<double>(amp<NP, T>(S, t, 1, x)) * up;
-    } else {
-      G[j] = 0.0;
-      cr[j] = ci[j] = 0.0;
-    }
+    const bool in = x < NP;
+    G[j] = in ? Gam[x] : 0.0;
+    up[j] = in ? Eh[x] : 0.0;
+    sr[j] = in ? static_cast<double>(amp<NP, T>(S, t, 0, x)) : 0.0;
+    si[j] = in ? static_cast<double>(amp<NP, T>(S, t, 1, x)) : 0.0;
   }
   double r = s_r[t];
   int m = s_m[t];
@@ -250,33 +279,66 @@ __device__ void finish_crossing(const StepArgs& a, int g, int t, int64_t jloc, T
   int net = s_net[t];
   const int gsz = a.gs[g];
   const double tk = (g - 1) * dt;
+  // the crossing test of the whole step, in FP64: sum_b |c_b|^2 e^{-G_b dt} = sum |S|^2
+  double nu0 = 0.0;
+#pragma unroll
+  for (int j = 0; j < PL; ++j) nu0 += sr[j] * sr[j] + si[j] * si[j];
+  nu0 = wave_sum(nu0);
+  if (nu0 > r) {
+    // no crossing after all (the state-precision test was within rounding): S stays
+    double pg = 0.0;
+#pragma unroll
+    for (int j = 0; j < PL; ++j)
+      if (lane + kWave * j < gsz) pg += sr[j] * sr[j] + si[j] * si[j];
+    pg = wave_sum(pg);
+    if (lane == 0) s_p[t] = pg / nu0;
+    return;
+  }
+  DrawCache draw;
+  draw.fill(a.seed, a.iid, traj, 3ull * m + 1);
+  // amplitudes at the start of the step's decay: undo the fused e^{-G dt / 2}
+  double cr[PL], ci[PL];
+#pragma unroll
+  for (int j = 0; j < PL; ++j) {
+    cr[j] = sr[j] * up[j];
+    ci[j] = si[j] * up[j];
+  }
+  const double* Rc = a.Rcol + static_cast<size_t>(g) * a.nq * NP * 4;
   double tau_e = 0.0;
   for (int guard = 0; guard < 4096; ++guard) {   // jumps within one step
     const double rem = dt - tau_e;
-    double part = 0.0;
-#pragma unroll
-    for (int j = 0; j < PL; ++j) part += (cr[j] * cr[j] + ci[j] * ci[j]) * exp(-G[j] * rem);
-    const double nu_end = wave_sum(part);
-    if (nu_end > r) {
+    if (guard > 0) {
+      // after a jump: does the norm reach the next threshold within the rest of the step?
+      double h[PL], part = 0.0;
 #pragma unroll
       for (int j = 0; j < PL; ++j) {
-        const double f = exp(-0.5 * G[j] * rem);
-        cr[j] *= f;
-        ci[j] *= f;
+        h[j] = exp(-0.5 * G[j] * rem);
+        part += (cr[j] * cr[j] + ci[j] * ci[j]) * (h[j] * h[j]);
       }
-      break;
+      const double nu_end = wave_sum(part);
+      if (nu_end > r) {
+#pragma unroll
+        for (int j = 0; j < PL; ++j) {
+          cr[j] *= h[j];
+          ci[j] *= h[j];
+        }
+        break;
+      }
     }
     // crossing time: Newton on log sum_b w_b e^{-G_b tau} = log r from tau = 0
-    double w[PL];
+    double w[PL], hf[PL];
 #pragma unroll
-    for (int j = 0; j < PL; ++j) w[j] = cr[j] * cr[j] + ci[j] * ci[j];
+    for (int j = 0; j < PL; ++j) {
+      w[j] = cr[j] * cr[j] + ci[j] * ci[j];
+      hf[j] = 1.0;
+    }
     double tau = 0.0;
     const double logr = log(r);
     for (int it = 0; it < 100; ++it) {
       double s0 = 0.0, s1 = 0.0;
 #pragma unroll
       for (int j = 0; j < PL; ++j) {
-        const double e = w[j] * exp(-G[j] * tau);
+        const double e = w[j] * (hf[j] * hf[j]);
         s0 += e;
         s1 += G[j] * e;
       }
@@ -286,27 +348,27 @@ __device__ void finish_crossing(const StepArgs& a, int g, int t, int64_t jloc, T
       const double fp = -s1 / s0;
       if (fp == 0.0) {
         tau = rem;
+#pragma unroll
+        for (int j = 0; j < PL; ++j) hf[j] = exp(-0.5 * G[j] * tau);
         break;
       }
       const double stp = -f / fp;
       if (!(stp > 0.0)) break;
       const double tn = fmin(tau + stp, rem);
-      if (tn - tau <= 1e-15 * dt) {
-        tau = tn;
-        break;
-      }
+      const bool done = (tn - tau <= 1e-15 * dt) || (tn >= rem);
       tau = tn;
-      if (tau >= rem) break;
+#pragma unroll
+      for (int j = 0; j < PL; ++j) hf[j] = exp(-0.5 * G[j] * tau);
+      if (done) break;
     }
 #pragma unroll
     for (int j = 0; j < PL; ++j) {
-      const double f = exp(-0.5 * G[j] * tau);
-      cr[j] *= f;
-      ci[j] *= f;
+      cr[j] *= hf[j];
+      ci[j] *= hf[j];
     }
     tau_e += tau;
-    const double u1 = draw_uniform(a.seed, a.iid, traj, 3ull * m + 1);
-    const double u2 = draw_uniform(a.seed, a.iid, traj, 3ull * m + 2);
+    const double u1 = draw(3ull * m + 1);
+    const double u2 = draw(3ull * m + 2);
     // source level b: first index whose running sum of q_b Gamma_b exceeds u1 * total
     int b = -1;
     {
@@ -341,12 +403,18 @@ __device__ void finish_crossing(const StepArgs& a, int g, int t, int64_t jloc, T
       break;
     }
     // qubit i and target a: inverse CDF over R[g][i][b][a] in i-major, a-minor order,
-    // taken in two stages -- the qubit from the row sums, then the target within
-    // that row -- which selects the same (i, a) as one pass over the whole list.
+    // taken in stages -- the qubit from the row sums, then the diagonal (omega = 0)
+    // element from the sum below it, and only for a != b a scan of the row --
+    // which selects the same (i, a) as one pass over the whole list.
     int qi = 0, ta = b;
     {
-      const double* Rqg = a.Rq + static_cast<size_t>(g) * a.nq * NP;
-      const double rs = (lane < a.nq) ? Rqg[static_cast<size_t>(lane) * NP + b] : 0.0;
+      double rs = 0.0, rlo = 0.0, rdg = 0.0;
+      if (lane < a.nq) {
+        const double* c4 = Rc + (static_cast<size_t>(lane) * NP + b) * 4;
+        rs = c4[0];
+        rlo = c4[1];
+        rdg = c4[2];
+      }
       const double cum_i = wave_inclusive_scan(rs);
       const double tot = __shfl(cum_i, kWave - 1, kWave);
       const double thr = u2 * tot;
@@ -355,25 +423,29 @@ __device__ void finish_crossing(const StepArgs& a, int g, int t, int64_t jloc, T
       qi = hit_i ? first_set_lane(hit_i) : last_set_lane(pos_i);
       if (qi < 0) qi = 0;
       const double before = (qi > 0) ? __shfl(cum_i, qi - 1, kWave) : 0.0;
-      const double* row = a.R + ((static_cast<size_t>(g) * a.nq + qi) * NP + b) * NP;
-      double v[PL];
+      const double lo_q = __shfl(rlo, qi, kWave), dg_q = __shfl(rdg, qi, kWave);
+      const double rel = thr - before;
+      if (!(rel >= lo_q && rel < lo_q + dg_q)) {
+        const double* row = a.R + ((static_cast<size_t>(g) * a.nq + qi) * NP + b) * NP;
+        double v[PL];
 #pragma unroll
-      for (int j = 0; j < PL; ++j) {
-        const int x = lane + kWave * j;
-        v[j] = (x < NP) ? row[x] : 0.0;
-      }
-      double carry = before;
-      int hit = -1, lastpos = -1;
+        for (int j = 0; j < PL; ++j) {
+          const int x = lane + kWave * j;
+          v[j] = (x < NP) ? row[x] : 0.0;
+        }
+        double carry = before;
+        int hit = -1, lastpos = -1;
 #pragma unroll
-      for (int j = 0; j < PL; ++j) {
-        const double cum = wave_inclusive_scan(v[j]) + carry;
-        carry = __shfl(cum, kWave - 1, kWave);
-        const uint64_t h = __ballot(cum > thr);
-        if (hit < 0 && h) hit = first_set_lane(h) + kWave * j;
-        const uint64_t pz = __ballot(v[j] > 0.0);
-        if (pz) lastpos = last_set_lane(pz) + kWave * j;
+        for (int j = 0; j < PL; ++j) {
+          const double cum = wave_inclusive_scan(v[j]) + carry;
+          carry = __shfl(cum, kWave - 1, kWave);
+          const uint64_t h = __ballot(cum > thr);
+          if (hit < 0 && h) hit = first_set_lane(h) + kWave * j;
+          const uint64_t pz = __ballot(v[j] > 0.0);
+          if (pz) lastpos = last_set_lane(pz) + kWave * j;
+        }
+        ta = (hit >= 0) ? hit : (lastpos >= 0 ? lastpos : b);
       }
-      ta = (hit >= 0) ? hit : (lastpos >= 0 ? lastpos : b);
     }
     int kind;
     if (ta != b) {
@@ -427,7 +499,7 @@ __device__ void finish_crossing(const StepArgs& a, int g, int t, int64_t jloc, T
     }
     ++cnt;
     ++m;
-    r = draw_uniform(a.seed, a.iid, traj, 3ull * m);
+    r = draw(3ull * m);
   }
   double pg = 0.0, pt = 0.0;
 #pragma unroll
@@ -1035,7 +1107,8 @@ aqt_status launch_run(aqt_ctx* ctx, const aqt_run_params* p, const aqt_outputs* 
   a.d64re = ctx->dre.as<double>();
   a.d64im = ctx->dim.as<double>();
   a.R = ctx->R.as<double>();
-  a.Rq = ctx->Rq.as<double>();
+  a.Rcol = ctx->Rcol.as<double>();
+  a.ehalf = ctx->ehalf.as<double>();
   a.zdiag = ctx->zdiag.as<double>();
   a.E = ctx->E.as<double>();
   a.gs = ctx->gs.as<int>();
@@ -1300,7 +1373,8 @@ aqt_status aqt_batch_create(aqt_batch** out, aqt_ctx* const* ctxs, int n, const 
     a.d64re = c->dre.as<double>();
     a.d64im = c->dim.as<double>();
     a.R = c->R.as<double>();
-    a.Rq = c->Rq.as<double>();
+    a.Rcol = c->Rcol.as<double>();
+    a.ehalf = c->ehalf.as<double>();
     a.zdiag = c->zdiag.as<double>();
     a.E = c->E.as<double>();
     a.gs = c->gs.as<int>();

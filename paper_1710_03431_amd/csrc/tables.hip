@@ -2,7 +2,8 @@
 //
 // finish_tables: Gamma_b = sum_{i,a} R[i][b][a], the diagonal of
 //   sum_i A_i^dag A_i (Sec. III eq. Heff with the rates absorbed, eq. Aired),
-//   with the per-qubit row sums kept for the two-stage channel draw,
+//   with, per (qubit, source level), the row sum, the partial sum below the
+//   diagonal and the diagonal element kept for the two-stage channel draw,
 //   and d_b = exp(-i e_b dt - Gamma_b dt / 2), the no-jump propagator over one
 //   step of the diagonal effective Hamiltonian (Sec. III eq. detun).
 // pack_for_precision: Delta = O - I rearranged into 16x16 MFMA A-operand
@@ -20,20 +21,30 @@ namespace aqt {
 namespace {
 
 __global__ void k_gamma_phase(const double* __restrict__ E, const double* __restrict__ R, int M, int NP, int n,
-                              int nq, double dt, double* __restrict__ Gamma, double* __restrict__ Rq,
-                              double* __restrict__ dre, double* __restrict__ dim) {
+                              int nq, double dt, double* __restrict__ Gamma, double* __restrict__ Rcol,
+                              double* __restrict__ ehalf, double* __restrict__ dre, double* __restrict__ dim) {
   const int64_t idx = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
   if (idx >= static_cast<int64_t>(M) * NP) return;
   const int g = static_cast<int>(idx / NP);
   const int b = static_cast<int>(idx - static_cast<int64_t>(g) * NP);
   double G = 0.0;
   for (int i = 0; i < nq; ++i) {
-    double rs = 0.0;
+    double rs = 0.0, lo = 0.0, dg = 0.0;
     if (b < n) {
       const double* row = R + ((static_cast<size_t>(g) * nq + i) * NP + b) * NP;
-      for (int a = 0; a < n; ++a) rs += row[a];
+      for (int a = 0; a < n; ++a) {
+        if (a == b) {
+          lo = rs;
+          dg = row[a];
+        }
+        rs += row[a];
+      }
     }
-    Rq[(static_cast<size_t>(g) * nq + i) * NP + b] = rs;
+    double* out = Rcol + ((static_cast<size_t>(g) * nq + i) * NP + b) * 4;
+    out[0] = rs;
+    out[1] = lo;
+    out[2] = dg;
+    out[3] = 0.0;
     G += rs;
   }
   Gamma[idx] = G;
@@ -43,9 +54,11 @@ __global__ void k_gamma_phase(const double* __restrict__ E, const double* __rest
     const double mag = exp(-0.5 * G * dt);
     dre[idx] = mag * cs;
     dim[idx] = -mag * sn;
+    ehalf[idx] = exp(0.5 * G * dt);
   } else {
     dre[idx] = 0.0;
     dim[idx] = 0.0;
+    ehalf[idx] = 0.0;
   }
 }
 
@@ -149,11 +162,12 @@ aqt_status finish_tables(aqt_ctx* ctx) {
   const int64_t cnt = static_cast<int64_t>(ctx->M) * ctx->NP;
   if (ctx->Gamma.reserve(cnt * sizeof(double)) != hipSuccess || ctx->dre.reserve(cnt * sizeof(double)) != hipSuccess ||
       ctx->dim.reserve(cnt * sizeof(double)) != hipSuccess ||
-      ctx->Rq.reserve(cnt * ctx->nq * sizeof(double)) != hipSuccess)
+      ctx->Rcol.reserve(cnt * ctx->nq * 4 * sizeof(double)) != hipSuccess ||
+      ctx->ehalf.reserve(cnt * sizeof(double)) != hipSuccess)
     return ctx->fail(AQT_ENOMEM, "table allocation failed");
   hipLaunchKernelGGL(k_gamma_phase, dim3(blocks_for(cnt)), dim3(256), 0, ctx->stream, ctx->E.as<double>(),
                      ctx->R.as<double>(), ctx->M, ctx->NP, ctx->n, ctx->nq, ctx->dt, ctx->Gamma.as<double>(),
-                     ctx->Rq.as<double>(), ctx->dre.as<double>(), ctx->dim.as<double>());
+                     ctx->Rcol.as<double>(), ctx->ehalf.as<double>(), ctx->dre.as<double>(), ctx->dim.as<double>());
   AQT_HIP(ctx, hipGetLastError());
   ctx->packed_for = -1;
   return AQT_OK;
