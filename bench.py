@@ -92,6 +92,22 @@ def cpu_baseline(inst, n_traj, n_steps):
                       f"beforehand, untimed)"}
 
 
+def measured_traffic(kernel_key):
+    """HBM bytes per launch of the timed kernel from the committed rocprofv3 counter
+    record, or None when the kernel source changed since the counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "k_trajectories_a2a8_n256_K10000_traffic.json")
+    src = os.path.join(ROOT, "paper_1710_03431_amd", "csrc", "step.hip")
+    try:
+        rec = json.load(open(path))
+        sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    except (OSError, ValueError):
+        return None
+    if rec.get("step_hip_sha256") != sha or rec.get("kernel") != kernel_key:
+        return None
+    return rec["traffic_bytes"]
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -134,7 +150,8 @@ def main():
     flops = FLOP_PER_TRAJ_STEP(n) * K * (M - 1)
     achieved = flops / (head["ms"] / 1e3)
     roof = {"bound": "mfma", "achieved": achieved / 1e12, "peak": PEAK[head_prec] / 1e12, "unit": "TFLOP/s",
-            "frac": achieved / PEAK[head_prec], "traffic": None,
+            "frac": achieved / PEAK[head_prec],
+            "traffic": measured_traffic("k_trajectories<256, 5, ModeF32>") if head_prec == "fp32" else None,
             "kernel": f"k_trajectories<n=256, {head_prec}>",
             "per_unit": f"{FLOP_PER_TRAJ_STEP(n)} flop per trajectory-step"}
     cpu = None

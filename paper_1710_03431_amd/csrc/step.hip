@@ -198,7 +198,7 @@ constexpr int prefetch_depth() {
 // major; column c = (t & 7) + 8 * part carries the real (part 0) or imaginary
 // (part 1) part of local trajectory t = 8 q + (c & 7).  Columns are padded to
 // NP + kPad elements so the 16 columns of an MFMA operand fall in distinct banks.
-constexpr int kPad = 4;
+constexpr int kPad = 4;   // >= 4: the B read-ahead touches padding rows NP..NP+3
 template <int NP, class T>
 using TileCols = T[16][NP + kPad];
 
@@ -665,6 +665,11 @@ __device__ void run_tile(const StepArgs& a, int64_t tile, TileShared<NP, TQ, typ
       }
     }
     if (g > 1) {
+      T bnx[QG];
+      if constexpr (Mode::KC == 4 && kSharedQ) {
+#pragma unroll
+        for (int qq = 0; qq < QG; ++qq) bnx[qq] = S[qq][lc][lane >> 4];
+      }
       for (int kc = 0; kc < NKC; kc += PF) {
 #pragma unroll
         for (int s2 = 0; s2 < PF; ++s2) {
@@ -680,7 +685,20 @@ __device__ void run_tile(const StepArgs& a, int64_t tile, TileShared<NP, TQ, typ
 #pragma unroll
           for (int u = 0; u < UPW; ++u)
             if (ok_u[u]) ring[s2][u] = load_frag<Mode>(a, frag_index(gn, u, kk));
-          if constexpr (Mode::KC == 4) {
+          if constexpr (Mode::KC == 4 && kSharedQ) {
+            // B for this chunk was read one chunk ahead; read the next one now (on
+            // the last chunk that is padding row NP + lane / 16: in bounds, unused)
+            T bcur[QG];
+#pragma unroll
+            for (int qq = 0; qq < QG; ++qq) bcur[qq] = bnx[qq];
+            const int krn = 4 * (k + 1) + (lane >> 4);
+#pragma unroll
+            for (int qq = 0; qq < QG; ++qq) bnx[qq] = S[qq][lc][krn];
+#pragma unroll
+            for (int u = 0; u < UPW; ++u)
+#pragma unroll
+              for (int qq = 0; qq < QG; ++qq) acc[u][qq] = mfma_k4(av[u].v, bcur[qq], acc[u][qq]);
+          } else if constexpr (Mode::KC == 4) {
             const int krow = 4 * k + (lane >> 4);
             T bv[UPW][QG];
 #pragma unroll
