@@ -130,6 +130,23 @@ AQT_API aqt_status aqt_set_bath(aqt_ctx* ctx, double eta, double omega_c, double
  * of H(0) is degenerate or the eigensolver fails. */
 AQT_API aqt_status aqt_precompute(aqt_ctx* ctx, int n_grid, int n_levels, double deg_tol);
 
+/* Eigensolver choice of aqt_precompute_ex. */
+enum { AQT_EIG_AUTO = 0, AQT_EIG_DENSE = 1, AQT_EIG_ITERATIVE = 2 };
+
+/* aqt_precompute with an explicit eigensolver (Sec. II eq. Lindblad2 needs the
+ * lowest eigenpairs of H(s) at every grid point):
+ *   AQT_EIG_DENSE      dense FP64 solver per grid point, 2^n_qubits <= 1024;
+ *   AQT_EIG_ITERATIVE  Chebyshev-filtered subspace iteration with a matrix-free
+ *                      H(s) (any 2^n_qubits; truncated spectra with
+ *                      n_levels + 16 <= 120 and n_levels < 2^n_qubits), warm-
+ *                      started from the previous grid point, converged to
+ *                      residual <= 1e-12 of a bound on |H|;
+ *   AQT_EIG_AUTO       dense when 2^n_qubits <= 1024, else iterative.
+ * Both apply the same canonical cluster basis, signs and truncation.
+ * AQT_EINVAL for an unknown method or sizes outside these limits; AQT_ENUMERIC
+ * if the iteration does not converge.  Synchronises the stream. */
+AQT_API aqt_status aqt_precompute_ex(aqt_ctx* ctx, int n_grid, int n_levels, double deg_tol, int method);
+
 /* Load externally computed tables instead of aqt_precompute (same meaning as the
  * tables aqt_precompute builds; host arrays, FP64, row-major):
  *   E[n_grid*n]; gs[n_grid] ground-cluster sizes; O[n_grid*n*n] with O[g] the

@@ -6,7 +6,7 @@ leg may import anything under oracle/.
 What is computed, per grid point s_g = g/(M-1), g = 0..M-1, t = s t_f:
 
 * eigenpairs of H(s_g) in ascending order (numpy eigh for dense sizes, scipy
-  eigsh for the 2^16 gadget), the "instantaneous energy eigenstates" of
+  eigsh from a seeded random start for the 2^16 gadget), the "instantaneous energy eigenstates" of
   Sec. II (eq. Lindblad2);
 * clusters: maximal runs of consecutive levels whose gaps are below deg_tol.
   Inside a cluster the basis is rotated to the eigenbasis of the projected
@@ -97,15 +97,22 @@ def canonicalize(E: np.ndarray, V: np.ndarray, deg_tol: float):
     return E, V * sgn[None, :], cl
 
 
-def eigen(inst, s: float, n_keep: int, deg_tol: float, guard: int = 16):
-    """Lowest n_keep canonical eigenpairs of H(s) plus the ground-cluster size."""
+def eigen(inst, s: float, n_keep: int, deg_tol: float, guard: int = 16, method: str = "auto"):
+    """Lowest n_keep canonical eigenpairs of H(s) plus the ground-cluster size.
+
+    Dense eigh up to 4096 states, else ARPACK Lanczos (eigsh) for n_keep + guard pairs.
+    Lanczos starts from a seeded random vector: a structured start such as the uniform
+    superposition lies in one symmetry sector of H (for instance the qubit-permutation
+    symmetric sector of the two-cluster gadget) and would miss every level outside it;
+    a generic start reaches all sectors, and the restarts resolve degenerate levels."""
     N = inst.dim
-    if N <= 4096:
+    if method == "dense" or (method == "auto" and N <= 4096):
         E, V = np.linalg.eigh(model.hamiltonian_dense(inst, s))
     else:
         k = min(N - 2, n_keep + guard)
         H = model.hamiltonian_sparse(inst, s)
-        E, V = spla.eigsh(H, k=k, which="SA", tol=1e-13, v0=np.ones(N) / np.sqrt(N))
+        v0 = np.random.default_rng(20171009).standard_normal(N)
+        E, V = spla.eigsh(H, k=k, which="SA", tol=1e-13, v0=v0)
         o = np.argsort(E)
         E, V = E[o], V[:, o]
     E, V, cl = canonicalize(E, V, deg_tol)

@@ -21,7 +21,7 @@ PRECISIONS = {"fp64": FP64, "fp32": FP32, "bf16": BF16}
 KIND_NAMES = ("relax", "excite", "dephase")
 
 EXPORTED = ("aqt_create", "aqt_destroy", "aqt_last_error", "aqt_version", "aqt_set_hamiltonian",
-            "aqt_set_schedule", "aqt_set_bath", "aqt_precompute", "aqt_set_tables", "aqt_get_tables",
+            "aqt_set_schedule", "aqt_set_bath", "aqt_precompute", "aqt_precompute_ex", "aqt_set_tables", "aqt_get_tables",
             "aqt_get_dims", "aqt_run", "aqt_batch_create", "aqt_batch_launch", "aqt_batch_tiles",
             "aqt_batch_last_error", "aqt_batch_destroy")
 BATCH_GRAPH, BATCH_AUTOTUNE = 1, 2
@@ -44,6 +44,8 @@ class Outputs(C.Structure):
                 ("net_hist", C.c_void_p), ("hist_lo", C.c_int32), ("hist_hi", C.c_int32),
                 ("final_state", C.c_void_p)]
 
+
+EIG_METHODS = {"auto": 0, "dense": 1, "iterative": 2}
 
 JUMP_DTYPE = np.dtype([("t", "<f8"), ("step", "<i4"), ("qubit", "<i2"), ("kind", "<i2"),
                        ("from_level", "<i4"), ("to_level", "<i4")])
@@ -83,6 +85,7 @@ def load_library(path: str = LIB_PATH):
     lib.aqt_set_schedule.argtypes = [ctx, C.c_double, C.c_int, dp, dp]
     lib.aqt_set_bath.argtypes = [ctx, C.c_double, C.c_double, C.c_double]
     lib.aqt_precompute.argtypes = [ctx, C.c_int, C.c_int, C.c_double]
+    lib.aqt_precompute_ex.argtypes = [ctx, C.c_int, C.c_int, C.c_double, C.c_int]
     lib.aqt_set_tables.argtypes = [ctx, C.c_int, C.c_int, dp, ip, dp, dp, dp, dp]
     lib.aqt_get_tables.argtypes = [ctx, dp, ip, dp, dp, dp, dp, dp, dp]
     lib.aqt_get_dims.argtypes = [ctx, ip, ip, ip]
@@ -171,8 +174,10 @@ class Engine:
         self.set_schedule(inst.t_f, inst.A_ctrl, inst.B_ctrl)
         self.set_bath(inst.eta, inst.omega_c, inst.T)
 
-    def precompute(self, n_grid: int, n_levels: int, deg_tol: float = 1e-8):
-        self._check(self.lib.aqt_precompute(self.ctx, int(n_grid), int(n_levels), float(deg_tol)))
+    def precompute(self, n_grid: int, n_levels: int, deg_tol: float = 1e-8, method: str = "auto"):
+        """GPU eigensystem and tables; method "auto", "dense" or "iterative"."""
+        m = EIG_METHODS[method]
+        self._check(self.lib.aqt_precompute_ex(self.ctx, int(n_grid), int(n_levels), float(deg_tol), m))
         self._dims()
 
     def set_tables(self, E, gs, O, cinit, R, zdiag):

@@ -140,7 +140,13 @@ aqt_status aqt_set_bath(aqt_ctx* ctx, double eta, double omega_c, double T) {
 }
 
 aqt_status aqt_precompute(aqt_ctx* ctx, int n_grid, int n_levels, double deg_tol) {
+  return aqt_precompute_ex(ctx, n_grid, n_levels, deg_tol, AQT_EIG_AUTO);
+}
+
+aqt_status aqt_precompute_ex(aqt_ctx* ctx, int n_grid, int n_levels, double deg_tol, int method) {
   if (!ctx) return AQT_EINVAL;
+  if (method != AQT_EIG_AUTO && method != AQT_EIG_DENSE && method != AQT_EIG_ITERATIVE)
+    return ctx->fail(AQT_EINVAL, "unknown eigensolver method");
   if (!ctx->have_h || !ctx->have_sched || !ctx->have_bath)
     return ctx->fail(AQT_ESTATE, "set_hamiltonian, set_schedule and set_bath must come first");
   const int N = 1 << ctx->nq;
@@ -150,7 +156,7 @@ aqt_status aqt_precompute(aqt_ctx* ctx, int n_grid, int n_levels, double deg_tol
   aqt_status s = set_device(ctx);
   if (s != AQT_OK) return s;
   ctx->have_tables = false;
-  s = aqt::precompute_tables(ctx, n_grid, n_levels, deg_tol);
+  s = aqt::precompute_tables(ctx, n_grid, n_levels, deg_tol, method);
   if (s != AQT_OK) return s;
   s = aqt::finish_tables(ctx);
   if (s != AQT_OK) return s;

@@ -74,7 +74,7 @@ aqt_status pack_for_precision(aqt_ctx* ctx, int precision);
 aqt_status launch_run(aqt_ctx* ctx, const aqt_run_params* p, const aqt_outputs* o);
 
 // precompute.hip: GPU eigensystem and tables.
-aqt_status precompute_tables(aqt_ctx* ctx, int n_grid, int n_levels, double deg_tol);
+aqt_status precompute_tables(aqt_ctx* ctx, int n_grid, int n_levels, double deg_tol, int method);
 
 inline int padded_levels(int n) {
   int np = 16;

@@ -229,12 +229,18 @@ __device__ void wg_back_transform(const double* A, int N, int lda, double* Z, in
   }
 }
 
-// Stable ascending rank of the eigenvalues: perm[rank] = index.
+// Stable ascending rank of the eigenvalues: perm[rank] = index.  A NaN ranks as
+// +infinity (ties by index), so perm is a permutation for any input and every
+// index read through it stays in range.
+__device__ __forceinline__ double rank_key(double v) { return (v == v) ? v : __builtin_huge_val(); }
 __device__ void wg_rank_ascending(const double* d, int N, int* perm) {
   for (int i = threadIdx.x; i < N; i += kEigThreads) {
-    const double di = d[i];
+    const double di = rank_key(d[i]);
     int rank = 0;
-    for (int j = 0; j < N; ++j) rank += (d[j] < di) || (d[j] == di && j < i);
+    for (int j = 0; j < N; ++j) {
+      const double dj = rank_key(d[j]);
+      rank += (dj < di) || (dj == di && j < i);
+    }
     perm[rank] = i;
   }
   __syncthreads();

@@ -12,6 +12,8 @@
 //                  V_g diag(sz_i) V_g^T (matrix elements <a|sz_i|b>)
 //   k_polar        polar factor of the truncated overlap via the eigen-
 //                  decomposition of M^T M; leakage 1 - sigma_min^2
+//   (2^n_qubits > 1024: Chebyshev-filtered subspace iteration with a
+//   matrix-free H replaces k_build_dense and k_dense_eig; see below)
 //   k_rates        R[i][b][a] = gamma(e_b - e_a) z_ab^2 (a != b),
 //                  gamma(0) z_bb^2 (a == b), Ohmic gamma (Sec. V), and zdiag
 // The ground state of H(s_0) (must be non-degenerate) is expressed in the
@@ -180,6 +182,7 @@ __global__ __launch_bounds__(kEigThreads) void k_canon(const double* __restrict_
       }
 #pragma unroll
     for (int o = 32; o >= 1; o >>= 1) first = min(first, __shfl_xor(first, o, kWave));
+    if (first >= N) first = 0;   // no entry qualified (non-finite vector): stay in range
     const bool flip = va[first] < 0.0;
     if (flip)
       for (int x = lane; x < N; x += kWave) va[x] = -va[x];
@@ -319,6 +322,7 @@ __device__ void wg_canonical_range(const double* P, int n, int k, double* K, dou
       }
 #pragma unroll
     for (int o = 32; o >= 1; o >>= 1) first = min(first, __shfl_xor(first, o, kWave));
+    if (first >= n) first = 0;   // no entry qualified (non-finite vector): stay in range
     const double sgn = (v[first] < 0.0) ? -1.0 : 1.0;
     for (int x = lane; x < n; x += kWave) out[static_cast<size_t>(q) * n + x] = sgn * v[x];
   }
@@ -505,15 +509,306 @@ aqt_status launch_gemm(aqt_ctx* ctx, const GemmArgs& g, int batch) {
   return AQT_OK;
 }
 
+// ------------------------------------------------------------------------
+// Lowest eigenpairs of large H(s) (2^n_qubits > 1024): Chebyshev-filtered
+// subspace iteration on a block of KB vectors with Rayleigh-Ritz steps
+// (Zhou and Saad's filtered subspace iteration), warm-started from the
+// previous grid point's Ritz vectors.  H is applied matrix-free: (H v)[x] =
+// -A sum_i v[x ^ 2^i] + B e_Z[x] v[x].  Vectors are rows of length N.
+
+constexpr int kHxChunk = 4096;   // x per workgroup of the block product (LDS-resident)
+
+// Y_j = alpha (H X_j) + beta X_j + gamma Z_j for the KB rows j (Z may be null).
+__global__ __launch_bounds__(256) void k_hx_block(const double* __restrict__ X, const double* __restrict__ Zin,
+                                                  double* __restrict__ Y, const double* __restrict__ eZ, int nq,
+                                                  double A, double B, double alpha, double beta, double gamma) {
+  __shared__ double sx[kHxChunk];
+  const int N = 1 << nq;
+  const int CH = N < kHxChunk ? N : kHxChunk;
+  const int lch = 31 - __clz(CH);
+  const int j = blockIdx.y;
+  const int x0 = blockIdx.x * CH;
+  const double* v = X + static_cast<size_t>(j) * N;
+  for (int t = threadIdx.x; t < CH; t += blockDim.x) sx[t] = v[x0 + t];
+  __syncthreads();
+  const int nlow = nq < lch ? nq : lch;
+  for (int t = threadIdx.x; t < CH; t += blockDim.x) {
+    const int x = x0 + t;
+    double flip = 0.0;
+    for (int i = 0; i < nlow; ++i) flip += sx[t ^ (1 << i)];
+    for (int i = lch; i < nq; ++i) flip += v[x ^ (1 << i)];
+    const double own = sx[t];
+    double out = alpha * (B * eZ[x] * own - A * flip) + beta * own;
+    if (Zin) out += gamma * Zin[static_cast<size_t>(j) * N + x];
+    Y[static_cast<size_t>(j) * N + x] = out;
+  }
+}
+
+// Y_j = sum_i C[i][j] X_i (C row-major KB x KB): the block times a small matrix.
+template <int KB>
+__global__ __launch_bounds__(256) void k_combine(const double* __restrict__ X, const double* __restrict__ C,
+                                                 double* __restrict__ Y, int N) {
+  __shared__ double sC[KB * KB];
+  for (int f = threadIdx.x; f < KB * KB; f += blockDim.x) sC[f] = C[f];
+  __syncthreads();
+  const int x = blockIdx.x * blockDim.x + threadIdx.x;
+  if (x >= N) return;
+  double acc[KB];
+#pragma unroll
+  for (int jj = 0; jj < KB; ++jj) acc[jj] = 0.0;
+  for (int i = 0; i < KB; ++i) {
+    const double xi = X[static_cast<size_t>(i) * N + x];
+#pragma unroll
+    for (int jj = 0; jj < KB; ++jj) acc[jj] += sC[i * KB + jj] * xi;
+  }
+#pragma unroll
+  for (int jj = 0; jj < KB; ++jj) Y[static_cast<size_t>(jj) * N + x] = acc[jj];
+}
+
+// Deterministic start block: entries in [-1, 1) from a counter hash.
+__global__ void k_random_block(double* X, int64_t count) {
+  const int64_t idx = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (idx >= count) return;
+  uint64_t z = static_cast<uint64_t>(idx) * 0x9E3779B97F4A7C15ull + 0x632BE59BD9B4E019ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  z ^= z >> 31;
+  X[idx] = static_cast<double>(z >> 11) * 0x1.0p-52 - 1.0;
+}
+
+// One workgroup, KB x KB symmetric S (row-major, symmetrised here):
+//   mode 0 (Rayleigh-Ritz): C = eigenvectors of S as columns, ascending; theta.
+//   mode 1 (orthonormalisation of a Gram matrix): with D = diag(S)^(1/2) and
+//     D^-1 S D^-1 = U L U^T, C = D^-1 U L^-1/2 so that X C has orthonormal rows.
+// ws: 2 KB^2 doubles.  status bit 1: eigensolver failed, bit 2: non-finite input.
+__global__ __launch_bounds__(kEigThreads) void k_small_eig(const double* __restrict__ S, int KB, int mode,
+                                                           double* __restrict__ C, double* __restrict__ theta,
+                                                           double* __restrict__ ws, int* __restrict__ status) {
+  __shared__ EigShared sh;
+  __shared__ int s_perm[kEigMaxN];
+  __shared__ double s_dinv[kEigMaxN];
+  double* A = ws;
+  double* Z = ws + static_cast<size_t>(KB) * KB;
+  for (int a = threadIdx.x; a < KB; a += blockDim.x)
+    s_dinv[a] = (mode == 1) ? 1.0 / sqrt(fmax(S[a * KB + a], 1e-300)) : 1.0;
+  __syncthreads();
+  for (int f = threadIdx.x; f < KB * KB; f += blockDim.x) {
+    const int i = f / KB, j = f - i * KB;
+    A[f] = 0.5 * (S[f] + S[j * KB + i]) * s_dinv[i] * s_dinv[j];
+  }
+  __syncthreads();
+  wg_tridiagonalize(A, KB, KB, sh);
+  const bool ok = wg_band_qr(Z, KB, KB, sh);
+  wg_rank_ascending(sh.d, KB, s_perm);
+  wg_back_transform(A, KB, KB, Z, KB, s_perm, KB, sh);
+  double lmax = 0.0, lmin = 1e300;
+  bool finite = true;
+  for (int a = 0; a < KB; ++a) {
+    finite = finite && (sh.d[a] - sh.d[a] == 0.0);
+    lmax = fmax(lmax, sh.d[a]);
+    lmin = fmin(lmin, sh.d[a]);
+  }
+  // a failed step reports and writes the identity, so the block stays finite until
+  // the host sees the status; Gram eigenvalues are floored at 1e-15 of the largest
+  // (directions lost to rounding come back rescaled, the next pass normalises them)
+  const bool bad = !ok || !finite || (mode == 1 && !(lmax > 0.0));
+  const double floor_l = 1e-15 * lmax;
+  for (int f = threadIdx.x; f < KB * KB; f += blockDim.x) {
+    const int i = f / KB, j = f - i * KB;   // C[i][j] = component i of vector j
+    const double zij = Z[static_cast<size_t>(s_perm[j]) * KB + i];
+    if (bad) C[f] = (i == j) ? 1.0 : 0.0;
+    else C[f] = (mode == 1) ? s_dinv[i] * zij / sqrt(fmax(sh.d[s_perm[j]], floor_l)) : zij;
+  }
+  if (mode == 0)
+    for (int a = threadIdx.x; a < KB; a += blockDim.x) theta[a] = sh.d[s_perm[a]];
+  if (threadIdx.x == 0 && bad) atomicOr(status, ok ? 2 : 1);
+}
+
+// res_j = |W_j - theta_j X_j| (one workgroup per row).
+__global__ __launch_bounds__(256) void k_resid(const double* __restrict__ X, const double* __restrict__ W,
+                                               const double* __restrict__ theta, int N, double* __restrict__ res) {
+  __shared__ double red[4];
+  const int j = blockIdx.x;
+  const double th = theta[j];
+  const double* xj = X + static_cast<size_t>(j) * N;
+  const double* wj = W + static_cast<size_t>(j) * N;
+  double acc = 0.0;
+  for (int x = threadIdx.x; x < N; x += blockDim.x) {
+    const double r = wj[x] - th * xj[x];
+    acc += r * r;
+  }
+  acc = wave_sum(acc);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) res[j] = sqrt(red[0] + red[1] + red[2] + red[3]);
+}
+
+struct Chfsi {
+  int nq = 0, N = 0, KB = 0, ksplit = 1;
+  DevBuf X, Y1, Y2, W, part, S, C, theta, res, ws, status;
+  std::vector<double> h_theta, h_res;
+  bool warm = false;
+  double hub = 0.0;   // upper bound of the spectrum (Gershgorin)
+};
+
+aqt_status chfsi_gram(aqt_ctx* ctx, Chfsi& c, const double* P, const double* Q) {
+  // S = P Q^T over x (KB x KB), split over x
+  const int kspan = (c.N + c.ksplit - 1) / c.ksplit;
+  GemmArgs ga{P, Q, c.part.as<double>(), 0, 0, static_cast<int64_t>(c.KB) * c.KB, c.KB, c.KB, c.N, c.N, c.N, c.KB,
+              0, c.nq, 0, c.ksplit, kspan};
+  aqt_status st = launch_gemm(ctx, ga, c.ksplit);
+  if (st != AQT_OK) return st;
+  hipLaunchKernelGGL(k_splitk_reduce, dim3(nblk(static_cast<int64_t>(c.KB) * c.KB)), dim3(256), 0, ctx->stream,
+                     c.part.as<double>(), c.ksplit, c.KB, c.KB, 1, c.S.as<double>(), 0, c.KB, 0);
+  AQT_HIP(ctx, hipGetLastError());
+  return AQT_OK;
+}
+
+aqt_status chfsi_combine(aqt_ctx* ctx, Chfsi& c, const double* in, double* out) {
+  if (c.KB == 64)
+    hipLaunchKernelGGL(k_combine<64>, dim3(nblk(c.N)), dim3(256), 0, ctx->stream, in, c.C.as<double>(), out, c.N);
+  else
+    hipLaunchKernelGGL(k_combine<128>, dim3(nblk(c.N)), dim3(256), 0, ctx->stream, in, c.C.as<double>(), out, c.N);
+  AQT_HIP(ctx, hipGetLastError());
+  return AQT_OK;
+}
+
+aqt_status chfsi_hx(aqt_ctx* ctx, Chfsi& c, const double* eZ, double A, double B, const double* in, const double* z,
+                    double* out, double alpha, double beta, double gamma) {
+  const int CH = std::min(c.N, kHxChunk);
+  hipLaunchKernelGGL(k_hx_block, dim3(c.N / CH, c.KB), dim3(256), 0, ctx->stream, in, z, out, eZ, c.nq, A, B, alpha,
+                     beta, gamma);
+  AQT_HIP(ctx, hipGetLastError());
+  return AQT_OK;
+}
+
+// Orthonormalise the rows of `in` into c.X (column scaling, then the inverse
+// square root of the Gram matrix, twice).
+aqt_status chfsi_orth(aqt_ctx* ctx, Chfsi& c, double* in) {
+  double* src = in;
+  for (int pass = 0; pass < 2; ++pass) {
+    aqt_status st = chfsi_gram(ctx, c, src, src);
+    if (st != AQT_OK) return st;
+    hipLaunchKernelGGL(k_small_eig, dim3(1), dim3(kEigThreads), 0, ctx->stream, c.S.as<double>(), c.KB, 1,
+                       c.C.as<double>(), c.theta.as<double>(), c.ws.as<double>(), c.status.as<int>());
+    AQT_HIP(ctx, hipGetLastError());
+    double* dst = (pass == 0) ? c.Y2.as<double>() : c.X.as<double>();
+    if (dst == src) dst = c.W.as<double>();
+    st = chfsi_combine(ctx, c, src, dst);
+    if (st != AQT_OK) return st;
+    src = dst;
+  }
+  if (src != c.X.as<double>())
+    AQT_HIP(ctx, hipMemcpyAsync(c.X.p, src, static_cast<size_t>(c.KB) * c.N * 8, hipMemcpyDeviceToDevice, ctx->stream));
+  return AQT_OK;
+}
+
+// Converge the lowest `nconv` Ritz pairs of H(s) = A H_X + B diag(e_Z) to
+// residual <= tol * hub.  On return c.X holds the KB Ritz vectors (ascending
+// Ritz values in c.theta).
+aqt_status chfsi_solve(aqt_ctx* ctx, Chfsi& c, const double* eZ, double A, double B, int nconv, double tol,
+                       const std::string& where) {
+  hipStream_t st = ctx->stream;
+  AQT_HIP(ctx, hipMemsetAsync(c.status.p, 0, 4, st));
+  if (!c.warm) {
+    hipLaunchKernelGGL(k_random_block, dim3(nblk(static_cast<int64_t>(c.KB) * c.N)), dim3(256), 0, st,
+                       c.X.as<double>(), static_cast<int64_t>(c.KB) * c.N);
+    AQT_HIP(ctx, hipGetLastError());
+    aqt_status s = chfsi_orth(ctx, c, c.X.as<double>());
+    if (s != AQT_OK) return s;
+  }
+  const int maxit = c.warm ? 80 : 150;
+  int hstat = 0;
+  for (int it = 0;; ++it) {
+    // Rayleigh-Ritz
+    aqt_status s = chfsi_hx(ctx, c, eZ, A, B, c.X.as<double>(), nullptr, c.W.as<double>(), 1.0, 0.0, 0.0);
+    if (s != AQT_OK) return s;
+    s = chfsi_gram(ctx, c, c.X.as<double>(), c.W.as<double>());
+    if (s != AQT_OK) return s;
+    hipLaunchKernelGGL(k_small_eig, dim3(1), dim3(kEigThreads), 0, st, c.S.as<double>(), c.KB, 0, c.C.as<double>(),
+                       c.theta.as<double>(), c.ws.as<double>(), c.status.as<int>());
+    AQT_HIP(ctx, hipGetLastError());
+    if ((s = chfsi_combine(ctx, c, c.X.as<double>(), c.Y1.as<double>())) != AQT_OK) return s;
+    if ((s = chfsi_combine(ctx, c, c.W.as<double>(), c.Y2.as<double>())) != AQT_OK) return s;
+    std::swap(c.X.p, c.Y1.p);
+    std::swap(c.W.p, c.Y2.p);
+    hipLaunchKernelGGL(k_resid, dim3(c.KB), dim3(256), 0, st, c.X.as<double>(), c.W.as<double>(),
+                       c.theta.as<double>(), c.N, c.res.as<double>());
+    AQT_HIP(ctx, hipGetLastError());
+    AQT_HIP(ctx, hipMemcpyAsync(c.h_theta.data(), c.theta.p, c.KB * 8, hipMemcpyDeviceToHost, st));
+    AQT_HIP(ctx, hipMemcpyAsync(c.h_res.data(), c.res.p, c.KB * 8, hipMemcpyDeviceToHost, st));
+    AQT_HIP(ctx, hipMemcpyAsync(&hstat, c.status.p, 4, hipMemcpyDeviceToHost, st));
+    AQT_HIP(ctx, hipStreamSynchronize(st));
+    if (hstat) return ctx->fail(AQT_ENUMERIC, "subspace iteration: small eigensolver failed " + where);
+    double worst = 0.0;
+    for (int j = 0; j < nconv; ++j) worst = std::max(worst, c.h_res[j]);
+    if (!(worst == worst)) return ctx->fail(AQT_ENUMERIC, "subspace iteration produced NaN " + where);
+    if (worst <= tol * c.hub) break;
+    if (it >= maxit)
+      return ctx->fail(AQT_ENUMERIC, "subspace iteration did not converge " + where + " (residual " +
+                                         std::to_string(worst / c.hub) + " of |H|)");
+    // Chebyshev filter damping [theta_last, hub], scaled at theta_0; the degree
+    // makes the slowest wanted level gain about 10^3 over the damped interval
+    const double lo = c.h_theta[0], cut = c.h_theta[c.KB - 1];
+    const double e = 0.5 * (c.hub - cut), cen = 0.5 * (c.hub + cut);
+    const double xw = std::fabs((c.h_theta[nconv - 1] - cen) / e);
+    const double xl = std::fabs((lo - cen) / e);
+    int degree = 256;
+    if (xw > 1.0 + 1e-12) degree = static_cast<int>(std::ceil(std::acosh(1e3) / std::acosh(xw)));
+    // amplification of the lowest level over the damped interval, T_d(x_lo) ~ e^{d acosh x_lo},
+    // kept below 1e10: beyond that the filtered block loses the directions it amplifies
+    // least to rounding (its Gram matrix becomes numerically singular)
+    if (xl > 1.0) degree = std::min(degree, static_cast<int>(std::log(1e10) / std::acosh(xl)));
+    degree = std::max(2, std::min(256, degree));
+    double sigma = e / (lo - cen);
+    const double tau = 2.0 / sigma;
+    double* x0 = c.X.as<double>();
+    double* y1 = c.Y1.as<double>();
+    double* y2 = c.Y2.as<double>();
+    if ((s = chfsi_hx(ctx, c, eZ, A, B, x0, nullptr, y1, sigma / e, -cen * sigma / e, 0.0)) != AQT_OK) return s;
+    for (int k = 2; k <= degree; ++k) {
+      const double sn = 1.0 / (tau - sigma);
+      if ((s = chfsi_hx(ctx, c, eZ, A, B, y1, x0, y2, 2.0 * sn / e, -2.0 * cen * sn / e, -sigma * sn)) != AQT_OK)
+        return s;
+      double* t = x0;
+      x0 = y1;
+      y1 = y2;
+      y2 = t;
+      sigma = sn;
+    }
+    // result in y1; orthonormalise into X (X may be one of the rotated buffers)
+    {
+      // make sure chfsi_orth's scratch (Y2, W) does not alias the filtered block
+      double* filt = y1;
+      if (filt != c.Y1.as<double>()) {
+        AQT_HIP(ctx, hipMemcpyAsync(c.Y1.p, filt, static_cast<size_t>(c.KB) * c.N * 8, hipMemcpyDeviceToDevice, st));
+        filt = c.Y1.as<double>();
+      }
+      if ((s = chfsi_orth(ctx, c, filt)) != AQT_OK) return s;
+    }
+  }
+  c.warm = true;
+  return AQT_OK;
+}
+
 }  // namespace
 
-aqt_status precompute_tables(aqt_ctx* ctx, int M, int n, double tol) {
+aqt_status precompute_tables(aqt_ctx* ctx, int M, int n, double tol, int method) {
   const int nq = ctx->nq;
   const int N = 1 << nq;
-  if (N > kEigMaxN) return ctx->fail(AQT_EINVAL, "dense eigensolver path needs 2^n_qubits <= 1024");
-  if (n < N && n > 128) return ctx->fail(AQT_EINVAL, "truncated spectra are limited to n <= 128 levels");
+  const bool iterative = (method == AQT_EIG_ITERATIVE) || (method == AQT_EIG_AUTO && N > kEigMaxN);
+  const int ncols = std::min(N, n + 16);   // levels solved for: n plus a guard for clusters at the cut
+  int KB = 0;                              // block size of the subspace iteration
+  if (iterative) {
+    if (n >= N) return ctx->fail(AQT_EINVAL, "the iterative eigensolver computes truncated spectra (n_levels < 2^n_qubits)");
+    // dense spectra of large spaces need the filter's cut well above the wanted levels
+    KB = (ncols + 8 <= 64 && N < 4096) ? 64 : 128;
+    if (ncols + 8 > KB || KB > N) return ctx->fail(AQT_EINVAL, "iterative eigensolver: n_levels too large for 2^n_qubits");
+  } else {
+    if (N > kEigMaxN) return ctx->fail(AQT_EINVAL, "dense eigensolver path needs 2^n_qubits <= 1024");
+    if (n < N && n > 128) return ctx->fail(AQT_EINVAL, "truncated spectra are limited to n <= 128 levels");
+  }
   const int NP = padded_levels(n);
-  const int ncols = std::min(N, n + 16);
   hipStream_t st = ctx->stream;
 
   // ---- schedule samples and Ising diagonal
@@ -554,7 +849,7 @@ aqt_status precompute_tables(aqt_ctx* ctx, int M, int n, double tol) {
   AQT_HIP(ctx, hipMemsetAsync(ctx->leak.p, 0, M * 8, st));
 
   // ---- chunked workspace
-  const size_t per_grid = 2 * static_cast<size_t>(N) * N            // H, Z
+  const size_t per_grid = (iterative ? 0 : 2 * static_cast<size_t>(N) * N)   // H, Z (dense path)
                           + static_cast<size_t>(ncols) * N            // canonical V
                           + 2 * static_cast<size_t>(ncols) * ncols + static_cast<size_t>(ncols) * N  // canon ws
                           + static_cast<size_t>(nq) * n * n           // z
@@ -563,7 +858,7 @@ aqt_status precompute_tables(aqt_ctx* ctx, int M, int n, double tol) {
   const size_t budget = size_t(2) << 30;
   int Gc = static_cast<int>(std::max<size_t>(1, std::min<size_t>(M, budget / (per_grid * 8))));
   DevBuf H, Z, Vc, Vprev, cws, zws, pws, Eraw, perm, status;
-  if (H.reserve(static_cast<size_t>(Gc) * N * N * 8) || Z.reserve(static_cast<size_t>(Gc) * N * N * 8) ||
+  if ((!iterative && (H.reserve(static_cast<size_t>(Gc) * N * N * 8) || Z.reserve(static_cast<size_t>(Gc) * N * N * 8))) ||
       Vc.reserve(static_cast<size_t>(Gc) * ncols * N * 8) || Vprev.reserve(static_cast<size_t>(ncols) * N * 8) ||
       cws.reserve(static_cast<size_t>(Gc) * (2 * static_cast<size_t>(ncols) * ncols + static_cast<size_t>(ncols) * N) * 8) ||
       zws.reserve(static_cast<size_t>(Gc) * nq * n * n * 8) || pws.reserve(static_cast<size_t>(Gc) * 9 * n * n * 8) ||
@@ -572,19 +867,67 @@ aqt_status precompute_tables(aqt_ctx* ctx, int M, int n, double tol) {
     return ctx->fail(AQT_ENOMEM, "precompute workspace allocation failed");
   std::vector<int> hstat(Gc);
   const size_t Vstride = static_cast<size_t>(ncols) * N;
+  Chfsi ch;
+  DevBuf ident;
+  if (iterative) {
+    ch.nq = nq;
+    ch.N = N;
+    ch.KB = KB;
+    ch.ksplit = std::max(1, std::min(256, N / 256));
+    const size_t blk = static_cast<size_t>(KB) * N * 8;
+    if (ch.X.reserve(blk) || ch.Y1.reserve(blk) || ch.Y2.reserve(blk) || ch.W.reserve(blk) ||
+        ch.part.reserve(static_cast<size_t>(ch.ksplit) * KB * KB * 8) || ch.S.reserve(KB * KB * 8) ||
+        ch.C.reserve(KB * KB * 8) || ch.theta.reserve(KB * 8) || ch.res.reserve(KB * 8) ||
+        ch.ws.reserve(2 * KB * KB * 8) || ch.status.reserve(4) || ident.reserve(KB * 4))
+      return ctx->fail(AQT_ENOMEM, "subspace iteration workspace allocation failed");
+    ch.h_theta.resize(KB);
+    ch.h_res.resize(KB);
+    std::vector<int> id(KB);
+    for (int a = 0; a < KB; ++a) id[a] = a;
+    AQT_HIP(ctx, hipMemcpyAsync(ident.p, id.data(), KB * 4, hipMemcpyHostToDevice, st));
+    std::vector<double> hz(N);
+    AQT_HIP(ctx, hipMemcpyAsync(hz.data(), eZ.p, N * 8, hipMemcpyDeviceToHost, st));
+    AQT_HIP(ctx, hipStreamSynchronize(st));
+    double zmax = 0.0;
+    for (double v : hz) zmax = std::max(zmax, std::fabs(v));
+    double amax = 0.0, bmax = 0.0;
+    for (int g = 0; g < M; ++g) {
+      amax = std::max(amax, std::fabs(Ag[g]));
+      bmax = std::max(bmax, std::fabs(Bg[g]));
+    }
+    ch.hub = amax * nq + bmax * zmax;   // Gershgorin bound on every H(s_g)
+  }
 
   for (int g0 = 0; g0 < M; g0 += Gc) {
     const int cnt = std::min(Gc, M - g0);
-    hipLaunchKernelGGL(k_build_dense, dim3(nblk(static_cast<int64_t>(N) * N * cnt)), dim3(256), 0, st,
-                       eZ.as<double>(), nq, dA.as<double>(), dB.as<double>(), g0, cnt, H.as<double>());
-    AQT_HIP(ctx, hipGetLastError());
-    hipLaunchKernelGGL(k_dense_eig, dim3(cnt), dim3(kEigThreads), 0, st, H.as<double>(), Z.as<double>(), N, ncols,
-                       Eraw.as<double>(), perm.as<int>(), status.as<int>());
-    AQT_HIP(ctx, hipGetLastError());
-    hipLaunchKernelGGL(k_canon, dim3(cnt), dim3(kEigThreads), 0, st, Z.as<double>(), perm.as<int>(),
-                       Eraw.as<double>(), N, ncols, n, NP, tol, g0, Vc.as<double>(), ctx->E.as<double>(),
-                       ctx->gs.as<int>(), cws.as<double>(), status.as<int>());
-    AQT_HIP(ctx, hipGetLastError());
+    if (!iterative) {
+      hipLaunchKernelGGL(k_build_dense, dim3(nblk(static_cast<int64_t>(N) * N * cnt)), dim3(256), 0, st,
+                         eZ.as<double>(), nq, dA.as<double>(), dB.as<double>(), g0, cnt, H.as<double>());
+      AQT_HIP(ctx, hipGetLastError());
+      hipLaunchKernelGGL(k_dense_eig, dim3(cnt), dim3(kEigThreads), 0, st, H.as<double>(), Z.as<double>(), N, ncols,
+                         Eraw.as<double>(), perm.as<int>(), status.as<int>());
+      AQT_HIP(ctx, hipGetLastError());
+      hipLaunchKernelGGL(k_canon, dim3(cnt), dim3(kEigThreads), 0, st, Z.as<double>(), perm.as<int>(),
+                         Eraw.as<double>(), N, ncols, n, NP, tol, g0, Vc.as<double>(), ctx->E.as<double>(),
+                         ctx->gs.as<int>(), cws.as<double>(), status.as<int>());
+      AQT_HIP(ctx, hipGetLastError());
+    } else {
+      AQT_HIP(ctx, hipMemsetAsync(status.p, 0, cnt * 4, st));
+      for (int c = 0; c < cnt; ++c) {
+        const int g = g0 + c;
+        // grid 0 only supplies the initial state (its ground state, checked to be
+        // non-degenerate); H(0) is typically highly degenerate, so only the two
+        // lowest levels are converged there
+        const int nconv = (g == 0) ? std::min(2, ncols) : ncols;
+        aqt_status s = chfsi_solve(ctx, ch, eZ.as<double>(), Ag[g], Bg[g], nconv, 1e-12,
+                                   "at grid point " + std::to_string(g));
+        if (s != AQT_OK) return s;
+        hipLaunchKernelGGL(k_canon, dim3(1), dim3(kEigThreads), 0, st, ch.X.as<double>(), ident.as<int>(),
+                           ch.theta.as<double>(), N, ncols, n, NP, tol, g, Vc.as<double>() + c * Vstride,
+                           ctx->E.as<double>(), ctx->gs.as<int>(), cws.as<double>(), status.as<int>() + c);
+        AQT_HIP(ctx, hipGetLastError());
+      }
+    }
     AQT_HIP(ctx, hipMemcpyAsync(hstat.data(), status.p, cnt * 4, hipMemcpyDeviceToHost, st));
     AQT_HIP(ctx, hipStreamSynchronize(st));
     for (int c = 0; c < cnt; ++c)

@@ -10,20 +10,21 @@ from gpu_common import compare_jump_records, sigma_bound
 pytestmark = pytest.mark.gpu
 
 
-def gpu_tables(inst, n_grid=None, n_levels=None, deg_tol=1e-8):
+def gpu_tables(inst, n_grid=None, n_levels=None, deg_tol=1e-8, method="auto"):
     from paper_1710_03431_amd.binding import Engine
     eng = Engine(0)
     eng.set_instance(inst)
-    eng.precompute(n_grid or inst.n_grid, n_levels or inst.levels, deg_tol)
+    eng.precompute(n_grid or inst.n_grid, n_levels or inst.levels, deg_tol, method=method)
     return eng
 
 
-def level_condition(E, E_all=None, deg_tol=1e-8):
-    """First-order eigenvector error bound per retained level: eps |H| / (distance to the
-    nearest level of the whole spectrum E_all outside its cluster).  Both eigensolvers are
-    backward stable, so eigenvector entries of two correct solvers may differ by about this."""
+def level_condition(E, E_all=None, deg_tol=1e-8, extra=0.0):
+    """First-order eigenvector error bound per retained level: (eps |H| + extra) / (distance
+    to the nearest level of the whole spectrum E_all outside its cluster).  Both eigensolvers
+    are backward stable, so eigenvector entries of two correct solvers may differ by about
+    this; `extra` adds a residual tolerance (iterative solvers)."""
     E_all = E if E_all is None else E_all
-    eps_h = 2.2e-16 * max(np.abs(E_all).max(), 1.0)
+    eps_h = 2.2e-16 * max(np.abs(E_all).max(), 1.0) + extra
     gap = np.full(len(E), np.inf)
     for a in range(len(E)):
         d = np.abs(E_all - E[a])
@@ -67,16 +68,30 @@ def align_signs(A, B, floor=1e-9):
 
 def sampled_tables(inst, grids, n_levels=None):
     """Oracle tables at the sampled grid points and at their predecessors (the overlap at
-    g involves the bases at g and g - 1), with V kept and the whole spectrum at each."""
+    g involves the bases at g and g - 1), with V kept and the spectrum at each (whole for
+    dense sizes, the retained levels plus the oracle's guard levels otherwise)."""
     from oracle import model
     want = set(grids) | {g - 1 for g in grids if g > 1}
     tabs = {T.g: T for T in spectrum.table_stream(inst, n_levels=n_levels, grids=want, keep_V=True)}
     M = inst.n_grid
-    full = {g: np.linalg.eigvalsh(model.hamiltonian_dense(inst, g / (M - 1))) for g in want}
+    n = n_levels or inst.levels
+    if inst.dim <= 4096:
+        full = {g: np.linalg.eigvalsh(model.hamiltonian_dense(inst, g / (M - 1))) for g in want}
+    else:
+        full = {g: spectrum.eigen(inst, g / (M - 1), n + 16, 1e-8)[0] for g in want}
     return [tabs[g] for g in sorted(grids)], tabs, full
 
 
-def check_tables(got, tabs, scale, prev=None, full=None, safety=200.0):
+def hamiltonian_bound(inst):
+    """The Gershgorin bound on |H(s)| the iterative eigensolver scales its tolerance by."""
+    from oracle import model
+    eZ = model.hz_diag(np.asarray(inst.h, dtype=float), np.asarray(inst.J, dtype=float))
+    A = np.abs(inst.A_ctrl).max()
+    B = np.abs(inst.B_ctrl).max()
+    return A * inst.n_qubits + B * np.abs(eZ).max()
+
+
+def check_tables(got, tabs, scale, prev=None, full=None, safety=200.0, res_abs=0.0):
     """E to 1e-12 of the spectral scale; overlaps, matrix-element rates, decay and zdiag
     to 1e-10 plus the first-order eigenvector-conditioning bound of the levels involved
     (rows: levels at g, columns: levels at g - 1 for the overlap)."""
@@ -84,11 +99,11 @@ def check_tables(got, tabs, scale, prev=None, full=None, safety=200.0):
         g = T.g
         np.testing.assert_allclose(got["E"][g], T.E, atol=1e-12 * scale, rtol=0, err_msg=f"E g={g}")
         assert got["gs"][g] == T.gs, g
-        kap = safety * level_condition(T.E, None if full is None else full[g])
+        kap = safety * level_condition(T.E, None if full is None else full[g], extra=2.0 * res_abs / safety)
         pair = kap[:, None] + kap[None, :]
         if T.O is not None:
             Tp = prev[g - 1]
-            kp = safety * level_condition(Tp.E, None if full is None else full[g - 1])
+            kp = safety * level_condition(Tp.E, None if full is None else full[g - 1], extra=2.0 * res_abs / safety)
             opair = kap[:, None] + kp[None, :]
             S = np.linalg.svd(T.V.T @ Tp.V, compute_uv=False)
             kept = S[S > 1e-4]
@@ -165,3 +180,51 @@ def test_degenerate_initial_state_is_rejected():
     with pytest.raises(AqtError) as e:
         gpu_tables(inst, n_grid=5)
     assert e.value.status == AQT_ENUMERIC
+
+
+def test_iterative_solver_tables_truncated():
+    """Chebyshev-filtered subspace iteration (forced on an 8-qubit instance truncated to 16
+    levels) against the oracle's dense eigensolver: energies, overlaps, rates."""
+    inst = W.pm1_all_to_all(8, 17, t_f=3000.0, n_grid=200, n_levels=16)
+    tabs, prev, full = sampled_tables(inst, {1, 2, 3, 100, 198, 199})
+    eng = gpu_tables(inst, method="iterative")
+    got = eng.get_tables()
+    check_tables(got, tabs, scale=100.0, prev=prev, full=full, res_abs=1e-12 * hamiltonian_bound(inst))
+    np.testing.assert_allclose(got["cinit"], tabs[0].cinit, atol=1e-9)
+
+
+def test_iterative_equals_dense_statistics():
+    """The same 7-qubit truncated instance through both GPU eigensolvers: FP64 trajectories
+    agree trajectory by trajectory (the tables agree to the solvers' accuracy)."""
+    inst = W.pm1_all_to_all(7, 23, t_f=2000.0, n_grid=150, n_levels=32)
+    a = gpu_tables(inst, method="dense")
+    b = gpu_tables(inst, method="iterative")
+    ra = a.run(500, "fp64", seed=4, record_capacity=32)
+    rb = b.run(500, "fp64", seed=4, record_capacity=32)
+    same = np.mean(ra["jump_count"] == rb["jump_count"])
+    assert same >= 0.99, same
+    np.testing.assert_allclose(ra["pgs_sum"], rb["pgs_sum"], rtol=0, atol=0.01 * 500)
+
+
+def test_gadget_tables_sampled():
+    """16-qubit gadget (N = 65536) truncated to 32 levels by the iterative solver at all 500
+    grid points; sampled grid points against the oracle's sparse eigensolver.  Energies
+    everywhere (with the multiplicities of the qubit-permutation symmetry); the basis-
+    dependent tables where no degenerate cluster is cut by the truncation (there the
+    retained subspace, and so any basis of it, is unique)."""
+    inst = W.config_gadget(1000)
+    n = inst.levels
+    tabs, prev, full = sampled_tables(inst, {1, 2, 250, 499})
+    eng = gpu_tables(inst)
+    got = eng.get_tables()
+    for T in tabs:
+        np.testing.assert_allclose(got["E"][T.g], T.E, atol=1e-12 * 400.0, rtol=0, err_msg=f"E g={T.g}")
+
+    def clean(g):
+        e = np.sort(full[g])
+        return e[n] - e[n - 1] >= 1e-6
+
+    ok = [T for T in tabs if clean(T.g) and (T.g == 1 or clean(T.g - 1))]
+    assert len(ok) >= 2, [T.g for T in tabs]
+    check_tables(got, ok, scale=400.0, prev=prev, full=full, res_abs=1e-12 * hamiltonian_bound(inst))
+    assert np.all(got["leak"][2:] < 0.5)

@@ -412,3 +412,22 @@ def test_a2a8_seed_is_first_with_unique_final_ground_state():
     inst = W.config_a2a8(10)
     e = np.sort(model.hz_diag(inst.h, inst.J))
     assert e[1] - e[0] > 0.5
+
+
+def test_sparse_eigensolver_finds_every_sector_and_multiplicity():
+    """The Lanczos path used above 4096 states against dense eigh on a 10-qubit two-cluster
+    gadget (qubit-permutation symmetry, degenerate levels at every s): same lowest 40
+    energies with multiplicities, and the same retained subspace."""
+    inst = W.gadget_instance(5, n_levels=24, n_grid=50)
+    for s in (0.3, 1.0):
+        Ed, Vd, gd = spectrum.eigen(inst, s, 40, 1e-8, method="dense")
+        Es, Vs, gsz = spectrum.eigen(inst, s, 40, 1e-8, method="sparse")
+        np.testing.assert_allclose(Es, Ed, atol=1e-9 * np.abs(Ed).max())
+        assert gd == gsz
+        # compare subspaces spanned by complete clusters within the 24 lowest levels
+        cut = 24
+        while cut > 0 and abs(Ed[cut] - Ed[cut - 1]) < 1e-6:
+            cut -= 1
+        Pd = Vd[:, :cut] @ Vd[:, :cut].T
+        Ps = Vs[:, :cut] @ Vs[:, :cut].T
+        assert np.abs(Pd - Ps).max() < 1e-7

@@ -133,24 +133,30 @@ def config_a2a8(n_traj: int = 10_000) -> Instance:
     return pm1_all_to_all(8, A2A8_SEED, n_grid=2000, n_traj=n_traj, t_f=1.0e4)
 
 
-def config_gadget(n_traj: int = 100_000) -> Instance:
-    """16-qubit two-cluster tunnelling gadget truncated to the 32 lowest levels.
-
-    Cluster A = qubits 0..7 (field +0.44), cluster B = qubits 8..15 (field -1);
-    all-to-all J = -1 inside each cluster and J_{i,i+8} = -1 between them.
-    """
-    n = 16
-    h = np.array([0.44] * 8 + [-1.0] * 8)
+def gadget_instance(m: int, n_levels: int = 32, n_grid: int = 500, t_f: float = 1.0e4,
+                    n_traj: int = 100_000, seed: int = 1604) -> Instance:
+    """Two-cluster tunnelling gadget on 2m qubits: cluster A = qubits 0..m-1 (field
+    +0.44), cluster B = qubits m..2m-1 (field -1); all-to-all J = -1 inside each cluster
+    and J_{i,i+m} = -1 between them.  Permuting the qubits of A together with the same
+    permutation of B is a symmetry, so H(s) has degenerate levels at every s."""
+    n = 2 * m
+    h = np.array([0.44] * m + [-1.0] * m)
     J = np.zeros((n, n))
-    for c in (0, 8):
-        for i in range(c, c + 8):
-            for j in range(i + 1, c + 8):
+    for c in (0, m):
+        for i in range(c, c + m):
+            for j in range(i + 1, c + m):
                 J[i, j] = -1.0
-    for i in range(8):
-        J[i, i + 8] = -1.0
+    for i in range(m):
+        J[i, i + m] = -1.0
     A, B = linear_schedule()
-    return Instance(name="gadget16", n_qubits=n, h=h, J=J, t_f=1.0e4, A_ctrl=A, B_ctrl=B,
-                    n_grid=500, n_levels=32, n_traj=n_traj, seed=1604)
+    return Instance(name=f"gadget{n}", n_qubits=n, h=h, J=J, t_f=t_f, A_ctrl=A, B_ctrl=B,
+                    n_grid=n_grid, n_levels=n_levels, n_traj=n_traj, seed=seed)
+
+
+def config_gadget(n_traj: int = 100_000) -> Instance:
+    """16-qubit two-cluster tunnelling gadget truncated to the 32 lowest levels, 500 grid
+    points, t_f = 10 us."""
+    return gadget_instance(8, n_traj=n_traj)
 
 
 def config_batched(n_instances: int = 256, seed: int = 2024, n_traj: int = 2048,
