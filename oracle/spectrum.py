@@ -100,20 +100,21 @@ def canonicalize(E: np.ndarray, V: np.ndarray, deg_tol: float):
 def eigen(inst, s: float, n_keep: int, deg_tol: float, guard: int = 16, method: str = "auto"):
     """Lowest n_keep canonical eigenpairs of H(s) plus the ground-cluster size.
 
-    Dense eigh up to 4096 states, else ARPACK Lanczos (eigsh) for n_keep + guard pairs.
-    Lanczos starts from a seeded random vector: a structured start such as the uniform
-    superposition lies in one symmetry sector of H (for instance the qubit-permutation
-    symmetric sector of the two-cluster gadget) and would miss every level outside it;
-    a generic start reaches all sectors, and the restarts resolve degenerate levels."""
+    Dense eigh up to 4096 states, else ARPACK Lanczos (eigsh).  Lanczos starts from a
+    seeded random vector: a structured start such as the uniform superposition lies in
+    one symmetry sector of H (for instance the qubit-permutation symmetric sector of the
+    two-cluster gadget) and would miss every level outside it.  A single Krylov sequence
+    also resolves degenerate levels only through its restarts, which needs room: it is
+    asked for 2 (n_keep + guard) pairs, of which the lowest n_keep + guard are used."""
     N = inst.dim
     if method == "dense" or (method == "auto" and N <= 4096):
         E, V = np.linalg.eigh(model.hamiltonian_dense(inst, s))
     else:
-        k = min(N - 2, n_keep + guard)
+        k = min(N - 2, 2 * (n_keep + guard))
         H = model.hamiltonian_sparse(inst, s)
         v0 = np.random.default_rng(20171009).standard_normal(N)
         E, V = spla.eigsh(H, k=k, which="SA", tol=1e-13, v0=v0)
-        o = np.argsort(E)
+        o = np.argsort(E)[: n_keep + guard]
         E, V = E[o], V[:, o]
     E, V, cl = canonicalize(E, V, deg_tol)
     gs = cl[0][1] - cl[0][0]
