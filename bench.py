@@ -1,13 +1,23 @@
-"""Throughput of the GPU trajectory engine on the 8-qubit all-to-all workload.
+"""Throughput of the GPU trajectory engine.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--cpu-traj 3072] [--cpu-grid 500] [--no-cpu]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload a2a8|ring4|gadget16]
+                    [--cpu-traj 3072] [--cpu-grid 500] [--no-cpu]
 
-One bench step = one aqt_run: 10^4 trajectories through the whole anneal
-(2000 grid points, 1999 trajectory steps each) with the eigenbasis tables
-already resident in HBM.  value = trajectory-steps/s of the FP32 MFMA path;
-the FP64 and BF16x3 paths are timed the same way and reported beside it, each
-with its ground-state-population error against the FP64 master equation.
-Prints one JSON line.
+One bench step = one aqt_run: all trajectories of the workload through the whole
+anneal with the eigenbasis tables already resident in HBM (the GPU precompute
+runs once, untimed, and is reported as precompute_s).  value = trajectory-steps/s
+of the workload's headline precision; the other precisions are timed the same way
+and reported beside it, each with its ground-state-population error against the
+FP64 master equation where a stored reference exists.  Prints one JSON line.
+
+Workloads:
+  a2a8      (default) 8-qubit all-to-all +-1 Ising anneal, full spectrum n = 256,
+            2000 grid points, t_f = 10 us, 10^4 trajectories, FP32 headline
+  ring4     4-qubit ring, full spectrum n = 16, 1001 grid points, t_f = 1 us,
+            10^3 trajectories, FP64 headline (the plain method)
+  gadget16  16-qubit two-cluster gadget (N = 65536) truncated to 32 levels by the
+            iterative eigensolver, 500 grid points, t_f = 10 us, 10^5 trajectories,
+            FP32 headline
 """
 import argparse
 import json
@@ -22,6 +32,7 @@ sys.path.insert(0, ROOT)
 METRIC = "trajectory-steps/s at 1 MI355X (mixed vs FP64) at stated error vs FP64 AME"
 PEAK = {"fp32": 157.3e12, "fp64": 78.6e12, "bf16": 2.5e15}
 FLOP_PER_TRAJ_STEP = lambda n: 4 * n * n + 10 * n   # overlap GEMM (real n x n by n x 2) + diagonal/norm
+TILE_TQ = {"a2a8": 5}   # column tiles the launch picks for 10^4 trajectories at n = 256 (TT = 40)
 
 
 def parse():
@@ -29,16 +40,38 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--n-traj", type=int, default=10_000)
+    ap.add_argument("--workload", default="a2a8", choices=("a2a8", "ring4", "gadget16"))
+    ap.add_argument("--n-traj", type=int, default=0, help="override the workload's trajectory count")
     ap.add_argument("--cpu-traj", type=int, default=3072)
-    ap.add_argument("--cpu-grid", type=int, default=500)
+    ap.add_argument("--cpu-grid", type=int, default=0, help="steps of the CPU sample (default per workload)")
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--precisions", default="fp32,fp64,bf16")
+    ap.add_argument("--precisions", default="")
     return ap.parse_args()
 
 
-def load_ame_reference():
-    path = os.path.join(ROOT, "tests", "golden", "a2a8_ame_pgs.json")
+def workload(name, n_traj):
+    import workloads as W
+    if name == "a2a8":
+        inst = W.config_a2a8(n_traj or 10_000)
+        return dict(inst=inst, head="fp32", precisions="fp32,fp64,bf16", golden="a2a8_ame_pgs.json", cpu_grid=500,
+                    text="8-qubit all-to-all +-1 Ising anneal, full spectrum n=256, 2000 grid points, "
+                         f"t_f=10us, {inst.n_traj} trajectories")
+    if name == "ring4":
+        inst = W.config_small().with_(n_traj=n_traj or 1000)
+        return dict(inst=inst, head="fp64", precisions="fp64,fp32", golden="small_ame_pgs.json", cpu_grid=1000,
+                    text="4-qubit ring, U[-1,1] couplings, full spectrum n=16, 1001 grid points, t_f=1us, "
+                         f"{inst.n_traj} trajectories")
+    inst = W.config_gadget(n_traj or 100_000)
+    # the oracle's sparse eigensolver takes ~10 s per grid point here: a 4-step CPU sample
+    return dict(inst=inst, head="fp32", precisions="fp32,fp64,bf16", golden=None, cpu_grid=4,
+                text="16-qubit two-cluster gadget (N=65536) truncated to 32 levels, 500 grid points, "
+                     f"t_f=10us, {inst.n_traj} trajectories")
+
+
+def load_ame_reference(name):
+    if not name:
+        return None
+    path = os.path.join(ROOT, "tests", "golden", name)
     if not os.path.exists(path):
         return None
     with open(path) as f:
@@ -61,13 +94,14 @@ def time_precision(eng, torch, K, prec, steps, warmup, seed):
         starts[i].record()
         eng.run_into(outs, K, prec, seed=seed + i)
         ends[i].record()
-        sums.append((outs["pgs_sum"][-1].clone(), outs["pgs_sumsq"][-1].clone()))
+        sums.append((outs["pgs_sum"][-1].clone(), outs["pgs_sumsq"][-1].clone(), outs["jump_totals"].clone()))
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     ev_ms = [s.elapsed_time(e) for s, e in zip(starts, ends)]
-    p = [float(a) / K for a, _ in sums]
-    q = [float(b) / K for _, b in sums]
-    return {"wall_s": wall, "event_ms": ev_ms, "pgs_final": p, "pgs_sq_final": q}
+    p = [float(a) / K for a, _, _ in sums]
+    q = [float(b) / K for _, b, _ in sums]
+    jumps = sum(float(j.sum()) for _, _, j in sums) / (K * len(sums))
+    return {"wall_s": wall, "event_ms": ev_ms, "pgs_final": p, "pgs_sq_final": q, "jumps_per_traj": jumps}
 
 
 def cpu_baseline(inst, n_traj, n_steps):
@@ -81,6 +115,7 @@ def cpu_baseline(inst, n_traj, n_steps):
         threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
     except Exception:
         threads = os.cpu_count()
+    n_steps = min(n_steps, inst.n_grid - 1)
     tabs = list(itertools.islice(spectrum.table_stream(inst), n_steps))
     t0 = time.perf_counter()
     trajectories.run(tabs, inst, n_traj, record=False)
@@ -88,7 +123,7 @@ def cpu_baseline(inst, n_traj, n_steps):
     steps = n_traj * len(tabs)
     return {"value": steps / dt, "unit": "trajectory-steps/s", "cores": threads, "kind": "oracle",
             "sample": f"{n_traj} trajectories x the first {len(tabs)} of {inst.n_grid - 1} steps of the "
-                      f"same 8-qubit anneal (FP64 NumPy oracle, {dt:.1f} s timed; its tables built "
+                      f"same anneal ({inst.name}; FP64 NumPy oracle, {dt:.1f} s timed; its tables built "
                       f"beforehand, untimed)"}
 
 
@@ -115,11 +150,11 @@ def main():
                           "n_gpus": args.gpus}))
         sys.exit(2)
     import torch
-    import workloads as W
     from paper_1710_03431_amd.binding import Engine
 
-    inst = W.config_a2a8(args.n_traj)
-    K = args.n_traj
+    wl = workload(args.workload, args.n_traj)
+    inst = wl["inst"]
+    K = inst.n_traj
     M = inst.n_grid
     n = inst.levels
     eng = Engine(0)
@@ -127,12 +162,12 @@ def main():
     t0 = time.perf_counter()
     eng.precompute(M, n)
     precompute_s = time.perf_counter() - t0
-    print(f"# precompute {precompute_s:.2f} s (n={n}, M={M})", file=sys.stderr, flush=True)
+    print(f"# precompute {precompute_s:.2f} s ({inst.name}, n={n}, M={M})", file=sys.stderr, flush=True)
 
-    ref = load_ame_reference()
+    ref = load_ame_reference(wl["golden"])
     p_ame = ref["pgs"][-1] if ref else None
     results = {}
-    for prec in args.precisions.split(","):
+    for prec in (args.precisions or wl["precisions"]).split(","):
         r = time_precision(eng, torch, K, prec, args.steps, args.warmup, seed=inst.seed)
         ms = sum(r["event_ms"]) / len(r["event_ms"])
         mean_p = sum(r["pgs_final"]) / len(r["pgs_final"])
@@ -141,33 +176,37 @@ def main():
         var = (sum(r["pgs_sq_final"]) * K - R * mean_p * mean_p) / (R - 1)
         se = math.sqrt(max(var, 0.0) / R)
         results[prec] = {"ms": ms, "value": K * (M - 1) / (ms / 1e3), "pgs_final": mean_p, "pgs_se": se,
-                         "err_vs_ame": (abs(mean_p - p_ame) if p_ame is not None else None), "wall_s": r["wall_s"]}
+                         "err_vs_ame": (abs(mean_p - p_ame) if p_ame is not None else None), "wall_s": r["wall_s"],
+                         "jumps_per_traj": r["jumps_per_traj"]}
         print(f"# {prec}: {ms:.2f} ms/run, {results[prec]['value']:.4g} traj-steps/s, "
-              f"P_GS(1)={mean_p:.5f}+-{se:.5f}", file=sys.stderr, flush=True)
+              f"P_GS(1)={mean_p:.5f}+-{se:.5f}, {r['jumps_per_traj']:.1f} jumps/trajectory", file=sys.stderr,
+              flush=True)
 
-    head = results.get("fp32") or next(iter(results.values()))
-    head_prec = "fp32" if "fp32" in results else next(iter(results))
+    head_prec = wl["head"] if wl["head"] in results else next(iter(results))
+    head = results[head_prec]
     flops = FLOP_PER_TRAJ_STEP(n) * K * (M - 1)
     achieved = flops / (head["ms"] / 1e3)
+    traffic = None
+    if args.workload == "a2a8" and head_prec == "fp32" and K == 10_000:
+        traffic = measured_traffic(f"k_trajectories<256, {TILE_TQ['a2a8']}, ModeF32>")
     roof = {"bound": "mfma", "achieved": achieved / 1e12, "peak": PEAK[head_prec] / 1e12, "unit": "TFLOP/s",
-            "frac": achieved / PEAK[head_prec],
-            "traffic": measured_traffic("k_trajectories<256, 5, ModeF32>") if head_prec == "fp32" else None,
-            "kernel": f"k_trajectories<n=256, {head_prec}>",
+            "frac": achieved / PEAK[head_prec], "traffic": traffic,
+            "kernel": f"k_trajectories<n={n}, {head_prec}>",
             "per_unit": f"{FLOP_PER_TRAJ_STEP(n)} flop per trajectory-step"}
     cpu = None
     if not args.no_cpu:
-        cpu = cpu_baseline(W.config_a2a8(args.cpu_traj), args.cpu_traj, args.cpu_grid)
+        cpu = cpu_baseline(inst.with_(n_traj=args.cpu_traj), args.cpu_traj, args.cpu_grid or wl["cpu_grid"])
     line = {
         "metric": METRIC, "value": head["value"], "unit": "trajectory-steps/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": head["ms"], "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": head_prec, "data": "synthetic",
-        "config": {"workload": "8-qubit all-to-all +-1 Ising anneal, full spectrum n=256, 2000 grid points, "
-                               "t_f=10us, 10^4 trajectories", "n_traj": K, "n_levels": n, "n_grid": M,
+        "config": {"workload": wl["text"], "name": inst.name, "n_traj": K, "n_levels": n, "n_grid": M,
                    "precision": head_prec, "seed": inst.seed},
         "error_vs_fp64_ame": {"P_GS_final_ame": p_ame,
                               **{p: {"P_GS_final": v["pgs_final"], "stderr": v["pgs_se"],
                                      "abs_err": v["err_vs_ame"]} for p, v in results.items()}},
-        "paths": {p: {"value": v["value"], "ms_per_step": v["ms"]} for p, v in results.items()},
+        "paths": {p: {"value": v["value"], "ms_per_step": v["ms"], "jumps_per_traj": v["jumps_per_traj"]}
+                  for p, v in results.items()},
         "precompute_s": precompute_s,
         "roofline": roof,
         "cpu_baseline": cpu,

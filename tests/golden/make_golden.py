@@ -7,7 +7,8 @@ It records
     "ground-state population" of Sec. V is that of a single level);
   * the split-step FP64 AME ground-state population of that instance on its
     2000-point grid (a2a8_ame_pgs.json), the reference for the stated error
-    of the GPU trajectory averages.
+    of the GPU trajectory averages (python tests/golden/make_golden.py --ame);
+  * the same for the 4-qubit ring workload (small_ame_pgs.json, --ame-small).
 """
 import json
 import os
@@ -44,9 +45,22 @@ def ame_a2a8():
                    "pgs": [float(p) for p in P]}, f)
 
 
+def ame_small():
+    from oracle import ame, spectrum
+    inst = workloads.config_small()
+    P = ame.split_step(spectrum.table_stream(inst), inst)
+    with open(os.path.join(HERE, "small_ame_pgs.json"), "w") as f:
+        json.dump({"source": "oracle.ame.split_step over oracle.spectrum.table_stream(workloads.config_small())",
+                   "instance": inst.name, "n_grid": inst.n_grid, "t_f": inst.t_f,
+                   "pgs": [float(p) for p in P]}, f)
+
+
 if __name__ == "__main__":
     if "--ame" in sys.argv:
         ame_a2a8()
+        sys.exit(0)
+    if "--ame-small" in sys.argv:
+        ame_small()
         sys.exit(0)
     rows = scan_a2a8()
     with open(os.path.join(HERE, "a2a8_seed_scan.json"), "w") as f:
