@@ -431,3 +431,30 @@ def test_sparse_eigensolver_finds_every_sector_and_multiplicity():
         Pd = Vd[:, :cut] @ Vd[:, :cut].T
         Ps = Vs[:, :cut] @ Vs[:, :cut].T
         assert np.abs(Pd - Ps).max() < 1e-7
+
+
+def test_polar_completion_is_orthogonal_and_agrees_on_kept_directions():
+    """Polar factor with lost directions: for M = U diag(s) W^T with one singular value
+    below the loss threshold, the completed factor is orthogonal, maps every kept right
+    singular vector w_a to u_a exactly as the polar factor does, and maps the lost one
+    into the orthogonal complement of the kept u_a; with nothing lost it is U W^T."""
+    rng = np.random.default_rng(5)
+    n = 6
+    U, _ = np.linalg.qr(rng.standard_normal((n, n)))
+    Wm, _ = np.linalg.qr(rng.standard_normal((n, n)))
+    s = np.array([1.0, 0.9, 0.7, 0.5, 0.2, 1e-9])
+    M = U @ np.diag(s) @ Wm.T
+    P, S = spectrum.polar(M)
+    np.testing.assert_allclose(P.T @ P, np.eye(n), atol=1e-12)
+    for a in range(n - 1):
+        np.testing.assert_allclose(P @ Wm[:, a], U[:, a], atol=1e-9)
+    lost = P @ Wm[:, n - 1]
+    assert np.abs(U[:, : n - 1].T @ lost).max() < 1e-9
+    assert abs(np.linalg.norm(lost) - 1.0) < 1e-12
+    s2 = np.array([1.0, 0.9, 0.7, 0.5, 0.2, 0.1])
+    P2, _ = spectrum.polar(U @ np.diag(s2) @ Wm.T)
+    np.testing.assert_allclose(P2, U @ Wm.T, atol=1e-12)
+    # the completion depends only on the lost and free subspaces, not on the signs the
+    # SVD happens to give their vectors: -M has the same subspaces, so the same completion
+    P3, _ = spectrum.polar(-M)
+    np.testing.assert_allclose(P3 @ Wm[:, n - 1], lost, atol=1e-9)
