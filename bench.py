@@ -1,6 +1,6 @@
 """Throughput of the GPU trajectory engine.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload a2a8|ring4|gadget16]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload a2a8|ring4|gadget16|batched]
                     [--cpu-traj 3072] [--cpu-grid 500] [--no-cpu]
 
 One bench step = one aqt_run: all trajectories of the workload through the whole
@@ -18,6 +18,9 @@ Workloads:
   gadget16  16-qubit two-cluster gadget (N = 65536) truncated to 32 levels by the
             iterative eigensolver, 500 grid points, t_f = 10 us, 10^5 trajectories,
             FP32 headline
+  batched   256 instances of 6-10 qubits truncated to 16, 32 or 64 levels, 1000 grid
+            points, t_f 1-100 us, 2048 trajectories each, all in one persistent
+            graph-captured launch with autotuned tiles; BF16x3 headline
 """
 import argparse
 import json
@@ -40,7 +43,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="a2a8", choices=("a2a8", "ring4", "gadget16"))
+    ap.add_argument("--workload", default="a2a8", choices=("a2a8", "ring4", "gadget16", "batched"))
     ap.add_argument("--n-traj", type=int, default=0, help="override the workload's trajectory count")
     ap.add_argument("--cpu-traj", type=int, default=3072)
     ap.add_argument("--cpu-grid", type=int, default=0, help="steps of the CPU sample (default per workload)")
@@ -143,12 +146,87 @@ def measured_traffic(kernel_key):
     return rec["traffic_bytes"]
 
 
+def bench_batched(args):
+    """256 instances in one persistent launch (aqt_batch_*), graph-captured, autotuned."""
+    import torch
+    import workloads as W
+    from paper_1710_03431_amd.binding import Batch, Engine
+    insts = W.config_batched(n_traj=args.n_traj or 2048)
+    t0 = time.perf_counter()
+    engines = []
+    for k, inst in enumerate(insts):
+        eng = Engine(0)
+        eng.set_instance(inst)
+        eng.precompute(inst.n_grid, inst.levels)
+        engines.append(eng)
+        if k % 8 == 7:
+            print(f"# precomputed {k + 1}/{len(insts)} instances, {time.perf_counter() - t0:.1f} s",
+                  file=sys.stderr, flush=True)
+    precompute_s = time.perf_counter() - t0
+    print(f"# precompute {precompute_s:.1f} s for {len(insts)} instances", file=sys.stderr, flush=True)
+    steps_total = sum(i.n_traj * (i.n_grid - 1) for i in insts)
+    flops = sum(FLOP_PER_TRAJ_STEP(i.levels) * i.n_traj * (i.n_grid - 1) for i in insts)
+    runs = [dict(n_traj=i.n_traj, seed=i.seed, instance_id=i.instance_id) for i in insts]
+    results = {}
+    for prec in (args.precisions or "bf16,fp32").split(","):
+        t1 = time.perf_counter()
+        b = Batch(engines, runs, precision=prec, graph=True, autotune=True)
+        setup_s = time.perf_counter() - t1
+        for _ in range(args.warmup):
+            b.launch()
+        torch.cuda.synchronize()
+        starts = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
+        ends = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
+        for i in range(args.steps):
+            starts[i].record()
+            b.launch()
+            ends[i].record()
+        torch.cuda.synchronize()
+        ms = sum(s.elapsed_time(e) for s, e in zip(starts, ends)) / args.steps
+        res = b.results()
+        p = [float(r["pgs_sum"][-1]) / i.n_traj for r, i in zip(res, insts)]
+        tiles = sorted(set(b.tiles))
+        b.close()
+        results[prec] = {"ms": ms, "value": steps_total / (ms / 1e3), "setup_s": setup_s, "tiles": tiles,
+                         "mean_pgs_final": sum(p) / len(p)}
+        print(f"# {prec}: {ms:.2f} ms/launch, {results[prec]['value']:.4g} traj-steps/s, tiles {tiles}, "
+              f"setup (graph capture + autotune) {setup_s:.1f} s", file=sys.stderr, flush=True)
+    head_prec = "bf16" if "bf16" in results else next(iter(results))
+    head = results[head_prec]
+    achieved = flops / (head["ms"] / 1e3)
+    cpu = None
+    if not args.no_cpu:
+        small = insts[0]
+        cpu = cpu_baseline(small.with_(n_traj=args.cpu_traj), args.cpu_traj, args.cpu_grid or 200)
+    line = {
+        "metric": METRIC, "value": head["value"], "unit": "trajectory-steps/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": head["ms"], "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": head_prec, "data": "synthetic",
+        "config": {"workload": f"{len(insts)} instances, 6-10 qubits, n in {{16,32,64}}, 1000 grid points, "
+                               f"t_f 1-100 us, {insts[0].n_traj} trajectories each, one graph-captured "
+                               "persistent launch", "n_instances": len(insts),
+                   "trajectory_steps_per_launch": steps_total, "precision": head_prec},
+        "error_vs_fp64_ame": None,
+        "paths": {p: {"value": v["value"], "ms_per_step": v["ms"], "tiles": v["tiles"],
+                      "mean_P_GS_final": v["mean_pgs_final"]} for p, v in results.items()},
+        "precompute_s": precompute_s,
+        "roofline": {"bound": "mfma", "achieved": achieved / 1e12, "peak": PEAK[head_prec] / 1e12,
+                     "unit": "TFLOP/s", "frac": achieved / PEAK[head_prec], "traffic": None,
+                     "kernel": f"k_batch<{head_prec}>", "per_unit": "4 n^2 + 10 n flop per trajectory-step"},
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line))
+
+
 def main():
     args = parse()
     if args.gpus != 1:
         print(json.dumps({"error": "this engine runs on one GPU; multi-GPU runs are not part of this build",
                           "n_gpus": args.gpus}))
         sys.exit(2)
+    if args.workload == "batched":
+        bench_batched(args)
+        return
     import torch
     from paper_1710_03431_amd.binding import Engine
 

@@ -246,4 +246,98 @@ __device__ void wg_rank_ascending(const double* d, int N, int* perm) {
   __syncthreads();
 }
 
+
+// ---- lowest eigenpairs of the band without the full rotation product --------
+// Number of eigenvalues of the symmetric tridiagonal (d, e) below x (Sturm count
+// of the LDL^T pivots; a zero pivot is replaced by -tiny).
+__device__ __forceinline__ int sturm_count(const double* d, const double* e, int N, double x, double tiny) {
+  int cnt = 0;
+  double q = d[0] - x;
+  cnt += q < 0.0;
+  for (int i = 1; i < N; ++i) {
+    const double den = (q != 0.0) ? q : -tiny;
+    q = (d[i] - x) - e[i - 1] * e[i - 1] / den;
+    cnt += q < 0.0;
+  }
+  return cnt;
+}
+
+// k-th smallest eigenvalue (0-based) of the band by bisection inside [lo, hi].
+__device__ double band_bisect(const double* d, const double* e, int N, int k, double lo, double hi, double tiny) {
+  for (int it = 0; it < 200; ++it) {
+    const double mid = 0.5 * (lo + hi);
+    if (!(mid > lo && mid < hi)) break;
+    if (hi - lo <= 4.440892098500626e-16 * fmax(fabs(lo), fabs(hi)) + tiny) break;
+    if (sturm_count(d, e, N, mid, tiny) > k) hi = mid;
+    else lo = mid;
+  }
+  return 0.5 * (lo + hi);
+}
+
+// Inverse iteration for eigenvalue lam of the band: LU of (T - lam I) with partial
+// pivoting (a zero pivot becomes tiny), three solves from a fixed start vector, each
+// normalised.  ws: 4N doubles plus N bytes of pivot flags; x: N doubles.
+__device__ void band_inverse_iteration(const double* d, const double* e, int N, double lam, double tiny,
+                                       unsigned seed, double* ws, unsigned char* piv, double* x) {
+  double* dl = ws;
+  double* dd = ws + N;
+  double* du = ws + 2 * N;
+  double* du2 = ws + 3 * N;
+  for (int i = 0; i < N; ++i) {
+    dd[i] = d[i] - lam;
+    if (i + 1 < N) {
+      dl[i] = e[i];
+      du[i] = e[i];
+    }
+    du2[i] = 0.0;
+  }
+  for (int i = 0; i + 1 < N; ++i) {
+    if (fabs(dd[i]) >= fabs(dl[i])) {
+      piv[i] = 0;
+      if (dd[i] == 0.0) dd[i] = tiny;
+      const double f = dl[i] / dd[i];
+      dl[i] = f;
+      dd[i + 1] -= f * du[i];
+    } else {
+      piv[i] = 1;
+      const double f = dd[i] / dl[i];
+      dd[i] = dl[i];
+      dl[i] = f;
+      const double t = du[i];
+      du[i] = dd[i + 1];
+      dd[i + 1] = t - f * dd[i + 1];
+      if (i + 2 < N) {
+        du2[i] = du[i + 1];
+        du[i + 1] = -f * du[i + 1];
+      }
+    }
+  }
+  if (dd[N - 1] == 0.0) dd[N - 1] = tiny;
+  uint32_t h = seed * 2654435761u + 12345u;
+  for (int i = 0; i < N; ++i) {
+    h ^= h << 13;
+    h ^= h >> 17;
+    h ^= h << 5;
+    x[i] = static_cast<double>(h & 0xffffff) * (1.0 / 16777216.0) - 0.5;
+  }
+  for (int it = 0; it < 3; ++it) {
+    for (int i = 0; i + 1 < N; ++i) {
+      if (piv[i] == 0) {
+        x[i + 1] -= dl[i] * x[i];
+      } else {
+        const double t = x[i];
+        x[i] = x[i + 1];
+        x[i + 1] = t - dl[i] * x[i];
+      }
+    }
+    x[N - 1] /= dd[N - 1];
+    if (N >= 2) x[N - 2] = (x[N - 2] - du[N - 2] * x[N - 1]) / dd[N - 2];
+    for (int i = N - 3; i >= 0; --i) x[i] = (x[i] - du[i] * x[i + 1] - du2[i] * x[i + 2]) / dd[i];
+    double nn = 0.0;
+    for (int i = 0; i < N; ++i) nn += x[i] * x[i];
+    const double inv = (nn > 0.0 && nn < 1e300) ? 1.0 / sqrt(nn) : 0.0;
+    for (int i = 0; i < N; ++i) x[i] *= inv;
+  }
+}
+
 }  // namespace aqt

@@ -71,23 +71,139 @@ __global__ void k_build_dense(const double* __restrict__ eZ, int nq, const doubl
 
 // One workgroup per matrix: eigenvalues (ascending, stable) and eigenvectors.
 // Z is column-major: Z[col * N + row]; perm[a] is the column of level a.
-__global__ __launch_bounds__(kEigThreads) void k_dense_eig(double* H, double* Z, int N, int ncols,
+__global__ __launch_bounds__(kEigThreads) void k_dense_eig(double* H, double* Z, int N, int ncols, int partial,
                                                            double* __restrict__ Eraw, int* __restrict__ perm,
                                                            int* __restrict__ status) {
   __shared__ EigShared sh;
   __shared__ int s_perm[kEigMaxN];
+  __shared__ double s_lo, s_hi;
   const int c = blockIdx.x;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   double* A = H + static_cast<size_t>(c) * N * N;
   double* Zc = Z + static_cast<size_t>(c) * N * N;
   wg_tridiagonalize(A, N, N, sh);
-  const bool ok = wg_band_qr(Zc, N, N, sh);
-  wg_rank_ascending(sh.d, N, s_perm);
-  wg_back_transform(A, N, N, Zc, N, s_perm, ncols, sh);
-  for (int a = threadIdx.x; a < N; a += blockDim.x) {
-    perm[static_cast<size_t>(c) * N + a] = s_perm[a];
-    Eraw[static_cast<size_t>(c) * N + a] = sh.d[s_perm[a]];
+  if (!partial) {
+    const bool ok = wg_band_qr(Zc, N, N, sh);
+    wg_rank_ascending(sh.d, N, s_perm);
+    wg_back_transform(A, N, N, Zc, N, s_perm, ncols, sh);
+    for (int a = tid; a < N; a += blockDim.x) {
+      perm[static_cast<size_t>(c) * N + a] = s_perm[a];
+      Eraw[static_cast<size_t>(c) * N + a] = sh.d[s_perm[a]];
+    }
+    if (tid == 0) status[c] = ok ? 0 : 1;
+    return;
   }
-  if (threadIdx.x == 0) status[c] = ok ? 0 : 1;
+  // Lowest ncols pairs only: bisection for the eigenvalues of the band, inverse
+  // iteration for its eigenvectors, one orthonormalisation and a Rayleigh-Ritz step
+  // on the band inside their span, then the Householder back-transform.  Columns
+  // ncols.. of Zc serve as workspace.
+  const int nc = ncols;
+  double* X = Zc;                                        // band eigenvectors, column-major
+  double* Dsv = Zc + static_cast<size_t>(nc) * N;        // band diagonal
+  double* Esv = Dsv + N;                                 // band off-diagonal
+  double* Bsv = Esv + N;                                 // reflection coefficients
+  double* lam = Bsv + N;                                 // nc
+  double* Tc = lam + nc;                                 // nc x nc
+  double* Zs = Tc + static_cast<size_t>(nc) * nc;        // nc x nc
+  double* Wt = Zs + static_cast<size_t>(nc) * nc;        // nc x N
+  double* lu = Wt + static_cast<size_t>(nc) * N;         // 4 N per vector
+  unsigned char* piv = reinterpret_cast<unsigned char*>(lu + 4 * static_cast<size_t>(nc) * N);
+  for (int i = tid; i < N; i += blockDim.x) {
+    Dsv[i] = sh.d[i];
+    Esv[i] = sh.e[i];
+    Bsv[i] = sh.beta[i];
+  }
+  if (tid == 0) {
+    double lo = 1e300, hi = -1e300;
+    for (int i = 0; i < N; ++i) {
+      const double r = ((i > 0) ? fabs(sh.e[i - 1]) : 0.0) + ((i + 1 < N) ? fabs(sh.e[i]) : 0.0);
+      lo = fmin(lo, sh.d[i] - r);
+      hi = fmax(hi, sh.d[i] + r);
+    }
+    const double pad = 1e-12 * fmax(fabs(lo), fabs(hi)) + 1e-300;
+    s_lo = lo - pad;
+    s_hi = hi + pad;
+  }
+  __syncthreads();
+  const double tiny = 2.220446049250313e-16 * fmax(fabs(s_lo), fabs(s_hi)) + 1e-300;
+  for (int t = tid; t < nc; t += blockDim.x) {
+    lam[t] = band_bisect(sh.d, sh.e, N, t, s_lo, s_hi, tiny);
+    band_inverse_iteration(sh.d, sh.e, N, lam[t], tiny, static_cast<unsigned>(t + 1), lu + 4 * static_cast<size_t>(t) * N,
+                           piv + static_cast<size_t>(t) * N, X + static_cast<size_t>(t) * N);
+  }
+  __syncthreads();
+  // modified Gram-Schmidt, two passes per vector
+  for (int j = 0; j < nc; ++j) {
+    double* xj = X + static_cast<size_t>(j) * N;
+    for (int pass = 0; pass < 2; ++pass) {
+      for (int i = 0; i < j; ++i) {
+        const double* xi = X + static_cast<size_t>(i) * N;
+        double part = 0.0;
+        for (int k = tid; k < N; k += blockDim.x) part += xi[k] * xj[k];
+        const double dot = block_sum(part, sh.red);
+        for (int k = tid; k < N; k += blockDim.x) xj[k] -= dot * xi[k];
+        __syncthreads();
+      }
+    }
+    double part = 0.0;
+    for (int k = tid; k < N; k += blockDim.x) part += xj[k] * xj[k];
+    const double nn = block_sum(part, sh.red);
+    const double inv = (nn > 0.0) ? 1.0 / sqrt(nn) : 0.0;
+    for (int k = tid; k < N; k += blockDim.x) xj[k] *= inv;
+    __syncthreads();
+  }
+  // Rayleigh-Ritz with the band inside span(X)
+  for (size_t f = tid; f < static_cast<size_t>(nc) * N; f += blockDim.x) {
+    const int j = static_cast<int>(f / N), k = static_cast<int>(f - static_cast<size_t>(j) * N);
+    const double* xj = X + static_cast<size_t>(j) * N;
+    double v = Dsv[k] * xj[k];
+    if (k > 0) v += Esv[k - 1] * xj[k - 1];
+    if (k + 1 < N) v += Esv[k] * xj[k + 1];
+    Wt[f] = v;
+  }
+  __syncthreads();
+  for (int p = wave; p < nc * nc; p += kEigThreads / kWave) {
+    const int i = p / nc, j = p - i * nc;
+    const double* xi = X + static_cast<size_t>(i) * N;
+    const double* wj = Wt + static_cast<size_t>(j) * N;
+    double acc = 0.0;
+    for (int k = lane; k < N; k += kWave) acc += xi[k] * wj[k];
+    acc = wave_sum(acc);
+    if (lane == 0) Tc[p] = acc;
+  }
+  __syncthreads();
+  for (int p = tid; p < nc * nc; p += blockDim.x) {
+    const int i = p / nc, j = p - i * nc;
+    if (i < j) {
+      const double m = 0.5 * (Tc[i * nc + j] + Tc[j * nc + i]);
+      Tc[i * nc + j] = m;
+      Tc[j * nc + i] = m;
+    }
+  }
+  __syncthreads();
+  wg_tridiagonalize(Tc, nc, nc, sh);
+  const bool ok = wg_band_qr(Zs, nc, nc, sh);
+  wg_rank_ascending(sh.d, nc, s_perm);
+  wg_back_transform(Tc, nc, nc, Zs, nc, s_perm, nc, sh);
+  for (int a = tid; a < nc; a += blockDim.x) lam[a] = sh.d[s_perm[a]];
+  for (size_t f = tid; f < static_cast<size_t>(nc) * N; f += blockDim.x) {
+    const int a = static_cast<int>(f / N), k = static_cast<int>(f - static_cast<size_t>(a) * N);
+    const double* q = Zs + static_cast<size_t>(s_perm[a]) * nc;
+    double acc = 0.0;
+    for (int i = 0; i < nc; ++i) acc += q[i] * X[static_cast<size_t>(i) * N + k];
+    Wt[f] = acc;
+  }
+  __syncthreads();
+  for (size_t f = tid; f < static_cast<size_t>(nc) * N; f += blockDim.x) X[f] = Wt[f];
+  for (int i = tid; i < N; i += blockDim.x) sh.beta[i] = Bsv[i];
+  for (int a = tid; a < nc; a += blockDim.x) s_perm[a] = a;
+  __syncthreads();
+  wg_back_transform(A, N, N, X, N, s_perm, nc, sh);
+  for (int a = tid; a < N; a += blockDim.x) {
+    perm[static_cast<size_t>(c) * N + a] = a;
+    Eraw[static_cast<size_t>(c) * N + a] = (a < nc) ? lam[a] : 0.0;
+  }
+  if (tid == 0) status[c] = ok ? 0 : 1;
 }
 
 // Canonical basis, signs and truncation.  Reads level a (< ncols) as column
@@ -810,6 +926,15 @@ aqt_status precompute_tables(aqt_ctx* ctx, int M, int n, double tol, int method)
   }
   const int NP = padded_levels(n);
   hipStream_t st = ctx->stream;
+  // dense path with ncols << N: bisection and inverse iteration instead of the full
+  // rotation product, when the workspace (columns ncols.. of the N x N eigenvector
+  // buffer) holds it
+  bool partial = false;
+  if (!iterative && ncols < N) {
+    const size_t c = ncols, NN = N;
+    const size_t need = 3 * NN + c + 2 * c * c + c * NN + 4 * c * NN + (c * NN + 7) / 8;
+    partial = need <= (NN - c) * NN;
+  }
 
   // ---- schedule samples and Ising diagonal
   std::vector<double> Ag(M), Bg(M);
@@ -855,7 +980,7 @@ aqt_status precompute_tables(aqt_ctx* ctx, int M, int n, double tol, int method)
                           + static_cast<size_t>(nq) * n * n           // z
                           + 9 * static_cast<size_t>(n) * n            // polar ws
                           + N;                                        // Eraw
-  const size_t budget = size_t(2) << 30;
+  const size_t budget = size_t(24) << 30;   // of 288 GB HBM: all grid points of a 10-qubit instance in one chunk
   int Gc = static_cast<int>(std::max<size_t>(1, std::min<size_t>(M, budget / (per_grid * 8))));
   DevBuf H, Z, Vc, Vprev, cws, zws, pws, Eraw, perm, status;
   if ((!iterative && (H.reserve(static_cast<size_t>(Gc) * N * N * 8) || Z.reserve(static_cast<size_t>(Gc) * N * N * 8))) ||
@@ -905,7 +1030,7 @@ aqt_status precompute_tables(aqt_ctx* ctx, int M, int n, double tol, int method)
                          eZ.as<double>(), nq, dA.as<double>(), dB.as<double>(), g0, cnt, H.as<double>());
       AQT_HIP(ctx, hipGetLastError());
       hipLaunchKernelGGL(k_dense_eig, dim3(cnt), dim3(kEigThreads), 0, st, H.as<double>(), Z.as<double>(), N, ncols,
-                         Eraw.as<double>(), perm.as<int>(), status.as<int>());
+                         partial ? 1 : 0, Eraw.as<double>(), perm.as<int>(), status.as<int>());
       AQT_HIP(ctx, hipGetLastError());
       hipLaunchKernelGGL(k_canon, dim3(cnt), dim3(kEigThreads), 0, st, Z.as<double>(), perm.as<int>(),
                          Eraw.as<double>(), N, ncols, n, NP, tol, g0, Vc.as<double>(), ctx->E.as<double>(),

@@ -182,6 +182,17 @@ def test_degenerate_initial_state_is_rejected():
     assert e.value.status == AQT_ENUMERIC
 
 
+def test_dense_lowest_levels_tables():
+    """9 qubits truncated to 32 levels: the dense path computes only the lowest 48 pairs
+    (bisection, inverse iteration, Rayleigh-Ritz); tables against the oracle's eigh."""
+    inst = W.pm1_all_to_all(9, 31, t_f=2000.0, n_grid=120, n_levels=32)
+    tabs, prev, full = sampled_tables(inst, {1, 2, 60, 118, 119})
+    eng = gpu_tables(inst, method="dense")
+    got = eng.get_tables()
+    check_tables(got, tabs, scale=100.0, prev=prev, full=full)
+    np.testing.assert_allclose(got["cinit"], tabs[0].cinit, atol=1e-9)
+
+
 def test_iterative_solver_tables_truncated():
     """Chebyshev-filtered subspace iteration (forced on an 8-qubit instance truncated to 16
     levels) against the oracle's dense eigensolver: energies, overlaps, rates."""
