@@ -219,20 +219,47 @@ __device__ __forceinline__ double xor8(double v) {
   return __builtin_bit_cast(double, (static_cast<uint64_t>(static_cast<uint32_t>(hi)) << 32) | static_cast<uint32_t>(lo));
 }
 
+// A crossing is handled by a segment of SEG consecutive lanes (SEG = NP when
+// NP <= 32, else the whole wavefront): a wavefront serves 64 / SEG crossings at
+// once.  Reductions, scans, ballots and broadcasts stay inside the segment.
+template <int SEG>
+__device__ __forceinline__ double seg_sum(double v) {
+#pragma unroll
+  for (int o = SEG / 2; o >= 1; o >>= 1) v += __shfl_xor(v, o, kWave);
+  return v;
+}
+template <int SEG>
+__device__ __forceinline__ double seg_scan(double v, int sl) {
+#pragma unroll
+  for (int o = 1; o < SEG; o <<= 1) {
+    const double u = __shfl_up(v, o, SEG);
+    if (sl >= o) v += u;
+  }
+  return v;
+}
+template <int SEG>
+__device__ __forceinline__ uint64_t seg_ballot(bool pred, int base) {
+  const uint64_t m = __ballot(pred);
+  return (SEG == 64) ? m : (m >> base) & ((1ull << SEG) - 1ull);
+}
+
 // Uniform draws of one trajectory served from Philox blocks computed in parallel:
-// lane l holds block B0 + l (four words), so one generator evaluation covers the
-// next 256 draws; later draws (more than about 80 jumps in one step) fall back
-// to a direct evaluation.
+// lane l of the segment holds block B0 + l (four words), so one generator
+// evaluation covers the next 4 SEG draws; later draws fall back to a direct
+// evaluation.
+template <int SEG>
 struct DrawCache {
   uint64_t B0;
   uint64_t w0, w1, w2, w3;
   uint64_t seed, iid, traj;
-  __device__ void fill(uint64_t seed_, uint64_t iid_, uint64_t traj_, uint64_t first_draw) {
+  int base;
+  __device__ void fill(uint64_t seed_, uint64_t iid_, uint64_t traj_, uint64_t first_draw, int base_, int sl) {
     seed = seed_;
     iid = iid_;
     traj = traj_;
+    base = base_;
     B0 = first_draw >> 2;
-    const Philox4 r = philox4x64_10(traj, B0 + (threadIdx.x & (kWave - 1)), 0, 0, seed, iid);
+    const Philox4 r = philox4x64_10(traj, B0 + sl, 0, 0, seed, iid);
     w0 = r.w[0];
     w1 = r.w[1];
     w2 = r.w[2];
@@ -240,10 +267,10 @@ struct DrawCache {
   }
   __device__ double operator()(uint64_t d) const {
     const uint64_t rel = (d >> 2) - B0;
-    if (rel >= static_cast<uint64_t>(kWave)) return draw_uniform(seed, iid, traj, d);
+    if (rel >= static_cast<uint64_t>(SEG)) return draw_uniform(seed, iid, traj, d);
     const unsigned k = static_cast<unsigned>(d & 3);
     const uint64_t mine = k == 0 ? w0 : (k == 1 ? w1 : (k == 2 ? w2 : w3));
-    const int src = static_cast<int>(rel);
+    const int src = base + static_cast<int>(rel);
     const uint32_t lo = __shfl(static_cast<uint32_t>(mine & 0xffffffffu), src, kWave);
     const uint32_t hi = __shfl(static_cast<uint32_t>(mine >> 32), src, kWave);
     return uniform_open01((static_cast<uint64_t>(hi) << 32) | lo);
@@ -257,8 +284,10 @@ template <int NP, class T>
 __device__ void finish_crossing(const StepArgs& a, int g, int t, int64_t jloc, TileCols<NP, T>* S,
                                 double* s_r, int* s_m, int* s_cnt, int* s_net, double* s_p,
                                 int* s_kind) {
-  constexpr int PL = (NP + kWave - 1) / kWave;
-  const int lane = threadIdx.x & (kWave - 1);
+  constexpr int SEG = (NP < kWave) ? NP : kWave;
+  constexpr int PL = NP / SEG;
+  const int lane = threadIdx.x & (SEG - 1);                    // lane within the segment
+  const int base = (threadIdx.x & (kWave - 1)) & ~(SEG - 1);   // first lane of the segment
   const double dt = a.dt;
   const uint64_t traj = a.traj0 + static_cast<uint64_t>(jloc);   // Philox counter word 0
   const double* Gam = a.Gamma + static_cast<size_t>(g) * NP;
@@ -266,7 +295,7 @@ __device__ void finish_crossing(const StepArgs& a, int g, int t, int64_t jloc, T
   double sr[PL], si[PL], G[PL], up[PL];
 #pragma unroll
   for (int j = 0; j < PL; ++j) {
-    const int x = lane + kWave * j;
+    const int x = lane + SEG * j;
     const bool in = x < NP;
     G[j] = in ? Gam[x] : 0.0;
     up[j] = in ? Eh[x] : 0.0;
@@ -283,19 +312,19 @@ __device__ void finish_crossing(const StepArgs& a, int g, int t, int64_t jloc, T
   double nu0 = 0.0;
 #pragma unroll
   for (int j = 0; j < PL; ++j) nu0 += sr[j] * sr[j] + si[j] * si[j];
-  nu0 = wave_sum(nu0);
+  nu0 = seg_sum<SEG>(nu0);
   if (nu0 > r) {
     // no crossing after all (the state-precision test was within rounding): S stays
     double pg = 0.0;
 #pragma unroll
     for (int j = 0; j < PL; ++j)
-      if (lane + kWave * j < gsz) pg += sr[j] * sr[j] + si[j] * si[j];
-    pg = wave_sum(pg);
+      if (lane + SEG * j < gsz) pg += sr[j] * sr[j] + si[j] * si[j];
+    pg = seg_sum<SEG>(pg);
     if (lane == 0) s_p[t] = pg / nu0;
     return;
   }
-  DrawCache draw;
-  draw.fill(a.seed, a.iid, traj, 3ull * m + 1);
+  DrawCache<SEG> draw;
+  draw.fill(a.seed, a.iid, traj, 3ull * m + 1, base, lane);
   // amplitudes at the start of the step's decay: undo the fused e^{-G dt / 2}
   double cr[PL], ci[PL];
 #pragma unroll
@@ -315,7 +344,7 @@ __device__ void finish_crossing(const StepArgs& a, int g, int t, int64_t jloc, T
         h[j] = exp(-0.5 * G[j] * rem);
         part += (cr[j] * cr[j] + ci[j] * ci[j]) * (h[j] * h[j]);
       }
-      const double nu_end = wave_sum(part);
+      const double nu_end = seg_sum<SEG>(part);
       if (nu_end > r) {
 #pragma unroll
         for (int j = 0; j < PL; ++j) {
@@ -342,8 +371,8 @@ __device__ void finish_crossing(const StepArgs& a, int g, int t, int64_t jloc, T
         s0 += e;
         s1 += G[j] * e;
       }
-      s0 = wave_sum(s0);
-      s1 = wave_sum(s1);
+      s0 = seg_sum<SEG>(s0);
+      s1 = seg_sum<SEG>(s1);
       const double f = log(s0) - logr;
       const double fp = -s1 / s0;
       if (fp == 0.0) {
@@ -378,17 +407,17 @@ __device__ void finish_crossing(const StepArgs& a, int g, int t, int64_t jloc, T
       double tot = 0.0;
 #pragma unroll
       for (int j = 0; j < PL; ++j) tot += wq[j];
-      tot = wave_sum(tot);
+      tot = seg_sum<SEG>(tot);
       const double thr = u1 * tot;
       int lastpos = -1;
 #pragma unroll
       for (int j = 0; j < PL; ++j) {
-        const double cum = wave_inclusive_scan(wq[j]) + carry;
-        carry = __shfl(cum, kWave - 1, kWave);
-        const uint64_t hit = __ballot(cum > thr);
-        if (b < 0 && hit) b = first_set_lane(hit) + kWave * j;
-        const uint64_t pos = __ballot(wq[j] > 0.0);
-        if (pos) lastpos = last_set_lane(pos) + kWave * j;
+        const double cum = seg_scan<SEG>(wq[j], lane) + carry;
+        carry = __shfl(cum, base + SEG - 1, kWave);
+        const uint64_t hit = seg_ballot<SEG>(cum > thr, base);
+        if (b < 0 && hit) b = first_set_lane(hit) + SEG * j;
+        const uint64_t pos = seg_ballot<SEG>(wq[j] > 0.0, base);
+        if (pos) lastpos = last_set_lane(pos) + SEG * j;
       }
       if (b < 0) b = lastpos;
     }
@@ -415,34 +444,34 @@ __device__ void finish_crossing(const StepArgs& a, int g, int t, int64_t jloc, T
         rlo = c4[1];
         rdg = c4[2];
       }
-      const double cum_i = wave_inclusive_scan(rs);
-      const double tot = __shfl(cum_i, kWave - 1, kWave);
+      const double cum_i = seg_scan<SEG>(rs, lane);
+      const double tot = __shfl(cum_i, base + SEG - 1, kWave);
       const double thr = u2 * tot;
-      const uint64_t hit_i = __ballot(cum_i > thr && lane < a.nq);
-      const uint64_t pos_i = __ballot(rs > 0.0);
+      const uint64_t hit_i = seg_ballot<SEG>(cum_i > thr && lane < a.nq, base);
+      const uint64_t pos_i = seg_ballot<SEG>(rs > 0.0, base);
       qi = hit_i ? first_set_lane(hit_i) : last_set_lane(pos_i);
       if (qi < 0) qi = 0;
-      const double before = (qi > 0) ? __shfl(cum_i, qi - 1, kWave) : 0.0;
-      const double lo_q = __shfl(rlo, qi, kWave), dg_q = __shfl(rdg, qi, kWave);
+      const double before = (qi > 0) ? __shfl(cum_i, base + qi - 1, kWave) : 0.0;
+      const double lo_q = __shfl(rlo, base + qi, kWave), dg_q = __shfl(rdg, base + qi, kWave);
       const double rel = thr - before;
       if (!(rel >= lo_q && rel < lo_q + dg_q)) {
         const double* row = a.R + ((static_cast<size_t>(g) * a.nq + qi) * NP + b) * NP;
         double v[PL];
 #pragma unroll
         for (int j = 0; j < PL; ++j) {
-          const int x = lane + kWave * j;
+          const int x = lane + SEG * j;
           v[j] = (x < NP) ? row[x] : 0.0;
         }
         double carry = before;
         int hit = -1, lastpos = -1;
 #pragma unroll
         for (int j = 0; j < PL; ++j) {
-          const double cum = wave_inclusive_scan(v[j]) + carry;
-          carry = __shfl(cum, kWave - 1, kWave);
-          const uint64_t h = __ballot(cum > thr);
-          if (hit < 0 && h) hit = first_set_lane(h) + kWave * j;
-          const uint64_t pz = __ballot(v[j] > 0.0);
-          if (pz) lastpos = last_set_lane(pz) + kWave * j;
+          const double cum = seg_scan<SEG>(v[j], lane) + carry;
+          carry = __shfl(cum, base + SEG - 1, kWave);
+          const uint64_t h = seg_ballot<SEG>(cum > thr, base);
+          if (hit < 0 && h) hit = first_set_lane(h) + SEG * j;
+          const uint64_t pz = seg_ballot<SEG>(v[j] > 0.0, base);
+          if (pz) lastpos = last_set_lane(pz) + SEG * j;
         }
         ta = (hit >= 0) ? hit : (lastpos >= 0 ? lastpos : b);
       }
@@ -455,7 +484,7 @@ __device__ void finish_crossing(const StepArgs& a, int g, int t, int64_t jloc, T
       const double inv = 1.0 / sqrt(pr * pr + pim * pim);
 #pragma unroll
       for (int j = 0; j < PL; ++j) {
-        const int x = lane + kWave * j;
+        const int x = lane + SEG * j;
         cr[j] = (x == ta) ? pr * inv : 0.0;
         ci[j] = (x == ta) ? pim * inv : 0.0;
       }
@@ -467,7 +496,7 @@ __device__ void finish_crossing(const StepArgs& a, int g, int t, int64_t jloc, T
       const double* zd = a.zdiag + (static_cast<size_t>(g) * a.nq + qi) * NP;
 #pragma unroll
       for (int j = 0; j < PL; ++j) {
-        const int x = lane + kWave * j;
+        const int x = lane + SEG * j;
         const double z = (x < NP) ? zd[x] : 0.0;
         cr[j] *= z;
         ci[j] *= z;
@@ -477,7 +506,7 @@ __device__ void finish_crossing(const StepArgs& a, int g, int t, int64_t jloc, T
     double nrm = 0.0;
 #pragma unroll
     for (int j = 0; j < PL; ++j) nrm += cr[j] * cr[j] + ci[j] * ci[j];
-    nrm = wave_sum(nrm);
+    nrm = seg_sum<SEG>(nrm);
     const double inv = 1.0 / sqrt(nrm);
 #pragma unroll
     for (int j = 0; j < PL; ++j) {
@@ -504,7 +533,7 @@ __device__ void finish_crossing(const StepArgs& a, int g, int t, int64_t jloc, T
   double pg = 0.0, pt = 0.0;
 #pragma unroll
   for (int j = 0; j < PL; ++j) {
-    const int x = lane + kWave * j;
+    const int x = lane + SEG * j;
     const double w2 = cr[j] * cr[j] + ci[j] * ci[j];
     pt += w2;
     if (x < gsz) pg += w2;
@@ -513,8 +542,8 @@ __device__ void finish_crossing(const StepArgs& a, int g, int t, int64_t jloc, T
       amp<NP, T>(S, t, 1, x) = static_cast<T>(ci[j]);
     }
   }
-  pg = wave_sum(pg);
-  pt = wave_sum(pt);
+  pg = seg_sum<SEG>(pg);
+  pt = seg_sum<SEG>(pt);
   if (lane == 0) {
     s_p[t] = pg / pt;
     s_r[t] = r;
@@ -852,9 +881,18 @@ __device__ void run_tile(const StepArgs& a, int64_t tile, TileShared<NP, TQ, typ
     }
     __syncthreads();
     const int ncross = __builtin_amdgcn_readfirstlane(s_nlist);
-    for (int e = wave; e < ncross; e += 4) {
-      const int t = s_list[e];
-      finish_crossing<NP, T>(a, g, t, tb + t, S, s_r, s_m, s_cnt, s_net, s_p, s_kind);
+    {
+      // 64 / SEG crossings per wavefront, one per segment of SEG lanes
+      constexpr int SEG = (NP < kWave) ? NP : kWave;
+      constexpr int NSEG = kWave / SEG;
+      const int seg = (tid & (kWave - 1)) / SEG;
+      for (int e0 = wave * NSEG; e0 < ncross; e0 += 4 * NSEG) {
+        const int e = e0 + seg;
+        if (e < ncross) {
+          const int t = s_list[e];
+          finish_crossing<NP, T>(a, g, t, tb + t, S, s_r, s_m, s_cnt, s_net, s_p, s_kind);
+        }
+      }
     }
     __syncthreads();
     // column tiles whose amplitudes the handler rewrote
