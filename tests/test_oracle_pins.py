@@ -458,3 +458,30 @@ def test_polar_completion_is_orthogonal_and_agrees_on_kept_directions():
     # SVD happens to give their vectors: -M has the same subspaces, so the same completion
     P3, _ = spectrum.polar(-M)
     np.testing.assert_allclose(P3 @ Wm[:, n - 1], lost, atol=1e-9)
+
+
+def test_gradient_oracle_two_level_closed_form():
+    """Central differences of the final ground-state population against the closed form
+    of a frozen two-level relaxation: P = 1 - Peq (1 - e^{-kappa t}), kappa = g(2A) + g(-2A)
+    proportional to eta, Peq = 1 / (1 + e^{2A/T}).  d/deta, the sum over the A controls
+    (a uniform shift of A), and d/dB = 0 (no field or coupling terms)."""
+    from oracle import gradient
+    A, t = 0.3, 150.0
+    inst = W.two_level_fixed(A=A, t_f=t, n_grid=41, eta=2e-3)
+    g = gradient.fd_gradient(inst, h=1e-5)
+
+    def closed(A_, eta_):
+        gp = model.gamma_ohmic(2 * A_, eta_, inst.omega_c, inst.T)
+        gm = model.gamma_ohmic(-2 * A_, eta_, inst.omega_c, inst.T)
+        peq = 1.0 / (1.0 + np.exp(2 * A_ / inst.T))
+        return 1.0 - peq * (1.0 - np.exp(-(gp + gm) * t))
+
+    gp = model.gamma_ohmic(2 * A, inst.eta, inst.omega_c, inst.T)
+    gm = model.gamma_ohmic(-2 * A, inst.eta, inst.omega_c, inst.T)
+    kappa, peq = gp + gm, 1.0 / (1.0 + np.exp(2 * A / inst.T))
+    d_eta = -peq * t * np.exp(-kappa * t) * kappa / inst.eta        # kappa is linear in eta
+    assert abs(g["deta"] - d_eta) <= 1e-6 * abs(d_eta)
+    hA = 1e-6
+    d_A = (closed(A + hA, inst.eta) - closed(A - hA, inst.eta)) / (2 * hA)
+    assert abs(g["dA"].sum() - d_A) <= 1e-5 * abs(d_A)
+    np.testing.assert_allclose(g["dB"], 0.0, atol=1e-12)
