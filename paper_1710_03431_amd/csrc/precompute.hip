@@ -214,7 +214,8 @@ __global__ __launch_bounds__(kEigThreads) void k_canon(const double* __restrict_
                                                        const double* __restrict__ Eraw, int N, int ncols, int n,
                                                        int NP, double tol, int g0, double* __restrict__ Vout,
                                                        double* __restrict__ Etab, int* __restrict__ gstab,
-                                                       double* __restrict__ ws, int* __restrict__ status) {
+                                                       double* __restrict__ ws, int* __restrict__ status,
+                                                       const double* __restrict__ Gfull) {
   __shared__ EigShared sh;
   __shared__ double s_E[kEigMaxN];
   __shared__ int s_cs[kEigMaxN + 1];
@@ -248,15 +249,22 @@ __global__ __launch_bounds__(kEigThreads) void k_canon(const double* __restrict_
   for (int q = 0; q < ncl; ++q) {
     const int a0 = s_cs[q], a1 = s_cs[q + 1], cs = a1 - a0;
     if (cs < 2) continue;
-    // G[i][j] = sum_x x V[a0+i][x] V[a0+j][x]
-    for (int p = wave; p < cs * cs; p += kEigThreads / kWave) {
-      const int i = p / cs, j = p - i * cs;
-      const double* vi = V + static_cast<size_t>(a0 + i) * N;
-      const double* vj = V + static_cast<size_t>(a0 + j) * N;
-      double acc = 0.0;
-      for (int x = lane; x < N; x += kWave) acc += static_cast<double>(x) * vi[x] * vj[x];
-      acc = wave_sum(acc);
-      if (lane == 0) G[i * cs + j] = acc;
+    // G[i][j] = sum_x x V[a0+i][x] V[a0+j][x] (precomputed for all ncols levels when Gfull is given)
+    if (Gfull) {
+      for (int p = tid; p < cs * cs; p += blockDim.x) {
+        const int i = p / cs, j = p - i * cs;
+        G[p] = Gfull[(static_cast<size_t>(c) * ncols + a0 + i) * ncols + a0 + j];
+      }
+    } else {
+      for (int p = wave; p < cs * cs; p += kEigThreads / kWave) {
+        const int i = p / cs, j = p - i * cs;
+        const double* vi = V + static_cast<size_t>(a0 + i) * N;
+        const double* vj = V + static_cast<size_t>(a0 + j) * N;
+        double acc = 0.0;
+        for (int x = lane; x < N; x += kWave) acc += static_cast<double>(x) * vi[x] * vj[x];
+        acc = wave_sum(acc);
+        if (lane == 0) G[i * cs + j] = acc;
+      }
     }
     __syncthreads();
     wg_tridiagonalize(G, cs, cs, sh);
@@ -314,7 +322,7 @@ __global__ __launch_bounds__(kEigThreads) void k_canon(const double* __restrict_
 
 // C[b][i][j] (+)= sum_x w(x) A[i][x] B[j][x] for rows i < ra, j < rb: 64x64 tile
 // per workgroup, x staged through LDS in chunks of 32, 16x16x4 FP64 MFMAs.
-// wmode 0: w = 1; 1: w = sz of qubit (bz % nq) (operands of batch bz / nq).
+// wmode 0: w = 1; 1: w = sz of qubit (bz % nq) (operands of batch bz / nq); 2: w = x.
 // sub_eye: subtract the identity (stores O - I).
 struct GemmArgs {
   const double* A;
@@ -352,6 +360,7 @@ __global__ __launch_bounds__(256) void k_gemm_f64(GemmArgs p) {
       const int r = f >> 5, k = f & 31, x = x0 + k;
       double w = 1.0;
       if (p.wmode == 1) w = ((x >> qubit) & 1) ? -1.0 : 1.0;
+      else if (p.wmode == 2) w = static_cast<double>(x);
       As[r][k] = (i0 + r < p.ra && x < xend) ? w * A[static_cast<size_t>(i0 + r) * p.lda + x] : 0.0;
       Bs[r][k] = (j0 + r < p.rb && x < xend) ? B[static_cast<size_t>(j0 + r) * p.ldb + x] : 0.0;
     }
@@ -695,7 +704,9 @@ __global__ void k_random_block(double* X, int64_t count) {
 // One workgroup, KB x KB symmetric S (row-major, symmetrised here):
 //   mode 0 (Rayleigh-Ritz): C = eigenvectors of S as columns, ascending; theta.
 //   mode 1 (orthonormalisation of a Gram matrix): with D = diag(S)^(1/2) and
-//     D^-1 S D^-1 = U L U^T, C = D^-1 U L^-1/2 so that X C has orthonormal rows.
+//     D^-1 S D^-1 = U L U^T, C = D^-1 U L^-1/2 so that X C has orthonormal rows;
+//   mode 2: the same by Cholesky, D^-1 S D^-1 = L L^T and C = D^-1 L^-T, with
+//     mode 1 as the fallback for a small pivot.
 // ws: 2 KB^2 doubles.  status bit 1: eigensolver failed, bit 2: non-finite input.
 __global__ __launch_bounds__(kEigThreads) void k_small_eig(const double* __restrict__ S, int KB, int mode,
                                                            double* __restrict__ C, double* __restrict__ theta,
@@ -706,13 +717,60 @@ __global__ __launch_bounds__(kEigThreads) void k_small_eig(const double* __restr
   double* A = ws;
   double* Z = ws + static_cast<size_t>(KB) * KB;
   for (int a = threadIdx.x; a < KB; a += blockDim.x)
-    s_dinv[a] = (mode == 1) ? 1.0 / sqrt(fmax(S[a * KB + a], 1e-300)) : 1.0;
+    s_dinv[a] = (mode >= 1) ? 1.0 / sqrt(fmax(S[a * KB + a], 1e-300)) : 1.0;
   __syncthreads();
   for (int f = threadIdx.x; f < KB * KB; f += blockDim.x) {
     const int i = f / KB, j = f - i * KB;
     A[f] = 0.5 * (S[f] + S[j * KB + i]) * s_dinv[i] * s_dinv[j];
   }
   __syncthreads();
+  if (mode == 2) {
+    // Cholesky A = L L^T of the column-scaled Gram matrix; C = D^-1 L^-T.  Falls back
+    // to the eigen route (mode 1) when a pivot is small (ill-conditioned block).
+    bool okc = true;
+    for (int k = 0; k < KB; ++k) {
+      const double piv = A[k * KB + k];
+      if (!(piv > 1e-10)) {
+        okc = false;
+        break;
+      }
+      const double lkk = sqrt(piv);
+      __syncthreads();
+      for (int i = k + threadIdx.x; i < KB; i += blockDim.x) A[i * KB + k] = (i == k) ? lkk : A[i * KB + k] / lkk;
+      __syncthreads();
+      const int m = KB - k - 1;
+      for (int f = threadIdx.x; f < m * m; f += blockDim.x) {
+        const int i = k + 1 + f / m, j = k + 1 + f % m;
+        if (j <= i) A[i * KB + j] -= A[i * KB + k] * A[j * KB + k];
+      }
+      __syncthreads();
+    }
+    if (okc) {
+      // L^-1 by forward substitution, one column per thread
+      for (int j = threadIdx.x; j < KB; j += blockDim.x)
+        for (int i = 0; i < KB; ++i) {
+          if (i < j) {
+            Z[i * KB + j] = 0.0;
+            continue;
+          }
+          double v = (i == j) ? 1.0 : 0.0;
+          for (int k = j; k < i; ++k) v -= A[i * KB + k] * Z[k * KB + j];
+          Z[i * KB + j] = v / A[i * KB + i];
+        }
+      __syncthreads();
+      for (int f = threadIdx.x; f < KB * KB; f += blockDim.x) {
+        const int i = f / KB, j = f - i * KB;
+        C[f] = s_dinv[i] * Z[j * KB + i];
+      }
+      return;
+    }
+    __syncthreads();
+    for (int f = threadIdx.x; f < KB * KB; f += blockDim.x) {
+      const int i = f / KB, j = f - i * KB;
+      A[f] = 0.5 * (S[f] + S[j * KB + i]) * s_dinv[i] * s_dinv[j];
+    }
+    __syncthreads();
+  }
   wg_tridiagonalize(A, KB, KB, sh);
   const bool ok = wg_band_qr(Z, KB, KB, sh);
   wg_rank_ascending(sh.d, KB, s_perm);
@@ -727,13 +785,13 @@ __global__ __launch_bounds__(kEigThreads) void k_small_eig(const double* __restr
   // a failed step reports and writes the identity, so the block stays finite until
   // the host sees the status; Gram eigenvalues are floored at 1e-15 of the largest
   // (directions lost to rounding come back rescaled, the next pass normalises them)
-  const bool bad = !ok || !finite || (mode == 1 && !(lmax > 0.0));
+  const bool bad = !ok || !finite || (mode >= 1 && !(lmax > 0.0));
   const double floor_l = 1e-15 * lmax;
   for (int f = threadIdx.x; f < KB * KB; f += blockDim.x) {
     const int i = f / KB, j = f - i * KB;   // C[i][j] = component i of vector j
     const double zij = Z[static_cast<size_t>(s_perm[j]) * KB + i];
     if (bad) C[f] = (i == j) ? 1.0 : 0.0;
-    else C[f] = (mode == 1) ? s_dinv[i] * zij / sqrt(fmax(sh.d[s_perm[j]], floor_l)) : zij;
+    else C[f] = (mode >= 1) ? s_dinv[i] * zij / sqrt(fmax(sh.d[s_perm[j]], floor_l)) : zij;
   }
   if (mode == 0)
     for (int a = threadIdx.x; a < KB; a += blockDim.x) theta[a] = sh.d[s_perm[a]];
@@ -805,7 +863,7 @@ aqt_status chfsi_orth(aqt_ctx* ctx, Chfsi& c, double* in) {
   for (int pass = 0; pass < 2; ++pass) {
     aqt_status st = chfsi_gram(ctx, c, src, src);
     if (st != AQT_OK) return st;
-    hipLaunchKernelGGL(k_small_eig, dim3(1), dim3(kEigThreads), 0, ctx->stream, c.S.as<double>(), c.KB, 1,
+    hipLaunchKernelGGL(k_small_eig, dim3(1), dim3(kEigThreads), 0, ctx->stream, c.S.as<double>(), c.KB, 2,
                        c.C.as<double>(), c.theta.as<double>(), c.ws.as<double>(), c.status.as<int>());
     AQT_HIP(ctx, hipGetLastError());
     double* dst = (pass == 0) ? c.Y2.as<double>() : c.X.as<double>();
@@ -1034,7 +1092,7 @@ aqt_status precompute_tables(aqt_ctx* ctx, int M, int n, double tol, int method)
       AQT_HIP(ctx, hipGetLastError());
       hipLaunchKernelGGL(k_canon, dim3(cnt), dim3(kEigThreads), 0, st, Z.as<double>(), perm.as<int>(),
                          Eraw.as<double>(), N, ncols, n, NP, tol, g0, Vc.as<double>(), ctx->E.as<double>(),
-                         ctx->gs.as<int>(), cws.as<double>(), status.as<int>());
+                         ctx->gs.as<int>(), cws.as<double>(), status.as<int>(), nullptr);
       AQT_HIP(ctx, hipGetLastError());
     } else {
       AQT_HIP(ctx, hipMemsetAsync(status.p, 0, cnt * 4, st));
@@ -1047,9 +1105,21 @@ aqt_status precompute_tables(aqt_ctx* ctx, int M, int n, double tol, int method)
         aqt_status s = chfsi_solve(ctx, ch, eZ.as<double>(), Ag[g], Bg[g], nconv, 1e-12,
                                    "at grid point " + std::to_string(g));
         if (s != AQT_OK) return s;
+        {
+          // Gram matrix of diag(x) over the ncols Ritz vectors (cluster rotations), split over x
+          const int kspan = (N + ch.ksplit - 1) / ch.ksplit;
+          GemmArgs ga{ch.X.as<double>(), ch.X.as<double>(), ch.part.as<double>(), 0, 0,
+                      static_cast<int64_t>(ncols) * ncols, ncols, ncols, N, N, N, ncols, 2, nq, 0, ch.ksplit, kspan};
+          aqt_status s2 = launch_gemm(ctx, ga, ch.ksplit);
+          if (s2 != AQT_OK) return s2;
+          hipLaunchKernelGGL(k_splitk_reduce, dim3(nblk(static_cast<int64_t>(ncols) * ncols)), dim3(256), 0, st,
+                             ch.part.as<double>(), ch.ksplit, ncols, ncols, 1, ch.S.as<double>(), 0, ncols, 0);
+          AQT_HIP(ctx, hipGetLastError());
+        }
         hipLaunchKernelGGL(k_canon, dim3(1), dim3(kEigThreads), 0, st, ch.X.as<double>(), ident.as<int>(),
                            ch.theta.as<double>(), N, ncols, n, NP, tol, g, Vc.as<double>() + c * Vstride,
-                           ctx->E.as<double>(), ctx->gs.as<int>(), cws.as<double>(), status.as<int>() + c);
+                           ctx->E.as<double>(), ctx->gs.as<int>(), cws.as<double>(), status.as<int>() + c,
+                           ch.S.as<double>());
         AQT_HIP(ctx, hipGetLastError());
       }
     }
