@@ -374,6 +374,9 @@ __device__ void finish_crossing(const StepArgs& a, int g, int t, int64_t jloc, T
       s0 = seg_sum<SEG>(s0);
       s1 = seg_sum<SEG>(s1);
       const double f = log(s0) - logr;
+      // converged once the log-ratio is at rounding level: further steps only follow
+      // the noise of the sums (for a slowly decaying level that noise exceeds 1e-15 dt)
+      if (fabs(f) <= 8.0 * 2.220446049250313e-16) break;
       const double fp = -s1 / s0;
       if (fp == 0.0) {
         tau = rem;
