@@ -2,7 +2,7 @@
 // instantaneous eigenbasis (Sec. IV waiting-time procedure; App. C validity;
 // jump-type law App. B eq. Pi(t); jump update Sec. III eq. jump).
 //
-// One workgroup (4 waves) owns a tile of TT = 8*TQ trajectories for the whole
+// One workgroup (WV = 4 or 8 wavefronts) owns a tile of TT = 8*TQ trajectories for the whole
 // anneal; their amplitudes stay in LDS.  Per grid step g (from s_{g-1} to s_g):
 //   1. C <- O_g C on MFMA, written as C + Delta_g C (identity split) so the
 //      accumulator starts from C.  Real Delta times complex C is one real GEMM
@@ -199,6 +199,15 @@ constexpr int prefetch_depth() {
 // (part 1) part of local trajectory t = 8 q + (c & 7).  Columns are padded to
 // NP + kPad elements so the 16 columns of an MFMA operand fall in distinct banks.
 constexpr int kPad = 4;   // >= 4: the B read-ahead touches padding rows NP..NP+3
+// Wavefronts per workgroup.  Eight (two per SIMD) let one wave's LDS and load waits
+// hide behind the other's MFMAs where each wave still has a large share of the
+// GEMM (>= 128 levels, FP32/FP64 and the batched kernel); small tiles and the
+// register-heavy BF16 path at 256 levels keep four.
+template <int NP, class Mode>
+constexpr int waves_for() {
+  return (NP >= 128 && Mode::KC == 4) ? 8 : 4;
+}
+constexpr int kBatchWaves = 8;
 template <int NP, class T>
 using TileCols = T[16][NP + kPad];
 
@@ -557,16 +566,16 @@ __device__ void finish_crossing(const StepArgs& a, int g, int t, int64_t jloc, T
 }
 
 // --------------------------------------------------------------- kernel ----
-// Work split of the overlap GEMM over the four waves: with four or more row
-// tiles each wave owns the row tiles rt = wave (mod 4) for every column tile
+// Work split of the overlap GEMM over the WV wavefronts: with WV or more row
+// tiles each wave owns the row tiles rt = wave (mod WV) for every column tile
 // (one A fragment feeds TQ MFMAs); with fewer, waves take (row tile, column
 // tile) pairs.  The k loop is outermost so each wave keeps UPW*QG independent
 // accumulator chains in flight.
-template <int NP, int TQ, class T>
+template <int NP, int TQ, class T, int WV>
 struct TileShared {
   static constexpr int NRT = NP / 16;
   static constexpr int TT = 8 * TQ;
-  static constexpr int NSLOT = (NRT >= 4) ? 4 : NRT;   // partial squared norms per trajectory
+  static constexpr int NSLOT = (NRT >= WV) ? WV : NRT;   // partial squared norms per trajectory
   TileCols<NP, T> S[TQ];
   T nu[NSLOT][TT];
   double r[TT];
@@ -577,21 +586,21 @@ struct TileShared {
   int kind[3];
 };
 
-template <int NP, int TQ, class Mode>
-__device__ void run_tile(const StepArgs& a, int64_t tile, TileShared<NP, TQ, typename Mode::T>& sh) {
+template <int NP, int TQ, class Mode, int WV>
+__device__ void run_tile(const StepArgs& a, int64_t tile, TileShared<NP, TQ, typename Mode::T, WV>& sh) {
   using T = typename Mode::T;
   using Acc = typename Mode::Acc;
   constexpr int NRT = NP / 16;
   constexpr int TT = 8 * TQ;
-  constexpr int QG = (NRT >= 4) ? TQ : 1;          // column tiles per work unit
+  constexpr int QG = (NRT >= WV) ? TQ : 1;         // column tiles per work unit
   constexpr int NUNITS = NRT * (TQ / QG);
-  constexpr int UPW = (NUNITS + 3) / 4;            // units per wave
+  constexpr int UPW = (NUNITS + WV - 1) / WV;      // units per wave
   constexpr int NKC = NP / Mode::KC;
   static_assert(TT <= kWave, "tile must fit one wavefront for the decision pass");
 
   auto& S = sh.S;
   auto& s_nu = sh.nu;
-  constexpr int NSLOT = TileShared<NP, TQ, T>::NSLOT;
+  constexpr int NSLOT = TileShared<NP, TQ, T, WV>::NSLOT;
   double* s_r = sh.r;
   double* s_p = sh.p;
   int* s_m = sh.m;
@@ -621,17 +630,17 @@ __device__ void run_tile(const StepArgs& a, int64_t tile, TileShared<NP, TQ, typ
   bool ok_u[UPW];
 #pragma unroll
   for (int u = 0; u < UPW; ++u) {
-    const int unit = wave + 4 * u;
-    ok_u[u] = (NUNITS % 4 == 0) || unit < NUNITS;   // 4 waves per workgroup
+    const int unit = wave + WV * u;
+    ok_u[u] = (NUNITS % WV == 0) || unit < NUNITS;
     rt_u[u] = unit % NRT;
     q0_u[u] = (unit / NRT) * QG;
   }
   Acc acc[UPW][QG];
-  // with >= 4 row tiles every unit covers all column tiles (q0 = 0) and each wave
-  // keeps one norm partial per trajectory (NSLOT = 4); otherwise units are
+  // with >= WV row tiles every unit covers all column tiles (q0 = 0) and each wave
+  // keeps one norm partial per trajectory (NSLOT = WV); otherwise units are
   // (row tile, column tile) pairs and the partials are per row tile
-  constexpr bool kSharedQ = (NRT >= 4);
-  static_assert(NSLOT == (kSharedQ ? 4 : NRT), "norm slots follow the work split");
+  constexpr bool kSharedQ = (NRT >= WV);
+  static_assert(NSLOT == (kSharedQ ? WV : NRT), "norm slots follow the work split");
 #define q0(u) (kSharedQ ? 0 : q0_u[u])
   // fragment (g, row tile, k chunk) lives at ((g * NRT + rt) * NKC + k) * 64 + lane
   size_t fbase[UPW];
@@ -889,7 +898,7 @@ __device__ void run_tile(const StepArgs& a, int64_t tile, TileShared<NP, TQ, typ
       constexpr int SEG = (NP < kWave) ? NP : kWave;
       constexpr int NSEG = kWave / SEG;
       const int seg = (tid & (kWave - 1)) / SEG;
-      for (int e0 = wave * NSEG; e0 < ncross; e0 += 4 * NSEG) {
+      for (int e0 = wave * NSEG; e0 < ncross; e0 += WV * NSEG) {
         const int e = e0 + seg;
         if (e < ncross) {
           const int t = s_list[e];
@@ -943,9 +952,10 @@ __device__ void run_tile(const StepArgs& a, int64_t tile, TileShared<NP, TQ, typ
 }
 
 template <int NP, int TQ, class Mode>
-__global__ __launch_bounds__(256) void k_trajectories(StepArgs a) {
-  __shared__ TileShared<NP, TQ, typename Mode::T> sh;
-  run_tile<NP, TQ, Mode>(a, blockIdx.x, sh);
+__global__ __launch_bounds__((waves_for<NP, Mode>() * 64)) void k_trajectories(StepArgs a) {
+  constexpr int WV = waves_for<NP, Mode>();
+  __shared__ TileShared<NP, TQ, typename Mode::T, WV> sh;
+  run_tile<NP, TQ, Mode, WV>(a, blockIdx.x, sh);
 }
 
 __global__ void k_reduce_partials(const double* __restrict__ partial, int64_t tiles, int M, double K,
@@ -990,7 +1000,7 @@ __global__ void k_batch_reset(int* counter) {
 
 template <int NP, int TQ, class Mode>
 __device__ constexpr size_t tile_lds() {
-  return sizeof(TileShared<NP, TQ, typename Mode::T>);
+  return sizeof(TileShared<NP, TQ, typename Mode::T, kBatchWaves>);
 }
 
 template <int MaxNP, class Mode>
@@ -1013,7 +1023,7 @@ __device__ __forceinline__ bool try_tile(const StepArgs& a, int tile, BufT* raw)
   constexpr bool f64 = sizeof(typename Mode::T) == 8;
   if constexpr (tq_allowed(NP, TQ, f64) && (NP != 16 || Mode::KC != 32)) {
     if (a.NP == NP && a.TQ == TQ) {
-      run_tile<NP, TQ, Mode>(a, tile, *reinterpret_cast<TileShared<NP, TQ, typename Mode::T>*>(raw));
+      run_tile<NP, TQ, Mode, kBatchWaves>(a, tile, *reinterpret_cast<TileShared<NP, TQ, typename Mode::T, kBatchWaves>*>(raw));
       return true;
     }
   }
@@ -1021,7 +1031,7 @@ __device__ __forceinline__ bool try_tile(const StepArgs& a, int tile, BufT* raw)
 }
 
 template <int MaxNP, class Mode>
-__global__ __launch_bounds__(256) void k_batch(const StepArgs* __restrict__ args, const BatchItem* __restrict__ items,
+__global__ __launch_bounds__(kBatchWaves * 64) void k_batch(const StepArgs* __restrict__ args, const BatchItem* __restrict__ items,
                                               int n_items, int* counter) {
   __shared__ __align__(16) unsigned char raw[batch_lds<MaxNP, Mode>()];
   __shared__ int s_item;
@@ -1076,7 +1086,7 @@ hipError_t launch_tq(int TQ, const StepArgs& a, int64_t blocks, hipStream_t st) 
   if constexpr (tq_allowed(NP, tq, f64)) {                                                    \
     if (TQ == tq) {                                                                           \
       hipLaunchKernelGGL((k_trajectories<NP, tq, Mode>), dim3(static_cast<unsigned>(blocks)), \
-                         dim3(256), 0, st, a);                                                \
+                         dim3(waves_for<NP, Mode>() * 64), 0, st, a);                         \
       return hipGetLastError();                                                               \
     }                                                                                         \
   }
@@ -1229,7 +1239,7 @@ template <int MaxNP, class Mode>
 hipError_t enqueue_batch_kernel(const aqt_batch* b, const StepArgs* dargs, const BatchItem* items, int n_items,
                                 int* counter, int grid, hipStream_t st) {
   hipLaunchKernelGGL(k_batch_reset, dim3(1), dim3(64), 0, st, counter);
-  hipLaunchKernelGGL((k_batch<MaxNP, Mode>), dim3(grid), dim3(256), 0, st, dargs, items, n_items, counter);
+  hipLaunchKernelGGL((k_batch<MaxNP, Mode>), dim3(grid), dim3(kBatchWaves * 64), 0, st, dargs, items, n_items, counter);
   return hipGetLastError();
 }
 
