@@ -142,7 +142,9 @@ def replay_log_weight(tables, inst, paths, n_grid=None):
         C *= np.exp(-1j * T.E * dt)[:, None]
         gs = T.gs
     pop = np.abs(C) ** 2
-    return 2.0 * logs + np.log(pop[:gs].sum(axis=0)), 2.0 * logs + np.log(pop.sum(axis=0)), C
+    with np.errstate(divide="ignore"):   # log 0 = -inf: the path ends outside the ground cluster
+        logW = 2.0 * logs + np.log(pop[:gs].sum(axis=0))
+    return logW, 2.0 * logs + np.log(pop.sum(axis=0)), C
 
 
 def trajectory_gradients(inst, n_traj: int, h: float = 1e-4, which=("A", "B", "eta"),
@@ -162,6 +164,8 @@ def trajectory_gradients(inst, n_traj: int, h: float = 1e-4, which=("A", "B", "e
         im, _ = _perturbed(inst, kind, j, -1.0, h)
         lp, _, _ = replay_log_weight(spectrum.all_tables(ip), ip, res.jumps)
         lm, _, _ = replay_log_weight(spectrum.all_tables(im), im, res.jumps)
-        g[:, col] = f * (lp - lm) / (2.0 * step)
+        # a path that ends outside the ground cluster has zero weight for every theta
+        with np.errstate(invalid="ignore"):
+            g[:, col] = np.where(f > 0.0, f * (lp - lm) / (2.0 * step), 0.0)
     return {"f": f, "g": g, "params": params, "jumps": res.jumps, "replay_state": C,
             "final_state": res.final_state}
