@@ -174,6 +174,32 @@ AQT_API aqt_status aqt_get_dims(aqt_ctx* ctx, int32_t* n_grid, int32_t* n_levels
  * still holds the true number of jumps of each trajectory. */
 AQT_API aqt_status aqt_run(aqt_ctx* ctx, const aqt_run_params* params, const aqt_outputs* out);
 
+/* ---- Gradient ------------------------------------------------------------------------
+ * Estimate of d E[P_GS(1)] / d theta, theta = (A_ctrl[0..m-1], B_ctrl[0..m-1], eta):
+ * the derivative of the trajectory average of the final ground-cluster population
+ * with respect to the schedule control points of aqt_set_schedule (m of each) and
+ * the coupling eta of aqt_set_bath.  Paths of the waiting-time procedure (Sec. IV)
+ * have density |psi~|^2 over a parameter-free measure on jump times and channels
+ * (Sec. III eqs. Heff and jump, App. B), so each trajectory contributes
+ * g = 2 Re <psi~|Pi|d psi~> / |psi~|^2: a pathwise term through the no-jump
+ * propagation and basis changes plus a score-function term for the jump times and
+ * channels, evaluated by an adjoint sweep with checkpointed recomputation of the
+ * forward steps.  Eigenvector derivatives use first-order perturbation theory with
+ * the canonical in-cluster basis held fixed.
+ *   params:   as aqt_run (precision AQT_FP64 or AQT_FP32, n_traj >= 2; record_capacity
+ *             is ignored: the paths are recorded internally).  The trajectories are
+ *             the ones aqt_run draws with the same params.
+ *   value, value_se: host, mean and standard error of P_GS(1) (may be NULL).
+ *   grad, grad_se:   host [2m+1], mean estimate and its standard error (may be NULL).
+ *   per_traj: device [n_traj][2m+2] or NULL: per trajectory f (final ground-cluster
+ *             population) followed by its 2m+1 estimates.
+ * Needs tables from aqt_precompute with n_levels = 2^n_qubits (AQT_ESTATE after
+ * aqt_set_tables, AQT_EINVAL for truncated spectra); the first call after a
+ * precompute re-runs the eigensolver to add the derivative tables.  AQT_ECAPACITY if
+ * one trajectory takes more than 64 omega = 0 jumps within one step.  Synchronises. */
+AQT_API aqt_status aqt_grad_pgs(aqt_ctx* ctx, const aqt_run_params* params, double* value, double* value_se,
+                                double* grad, double* grad_se, double* per_traj);
+
 /* ---- Batched runs: many instances in one persistent launch --------------------------
  * Each context (with tables loaded) is one instance with its own run parameters and
  * output buffers.  One kernel launch runs every (instance, tile) work item from an

@@ -22,7 +22,7 @@ KIND_NAMES = ("relax", "excite", "dephase")
 
 EXPORTED = ("aqt_create", "aqt_destroy", "aqt_last_error", "aqt_version", "aqt_set_hamiltonian",
             "aqt_set_schedule", "aqt_set_bath", "aqt_precompute", "aqt_precompute_ex", "aqt_set_tables", "aqt_get_tables",
-            "aqt_get_dims", "aqt_run", "aqt_batch_create", "aqt_batch_launch", "aqt_batch_tiles",
+            "aqt_get_dims", "aqt_run", "aqt_grad_pgs", "aqt_batch_create", "aqt_batch_launch", "aqt_batch_tiles",
             "aqt_batch_last_error", "aqt_batch_destroy")
 BATCH_GRAPH, BATCH_AUTOTUNE = 1, 2
 
@@ -90,6 +90,7 @@ def load_library(path: str = LIB_PATH):
     lib.aqt_get_tables.argtypes = [ctx, dp, ip, dp, dp, dp, dp, dp, dp]
     lib.aqt_get_dims.argtypes = [ctx, ip, ip, ip]
     lib.aqt_run.argtypes = [ctx, C.POINTER(RunParams), C.POINTER(Outputs)]
+    lib.aqt_grad_pgs.argtypes = [ctx, C.POINTER(RunParams), dp, dp, dp, dp, C.c_void_p]
     lib.aqt_batch_create.argtypes = [C.POINTER(C.c_void_p), C.POINTER(C.c_void_p), C.c_int,
                                      C.POINTER(RunParams), C.POINTER(Outputs), C.c_int]
     lib.aqt_batch_launch.argtypes = [C.c_void_p]
@@ -138,6 +139,7 @@ class Engine:
             raise AqtError(st, f"aqt_create failed on device {device} (no usable HIP device?)")
         self.ctx = h
         self.n_grid = self.n_levels = self.n_qubits = None
+        self.n_ctrl = 0
 
     def close(self):
         if getattr(self, "ctx", None):
@@ -164,6 +166,7 @@ class Engine:
         A = _f64(A_ctrl)
         B = _f64(B_ctrl)
         self._check(self.lib.aqt_set_schedule(self.ctx, float(t_f), len(A), _dptr(A), _dptr(B)))
+        self.n_ctrl = len(A)
 
     def set_bath(self, eta, omega_c, T):
         self._check(self.lib.aqt_set_bath(self.ctx, float(eta), float(omega_c), float(T)))
@@ -260,6 +263,27 @@ class Engine:
         if final_state:
             res["final_state"] = res["final_state"].reshape(n_traj, self.n_levels, 2)
         return res
+
+
+    # ---------------------------------------------------------------- gradient
+    def grad_pgs(self, n_traj: int, precision="fp32", seed=0, instance_id=0, traj_offset=0, tile=0,
+                 per_trajectory=False):
+        """Gradient of E[P_GS(1)] with respect to (A controls, B controls, eta) (synchronises).
+        Returns value, value_se, grad, grad_se and, on request, per_traj [K][2m+2]."""
+        m = self.n_ctrl
+        p = _params(n_traj, precision, seed, instance_id, traj_offset, 0, tile)
+        v, vse = np.zeros(1), np.zeros(1)
+        g, gse = np.zeros(2 * m + 1), np.zeros(2 * m + 1)
+        pt = None
+        if per_trajectory:
+            t = self.torch
+            pt = t.zeros((n_traj, 2 * m + 2), dtype=t.float64, device=t.device("cuda", self.device))
+        self._check(self.lib.aqt_grad_pgs(self.ctx, C.byref(p), _dptr(v), _dptr(vse), _dptr(g), _dptr(gse),
+                                          None if pt is None else pt.data_ptr()))
+        out = {"value": float(v[0]), "value_se": float(vse[0]), "grad": g, "grad_se": gse}
+        if pt is not None:
+            out["per_traj"] = pt.cpu().numpy()
+        return out
 
 
 def _params(n_traj, precision, seed, instance_id, traj_offset, record_capacity, tile):

@@ -156,12 +156,16 @@ aqt_status aqt_precompute_ex(aqt_ctx* ctx, int n_grid, int n_levels, double deg_
   aqt_status s = set_device(ctx);
   if (s != AQT_OK) return s;
   ctx->have_tables = false;
+  ctx->last_from_solver = false;
   s = aqt::precompute_tables(ctx, n_grid, n_levels, deg_tol, method);
   if (s != AQT_OK) return s;
   s = aqt::finish_tables(ctx);
   if (s != AQT_OK) return s;
   AQT_HIP(ctx, hipStreamSynchronize(ctx->stream));
   ctx->have_tables = true;
+  ctx->last_from_solver = true;
+  ctx->last_method = method;
+  ctx->last_tol = deg_tol;
   return AQT_OK;
 }
 
@@ -178,6 +182,8 @@ aqt_status aqt_set_tables(aqt_ctx* ctx, int n_grid, int n_levels, const double* 
   if (s != AQT_OK) return s;
   const int n = n_levels, NP = aqt::padded_levels(n), nq = ctx->nq;
   ctx->have_tables = false;
+  ctx->have_grad = false;
+  ctx->last_from_solver = false;
   ctx->M = n_grid;
   ctx->n = n;
   ctx->NP = NP;
@@ -252,6 +258,31 @@ aqt_status aqt_run(aqt_ctx* ctx, const aqt_run_params* p, const aqt_outputs* o) 
   aqt_status s = set_device(ctx);
   if (s != AQT_OK) return s;
   return aqt::launch_run(ctx, p, o);
+}
+
+aqt_status aqt_grad_pgs(aqt_ctx* ctx, const aqt_run_params* p, double* value, double* value_se, double* grad,
+                        double* grad_se, double* per_traj) {
+  if (!ctx) return AQT_EINVAL;
+  if (!p) return ctx->fail(AQT_EINVAL, "params are required");
+  if (!ctx->have_tables) return ctx->fail(AQT_ESTATE, "precompute must come first");
+  if (!ctx->last_from_solver)
+    return ctx->fail(AQT_ESTATE, "the gradient needs tables from aqt_precompute (eigenvectors), not aqt_set_tables");
+  if (ctx->n != (1 << ctx->nq))
+    return ctx->fail(AQT_EINVAL, "the gradient needs the full spectrum (n_levels = 2^n_qubits)");
+  if (p->n_traj < 2) return ctx->fail(AQT_EINVAL, "n_traj must be >= 2");
+  if (p->precision != AQT_FP64 && p->precision != AQT_FP32)
+    return ctx->fail(AQT_EINVAL, "the gradient runs in AQT_FP64 or AQT_FP32");
+  aqt_status s = set_device(ctx);
+  if (s != AQT_OK) return s;
+  if (!ctx->have_grad) {
+    ctx->have_tables = false;
+    s = aqt::precompute_tables(ctx, ctx->M, ctx->n, ctx->last_tol, ctx->last_method, true);
+    if (s != AQT_OK) return s;
+    if ((s = aqt::finish_tables(ctx)) != AQT_OK) return s;
+    AQT_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    ctx->have_tables = true;
+  }
+  return aqt::launch_grad(ctx, p, value, value_se, grad, grad_se, per_traj);
 }
 
 }  // extern "C"

@@ -43,6 +43,18 @@ struct aqt_ctx {
   aqt::DevBuf dre, dim; // [M][NP] FP64 exp(-i e dt - Gamma dt / 2)
   aqt::DevBuf leak;     // [M]
 
+  // ---- derivative tables of the gradient (direction 0 = A(s_g), 1 = B(s_g)); full spectrum only
+  bool have_grad = false;
+  int last_method = 0;      // eigensolver and cluster tolerance of the last aqt_precompute
+  double last_tol = 0.0;
+  bool last_from_solver = false;   // tables came from aqt_precompute (not aqt_set_tables)
+  aqt::DevBuf Xd;       // [M][2][NP][NP] X[x][y]: dv_y = sum_x v_x X[x][y]
+  aqt::DevBuf dE;       // [M][2][NP]
+  aqt::DevBuf dGam;     // [M][2][NP]
+  aqt::DevBuf dzd;      // [M][2][nq][NP] d z_i[x][x]
+  aqt::DevBuf dll;      // [M][2][nq][NP(b)][NP(a)] d log |l_i,ab|
+  aqt::DevBuf dcin;     // [2][NP] derivative of the initial state through grid 0
+
   // ---- per-precision packed operands of the step kernel (built lazily)
   int packed_for = -1;      // aqt_precision the packs below hold, -1 = none
   aqt::DevBuf pk_a, pk_b;   // Delta fragments (hi / lo for BF16)
@@ -74,7 +86,11 @@ aqt_status pack_for_precision(aqt_ctx* ctx, int precision);
 aqt_status launch_run(aqt_ctx* ctx, const aqt_run_params* p, const aqt_outputs* o);
 
 // precompute.hip: GPU eigensystem and tables.
-aqt_status precompute_tables(aqt_ctx* ctx, int n_grid, int n_levels, double deg_tol, int method);
+aqt_status precompute_tables(aqt_ctx* ctx, int n_grid, int n_levels, double deg_tol, int method, bool grad = false);
+
+// grad.hip: adjoint gradient of the final ground-cluster population.
+aqt_status launch_grad(aqt_ctx* ctx, const aqt_run_params* p, double* value, double* value_se, double* grad,
+                       double* grad_se, double* per_traj);
 
 inline int padded_levels(int n) {
   int np = 16;

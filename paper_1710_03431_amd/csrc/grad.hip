@@ -1,0 +1,728 @@
+// Adjoint gradient of the trajectory average of the final ground-cluster population
+// with respect to the schedule control points and the bath coupling eta.
+//
+// A trajectory of the waiting-time procedure (Sec. IV) is a path: its jump times
+// and channels.  Paths have density |psi~|^2 with respect to a measure that does
+// not depend on the parameters (Lebesgue measure on times, counting measure on
+// channels), psi~ being the unnormalised amplitude built from the no-jump
+// propagators (Sec. III eq. Heff), the basis changes O_g and the jump operators
+// sqrt(gamma) A (Sec. III eq. jump, App. B).  So E[P_GS] is the integral over paths
+// of <psi~|Pi|psi~>, and each trajectory gives the unbiased estimate
+//
+//   g = 2 Re <psi~|Pi| d psi~> / |psi~|^2,
+//
+// the sum of a pathwise term (derivative of the normalised final population along
+// the fixed path) and a score-function term (derivative of the path density) for the
+// jump times and channels.  d psi~ is a sum over the factors F of psi~; with the
+// adjoint lambda propagated backward (lambda_before = F^H lambda_after / rho, rho the
+// forward renormalisation of that factor, lambda_final = Pi psi / |psi|^2) a factor
+// contributes 2 Re <lambda_after| dF |psi_before> / rho.  <lambda|psi> = f (the
+// trajectory's final ground-cluster population) at every point of the path.
+//
+// Factors per step g (from s_{g-1} to s_g; generator frozen at s_g) and what they give:
+//   basis change O_g = V_g^T V_{g-1}: with dV_g = V_g X_g (first-order perturbation
+//     theory; X antisymmetric), grid g collects -2 Re <lambda_A|X_g|psi_A> (just after
+//     O_g) and +2 Re <lambda_B|X_g|psi_B> (just before O_{g+1}); grid 0 acts through
+//     the initial state, 2 Re <lambda_A|V_1 dv_0> at step 1.  These are MFMA products
+//     X_g [psi_A psi_B] contracted with the adjoints.
+//   no-jump propagation exp(-i e tau - Gamma tau / 2) (diagonal): per component
+//     P_x = conj(lambda_x) psi_x is constant between a != b jumps; a step without one
+//     gives 2 dt sum de_x Im P_x - dt sum dGamma_x Re P_x.
+//   jump b -> a (a != b), operator sqrt(gamma(e_b - e_a)) z_ab |a><b|: the state
+//     collapses, so every factor of the step is single-component and contributes
+//     through f alone: 2 f d log|l_ab| per such jump and -f tau dGamma_c for each
+//     stretch spent in component c.
+//   omega = 0 operator sqrt(gamma(0)) diag(z_i): 2 Re <lambda_after| diag(dz_i) |psi_before>
+//     / |diag(z_i) psi_before| (gamma(0) cancels).
+// eta scales every rate: dGamma = Gamma / eta, d log l = 1 / (2 eta), no basis change.
+// Controls enter through A(s_g) and B(s_g) with the hat-function weights of the
+// piecewise-linear schedule.
+//
+// The forward paths come from the trajectory kernel (its jump records); one
+// workgroup owns TT trajectories for the whole sweep: a forward replay that stores
+// the state every C steps, then per segment of C steps (last first) a replay that
+// keeps every post-kick state, followed by the backward steps of that segment.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <vector>
+
+#include "common.hpp"
+#include "ctx.hpp"
+
+namespace aqt {
+namespace {
+
+constexpr int kGW = 4;              // wavefronts per workgroup
+constexpr int kGThreads = kGW * 64;
+constexpr int kMaxSeg = 64;         // steps per checkpoint segment
+constexpr int kMaxJ = 64;           // omega = 0 jumps of one trajectory within one step
+
+typedef float f4 __attribute__((ext_vector_type(4)));
+typedef double d4 __attribute__((ext_vector_type(4)));
+
+template <class T> struct Mfma;
+template <> struct Mfma<float> {
+  using acc_t = f4;
+  __device__ static acc_t zero() { return f4{0.f, 0.f, 0.f, 0.f}; }
+  __device__ static acc_t step(float a, float b, acc_t c) { return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0); }
+  // element e of lane l holds output row 4 (l / 16) + e, column l % 16
+  __device__ static int row(int lane, int e) { return 4 * (lane >> 4) + e; }
+};
+template <> struct Mfma<double> {
+  using acc_t = d4;
+  __device__ static acc_t zero() { return d4{0.0, 0.0, 0.0, 0.0}; }
+  __device__ static acc_t step(double a, double b, acc_t c) { return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0); }
+  // element e of lane l holds output row l / 16 + 4 e, column l % 16
+  __device__ static int row(int lane, int e) { return (lane >> 4) + 4 * e; }
+};
+
+struct GradArgs {
+  const double* dlt;     // [M][NP][NP] O_g - I
+  const double* cinit;   // [NP]
+  const double* E;       // [M][NP]
+  const double* Gam;     // [M][NP]
+  const double* zdiag;   // [M][nq][NP]
+  const double* dre;     // [M][NP] Re exp(-i e dt - Gamma dt / 2)
+  const double* dim;
+  const int* gs;         // [M]
+  const double* Xd;      // [M][2][NP][NP]
+  const double* dE;      // [M][2][NP]
+  const double* dGam;    // [M][2][NP]
+  const double* dzd;     // [M][2][nq][NP]
+  const double* dll;     // [M][2][nq][NP][NP]
+  const double* dcin;    // [2][NP]
+  const aqt_jump* jumps; // [K][cap]
+  const int32_t* jcount; // [K]
+  int cap;
+  void* ckpt;            // [tiles][S][NP][NC] states after steps sC
+  int* ckcur;            // [tiles][S][TT] record cursors there
+  void* seg;             // [tiles][C][NP][NC] post-kick states of the segment
+  double* out;           // [K][1 + P]: f, then dP/dA_j, dP/dB_j, dP/deta
+  int* status;           // bit 0: more than kMaxJ omega = 0 jumps in one step
+  int M, nq, nctrl, C, S;
+  double dt, eta;
+  int64_t K, tile0;
+};
+
+// Y = (I + A) B or (I + A^T) B over NP x NC; A row-major FP64 in global memory, B and Y
+// in LDS with leading dimension LD.  Y must not alias B.
+template <int NP, int NC, int LD, class T>
+__device__ void gemm_kick(const double* __restrict__ A, bool trans, const T* B, T* Y) {
+  constexpr int RT = NP / 16, CT = NC / 16;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  for (int tile = wave; tile < RT * CT; tile += kGW) {
+    const int rt = tile / CT, ct = tile - rt * CT;
+    const int row = rt * 16 + (lane & 15), kk = lane >> 4, col = ct * 16 + (lane & 15);
+    typename Mfma<T>::acc_t acc = Mfma<T>::zero();
+#pragma unroll 8
+    for (int k0 = 0; k0 < NP; k0 += 4) {
+      const int k = k0 + kk;
+      const double av = trans ? A[static_cast<size_t>(k) * NP + row] : A[static_cast<size_t>(row) * NP + k];
+      acc = Mfma<T>::step(static_cast<T>(av), B[k * LD + col], acc);
+    }
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int r = rt * 16 + Mfma<T>::row(lane, e);
+      Y[r * LD + col] = acc[e] + B[r * LD + col];
+    }
+  }
+}
+
+// part[t] += Re <L_t | X | B_t> for the TT trajectories (columns 2t, 2t+1 = re, im);
+// each wave adds to its own part row.
+template <int NP, int NC, int LD, class T>
+__device__ void gemm_dot(const double* __restrict__ X, const T* B, const T* L, double* part) {
+  constexpr int RT = NP / 16, CT = NC / 16;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  for (int tile = wave; tile < RT * CT; tile += kGW) {
+    const int rt = tile / CT, ct = tile - rt * CT;
+    const int row = rt * 16 + (lane & 15), kk = lane >> 4, col = ct * 16 + (lane & 15);
+    typename Mfma<T>::acc_t acc = Mfma<T>::zero();
+#pragma unroll 8
+    for (int k0 = 0; k0 < NP; k0 += 4) {
+      const int k = k0 + kk;
+      acc = Mfma<T>::step(static_cast<T>(X[static_cast<size_t>(row) * NP + k]), B[k * LD + col], acc);
+    }
+    double s = 0.0;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int r = rt * 16 + Mfma<T>::row(lane, e);
+      s += static_cast<double>(L[r * LD + col]) * static_cast<double>(acc[e]);
+    }
+    s += __shfl_xor(s, 16, 64);
+    s += __shfl_xor(s, 32, 64);
+    s += __shfl_xor(s, 1, 64);
+    if (lane < 16 && !(lane & 1)) part[(ct * 16 + lane) >> 1] += s;
+  }
+}
+
+template <int NP, int TT, class T>
+struct GradShared {
+  static constexpr int NC = 2 * TT;
+  static constexpr int LD = NC + 1;
+  T PA[NP * LD];                 // psi just after the step's kick
+  T PB[NP * LD];                 // psi at the end of the step
+  T LA[NP * LD];                 // adjoints at the same points
+  T LB[NP * LD];
+  int cur[TT];                   // running record cursor
+  int scur[kMaxSeg][TT];         // record cursor at the start of each step of the segment
+  double f[TT];                  // final ground-cluster population
+  double S[TT][3];               // handler terms of the current grid point (A, B, eta)
+  double part[kGW][4][TT];       // X-term partial sums
+  double rho[kGW][kMaxJ];        // |diag(z) psi| of the omega = 0 jumps of one trajectory-step
+};
+
+// Records of trajectory j's step g (record step g - 1) start at m0; returns the end.
+__device__ inline int step_end(const aqt_jump* rec, int cnt, int m0, int g) {
+  int m = m0;
+  while (m < cnt && rec[m].step == g - 1) ++m;
+  return m;
+}
+
+// Replays step g of trajectory t: PA columns -> PB columns.  Between jumps the
+// components decay by exp(-Gamma tau / 2); an a != b jump leaves e_a; an omega = 0
+// jump multiplies by z_i and renormalises (rho[k] receives the norm before it); the
+// phases exp(-i e dt) are applied at the end of the step.
+template <int NP, int LD, class T>
+__device__ void replay_step(const GradArgs& a, int g, const aqt_jump* rec, int m0, int m1, const T* PA, T* PB, int t,
+                            double* rho) {
+  constexpr int NR = (NP + 63) / 64;
+  const int lane = threadIdx.x & 63;
+  const size_t gN = static_cast<size_t>(g) * NP;
+  double pr[NR], pi[NR];
+#pragma unroll
+  for (int r = 0; r < NR; ++r) {
+    const int x = lane + 64 * r;
+    pr[r] = (x < NP) ? static_cast<double>(PA[x * LD + 2 * t]) : 0.0;
+    pi[r] = (x < NP) ? static_cast<double>(PA[x * LD + 2 * t + 1]) : 0.0;
+  }
+  if (m1 == m0) {
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+      const int x = lane + 64 * r;
+      if (x < NP) {
+        const double dr = a.dre[gN + x], di = a.dim[gN + x];
+        PB[x * LD + 2 * t] = static_cast<T>(dr * pr[r] - di * pi[r]);
+        PB[x * LD + 2 * t + 1] = static_cast<T>(dr * pi[r] + di * pr[r]);
+      }
+    }
+    return;
+  }
+  const double tk = (g - 1) * a.dt;
+  double tau_e = 0.0;
+  for (int m = m0; m < m1; ++m) {
+    const aqt_jump J = rec[m];
+    const double tau = J.t - tk;
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+      const int x = lane + 64 * r;
+      if (x < NP) {
+        const double dec = exp(-0.5 * a.Gam[gN + x] * (tau - tau_e));
+        pr[r] *= dec;
+        pi[r] *= dec;
+      }
+    }
+    tau_e = tau;
+    if (J.from_level != J.to_level) {
+#pragma unroll
+      for (int r = 0; r < NR; ++r) {
+        pr[r] = (lane + 64 * r == J.to_level) ? 1.0 : 0.0;
+        pi[r] = 0.0;
+      }
+    } else {
+      const double* z = a.zdiag + (static_cast<size_t>(g) * a.nq + J.qubit) * NP;
+      double nrm = 0.0;
+#pragma unroll
+      for (int r = 0; r < NR; ++r) {
+        const int x = lane + 64 * r;
+        const double zz = (x < NP) ? z[x] : 0.0;
+        pr[r] *= zz;
+        pi[r] *= zz;
+        nrm += pr[r] * pr[r] + pi[r] * pi[r];
+      }
+      nrm = wave_sum(nrm);
+      const double rn = sqrt(nrm);
+      if (rho && m - m0 < kMaxJ) rho[m - m0] = rn;   // every lane writes (and later reads) the same value
+      const double inv = 1.0 / rn;
+#pragma unroll
+      for (int r = 0; r < NR; ++r) {
+        pr[r] *= inv;
+        pi[r] *= inv;
+      }
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < NR; ++r) {
+    const int x = lane + 64 * r;
+    if (x < NP) {
+      const double dec = exp(-0.5 * a.Gam[gN + x] * (a.dt - tau_e));
+      double sn, cs;
+      sincos(a.E[gN + x] * a.dt, &sn, &cs);
+      const double ur = pr[r] * dec, ui = pi[r] * dec;
+      PB[x * LD + 2 * t] = static_cast<T>(cs * ur + sn * ui);       // times exp(-i e dt)
+      PB[x * LD + 2 * t + 1] = static_cast<T>(cs * ui - sn * ur);
+    }
+  }
+}
+
+// Backward through step g for trajectory t (wave-uniform): adds the decay, phase and
+// jump terms of grid g to S[3] (directions A, B and eta) and writes lambda_A into LA.
+template <int NP, int LD, class T>
+__device__ void adjoint_step(const GradArgs& a, int g, const aqt_jump* rec, int m0, int m1, const T* PA, const T* PB,
+                             const T* LB, T* LA, int t, double f, const double* rho, double S[3]) {
+  constexpr int NR = (NP + 63) / 64;
+  const int lane = threadIdx.x & 63;
+  const size_t gN = static_cast<size_t>(g) * NP;
+  const double* dE0 = a.dE + (static_cast<size_t>(g) * 2) * NP;
+  const double* dE1 = dE0 + NP;
+  const double* dG0 = a.dGam + (static_cast<size_t>(g) * 2) * NP;
+  const double* dG1 = dG0 + NP;
+  const double dt = a.dt, ieta = 1.0 / a.eta;
+  bool has_ab = false;
+  int b1 = 0;
+  for (int m = m0; m < m1; ++m)
+    if (rec[m].from_level != rec[m].to_level) {
+      has_ab = true;
+      b1 = rec[m].from_level;
+      break;
+    }
+  if (has_ab) {
+    // every factor of the step acts on one component: terms through f alone
+    const double tk = (g - 1) * dt;
+    int c = b1;
+    double tp = 0.0, s0 = 0.0, s1 = 0.0, s2 = 0.0;
+    for (int m = m0; m < m1; ++m) {
+      const aqt_jump J = rec[m];
+      const double tau = J.t - tk, dur = tau - tp;
+      s0 -= f * dur * dG0[c];
+      s1 -= f * dur * dG1[c];
+      s2 -= f * dur * a.Gam[gN + c] * ieta;
+      tp = tau;
+      const size_t gi = (static_cast<size_t>(g) * 2) * a.nq + J.qubit;   // [g][dir = 0][i]
+      const size_t dstride = static_cast<size_t>(a.nq);                     // dir 1 is nq rows further
+      if (J.from_level != J.to_level) {
+        const size_t o = (gi * NP + J.from_level) * NP + J.to_level;
+        s0 += 2.0 * f * a.dll[o];
+        s1 += 2.0 * f * a.dll[o + dstride * NP * NP];
+        c = J.to_level;
+      } else {
+        const double zc = a.zdiag[(static_cast<size_t>(g) * a.nq + J.qubit) * NP + c];
+        s0 += 2.0 * f * a.dzd[gi * NP + c] / zc;
+        s1 += 2.0 * f * a.dzd[(gi + dstride) * NP + c] / zc;
+      }
+      s2 += f * ieta;
+    }
+    const double dur = dt - tp;
+    s0 -= f * dur * dG0[c];
+    s1 -= f * dur * dG1[c];
+    s2 -= f * dur * a.Gam[gN + c] * ieta;
+    S[0] += s0;
+    S[1] += s1;
+    S[2] += s2;
+    // lambda_A = f psi_A,b1 / |psi_A,b1|^2 e_b1
+    const double ar = static_cast<double>(PA[b1 * LD + 2 * t]), ai = static_cast<double>(PA[b1 * LD + 2 * t + 1]);
+    const double sc = f / (ar * ar + ai * ai);
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+      const int x = lane + 64 * r;
+      if (x < NP) {
+        LA[x * LD + 2 * t] = static_cast<T>(x == b1 ? sc * ar : 0.0);
+        LA[x * LD + 2 * t + 1] = static_cast<T>(x == b1 ? sc * ai : 0.0);
+      }
+    }
+    return;
+  }
+  // no collapse: P_x = conj(lambda_B,x) psi_B,x is constant through the step
+  const int nj = m1 - m0;
+  double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+  double fr[NR], fi[NR];   // total step factor F_x = d_x prod_k z_k,x / rho_k
+#pragma unroll
+  for (int r = 0; r < NR; ++r) {
+    const int x = lane + 64 * r;
+    fr[r] = fi[r] = 0.0;
+    if (x >= NP) continue;
+    const double lr = static_cast<double>(LB[x * LD + 2 * t]), li = static_cast<double>(LB[x * LD + 2 * t + 1]);
+    const double br = static_cast<double>(PB[x * LD + 2 * t]), bi = static_cast<double>(PB[x * LD + 2 * t + 1]);
+    const double Pr = lr * br + li * bi, Pi = lr * bi - li * br;
+    s0 += 2.0 * dt * dE0[x] * Pi - dt * dG0[x] * Pr;
+    s1 += 2.0 * dt * dE1[x] * Pi - dt * dG1[x] * Pr;
+    s2 -= dt * ieta * a.Gam[gN + x] * Pr;
+    double pr = 1.0;
+    for (int k = 0; k < nj && k < kMaxJ; ++k)
+      pr *= a.zdiag[(static_cast<size_t>(g) * a.nq + rec[m0 + k].qubit) * NP + x] / rho[k];
+    fr[r] = a.dre[gN + x] * pr;
+    fi[r] = a.dim[gN + x] * pr;
+  }
+  for (int k = 0; k < nj && k < kMaxJ; ++k) {
+    // 2 Re <lambda_after| diag(dz) |psi_before> / rho_k, with
+    // conj(lambda_after,x) psi_before,x = d_x prod_{k' != k} (z_k',x / rho_k') conj(lambda_B,x) psi_A,x
+    const int qi = rec[m0 + k].qubit;
+    const size_t gi = (static_cast<size_t>(g) * 2) * a.nq + qi;
+    double c0 = 0.0, c1 = 0.0;
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+      const int x = lane + 64 * r;
+      if (x >= NP) continue;
+      double pr = 1.0;
+      for (int k2 = 0; k2 < nj && k2 < kMaxJ; ++k2)
+        if (k2 != k) pr *= a.zdiag[(static_cast<size_t>(g) * a.nq + rec[m0 + k2].qubit) * NP + x] / rho[k2];
+      const double lr = static_cast<double>(LB[x * LD + 2 * t]), li = static_cast<double>(LB[x * LD + 2 * t + 1]);
+      const double ar = static_cast<double>(PA[x * LD + 2 * t]), ai = static_cast<double>(PA[x * LD + 2 * t + 1]);
+      const double qr = lr * ar + li * ai, qm = lr * ai - li * ar;   // conj(lambda_B) psi_A
+      const double re = (a.dre[gN + x] * qr - a.dim[gN + x] * qm) * pr;
+      c0 += a.dzd[gi * NP + x] * re;
+      c1 += a.dzd[(gi + a.nq) * NP + x] * re;
+    }
+    s0 += 2.0 * c0 / rho[k];
+    s1 += 2.0 * c1 / rho[k];
+    if (lane == 0) s2 += f * ieta;   // summed over lanes below
+  }
+  S[0] += wave_sum(s0);
+  S[1] += wave_sum(s1);
+  S[2] += wave_sum(s2);
+  // lambda_A = conj(F) lambda_B
+#pragma unroll
+  for (int r = 0; r < NR; ++r) {
+    const int x = lane + 64 * r;
+    if (x >= NP) continue;
+    const double lr = static_cast<double>(LB[x * LD + 2 * t]), li = static_cast<double>(LB[x * LD + 2 * t + 1]);
+    LA[x * LD + 2 * t] = static_cast<T>(fr[r] * lr + fi[r] * li);
+    LA[x * LD + 2 * t + 1] = static_cast<T>(fr[r] * li - fi[r] * lr);
+  }
+}
+
+// Copies between an LDS state tile (leading dimension LD) and a dense [NP][NC] block.
+template <int NP, int NC, int LD, class T>
+__device__ void tile_store(const T* src, T* __restrict__ dst) {
+  for (int f = threadIdx.x; f < NP * NC; f += kGThreads) dst[f] = src[(f / NC) * LD + (f % NC)];
+}
+template <int NP, int NC, int LD, class T>
+__device__ void tile_load(const T* __restrict__ src, T* dst) {
+  for (int f = threadIdx.x; f < NP * NC; f += kGThreads) dst[(f / NC) * LD + (f % NC)] = src[f];
+}
+
+template <int NP, int TT, class T>
+__global__ __launch_bounds__(kGThreads) void k_grad(GradArgs a) {
+  using SH = GradShared<NP, TT, T>;
+  constexpr int NC = SH::NC, LD = SH::LD;
+  __shared__ SH sh;
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int64_t tile = a.tile0 + blockIdx.x;
+  const int64_t lt = blockIdx.x;   // tile within this launch (workspace index)
+  const int P = 2 * a.nctrl + 1;
+  T* ck = static_cast<T*>(a.ckpt) + lt * a.S * NP * NC;
+  int* ckc = a.ckcur + lt * a.S * TT;
+  T* sg = static_cast<T*>(a.seg) + lt * a.C * NP * NC;
+  auto traj = [&](int t) { return tile * TT + t; };
+  auto active = [&](int t) { return traj(t) < a.K; };
+  auto recs = [&](int t) { return a.jumps + traj(t) * a.cap; };
+  auto count = [&](int t) { return a.jcount[traj(t)]; };
+
+  auto kick = [&](int g) {   // PA = O_g PB (g >= 2) or the initial state (g = 1)
+    if (g == 1) {
+      for (int f = tid; f < NP * NC; f += kGThreads) {
+        const int x = f / NC, col = f % NC;
+        sh.PA[x * LD + col] = (!(col & 1) && active(col >> 1)) ? static_cast<T>(a.cinit[x]) : static_cast<T>(0);
+      }
+    } else {
+      gemm_kick<NP, NC, LD, T>(a.dlt + static_cast<size_t>(g) * NP * NP, false, sh.PB, sh.PA);
+    }
+  };
+  auto forward = [&](int g) {   // PB = step g (PA); advances the cursors
+    for (int t = wave; t < TT; t += kGW) {
+      if (!active(t)) continue;
+      const int m0 = sh.cur[t];
+      const int m1 = step_end(recs(t), count(t), m0, g);
+      replay_step<NP, LD, T>(a, g, recs(t), m0, m1, sh.PA, sh.PB, t, nullptr);
+      if (lane == 0) sh.cur[t] = m1;
+    }
+  };
+
+  // ---- forward replay with checkpoints
+  for (int t = tid; t < TT; t += kGThreads) sh.cur[t] = 0;
+  for (int f = tid; f < NP * LD; f += kGThreads) {
+    sh.PB[f] = static_cast<T>(0);
+    sh.LB[f] = static_cast<T>(0);
+    sh.LA[f] = static_cast<T>(0);
+  }
+  __syncthreads();
+  for (int g = 1; g < a.M; ++g) {
+    kick(g);
+    __syncthreads();
+    forward(g);
+    __syncthreads();
+    if (g % a.C == 0 && g < a.M - 1) {
+      const int s = g / a.C;
+      tile_store<NP, NC, LD, T>(sh.PB, ck + static_cast<size_t>(s) * NP * NC);
+      for (int t = tid; t < TT; t += kGThreads) ckc[s * TT + t] = sh.cur[t];
+      __syncthreads();
+    }
+  }
+
+  // ---- backward, one segment at a time (last first)
+  for (int s = a.S - 1; s >= 0; --s) {
+    const int glo = s * a.C + 1, ghi = std::min((s + 1) * a.C, a.M - 1);
+    if (s > 0) tile_load<NP, NC, LD, T>(ck + static_cast<size_t>(s) * NP * NC, sh.PB);
+    for (int t = tid; t < TT; t += kGThreads) sh.cur[t] = (s > 0) ? ckc[s * TT + t] : 0;
+    __syncthreads();
+    for (int g = glo; g <= ghi; ++g) {
+      kick(g);
+      for (int t = tid; t < TT; t += kGThreads) sh.scur[g - glo][t] = sh.cur[t];
+      __syncthreads();
+      tile_store<NP, NC, LD, T>(sh.PA, sg + static_cast<size_t>(g - glo) * NP * NC);
+      if (g < ghi) forward(g);
+      __syncthreads();
+    }
+    for (int g = ghi; g >= glo; --g) {
+      tile_load<NP, NC, LD, T>(sg + static_cast<size_t>(g - glo) * NP * NC, sh.PA);
+      for (int f = tid; f < kGW * 4 * TT; f += kGThreads) (&sh.part[0][0][0])[f] = 0.0;
+      __syncthreads();
+      for (int t = wave; t < TT; t += kGW) {
+        if (!active(t)) {
+          if (lane < 3) sh.S[t][lane] = 0.0;
+          continue;
+        }
+        const aqt_jump* rec = recs(t);
+        const int m0 = sh.scur[g - glo][t];
+        const int m1 = step_end(rec, count(t), m0, g);
+        if (m1 - m0 > kMaxJ && lane == 0) a.status[0] = 1;
+        replay_step<NP, LD, T>(a, g, rec, m0, m1, sh.PA, sh.PB, t, sh.rho[wave]);
+        double f;
+        if (g == a.M - 1) {
+          // lambda = Pi psi / |psi|^2 with Pi the ground cluster of the last grid point
+          const int gsz = a.gs[a.M - 1];
+          double nn = 0.0, pg = 0.0;
+          for (int x = lane; x < NP; x += 64) {
+            const double br = static_cast<double>(sh.PB[x * LD + 2 * t]), bi = static_cast<double>(sh.PB[x * LD + 2 * t + 1]);
+            nn += br * br + bi * bi;
+            if (x < gsz) pg += br * br + bi * bi;
+          }
+          nn = wave_sum(nn);
+          pg = wave_sum(pg);
+          for (int x = lane; x < NP; x += 64) {
+            const double w = (x < gsz) ? 1.0 / nn : 0.0;
+            sh.LB[x * LD + 2 * t] = static_cast<T>(w * static_cast<double>(sh.PB[x * LD + 2 * t]));
+            sh.LB[x * LD + 2 * t + 1] = static_cast<T>(w * static_cast<double>(sh.PB[x * LD + 2 * t + 1]));
+          }
+          f = pg / nn;
+          sh.f[t] = f;
+        } else {
+          f = sh.f[t];
+        }
+        double S[3] = {0.0, 0.0, 0.0};
+        adjoint_step<NP, LD, T>(a, g, rec, m0, m1, sh.PA, sh.PB, sh.LB, sh.LA, t, f, sh.rho[wave], S);
+        if (g == 1) {
+          // grid 0 through the initial state: 2 Re <lambda_A | dcin>
+          double c0 = 0.0, c1 = 0.0;
+          for (int x = lane; x < NP; x += 64) {
+            const double lr = static_cast<double>(sh.LA[x * LD + 2 * t]);
+            c0 += lr * a.dcin[x];
+            c1 += lr * a.dcin[NP + x];
+          }
+          c0 = wave_sum(c0);
+          c1 = wave_sum(c1);
+          if (lane == 0) {
+            double* o = a.out + traj(t) * (1 + P);
+            o[1] += 2.0 * c0;            // grid 0: s = 0, weight 1 on control 0
+            o[1 + a.nctrl] += 2.0 * c1;
+          }
+        }
+        if (lane == 0) {
+          sh.S[t][0] = S[0];
+          sh.S[t][1] = S[1];
+          sh.S[t][2] = S[2];
+        }
+      }
+      __syncthreads();
+      // basis-change terms of grid g
+      for (int dir = 0; dir < 2; ++dir) {
+        const double* X = a.Xd + (static_cast<size_t>(g) * 2 + dir) * NP * NP;
+        gemm_dot<NP, NC, LD, T>(X, sh.PA, sh.LA, sh.part[wave][2 * dir]);
+        if (g < a.M - 1) gemm_dot<NP, NC, LD, T>(X, sh.PB, sh.LB, sh.part[wave][2 * dir + 1]);
+      }
+      __syncthreads();
+      for (int t = tid; t < TT; t += kGThreads) {
+        if (!active(t)) continue;
+        double xa[2];
+        for (int dir = 0; dir < 2; ++dir) {
+          double pa = 0.0, pb = 0.0;
+          for (int w = 0; w < kGW; ++w) {
+            pa += sh.part[w][2 * dir][t];
+            pb += sh.part[w][2 * dir + 1][t];
+          }
+          xa[dir] = sh.S[t][dir] + 2.0 * (pb - pa);
+        }
+        const double u = static_cast<double>(g) / (a.M - 1) * (a.nctrl - 1);
+        const int j = std::min(static_cast<int>(floor(u)), a.nctrl - 2);
+        const double fr = u - j;
+        double* o = a.out + traj(t) * (1 + P);
+        o[1 + j] += (1.0 - fr) * xa[0];
+        o[2 + j] += fr * xa[0];
+        o[1 + a.nctrl + j] += (1.0 - fr) * xa[1];
+        o[2 + a.nctrl + j] += fr * xa[1];
+        o[P] += sh.S[t][2];
+        if (g == a.M - 1) o[0] = sh.f[t];
+      }
+      // adjoint before the kick: lambda_B(g - 1) = O_g^T lambda_A(g)
+      if (g >= 2) gemm_kick<NP, NC, LD, T>(a.dlt + static_cast<size_t>(g) * NP * NP, true, sh.LA, sh.LB);
+      __syncthreads();
+    }
+  }
+}
+
+// Column sums and sums of squares of out[K][ncol] (one workgroup per column, fixed order).
+__global__ __launch_bounds__(256) void k_colstats(const double* __restrict__ out, int64_t K, int ncol,
+                                                  double* __restrict__ stats) {
+  __shared__ double r1[4], r2[4];
+  const int c = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  double s1 = 0.0, s2 = 0.0;
+  for (int64_t j = tid; j < K; j += 256) {
+    const double v = out[j * ncol + c];
+    s1 += v;
+    s2 += v * v;
+  }
+  s1 = wave_sum(s1);
+  s2 = wave_sum(s2);
+  if (lane == 0) {
+    r1[wave] = s1;
+    r2[wave] = s2;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    stats[2 * c] = r1[0] + r1[1] + r1[2] + r1[3];
+    stats[2 * c + 1] = r2[0] + r2[1] + r2[2] + r2[3];
+  }
+}
+
+template <int NP, int TT, class T>
+aqt_status launch_sweep(aqt_ctx* ctx, GradArgs& ga, int64_t tiles) {
+  constexpr int NC = 2 * TT;
+  const size_t per_tile = (static_cast<size_t>(ga.S) + ga.C) * NP * NC * sizeof(T) + static_cast<size_t>(ga.S) * TT * 4;
+  const size_t budget = size_t(16) << 30;
+  const int64_t chunk = std::max<int64_t>(1, std::min<int64_t>(tiles, static_cast<int64_t>(budget / per_tile)));
+  DevBuf ws;
+  if (ws.reserve(per_tile * chunk) != hipSuccess) return ctx->fail(AQT_ENOMEM, "gradient workspace allocation failed");
+  char* base = static_cast<char*>(ws.p);
+  ga.ckpt = base;
+  ga.seg = base + static_cast<size_t>(chunk) * ga.S * NP * NC * sizeof(T);
+  ga.ckcur = reinterpret_cast<int*>(base + static_cast<size_t>(chunk) * (ga.S + ga.C) * NP * NC * sizeof(T));
+  for (int64_t t0 = 0; t0 < tiles; t0 += chunk) {
+    ga.tile0 = t0;
+    const int64_t nt = std::min(chunk, tiles - t0);
+    hipLaunchKernelGGL((k_grad<NP, TT, T>), dim3(static_cast<unsigned>(nt)), dim3(kGThreads), 0, ctx->stream, ga);
+    AQT_HIP(ctx, hipGetLastError());
+  }
+  AQT_HIP(ctx, hipStreamSynchronize(ctx->stream));   // the workspace is freed on return
+  return AQT_OK;
+}
+
+}  // namespace
+
+aqt_status launch_grad(aqt_ctx* ctx, const aqt_run_params* p, double* value, double* value_se, double* grad,
+                       double* grad_se, double* per_traj) {
+  const int64_t K = p->n_traj;
+  const int nctrl = static_cast<int>(ctx->A_ctrl.size());
+  if (nctrl < 2) return ctx->fail(AQT_EINVAL, "the gradient needs at least two control points");
+  const int P = 2 * nctrl + 1;
+  const int NP = ctx->NP;
+  hipStream_t st = ctx->stream;
+
+  // forward paths from the trajectory kernel, every jump recorded
+  DevBuf jc, jr, outb, stats, status;
+  if (jc.reserve(K * 4) || status.reserve(4) || stats.reserve(2 * (P + 1) * 8))
+    return ctx->fail(AQT_ENOMEM, "gradient allocation failed");
+  int cap = 32;
+  for (int attempt = 0; attempt < 2; ++attempt) {
+    if (jr.reserve(static_cast<size_t>(K) * cap * sizeof(aqt_jump)) != hipSuccess)
+      return ctx->fail(AQT_ENOMEM, "jump record allocation failed");
+    aqt_run_params rp = *p;
+    rp.record_capacity = cap;
+    aqt_outputs o{};
+    o.jump_count = jc.as<int32_t>();
+    o.jumps = jr.as<aqt_jump>();
+    aqt_status s = launch_run(ctx, &rp, &o);
+    if (s != AQT_OK) return s;
+    std::vector<int32_t> cnt(K);
+    AQT_HIP(ctx, hipMemcpyAsync(cnt.data(), jc.p, K * 4, hipMemcpyDeviceToHost, st));
+    AQT_HIP(ctx, hipStreamSynchronize(st));
+    const int mx = cnt.empty() ? 0 : *std::max_element(cnt.begin(), cnt.end());
+    if (mx <= cap) break;
+    if (attempt == 1) return ctx->fail(AQT_ENUMERIC, "jump counts changed between identical runs");
+    cap = mx;
+  }
+
+  double* out = per_traj;
+  if (!out) {
+    if (outb.reserve(static_cast<size_t>(K) * (P + 1) * 8) != hipSuccess)
+      return ctx->fail(AQT_ENOMEM, "gradient output allocation failed");
+    out = outb.as<double>();
+  }
+  AQT_HIP(ctx, hipMemsetAsync(out, 0, static_cast<size_t>(K) * (P + 1) * 8, st));
+  AQT_HIP(ctx, hipMemsetAsync(status.p, 0, 4, st));
+
+  GradArgs ga{};
+  ga.dlt = ctx->dlt.as<double>();
+  ga.cinit = ctx->cinit.as<double>();
+  ga.E = ctx->E.as<double>();
+  ga.Gam = ctx->Gamma.as<double>();
+  ga.zdiag = ctx->zdiag.as<double>();
+  ga.dre = ctx->dre.as<double>();
+  ga.dim = ctx->dim.as<double>();
+  ga.gs = ctx->gs.as<int>();
+  ga.Xd = ctx->Xd.as<double>();
+  ga.dE = ctx->dE.as<double>();
+  ga.dGam = ctx->dGam.as<double>();
+  ga.dzd = ctx->dzd.as<double>();
+  ga.dll = ctx->dll.as<double>();
+  ga.dcin = ctx->dcin.as<double>();
+  ga.jumps = jr.as<aqt_jump>();
+  ga.jcount = jc.as<int32_t>();
+  ga.cap = cap;
+  ga.out = out;
+  ga.status = status.as<int>();
+  ga.M = ctx->M;
+  ga.nq = ctx->nq;
+  ga.nctrl = nctrl;
+  ga.C = std::min(kMaxSeg, std::max(1, static_cast<int>(std::ceil(std::sqrt(static_cast<double>(ctx->M - 1))))));
+  ga.S = (ctx->M - 1 + ga.C - 1) / ga.C;
+  ga.dt = ctx->dt;
+  ga.eta = ctx->eta;
+  ga.K = K;
+  if (!(ga.eta > 0.0)) return ctx->fail(AQT_EINVAL, "the gradient needs eta > 0");
+
+  const bool f64 = p->precision == AQT_FP64;
+  aqt_status s = AQT_OK;
+#define AQT_SWEEP(np, tt, T) s = launch_sweep<np, tt, T>(ctx, ga, (K + (tt) - 1) / (tt))
+  switch (NP) {
+    case 16: if (f64) AQT_SWEEP(16, 16, double); else AQT_SWEEP(16, 16, float); break;
+    case 32: if (f64) AQT_SWEEP(32, 16, double); else AQT_SWEEP(32, 16, float); break;
+    case 64: if (f64) AQT_SWEEP(64, 16, double); else AQT_SWEEP(64, 16, float); break;
+    case 128: if (f64) AQT_SWEEP(128, 16, double); else AQT_SWEEP(128, 16, float); break;
+    case 256: if (f64) AQT_SWEEP(256, 8, double); else AQT_SWEEP(256, 16, float); break;
+    default: return ctx->fail(AQT_EINVAL, "unsupported level count");
+  }
+#undef AQT_SWEEP
+  if (s != AQT_OK) return s;
+  int hstat = 0;
+  AQT_HIP(ctx, hipMemcpy(&hstat, status.p, 4, hipMemcpyDeviceToHost));
+  if (hstat) return ctx->fail(AQT_ECAPACITY, "more than 64 omega = 0 jumps of one trajectory within one step");
+
+  hipLaunchKernelGGL(k_colstats, dim3(P + 1), dim3(256), 0, st, out, K, P + 1, stats.as<double>());
+  AQT_HIP(ctx, hipGetLastError());
+  std::vector<double> hs(2 * (P + 1));
+  AQT_HIP(ctx, hipMemcpyAsync(hs.data(), stats.p, hs.size() * 8, hipMemcpyDeviceToHost, st));
+  AQT_HIP(ctx, hipStreamSynchronize(st));
+  auto mean_se = [&](int c, double* m, double* se) {
+    const double mu = hs[2 * c] / K;
+    const double var = std::max(0.0, (hs[2 * c + 1] - K * mu * mu) / (K - 1));
+    if (m) *m = mu;
+    if (se) *se = std::sqrt(var / K);
+  };
+  mean_se(0, value, value_se);
+  for (int c = 1; c <= P; ++c) mean_se(c, grad ? grad + c - 1 : nullptr, grad_se ? grad_se + c - 1 : nullptr);
+  return AQT_OK;
+}
+
+}  // namespace aqt

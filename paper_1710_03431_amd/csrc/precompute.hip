@@ -322,7 +322,8 @@ __global__ __launch_bounds__(kEigThreads) void k_canon(const double* __restrict_
 
 // C[b][i][j] (+)= sum_x w(x) A[i][x] B[j][x] for rows i < ra, j < rb: 64x64 tile
 // per workgroup, x staged through LDS in chunks of 32, 16x16x4 FP64 MFMAs.
-// wmode 0: w = 1; 1: w = sz of qubit (bz % nq) (operands of batch bz / nq); 2: w = x.
+// wmode 0: w = 1; 1: w = sz of qubit (bz % nq) (operands of batch bz / nq); 2: w = x;
+// 3: w = wvec[x].  bdiv > 1: operand B of batch bz is B + sB * (bz / bdiv).
 // sub_eye: subtract the identity (stores O - I).
 struct GemmArgs {
   const double* A;
@@ -333,6 +334,8 @@ struct GemmArgs {
   int wmode, nq, sub_eye;
   int ksplit = 1;   // > 1: blockIdx.z = batch * ksplit + part, each part sums x in its
   int kspan = 0;    // span of kspan and writes a compact [ra][rb] partial at C + sC * blockIdx.z
+  const double* wvec = nullptr;
+  int bdiv = 1;
 };
 
 __global__ __launch_bounds__(256) void k_gemm_f64(GemmArgs p) {
@@ -346,7 +349,7 @@ __global__ __launch_bounds__(256) void k_gemm_f64(GemmArgs p) {
   const int opb = (p.wmode == 1) ? bz / p.nq : bz;
   const int qubit = (p.wmode == 1) ? bz % p.nq : 0;
   const double* A = p.A + p.sA * opb;
-  const double* B = p.B + p.sB * opb;
+  const double* B = p.B + p.sB * ((p.bdiv > 1) ? bz / p.bdiv : opb);
   double* C = p.C + p.sC * blockIdx.z;
   const int i0 = blockIdx.y * 64, j0 = blockIdx.x * 64;
   const int wi = (wave >> 1) * 32, wj = (wave & 1) * 32;
@@ -361,6 +364,7 @@ __global__ __launch_bounds__(256) void k_gemm_f64(GemmArgs p) {
       double w = 1.0;
       if (p.wmode == 1) w = ((x >> qubit) & 1) ? -1.0 : 1.0;
       else if (p.wmode == 2) w = static_cast<double>(x);
+      else if (p.wmode == 3 && x < xend) w = p.wvec[x];
       As[r][k] = (i0 + r < p.ra && x < xend) ? w * A[static_cast<size_t>(i0 + r) * p.lda + x] : 0.0;
       Bs[r][k] = (j0 + r < p.rb && x < xend) ? B[static_cast<size_t>(j0 + r) * p.ldb + x] : 0.0;
     }
@@ -624,6 +628,142 @@ __global__ void k_cinit(const double* __restrict__ V0, const double* __restrict_
   const double inv = 1.0 / sqrt(nn);
   for (int a = tid; a < NP; a += blockDim.x) cinit[a] = (a < n) ? s_c[a] * inv : 0.0;
   if (tid == 0) leak[1] = 1.0 - nn;
+}
+
+// ---- derivative tables of the gradient (full spectrum, n = 2^n_qubits) ----------
+// Directions: 0 = A(s_g) (operator H_X = -sum_i sx_i), 1 = B(s_g) (operator
+// diag(e_Z)).  First-order perturbation theory of the symmetric eigenproblem:
+// de_a = <a|H'|a>, dv_b = sum_a v_a X_ab with X_ab = <a|H'|b> / (e_b - e_a) for
+// levels in different clusters and 0 inside a cluster (the canonical in-cluster
+// basis is held fixed), so X is antisymmetric and dz_i = z_i X - X z_i.
+
+// W[c][b][x] = (H_X v_b)[x] = -sum_i v_b[x ^ 2^i] for the n rows of cnt grid points.
+__global__ void k_hx_rows(const double* __restrict__ V, int64_t vstride, int N, int nq, int n, int cnt,
+                          double* __restrict__ W) {
+  const int64_t per = static_cast<int64_t>(n) * N;
+  const int64_t idx = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (idx >= per * cnt) return;
+  const int c = static_cast<int>(idx / per);
+  const int64_t r = idx - c * per;
+  const int b = static_cast<int>(r / N), x = static_cast<int>(r - static_cast<int64_t>(b) * N);
+  const double* v = V + c * vstride + static_cast<int64_t>(b) * N;
+  double acc = 0.0;
+  for (int i = 0; i < nq; ++i) acc -= v[x ^ (1 << i)];
+  W[idx] = acc;
+}
+
+// X[g][dir] (NP x NP, zero padded) and de[g][dir] from Hd[c][dir] = V H' V^T (n x n).
+__global__ void k_xmat(const double* __restrict__ Hd, int n, int NP, const double* __restrict__ E, int g0,
+                       double tol, double* __restrict__ Xd, double* __restrict__ dE) {
+  __shared__ int cl[256];
+  const int c = blockIdx.x, dir = blockIdx.y, g = g0 + c;
+  const double* e = E + static_cast<size_t>(g) * NP;
+  if (threadIdx.x == 0) {
+    int id = 0;
+    cl[0] = 0;
+    for (int a = 1; a < n; ++a) {
+      if (e[a] - e[a - 1] >= tol) ++id;
+      cl[a] = id;
+    }
+  }
+  __syncthreads();
+  const double* H = Hd + (static_cast<size_t>(c) * 2 + dir) * n * n;
+  double* X = Xd + (static_cast<size_t>(g) * 2 + dir) * NP * NP;
+  for (int f = threadIdx.x; f < NP * NP; f += blockDim.x) {
+    const int x = f / NP, y = f - x * NP;
+    double v = 0.0;
+    if (x < n && y < n && cl[x] != cl[y]) v = H[x * n + y] / (e[y] - e[x]);
+    X[f] = v;
+  }
+  for (int x = threadIdx.x; x < NP; x += blockDim.x)
+    dE[(static_cast<size_t>(g) * 2 + dir) * NP + x] = (x < n) ? H[x * n + x] : 0.0;
+}
+
+// d log gamma / d w of the Ohmic rate (w != 0 form; series below |w/T| = 1e-3).
+__device__ double dlog_gamma(double w, double wc, double T) {
+  const double x = w / T;
+  const double h = (fabs(x) < 1e-3) ? 0.5 - x / 12.0 + x * x * x / 720.0 : 1.0 / x - 1.0 / expm1(x);
+  const double sg = (w > 0.0) ? 1.0 : ((w < 0.0) ? -1.0 : 0.0);
+  return h / T - sg / wc;
+}
+
+// From z_i (chunk-local [c][i][a][b], ld n) and Q[dir][c][i] = z_i X^T (row products):
+// dz_i = -(Q + Q^T);  dzd[g][dir][i][b] = dz_i[b][b];
+// dll[g][dir][i][b][a] = d log |l_i,ab| = (1/2) dlog_gamma(w_ab) (de_b - de_a) + dz_ab / z_ab
+// for a != b (l = sqrt(gamma(w_ab)) z_ab, the b -> a operator), 0 on the diagonal;
+// dGam[g][dir][b] = d Gamma_b = sum_i [sum_{a != b} dR_i,ab + 2 gamma(0) z_bb dz_bb].
+__global__ void k_dtables(const double* __restrict__ z, const double* __restrict__ Q, const double* __restrict__ E,
+                          const double* __restrict__ dE, int n, int NP, int nq, int zg0, int zcnt, double eta,
+                          double wc, double T, double* __restrict__ dGam, double* __restrict__ dzd,
+                          double* __restrict__ dll) {
+  const int64_t idx = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (idx >= static_cast<int64_t>(zcnt) * 2 * NP) return;
+  const int c = static_cast<int>(idx / (2 * NP));
+  const int dir = static_cast<int>((idx / NP) & 1);
+  const int b = static_cast<int>(idx % NP);
+  const int g = zg0 + c;
+  const size_t gd = static_cast<size_t>(g) * 2 + dir;
+  const double* e = E + static_cast<size_t>(g) * NP;
+  const double* de = dE + gd * NP;
+  const double g0 = 2.0 * M_PI * eta * T;
+  double dG = 0.0;
+  for (int i = 0; i < nq; ++i) {
+    double* dl = dll + ((gd * nq + i) * NP + b) * NP;
+    if (b >= n) {
+      for (int a = 0; a < NP; ++a) dl[a] = 0.0;
+      dzd[(gd * nq + i) * NP + b] = 0.0;
+      continue;
+    }
+    const double* zi = z + (static_cast<size_t>(c) * nq + i) * n * n;
+    const double* Qi = Q + ((static_cast<size_t>(dir) * zcnt + c) * nq + i) * n * n;
+    for (int a = 0; a < NP; ++a) {
+      if (a >= n) {
+        dl[a] = 0.0;
+        continue;
+      }
+      const double zab = zi[a * n + b];
+      const double dz = -(Qi[a * n + b] + Qi[b * n + a]);
+      if (a == b) {
+        dzd[(gd * nq + i) * NP + b] = dz;
+        dG += 2.0 * g0 * zab * dz;
+        dl[a] = 0.0;
+        continue;
+      }
+      const double w = e[b] - e[a];
+      const double gam = gamma_ohmic(w, eta, wc, T);
+      const double lg = (w == 0.0) ? 0.5 / T : dlog_gamma(w, wc, T);
+      const double dw = de[b] - de[a];
+      dG += gam * (lg * dw * zab * zab + 2.0 * zab * dz);
+      dl[a] = (zab != 0.0) ? 0.5 * lg * dw + dz / zab : 0.0;
+    }
+  }
+  dGam[gd * NP + b] = (b < n) ? dG : 0.0;
+}
+
+// dcin[dir] = V_1 dv_0: derivative of the initial state (ground state of H(s_0)) in the
+// grid-1 basis through grid 0's eigenvectors, dv_0 = sum_y v_y X_0[y][0].
+__global__ __launch_bounds__(256) void k_dcinit(const double* __restrict__ V0, const double* __restrict__ V1,
+                                                const double* __restrict__ X0, int N, int n, int NP,
+                                                double* __restrict__ dcin) {
+  __shared__ double u[kEigMaxN];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  for (int dir = 0; dir < 2; ++dir) {
+    const double* X = X0 + static_cast<size_t>(dir) * NP * NP;
+    for (int x = tid; x < N; x += blockDim.x) {
+      double acc = 0.0;
+      for (int y = 0; y < n; ++y) acc += X[static_cast<size_t>(y) * NP] * V0[static_cast<size_t>(y) * N + x];
+      u[x] = acc;
+    }
+    __syncthreads();
+    for (int a = wave; a < NP; a += 4) {
+      double acc = 0.0;
+      if (a < n)
+        for (int x = lane; x < N; x += 64) acc += V1[static_cast<size_t>(a) * N + x] * u[x];
+      acc = wave_sum(acc);
+      if (lane == 0) dcin[dir * NP + a] = acc;
+    }
+    __syncthreads();
+  }
 }
 
 aqt_status launch_gemm(aqt_ctx* ctx, const GemmArgs& g, int batch) {
@@ -967,9 +1107,11 @@ aqt_status chfsi_solve(aqt_ctx* ctx, Chfsi& c, const double* eZ, double A, doubl
 
 }  // namespace
 
-aqt_status precompute_tables(aqt_ctx* ctx, int M, int n, double tol, int method) {
+aqt_status precompute_tables(aqt_ctx* ctx, int M, int n, double tol, int method, bool grad) {
   const int nq = ctx->nq;
   const int N = 1 << nq;
+  ctx->have_grad = false;
+  if (grad && n != N) return ctx->fail(AQT_EINVAL, "gradient tables need the full spectrum (n_levels = 2^n_qubits)");
   const bool iterative = (method == AQT_EIG_ITERATIVE) || (method == AQT_EIG_AUTO && N > kEigMaxN);
   const int ncols = std::min(N, n + 16);   // levels solved for: n plus a guard for clusters at the cut
   int KB = 0;                              // block size of the subspace iteration
@@ -1037,7 +1179,10 @@ aqt_status precompute_tables(aqt_ctx* ctx, int M, int n, double tol, int method)
                           + 2 * static_cast<size_t>(ncols) * ncols + static_cast<size_t>(ncols) * N  // canon ws
                           + static_cast<size_t>(nq) * n * n           // z
                           + 9 * static_cast<size_t>(n) * n            // polar ws
-                          + N;                                        // Eraw
+                          + N                                         // Eraw
+                          + (grad ? static_cast<size_t>(n) * N + 2 * static_cast<size_t>(n) * n +
+                                        2 * static_cast<size_t>(nq) * n * n
+                                  : 0);                               // H_X rows, V H' V^T, z X^T
   const size_t budget = size_t(24) << 30;   // of 288 GB HBM: all grid points of a 10-qubit instance in one chunk
   int Gc = static_cast<int>(std::max<size_t>(1, std::min<size_t>(M, budget / (per_grid * 8))));
   DevBuf H, Z, Vc, Vprev, cws, zws, pws, Eraw, perm, status;
@@ -1048,6 +1193,18 @@ aqt_status precompute_tables(aqt_ctx* ctx, int M, int n, double tol, int method)
       Eraw.reserve(static_cast<size_t>(Gc) * N * 8) || perm.reserve(static_cast<size_t>(Gc) * N * 4) ||
       status.reserve(static_cast<size_t>(Gc) * 4))
     return ctx->fail(AQT_ENOMEM, "precompute workspace allocation failed");
+  DevBuf Wx, Hd, Qz;
+  if (grad) {
+    const size_t sn = n, sN = N, snp = NP;
+    if (Wx.reserve(Gc * sn * sN * 8) || Hd.reserve(Gc * 2 * sn * sn * 8) || Qz.reserve(Gc * 2 * nq * sn * sn * 8) ||
+        ctx->Xd.reserve(M * 2 * snp * snp * 8) || ctx->dE.reserve(M * 2 * snp * 8) ||
+        ctx->dGam.reserve(M * 2 * snp * 8) || ctx->dzd.reserve(M * 2 * nq * snp * 8) ||
+        ctx->dll.reserve(M * 2 * nq * snp * snp * 8) || ctx->dcin.reserve(2 * snp * 8))
+      return ctx->fail(AQT_ENOMEM, "gradient table allocation failed");
+    AQT_HIP(ctx, hipMemsetAsync(ctx->dGam.p, 0, 2 * snp * 8, st));          // g = 0 unused
+    AQT_HIP(ctx, hipMemsetAsync(ctx->dzd.p, 0, 2 * nq * snp * 8, st));
+    AQT_HIP(ctx, hipMemsetAsync(ctx->dll.p, 0, 2 * nq * snp * snp * 8, st));
+  }
   std::vector<int> hstat(Gc);
   const size_t Vstride = static_cast<size_t>(ncols) * N;
   Chfsi ch;
@@ -1185,12 +1342,53 @@ aqt_status precompute_tables(aqt_ctx* ctx, int M, int n, double tol, int method)
                          ctx->R.as<double>(), ctx->zdiag.as<double>());
       AQT_HIP(ctx, hipGetLastError());
     }
+    if (grad) {
+      // V H' V^T for both directions at every grid point of the chunk, then X and de
+      const int64_t nn = static_cast<int64_t>(n) * n;
+      hipLaunchKernelGGL(k_hx_rows, dim3(nblk(static_cast<int64_t>(cnt) * n * N)), dim3(256), 0, st, Vc.as<double>(),
+                         static_cast<int64_t>(Vstride), N, nq, n, cnt, Wx.as<double>());
+      AQT_HIP(ctx, hipGetLastError());
+      GemmArgs gx{Vc.as<double>(), Wx.as<double>(), Hd.as<double>(), static_cast<int64_t>(Vstride),
+                  static_cast<int64_t>(n) * N, 2 * nn, n, n, N, N, N, n, 0, nq, 0};
+      aqt_status s = launch_gemm(ctx, gx, cnt);
+      if (s != AQT_OK) return s;
+      GemmArgs gz{Vc.as<double>(), Vc.as<double>(), Hd.as<double>() + nn, static_cast<int64_t>(Vstride),
+                  static_cast<int64_t>(Vstride), 2 * nn, n, n, N, N, N, n, 3, nq, 0};
+      gz.wvec = eZ.as<double>();
+      if ((s = launch_gemm(ctx, gz, cnt)) != AQT_OK) return s;
+      hipLaunchKernelGGL(k_xmat, dim3(cnt, 2), dim3(256), 0, st, Hd.as<double>(), n, NP, ctx->E.as<double>(), g0, tol,
+                         ctx->Xd.as<double>(), ctx->dE.as<double>());
+      AQT_HIP(ctx, hipGetLastError());
+      if (g0 <= 1 && g0 + cnt > 1) {
+        const int c1 = 1 - g0;
+        const double* V1 = Vc.as<double>() + c1 * Vstride;
+        const double* V0 = (c1 == 0) ? Vprev.as<double>() : Vc.as<double>() + (c1 - 1) * Vstride;
+        hipLaunchKernelGGL(k_dcinit, dim3(1), dim3(256), 0, st, V0, V1, ctx->Xd.as<double>(), N, n, NP,
+                           ctx->dcin.as<double>());
+        AQT_HIP(ctx, hipGetLastError());
+      }
+      if (zcnt > 0) {
+        for (int dir = 0; dir < 2; ++dir) {
+          GemmArgs gq{zws.as<double>(), ctx->Xd.as<double>() + (static_cast<size_t>(zg0) * 2 + dir) * NP * NP,
+                      Qz.as<double>() + static_cast<size_t>(dir) * zcnt * nq * nn, nn,
+                      2 * static_cast<int64_t>(NP) * NP, nn, n, n, n, n, NP, n, 0, nq, 0};
+          gq.bdiv = nq;
+          if ((s = launch_gemm(ctx, gq, zcnt * nq)) != AQT_OK) return s;
+        }
+        hipLaunchKernelGGL(k_dtables, dim3(nblk(static_cast<int64_t>(zcnt) * 2 * NP)), dim3(256), 0, st,
+                           zws.as<double>(), Qz.as<double>(), ctx->E.as<double>(), ctx->dE.as<double>(), n, NP, nq,
+                           zg0, zcnt, ctx->eta, ctx->omega_c, ctx->T, ctx->dGam.as<double>(), ctx->dzd.as<double>(),
+                           ctx->dll.as<double>());
+        AQT_HIP(ctx, hipGetLastError());
+      }
+    }
     AQT_HIP(ctx, hipMemcpyAsync(Vprev.p, Vc.as<double>() + (cnt - 1) * Vstride, Vstride * 8, hipMemcpyDeviceToDevice, st));
     AQT_HIP(ctx, hipMemcpyAsync(hstat.data(), status.p, cnt * 4, hipMemcpyDeviceToHost, st));
     AQT_HIP(ctx, hipStreamSynchronize(st));
     for (int c = 0; c < cnt; ++c)
       if (hstat[c]) return ctx->fail(AQT_ENUMERIC, "polar factor eigensolver failed at grid " + std::to_string(g0 + c));
   }
+  ctx->have_grad = grad;
   return AQT_OK;
 }
 

@@ -1,0 +1,119 @@
+"""Parity of the HIP adjoint gradient (aqt_grad_pgs) with the FP64 oracle.
+
+The oracle's per-trajectory estimates are central differences of each path's own
+log weight (jump times and channels held fixed), rebuilt from perturbed tables;
+its mean is pinned to the central differences of the split-step AME.  The GPU
+evaluates the same estimator by an adjoint sweep, so in FP64 the two agree per
+trajectory wherever the jump sequences agree, and the FP32 mean agrees with the
+AME differences within the statistical error.
+"""
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import gradient
+
+from gpu_common import compare_jump_records
+
+pytestmark = pytest.mark.gpu
+
+
+def _engine(inst):
+    from paper_1710_03431_amd.binding import Engine
+    eng = Engine(0)
+    eng.set_instance(inst)
+    eng.precompute(inst.n_grid, inst.levels)
+    return eng
+
+
+def _ring3(n_ctrl=3):
+    A, B = W.linear_schedule(n_ctrl)
+    return W.ring_instance(3, 8, t_f=1.5, eta=0.1, n_grid=101, A_ctrl=A, B_ctrl=B)
+
+
+def _matched(eng, inst, K, ref_jumps):
+    """Indices of trajectories whose GPU jump sequence equals the oracle's (FP64 run)."""
+    cap = max(8, max(len(j) for j in ref_jumps) + 1)
+    res = eng.run(K, "fp64", seed=inst.seed, instance_id=inst.instance_id, record_capacity=cap)
+    frac, _ = compare_jump_records(res["jumps"], res["jump_count"], ref_jumps, inst.t_f)
+    same = []
+    for j in range(K):
+        one, _ = compare_jump_records(res["jumps"][j:j + 1], res["jump_count"][j:j + 1], ref_jumps[j:j + 1],
+                                      inst.t_f)
+        if one == 1.0:
+            same.append(j)
+    return np.array(same), frac
+
+
+@pytest.mark.parametrize("inst_fn,K", [(_ring3, 96), (lambda: _ring3(5), 48)])
+def test_fp64_per_trajectory_gradient(inst_fn, K):
+    """3-qubit ring, fast strongly coupled anneal (about two jumps per trajectory, jumps
+    from superpositions and omega = 0 jumps): f and every component of g per trajectory."""
+    inst = inst_fn()
+    ref = gradient.trajectory_gradients(inst, K)
+    eng = _engine(inst)
+    out = eng.grad_pgs(K, "fp64", seed=inst.seed, instance_id=inst.instance_id, per_trajectory=True)
+    pt = out["per_traj"]
+    same, frac = _matched(eng, inst, K, ref["jumps"])
+    assert frac >= 0.97 and len(same) >= K - 2, frac
+    np.testing.assert_allclose(pt[same, 0], ref["f"][same], atol=1e-11)
+    g_gpu, g_ref = pt[same, 1:], ref["g"][same]
+    scale = np.maximum(np.abs(g_ref).max(axis=0), 1e-3)
+    err = np.abs(g_gpu - g_ref) / scale
+    assert err.max() <= 2e-6, (err.max(axis=0), np.unravel_index(err.argmax(), err.shape))
+    # host reductions of the same per-trajectory values
+    np.testing.assert_allclose(out["value"], pt[:, 0].mean(), rtol=1e-12)
+    np.testing.assert_allclose(out["grad"], pt[:, 1:].mean(axis=0), rtol=1e-10, atol=1e-14)
+    np.testing.assert_allclose(out["grad_se"], pt[:, 1:].std(axis=0, ddof=1) / np.sqrt(K), rtol=1e-8)
+
+
+def test_fp64_two_level_gradient_per_trajectory():
+    """Fixed two-level relaxation (one qubit, B = 0): no field, so every d/dB_j is zero."""
+    inst = W.two_level_fixed(A=0.3, t_f=150.0, n_grid=41, eta=2e-3)
+    K = 64
+    ref = gradient.trajectory_gradients(inst, K)
+    eng = _engine(inst)
+    out = eng.grad_pgs(K, "fp64", seed=inst.seed, instance_id=inst.instance_id, per_trajectory=True)
+    pt = out["per_traj"]
+    same, frac = _matched(eng, inst, K, ref["jumps"])
+    assert len(same) >= K - 1
+    g_gpu, g_ref = pt[same, 1:], ref["g"][same]
+    scale = np.maximum(np.abs(g_ref).max(axis=0), 1e-3)
+    assert (np.abs(g_gpu - g_ref) / scale).max() <= 2e-6
+    np.testing.assert_array_equal(pt[:, 3:5], 0.0)
+
+
+@pytest.mark.parametrize("prec,K", [("fp32", 20000), ("fp64", 20000)])
+def test_gradient_mean_matches_ame_differences(prec, K):
+    """The estimator's mean against central differences of the FP64 split-step AME,
+    within three standard errors (plus 1e-3 of the largest component in FP32)."""
+    inst = _ring3()
+    fd = gradient.fd_gradient(inst)
+    ref = np.concatenate([fd["dA"], fd["dB"], [fd["deta"]]])
+    eng = _engine(inst)
+    out = eng.grad_pgs(K, prec, seed=inst.seed, instance_id=inst.instance_id)
+    tol = 3.0 * out["grad_se"] + (1e-3 * np.abs(ref).max() if prec == "fp32" else 1e-5)
+    assert np.all(np.abs(out["grad"] - ref) <= tol), (out["grad"], ref, out["grad_se"])
+    assert np.sum(np.abs(ref) > 5.0 * out["grad_se"]) >= 4
+
+
+def test_gradient_argument_errors():
+    from paper_1710_03431_amd.binding import AqtError, Engine
+    inst = W.ring_instance(3, 8, t_f=1.5, eta=0.1, n_grid=21)
+    eng = Engine(0)
+    eng.set_instance(inst)
+    eng.precompute(21, 4)                     # truncated spectrum
+    with pytest.raises(AqtError):
+        eng.grad_pgs(16, "fp32")
+    eng.precompute(21, 8)
+    with pytest.raises(AqtError):
+        eng.grad_pgs(16, "bf16")
+    with pytest.raises(AqtError):
+        eng.grad_pgs(1, "fp32")
+    t = eng.get_tables(("E", "gs", "O", "cinit", "R", "zdiag"))
+    eng.set_tables(t["E"], t["gs"], t["O"], t["cinit"], t["R"], t["zdiag"])
+    with pytest.raises(AqtError):              # no eigenvectors behind host tables
+        eng.grad_pgs(16, "fp32")
+    eng.precompute(21, 8)
+    out = eng.grad_pgs(16, "fp32")
+    assert np.all(np.isfinite(out["grad"]))
