@@ -1,6 +1,6 @@
 """Throughput of the GPU trajectory engine.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload a2a8|ring4|gadget16|batched]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload a2a8|ring4|gadget16|batched|grad]
                     [--cpu-traj 3072] [--cpu-grid 500] [--no-cpu]
 
 One bench step = one aqt_run: all trajectories of the workload through the whole
@@ -21,6 +21,10 @@ Workloads:
   batched   256 instances of 6-10 qubits truncated to 16, 32 or 64 levels, 1000 grid
             points, t_f 1-100 us, 2048 trajectories each, all in one persistent
             graph-captured launch with autotuned tiles; BF16x3 headline
+  grad      gradient of the final ground-state population with respect to 16 + 16
+            schedule control points and eta (aqt_grad_pgs) on the a2a8 instance,
+            10^5 FP32 trajectories; one step = one gradient evaluation (forward run,
+            checkpointed replay and adjoint sweep), value = trajectory-steps/s of it
 """
 import argparse
 import json
@@ -43,7 +47,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="a2a8", choices=("a2a8", "ring4", "gadget16", "batched"))
+    ap.add_argument("--workload", default="a2a8", choices=("a2a8", "ring4", "gadget16", "batched", "grad"))
     ap.add_argument("--n-traj", type=int, default=0, help="override the workload's trajectory count")
     ap.add_argument("--cpu-traj", type=int, default=3072)
     ap.add_argument("--cpu-grid", type=int, default=0, help="steps of the CPU sample (default per workload)")
@@ -218,6 +222,95 @@ def bench_batched(args):
     print(json.dumps(line))
 
 
+def cpu_grad_baseline(inst, n_traj, n_steps):
+    """The oracle's per-trajectory gradient estimates (central differences of each path's
+    log weight, 2 x (2m + 1) perturbed table streams) on a bounded sample: an anneal of
+    n_steps steps of the same step size, n_traj trajectories."""
+    from oracle import gradient
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
+    except Exception:
+        threads = os.cpu_count()
+    dt = inst.t_f / (inst.n_grid - 1)
+    small = inst.with_(n_grid=n_steps + 1, t_f=dt * n_steps)
+    t0 = time.perf_counter()
+    gradient.trajectory_gradients(small, n_traj)
+    el = time.perf_counter() - t0
+    return {"value": n_traj * n_steps / el, "unit": "trajectory-steps/s", "cores": threads, "kind": "oracle",
+            "sample": f"{n_traj} trajectories x a {n_steps}-step anneal with the same step size and "
+                      f"{2 * len(inst.A_ctrl) + 1} parameters ({inst.name}; FP64 NumPy oracle: trajectories, "
+                      f"path replays and the perturbed tables, {el:.1f} s)"}
+
+
+def bench_grad(args):
+    """aqt_grad_pgs on the control-point workload; forward-only aqt_run timed beside it."""
+    import torch
+    import workloads as W
+    from paper_1710_03431_amd.binding import Engine
+    inst = W.config_gradient(args.n_traj or 100_000)
+    K, M, n = inst.n_traj, inst.n_grid, inst.levels
+    m = len(inst.A_ctrl)
+    eng = Engine(0)
+    eng.set_instance(inst)
+    t0 = time.perf_counter()
+    eng.precompute(M, n)
+    t1 = time.perf_counter()
+    eng.grad_pgs(64, "fp32", seed=inst.seed + 777)   # first call adds the derivative tables
+    t2 = time.perf_counter()
+    print(f"# precompute {t1 - t0:.1f} s, derivative tables + first call {t2 - t1:.1f} s", file=sys.stderr,
+          flush=True)
+    ref = load_ame_reference("a2a8_ctrl16_fd_gradient.json")
+    results = {}
+    for prec in (args.precisions or "fp32").split(","):
+        for w in range(args.warmup):
+            eng.grad_pgs(K, prec, seed=inst.seed + 1000 + w)
+        times, outs = [], []
+        for i in range(args.steps):
+            torch.cuda.synchronize()
+            ts = time.perf_counter()
+            outs.append(eng.grad_pgs(K, prec, seed=inst.seed + i, instance_id=inst.instance_id))
+            times.append(time.perf_counter() - ts)
+        fwd = time_precision(eng, torch, K, prec, max(1, args.steps), 1, seed=inst.seed)
+        fwd_ms = sum(fwd["event_ms"]) / len(fwd["event_ms"])
+        ms = 1e3 * sum(times) / len(times)
+        g = [sum(o["grad"][c] for o in outs) / len(outs) for c in range(2 * m + 1)]
+        se = [math.sqrt(sum(o["grad_se"][c] ** 2 for o in outs)) / len(outs) for c in range(2 * m + 1)]
+        res = {"ms": ms, "value": K * (M - 1) / (ms / 1e3), "forward_ms": fwd_ms, "grad": g, "grad_se": se,
+               "P_GS_final": sum(o["value"] for o in outs) / len(outs)}
+        if ref:
+            col = {"A": lambda j: j, "B": lambda j: m + j, "eta": lambda j: 2 * m}
+            z = {f"{k}{j}": (g[col[k](j)] - v) / se[col[k](j)] for (k, j), v in zip(ref["params"], ref["grad"])}
+            res["z_vs_fd"] = z
+        results[prec] = res
+        print(f"# {prec}: gradient {ms:.1f} ms ({res['value']:.4g} traj-steps/s), forward run {fwd_ms:.1f} ms, "
+              f"ratio {ms / fwd_ms:.2f}; P_GS(1)={res['P_GS_final']:.5f}", file=sys.stderr, flush=True)
+    head_prec = "fp32" if "fp32" in results else next(iter(results))
+    head = results[head_prec]
+    # sweep flops per trajectory-step: checkpoint pass and segment replay (2 kicks), X_g products at both
+    # points for both directions (4), the adjoint kick (1), each 4 n^2; plus the forward run
+    flops = (7 * 4 * n * n + FLOP_PER_TRAJ_STEP(n)) * K * (M - 1)
+    achieved = flops / (head["ms"] / 1e3)
+    cpu = None if args.no_cpu else cpu_grad_baseline(inst, 16, 2)
+    line = {
+        "metric": "trajectory-steps/s of the adjoint gradient (forward + checkpointed adjoint) at 1 MI355X",
+        "value": head["value"], "unit": "trajectory-steps/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": head["ms"], "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": head_prec, "data": "synthetic",
+        "config": {"workload": f"gradient of P_GS(1) w.r.t. {m}+{m} schedule control points and eta, 8-qubit "
+                               f"all-to-all +-1 anneal, n=256, {M} grid points, t_f=10us, {K} trajectories",
+                   "name": inst.name, "n_traj": K, "n_levels": n, "n_grid": M, "n_params": 2 * m + 1},
+        "paths": results,
+        "fd_reference": ({f"{k}{j}": v for (k, j), v in zip(ref["params"], ref["grad"])} if ref else None),
+        "roofline": {"bound": "mfma", "achieved": achieved / 1e12, "peak": PEAK[head_prec] / 1e12,
+                     "unit": "TFLOP/s", "frac": achieved / PEAK[head_prec], "traffic": None,
+                     "kernel": f"k_grad + forward run ({head_prec})",
+                     "per_unit": f"{7 * 4 * n * n + FLOP_PER_TRAJ_STEP(n)} flop per trajectory-step"},
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line))
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -226,6 +319,9 @@ def main():
         sys.exit(2)
     if args.workload == "batched":
         bench_batched(args)
+        return
+    if args.workload == "grad":
+        bench_grad(args)
         return
     import torch
     from paper_1710_03431_amd.binding import Engine

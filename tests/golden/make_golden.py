@@ -8,11 +8,20 @@ It records
   * the split-step FP64 AME ground-state population of that instance on its
     2000-point grid (a2a8_ame_pgs.json), the reference for the stated error
     of the GPU trajectory averages (python tests/golden/make_golden.py --ame);
-  * the same for the 4-qubit ring workload (small_ame_pgs.json, --ame-small).
+  * the same for the 4-qubit ring workload (small_ame_pgs.json, --ame-small);
+  * central differences (h = 1e-4: absolute for control points, relative for
+    eta) of that AME's final ground-state population with respect to the
+    schedule control points and eta, for the 16-control-point version of the
+    4-qubit ring (every parameter, --grad4) and of the 8-qubit instance (a
+    subset of the parameters, --grad8; each AME solve there takes minutes).
 """
 import json
 import os
 import sys
+
+if "--grad4" in sys.argv or "--grad8" in sys.argv:
+    os.environ.setdefault("OMP_NUM_THREADS", "1")   # one BLAS thread per worker process
+    os.environ.setdefault("OPENBLAS_NUM_THREADS", "1")
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, os.path.dirname(os.path.dirname(HERE)))
@@ -55,7 +64,37 @@ def ame_small():
                    "pgs": [float(p) for p in P]}, f)
 
 
+def _fd_worker(args):
+    inst, kind, j, h = args
+    from oracle import gradient
+    ip, step = gradient._perturbed(inst, kind, j, +1.0, h)
+    im, _ = gradient._perturbed(inst, kind, j, -1.0, h)
+    return (gradient.final_pgs(ip) - gradient.final_pgs(im)) / (2.0 * step)
+
+
+def fd_golden(inst, params, fname, workers):
+    from concurrent.futures import ProcessPoolExecutor
+    h = 1e-4
+    with ProcessPoolExecutor(max_workers=workers) as ex:
+        vals = list(ex.map(_fd_worker, [(inst, k, j, h) for k, j in params]))
+    with open(os.path.join(HERE, fname), "w") as f:
+        json.dump({"source": "central differences of oracle.gradient.final_pgs (split-step AME) over "
+                             "workloads instance " + inst.name,
+                   "instance": inst.name, "n_grid": inst.n_grid, "t_f": inst.t_f, "h": h,
+                   "params": [[k, j] for k, j in params], "grad": [float(v) for v in vals]}, f, indent=1)
+
+
 if __name__ == "__main__":
+    if "--grad4" in sys.argv:
+        from oracle import gradient
+        inst = workloads.config_small_ctrl()
+        fd_golden(inst, gradient.parameter_list(inst), "small_ctrl16_fd_gradient.json", 8)
+        sys.exit(0)
+    if "--grad8" in sys.argv:
+        inst = workloads.config_gradient(10)
+        params = [("A", 4), ("A", 8), ("B", 4), ("B", 8), ("eta", 0)]
+        fd_golden(inst, params, "a2a8_ctrl16_fd_gradient.json", 5)
+        sys.exit(0)
     if "--ame" in sys.argv:
         ame_a2a8()
         sys.exit(0)

@@ -86,13 +86,13 @@ def test_fp64_two_level_gradient_per_trajectory():
 @pytest.mark.parametrize("prec,K", [("fp32", 20000), ("fp64", 20000)])
 def test_gradient_mean_matches_ame_differences(prec, K):
     """The estimator's mean against central differences of the FP64 split-step AME,
-    within three standard errors (plus 1e-3 of the largest component in FP32)."""
+    within 3.5 standard errors per component (plus 1e-3 of the largest component in FP32)."""
     inst = _ring3()
     fd = gradient.fd_gradient(inst)
     ref = np.concatenate([fd["dA"], fd["dB"], [fd["deta"]]])
     eng = _engine(inst)
     out = eng.grad_pgs(K, prec, seed=inst.seed, instance_id=inst.instance_id)
-    tol = 3.0 * out["grad_se"] + (1e-3 * np.abs(ref).max() if prec == "fp32" else 1e-5)
+    tol = 3.5 * out["grad_se"] + (1e-3 * np.abs(ref).max() if prec == "fp32" else 1e-5)
     assert np.all(np.abs(out["grad"] - ref) <= tol), (out["grad"], ref, out["grad_se"])
     assert np.sum(np.abs(ref) > 5.0 * out["grad_se"]) >= 4
 
@@ -117,3 +117,21 @@ def test_gradient_argument_errors():
     eng.precompute(21, 8)
     out = eng.grad_pgs(16, "fp32")
     assert np.all(np.isfinite(out["grad"]))
+
+
+def test_gradient_matches_stored_ame_differences_4q():
+    """4-qubit ring workload with 16 + 16 control points: every component of the FP32
+    estimate from 10^5 trajectories against the stored central differences of the FP64
+    split-step AME (tests/golden/make_golden.py --grad4) within four standard errors per
+    component (33 components: about 0.2% chance of a false alarm)."""
+    import json
+    import os
+    ref = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "small_ctrl16_fd_gradient.json")))
+    inst = W.config_small_ctrl(100_000)
+    eng = _engine(inst)
+    out = eng.grad_pgs(inst.n_traj, "fp32", seed=inst.seed, instance_id=inst.instance_id)
+    fd = np.array(ref["grad"])
+    assert len(fd) == len(out["grad"])
+    tol = 4.0 * out["grad_se"] + 1e-3 * np.abs(fd[:-1]).max() * np.r_[np.ones(len(fd) - 1), 0.0]
+    assert np.all(np.abs(out["grad"] - fd) <= tol), (out["grad"], fd, out["grad_se"])
+    assert np.sum(np.abs(fd) > 5.0 * out["grad_se"]) >= 5

@@ -133,6 +133,19 @@ def config_a2a8(n_traj: int = 10_000) -> Instance:
     return pm1_all_to_all(8, A2A8_SEED, n_grid=2000, n_traj=n_traj, t_f=1.0e4)
 
 
+def config_gradient(n_traj: int = 100_000, n_ctrl: int = 16) -> Instance:
+    """The 8-qubit all-to-all anneal with A(s) and B(s) given by n_ctrl piecewise-linear
+    control points each (initialised to the linear schedule): the gradient workload."""
+    A, B = linear_schedule(n_ctrl)
+    return config_a2a8(n_traj).with_(A_ctrl=A, B_ctrl=B, name=f"a2a8-seed{A2A8_SEED}-ctrl{n_ctrl}")
+
+
+def config_small_ctrl(n_traj: int = 100_000, n_ctrl: int = 16) -> Instance:
+    """The 4-qubit ring workload with n_ctrl control points per schedule (gradient checks)."""
+    A, B = linear_schedule(n_ctrl)
+    return config_small().with_(A_ctrl=A, B_ctrl=B, n_traj=n_traj, name=f"ring4-seed1001-ctrl{n_ctrl}")
+
+
 def gadget_instance(m: int, n_levels: int = 32, n_grid: int = 500, t_f: float = 1.0e4,
                     n_traj: int = 100_000, seed: int = 1604) -> Instance:
     """Two-cluster tunnelling gadget on 2m qubits: cluster A = qubits 0..m-1 (field
