@@ -54,6 +54,8 @@ struct aqt_ctx {
   aqt::DevBuf dzd;      // [M][2][nq][NP] d z_i[x][x]
   aqt::DevBuf dll;      // [M][2][nq][NP(b)][NP(a)] d log |l_i,ab|
   aqt::DevBuf dcin;     // [2][NP] derivative of the initial state through grid 0
+  int gpk_prec = -1;    // precision of the sweep operands below, -1 = none
+  aqt::DevBuf gpk_D, gpk_DT, gpk_X;   // O_g - I, its transpose, X_g in that precision
 
   // ---- per-precision packed operands of the step kernel (built lazily)
   int packed_for = -1;      // aqt_precision the packs below hold, -1 = none

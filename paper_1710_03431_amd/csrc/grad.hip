@@ -54,7 +54,7 @@
 namespace aqt {
 namespace {
 
-constexpr int kGW = 4;              // wavefronts per workgroup
+constexpr int kGW = 8;              // wavefronts per workgroup
 constexpr int kGThreads = kGW * 64;
 constexpr int kMaxSeg = 64;         // steps per checkpoint segment
 constexpr int kMaxJ = 64;           // omega = 0 jumps of one trajectory within one step
@@ -79,7 +79,9 @@ template <> struct Mfma<double> {
 };
 
 struct GradArgs {
-  const double* dlt;     // [M][NP][NP] O_g - I
+  const void* pD;        // [M][NP][NP] O_g - I in the state precision
+  const void* pDT;       // [M][NP][NP] its transpose
+  const void* pX;        // [M][2][NP][NP] X_g in the state precision
   const double* cinit;   // [NP]
   const double* E;       // [M][NP]
   const double* Gam;     // [M][NP]
@@ -106,55 +108,95 @@ struct GradArgs {
   int64_t K, tile0;
 };
 
-// Y = (I + A) B or (I + A^T) B over NP x NC; A row-major FP64 in global memory, B and Y
-// in LDS with leading dimension LD.  Y must not alias B.
-template <int NP, int NC, int LD, class T>
-__device__ void gemm_kick(const double* __restrict__ A, bool trans, const T* B, T* Y) {
-  constexpr int RT = NP / 16, CT = NC / 16;
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  for (int tile = wave; tile < RT * CT; tile += kGW) {
-    const int rt = tile / CT, ct = tile - rt * CT;
-    const int row = rt * 16 + (lane & 15), kk = lane >> 4, col = ct * 16 + (lane & 15);
-    typename Mfma<T>::acc_t acc = Mfma<T>::zero();
-#pragma unroll 8
-    for (int k0 = 0; k0 < NP; k0 += 4) {
-      const int k = k0 + kk;
-      const double av = trans ? A[static_cast<size_t>(k) * NP + row] : A[static_cast<size_t>(row) * NP + k];
-      acc = Mfma<T>::step(static_cast<T>(av), B[k * LD + col], acc);
-    }
+// Operand A of the products below: an NP x NP row-major matrix in the state precision
+// (packed copies of O_g - I, its transpose and X_g), read straight into registers.  Each
+// wave owns whole 16-row tiles; lane (r, q) of the 16 x 4 fragment grid loads VW
+// consecutive entries A[row][k..k+VW) with one 16-byte load, so one MFMA step takes
+// k = 4 VW j + VW q + e (e < VW) from lane q: any bijection of k onto (step, lane
+// group) is a valid contraction as long as A and B use the same one.
+template <class T> struct Vec;
+template <> struct Vec<float> { using t = float __attribute__((ext_vector_type(4))); static constexpr int W = 4; };
+template <> struct Vec<double> { using t = double __attribute__((ext_vector_type(2))); static constexpr int W = 2; };
+
+// acc[b][ct] += A[rows of tile rt][:] * B_b[:, columns of tile ct] for NB LDS operands.
+template <int NP, int NC, int LD, class T, int NB>
+__device__ __forceinline__ void panel_mma(const T* __restrict__ A, int rt, const T* const (&B)[NB],
+                                          typename Mfma<T>::acc_t (&acc)[NB][NC / 16]) {
+  constexpr int VW = Vec<T>::W;
+  constexpr int NJ = NP / (4 * VW);                // vector loads per lane for the whole panel
+  constexpr int JCH = (NJ < 8) ? NJ : 8;           // loads kept in flight
+  using V = typename Vec<T>::t;
+  const int lane = threadIdx.x & 63, q = lane >> 4, c = lane & 15;
+  const V* arow = reinterpret_cast<const V*>(A + static_cast<size_t>(rt * 16 + c) * NP) + q;
+#pragma unroll 1
+  for (int j0 = 0; j0 < NJ; j0 += JCH) {
+    V av[JCH];
 #pragma unroll
-    for (int e = 0; e < 4; ++e) {
-      const int r = rt * 16 + Mfma<T>::row(lane, e);
-      Y[r * LD + col] = acc[e] + B[r * LD + col];
-    }
+    for (int u = 0; u < JCH; ++u) av[u] = arow[(j0 + u) * 4];
+#pragma unroll
+    for (int u = 0; u < JCH; ++u)
+#pragma unroll
+      for (int e = 0; e < VW; ++e) {
+        const int k = (j0 + u) * 4 * VW + q * VW + e;
+#pragma unroll
+        for (int b = 0; b < NB; ++b)
+#pragma unroll
+          for (int ct = 0; ct < NC / 16; ++ct)
+            acc[b][ct] = Mfma<T>::step(av[u][e], B[b][k * LD + ct * 16 + c], acc[b][ct]);
+      }
   }
 }
 
-// part[t] += Re <L_t | X | B_t> for the TT trajectories (columns 2t, 2t+1 = re, im);
-// each wave adds to its own part row.
+// Y = (I + A) B over NP x NC (A = O_g - I or its transpose); B and Y in LDS, Y != B.
 template <int NP, int NC, int LD, class T>
-__device__ void gemm_dot(const double* __restrict__ X, const T* B, const T* L, double* part) {
+__device__ void gemm_kick(const T* __restrict__ A, const T* B, T* Y) {
   constexpr int RT = NP / 16, CT = NC / 16;
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  for (int tile = wave; tile < RT * CT; tile += kGW) {
-    const int rt = tile / CT, ct = tile - rt * CT;
-    const int row = rt * 16 + (lane & 15), kk = lane >> 4, col = ct * 16 + (lane & 15);
-    typename Mfma<T>::acc_t acc = Mfma<T>::zero();
-#pragma unroll 8
-    for (int k0 = 0; k0 < NP; k0 += 4) {
-      const int k = k0 + kk;
-      acc = Mfma<T>::step(static_cast<T>(X[static_cast<size_t>(row) * NP + k]), B[k * LD + col], acc);
-    }
-    double s = 0.0;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, c = lane & 15;
+  const T* const Bs[1] = {B};
+  for (int rt = wave; rt < RT; rt += kGW) {
+    typename Mfma<T>::acc_t acc[1][CT];
 #pragma unroll
-    for (int e = 0; e < 4; ++e) {
-      const int r = rt * 16 + Mfma<T>::row(lane, e);
-      s += static_cast<double>(L[r * LD + col]) * static_cast<double>(acc[e]);
-    }
-    s += __shfl_xor(s, 16, 64);
-    s += __shfl_xor(s, 32, 64);
-    s += __shfl_xor(s, 1, 64);
-    if (lane < 16 && !(lane & 1)) part[(ct * 16 + lane) >> 1] += s;
+    for (int ct = 0; ct < CT; ++ct) acc[0][ct] = Mfma<T>::zero();
+    panel_mma<NP, NC, LD, T, 1>(A, rt, Bs, acc);
+#pragma unroll
+    for (int ct = 0; ct < CT; ++ct)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int r = rt * 16 + Mfma<T>::row(lane, e), col = ct * 16 + c;
+        Y[r * LD + col] = acc[0][ct][e] + B[r * LD + col];
+      }
+  }
+}
+
+// part[2 b][t] += Re <L_b,t | X | B_b,t> for the TT trajectories of each of the NB
+// operand pairs (columns 2t, 2t+1 = re, im); each wave adds to its own part rows.
+template <int NP, int NC, int LD, class T, int NB>
+__device__ void gemm_dot(const T* __restrict__ X, const T* const (&B)[NB], const T* const (&L)[NB], double* part,
+                         int pstride) {
+  constexpr int RT = NP / 16, CT = NC / 16;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, c = lane & 15;
+  for (int rt = wave; rt < RT; rt += kGW) {
+    typename Mfma<T>::acc_t acc[NB][CT];
+#pragma unroll
+    for (int b = 0; b < NB; ++b)
+#pragma unroll
+      for (int ct = 0; ct < CT; ++ct) acc[b][ct] = Mfma<T>::zero();
+    panel_mma<NP, NC, LD, T, NB>(X, rt, B, acc);
+#pragma unroll
+    for (int b = 0; b < NB; ++b)
+#pragma unroll
+      for (int ct = 0; ct < CT; ++ct) {
+        double s = 0.0;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const int r = rt * 16 + Mfma<T>::row(lane, e);
+          s += static_cast<double>(L[b][r * LD + ct * 16 + c]) * static_cast<double>(acc[b][ct][e]);
+        }
+        s += __shfl_xor(s, 16, 64);
+        s += __shfl_xor(s, 32, 64);
+        s += __shfl_xor(s, 1, 64);
+        if (lane < 16 && !(lane & 1)) part[b * pstride + ((ct * 16 + lane) >> 1)] += s;
+      }
   }
 }
 
@@ -427,7 +469,7 @@ __global__ __launch_bounds__(kGThreads) void k_grad(GradArgs a) {
         sh.PA[x * LD + col] = (!(col & 1) && active(col >> 1)) ? static_cast<T>(a.cinit[x]) : static_cast<T>(0);
       }
     } else {
-      gemm_kick<NP, NC, LD, T>(a.dlt + static_cast<size_t>(g) * NP * NP, false, sh.PB, sh.PA);
+      gemm_kick<NP, NC, LD, T>(static_cast<const T*>(a.pD) + static_cast<size_t>(g) * NP * NP, sh.PB, sh.PA);
     }
   };
   auto forward = [&](int g) {   // PB = step g (PA); advances the cursors
@@ -538,9 +580,16 @@ __global__ __launch_bounds__(kGThreads) void k_grad(GradArgs a) {
       __syncthreads();
       // basis-change terms of grid g
       for (int dir = 0; dir < 2; ++dir) {
-        const double* X = a.Xd + (static_cast<size_t>(g) * 2 + dir) * NP * NP;
-        gemm_dot<NP, NC, LD, T>(X, sh.PA, sh.LA, sh.part[wave][2 * dir]);
-        if (g < a.M - 1) gemm_dot<NP, NC, LD, T>(X, sh.PB, sh.LB, sh.part[wave][2 * dir + 1]);
+        const T* X = static_cast<const T*>(a.pX) + (static_cast<size_t>(g) * 2 + dir) * NP * NP;
+        if (g < a.M - 1) {
+          const T* const B2[2] = {sh.PA, sh.PB};
+          const T* const L2[2] = {sh.LA, sh.LB};
+          gemm_dot<NP, NC, LD, T, 2>(X, B2, L2, &sh.part[wave][2 * dir][0], TT);
+        } else {
+          const T* const B1[1] = {sh.PA};
+          const T* const L1[1] = {sh.LA};
+          gemm_dot<NP, NC, LD, T, 1>(X, B1, L1, &sh.part[wave][2 * dir][0], TT);
+        }
       }
       __syncthreads();
       for (int t = tid; t < TT; t += kGThreads) {
@@ -566,7 +615,7 @@ __global__ __launch_bounds__(kGThreads) void k_grad(GradArgs a) {
         if (g == a.M - 1) o[0] = sh.f[t];
       }
       // adjoint before the kick: lambda_B(g - 1) = O_g^T lambda_A(g)
-      if (g >= 2) gemm_kick<NP, NC, LD, T>(a.dlt + static_cast<size_t>(g) * NP * NP, true, sh.LA, sh.LB);
+      if (g >= 2) gemm_kick<NP, NC, LD, T>(static_cast<const T*>(a.pDT) + static_cast<size_t>(g) * NP * NP, sh.LA, sh.LB);
       __syncthreads();
     }
   }
@@ -593,6 +642,23 @@ __global__ __launch_bounds__(256) void k_colstats(const double* __restrict__ out
   if (tid == 0) {
     stats[2 * c] = r1[0] + r1[1] + r1[2] + r1[3];
     stats[2 * c + 1] = r2[0] + r2[1] + r2[2] + r2[3];
+  }
+}
+
+// State-precision copies of O_g - I, its transpose and X_g for the sweep's products.
+template <class T>
+__global__ void k_grad_pack(const double* __restrict__ dlt, const double* __restrict__ Xd, int M, int NP,
+                            T* __restrict__ D, T* __restrict__ DT, T* __restrict__ X) {
+  const int64_t per = static_cast<int64_t>(NP) * NP;
+  const int64_t tot = per * M;
+  for (int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < tot;
+       i += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+    const int64_t g = i / per, r = i - g * per;
+    const int a = static_cast<int>(r / NP), b = static_cast<int>(r - static_cast<int64_t>(a) * NP);
+    D[i] = static_cast<T>(dlt[i]);
+    DT[i] = static_cast<T>(dlt[g * per + static_cast<int64_t>(b) * NP + a]);
+    X[2 * g * per + r] = static_cast<T>(Xd[2 * g * per + r]);
+    X[(2 * g + 1) * per + r] = static_cast<T>(Xd[(2 * g + 1) * per + r]);
   }
 }
 
@@ -663,7 +729,6 @@ aqt_status launch_grad(aqt_ctx* ctx, const aqt_run_params* p, double* value, dou
   AQT_HIP(ctx, hipMemsetAsync(status.p, 0, 4, st));
 
   GradArgs ga{};
-  ga.dlt = ctx->dlt.as<double>();
   ga.cinit = ctx->cinit.as<double>();
   ga.E = ctx->E.as<double>();
   ga.Gam = ctx->Gamma.as<double>();
@@ -693,6 +758,25 @@ aqt_status launch_grad(aqt_ctx* ctx, const aqt_run_params* p, double* value, dou
   if (!(ga.eta > 0.0)) return ctx->fail(AQT_EINVAL, "the gradient needs eta > 0");
 
   const bool f64 = p->precision == AQT_FP64;
+  if (ctx->gpk_prec != p->precision) {
+    const size_t el = f64 ? 8 : 4, per = static_cast<size_t>(NP) * NP * ctx->M;
+    if (ctx->gpk_D.reserve(per * el) || ctx->gpk_DT.reserve(per * el) || ctx->gpk_X.reserve(2 * per * el))
+      return ctx->fail(AQT_ENOMEM, "gradient operand allocation failed");
+    const unsigned blocks = static_cast<unsigned>(std::min<size_t>(65536, (per + 255) / 256));
+    if (f64)
+      hipLaunchKernelGGL(k_grad_pack<double>, dim3(blocks), dim3(256), 0, st, ctx->dlt.as<double>(),
+                         ctx->Xd.as<double>(), ctx->M, NP, ctx->gpk_D.as<double>(), ctx->gpk_DT.as<double>(),
+                         ctx->gpk_X.as<double>());
+    else
+      hipLaunchKernelGGL(k_grad_pack<float>, dim3(blocks), dim3(256), 0, st, ctx->dlt.as<double>(),
+                         ctx->Xd.as<double>(), ctx->M, NP, ctx->gpk_D.as<float>(), ctx->gpk_DT.as<float>(),
+                         ctx->gpk_X.as<float>());
+    AQT_HIP(ctx, hipGetLastError());
+    ctx->gpk_prec = p->precision;
+  }
+  ga.pD = ctx->gpk_D.p;
+  ga.pDT = ctx->gpk_DT.p;
+  ga.pX = ctx->gpk_X.p;
   aqt_status s = AQT_OK;
 #define AQT_SWEEP(np, tt, T) s = launch_sweep<np, tt, T>(ctx, ga, (K + (tt) - 1) / (tt))
   switch (NP) {

@@ -1111,6 +1111,7 @@ aqt_status precompute_tables(aqt_ctx* ctx, int M, int n, double tol, int method,
   const int nq = ctx->nq;
   const int N = 1 << nq;
   ctx->have_grad = false;
+  ctx->gpk_prec = -1;
   if (grad && n != N) return ctx->fail(AQT_EINVAL, "gradient tables need the full spectrum (n_levels = 2^n_qubits)");
   const bool iterative = (method == AQT_EIG_ITERATIVE) || (method == AQT_EIG_AUTO && N > kEigMaxN);
   const int ncols = std::min(N, n + 16);   // levels solved for: n plus a guard for clusters at the cut
