@@ -1114,14 +1114,35 @@ hipError_t launch_mode(int NP, int TQ, const StepArgs& a, int64_t blocks, hipStr
 // Column tiles per workgroup: minimise the largest per-CU load
 // ceil(workgroups / CUs) * TQ (every workgroup does the same work per
 // trajectory-step), preferring larger tiles on ties (fewer overlap re-reads).
+// Trajectories per workgroup (TQ column tiles of 8).  >= 128 levels: one workgroup per
+// CU, so the launch takes ceil(workgroups / CUs) rounds, each costing the measured
+// time of one tile of that width (relative units, n = 256 on MI355X; wider tiles
+// amortise the overlap operand over more trajectories).  Smaller level counts fit
+// several workgroups per CU: the widest tile that still gives every CU a workgroup.
 int choose_tq(int NP, int precision, int64_t K, int cus) {
   const int64_t tiles8 = (K + 7) / 8;
+  const bool f64 = precision == AQT_FP64;
+  if (NP <= 64) {
+    int best = 1;
+    for (int tq : kTQ)
+      if (tq_allowed(NP, tq, f64) && (tiles8 + tq - 1) / tq >= cus) best = tq > best ? tq : best;
+    return best;
+  }
+  auto round_cost = [&](int tq) -> int64_t {
+    if (f64) return tq == 1 ? 24 : 43;
+    switch (tq) {
+      case 1: return 30;
+      case 2: return 63;
+      case 4: return 44;
+      default: return 59;
+    }
+  };
   int best = 1;
   int64_t best_cost = INT64_MAX;
   for (int tq : kTQ) {
-    if (!tq_allowed(NP, tq, precision == AQT_FP64)) continue;
+    if (!tq_allowed(NP, tq, f64)) continue;
     const int64_t wgs = (tiles8 + tq - 1) / tq;
-    const int64_t cost = ((wgs + cus - 1) / cus) * tq;
+    const int64_t cost = ((wgs + cus - 1) / cus) * round_cost(tq);
     if (cost < best_cost || (cost == best_cost && tq > best)) {
       best = tq;
       best_cost = cost;
