@@ -203,7 +203,9 @@ __device__ void gemm_dot(const T* __restrict__ X, const T* const (&B)[NB], const
 template <int NP, int TT, class T>
 struct GradShared {
   static constexpr int NC = 2 * TT;
-  static constexpr int LD = NC + 1;
+  // FP32: 4 LD = 16 (mod 64) puts the four k rows of an MFMA operand read in disjoint bank
+  // ranges; FP64 keeps the smallest odd stride (LDS budget at 256 levels)
+  static constexpr int LD = (sizeof(T) == 4 && NC == 32) ? 36 : NC + 1;
   T PA[NP * LD];                 // psi just after the step's kick
   T PB[NP * LD];                 // psi at the end of the step
   T LA[NP * LD];                 // adjoints at the same points
@@ -666,7 +668,7 @@ template <int NP, int TT, class T>
 aqt_status launch_sweep(aqt_ctx* ctx, GradArgs& ga, int64_t tiles) {
   constexpr int NC = 2 * TT;
   const size_t per_tile = (static_cast<size_t>(ga.S) + ga.C) * NP * NC * sizeof(T) + static_cast<size_t>(ga.S) * TT * 4;
-  const size_t budget = size_t(16) << 30;
+  const size_t budget = size_t(40) << 30;   // of 288 GB: 10^5 trajectories at 256 levels in one launch
   const int64_t chunk = std::max<int64_t>(1, std::min<int64_t>(tiles, static_cast<int64_t>(budget / per_tile)));
   DevBuf ws;
   if (ws.reserve(per_tile * chunk) != hipSuccess) return ctx->fail(AQT_ENOMEM, "gradient workspace allocation failed");
