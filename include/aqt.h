@@ -85,7 +85,8 @@ typedef struct {
   uint64_t instance_id;     /* Philox key word 1                                    */
   uint64_t traj_offset;     /* trajectory ids are traj_offset .. traj_offset+K-1     */
   int32_t tile;             /* trajectories per workgroup: 8, 16, 32, 40 or 64 (0: auto) */
-  int32_t reserved;
+  int32_t segment;          /* aqt_grad_pgs only: steps per checkpoint segment of the
+                               adjoint sweep (0: automatic); ignored by aqt_run       */
 } aqt_run_params;
 
 /* Device output buffers of aqt_run (any pointer may be NULL to skip it). */
@@ -187,7 +188,10 @@ AQT_API aqt_status aqt_run(aqt_ctx* ctx, const aqt_run_params* params, const aqt
  * forward steps.  Eigenvector derivatives use first-order perturbation theory with
  * the canonical in-cluster basis held fixed.
  *   params:   as aqt_run (precision AQT_FP64 or AQT_FP32, n_traj >= 2; record_capacity
- *             is ignored: the paths are recorded internally).  The trajectories are
+ *             is ignored: the paths are recorded internally; segment > 0 forces
+ *             checkpoint segments of that many steps, else the sweep keeps every
+ *             post-kick state when the workspace allows, with segments of about
+ *             sqrt(n_grid) steps otherwise; segment < 0 is AQT_EINVAL).  The trajectories are
  *             the ones aqt_run draws with the same params.
  *   value, value_se: host, mean and standard error of P_GS(1) (may be NULL).
  *   grad, grad_se:   host [2m+1], mean estimate and its standard error (may be NULL).

@@ -35,7 +35,7 @@ class Jump(C.Structure):
 class RunParams(C.Structure):
     _fields_ = [("precision", C.c_int32), ("record_capacity", C.c_int32), ("n_traj", C.c_int64),
                 ("seed", C.c_uint64), ("instance_id", C.c_uint64), ("traj_offset", C.c_uint64),
-                ("tile", C.c_int32), ("reserved", C.c_int32)]
+                ("tile", C.c_int32), ("segment", C.c_int32)]
 
 
 class Outputs(C.Structure):
@@ -237,7 +237,7 @@ class Engine:
         prec = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
         p = RunParams(precision=prec, record_capacity=int(record_capacity), n_traj=int(n_traj),
                       seed=int(seed), instance_id=int(instance_id), traj_offset=int(traj_offset),
-                      tile=int(tile), reserved=0)
+                      tile=int(tile), segment=0)
 
         def ptr(k):
             v = outs.get(k)
@@ -267,11 +267,12 @@ class Engine:
 
     # ---------------------------------------------------------------- gradient
     def grad_pgs(self, n_traj: int, precision="fp32", seed=0, instance_id=0, traj_offset=0, tile=0,
-                 per_trajectory=False):
+                 per_trajectory=False, segment=0):
         """Gradient of E[P_GS(1)] with respect to (A controls, B controls, eta) (synchronises).
         Returns value, value_se, grad, grad_se and, on request, per_traj [K][2m+2]."""
         m = self.n_ctrl
         p = _params(n_traj, precision, seed, instance_id, traj_offset, 0, tile)
+        p.segment = int(segment)
         v, vse = np.zeros(1), np.zeros(1)
         g, gse = np.zeros(2 * m + 1), np.zeros(2 * m + 1)
         pt = None
@@ -289,7 +290,7 @@ class Engine:
 def _params(n_traj, precision, seed, instance_id, traj_offset, record_capacity, tile):
     prec = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
     return RunParams(precision=prec, record_capacity=int(record_capacity), n_traj=int(n_traj), seed=int(seed),
-                     instance_id=int(instance_id), traj_offset=int(traj_offset), tile=int(tile), reserved=0)
+                     instance_id=int(instance_id), traj_offset=int(traj_offset), tile=int(tile), segment=0)
 
 
 def _outputs(outs):

@@ -272,6 +272,7 @@ aqt_status aqt_grad_pgs(aqt_ctx* ctx, const aqt_run_params* p, double* value, do
   if (p->n_traj < 2) return ctx->fail(AQT_EINVAL, "n_traj must be >= 2");
   if (p->precision != AQT_FP64 && p->precision != AQT_FP32)
     return ctx->fail(AQT_EINVAL, "the gradient runs in AQT_FP64 or AQT_FP32");
+  if (p->segment < 0) return ctx->fail(AQT_EINVAL, "segment must be >= 0");
   aqt_status s = set_device(ctx);
   if (s != AQT_OK) return s;
   if (!ctx->have_grad) {

@@ -56,7 +56,6 @@ namespace {
 
 constexpr int kGW = 8;              // wavefronts per workgroup
 constexpr int kGThreads = kGW * 64;
-constexpr int kMaxSeg = 64;         // steps per checkpoint segment
 constexpr int kMaxJ = 64;           // omega = 0 jumps of one trajectory within one step
 
 typedef float f4 __attribute__((ext_vector_type(4)));
@@ -101,6 +100,7 @@ struct GradArgs {
   void* ckpt;            // [tiles][S][NP][NC] states after steps sC
   int* ckcur;            // [tiles][S][TT] record cursors there
   void* seg;             // [tiles][C][NP][NC] post-kick states of the segment
+  int* scur;             // [tiles][C][TT] record cursor at the start of each step of the segment
   double* out;           // [K][1 + P]: f, then dP/dA_j, dP/dB_j, dP/deta
   int* status;           // bit 0: more than kMaxJ omega = 0 jumps in one step
   int M, nq, nctrl, C, S;
@@ -211,7 +211,6 @@ struct GradShared {
   T LA[NP * LD];                 // adjoints at the same points
   T LB[NP * LD];
   int cur[TT];                   // running record cursor
-  int scur[kMaxSeg][TT];         // record cursor at the start of each step of the segment
   double f[TT];                  // final ground-cluster population
   double S[TT][3];               // handler terms of the current grid point (A, B, eta)
   double part[kGW][4][TT];       // X-term partial sums
@@ -459,6 +458,7 @@ __global__ __launch_bounds__(kGThreads) void k_grad(GradArgs a) {
   T* ck = static_cast<T*>(a.ckpt) + lt * a.S * NP * NC;
   int* ckc = a.ckcur + lt * a.S * TT;
   T* sg = static_cast<T*>(a.seg) + lt * a.C * NP * NC;
+  int* scur = a.scur + lt * a.C * TT;
   auto traj = [&](int t) { return tile * TT + t; };
   auto active = [&](int t) { return traj(t) < a.K; };
   auto recs = [&](int t) { return a.jumps + traj(t) * a.cap; };
@@ -484,7 +484,7 @@ __global__ __launch_bounds__(kGThreads) void k_grad(GradArgs a) {
     }
   };
 
-  // ---- forward replay with checkpoints
+  // ---- forward replay with checkpoints (not needed when one segment spans the anneal)
   for (int t = tid; t < TT; t += kGThreads) sh.cur[t] = 0;
   for (int f = tid; f < NP * LD; f += kGThreads) {
     sh.PB[f] = static_cast<T>(0);
@@ -492,7 +492,7 @@ __global__ __launch_bounds__(kGThreads) void k_grad(GradArgs a) {
     sh.LA[f] = static_cast<T>(0);
   }
   __syncthreads();
-  for (int g = 1; g < a.M; ++g) {
+  for (int g = 1; a.S > 1 && g < a.M; ++g) {
     kick(g);
     __syncthreads();
     forward(g);
@@ -513,7 +513,7 @@ __global__ __launch_bounds__(kGThreads) void k_grad(GradArgs a) {
     __syncthreads();
     for (int g = glo; g <= ghi; ++g) {
       kick(g);
-      for (int t = tid; t < TT; t += kGThreads) sh.scur[g - glo][t] = sh.cur[t];
+      for (int t = tid; t < TT; t += kGThreads) scur[(g - glo) * TT + t] = sh.cur[t];
       __syncthreads();
       tile_store<NP, NC, LD, T>(sh.PA, sg + static_cast<size_t>(g - glo) * NP * NC);
       if (g < ghi) forward(g);
@@ -529,7 +529,7 @@ __global__ __launch_bounds__(kGThreads) void k_grad(GradArgs a) {
           continue;
         }
         const aqt_jump* rec = recs(t);
-        const int m0 = sh.scur[g - glo][t];
+        const int m0 = scur[(g - glo) * TT + t];
         const int m1 = step_end(rec, count(t), m0, g);
         if (m1 - m0 > kMaxJ && lane == 0) a.status[0] = 1;
         replay_step<NP, LD, T>(a, g, rec, m0, m1, sh.PA, sh.PB, t, sh.rho[wave]);
@@ -664,18 +664,37 @@ __global__ void k_grad_pack(const double* __restrict__ dlt, const double* __rest
   }
 }
 
+// Segment length: the whole anneal (every post-kick state kept, no checkpoint pass)
+// when that fits the workspace budget for at least one CU-full of tiles; else about
+// sqrt(M - 1) steps with checkpoints.  Launches take whole CU-fulls of tiles.
 template <int NP, int TT, class T>
-aqt_status launch_sweep(aqt_ctx* ctx, GradArgs& ga, int64_t tiles) {
+aqt_status launch_sweep(aqt_ctx* ctx, GradArgs& ga, int64_t tiles, int cus, int seg_req) {
   constexpr int NC = 2 * TT;
-  const size_t per_tile = (static_cast<size_t>(ga.S) + ga.C) * NP * NC * sizeof(T) + static_cast<size_t>(ga.S) * TT * 4;
-  const size_t budget = size_t(40) << 30;   // of 288 GB: 10^5 trajectories at 256 levels in one launch
-  const int64_t chunk = std::max<int64_t>(1, std::min<int64_t>(tiles, static_cast<int64_t>(budget / per_tile)));
+  const size_t budget = size_t(40) << 30;   // of 288 GB HBM
+  auto per_tile = [&](int C, int S) {
+    return (static_cast<size_t>(S) + C) * NP * NC * sizeof(T) + (static_cast<size_t>(S) + C) * TT * 4;
+  };
+  const int steps = ga.M - 1;
+  const int64_t want = std::min<int64_t>(tiles, cus);
+  if (seg_req > 0) {
+    ga.C = std::min(seg_req, steps);
+  } else if (static_cast<int64_t>(budget / per_tile(steps, 1)) >= want) {
+    ga.C = steps;
+  } else {
+    ga.C = std::max(1, static_cast<int>(std::ceil(std::sqrt(static_cast<double>(steps)))));
+  }
+  ga.S = (steps + ga.C - 1) / ga.C;
+  const size_t pt = per_tile(ga.C, ga.S);
+  int64_t chunk = std::max<int64_t>(1, std::min<int64_t>(tiles, static_cast<int64_t>(budget / pt)));
+  if (chunk < tiles && chunk >= cus) chunk = (chunk / cus) * cus;
   DevBuf ws;
-  if (ws.reserve(per_tile * chunk) != hipSuccess) return ctx->fail(AQT_ENOMEM, "gradient workspace allocation failed");
+  if (ws.reserve(pt * chunk) != hipSuccess) return ctx->fail(AQT_ENOMEM, "gradient workspace allocation failed");
   char* base = static_cast<char*>(ws.p);
+  const size_t st = static_cast<size_t>(chunk) * NP * NC * sizeof(T);
   ga.ckpt = base;
-  ga.seg = base + static_cast<size_t>(chunk) * ga.S * NP * NC * sizeof(T);
-  ga.ckcur = reinterpret_cast<int*>(base + static_cast<size_t>(chunk) * (ga.S + ga.C) * NP * NC * sizeof(T));
+  ga.seg = base + st * ga.S;
+  ga.ckcur = reinterpret_cast<int*>(base + st * (ga.S + ga.C));
+  ga.scur = ga.ckcur + static_cast<size_t>(chunk) * ga.S * TT;
   for (int64_t t0 = 0; t0 < tiles; t0 += chunk) {
     ga.tile0 = t0;
     const int64_t nt = std::min(chunk, tiles - t0);
@@ -752,14 +771,20 @@ aqt_status launch_grad(aqt_ctx* ctx, const aqt_run_params* p, double* value, dou
   ga.M = ctx->M;
   ga.nq = ctx->nq;
   ga.nctrl = nctrl;
-  ga.C = std::min(kMaxSeg, std::max(1, static_cast<int>(std::ceil(std::sqrt(static_cast<double>(ctx->M - 1))))));
-  ga.S = (ctx->M - 1 + ga.C - 1) / ga.C;
   ga.dt = ctx->dt;
   ga.eta = ctx->eta;
   ga.K = K;
   if (!(ga.eta > 0.0)) return ctx->fail(AQT_EINVAL, "the gradient needs eta > 0");
 
   const bool f64 = p->precision == AQT_FP64;
+  int cus = 256;
+  {
+    int dev = 0;
+    hipDeviceProp_t prop;
+    if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess &&
+        prop.multiProcessorCount > 0)
+      cus = prop.multiProcessorCount;
+  }
   if (ctx->gpk_prec != p->precision) {
     const size_t el = f64 ? 8 : 4, per = static_cast<size_t>(NP) * NP * ctx->M;
     if (ctx->gpk_D.reserve(per * el) || ctx->gpk_DT.reserve(per * el) || ctx->gpk_X.reserve(2 * per * el))
@@ -780,7 +805,7 @@ aqt_status launch_grad(aqt_ctx* ctx, const aqt_run_params* p, double* value, dou
   ga.pDT = ctx->gpk_DT.p;
   ga.pX = ctx->gpk_X.p;
   aqt_status s = AQT_OK;
-#define AQT_SWEEP(np, tt, T) s = launch_sweep<np, tt, T>(ctx, ga, (K + (tt) - 1) / (tt))
+#define AQT_SWEEP(np, tt, T) s = launch_sweep<np, tt, T>(ctx, ga, (K + (tt) - 1) / (tt), cus, p->segment)
   switch (NP) {
     case 16: if (f64) AQT_SWEEP(16, 16, double); else AQT_SWEEP(16, 16, float); break;
     case 32: if (f64) AQT_SWEEP(32, 16, double); else AQT_SWEEP(32, 16, float); break;

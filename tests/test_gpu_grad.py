@@ -135,3 +135,21 @@ def test_gradient_matches_stored_ame_differences_4q():
     tol = 4.0 * out["grad_se"] + 1e-3 * np.abs(fd[:-1]).max() * np.r_[np.ones(len(fd) - 1), 0.0]
     assert np.all(np.abs(out["grad"] - fd) <= tol), (out["grad"], fd, out["grad_se"])
     assert np.sum(np.abs(fd) > 5.0 * out["grad_se"]) >= 5
+
+
+@pytest.mark.parametrize("segment", [1, 7, 33])
+def test_checkpoint_segments_do_not_change_results(segment):
+    """The sweep keeps every post-kick state here; forcing checkpoint segments (a forward
+    pass storing every segment-th state, then a replay per segment) reproduces the
+    same per-trajectory values bit for bit, including a ragged last tile."""
+    inst = _ring3()
+    eng = _engine(inst)
+    K = 40
+    a = eng.grad_pgs(K, "fp64", seed=inst.seed, instance_id=inst.instance_id, per_trajectory=True)
+    b = eng.grad_pgs(K, "fp64", seed=inst.seed, instance_id=inst.instance_id, per_trajectory=True,
+                     segment=segment)
+    np.testing.assert_array_equal(a["per_traj"], b["per_traj"])
+    c = eng.grad_pgs(K, "fp32", seed=inst.seed, instance_id=inst.instance_id, per_trajectory=True,
+                     segment=segment)
+    d = eng.grad_pgs(K, "fp32", seed=inst.seed, instance_id=inst.instance_id, per_trajectory=True)
+    np.testing.assert_array_equal(c["per_traj"], d["per_traj"])
