@@ -195,8 +195,12 @@ AQT_API aqt_status aqt_run(aqt_ctx* ctx, const aqt_run_params* params, const aqt
  *             the ones aqt_run draws with the same params.
  *   value, value_se: host, mean and standard error of P_GS(1) (may be NULL).
  *   grad, grad_se:   host [2m+1], mean estimate and its standard error (may be NULL).
- *   per_traj: device [n_traj][2m+2] or NULL: per trajectory f (final ground-cluster
- *             population) followed by its 2m+1 estimates.
+ *   per_traj: device [n_traj][2(2m+2)] or NULL: per trajectory f (final ground-cluster
+ *             population) and its 2m+1 estimates g, then 1 and the 2m+1 components of
+ *             s = d log |psi~|^2 (the path-density score, mean zero).
+ * The reported gradient is mean(g) - c mean(s) with c = Cov(g, s) / Var(s) per component
+ * (a control variate from the same trajectories: it removes the part of the score-function
+ * noise that does not depend on f; its bias is O(1/n_traj)); grad_se is its standard error.
  * Needs tables from aqt_precompute with n_levels = 2^n_qubits (AQT_ESTATE after
  * aqt_set_tables, AQT_EINVAL for truncated spectra); the first call after a
  * precompute re-runs the eigensolver to add the derivative tables.  AQT_ECAPACITY if

@@ -28,7 +28,9 @@ Two quantities are differentiated:
   f = <psi~|Pi|psi~> / |psi~|^2 the trajectory's own final ground-cluster
   population.  Here the derivative is taken by central differences of the log
   weight of the trajectory's own path (times and channels held fixed), rebuilt
-  from the tables of the perturbed instance.
+  from the tables of the perturbed instance.  The same with Pi replaced by the
+  identity gives s = d log |psi~|^2 / dtheta, the score of the path density,
+  whose mean is zero (the derivative of the total probability 1).
 """
 from __future__ import annotations
 
@@ -149,23 +151,25 @@ def replay_log_weight(tables, inst, paths, n_grid=None):
 
 def trajectory_gradients(inst, n_traj: int, h: float = 1e-4, which=("A", "B", "eta"),
                          traj_offset: int = 0) -> dict:
-    """Per-trajectory gradient estimates g[j, p] (module docstring) for the parameters of
-    parameter_list(inst, which), from trajectories.run on the instance's tables.
-    Also returns f[j] (final ground-cluster population), the recorded paths and the
-    final states of the replay."""
+    """Per-trajectory gradient estimates g[j, p] and path-density scores score[j, p]
+    (module docstring) for the parameters of parameter_list(inst, which), from
+    trajectories.run on the instance's tables.  Also returns f[j] (final ground-cluster
+    population), the recorded paths and the final states of the replay."""
     tabs = spectrum.all_tables(inst)
     res = trajectories.run(tabs, inst, n_traj, record=True, traj_offset=traj_offset)
     logW, logN, C = replay_log_weight(tabs, inst, res.jumps)
     f = np.exp(logW - logN)
     params = parameter_list(inst, which)
     g = np.zeros((n_traj, len(params)))
+    score = np.zeros((n_traj, len(params)))
     for col, (kind, j) in enumerate(params):
         ip, step = _perturbed(inst, kind, j, +1.0, h)
         im, _ = _perturbed(inst, kind, j, -1.0, h)
-        lp, _, _ = replay_log_weight(spectrum.all_tables(ip), ip, res.jumps)
-        lm, _, _ = replay_log_weight(spectrum.all_tables(im), im, res.jumps)
+        lp, np_, _ = replay_log_weight(spectrum.all_tables(ip), ip, res.jumps)
+        lm, nm_, _ = replay_log_weight(spectrum.all_tables(im), im, res.jumps)
+        score[:, col] = (np_ - nm_) / (2.0 * step)
         # a path that ends outside the ground cluster has zero weight for every theta
         with np.errstate(invalid="ignore"):
             g[:, col] = np.where(f > 0.0, f * (lp - lm) / (2.0 * step), 0.0)
-    return {"f": f, "g": g, "params": params, "jumps": res.jumps, "replay_state": C,
+    return {"f": f, "g": g, "score": score, "params": params, "jumps": res.jumps, "replay_state": C,
             "final_state": res.final_state}

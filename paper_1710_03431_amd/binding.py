@@ -269,7 +269,8 @@ class Engine:
     def grad_pgs(self, n_traj: int, precision="fp32", seed=0, instance_id=0, traj_offset=0, tile=0,
                  per_trajectory=False, segment=0):
         """Gradient of E[P_GS(1)] with respect to (A controls, B controls, eta) (synchronises).
-        Returns value, value_se, grad, grad_se and, on request, per_traj [K][2m+2]."""
+        Returns value, value_se, grad, grad_se and, on request, per_traj [K][2(2m+2)]
+        (f, g, then 1, s; see aqt_grad_pgs)."""
         m = self.n_ctrl
         p = _params(n_traj, precision, seed, instance_id, traj_offset, 0, tile)
         p.segment = int(segment)
@@ -278,7 +279,7 @@ class Engine:
         pt = None
         if per_trajectory:
             t = self.torch
-            pt = t.zeros((n_traj, 2 * m + 2), dtype=t.float64, device=t.device("cuda", self.device))
+            pt = t.zeros((n_traj, 2 * (2 * m + 2)), dtype=t.float64, device=t.device("cuda", self.device))
         self._check(self.lib.aqt_grad_pgs(self.ctx, C.byref(p), _dptr(v), _dptr(vse), _dptr(g), _dptr(gse),
                                           None if pt is None else pt.data_ptr()))
         out = {"value": float(v[0]), "value_se": float(vse[0]), "grad": g, "grad_se": gse}

@@ -101,7 +101,9 @@ struct GradArgs {
   int* ckcur;            // [tiles][S][TT] record cursors there
   void* seg;             // [tiles][C][NP][NC] post-kick states of the segment
   int* scur;             // [tiles][C][TT] record cursor at the start of each step of the segment
-  double* out;           // [K][1 + P]: f, then dP/dA_j, dP/dB_j, dP/deta
+  double* out;           // row j at out + j * ostride: f, then dP/dA_j, dP/dB_j, dP/deta
+  int ostride;
+  int proj;              // levels of the final projector: the ground cluster, or all (path-density score)
   int* status;           // bit 0: more than kMaxJ omega = 0 jumps in one step
   int M, nq, nctrl, C, S;
   double dt, eta;
@@ -536,7 +538,7 @@ __global__ __launch_bounds__(kGThreads) void k_grad(GradArgs a) {
         double f;
         if (g == a.M - 1) {
           // lambda = Pi psi / |psi|^2 with Pi the ground cluster of the last grid point
-          const int gsz = a.gs[a.M - 1];
+          const int gsz = a.proj;
           double nn = 0.0, pg = 0.0;
           for (int x = lane; x < NP; x += 64) {
             const double br = static_cast<double>(sh.PB[x * LD + 2 * t]), bi = static_cast<double>(sh.PB[x * LD + 2 * t + 1]);
@@ -568,7 +570,7 @@ __global__ __launch_bounds__(kGThreads) void k_grad(GradArgs a) {
           c0 = wave_sum(c0);
           c1 = wave_sum(c1);
           if (lane == 0) {
-            double* o = a.out + traj(t) * (1 + P);
+            double* o = a.out + traj(t) * a.ostride;
             o[1] += 2.0 * c0;            // grid 0: s = 0, weight 1 on control 0
             o[1 + a.nctrl] += 2.0 * c1;
           }
@@ -608,7 +610,7 @@ __global__ __launch_bounds__(kGThreads) void k_grad(GradArgs a) {
         const double u = static_cast<double>(g) / (a.M - 1) * (a.nctrl - 1);
         const int j = std::min(static_cast<int>(floor(u)), a.nctrl - 2);
         const double fr = u - j;
-        double* o = a.out + traj(t) * (1 + P);
+        double* o = a.out + traj(t) * a.ostride;
         o[1 + j] += (1.0 - fr) * xa[0];
         o[2 + j] += fr * xa[0];
         o[1 + a.nctrl + j] += (1.0 - fr) * xa[1];
@@ -623,28 +625,27 @@ __global__ __launch_bounds__(kGThreads) void k_grad(GradArgs a) {
   }
 }
 
-// Column sums and sums of squares of out[K][ncol] (one workgroup per column, fixed order).
-__global__ __launch_bounds__(256) void k_colstats(const double* __restrict__ out, int64_t K, int ncol,
+// Per column c < half of out[K][2 half]: sums of v = out[j][c], v^2, w = out[j][c + half],
+// w^2 and v w (one workgroup per column, fixed order).
+__global__ __launch_bounds__(256) void k_colstats(const double* __restrict__ out, int64_t K, int half,
                                                   double* __restrict__ stats) {
-  __shared__ double r1[4], r2[4];
+  __shared__ double r[5][4];
   const int c = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  double s1 = 0.0, s2 = 0.0;
+  double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
   for (int64_t j = tid; j < K; j += 256) {
-    const double v = out[j * ncol + c];
-    s1 += v;
-    s2 += v * v;
+    const double v = out[j * 2 * half + c], w = out[j * 2 * half + half + c];
+    acc[0] += v;
+    acc[1] += v * v;
+    acc[2] += w;
+    acc[3] += w * w;
+    acc[4] += v * w;
   }
-  s1 = wave_sum(s1);
-  s2 = wave_sum(s2);
-  if (lane == 0) {
-    r1[wave] = s1;
-    r2[wave] = s2;
+  for (int q = 0; q < 5; ++q) {
+    const double t = wave_sum(acc[q]);
+    if (lane == 0) r[q][wave] = t;
   }
   __syncthreads();
-  if (tid == 0) {
-    stats[2 * c] = r1[0] + r1[1] + r1[2] + r1[3];
-    stats[2 * c + 1] = r2[0] + r2[1] + r2[2] + r2[3];
-  }
+  if (tid < 5) stats[5 * c + tid] = r[tid][0] + r[tid][1] + r[tid][2] + r[tid][3];
 }
 
 // State-precision copies of O_g - I, its transpose and X_g for the sweep's products.
@@ -718,7 +719,7 @@ aqt_status launch_grad(aqt_ctx* ctx, const aqt_run_params* p, double* value, dou
 
   // forward paths from the trajectory kernel, every jump recorded
   DevBuf jc, jr, outb, stats, status;
-  if (jc.reserve(K * 4) || status.reserve(4) || stats.reserve(2 * (P + 1) * 8))
+  if (jc.reserve(K * 4) || status.reserve(4) || stats.reserve(5 * (P + 1) * 8))
     return ctx->fail(AQT_ENOMEM, "gradient allocation failed");
   int cap = 32;
   for (int attempt = 0; attempt < 2; ++attempt) {
@@ -740,13 +741,18 @@ aqt_status launch_grad(aqt_ctx* ctx, const aqt_run_params* p, double* value, dou
     cap = mx;
   }
 
+  // per trajectory: [f, g (P)] for the ground-cluster projector, then [1, s (P)] for the
+  // identity (s = d log |psi~|^2, the path-density score: mean zero, a control variate)
   double* out = per_traj;
+  const size_t rowb = 2 * static_cast<size_t>(P + 1) * 8;
   if (!out) {
-    if (outb.reserve(static_cast<size_t>(K) * (P + 1) * 8) != hipSuccess)
+    if (outb.reserve(static_cast<size_t>(K) * rowb) != hipSuccess)
       return ctx->fail(AQT_ENOMEM, "gradient output allocation failed");
     out = outb.as<double>();
   }
-  AQT_HIP(ctx, hipMemsetAsync(out, 0, static_cast<size_t>(K) * (P + 1) * 8, st));
+  AQT_HIP(ctx, hipMemsetAsync(out, 0, static_cast<size_t>(K) * rowb, st));
+  int gs_last = 1;
+  AQT_HIP(ctx, hipMemcpy(&gs_last, ctx->gs.as<int>() + (ctx->M - 1), 4, hipMemcpyDeviceToHost));
   AQT_HIP(ctx, hipMemsetAsync(status.p, 0, 4, st));
 
   GradArgs ga{};
@@ -767,6 +773,7 @@ aqt_status launch_grad(aqt_ctx* ctx, const aqt_run_params* p, double* value, dou
   ga.jcount = jc.as<int32_t>();
   ga.cap = cap;
   ga.out = out;
+  ga.ostride = 2 * (P + 1);
   ga.status = status.as<int>();
   ga.M = ctx->M;
   ga.nq = ctx->nq;
@@ -806,33 +813,47 @@ aqt_status launch_grad(aqt_ctx* ctx, const aqt_run_params* p, double* value, dou
   ga.pX = ctx->gpk_X.p;
   aqt_status s = AQT_OK;
 #define AQT_SWEEP(np, tt, T) s = launch_sweep<np, tt, T>(ctx, ga, (K + (tt) - 1) / (tt), cus, p->segment)
-  switch (NP) {
-    case 16: if (f64) AQT_SWEEP(16, 16, double); else AQT_SWEEP(16, 16, float); break;
-    case 32: if (f64) AQT_SWEEP(32, 16, double); else AQT_SWEEP(32, 16, float); break;
-    case 64: if (f64) AQT_SWEEP(64, 16, double); else AQT_SWEEP(64, 16, float); break;
-    case 128: if (f64) AQT_SWEEP(128, 16, double); else AQT_SWEEP(128, 16, float); break;
-    case 256: if (f64) AQT_SWEEP(256, 8, double); else AQT_SWEEP(256, 16, float); break;
-    default: return ctx->fail(AQT_EINVAL, "unsupported level count");
+  for (int pass = 0; pass < 2; ++pass) {
+    ga.out = out + pass * (P + 1);
+    ga.proj = pass ? ctx->n : gs_last;
+    switch (NP) {
+      case 16: if (f64) AQT_SWEEP(16, 16, double); else AQT_SWEEP(16, 16, float); break;
+      case 32: if (f64) AQT_SWEEP(32, 16, double); else AQT_SWEEP(32, 16, float); break;
+      case 64: if (f64) AQT_SWEEP(64, 16, double); else AQT_SWEEP(64, 16, float); break;
+      case 128: if (f64) AQT_SWEEP(128, 16, double); else AQT_SWEEP(128, 16, float); break;
+      case 256: if (f64) AQT_SWEEP(256, 8, double); else AQT_SWEEP(256, 16, float); break;
+      default: return ctx->fail(AQT_EINVAL, "unsupported level count");
+    }
+    if (s != AQT_OK) return s;
   }
 #undef AQT_SWEEP
-  if (s != AQT_OK) return s;
   int hstat = 0;
   AQT_HIP(ctx, hipMemcpy(&hstat, status.p, 4, hipMemcpyDeviceToHost));
   if (hstat) return ctx->fail(AQT_ECAPACITY, "more than 64 omega = 0 jumps of one trajectory within one step");
 
   hipLaunchKernelGGL(k_colstats, dim3(P + 1), dim3(256), 0, st, out, K, P + 1, stats.as<double>());
   AQT_HIP(ctx, hipGetLastError());
-  std::vector<double> hs(2 * (P + 1));
+  std::vector<double> hs(5 * (P + 1));
   AQT_HIP(ctx, hipMemcpyAsync(hs.data(), stats.p, hs.size() * 8, hipMemcpyDeviceToHost, st));
   AQT_HIP(ctx, hipStreamSynchronize(st));
-  auto mean_se = [&](int c, double* m, double* se) {
-    const double mu = hs[2 * c] / K;
-    const double var = std::max(0.0, (hs[2 * c + 1] - K * mu * mu) / (K - 1));
-    if (m) *m = mu;
-    if (se) *se = std::sqrt(var / K);
-  };
-  mean_se(0, value, value_se);
-  for (int c = 1; c <= P; ++c) mean_se(c, grad ? grad + c - 1 : nullptr, grad_se ? grad_se + c - 1 : nullptr);
+  const double Kd = static_cast<double>(K);
+  {
+    const double mu = hs[0] / Kd, var = std::max(0.0, (hs[1] - Kd * mu * mu) / (Kd - 1));
+    if (value) *value = mu;
+    if (value_se) *value_se = std::sqrt(var / Kd);
+  }
+  // control variate: mean(g) - c mean(s), c = Cov(g, s) / Var(s) from the same sample
+  for (int c = 1; c <= P; ++c) {
+    const double* h = &hs[5 * c];
+    const double mg = h[0] / Kd, ms = h[2] / Kd;
+    const double vg = std::max(0.0, (h[1] - Kd * mg * mg) / (Kd - 1));
+    const double vs = std::max(0.0, (h[3] - Kd * ms * ms) / (Kd - 1));
+    const double cv = (h[4] - Kd * mg * ms) / (Kd - 1);
+    const double cc = (vs > 0.0) ? cv / vs : 0.0;
+    const double var = std::max(0.0, vg - cc * cv);
+    if (grad) grad[c - 1] = mg - cc * ms;
+    if (grad_se) grad_se[c - 1] = std::sqrt(var / Kd);
+  }
   return AQT_OK;
 }
 

@@ -54,17 +54,22 @@ def test_fp64_per_trajectory_gradient(inst_fn, K):
     eng = _engine(inst)
     out = eng.grad_pgs(K, "fp64", seed=inst.seed, instance_id=inst.instance_id, per_trajectory=True)
     pt = out["per_traj"]
+    P = pt.shape[1] // 2 - 1
     same, frac = _matched(eng, inst, K, ref["jumps"])
     assert frac >= 0.97 and len(same) >= K - 2, frac
     np.testing.assert_allclose(pt[same, 0], ref["f"][same], atol=1e-11)
-    g_gpu, g_ref = pt[same, 1:], ref["g"][same]
-    scale = np.maximum(np.abs(g_ref).max(axis=0), 1e-3)
-    err = np.abs(g_gpu - g_ref) / scale
-    assert err.max() <= 2e-6, (err.max(axis=0), np.unravel_index(err.argmax(), err.shape))
-    # host reductions of the same per-trajectory values
+    np.testing.assert_array_equal(pt[:, P + 1], 1.0)
+    for got, want in ((pt[same, 1:P + 1], ref["g"][same]), (pt[same, P + 2:], ref["score"][same])):
+        scale = np.maximum(np.abs(want).max(axis=0), 1e-3)
+        err = np.abs(got - want) / scale
+        assert err.max() <= 2e-6, (err.max(axis=0), np.unravel_index(err.argmax(), err.shape))
+    # host reductions of the same per-trajectory values (control variate with the score)
+    g, sc = pt[:, 1:P + 1], pt[:, P + 2:]
+    cov = ((g - g.mean(0)) * (sc - sc.mean(0))).sum(0) / (K - 1)
+    c = cov / sc.var(axis=0, ddof=1)
     np.testing.assert_allclose(out["value"], pt[:, 0].mean(), rtol=1e-12)
-    np.testing.assert_allclose(out["grad"], pt[:, 1:].mean(axis=0), rtol=1e-10, atol=1e-14)
-    np.testing.assert_allclose(out["grad_se"], pt[:, 1:].std(axis=0, ddof=1) / np.sqrt(K), rtol=1e-8)
+    np.testing.assert_allclose(out["grad"], g.mean(0) - c * sc.mean(0), rtol=1e-9, atol=1e-13)
+    np.testing.assert_allclose(out["grad_se"], (g - c * sc).std(axis=0, ddof=1) / np.sqrt(K), rtol=1e-6)
 
 
 def test_fp64_two_level_gradient_per_trajectory():
@@ -75,12 +80,14 @@ def test_fp64_two_level_gradient_per_trajectory():
     eng = _engine(inst)
     out = eng.grad_pgs(K, "fp64", seed=inst.seed, instance_id=inst.instance_id, per_trajectory=True)
     pt = out["per_traj"]
+    P = pt.shape[1] // 2 - 1
     same, frac = _matched(eng, inst, K, ref["jumps"])
     assert len(same) >= K - 1
-    g_gpu, g_ref = pt[same, 1:], ref["g"][same]
-    scale = np.maximum(np.abs(g_ref).max(axis=0), 1e-3)
-    assert (np.abs(g_gpu - g_ref) / scale).max() <= 2e-6
+    for got, want in ((pt[same, 1:P + 1], ref["g"][same]), (pt[same, P + 2:], ref["score"][same])):
+        scale = np.maximum(np.abs(want).max(axis=0), 1e-3)
+        assert (np.abs(got - want) / scale).max() <= 2e-6
     np.testing.assert_array_equal(pt[:, 3:5], 0.0)
+    np.testing.assert_array_equal(pt[:, P + 4:P + 6], 0.0)
 
 
 @pytest.mark.parametrize("prec,K", [("fp32", 20000), ("fp64", 20000)])

@@ -527,3 +527,7 @@ def test_trajectory_gradient_estimates_are_unbiased():
     assert np.all(np.abs(m - ref) <= 3.0 * se + 1e-4), (m, ref, se)
     # the estimates are informative: the largest components are resolved well beyond noise
     assert np.sum(np.abs(ref) > 5.0 * se) >= 3
+    # the path-density score has mean zero (the total probability does not depend on theta)
+    s = r["score"]
+    assert np.all(np.abs(s.mean(axis=0)) <= 3.0 * s.std(axis=0, ddof=1) / np.sqrt(K))
+    assert np.all(s.std(axis=0) > 0)
