@@ -175,6 +175,21 @@ AQT_API aqt_status aqt_get_dims(aqt_ctx* ctx, int32_t* n_grid, int32_t* n_levels
  * still holds the true number of jumps of each trajectory. */
 AQT_API aqt_status aqt_run(aqt_ctx* ctx, const aqt_run_params* params, const aqt_outputs* out);
 
+/* ---- Lamb shift ----------------------------------------------------------------------
+ * enabled != 0 adds the Lamb-shift Hamiltonian of the Ohmic bath, H_LS = sum_i sum_w S(w)
+ * A_i,w^dag A_i,w (Sec. II eq. ME2-H; the operators of the Bohr-frequency grouping), with
+ * S(w) = (1/2pi) P int gamma(w') / (w - w') dw', to the tables built by the next
+ * aqt_precompute.  H_LS is diagonal in the eigenbasis, so only the energies that set the
+ * no-jump phases move: level b gets sum_i [sum_{a != b} S(e_b - e_a) z_ab^2 + S(0) z_bb^2];
+ * Bohr frequencies, rates and jump kinds keep the energies of H_S.  Off by default; tables
+ * given with aqt_set_tables are used as given.  Invalidates loaded tables (precompute
+ * again).  aqt_grad_pgs returns AQT_EINVAL while it is on. */
+AQT_API aqt_status aqt_set_lamb_shift(aqt_ctx* ctx, int enabled);
+
+/* The Lamb shift of every level at every grid point (host [n_grid * n_levels], row-major;
+ * zeros when off).  Synchronises. */
+AQT_API aqt_status aqt_get_lamb_shift(aqt_ctx* ctx, double* shift);
+
 /* ---- Gradient ------------------------------------------------------------------------
  * Estimate of d E[P_GS(1)] / d theta, theta = (A_ctrl[0..m-1], B_ctrl[0..m-1], eta):
  * the derivative of the trajectory average of the final ground-cluster population

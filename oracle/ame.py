@@ -4,7 +4,9 @@ TEST INFRASTRUCTURE: only tests/, the smoke check and the bench's cpu_baseline
 leg may import anything under oracle/.
 
 Three independent routes to the AME of Sec. II (eqs. ME2-H, ME2-L, Lindblad2,
-dissdiag) with the Lamb shift set to zero (the paper gives no S(w)):
+dissdiag).  The Lamb shift is zero unless the instance asks for it (the paper gives no
+S(w); model.lamb_S is the Ohmic bath's); split_step and liouvillian include it then,
+continuous does not support it:
 
 split_step   -- the exact mean of the trajectory process on the same grid:
                 rho <- O_g rho O_g^T, then rho <- exp(L_g dt) rho with L_g the
@@ -41,7 +43,7 @@ def rate_matrix(T) -> np.ndarray:
 
 def coherence_factor(T, inst, dt: float) -> np.ndarray:
     g0 = float(model.gamma_ohmic(0.0, inst.eta, inst.omega_c, inst.T))
-    E, Gam, zd = T.E, T.Gamma, T.zdiag
+    E, Gam, zd = T.Eph, T.Gamma, T.zdiag
     cross = g0 * (zd.T @ zd)                      # gamma(0) sum_i z_aa z_bb
     rate = (-1j * (E[:, None] - E[None, :]) - 0.5 * (Gam[:, None] + Gam[None, :]) + cross)
     return np.exp(rate * dt)
@@ -135,11 +137,33 @@ def lindblad_operators(T, inst, tol: float = 1e-9):
     return ops
 
 
+def lamb_hamiltonian(T, inst) -> np.ndarray:
+    """H_LS = sum_i sum_w S(w) A_i,w^dag A_i,w (eq. ME2-H) as a matrix, built from the
+    unscaled operators of lindblad_operators' grouping (one per a != b pair, one omega = 0
+    operator per qubit)."""
+    n = len(T.E)
+    H = np.zeros((n, n))
+    for i in range(inst.n_qubits):
+        z = T.z[i]
+        for a in range(n):
+            for b in range(n):
+                if a == b:
+                    continue
+                A = np.zeros((n, n))
+                A[a, b] = z[a, b]
+                H += model.lamb_S(float(T.E[b] - T.E[a]), inst.eta, inst.omega_c, inst.T) * (A.T @ A)
+        A0 = np.diag(np.diag(z))
+        H += model.lamb_S(0.0, inst.eta, inst.omega_c, inst.T) * (A0.T @ A0)
+    return H
+
+
 def liouvillian(T, inst) -> np.ndarray:
     """Superoperator of drho/dt = -i[H, rho] + sum_k (L rho L^+ - {L^+L, rho}/2), column-stacked."""
     n = len(T.E)
     I = np.eye(n)
     H = np.diag(T.E).astype(np.complex128)
+    if getattr(inst, "lamb_shift", False):
+        H = H + lamb_hamiltonian(T, inst)
     Lsup = -1j * (np.kron(I, H) - np.kron(H.T, I))
     for L in lindblad_operators(T, inst):
         LdL = L.conj().T @ L
@@ -149,6 +173,8 @@ def liouvillian(T, inst) -> np.ndarray:
 
 def continuous(inst, s_eval, rtol=1e-10, atol=1e-12):
     """Lab-frame AME integrated in t; returns instantaneous ground-state populations at s_eval."""
+    if getattr(inst, "lamb_shift", False):
+        raise NotImplementedError("the continuous AME is built without the Lamb shift")
     nq, N = inst.n_qubits, inst.dim
     HX = model.hx_dense(nq)
     HZ = model.hz_dense(inst.h, inst.J)

@@ -141,7 +141,7 @@ def replay_log_weight(tables, inst, paths, n_grid=None):
                     c = y / np.linalg.norm(y)
                 m += 1
             C[:, j] = c * np.exp(-0.5 * T.Gamma * (dt - tau_e))
-        C *= np.exp(-1j * T.E * dt)[:, None]
+        C *= np.exp(-1j * T.Eph * dt)[:, None]
         gs = T.gs
     pop = np.abs(C) ** 2
     with np.errstate(divide="ignore"):   # log 0 = -inf: the path ends outside the ground cluster

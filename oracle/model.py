@@ -95,6 +95,40 @@ def gamma_ohmic(omega, eta: float, omega_c: float, T: float):
     out = np.empty_like(omega)
     nz = omega != 0.0
     w = omega[nz]
-    out[nz] = 2.0 * math.pi * eta * w * np.exp(-np.abs(w) / omega_c) / (-np.expm1(-beta * w))
+    with np.errstate(over="ignore"):   # expm1 -> inf far below zero frequency: gamma -> 0
+        out[nz] = 2.0 * math.pi * eta * w * np.exp(-np.abs(w) / omega_c) / (-np.expm1(-beta * w))
     out[~nz] = 2.0 * math.pi * eta / beta
     return out
+
+
+def lamb_S(omega: float, eta: float, omega_c: float, T: float) -> float:
+    """Lamb-shift function of the Ohmic bath: the principal value
+    S(w) = (1/2pi) P int gamma(w') / (w - w') dw' (the imaginary part of the one-sided
+    transform of the bath correlation function, whose real part is gamma / 2), written
+    with w' = w -+ u as the regular integral (1/2pi) int_0^inf [gamma(w - u) - gamma(w + u)] / u du.
+    gamma has a kink at zero frequency (the |w| of the cutoff), i.e. at u = |w|: the
+    integral is split there."""
+    import warnings
+    import scipy.integrate as si
+    w = float(omega)
+
+    def f(u):
+        return float(gamma_ohmic(w - u, eta, omega_c, T) - gamma_ohmic(w + u, eta, omega_c, T)) / u
+
+    a = abs(w)
+    edges = [0.0, a] if a > 0.0 else [0.0]
+    edges += [a + 40.0 * T, a + 40.0 * T + 60.0 * omega_c]
+    total = 0.0
+    with warnings.catch_warnings():   # quad reports rounding once the 1e-13 target is reached
+        warnings.simplefilter("ignore", si.IntegrationWarning)
+        for lo, hi in zip(edges[:-1], edges[1:]):
+            total += si.quad(f, lo, hi, epsabs=1e-16, epsrel=1e-13, limit=400)[0]
+        total += si.quad(f, edges[-1], np.inf, epsabs=1e-16, epsrel=1e-13, limit=200)[0]
+    return total / (2.0 * math.pi)
+
+
+def lamb_S_zero_temperature(omega, eta: float, omega_c: float):
+    """S(w) of the Ohmic bath at T = 0 in closed form: eta (-wc + w e^{-w/wc} Ei(w/wc))."""
+    import scipy.special as ss
+    w = np.asarray(omega, dtype=np.float64)
+    return eta * (-omega_c + w * np.exp(-w / omega_c) * ss.expi(w / omega_c))

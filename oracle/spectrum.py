@@ -59,6 +59,12 @@ class GridTables:
     d: np.ndarray            # [n] complex
     leak: float
     V: Optional[np.ndarray] = None   # [N, n] (kept only on request)
+    shift: Optional[np.ndarray] = None   # [n] Lamb shift of each level (zeros when off)
+
+    @property
+    def Eph(self) -> np.ndarray:
+        """Energies that set the phases: e_b plus the Lamb shift."""
+        return self.E if self.shift is None else self.E + self.shift
 
 
 def clusters(E: np.ndarray, deg_tol: float):
@@ -168,8 +174,35 @@ def grid_tables(inst, E: np.ndarray, V: np.ndarray, dt: float):
         R[i] = (gam * z[i] ** 2).T                        # R[i, b, a]
     Gamma = R.sum(axis=(0, 2))
     zdiag = np.stack([np.diag(z[i]) for i in range(nq)])
-    d = np.exp(-1j * E * dt - 0.5 * Gamma * dt)
-    return z, R, Gamma, zdiag, d
+    shift = lamb_shift(inst, E, z) if getattr(inst, "lamb_shift", False) else np.zeros(n)
+    d = np.exp(-1j * (E + shift) * dt - 0.5 * Gamma * dt)
+    return z, R, Gamma, zdiag, d, shift
+
+
+def lamb_shift(inst, E: np.ndarray, z: np.ndarray) -> np.ndarray:
+    """Diagonal of H_LS = sum_i sum_w S(w) A_i,w^dag A_i,w in the eigenbasis (Sec. II,
+    eq. ME2-H; the operators of the Bohr-frequency reading): level b collects
+    S(e_b - e_a) z_i[a,b]^2 from every a != b and S(0) z_i[b,b]^2 from the omega = 0
+    operator of each qubit."""
+    n = len(E)
+    cache = {}
+
+    def S(w):
+        if w not in cache:
+            cache[w] = model.lamb_S(w, inst.eta, inst.omega_c, inst.T)
+        return cache[w]
+
+    out = np.zeros(n)
+    s0 = S(0.0)
+    for b in range(n):
+        acc = 0.0
+        for a in range(n):
+            if a != b:
+                w2 = (z[:, a, b] ** 2).sum()
+                acc += S(float(E[b] - E[a])) * w2
+        acc += s0 * (z[:, b, b] ** 2).sum()
+        out[b] = acc
+    return out
 
 
 def n_steps_dt(inst, n_grid: int):
@@ -207,11 +240,11 @@ def table_stream(inst, n_grid: Optional[int] = None, n_levels: Optional[int] = N
             O, S = polar(V.T @ Vp)
             leak = 1.0 - float(S.min()) ** 2
             cinit = None
-        z, R, Gamma, zdiag, d = grid_tables(inst, E, V, dt)
+        z, R, Gamma, zdiag, d, shift = grid_tables(inst, E, V, dt)
         Vprev = V
         if grids is None or g in grids:
             yield GridTables(g=g, s=s, E=E, gs=gs, O=O, cinit=cinit, z=z, R=R, Gamma=Gamma,
-                             zdiag=zdiag, d=d, leak=leak, V=V if keep_V else None)
+                             zdiag=zdiag, d=d, leak=leak, V=V if keep_V else None, shift=shift)
 
 
 def all_tables(inst, **kw):

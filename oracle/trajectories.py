@@ -156,7 +156,7 @@ def run(tables: Iterable, inst, n_traj: int, *, n_grid: Optional[int] = None, se
                 m[j] += 1
                 r[j] = philox.draw_scalar(seed, iid, tid[j], 3 * m[j])
             c[:, j] = cj
-        c *= np.exp(-1j * T.E * dt)[:, None]
+        c *= np.exp(-1j * T.Eph * dt)[:, None]
         pop = np.abs(c) ** 2
         p = pop[:T.gs].sum(axis=0) / pop.sum(axis=0)
         pgs_sum[g] = p.sum()

@@ -22,7 +22,8 @@ KIND_NAMES = ("relax", "excite", "dephase")
 
 EXPORTED = ("aqt_create", "aqt_destroy", "aqt_last_error", "aqt_version", "aqt_set_hamiltonian",
             "aqt_set_schedule", "aqt_set_bath", "aqt_precompute", "aqt_precompute_ex", "aqt_set_tables", "aqt_get_tables",
-            "aqt_get_dims", "aqt_run", "aqt_grad_pgs", "aqt_batch_create", "aqt_batch_launch", "aqt_batch_tiles",
+            "aqt_get_dims", "aqt_run", "aqt_grad_pgs", "aqt_set_lamb_shift", "aqt_get_lamb_shift",
+            "aqt_batch_create", "aqt_batch_launch", "aqt_batch_tiles",
             "aqt_batch_last_error", "aqt_batch_destroy")
 BATCH_GRAPH, BATCH_AUTOTUNE = 1, 2
 
@@ -91,6 +92,8 @@ def load_library(path: str = LIB_PATH):
     lib.aqt_get_dims.argtypes = [ctx, ip, ip, ip]
     lib.aqt_run.argtypes = [ctx, C.POINTER(RunParams), C.POINTER(Outputs)]
     lib.aqt_grad_pgs.argtypes = [ctx, C.POINTER(RunParams), dp, dp, dp, dp, C.c_void_p]
+    lib.aqt_set_lamb_shift.argtypes = [ctx, C.c_int]
+    lib.aqt_get_lamb_shift.argtypes = [ctx, dp]
     lib.aqt_batch_create.argtypes = [C.POINTER(C.c_void_p), C.POINTER(C.c_void_p), C.c_int,
                                      C.POINTER(RunParams), C.POINTER(Outputs), C.c_int]
     lib.aqt_batch_launch.argtypes = [C.c_void_p]
@@ -171,11 +174,20 @@ class Engine:
     def set_bath(self, eta, omega_c, T):
         self._check(self.lib.aqt_set_bath(self.ctx, float(eta), float(omega_c), float(T)))
 
+    def set_lamb_shift(self, enabled: bool):
+        self._check(self.lib.aqt_set_lamb_shift(self.ctx, int(bool(enabled))))
+
+    def get_lamb_shift(self):
+        out = np.zeros((self.n_grid, self.n_levels))
+        self._check(self.lib.aqt_get_lamb_shift(self.ctx, _dptr(out)))
+        return out
+
     def set_instance(self, inst):
-        """Hamiltonian, schedule and bath of a workloads.Instance."""
+        """Hamiltonian, schedule, bath and Lamb-shift choice of a workloads.Instance."""
         self.set_hamiltonian(inst.h, inst.J)
         self.set_schedule(inst.t_f, inst.A_ctrl, inst.B_ctrl)
         self.set_bath(inst.eta, inst.omega_c, inst.T)
+        self.set_lamb_shift(getattr(inst, "lamb_shift", False))
 
     def precompute(self, n_grid: int, n_levels: int, deg_tol: float = 1e-8, method: str = "auto"):
         """GPU eigensystem and tables; method "auto", "dense" or "iterative"."""

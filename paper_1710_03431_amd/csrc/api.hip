@@ -207,6 +207,10 @@ aqt_status aqt_set_tables(aqt_ctx* ctx, int n_grid, int n_levels, const double* 
   AQT_HIP(ctx, hipMemcpy(ctx->gs.p, gs, n_grid * sizeof(int32_t), hipMemcpyHostToDevice));
   if (ctx->leak.reserve(n_grid * sizeof(double)) != hipSuccess) return ctx->fail(AQT_ENOMEM, "table allocation failed");
   AQT_HIP(ctx, hipMemset(ctx->leak.p, 0, n_grid * sizeof(double)));
+  // host tables carry their own energies: no Lamb shift is added to them
+  if (ctx->shift.reserve(static_cast<size_t>(n_grid) * NP * sizeof(double)) != hipSuccess)
+    return ctx->fail(AQT_ENOMEM, "table allocation failed");
+  AQT_HIP(ctx, hipMemset(ctx->shift.p, 0, static_cast<size_t>(n_grid) * NP * sizeof(double)));
   if ((s = aqt::finish_tables(ctx)) != AQT_OK) return s;
   AQT_HIP(ctx, hipStreamSynchronize(ctx->stream));
   ctx->have_tables = true;
@@ -260,11 +264,30 @@ aqt_status aqt_run(aqt_ctx* ctx, const aqt_run_params* p, const aqt_outputs* o) 
   return aqt::launch_run(ctx, p, o);
 }
 
+aqt_status aqt_set_lamb_shift(aqt_ctx* ctx, int enabled) {
+  if (!ctx) return AQT_EINVAL;
+  ctx->lamb = enabled != 0;
+  ctx->have_tables = false;
+  ctx->have_grad = false;
+  return AQT_OK;
+}
+
+aqt_status aqt_get_lamb_shift(aqt_ctx* ctx, double* shift) {
+  if (!ctx) return AQT_EINVAL;
+  if (!ctx->have_tables) return ctx->fail(AQT_ESTATE, "no tables loaded");
+  if (!shift) return ctx->fail(AQT_EINVAL, "shift is required");
+  aqt_status s = set_device(ctx);
+  if (s != AQT_OK) return s;
+  AQT_HIP(ctx, hipStreamSynchronize(ctx->stream));
+  return download_unpadded(ctx, shift, ctx->shift, ctx->M, ctx->n, ctx->NP, false);
+}
+
 aqt_status aqt_grad_pgs(aqt_ctx* ctx, const aqt_run_params* p, double* value, double* value_se, double* grad,
                         double* grad_se, double* per_traj) {
   if (!ctx) return AQT_EINVAL;
   if (!p) return ctx->fail(AQT_EINVAL, "params are required");
   if (!ctx->have_tables) return ctx->fail(AQT_ESTATE, "precompute must come first");
+  if (ctx->lamb) return ctx->fail(AQT_EINVAL, "the gradient does not include the Lamb shift's derivative");
   if (!ctx->last_from_solver)
     return ctx->fail(AQT_ESTATE, "the gradient needs tables from aqt_precompute (eigenvectors), not aqt_set_tables");
   if (ctx->n != (1 << ctx->nq))

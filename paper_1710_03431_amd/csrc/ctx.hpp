@@ -24,6 +24,7 @@ struct aqt_ctx {
   bool have_sched = false;
   double eta = 0.0, omega_c = 0.0, T = 0.0;
   bool have_bath = false;
+  bool lamb = false;    // add the Lamb shift at the next precompute
 
   // ---- tables (device, FP64 masters; rows padded to NP with zeros)
   bool have_tables = false;
@@ -42,6 +43,7 @@ struct aqt_ctx {
   aqt::DevBuf ehalf;    // [M][NP] exp(+Gamma dt / 2), undoes the step's decay
   aqt::DevBuf dre, dim; // [M][NP] FP64 exp(-i e dt - Gamma dt / 2)
   aqt::DevBuf leak;     // [M]
+  aqt::DevBuf shift;    // [M][NP] Lamb shift of each level (zeros when off); phases use E + shift
 
   // ---- derivative tables of the gradient (direction 0 = A(s_g), 1 = B(s_g)); full spectrum only
   bool have_grad = false;

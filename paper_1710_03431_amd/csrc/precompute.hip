@@ -630,6 +630,95 @@ __global__ void k_cinit(const double* __restrict__ V0, const double* __restrict_
   if (tid == 0) leak[1] = 1.0 - nn;
 }
 
+// ---- Lamb shift (Sec. II eq. ME2-H) -------------------------------------------------
+// H_LS = sum_i sum_w S(w) A_i,w^dag A_i,w is diagonal in the eigenbasis: level b gets
+// sum_i [sum_{a != b} S(e_b - e_a) z_ab^2 + S(0) z_bb^2].  S(w) = (1/2pi) P int gamma(w') /
+// (w - w') dw' = (1/2pi) int_0^inf [gamma(w - u) - gamma(w + u)] / u du, tabulated once per
+// precompute on nodes w_k = W sinh(sigma x_k) / sinh(sigma), x_k uniform in [-1, 1] (fine
+// near w = 0, where S has a w log|w| term from the kink of gamma), by composite 16-point
+// Gauss-Legendre panels that start at the kink u = |w| and double in width up to wc / 2.
+constexpr int kLambNodes = 16385;
+constexpr double kLambSigma = 10.0;
+
+struct LambTable {
+  const double* S;   // [kLambNodes]
+  double W;          // largest |w| covered
+};
+
+__device__ double lamb_integrand_panel(double w, double lo, double hi, double eta, double wc, double T,
+                                       const double* __restrict__ glx, const double* __restrict__ glw) {
+  const double c = 0.5 * (hi + lo), h = 0.5 * (hi - lo);
+  double s = 0.0;
+  for (int q = 0; q < 16; ++q) {
+    const double u = c + h * glx[q];
+    s += glw[q] * (gamma_ohmic(w - u, eta, wc, T) - gamma_ohmic(w + u, eta, wc, T)) / u;
+  }
+  return h * s;
+}
+
+__global__ void k_lamb_table(double W, double eta, double wc, double T, const double* __restrict__ glx,
+                             const double* __restrict__ glw, double* __restrict__ S) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= kLambNodes) return;
+  const double x = -1.0 + 2.0 * k / (kLambNodes - 1);
+  const double w = W * sinh(kLambSigma * x) / sinh(kLambSigma);
+  const double a = fabs(w);
+  const double h0 = fmin(T, wc) / 8.0, hmax = 0.5 * wc;
+  const double U = a + 40.0 * T + 60.0 * wc;
+  double sum = 0.0, lo = a, hw = h0;
+  while (lo < U) {
+    const double hi = fmin(lo + hw, U);
+    sum += lamb_integrand_panel(w, lo, hi, eta, wc, T, glx, glw);
+    lo = hi;
+    hw = fmin(2.0 * hw, hmax);
+  }
+  double hi = a;
+  hw = h0;
+  while (hi > 0.0) {
+    const double l2 = fmax(hi - hw, 0.0);
+    sum += lamb_integrand_panel(w, l2, hi, eta, wc, T, glx, glw);
+    hi = l2;
+    hw = fmin(2.0 * hw, hmax);
+  }
+  S[k] = sum / (2.0 * M_PI);
+}
+
+// S(w) by cubic Lagrange interpolation in x (|w| <= W).
+__device__ double lamb_S(const LambTable& t, double w) {
+  const double x = asinh(w * sinh(kLambSigma) / t.W) / kLambSigma;
+  const double dx = 2.0 / (kLambNodes - 1);
+  int k = static_cast<int>(floor((x + 1.0) / dx)) - 1;
+  k = min(max(k, 0), kLambNodes - 4);
+  const double u = (x + 1.0) / dx - k;   // position in node units from node k
+  const double l0 = -(u - 1.0) * (u - 2.0) * (u - 3.0) / 6.0;
+  const double l1 = u * (u - 2.0) * (u - 3.0) / 2.0;
+  const double l2 = -u * (u - 1.0) * (u - 3.0) / 2.0;
+  const double l3 = u * (u - 1.0) * (u - 2.0) / 6.0;
+  return l0 * t.S[k] + l1 * t.S[k + 1] + l2 * t.S[k + 2] + l3 * t.S[k + 3];
+}
+
+// shift[g][b] from z (chunk-local [c][i][a][b], ld n) for grid points zg0 .. zg0 + zcnt - 1.
+__global__ void k_lamb_shift(const double* __restrict__ z, const double* __restrict__ E, int n, int NP, int nq,
+                             int zg0, int zcnt, LambTable tab, double* __restrict__ shift) {
+  const int64_t idx = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (idx >= static_cast<int64_t>(zcnt) * NP) return;
+  const int c = static_cast<int>(idx / NP), b = static_cast<int>(idx % NP);
+  const int g = zg0 + c;
+  double acc = 0.0;
+  if (b < n) {
+    const double* e = E + static_cast<size_t>(g) * NP;
+    const double s0 = lamb_S(tab, 0.0);
+    for (int i = 0; i < nq; ++i) {
+      const double* zi = z + (static_cast<size_t>(c) * nq + i) * n * n;
+      for (int a = 0; a < n; ++a) {
+        const double zab = zi[a * n + b];
+        acc += ((a == b) ? s0 : lamb_S(tab, e[b] - e[a])) * zab * zab;
+      }
+    }
+  }
+  shift[static_cast<size_t>(g) * NP + b] = acc;
+}
+
 // ---- derivative tables of the gradient (full spectrum, n = 2^n_qubits) ----------
 // Directions: 0 = A(s_g) (operator H_X = -sum_i sx_i), 1 = B(s_g) (operator
 // diag(e_Z)).  First-order perturbation theory of the symmetric eigenproblem:
@@ -1167,12 +1256,55 @@ aqt_status precompute_tables(aqt_ctx* ctx, int M, int n, double tol, int method,
   const size_t sNP = static_cast<size_t>(NP);
   if (ctx->E.reserve(M * sNP * 8) || ctx->gs.reserve(M * 4) || ctx->dlt.reserve(M * sNP * sNP * 8) ||
       ctx->cinit.reserve(sNP * 8) || ctx->R.reserve(static_cast<size_t>(M) * nq * sNP * sNP * 8) ||
-      ctx->zdiag.reserve(static_cast<size_t>(M) * nq * sNP * 8) || ctx->leak.reserve(M * 8))
+      ctx->zdiag.reserve(static_cast<size_t>(M) * nq * sNP * 8) || ctx->leak.reserve(M * 8) ||
+      ctx->shift.reserve(M * sNP * 8))
     return ctx->fail(AQT_ENOMEM, "table allocation failed");
   AQT_HIP(ctx, hipMemsetAsync(ctx->dlt.p, 0, M * sNP * sNP * 8, st));
   AQT_HIP(ctx, hipMemsetAsync(ctx->R.p, 0, static_cast<size_t>(sNP) * sNP * nq * 8, st));       // g = 0 unused
   AQT_HIP(ctx, hipMemsetAsync(ctx->zdiag.p, 0, static_cast<size_t>(sNP) * nq * 8, st));
   AQT_HIP(ctx, hipMemsetAsync(ctx->leak.p, 0, M * 8, st));
+  AQT_HIP(ctx, hipMemsetAsync(ctx->shift.p, 0, M * sNP * 8, st));
+  // Lamb-shift function table over every Bohr frequency (Gershgorin bound on |e|)
+  DevBuf lambS, gl;
+  LambTable ltab{nullptr, 0.0};
+  if (ctx->lamb) {
+    double hsum = 0.0;
+    for (double v : ctx->h) hsum += std::fabs(v);
+    for (int i = 0; i < nq; ++i)
+      for (int j = i + 1; j < nq; ++j) hsum += std::fabs(ctx->J[i * nq + j]);
+    double amax = 0.0, bmax = 0.0;
+    for (int g = 0; g < M; ++g) {
+      amax = std::max(amax, std::fabs(Ag[g]));
+      bmax = std::max(bmax, std::fabs(Bg[g]));
+    }
+    ltab.W = 2.0 * (amax * nq + bmax * hsum) * 1.01 + 1.0;
+    // 16-point Gauss-Legendre nodes (Newton on P_16) and weights
+    std::vector<double> glh(32);
+    for (int q = 0; q < 16; ++q) {
+      double x = std::cos(M_PI * (q + 0.75) / 16.5), dp = 1.0;
+      for (int it = 0; it < 100; ++it) {
+        double p0 = 1.0, p1 = x;
+        for (int l = 2; l <= 16; ++l) {
+          const double p2 = ((2.0 * l - 1.0) * x * p1 - (l - 1.0) * p0) / l;
+          p0 = p1;
+          p1 = p2;
+        }
+        dp = 16.0 * (x * p1 - p0) / (x * x - 1.0);
+        const double dx = p1 / dp;
+        x -= dx;
+        if (std::fabs(dx) < 1e-16) break;
+      }
+      glh[q] = x;
+      glh[16 + q] = 2.0 / ((1.0 - x * x) * dp * dp);
+    }
+    if (lambS.reserve(kLambNodes * 8) || gl.reserve(32 * 8))
+      return ctx->fail(AQT_ENOMEM, "Lamb-shift table allocation failed");
+    AQT_HIP(ctx, hipMemcpyAsync(gl.p, glh.data(), 32 * 8, hipMemcpyHostToDevice, st));
+    hipLaunchKernelGGL(k_lamb_table, dim3(nblk(kLambNodes, 64)), dim3(64), 0, st, ltab.W, ctx->eta, ctx->omega_c,
+                       ctx->T, gl.as<double>(), gl.as<double>() + 16, lambS.as<double>());
+    AQT_HIP(ctx, hipGetLastError());
+    ltab.S = lambS.as<double>();
+  }
 
   // ---- chunked workspace
   const size_t per_grid = (iterative ? 0 : 2 * static_cast<size_t>(N) * N)   // H, Z (dense path)
@@ -1342,6 +1474,11 @@ aqt_status precompute_tables(aqt_ctx* ctx, int M, int n, double tol, int method,
                          zws.as<double>(), ctx->E.as<double>(), n, NP, nq, zg0, zcnt, ctx->eta, ctx->omega_c, ctx->T,
                          ctx->R.as<double>(), ctx->zdiag.as<double>());
       AQT_HIP(ctx, hipGetLastError());
+      if (ctx->lamb) {
+        hipLaunchKernelGGL(k_lamb_shift, dim3(nblk(static_cast<int64_t>(zcnt) * NP)), dim3(256), 0, st,
+                           zws.as<double>(), ctx->E.as<double>(), n, NP, nq, zg0, zcnt, ltab, ctx->shift.as<double>());
+        AQT_HIP(ctx, hipGetLastError());
+      }
     }
     if (grad) {
       // V H' V^T for both directions at every grid point of the chunk, then X and de

@@ -20,7 +20,8 @@
 namespace aqt {
 namespace {
 
-__global__ void k_gamma_phase(const double* __restrict__ E, const double* __restrict__ R, int M, int NP, int n,
+__global__ void k_gamma_phase(const double* __restrict__ E, const double* __restrict__ shift,
+                              const double* __restrict__ R, int M, int NP, int n,
                               int nq, double dt, double* __restrict__ Gamma, double* __restrict__ Rcol,
                               double* __restrict__ ehalf, double* __restrict__ dre, double* __restrict__ dim) {
   const int64_t idx = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
@@ -50,7 +51,7 @@ __global__ void k_gamma_phase(const double* __restrict__ E, const double* __rest
   Gamma[idx] = G;
   if (b < n) {
     double sn, cs;
-    sincos(E[idx] * dt, &sn, &cs);
+    sincos((E[idx] + shift[idx]) * dt, &sn, &cs);   // phases of H_S + H_LS
     const double mag = exp(-0.5 * G * dt);
     dre[idx] = mag * cs;
     dim[idx] = -mag * sn;
@@ -166,7 +167,7 @@ aqt_status finish_tables(aqt_ctx* ctx) {
       ctx->ehalf.reserve(cnt * sizeof(double)) != hipSuccess)
     return ctx->fail(AQT_ENOMEM, "table allocation failed");
   hipLaunchKernelGGL(k_gamma_phase, dim3(blocks_for(cnt)), dim3(256), 0, ctx->stream, ctx->E.as<double>(),
-                     ctx->R.as<double>(), ctx->M, ctx->NP, ctx->n, ctx->nq, ctx->dt, ctx->Gamma.as<double>(),
+                     ctx->shift.as<double>(), ctx->R.as<double>(), ctx->M, ctx->NP, ctx->n, ctx->nq, ctx->dt, ctx->Gamma.as<double>(),
                      ctx->Rcol.as<double>(), ctx->ehalf.as<double>(), ctx->dre.as<double>(), ctx->dim.as<double>());
   AQT_HIP(ctx, hipGetLastError());
   ctx->packed_for = -1;

@@ -171,9 +171,11 @@ def test_rate_matrix_detailed_balance_and_gibbs_null_vector():
 
 
 # ---------------------------------------------------------------- AME --------
-def test_split_step_map_equals_explicit_liouvillian():
-    """Decoupled population/coherence update = expm of the Lindbladian built from eq. Lindblad2."""
-    inst = W.ring_instance(2, 3, t_f=40.0)
+@pytest.mark.parametrize("lamb", [False, True])
+def test_split_step_map_equals_explicit_liouvillian(lamb):
+    """Decoupled population/coherence update = expm of the Lindbladian built from eq. Lindblad2
+    (with lamb: plus -i[H_LS, rho], H_LS = sum S(w) A^dag A built from the operators)."""
+    inst = W.ring_instance(2, 3, t_f=40.0, lamb_shift=lamb)
     for T in spectrum.all_tables(inst, n_grid=6)[1:4]:
         dt = 3.7
         rng = np.random.default_rng(T.g)
@@ -531,3 +533,32 @@ def test_trajectory_gradient_estimates_are_unbiased():
     s = r["score"]
     assert np.all(np.abs(s.mean(axis=0)) <= 3.0 * s.std(axis=0, ddof=1) / np.sqrt(K))
     assert np.all(s.std(axis=0) > 0)
+
+
+def test_lamb_shift_function_zero_temperature_closed_form():
+    """The principal-value integral of the Ohmic gamma against the T = 0 closed form
+    eta (-wc + w e^{-w/wc} Ei(w/wc)) at a temperature far below every |w| tested."""
+    wc = 8 * np.pi
+    for w in (-80.0, -20.0, -3.0, -0.5, 0.5, 3.0, 20.0, 80.0):
+        got = model.lamb_S(w, 1e-4, wc, 1e-3)
+        want = float(model.lamb_S_zero_temperature(w, 1e-4, wc))
+        assert abs(got - want) <= 1e-6 * abs(want), (w, got, want)
+
+
+def test_lamb_shift_function_at_zero_frequency():
+    """S(0) = -(1/2pi) int gamma(w)/w dw = -eta wc at every temperature: the Bose factors
+    of +w and -w add to one."""
+    for T in (0.05, 1.571044, 7.0):
+        assert abs(model.lamb_S(0.0, 2e-4, 5.0, T) + 2e-4 * 5.0) <= 1e-12
+
+
+def test_lamb_shift_leaves_frozen_populations_alone():
+    """H_LS commutes with H_S (it is diagonal in the eigenbasis): for a frozen Hamiltonian
+    started in its ground state the split-step AME state does not change at all."""
+    inst = W.ring_instance(2, 3, t_f=40.0, n_grid=6, A_ctrl=np.array([1.0, 1.0]), B_ctrl=np.array([0.7, 0.7]),
+                           eta=1e-2)
+    P0, r0 = ame.split_step(spectrum.all_tables(inst), inst, keep_rho=True)
+    P1, r1 = ame.split_step(spectrum.all_tables(inst.with_(lamb_shift=True)), inst.with_(lamb_shift=True),
+                            keep_rho=True)
+    np.testing.assert_allclose(np.diag(r1).real, np.diag(r0).real, atol=1e-14)
+    np.testing.assert_allclose(P1, P0, atol=1e-14)

@@ -48,6 +48,7 @@ class Instance:
     eta: float = 1e-4             # dimensionless coupling (the paper's g^2)
     omega_c: float = 8.0 * math.pi
     T: float = kelvin_to_rad_per_ns(0.012)
+    lamb_shift: bool = False      # include the Lamb-shift Hamiltonian of the Ohmic bath
     n_grid: int = 1001            # s-grid points (n_grid - 1 steps)
     n_levels: int = 0             # retained levels; 0 = full spectrum
     n_traj: int = 1000
