@@ -153,7 +153,7 @@ def test_relaxation_rate_closed_form():
         lam = sum(model.gamma_ohmic(w10, inst.eta, inst.omega_c, inst.T) *
                   (V[:, 0] @ model.pauli_on(model.SZ, a, 4) @ V[:, 1]) ** 2 for a in range(4))
         Ec, Vc, _ = spectrum.eigen(inst, s, 16, 1e-8)
-        _, R, _, _, _ = spectrum.grid_tables(inst, Ec, Vc, 1.0)
+        _, R, _, _, _, _ = spectrum.grid_tables(inst, Ec, Vc, 1.0)
         np.testing.assert_allclose(R[:, 1, 0].sum(), lam, rtol=1e-12)
 
 
