@@ -287,9 +287,10 @@ def bench_grad(args):
               f"ratio {ms / fwd_ms:.2f}; P_GS(1)={res['P_GS_final']:.5f}", file=sys.stderr, flush=True)
     head_prec = "fp32" if "fp32" in results else next(iter(results))
     head = results[head_prec]
-    # sweep flops per trajectory-step: checkpoint pass and segment replay (2 kicks), X_g products at both
-    # points for both directions (4), the adjoint kick (1), each 4 n^2; plus the forward run
-    flops = (7 * 4 * n * n + FLOP_PER_TRAJ_STEP(n)) * K * (M - 1)
+    # per trajectory-step and sweep: the replay kick, X_g products at both points for both directions (4)
+    # and the adjoint kick, each 4 n^2 flop; two sweeps (projector and score); plus the forward run
+    per_unit = 2 * 6 * 4 * n * n + FLOP_PER_TRAJ_STEP(n)
+    flops = per_unit * K * (M - 1)
     achieved = flops / (head["ms"] / 1e3)
     cpu = None if args.no_cpu else cpu_grad_baseline(inst, 16, 2)
     line = {
@@ -305,7 +306,7 @@ def bench_grad(args):
         "roofline": {"bound": "mfma", "achieved": achieved / 1e12, "peak": PEAK[head_prec] / 1e12,
                      "unit": "TFLOP/s", "frac": achieved / PEAK[head_prec], "traffic": None,
                      "kernel": f"k_grad + forward run ({head_prec})",
-                     "per_unit": f"{7 * 4 * n * n + FLOP_PER_TRAJ_STEP(n)} flop per trajectory-step"},
+                     "per_unit": f"{per_unit} flop per trajectory-step"},
         "cpu_baseline": cpu,
     }
     print(json.dumps(line))
