@@ -157,6 +157,44 @@ def lamb_hamiltonian(T, inst) -> np.ndarray:
     return H
 
 
+def liouvillian_correlated(T, inst, zq) -> np.ndarray:
+    """Eq. ME2-L with gamma_ab(w) = C_ab gamma(w), written as the double sum over qubits
+    a, b of sum_w C_ab gamma(w) (L_b,w rho L_a,w^dag - {L_a,w^dag L_b,w, rho} / 2), with
+    the per-qubit operators of the Bohr-frequency grouping (one per a != b pair of
+    levels, one omega = 0 operator) built from zq[q] = <a|sz_q|b>; no factorisation of
+    C.  Column-stacked superoperator (no Lamb shift)."""
+    n = len(T.E)
+    nq = inst.n_qubits
+    C = np.eye(nq) if getattr(inst, "bath_corr", None) is None else np.asarray(inst.bath_corr, dtype=np.float64)
+    I = np.eye(n)
+    H = np.diag(T.E).astype(np.complex128)
+    Lsup = -1j * (np.kron(I, H) - np.kron(H.T, I))
+
+    def add(ops, gam):
+        nonlocal Lsup
+        for qa in range(nq):
+            for qb in range(nq):
+                c = C[qa, qb] * gam
+                if c == 0.0:
+                    continue
+                La, Lb = ops[qa], ops[qb]
+                LdL = La.conj().T @ Lb
+                Lsup = Lsup + c * (np.kron(La.conj(), Lb) - 0.5 * (np.kron(I, LdL) + np.kron(LdL.T, I)))
+
+    for a in range(n):
+        for b in range(n):
+            if a == b:
+                continue
+            ops = []
+            for q in range(nq):
+                L = np.zeros((n, n))
+                L[a, b] = zq[q][a, b]
+                ops.append(L)
+            add(ops, float(model.gamma_ohmic(T.E[b] - T.E[a], inst.eta, inst.omega_c, inst.T)))
+    add([np.diag(np.diag(zq[q])) for q in range(nq)], float(model.gamma_ohmic(0.0, inst.eta, inst.omega_c, inst.T)))
+    return Lsup
+
+
 def liouvillian(T, inst) -> np.ndarray:
     """Superoperator of drho/dt = -i[H, rho] + sum_k (L rho L^+ - {L^+L, rho}/2), column-stacked."""
     n = len(T.E)

@@ -132,3 +132,17 @@ def lamb_S_zero_temperature(omega, eta: float, omega_c: float):
     import scipy.special as ss
     w = np.asarray(omega, dtype=np.float64)
     return eta * (-omega_c + w * np.exp(-w / omega_c) * ss.expi(w / omega_c))
+
+
+def channel_weights(inst) -> np.ndarray:
+    """Diagonal coupling operators of the jump channels, [n_channels, 2^n] (Sec. II eq. ME2-L
+    with gamma_ab(w) = C_ab gamma(w)).  Independent baths: sz_i of each qubit.  Correlated
+    baths: with C = L L^T (Cholesky; C positive definite) the double sum over qubits becomes
+    a sum over channels k with operators sum_a L[a, k] sz_a, each with rate gamma(w)."""
+    n = inst.n_qubits
+    sz = np.stack([sz_diag(i, n) for i in range(n)])
+    C = getattr(inst, "bath_corr", None)
+    if C is None:
+        return sz
+    L = np.linalg.cholesky(np.asarray(C, dtype=np.float64))
+    return L.T @ sz

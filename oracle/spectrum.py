@@ -163,9 +163,10 @@ def polar(M: np.ndarray, tau: float = 1e-4):
 def grid_tables(inst, E: np.ndarray, V: np.ndarray, dt: float):
     nq = inst.n_qubits
     n = len(E)
+    w = model.channel_weights(inst)                      # [channel, x]
     z = np.empty((nq, n, n))
     for i in range(nq):
-        z[i] = V.T @ (model.sz_diag(i, nq)[:, None] * V)
+        z[i] = V.T @ (w[i][:, None] * V)
     omega = E[None, :] - E[:, None]                      # omega[a, b] = E_b - E_a
     gam = model.gamma_ohmic(omega, inst.eta, inst.omega_c, inst.T)
     np.fill_diagonal(gam, model.gamma_ohmic(0.0, inst.eta, inst.omega_c, inst.T))

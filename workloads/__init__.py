@@ -49,6 +49,8 @@ class Instance:
     omega_c: float = 8.0 * math.pi
     T: float = kelvin_to_rad_per_ns(0.012)
     lamb_shift: bool = False      # include the Lamb-shift Hamiltonian of the Ohmic bath
+    bath_corr: Optional[np.ndarray] = None   # [n_qubits, n_qubits] correlation C of the baths
+                                             # (gamma_ab(w) = C_ab gamma(w)); None = independent
     n_grid: int = 1001            # s-grid points (n_grid - 1 steps)
     n_levels: int = 0             # retained levels; 0 = full spectrum
     n_traj: int = 1000
