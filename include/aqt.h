@@ -175,6 +175,19 @@ AQT_API aqt_status aqt_get_dims(aqt_ctx* ctx, int32_t* n_grid, int32_t* n_levels
  * still holds the true number of jumps of each trajectory. */
 AQT_API aqt_status aqt_run(aqt_ctx* ctx, const aqt_run_params* params, const aqt_outputs* out);
 
+/* ---- Correlated baths -----------------------------------------------------------------
+ * Baths with gamma_ab(w) = C_ab gamma(w) (Sec. II eq. ME2-L with a frequency-independent
+ * correlation between the qubits' baths; the Lamb shift, when on, uses C_ab S(w) alike).
+ * C: host [n_qubits * n_qubits], row-major, symmetric positive definite (C = I: the
+ * independent baths of the default; NULL restores them).  With C = L L^T (Cholesky) the
+ * double sum over qubits is a sum over n_qubits jump channels with coupling operators
+ * sum_a L[a][k] sz_a, each with rate gamma(w); every table, jump record ("qubit" is then
+ * the channel k) and the gradient refer to these channels.  Applies from the next
+ * aqt_precompute (loaded tables are invalidated); cleared by aqt_set_hamiltonian with a
+ * different qubit count.  AQT_ESTATE before aqt_set_hamiltonian; AQT_EINVAL if C is not
+ * finite, symmetric (1e-12 relative) or positive definite. */
+AQT_API aqt_status aqt_set_bath_correlation(aqt_ctx* ctx, const double* C);
+
 /* ---- Lamb shift ----------------------------------------------------------------------
  * enabled != 0 adds the Lamb-shift Hamiltonian of the Ohmic bath, H_LS = sum_i sum_w S(w)
  * A_i,w^dag A_i,w (Sec. II eq. ME2-H; the operators of the Bohr-frequency grouping), with

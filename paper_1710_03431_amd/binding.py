@@ -23,6 +23,7 @@ KIND_NAMES = ("relax", "excite", "dephase")
 EXPORTED = ("aqt_create", "aqt_destroy", "aqt_last_error", "aqt_version", "aqt_set_hamiltonian",
             "aqt_set_schedule", "aqt_set_bath", "aqt_precompute", "aqt_precompute_ex", "aqt_set_tables", "aqt_get_tables",
             "aqt_get_dims", "aqt_run", "aqt_grad_pgs", "aqt_set_lamb_shift", "aqt_get_lamb_shift",
+            "aqt_set_bath_correlation",
             "aqt_batch_create", "aqt_batch_launch", "aqt_batch_tiles",
             "aqt_batch_last_error", "aqt_batch_destroy")
 BATCH_GRAPH, BATCH_AUTOTUNE = 1, 2
@@ -93,6 +94,7 @@ def load_library(path: str = LIB_PATH):
     lib.aqt_run.argtypes = [ctx, C.POINTER(RunParams), C.POINTER(Outputs)]
     lib.aqt_grad_pgs.argtypes = [ctx, C.POINTER(RunParams), dp, dp, dp, dp, C.c_void_p]
     lib.aqt_set_lamb_shift.argtypes = [ctx, C.c_int]
+    lib.aqt_set_bath_correlation.argtypes = [ctx, dp]
     lib.aqt_get_lamb_shift.argtypes = [ctx, dp]
     lib.aqt_batch_create.argtypes = [C.POINTER(C.c_void_p), C.POINTER(C.c_void_p), C.c_int,
                                      C.POINTER(RunParams), C.POINTER(Outputs), C.c_int]
@@ -174,6 +176,10 @@ class Engine:
     def set_bath(self, eta, omega_c, T):
         self._check(self.lib.aqt_set_bath(self.ctx, float(eta), float(omega_c), float(T)))
 
+    def set_bath_correlation(self, C=None):
+        """gamma_ab(w) = C_ab gamma(w) between the qubits' baths (None: independent)."""
+        self._check(self.lib.aqt_set_bath_correlation(self.ctx, None if C is None else _dptr(_f64(C))))
+
     def set_lamb_shift(self, enabled: bool):
         self._check(self.lib.aqt_set_lamb_shift(self.ctx, int(bool(enabled))))
 
@@ -187,6 +193,7 @@ class Engine:
         self.set_hamiltonian(inst.h, inst.J)
         self.set_schedule(inst.t_f, inst.A_ctrl, inst.B_ctrl)
         self.set_bath(inst.eta, inst.omega_c, inst.T)
+        self.set_bath_correlation(getattr(inst, "bath_corr", None))
         self.set_lamb_shift(getattr(inst, "lamb_shift", False))
 
     def precompute(self, n_grid: int, n_levels: int, deg_tol: float = 1e-8, method: str = "auto"):

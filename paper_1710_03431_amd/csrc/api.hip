@@ -1,8 +1,9 @@
 // C-ABI entry points of libaqt (declared and documented in include/aqt.h).
 // Argument validation, host->device staging and call-order checks live here;
-// the numerical work is in tables.hip, step.hip and precompute.hip.
+// the numerical work is in tables.hip, step.hip, precompute.hip and grad.hip.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <new>
@@ -104,6 +105,7 @@ aqt_status aqt_set_hamiltonian(aqt_ctx* ctx, int n_qubits, const double* h, cons
   if (!h || !J) return ctx->fail(AQT_EINVAL, "h and J must be non-null");
   if (!finite_all(h, n_qubits) || !finite_all(J, static_cast<size_t>(n_qubits) * n_qubits))
     return ctx->fail(AQT_EINVAL, "h and J must be finite");
+  if (ctx->nq != n_qubits) ctx->chol.clear();   // a correlation matrix is per qubit count
   ctx->nq = n_qubits;
   ctx->h.assign(h, h + n_qubits);
   ctx->J.assign(J, J + static_cast<size_t>(n_qubits) * n_qubits);
@@ -262,6 +264,41 @@ aqt_status aqt_run(aqt_ctx* ctx, const aqt_run_params* p, const aqt_outputs* o) 
   aqt_status s = set_device(ctx);
   if (s != AQT_OK) return s;
   return aqt::launch_run(ctx, p, o);
+}
+
+aqt_status aqt_set_bath_correlation(aqt_ctx* ctx, const double* C) {
+  if (!ctx) return AQT_EINVAL;
+  if (!ctx->have_h) return ctx->fail(AQT_ESTATE, "set_hamiltonian must come first");
+  const int nq = ctx->nq;
+  if (!C) {
+    ctx->chol.clear();
+  } else {
+    double scale = 0.0;
+    for (int i = 0; i < nq * nq; ++i) {
+      if (!std::isfinite(C[i])) return ctx->fail(AQT_EINVAL, "correlation matrix has non-finite entries");
+      scale = std::max(scale, std::fabs(C[i]));
+    }
+    for (int i = 0; i < nq; ++i)
+      for (int j = 0; j < i; ++j)
+        if (std::fabs(C[i * nq + j] - C[j * nq + i]) > 1e-12 * scale)
+          return ctx->fail(AQT_EINVAL, "correlation matrix is not symmetric");
+    std::vector<double> L(static_cast<size_t>(nq) * nq, 0.0);
+    for (int j = 0; j < nq; ++j) {
+      double d = C[j * nq + j];
+      for (int k = 0; k < j; ++k) d -= L[j * nq + k] * L[j * nq + k];
+      if (!(d > 1e-12 * scale)) return ctx->fail(AQT_EINVAL, "correlation matrix is not positive definite");
+      L[j * nq + j] = std::sqrt(d);
+      for (int i = j + 1; i < nq; ++i) {
+        double v = C[i * nq + j];
+        for (int k = 0; k < j; ++k) v -= L[i * nq + k] * L[j * nq + k];
+        L[i * nq + j] = v / L[j * nq + j];
+      }
+    }
+    ctx->chol = L;
+  }
+  ctx->have_tables = false;
+  ctx->have_grad = false;
+  return AQT_OK;
 }
 
 aqt_status aqt_set_lamb_shift(aqt_ctx* ctx, int enabled) {

@@ -25,6 +25,7 @@ struct aqt_ctx {
   double eta = 0.0, omega_c = 0.0, T = 0.0;
   bool have_bath = false;
   bool lamb = false;    // add the Lamb shift at the next precompute
+  std::vector<double> chol;   // nq x nq lower Cholesky factor of the bath correlation (empty: independent)
 
   // ---- tables (device, FP64 masters; rows padded to NP with zeros)
   bool have_tables = false;

@@ -323,7 +323,7 @@ __global__ __launch_bounds__(kEigThreads) void k_canon(const double* __restrict_
 // C[b][i][j] (+)= sum_x w(x) A[i][x] B[j][x] for rows i < ra, j < rb: 64x64 tile
 // per workgroup, x staged through LDS in chunks of 32, 16x16x4 FP64 MFMAs.
 // wmode 0: w = 1; 1: w = sz of qubit (bz % nq) (operands of batch bz / nq); 2: w = x;
-// 3: w = wvec[x].  bdiv > 1: operand B of batch bz is B + sB * (bz / bdiv).
+// 3: w = wvec[x]; 4: w = wvec[(bz % nq) K + x] (channel weights; operands of batch bz / nq).  bdiv > 1: operand B of batch bz is B + sB * (bz / bdiv).
 // sub_eye: subtract the identity (stores O - I).
 struct GemmArgs {
   const double* A;
@@ -346,8 +346,8 @@ __global__ __launch_bounds__(256) void k_gemm_f64(GemmArgs p) {
   const int kpart = blockIdx.z - bz * p.ksplit;
   const int xbeg = (p.ksplit > 1) ? kpart * p.kspan : 0;
   const int xend = (p.ksplit > 1) ? min(p.K, xbeg + p.kspan) : p.K;
-  const int opb = (p.wmode == 1) ? bz / p.nq : bz;
-  const int qubit = (p.wmode == 1) ? bz % p.nq : 0;
+  const int opb = (p.wmode == 1 || p.wmode == 4) ? bz / p.nq : bz;
+  const int qubit = (p.wmode == 1 || p.wmode == 4) ? bz % p.nq : 0;
   const double* A = p.A + p.sA * opb;
   const double* B = p.B + p.sB * ((p.bdiv > 1) ? bz / p.bdiv : opb);
   double* C = p.C + p.sC * blockIdx.z;
@@ -365,6 +365,7 @@ __global__ __launch_bounds__(256) void k_gemm_f64(GemmArgs p) {
       if (p.wmode == 1) w = ((x >> qubit) & 1) ? -1.0 : 1.0;
       else if (p.wmode == 2) w = static_cast<double>(x);
       else if (p.wmode == 3 && x < xend) w = p.wvec[x];
+      else if (p.wmode == 4 && x < xend) w = p.wvec[static_cast<size_t>(qubit) * p.K + x];
       As[r][k] = (i0 + r < p.ra && x < xend) ? w * A[static_cast<size_t>(i0 + r) * p.lda + x] : 0.0;
       Bs[r][k] = (j0 + r < p.rb && x < xend) ? B[static_cast<size_t>(j0 + r) * p.ldb + x] : 0.0;
     }
@@ -1264,6 +1265,20 @@ aqt_status precompute_tables(aqt_ctx* ctx, int M, int n, double tol, int method,
   AQT_HIP(ctx, hipMemsetAsync(ctx->zdiag.p, 0, static_cast<size_t>(sNP) * nq * 8, st));
   AQT_HIP(ctx, hipMemsetAsync(ctx->leak.p, 0, M * 8, st));
   AQT_HIP(ctx, hipMemsetAsync(ctx->shift.p, 0, M * sNP * 8, st));
+  // jump-channel couplings: sz of each qubit, or for correlated baths gamma_ab = C_ab gamma
+  // with C = L L^T the channels sum_a L[a][k] sz_a (Sec. II eq. ME2-L)
+  DevBuf chw;
+  if (!ctx->chol.empty()) {
+    std::vector<double> w(static_cast<size_t>(nq) * N);
+    for (int k = 0; k < nq; ++k)
+      for (int x = 0; x < N; ++x) {
+        double acc = 0.0;
+        for (int a = k; a < nq; ++a) acc += ctx->chol[a * nq + k] * (((x >> a) & 1) ? -1.0 : 1.0);
+        w[static_cast<size_t>(k) * N + x] = acc;
+      }
+    if (chw.reserve(w.size() * 8)) return ctx->fail(AQT_ENOMEM, "channel weight allocation failed");
+    AQT_HIP(ctx, hipMemcpyAsync(chw.p, w.data(), w.size() * 8, hipMemcpyHostToDevice, st));
+  }
   // Lamb-shift function table over every Bohr frequency (Gershgorin bound on |e|)
   DevBuf lambS, gl;
   LambTable ltab{nullptr, 0.0};
@@ -1467,7 +1482,8 @@ aqt_status precompute_tables(aqt_ctx* ctx, int M, int n, double tol, int method,
       const int off = zg0 - g0;
       GemmArgs ga{Vc.as<double>() + off * Vstride, Vc.as<double>() + off * Vstride, zws.as<double>(),
                   static_cast<int64_t>(Vstride), static_cast<int64_t>(Vstride), static_cast<int64_t>(n) * n,
-                  n, n, N, N, N, n, 1, nq, 0};
+                  n, n, N, N, N, n, chw.p ? 4 : 1, nq, 0};
+      ga.wvec = chw.as<double>();
       aqt_status s = launch_gemm(ctx, ga, zcnt * nq);
       if (s != AQT_OK) return s;
       hipLaunchKernelGGL(k_rates, dim3(nblk(static_cast<int64_t>(nq) * NP * NP * zcnt)), dim3(256), 0, st,
