@@ -170,3 +170,81 @@ def mean_and_stderr(sum_, sumsq, R: int):
     mean = sum_ / R
     var = (sumsq - R * mean * mean) / (R - 1)
     return mean, np.sqrt(np.maximum(var, 0.0) / R)
+
+
+def run_fixed_step(tables: Iterable, inst, n_traj: int, substeps: int, *, n_grid: Optional[int] = None,
+                   seed: Optional[int] = None, instance_id: Optional[int] = None, traj_offset: int = 0,
+                   record: bool = True) -> TrajectoryResult:
+    """Fixed-step quantum-jump unraveling (App. B, "to jump or not to jump"): each grid step
+    of length dt is cut into `substeps` sub-steps of length h with the generator frozen at
+    the grid point (as in run).  Per sub-step the normalised state has jump probability
+    dp = h sum_b |c_b|^2 Gamma_b (eq. lambda); a uniform eps decides: eps >= dp evolves
+    with the no-jump propagator exp(-i e h - Gamma h / 2) and renormalises, eps < dp
+    applies the jump operator drawn with probability proportional to its rate (eq. Pi(t):
+    source b with weight |c_b|^2 Gamma_b, then qubit and target by R, as in run) and
+    renormalises.  First order in h: the mean approaches the master equation as h -> 0.
+
+    Draws: sub-step u = (g - 1) substeps + s of trajectory j uses draws 3u (eps), 3u + 1
+    (source) and 3u + 2 (qubit and target).  Jump records carry the sub-step's start time."""
+    M = n_grid or inst.n_grid
+    dt = inst.t_f / (M - 1)
+    h = dt / substeps
+    seed = inst.seed if seed is None else seed
+    iid = inst.instance_id if instance_id is None else instance_id
+    K = n_traj
+    tid = np.arange(traj_offset, traj_offset + K, dtype=np.uint64)
+    pgs_sum = np.zeros(M)
+    pgs_sumsq = np.zeros(M)
+    pgs_sum[0] = K
+    pgs_sumsq[0] = K
+    jumps = [[] for _ in range(K)] if record else None
+    net = np.zeros(K, dtype=np.int64)
+    kinds = np.zeros(3, dtype=np.int64)
+    c = None
+    for T in tables:
+        g = T.g
+        k = g - 1
+        if g == 1:
+            c = np.repeat(T.cinit.astype(np.complex128)[:, None], K, axis=1)
+        else:
+            c = T.O @ c
+        Gam = T.Gamma
+        dsub = np.exp(-1j * T.Eph * h - 0.5 * Gam * h)
+        for s in range(substeps):
+            u = k * substeps + s
+            pop = np.abs(c) ** 2
+            dp = h * (pop * Gam[:, None]).sum(axis=0) / pop.sum(axis=0)
+            eps = philox.draw(seed, iid, tid, np.uint64(3 * u))
+            jump = eps < dp
+            stay = ~jump
+            c[:, stay] *= dsub[:, None]
+            c[:, stay] /= np.linalg.norm(c[:, stay], axis=0)[None, :]
+            for j in np.nonzero(jump)[0]:
+                cj = c[:, j]
+                q = np.abs(cj) ** 2
+                u1 = philox.draw_scalar(seed, iid, tid[j], 3 * u + 1)
+                u2 = philox.draw_scalar(seed, iid, tid[j], 3 * u + 2)
+                b = pick(q * Gam, float(u1))
+                ia = pick(T.R[:, b, :].ravel(), float(u2))
+                i, a = divmod(ia, len(Gam))
+                if a != b:
+                    cj = np.zeros_like(cj)
+                    cj[a] = 1.0
+                    kind = KIND_RELAX if T.E[a] <= T.E[b] else KIND_EXCITE
+                    if a < T.gs <= b:
+                        net[j] += 1
+                    elif b < T.gs <= a:
+                        net[j] -= 1
+                else:
+                    cj = T.zdiag[i] * cj
+                    kind = KIND_DEPHASE
+                c[:, j] = cj / np.linalg.norm(cj)
+                kinds[kind] += 1
+                if record:
+                    jumps[j].append((k * dt + s * h, k, int(i), int(b), int(a), kind))
+        pop = np.abs(c) ** 2
+        p = pop[:T.gs].sum(axis=0) / pop.sum(axis=0)
+        pgs_sum[g] = p.sum()
+        pgs_sumsq[g] = (p * p).sum()
+    return TrajectoryResult(pgs_sum=pgs_sum, pgs_sumsq=pgs_sumsq, jumps=jumps, net_gs=net,
+                            kind_totals=kinds, final_state=c, n_traj=K)

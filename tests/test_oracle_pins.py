@@ -586,3 +586,37 @@ def test_correlated_baths_split_step_equals_double_sum(rho):
         base = spectrum.all_tables(inst.with_(bath_corr=None), n_grid=6)
         for T, B in zip(spectrum.all_tables(inst, n_grid=6), base):
             np.testing.assert_array_equal(T.R, B.R)
+
+
+def test_fixed_step_two_level_follows_the_discrete_chain():
+    """Fixed-step unraveling (App. B): a frozen two-level system stays in eigenstates, and
+    per sub-step h it jumps 0 -> 1 with probability h W10 and 1 -> 0 with h W01, so its
+    mean follows the discrete chain p <- p (1 - h W10) + (1 - p) h W01, not the AME's
+    exponential relaxation (which the waiting-time procedure reproduces)."""
+    inst = W.two_level_fixed(A=0.3, t_f=20.0, n_grid=11, eta=1e-2)
+    tabs = spectrum.all_tables(inst)
+    S, K = 2, 20000
+    res = trajectories.run_fixed_step(tabs, inst, K, S, record=False)
+    T = tabs[0]
+    W10, W01 = T.R[:, 0, 1].sum(), T.R[:, 1, 0].sum()
+    h = inst.t_f / (inst.n_grid - 1) / S
+    p, chain = 1.0, [1.0]
+    for _ in range(1, inst.n_grid):
+        for _ in range(S):
+            p = p * (1 - h * W10) + (1 - p) * h * W01
+        chain.append(p)
+    chain = np.array(chain)
+    m, se = trajectories.mean_and_stderr(res.pgs_sum, res.pgs_sumsq, K)
+    assert np.all(np.abs(m - chain)[1:] <= 3 * se[1:])
+    P = ame.split_step(tabs, inst)
+    assert np.max(np.abs(m - P)[1:] / se[1:]) > 4
+
+
+def test_fixed_step_closed_system_is_the_no_jump_evolution():
+    """eta = 0: no jumps, and the fixed-step state equals the waiting-time run's."""
+    inst = W.ring_instance(3, 77, t_f=30.0, eta=0.0, n_grid=60)
+    tabs = spectrum.all_tables(inst)
+    a = trajectories.run_fixed_step(tabs, inst, 3, 5)
+    b = trajectories.run(tabs, inst, 3)
+    assert a.kind_totals.sum() == 0
+    np.testing.assert_allclose(a.final_state, b.final_state, atol=1e-12)
