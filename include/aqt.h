@@ -175,6 +175,24 @@ AQT_API aqt_status aqt_get_dims(aqt_ctx* ctx, int32_t* n_grid, int32_t* n_levels
  * still holds the true number of jumps of each trajectory. */
 AQT_API aqt_status aqt_run(aqt_ctx* ctx, const aqt_run_params* params, const aqt_outputs* out);
 
+/* ---- Fixed-step unraveling ------------------------------------------------------------
+ * The second unraveling (App. B, "to jump or not to jump"): every grid step is cut into
+ * `substeps` sub-steps of length h = dt / substeps with the same frozen generator and
+ * basis changes as aqt_run.  Per sub-step the normalised state jumps with probability
+ * dp = h sum_b |c_b|^2 Gamma_b (eq. lambda): a uniform eps < dp applies the jump drawn as
+ * in aqt_run (source weight |c_b|^2 Gamma_b, then channel and target by R; eq. Pi(t)),
+ * otherwise the sub-step's no-jump propagator is applied; the state is renormalised
+ * either way.  First order in h (aqt_run's waiting-time procedure is exact within each
+ * step): a cross-check of the unraveling, its mean approaching the master equation as
+ * h -> 0.  Draws: sub-step u = (step) substeps + s uses draws 3u (eps), 3u + 1 (source),
+ * 3u + 2 (channel and target) of the same Philox streams; jump records carry the
+ * sub-step's start time.  params as aqt_run (precision AQT_FP64 or AQT_FP32; tile and
+ * segment ignored: 16 trajectories per workgroup).  Writes pgs_sum, pgs_sumsq,
+ * jump_totals (+=), jump_count, jumps, net_gs, final_state (each may be NULL); net_hist
+ * must be NULL.  Stream-ordered; never synchronises. */
+AQT_API aqt_status aqt_run_fixed_step(aqt_ctx* ctx, const aqt_run_params* params, int substeps,
+                                      const aqt_outputs* out);
+
 /* ---- Correlated baths -----------------------------------------------------------------
  * Baths with gamma_ab(w) = C_ab gamma(w) (Sec. II eq. ME2-L with a frequency-independent
  * correlation between the qubits' baths; the Lamb shift, when on, uses C_ab S(w) alike).

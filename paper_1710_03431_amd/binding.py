@@ -23,7 +23,7 @@ KIND_NAMES = ("relax", "excite", "dephase")
 EXPORTED = ("aqt_create", "aqt_destroy", "aqt_last_error", "aqt_version", "aqt_set_hamiltonian",
             "aqt_set_schedule", "aqt_set_bath", "aqt_precompute", "aqt_precompute_ex", "aqt_set_tables", "aqt_get_tables",
             "aqt_get_dims", "aqt_run", "aqt_grad_pgs", "aqt_set_lamb_shift", "aqt_get_lamb_shift",
-            "aqt_set_bath_correlation",
+            "aqt_set_bath_correlation", "aqt_run_fixed_step",
             "aqt_batch_create", "aqt_batch_launch", "aqt_batch_tiles",
             "aqt_batch_last_error", "aqt_batch_destroy")
 BATCH_GRAPH, BATCH_AUTOTUNE = 1, 2
@@ -95,6 +95,7 @@ def load_library(path: str = LIB_PATH):
     lib.aqt_grad_pgs.argtypes = [ctx, C.POINTER(RunParams), dp, dp, dp, dp, C.c_void_p]
     lib.aqt_set_lamb_shift.argtypes = [ctx, C.c_int]
     lib.aqt_set_bath_correlation.argtypes = [ctx, dp]
+    lib.aqt_run_fixed_step.argtypes = [ctx, C.POINTER(RunParams), C.c_int, C.POINTER(Outputs)]
     lib.aqt_get_lamb_shift.argtypes = [ctx, dp]
     lib.aqt_batch_create.argtypes = [C.POINTER(C.c_void_p), C.POINTER(C.c_void_p), C.c_int,
                                      C.POINTER(RunParams), C.POINTER(Outputs), C.c_int]
@@ -283,6 +284,29 @@ class Engine:
             res["final_state"] = res["final_state"].reshape(n_traj, self.n_levels, 2)
         return res
 
+
+    def run_fixed_step(self, n_traj: int, substeps: int, precision="fp64", seed=0, instance_id=0, traj_offset=0,
+                       record_capacity=0, final_state=False):
+        """Fixed-step unraveling (aqt_run_fixed_step); host numpy results (synchronises)."""
+        outs = self.alloc_outputs(n_traj, record_capacity, (0, 0), final_state)
+        outs.pop("net_hist")
+        p = _params(n_traj, precision, seed, instance_id, traj_offset, record_capacity, 0)
+
+        def ptr(k):
+            v = outs.get(k)
+            return None if v is None else v.data_ptr()
+
+        o = Outputs(pgs_sum=ptr("pgs_sum"), pgs_sumsq=ptr("pgs_sumsq"), jump_totals=ptr("jump_totals"),
+                    jump_count=ptr("jump_count"), jumps=ptr("jumps"), net_gs=ptr("net_gs"), net_hist=None,
+                    hist_lo=0, hist_hi=0, final_state=ptr("final_state"))
+        self._check(self.lib.aqt_run_fixed_step(self.ctx, C.byref(p), int(substeps), C.byref(o)))
+        self.stream.synchronize()
+        res = {k: v.cpu().numpy() for k, v in outs.items() if k not in ("hist", "jumps")}
+        if record_capacity:
+            res["jumps"] = outs["jumps"].cpu().numpy().view(JUMP_DTYPE).reshape(n_traj, record_capacity)
+        if final_state:
+            res["final_state"] = res["final_state"].reshape(n_traj, self.n_levels, 2)
+        return res
 
     # ---------------------------------------------------------------- gradient
     def grad_pgs(self, n_traj: int, precision="fp32", seed=0, instance_id=0, traj_offset=0, tile=0,

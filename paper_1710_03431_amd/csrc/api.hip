@@ -266,6 +266,22 @@ aqt_status aqt_run(aqt_ctx* ctx, const aqt_run_params* p, const aqt_outputs* o) 
   return aqt::launch_run(ctx, p, o);
 }
 
+aqt_status aqt_run_fixed_step(aqt_ctx* ctx, const aqt_run_params* p, int substeps, const aqt_outputs* o) {
+  if (!ctx) return AQT_EINVAL;
+  if (!p || !o) return ctx->fail(AQT_EINVAL, "params and outputs are required");
+  if (!ctx->have_tables) return ctx->fail(AQT_ESTATE, "precompute or set_tables must come first");
+  if (p->n_traj < 1) return ctx->fail(AQT_EINVAL, "n_traj must be >= 1");
+  if (p->precision != AQT_FP64 && p->precision != AQT_FP32)
+    return ctx->fail(AQT_EINVAL, "the fixed-step unraveling runs in AQT_FP64 or AQT_FP32");
+  if (substeps < 1) return ctx->fail(AQT_EINVAL, "substeps must be >= 1");
+  if (p->record_capacity < 0) return ctx->fail(AQT_EINVAL, "record_capacity must be >= 0");
+  if (p->record_capacity > 0 && !o->jumps) return ctx->fail(AQT_EINVAL, "record_capacity > 0 needs a jumps buffer");
+  if (o->net_hist) return ctx->fail(AQT_EINVAL, "the fixed-step unraveling does not fill net_hist");
+  aqt_status s = set_device(ctx);
+  if (s != AQT_OK) return s;
+  return aqt::launch_fixed_step(ctx, p, substeps, o);
+}
+
 aqt_status aqt_set_bath_correlation(aqt_ctx* ctx, const double* C) {
   if (!ctx) return AQT_EINVAL;
   if (!ctx->have_h) return ctx->fail(AQT_ESTATE, "set_hamiltonian must come first");

@@ -57,6 +57,8 @@ struct aqt_ctx {
   aqt::DevBuf dzd;      // [M][2][nq][NP] d z_i[x][x]
   aqt::DevBuf dll;      // [M][2][nq][NP(b)][NP(a)] d log |l_i,ab|
   aqt::DevBuf dcin;     // [2][NP] derivative of the initial state through grid 0
+  int fix_prec = -1;    // precision of the fixed-step kernel's O_g - I copy, -1 = none
+  aqt::DevBuf fix_D;
   int gpk_prec = -1;    // precision of the sweep operands below, -1 = none
   aqt::DevBuf gpk_D, gpk_DT, gpk_X;   // O_g - I, its transpose, X_g in that precision
 
@@ -92,6 +94,9 @@ aqt_status launch_run(aqt_ctx* ctx, const aqt_run_params* p, const aqt_outputs* 
 
 // precompute.hip: GPU eigensystem and tables.
 aqt_status precompute_tables(aqt_ctx* ctx, int n_grid, int n_levels, double deg_tol, int method, bool grad = false);
+
+// mcwf.hip: fixed-step unraveling.
+aqt_status launch_fixed_step(aqt_ctx* ctx, const aqt_run_params* p, int substeps, const aqt_outputs* o);
 
 // grad.hip: adjoint gradient of the final ground-cluster population.
 aqt_status launch_grad(aqt_ctx* ctx, const aqt_run_params* p, double* value, double* value_se, double* grad,

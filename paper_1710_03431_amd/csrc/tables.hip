@@ -171,6 +171,7 @@ aqt_status finish_tables(aqt_ctx* ctx) {
                      ctx->Rcol.as<double>(), ctx->ehalf.as<double>(), ctx->dre.as<double>(), ctx->dim.as<double>());
   AQT_HIP(ctx, hipGetLastError());
   ctx->packed_for = -1;
+  ctx->fix_prec = -1;
   return AQT_OK;
 }
 
