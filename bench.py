@@ -1,6 +1,7 @@
 """Throughput of the GPU trajectory engine.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload a2a8|ring4|gadget16|batched|grad]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload a2a8|ring4|gadget16|batched|grad|fixed]
+                    [--lamb-shift]
                     [--cpu-traj 3072] [--cpu-grid 500] [--no-cpu]
 
 One bench step = one aqt_run: all trajectories of the workload through the whole
@@ -25,6 +26,10 @@ Workloads:
             schedule control points and eta (aqt_grad_pgs) on the a2a8 instance,
             10^5 FP32 trajectories; one step = one gradient evaluation (forward run,
             checkpointed replay and adjoint sweep), value = trajectory-steps/s of it
+  fixed     the a2a8 anneal with the fixed-step unraveling (aqt_run_fixed_step, 4
+            sub-steps per grid step), FP32; value = grid trajectory-steps/s, with the
+            waiting-time run timed beside it
+--lamb-shift adds the Ohmic Lamb shift to the tables (a2a8, ring4, fixed)
 """
 import argparse
 import json
@@ -47,7 +52,9 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="a2a8", choices=("a2a8", "ring4", "gadget16", "batched", "grad"))
+    ap.add_argument("--workload", default="a2a8", choices=("a2a8", "ring4", "gadget16", "batched", "grad", "fixed"))
+    ap.add_argument("--lamb-shift", action="store_true")
+    ap.add_argument("--substeps", type=int, default=4)
     ap.add_argument("--n-traj", type=int, default=0, help="override the workload's trajectory count")
     ap.add_argument("--cpu-traj", type=int, default=3072)
     ap.add_argument("--cpu-grid", type=int, default=0, help="steps of the CPU sample (default per workload)")
@@ -312,6 +319,53 @@ def bench_grad(args):
     print(json.dumps(line))
 
 
+def bench_fixed(args):
+    """Fixed-step unraveling on the a2a8 anneal, waiting-time aqt_run beside it."""
+    import torch
+    import workloads as W
+    from paper_1710_03431_amd.binding import Engine
+    inst = W.config_a2a8(args.n_traj or 10_000).with_(lamb_shift=args.lamb_shift)
+    K, M, n, S = inst.n_traj, inst.n_grid, inst.levels, args.substeps
+    eng = Engine(0)
+    eng.set_instance(inst)
+    t0 = time.perf_counter()
+    eng.precompute(M, n)
+    precompute_s = time.perf_counter() - t0
+    ref = load_ame_reference(None if args.lamb_shift else "a2a8_ame_pgs.json")
+    for w in range(args.warmup):
+        eng.run_fixed_step(K, S, "fp32", seed=inst.seed + 100 + w)
+    times, p = [], []
+    for i in range(args.steps):
+        torch.cuda.synchronize()
+        ts = time.perf_counter()
+        r = eng.run_fixed_step(K, S, "fp32", seed=inst.seed + i, instance_id=inst.instance_id)
+        times.append(time.perf_counter() - ts)
+        p.append(float(r["pgs_sum"][-1]) / K)
+    ms = 1e3 * sum(times) / len(times)
+    wt = time_precision(eng, torch, K, "fp32", max(1, args.steps), 1, seed=inst.seed)
+    wt_ms = sum(wt["event_ms"]) / len(wt["event_ms"])
+    flops = FLOP_PER_TRAJ_STEP(n) * K * (M - 1)
+    achieved = flops / (ms / 1e3)
+    print(f"# fixed-step ({S} sub-steps): {ms:.1f} ms/run, waiting-time {wt_ms:.1f} ms/run; "
+          f"P_GS(1) {sum(p) / len(p):.5f} vs waiting-time {sum(wt['pgs_final']) / len(wt['pgs_final']):.5f}",
+          file=sys.stderr, flush=True)
+    line = {
+        "metric": "grid trajectory-steps/s of the fixed-step unraveling at 1 MI355X", "value": K * (M - 1) / (ms / 1e3),
+        "unit": "trajectory-steps/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "fp32", "data": "synthetic",
+        "config": {"workload": f"8-qubit all-to-all +-1 anneal, n=256, {M} grid points x {S} sub-steps, t_f=10us, "
+                               f"{K} trajectories" + (", Lamb shift" if args.lamb_shift else ""),
+                   "substeps": S, "lamb_shift": args.lamb_shift},
+        "P_GS_final": sum(p) / len(p), "P_GS_final_waiting_time": sum(wt["pgs_final"]) / len(wt["pgs_final"]),
+        "P_GS_final_ame": (ref["pgs"][-1] if ref else None), "waiting_time_ms": wt_ms, "precompute_s": precompute_s,
+        "roofline": {"bound": "mfma", "achieved": achieved / 1e12, "peak": PEAK["fp32"] / 1e12, "unit": "TFLOP/s",
+                     "frac": achieved / PEAK["fp32"], "traffic": None, "kernel": "k_fixed_step<256, 16, float>",
+                     "per_unit": f"{FLOP_PER_TRAJ_STEP(n)} flop per grid trajectory-step (the basis change)"},
+        "cpu_baseline": None,
+    }
+    print(json.dumps(line))
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -324,11 +378,16 @@ def main():
     if args.workload == "grad":
         bench_grad(args)
         return
+    if args.workload == "fixed":
+        bench_fixed(args)
+        return
     import torch
     from paper_1710_03431_amd.binding import Engine
 
     wl = workload(args.workload, args.n_traj)
-    inst = wl["inst"]
+    inst = wl["inst"].with_(lamb_shift=args.lamb_shift)
+    if args.lamb_shift:
+        wl["golden"] = None   # the stored AME references have no Lamb shift
     K = inst.n_traj
     M = inst.n_grid
     n = inst.levels
@@ -375,8 +434,8 @@ def main():
         "metric": METRIC, "value": head["value"], "unit": "trajectory-steps/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": head["ms"], "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": head_prec, "data": "synthetic",
-        "config": {"workload": wl["text"], "name": inst.name, "n_traj": K, "n_levels": n, "n_grid": M,
-                   "precision": head_prec, "seed": inst.seed},
+        "config": {"workload": wl["text"] + (", Lamb shift" if args.lamb_shift else ""), "name": inst.name,
+                   "n_traj": K, "n_levels": n, "n_grid": M, "precision": head_prec, "seed": inst.seed},
         "error_vs_fp64_ame": {"P_GS_final_ame": p_ame,
                               **{p: {"P_GS_final": v["pgs_final"], "stderr": v["pgs_se"],
                                      "abs_err": v["err_vs_ame"]} for p, v in results.items()}},
