@@ -61,7 +61,6 @@ def step_map(rho: np.ndarray, T, inst, dt: float) -> np.ndarray:
 def split_step(tables, inst, n_grid=None, keep_rho=False):
     """P_GS(s_g) for g = 0..M-1 (and optionally the final rho) of the split-step AME."""
     M = n_grid or inst.n_grid
-    dt = inst.t_f / (M - 1)
     P = np.zeros(M)
     P[0] = 1.0
     rho = None
@@ -70,7 +69,7 @@ def split_step(tables, inst, n_grid=None, keep_rho=False):
             rho = np.outer(T.cinit, T.cinit).astype(np.complex128)
         else:
             rho = T.O @ rho @ T.O.T
-        rho = step_map(rho, T, inst, dt)
+        rho = step_map(rho, T, inst, T.dt)
         P[T.g] = float(np.real(np.trace(rho[:T.gs, :T.gs])))
     return (P, rho) if keep_rho else P
 
@@ -84,11 +83,10 @@ def expected_jumps(tables, inst, n_grid=None):
     gamma(0) sum_b z_i[b, b]^2 rho_bb.  Within a step the populations follow
     expm(W tau) p, integrated exactly with an augmented matrix exponential.
     """
-    M = n_grid or inst.n_grid
-    dt = inst.t_f / (M - 1)
     out = np.zeros(3)
     rho = None
     for T in tables:
+        dt = T.dt
         if T.g == 1:
             rho = np.outer(T.cinit, T.cinit).astype(np.complex128)
         else:

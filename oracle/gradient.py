@@ -105,8 +105,6 @@ def replay_log_weight(tables, inst, paths, n_grid=None):
 
     Returns (log <psi~|Pi|psi~>, log <psi~|psi~>, final carried states [n, K]) with Pi
     the projector on the ground cluster of the last grid point."""
-    M = n_grid or inst.n_grid
-    dt = inst.t_f / (M - 1)
     K = len(paths)
     first = defaultdict(list)            # step -> [(trajectory, index of its first jump in the step)]
     for j, p in enumerate(paths):
@@ -118,7 +116,7 @@ def replay_log_weight(tables, inst, paths, n_grid=None):
     gs = 1
     for T in tables:
         k = T.g - 1
-        t_k = k * dt
+        t_k, dt = T.t0, T.dt
         C = np.repeat(T.cinit.astype(np.complex128)[:, None], K, axis=1) if T.g == 1 else T.O @ C
         starts = first.get(k, [])
         saved = [C[:, j].copy() for j, _ in starts]

@@ -60,6 +60,8 @@ class GridTables:
     leak: float
     V: Optional[np.ndarray] = None   # [N, n] (kept only on request)
     shift: Optional[np.ndarray] = None   # [n] Lamb shift of each level (zeros when off)
+    dt: float = 0.0          # length of the step into this grid point (ns)
+    t0: float = 0.0          # time at its start (ns)
 
     @property
     def Eph(self) -> np.ndarray:
@@ -224,6 +226,7 @@ def table_stream(inst, n_grid: Optional[int] = None, n_levels: Optional[int] = N
     Vprev = None
     for g in range(1, M):
         s = g / (M - 1)
+        t0 = (g - 1) * dt
         need_prev = grids is not None and (g + 1) in grids
         if grids is not None and g not in grids and not need_prev:
             Vprev = None
@@ -245,8 +248,10 @@ def table_stream(inst, n_grid: Optional[int] = None, n_levels: Optional[int] = N
         Vprev = V
         if grids is None or g in grids:
             yield GridTables(g=g, s=s, E=E, gs=gs, O=O, cinit=cinit, z=z, R=R, Gamma=Gamma,
-                             zdiag=zdiag, d=d, leak=leak, V=V if keep_V else None, shift=shift)
+                             zdiag=zdiag, d=d, leak=leak, V=V if keep_V else None, shift=shift,
+                             dt=dt, t0=t0)
 
 
 def all_tables(inst, **kw):
     return list(table_stream(inst, **kw))
+

@@ -93,7 +93,6 @@ def run(tables: Iterable, inst, n_traj: int, *, n_grid: Optional[int] = None, se
         instance_id: Optional[int] = None, traj_offset: int = 0, record: bool = True,
         n_levels: Optional[int] = None) -> TrajectoryResult:
     M = n_grid or inst.n_grid
-    dt = inst.t_f / (M - 1)
     seed = inst.seed if seed is None else seed
     iid = inst.instance_id if instance_id is None else instance_id
     K = n_traj
@@ -111,7 +110,7 @@ def run(tables: Iterable, inst, n_traj: int, *, n_grid: Optional[int] = None, se
     for T in tables:
         g = T.g
         k = g - 1
-        t_k = k * dt
+        t_k, dt = T.t0, T.dt
         if g == 1:
             c = np.repeat(T.cinit.astype(np.complex128)[:, None], K, axis=1)
         else:
@@ -187,8 +186,6 @@ def run_fixed_step(tables: Iterable, inst, n_traj: int, substeps: int, *, n_grid
     Draws: sub-step u = (g - 1) substeps + s of trajectory j uses draws 3u (eps), 3u + 1
     (source) and 3u + 2 (qubit and target).  Jump records carry the sub-step's start time."""
     M = n_grid or inst.n_grid
-    dt = inst.t_f / (M - 1)
-    h = dt / substeps
     seed = inst.seed if seed is None else seed
     iid = inst.instance_id if instance_id is None else instance_id
     K = n_traj
@@ -204,6 +201,7 @@ def run_fixed_step(tables: Iterable, inst, n_traj: int, substeps: int, *, n_grid
     for T in tables:
         g = T.g
         k = g - 1
+        h = T.dt / substeps
         if g == 1:
             c = np.repeat(T.cinit.astype(np.complex128)[:, None], K, axis=1)
         else:
@@ -241,7 +239,7 @@ def run_fixed_step(tables: Iterable, inst, n_traj: int, substeps: int, *, n_grid
                 c[:, j] = cj / np.linalg.norm(cj)
                 kinds[kind] += 1
                 if record:
-                    jumps[j].append((k * dt + s * h, k, int(i), int(b), int(a), kind))
+                    jumps[j].append((T.t0 + s * h, k, int(i), int(b), int(a), kind))
         pop = np.abs(c) ** 2
         p = pop[:T.gs].sum(axis=0) / pop.sum(axis=0)
         pgs_sum[g] = p.sum()
