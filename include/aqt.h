@@ -250,7 +250,7 @@ AQT_API aqt_status aqt_get_lamb_shift(aqt_ctx* ctx, double* shift);
  * Needs tables from aqt_precompute with n_levels = 2^n_qubits (AQT_ESTATE after
  * aqt_set_tables, AQT_EINVAL for truncated spectra); the first call after a
  * precompute re-runs the eigensolver to add the derivative tables.  AQT_ECAPACITY if
- * one trajectory takes more than 64 omega = 0 jumps within one step.  Synchronises. */
+ * one trajectory takes more than 32 omega = 0 jumps within one step.  Synchronises. */
 AQT_API aqt_status aqt_grad_pgs(aqt_ctx* ctx, const aqt_run_params* params, double* value, double* value_se,
                                 double* grad, double* grad_se, double* per_traj);
 

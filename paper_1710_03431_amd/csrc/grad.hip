@@ -38,6 +38,10 @@
 // Controls enter through A(s_g) and B(s_g) with the hat-function weights of the
 // piecewise-linear schedule.
 //
+// The same sweep carries a second adjoint with the identity in place of Pi: it gives
+// s = d log |psi~|^2, the score of the path density (mean zero), used as a control
+// variate.  Both adjoints share the replayed states and the X_g products.
+//
 // The forward paths come from the trajectory kernel (its jump records); one
 // workgroup owns TT trajectories for the whole sweep: a forward replay that stores
 // the state every C steps, then per segment of C steps (last first) a replay that
@@ -57,7 +61,7 @@ namespace {
 
 using namespace tile;
 
-constexpr int kMaxJ = 64;           // omega = 0 jumps of one trajectory within one step
+constexpr int kMaxJ = 32;           // omega = 0 jumps of one trajectory within one step
 
 struct GradArgs {
   const void* pD;        // [M][NP][NP] O_g - I in the state precision
@@ -92,35 +96,40 @@ struct GradArgs {
   int64_t K, tile0;
 };
 
-// part[2 b][t] += Re <L_b,t | X | B_b,t> for the TT trajectories of each of the NB
-// operand pairs (columns 2t, 2t+1 = re, im); each wave adds to its own part rows.
-template <int NP, int NC, int LD, class T, int NB>
-__device__ void gemm_dot(const T* __restrict__ X, const T* const (&B)[NB], const T* const (&L)[NB], double* part,
-                         int pstride) {
+// part1[t] += Re <L1_t | X | B_t> and part2[t] += Re <L2_t | X | B_t>: one product, two
+// adjoints (columns 2t, 2t+1 = re, im); each wave adds to its own part rows.
+template <int NP, int NC, int LD, class T>
+__device__ void gemm_dot2(const T* __restrict__ X, const T* B, const T* L1, const T* L2, double* part1,
+                          double* part2) {
   constexpr int RT = NP / 16, CT = NC / 16;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, c = lane & 15;
+  const T* const Bs[1] = {B};
   for (int rt = wave; rt < RT; rt += kGW) {
-    typename Mfma<T>::acc_t acc[NB][CT];
+    typename Mfma<T>::acc_t acc[1][CT];
 #pragma unroll
-    for (int b = 0; b < NB; ++b)
+    for (int ct = 0; ct < CT; ++ct) acc[0][ct] = Mfma<T>::zero();
+    panel_mma<NP, NC, LD, T, 1>(X, rt, Bs, acc);
 #pragma unroll
-      for (int ct = 0; ct < CT; ++ct) acc[b][ct] = Mfma<T>::zero();
-    panel_mma<NP, NC, LD, T, NB>(X, rt, B, acc);
+    for (int ct = 0; ct < CT; ++ct) {
+      double s1 = 0.0, s2 = 0.0;
 #pragma unroll
-    for (int b = 0; b < NB; ++b)
-#pragma unroll
-      for (int ct = 0; ct < CT; ++ct) {
-        double s = 0.0;
-#pragma unroll
-        for (int e = 0; e < 4; ++e) {
-          const int r = rt * 16 + Mfma<T>::row(lane, e);
-          s += static_cast<double>(L[b][r * LD + ct * 16 + c]) * static_cast<double>(acc[b][ct][e]);
-        }
-        s += __shfl_xor(s, 16, 64);
-        s += __shfl_xor(s, 32, 64);
-        s += __shfl_xor(s, 1, 64);
-        if (lane < 16 && !(lane & 1)) part[b * pstride + ((ct * 16 + lane) >> 1)] += s;
+      for (int e = 0; e < 4; ++e) {
+        const int r = rt * 16 + Mfma<T>::row(lane, e), col = ct * 16 + c;
+        const double y = static_cast<double>(acc[0][ct][e]);
+        s1 += static_cast<double>(L1[r * LD + col]) * y;
+        s2 += static_cast<double>(L2[r * LD + col]) * y;
       }
+      s1 += __shfl_xor(s1, 16, 64);
+      s1 += __shfl_xor(s1, 32, 64);
+      s1 += __shfl_xor(s1, 1, 64);
+      s2 += __shfl_xor(s2, 16, 64);
+      s2 += __shfl_xor(s2, 32, 64);
+      s2 += __shfl_xor(s2, 1, 64);
+      if (lane < 16 && !(lane & 1)) {
+        part1[(ct * 16 + lane) >> 1] += s1;
+        part2[(ct * 16 + lane) >> 1] += s2;
+      }
+    }
   }
 }
 
@@ -130,15 +139,14 @@ struct GradShared {
   // FP32: 4 LD = 16 (mod 64) puts the four k rows of an MFMA operand read in disjoint bank
   // ranges; FP64 keeps the smallest odd stride (LDS budget at 256 levels)
   static constexpr int LD = (sizeof(T) == 4 && NC == 32) ? 36 : NC + 1;
-  T PA[NP * LD];                 // psi just after the step's kick
-  T PB[NP * LD];                 // psi at the end of the step
-  T LA[NP * LD];                 // adjoints at the same points
-  T LB[NP * LD];
+  // four state tiles whose roles rotate: the post-kick state, the end-of-step state and the
+  // two adjoints (ground-cluster projector; identity, for the path-density score)
+  T buf[4][NP * LD];
   int cur[TT];                   // running record cursor
   double f[TT];                  // final ground-cluster population
-  double S[TT][3];               // handler terms of the current grid point (A, B, eta)
-  double part[kGW][4][TT];       // X-term partial sums
-  double rho[kGW][kMaxJ];        // |diag(z) psi| of the omega = 0 jumps of one trajectory-step
+  double S[TT][6];               // handler terms of the current grid point: (A, B, eta) per adjoint
+  double part[kGW][8][TT];       // X-term partial sums [direction][point][adjoint]
+  double rho[TT][kMaxJ];         // |diag(z) psi| of the omega = 0 jumps of one trajectory-step
 };
 
 // Records of trajectory j's step g (record step g - 1) start at m0; returns the end.
@@ -377,23 +385,27 @@ __global__ __launch_bounds__(kGThreads) void k_grad(GradArgs a) {
   auto active = [&](int t) { return traj(t) < a.K; };
   auto recs = [&](int t) { return a.jumps + traj(t) * a.cap; };
   auto count = [&](int t) { return a.jcount[traj(t)]; };
+  // roles of the four LDS tiles (workgroup-uniform): post-kick state, end-of-step state,
+  // adjoint of the projector, adjoint of the identity
+  int iA = 0, iB = 1, iL = 2, iM = 3;
 
-  auto kick = [&](int g) {   // PA = O_g PB (g >= 2) or the initial state (g = 1)
+  auto kick = [&](int g) {   // A = O_g B (g >= 2) or the initial state (g = 1)
+    T* PA = sh.buf[iA];
     if (g == 1) {
       for (int f = tid; f < NP * NC; f += kGThreads) {
         const int x = f / NC, col = f % NC;
-        sh.PA[x * LD + col] = (!(col & 1) && active(col >> 1)) ? static_cast<T>(a.cinit[x]) : static_cast<T>(0);
+        PA[x * LD + col] = (!(col & 1) && active(col >> 1)) ? static_cast<T>(a.cinit[x]) : static_cast<T>(0);
       }
     } else {
-      gemm_kick<NP, NC, LD, T>(static_cast<const T*>(a.pD) + static_cast<size_t>(g) * NP * NP, sh.PB, sh.PA);
+      gemm_kick<NP, NC, LD, T>(static_cast<const T*>(a.pD) + static_cast<size_t>(g) * NP * NP, sh.buf[iB], PA);
     }
   };
-  auto forward = [&](int g) {   // PB = step g (PA); advances the cursors
+  auto forward = [&](int g) {   // B = step g (A); advances the cursors
     for (int t = wave; t < TT; t += kGW) {
       if (!active(t)) continue;
       const int m0 = sh.cur[t];
       const int m1 = step_end(recs(t), count(t), m0, g);
-      replay_step<NP, LD, T>(a, g, recs(t), m0, m1, sh.PA, sh.PB, t, nullptr);
+      replay_step<NP, LD, T>(a, g, recs(t), m0, m1, sh.buf[iA], sh.buf[iB], t, nullptr);
       if (lane == 0) sh.cur[t] = m1;
     }
   };
@@ -401,9 +413,9 @@ __global__ __launch_bounds__(kGThreads) void k_grad(GradArgs a) {
   // ---- forward replay with checkpoints (not needed when one segment spans the anneal)
   for (int t = tid; t < TT; t += kGThreads) sh.cur[t] = 0;
   for (int f = tid; f < NP * LD; f += kGThreads) {
-    sh.PB[f] = static_cast<T>(0);
-    sh.LB[f] = static_cast<T>(0);
-    sh.LA[f] = static_cast<T>(0);
+    sh.buf[iB][f] = static_cast<T>(0);
+    sh.buf[iL][f] = static_cast<T>(0);
+    sh.buf[iM][f] = static_cast<T>(0);
   }
   __syncthreads();
   for (int g = 1; a.S > 1 && g < a.M; ++g) {
@@ -413,7 +425,7 @@ __global__ __launch_bounds__(kGThreads) void k_grad(GradArgs a) {
     __syncthreads();
     if (g % a.C == 0 && g < a.M - 1) {
       const int s = g / a.C;
-      tile_store<NP, NC, LD, T>(sh.PB, ck + static_cast<size_t>(s) * NP * NC);
+      tile_store<NP, NC, LD, T>(sh.buf[iB], ck + static_cast<size_t>(s) * NP * NC);
       for (int t = tid; t < TT; t += kGThreads) ckc[s * TT + t] = sh.cur[t];
       __syncthreads();
     }
@@ -422,116 +434,144 @@ __global__ __launch_bounds__(kGThreads) void k_grad(GradArgs a) {
   // ---- backward, one segment at a time (last first)
   for (int s = a.S - 1; s >= 0; --s) {
     const int glo = s * a.C + 1, ghi = std::min((s + 1) * a.C, a.M - 1);
-    if (s > 0) tile_load<NP, NC, LD, T>(ck + static_cast<size_t>(s) * NP * NC, sh.PB);
+    if (s > 0) tile_load<NP, NC, LD, T>(ck + static_cast<size_t>(s) * NP * NC, sh.buf[iB]);
     for (int t = tid; t < TT; t += kGThreads) sh.cur[t] = (s > 0) ? ckc[s * TT + t] : 0;
     __syncthreads();
     for (int g = glo; g <= ghi; ++g) {
       kick(g);
       for (int t = tid; t < TT; t += kGThreads) scur[(g - glo) * TT + t] = sh.cur[t];
       __syncthreads();
-      tile_store<NP, NC, LD, T>(sh.PA, sg + static_cast<size_t>(g - glo) * NP * NC);
+      tile_store<NP, NC, LD, T>(sh.buf[iA], sg + static_cast<size_t>(g - glo) * NP * NC);
       if (g < ghi) forward(g);
       __syncthreads();
     }
     for (int g = ghi; g >= glo; --g) {
-      tile_load<NP, NC, LD, T>(sg + static_cast<size_t>(g - glo) * NP * NC, sh.PA);
-      for (int f = tid; f < kGW * 4 * TT; f += kGThreads) (&sh.part[0][0][0])[f] = 0.0;
+      T* PA = sh.buf[iA];
+      T* PB = sh.buf[iB];
+      T* LP = sh.buf[iL];
+      T* LI = sh.buf[iM];
+      tile_load<NP, NC, LD, T>(sg + static_cast<size_t>(g - glo) * NP * NC, PA);
+      for (int f = tid; f < kGW * 8 * TT; f += kGThreads) (&sh.part[0][0][0])[f] = 0.0;
       __syncthreads();
+      // end-of-step state (and the adjoints' final condition at the last grid point)
       for (int t = wave; t < TT; t += kGW) {
-        if (!active(t)) {
-          if (lane < 3) sh.S[t][lane] = 0.0;
-          continue;
-        }
+        if (!active(t)) continue;
         const aqt_jump* rec = recs(t);
         const int m0 = scur[(g - glo) * TT + t];
         const int m1 = step_end(rec, count(t), m0, g);
         if (m1 - m0 > kMaxJ && lane == 0) a.status[0] = 1;
-        replay_step<NP, LD, T>(a, g, rec, m0, m1, sh.PA, sh.PB, t, sh.rho[wave]);
-        double f;
+        replay_step<NP, LD, T>(a, g, rec, m0, m1, PA, PB, t, sh.rho[t]);
         if (g == a.M - 1) {
-          // lambda = Pi psi / |psi|^2 with Pi the ground cluster of the last grid point
+          // lambda = Pi psi / |psi|^2 (Pi: ground cluster of the last grid point) and psi / |psi|^2
           const int gsz = a.proj;
           double nn = 0.0, pg = 0.0;
           for (int x = lane; x < NP; x += 64) {
-            const double br = static_cast<double>(sh.PB[x * LD + 2 * t]), bi = static_cast<double>(sh.PB[x * LD + 2 * t + 1]);
+            const double br = static_cast<double>(PB[x * LD + 2 * t]), bi = static_cast<double>(PB[x * LD + 2 * t + 1]);
             nn += br * br + bi * bi;
             if (x < gsz) pg += br * br + bi * bi;
           }
           nn = wave_sum(nn);
           pg = wave_sum(pg);
           for (int x = lane; x < NP; x += 64) {
+            const double br = static_cast<double>(PB[x * LD + 2 * t]), bi = static_cast<double>(PB[x * LD + 2 * t + 1]);
             const double w = (x < gsz) ? 1.0 / nn : 0.0;
-            sh.LB[x * LD + 2 * t] = static_cast<T>(w * static_cast<double>(sh.PB[x * LD + 2 * t]));
-            sh.LB[x * LD + 2 * t + 1] = static_cast<T>(w * static_cast<double>(sh.PB[x * LD + 2 * t + 1]));
+            LP[x * LD + 2 * t] = static_cast<T>(w * br);
+            LP[x * LD + 2 * t + 1] = static_cast<T>(w * bi);
+            LI[x * LD + 2 * t] = static_cast<T>(br / nn);
+            LI[x * LD + 2 * t + 1] = static_cast<T>(bi / nn);
           }
-          f = pg / nn;
-          sh.f[t] = f;
-        } else {
-          f = sh.f[t];
-        }
-        double S[3] = {0.0, 0.0, 0.0};
-        adjoint_step<NP, LD, T>(a, g, rec, m0, m1, sh.PA, sh.PB, sh.LB, sh.LA, t, f, sh.rho[wave], S);
-        if (g == 1) {
-          // grid 0 through the initial state: 2 Re <lambda_A | dcin>
-          double c0 = 0.0, c1 = 0.0;
-          for (int x = lane; x < NP; x += 64) {
-            const double lr = static_cast<double>(sh.LA[x * LD + 2 * t]);
-            c0 += lr * a.dcin[x];
-            c1 += lr * a.dcin[NP + x];
-          }
-          c0 = wave_sum(c0);
-          c1 = wave_sum(c1);
-          if (lane == 0) {
-            double* o = a.out + traj(t) * a.ostride;
-            o[1] += 2.0 * c0;            // grid 0: s = 0, weight 1 on control 0
-            o[1 + a.nctrl] += 2.0 * c1;
-          }
-        }
-        if (lane == 0) {
-          sh.S[t][0] = S[0];
-          sh.S[t][1] = S[1];
-          sh.S[t][2] = S[2];
+          if (lane == 0) sh.f[t] = pg / nn;
         }
       }
       __syncthreads();
-      // basis-change terms of grid g
+      // basis-change terms at the end of the step (the point before O_{g+1})
+      if (g < a.M - 1)
+        for (int dir = 0; dir < 2; ++dir) {
+          const T* X = static_cast<const T*>(a.pX) + (static_cast<size_t>(g) * 2 + dir) * NP * NP;
+          gemm_dot2<NP, NC, LD, T>(X, PB, LP, LI, &sh.part[wave][dir * 4 + 2][0], &sh.part[wave][dir * 4 + 3][0]);
+        }
+      __syncthreads();
+      // backward through the step, both adjoints in place
+      for (int t = wave; t < TT; t += kGW) {
+        if (!active(t)) {
+          if (lane < 6) sh.S[t][lane] = 0.0;
+          continue;
+        }
+        const aqt_jump* rec = recs(t);
+        const int m0 = scur[(g - glo) * TT + t];
+        const int m1 = step_end(rec, count(t), m0, g);
+        double S1[3] = {0.0, 0.0, 0.0}, S2[3] = {0.0, 0.0, 0.0};
+        adjoint_step<NP, LD, T>(a, g, rec, m0, m1, PA, PB, LP, LP, t, sh.f[t], sh.rho[t], S1);
+        adjoint_step<NP, LD, T>(a, g, rec, m0, m1, PA, PB, LI, LI, t, 1.0, sh.rho[t], S2);
+        if (g == 1) {
+          // grid 0 through the initial state: 2 Re <lambda_A | dcin>
+          double c[4] = {0.0, 0.0, 0.0, 0.0};
+          for (int x = lane; x < NP; x += 64) {
+            const double l1 = static_cast<double>(LP[x * LD + 2 * t]), l2 = static_cast<double>(LI[x * LD + 2 * t]);
+            c[0] += l1 * a.dcin[x];
+            c[1] += l1 * a.dcin[NP + x];
+            c[2] += l2 * a.dcin[x];
+            c[3] += l2 * a.dcin[NP + x];
+          }
+          for (int q = 0; q < 4; ++q) c[q] = wave_sum(c[q]);
+          if (lane == 0) {
+            double* o = a.out + traj(t) * a.ostride;
+            o[1] += 2.0 * c[0];            // grid 0: s = 0, weight 1 on control 0
+            o[1 + a.nctrl] += 2.0 * c[1];
+            o[P + 2] += 2.0 * c[2];
+            o[P + 2 + a.nctrl] += 2.0 * c[3];
+          }
+        }
+        if (lane == 0)
+          for (int q = 0; q < 3; ++q) {
+            sh.S[t][q] = S1[q];
+            sh.S[t][3 + q] = S2[q];
+          }
+      }
+      __syncthreads();
+      // basis-change terms just after O_g
       for (int dir = 0; dir < 2; ++dir) {
         const T* X = static_cast<const T*>(a.pX) + (static_cast<size_t>(g) * 2 + dir) * NP * NP;
-        if (g < a.M - 1) {
-          const T* const B2[2] = {sh.PA, sh.PB};
-          const T* const L2[2] = {sh.LA, sh.LB};
-          gemm_dot<NP, NC, LD, T, 2>(X, B2, L2, &sh.part[wave][2 * dir][0], TT);
-        } else {
-          const T* const B1[1] = {sh.PA};
-          const T* const L1[1] = {sh.LA};
-          gemm_dot<NP, NC, LD, T, 1>(X, B1, L1, &sh.part[wave][2 * dir][0], TT);
-        }
+        gemm_dot2<NP, NC, LD, T>(X, PA, LP, LI, &sh.part[wave][dir * 4 + 0][0], &sh.part[wave][dir * 4 + 1][0]);
       }
       __syncthreads();
       for (int t = tid; t < TT; t += kGThreads) {
         if (!active(t)) continue;
-        double xa[2];
-        for (int dir = 0; dir < 2; ++dir) {
-          double pa = 0.0, pb = 0.0;
-          for (int w = 0; w < kGW; ++w) {
-            pa += sh.part[w][2 * dir][t];
-            pb += sh.part[w][2 * dir + 1][t];
-          }
-          xa[dir] = sh.S[t][dir] + 2.0 * (pb - pa);
-        }
         const double u = static_cast<double>(g) / (a.M - 1) * (a.nctrl - 1);
         const int j = std::min(static_cast<int>(floor(u)), a.nctrl - 2);
         const double fr = u - j;
-        double* o = a.out + traj(t) * a.ostride;
-        o[1 + j] += (1.0 - fr) * xa[0];
-        o[2 + j] += fr * xa[0];
-        o[1 + a.nctrl + j] += (1.0 - fr) * xa[1];
-        o[2 + a.nctrl + j] += fr * xa[1];
-        o[P] += sh.S[t][2];
-        if (g == a.M - 1) o[0] = sh.f[t];
+        for (int adj = 0; adj < 2; ++adj) {
+          double xa[2];
+          for (int dir = 0; dir < 2; ++dir) {
+            double pa = 0.0, pb = 0.0;
+            for (int w = 0; w < kGW; ++w) {
+              pa += sh.part[w][dir * 4 + adj][t];
+              pb += sh.part[w][dir * 4 + 2 + adj][t];
+            }
+            xa[dir] = sh.S[t][3 * adj + dir] + 2.0 * (pb - pa);
+          }
+          double* o = a.out + traj(t) * a.ostride + adj * (P + 1);
+          o[1 + j] += (1.0 - fr) * xa[0];
+          o[2 + j] += fr * xa[0];
+          o[1 + a.nctrl + j] += (1.0 - fr) * xa[1];
+          o[2 + a.nctrl + j] += fr * xa[1];
+          o[P] += sh.S[t][3 * adj + 2];
+          if (g == a.M - 1) o[0] = adj ? 1.0 : sh.f[t];
+        }
       }
-      // adjoint before the kick: lambda_B(g - 1) = O_g^T lambda_A(g)
-      if (g >= 2) gemm_kick<NP, NC, LD, T>(static_cast<const T*>(a.pDT) + static_cast<size_t>(g) * NP * NP, sh.LA, sh.LB);
+      // adjoints before the kick, lambda_B(g - 1) = O_g^T lambda_A(g), into the two state
+      // tiles of this step; the tiles then swap roles
+      if (g >= 2) {
+        const T* DT = static_cast<const T*>(a.pDT) + static_cast<size_t>(g) * NP * NP;
+        gemm_kick<NP, NC, LD, T>(DT, LP, PB);
+        gemm_kick<NP, NC, LD, T>(DT, LI, PA);
+        int tmp = iL;
+        iL = iB;
+        iB = tmp;
+        tmp = iM;
+        iM = iA;
+        iA = tmp;
+      }
       __syncthreads();
     }
   }
@@ -725,9 +765,9 @@ aqt_status launch_grad(aqt_ctx* ctx, const aqt_run_params* p, double* value, dou
   ga.pX = ctx->gpk_X.p;
   aqt_status s = AQT_OK;
 #define AQT_SWEEP(np, tt, T) s = launch_sweep<np, tt, T>(ctx, ga, (K + (tt) - 1) / (tt), cus, p->segment)
-  for (int pass = 0; pass < 2; ++pass) {
-    ga.out = out + pass * (P + 1);
-    ga.proj = pass ? ctx->n : gs_last;
+  {
+    ga.out = out;
+    ga.proj = gs_last;
     switch (NP) {
       case 16: if (f64) AQT_SWEEP(16, 16, double); else AQT_SWEEP(16, 16, float); break;
       case 32: if (f64) AQT_SWEEP(32, 16, double); else AQT_SWEEP(32, 16, float); break;
@@ -741,7 +781,7 @@ aqt_status launch_grad(aqt_ctx* ctx, const aqt_run_params* p, double* value, dou
 #undef AQT_SWEEP
   int hstat = 0;
   AQT_HIP(ctx, hipMemcpy(&hstat, status.p, 4, hipMemcpyDeviceToHost));
-  if (hstat) return ctx->fail(AQT_ECAPACITY, "more than 64 omega = 0 jumps of one trajectory within one step");
+  if (hstat) return ctx->fail(AQT_ECAPACITY, "more than 32 omega = 0 jumps of one trajectory within one step");
 
   hipLaunchKernelGGL(k_colstats, dim3(P + 1), dim3(256), 0, st, out, K, P + 1, stats.as<double>());
   AQT_HIP(ctx, hipGetLastError());
