@@ -1,7 +1,7 @@
 """Throughput of the GPU trajectory engine.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload a2a8|ring4|gadget16|batched|grad|fixed]
-                    [--lamb-shift]
+                    [--lamb-shift] [--bath-corr RHO]
                     [--cpu-traj 3072] [--cpu-grid 500] [--no-cpu]
 
 One bench step = one aqt_run: all trajectories of the workload through the whole
@@ -30,6 +30,7 @@ Workloads:
             sub-steps per grid step), FP32; value = grid trajectory-steps/s, with the
             waiting-time run timed beside it
 --lamb-shift adds the Ohmic Lamb shift to the tables (a2a8, ring4, fixed)
+--bath-corr RHO correlates the qubits' baths, C_ab = RHO^|a - b| (a2a8, ring4)
 """
 import argparse
 import json
@@ -54,6 +55,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="a2a8", choices=("a2a8", "ring4", "gadget16", "batched", "grad", "fixed"))
     ap.add_argument("--lamb-shift", action="store_true")
+    ap.add_argument("--bath-corr", type=float, default=None)
     ap.add_argument("--substeps", type=int, default=4)
     ap.add_argument("--n-traj", type=int, default=0, help="override the workload's trajectory count")
     ap.add_argument("--cpu-traj", type=int, default=3072)
@@ -386,8 +388,12 @@ def main():
 
     wl = workload(args.workload, args.n_traj)
     inst = wl["inst"].with_(lamb_shift=args.lamb_shift)
-    if args.lamb_shift:
-        wl["golden"] = None   # the stored AME references have no Lamb shift
+    if args.bath_corr is not None:
+        import numpy as np
+        q = inst.n_qubits
+        inst = inst.with_(bath_corr=np.array([[args.bath_corr ** abs(a - b) for b in range(q)] for a in range(q)]))
+    if args.lamb_shift or args.bath_corr is not None:
+        wl["golden"] = None   # the stored AME references are for independent baths without the Lamb shift
     K = inst.n_traj
     M = inst.n_grid
     n = inst.levels
@@ -434,7 +440,9 @@ def main():
         "metric": METRIC, "value": head["value"], "unit": "trajectory-steps/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": head["ms"], "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": head_prec, "data": "synthetic",
-        "config": {"workload": wl["text"] + (", Lamb shift" if args.lamb_shift else ""), "name": inst.name,
+        "config": {"workload": wl["text"] + (", Lamb shift" if args.lamb_shift else "")
+                   + (f", bath correlation {args.bath_corr}^|a-b|" if args.bath_corr is not None else ""),
+                   "name": inst.name,
                    "n_traj": K, "n_levels": n, "n_grid": M, "precision": head_prec, "seed": inst.seed},
         "error_vs_fp64_ame": {"P_GS_final_ame": p_ame,
                               **{p: {"P_GS_final": v["pgs_final"], "stderr": v["pgs_se"],
