@@ -73,8 +73,6 @@ struct GradArgs {
   const double* zdiag;   // [M][nq][NP]
   const double* dre;     // [M][NP] Re exp(-i e dt - Gamma dt / 2)
   const double* dim;
-  const int* gs;         // [M]
-  const double* Xd;      // [M][2][NP][NP]
   const double* dE;      // [M][2][NP]
   const double* dGam;    // [M][2][NP]
   const double* dzd;     // [M][2][nq][NP]
@@ -714,8 +712,6 @@ aqt_status launch_grad(aqt_ctx* ctx, const aqt_run_params* p, double* value, dou
   ga.zdiag = ctx->zdiag.as<double>();
   ga.dre = ctx->dre.as<double>();
   ga.dim = ctx->dim.as<double>();
-  ga.gs = ctx->gs.as<int>();
-  ga.Xd = ctx->Xd.as<double>();
   ga.dE = ctx->dE.as<double>();
   ga.dGam = ctx->dGam.as<double>();
   ga.dzd = ctx->dzd.as<double>();
