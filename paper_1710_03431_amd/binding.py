@@ -347,6 +347,45 @@ def _outputs(outs):
                    final_state=ptr("final_state"))
 
 
+def _pgs_function():
+    """torch.autograd.Function for E[P_GS(1)] of an Engine's instance (built lazily so that
+    importing this module does not import torch)."""
+    import torch
+
+    class PGS(torch.autograd.Function):
+        """value = E[P_GS(1)] estimated from n_traj trajectories; backward multiplies the
+        gradient that aqt_grad_pgs returns with the same forward call (controls of A, of B,
+        eta; CPU float64 tensors).  The engine's Hamiltonian and bath constants other than
+        eta are used as set; the schedule and eta are taken from the inputs."""
+
+        @staticmethod
+        def forward(ctx, A_ctrl, B_ctrl, eta, engine, t_f, omega_c, T, n_grid, n_levels, n_traj, precision, seed):
+            engine.set_schedule(t_f, A_ctrl.detach().cpu().numpy(), B_ctrl.detach().cpu().numpy())
+            engine.set_bath(float(eta), omega_c, T)
+            engine.precompute(n_grid, n_levels)
+            out = engine.grad_pgs(n_traj, precision, seed=seed)
+            m = A_ctrl.numel()
+            g = torch.as_tensor(out["grad"], dtype=torch.float64)
+            ctx.save_for_backward(g[:m].clone(), g[m:2 * m].clone(), g[2 * m:].clone())
+            ctx.value_se = out["value_se"]
+            return torch.tensor(out["value"], dtype=torch.float64)
+
+        @staticmethod
+        def backward(ctx, grad_out):
+            gA, gB, ge = ctx.saved_tensors
+            return (grad_out * gA, grad_out * gB, (grad_out * ge).reshape(()), None, None, None, None, None, None,
+                    None, None, None)
+
+    return PGS
+
+
+def pgs(engine, A_ctrl, B_ctrl, eta, *, t_f, omega_c, T, n_grid, n_levels, n_traj, precision="fp32", seed=0):
+    """Differentiable E[P_GS(1)] (see _pgs_function): A_ctrl, B_ctrl and eta are CPU float64
+    tensors (eta 0-dimensional); gradients flow to them through aqt_grad_pgs."""
+    return _pgs_function().apply(A_ctrl, B_ctrl, eta, engine, t_f, omega_c, T, n_grid, n_levels, n_traj,
+                                 precision, seed)
+
+
 class Batch:
     """Many instances (Engines with tables) run by one persistent launch (aqt_batch_*).
 

@@ -160,3 +160,23 @@ def test_checkpoint_segments_do_not_change_results(segment):
                      segment=segment)
     d = eng.grad_pgs(K, "fp32", seed=inst.seed, instance_id=inst.instance_id, per_trajectory=True)
     np.testing.assert_array_equal(c["per_traj"], d["per_traj"])
+
+
+def test_autograd_function_matches_the_entry_point():
+    """The torch.autograd.Function wrapper returns aqt_grad_pgs's value and gradient."""
+    import torch
+    from paper_1710_03431_amd import binding
+    inst = _ring3()
+    A = torch.tensor(inst.A_ctrl, dtype=torch.float64, requires_grad=True)
+    B = torch.tensor(inst.B_ctrl, dtype=torch.float64, requires_grad=True)
+    eta = torch.tensor(inst.eta, dtype=torch.float64, requires_grad=True)
+    eng = _engine(inst)
+    v = binding.pgs(eng, A, B, eta, t_f=inst.t_f, omega_c=inst.omega_c, T=inst.T, n_grid=inst.n_grid,
+                    n_levels=inst.levels, n_traj=4000, precision="fp64", seed=inst.seed)
+    (3.0 * v).backward()
+    ref = _engine(inst).grad_pgs(4000, "fp64", seed=inst.seed)
+    assert abs(float(v) - ref["value"]) <= 1e-12
+    m = len(inst.A_ctrl)
+    np.testing.assert_allclose(A.grad.numpy(), 3.0 * ref["grad"][:m], rtol=1e-12, atol=1e-15)
+    np.testing.assert_allclose(B.grad.numpy(), 3.0 * ref["grad"][m:2 * m], rtol=1e-12, atol=1e-15)
+    np.testing.assert_allclose(float(eta.grad), 3.0 * ref["grad"][2 * m], rtol=1e-12)
