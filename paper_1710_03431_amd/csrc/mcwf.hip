@@ -137,8 +137,12 @@ __global__ __launch_bounds__(kGThreads) void k_fixed_step(FixArgs a) {
         cr[r] = (x < NP) ? static_cast<double>(PA[x * LD + 2 * t]) : 0.0;
         ci[r] = (x < NP) ? static_cast<double>(PA[x * LD + 2 * t + 1]) : 0.0;
       }
+      // the decision draws of up to 64 sub-steps at once, one Philox evaluation per lane
+      double eps_l = 0.0;
       for (int s = 0; s < a.S; ++s) {
         const uint64_t u = static_cast<uint64_t>(g - 1) * a.S + s;
+        if ((s & 63) == 0 && lane < a.S - s) eps_l = draw_uniform(a.seed, a.iid, tj, 3 * (u + lane));
+        const double eps = __shfl(eps_l, s & 63, 64);
         double nn = 0.0, rate = 0.0;
 #pragma unroll
         for (int r = 0; r < NR; ++r) {
@@ -149,7 +153,6 @@ __global__ __launch_bounds__(kGThreads) void k_fixed_step(FixArgs a) {
         nn = wave_sum(nn);
         rate = wave_sum(rate);
         const double dp = h * rate / nn;
-        const double eps = draw_uniform(a.seed, a.iid, tj, 3 * u);
         if (!(eps < dp)) {
           double n2 = 0.0;
 #pragma unroll
