@@ -296,9 +296,10 @@ def bench_grad(args):
               f"ratio {ms / fwd_ms:.2f}; P_GS(1)={res['P_GS_final']:.5f}", file=sys.stderr, flush=True)
     head_prec = "fp32" if "fp32" in results else next(iter(results))
     head = results[head_prec]
-    # per trajectory-step: the replay kick, X_g products at both points for both directions (4, shared
-    # by the two adjoints) and the two adjoint kicks, each 4 n^2 flop; plus the forward run
-    per_unit = 7 * 4 * n * n + FLOP_PER_TRAJ_STEP(n)
+    # per trajectory-step: the replay kick, X_g products at both points (2; one product serves both
+    # schedule directions and both adjoints) and the two adjoint kicks, each 4 n^2 flop; plus the
+    # forward run
+    per_unit = 5 * 4 * n * n + FLOP_PER_TRAJ_STEP(n)
     flops = per_unit * K * (M - 1)
     achieved = flops / (head["ms"] / 1e3)
     cpu = None if args.no_cpu else cpu_grad_baseline(inst, 16, 2)

@@ -57,10 +57,12 @@ struct aqt_ctx {
   aqt::DevBuf dzd;      // [M][2][nq][NP] d z_i[x][x]
   aqt::DevBuf dll;      // [M][2][nq][NP(b)][NP(a)] d log |l_i,ab|
   aqt::DevBuf dcin;     // [2][NP] derivative of the initial state through grid 0
+  std::vector<double> sched_A, sched_B;   // [M] A(s_g), B(s_g) of the last aqt_precompute
   int fix_prec = -1;    // precision of the fixed-step kernel's O_g - I copy, -1 = none
   aqt::DevBuf fix_D;
   int gpk_prec = -1;    // precision of the sweep operands below, -1 = none
   aqt::DevBuf gpk_D, gpk_DT, gpk_X;   // O_g - I, its transpose, X_g in that precision
+  aqt::DevBuf gpk_xc;   // [M][3] X^A_g = xc[0] X_g, X^B_g = xc[1] X_g, xc[2] = direction held in X_g
 
   // ---- per-precision packed operands of the step kernel (built lazily)
   int packed_for = -1;      // aqt_precision the packs below hold, -1 = none

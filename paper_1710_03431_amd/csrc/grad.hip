@@ -24,7 +24,10 @@
 //     theory; X antisymmetric), grid g collects -2 Re <lambda_A|X_g|psi_A> (just after
 //     O_g) and +2 Re <lambda_B|X_g|psi_B> (just before O_{g+1}); grid 0 acts through
 //     the initial state, 2 Re <lambda_A|V_1 dv_0> at step 1.  These are MFMA products
-//     X_g [psi_A psi_B] contracted with the adjoints.
+//     X_g [psi_A psi_B] contracted with the adjoints.  H(s_g) = A(s_g) H_X + B(s_g) H_Z is
+//     diagonal in its own eigenbasis, so the off-diagonal parts of V^T H_X V and V^T H_Z V
+//     are proportional (A <.>_X + B <.>_Z = 0 off the diagonal), and so are X^A_g and X^B_g:
+//     one product per point serves both directions, scaled per grid point.
 //   no-jump propagation exp(-i e tau - Gamma tau / 2) (diagonal): per component
 //     P_x = conj(lambda_x) psi_x is constant between a != b jumps; a step without one
 //     gives 2 dt sum de_x Im P_x - dt sum dGamma_x Re P_x.
@@ -66,7 +69,8 @@ constexpr int kMaxJ = 32;           // omega = 0 jumps of one trajectory within 
 struct GradArgs {
   const void* pD;        // [M][NP][NP] O_g - I in the state precision
   const void* pDT;       // [M][NP][NP] its transpose
-  const void* pX;        // [M][2][NP][NP] X_g in the state precision
+  const void* pX;        // [M][NP][NP] X_g in the state precision (X^A_g = xc[0] X_g, X^B_g = xc[1] X_g)
+  const double* xc;      // [M][3]
   const double* cinit;   // [NP]
   const double* E;       // [M][NP]
   const double* Gam;     // [M][NP]
@@ -143,7 +147,7 @@ struct GradShared {
   int cur[TT];                   // running record cursor
   double f[TT];                  // final ground-cluster population
   double S[TT][6];               // handler terms of the current grid point: (A, B, eta) per adjoint
-  double part[kGW][8][TT];       // X-term partial sums [direction][point][adjoint]
+  double part[kGW][4][TT];       // X-term partial sums [point][adjoint]
   double rho[TT][kMaxJ];         // |diag(z) psi| of the omega = 0 jumps of one trajectory-step
 };
 
@@ -449,7 +453,7 @@ __global__ __launch_bounds__(kGThreads) void k_grad(GradArgs a) {
       T* LP = sh.buf[iL];
       T* LI = sh.buf[iM];
       tile_load<NP, NC, LD, T>(sg + static_cast<size_t>(g - glo) * NP * NC, PA);
-      for (int f = tid; f < kGW * 8 * TT; f += kGThreads) (&sh.part[0][0][0])[f] = 0.0;
+      for (int f = tid; f < kGW * 4 * TT; f += kGThreads) (&sh.part[0][0][0])[f] = 0.0;
       __syncthreads();
       // end-of-step state (and the adjoints' final condition at the last grid point)
       for (int t = wave; t < TT; t += kGW) {
@@ -484,10 +488,8 @@ __global__ __launch_bounds__(kGThreads) void k_grad(GradArgs a) {
       __syncthreads();
       // basis-change terms at the end of the step (the point before O_{g+1})
       if (g < a.M - 1)
-        for (int dir = 0; dir < 2; ++dir) {
-          const T* X = static_cast<const T*>(a.pX) + (static_cast<size_t>(g) * 2 + dir) * NP * NP;
-          gemm_dot2<NP, NC, LD, T>(X, PB, LP, LI, &sh.part[wave][dir * 4 + 2][0], &sh.part[wave][dir * 4 + 3][0]);
-        }
+        gemm_dot2<NP, NC, LD, T>(static_cast<const T*>(a.pX) + static_cast<size_t>(g) * NP * NP, PB, LP, LI,
+                                 &sh.part[wave][2][0], &sh.part[wave][3][0]);
       __syncthreads();
       // backward through the step, both adjoints in place
       for (int t = wave; t < TT; t += kGW) {
@@ -528,10 +530,8 @@ __global__ __launch_bounds__(kGThreads) void k_grad(GradArgs a) {
       }
       __syncthreads();
       // basis-change terms just after O_g
-      for (int dir = 0; dir < 2; ++dir) {
-        const T* X = static_cast<const T*>(a.pX) + (static_cast<size_t>(g) * 2 + dir) * NP * NP;
-        gemm_dot2<NP, NC, LD, T>(X, PA, LP, LI, &sh.part[wave][dir * 4 + 0][0], &sh.part[wave][dir * 4 + 1][0]);
-      }
+      gemm_dot2<NP, NC, LD, T>(static_cast<const T*>(a.pX) + static_cast<size_t>(g) * NP * NP, PA, LP, LI,
+                               &sh.part[wave][0][0], &sh.part[wave][1][0]);
       __syncthreads();
       for (int t = tid; t < TT; t += kGThreads) {
         if (!active(t)) continue;
@@ -539,15 +539,13 @@ __global__ __launch_bounds__(kGThreads) void k_grad(GradArgs a) {
         const int j = std::min(static_cast<int>(floor(u)), a.nctrl - 2);
         const double fr = u - j;
         for (int adj = 0; adj < 2; ++adj) {
-          double xa[2];
-          for (int dir = 0; dir < 2; ++dir) {
-            double pa = 0.0, pb = 0.0;
-            for (int w = 0; w < kGW; ++w) {
-              pa += sh.part[w][dir * 4 + adj][t];
-              pb += sh.part[w][dir * 4 + 2 + adj][t];
-            }
-            xa[dir] = sh.S[t][3 * adj + dir] + 2.0 * (pb - pa);
+          double pa = 0.0, pb = 0.0;
+          for (int w = 0; w < kGW; ++w) {
+            pa += sh.part[w][adj][t];
+            pb += sh.part[w][2 + adj][t];
           }
+          double xa[2];
+          for (int dir = 0; dir < 2; ++dir) xa[dir] = sh.S[t][3 * adj + dir] + 2.0 * a.xc[3 * g + dir] * (pb - pa);
           double* o = a.out + traj(t) * a.ostride + adj * (P + 1);
           o[1 + j] += (1.0 - fr) * xa[0];
           o[2 + j] += fr * xa[0];
@@ -598,10 +596,12 @@ __global__ __launch_bounds__(256) void k_colstats(const double* __restrict__ out
   if (tid < 5) stats[5 * c + tid] = r[tid][0] + r[tid][1] + r[tid][2] + r[tid][3];
 }
 
-// State-precision copies of O_g - I, its transpose and X_g for the sweep's products.
+// State-precision copies of O_g - I, its transpose and X_g (the direction xc[g][2] of the
+// FP64 tables) for the sweep's products.
 template <class T>
-__global__ void k_grad_pack(const double* __restrict__ dlt, const double* __restrict__ Xd, int M, int NP,
-                            T* __restrict__ D, T* __restrict__ DT, T* __restrict__ X) {
+__global__ void k_grad_pack(const double* __restrict__ dlt, const double* __restrict__ Xd,
+                            const double* __restrict__ xc, int M, int NP, T* __restrict__ D, T* __restrict__ DT,
+                            T* __restrict__ X) {
   const int64_t per = static_cast<int64_t>(NP) * NP;
   const int64_t tot = per * M;
   for (int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < tot;
@@ -610,8 +610,8 @@ __global__ void k_grad_pack(const double* __restrict__ dlt, const double* __rest
     const int a = static_cast<int>(r / NP), b = static_cast<int>(r - static_cast<int64_t>(a) * NP);
     D[i] = static_cast<T>(dlt[i]);
     DT[i] = static_cast<T>(dlt[g * per + static_cast<int64_t>(b) * NP + a]);
-    X[2 * g * per + r] = static_cast<T>(Xd[2 * g * per + r]);
-    X[(2 * g + 1) * per + r] = static_cast<T>(Xd[(2 * g + 1) * per + r]);
+    const int dir = (xc[3 * g + 2] != 0.0) ? 1 : 0;
+    X[i] = static_cast<T>(Xd[(2 * g + dir) * per + r]);
   }
 }
 
@@ -741,24 +741,45 @@ aqt_status launch_grad(aqt_ctx* ctx, const aqt_run_params* p, double* value, dou
       cus = prop.multiProcessorCount;
   }
   if (ctx->gpk_prec != p->precision) {
-    const size_t el = f64 ? 8 : 4, per = static_cast<size_t>(NP) * NP * ctx->M;
-    if (ctx->gpk_D.reserve(per * el) || ctx->gpk_DT.reserve(per * el) || ctx->gpk_X.reserve(2 * per * el))
+    const int M = ctx->M;
+    if (static_cast<int>(ctx->sched_A.size()) != M || static_cast<int>(ctx->sched_B.size()) != M)
+      return ctx->fail(AQT_ESTATE, "schedule samples missing; call aqt_precompute");
+    // A X^A + B X^B = 0 at every grid point: X_g holds X^B when |A| >= |B| (then
+    // X^A = -(B / A) X^B), else X^A; the other direction is a scaling of magnitude <= 1
+    std::vector<double> xc(3 * static_cast<size_t>(M));
+    for (int g = 0; g < M; ++g) {
+      const double A = ctx->sched_A[g], B = ctx->sched_B[g];
+      double* c = &xc[3 * static_cast<size_t>(g)];
+      if (A == 0.0 && B == 0.0) {
+        c[0] = 1.0, c[1] = 0.0, c[2] = 0.0;
+      } else if (std::fabs(A) >= std::fabs(B)) {
+        c[0] = -B / A, c[1] = 1.0, c[2] = 1.0;
+      } else {
+        c[0] = 1.0, c[1] = -A / B, c[2] = 0.0;
+      }
+    }
+    const size_t el = f64 ? 8 : 4, per = static_cast<size_t>(NP) * NP * M;
+    if (ctx->gpk_D.reserve(per * el) || ctx->gpk_DT.reserve(per * el) || ctx->gpk_X.reserve(per * el) ||
+        ctx->gpk_xc.reserve(xc.size() * 8))
       return ctx->fail(AQT_ENOMEM, "gradient operand allocation failed");
+    AQT_HIP(ctx, hipMemcpyAsync(ctx->gpk_xc.p, xc.data(), xc.size() * 8, hipMemcpyHostToDevice, st));
+    AQT_HIP(ctx, hipStreamSynchronize(st));
     const unsigned blocks = static_cast<unsigned>(std::min<size_t>(65536, (per + 255) / 256));
     if (f64)
       hipLaunchKernelGGL(k_grad_pack<double>, dim3(blocks), dim3(256), 0, st, ctx->dlt.as<double>(),
-                         ctx->Xd.as<double>(), ctx->M, NP, ctx->gpk_D.as<double>(), ctx->gpk_DT.as<double>(),
-                         ctx->gpk_X.as<double>());
+                         ctx->Xd.as<double>(), ctx->gpk_xc.as<double>(), M, NP, ctx->gpk_D.as<double>(),
+                         ctx->gpk_DT.as<double>(), ctx->gpk_X.as<double>());
     else
       hipLaunchKernelGGL(k_grad_pack<float>, dim3(blocks), dim3(256), 0, st, ctx->dlt.as<double>(),
-                         ctx->Xd.as<double>(), ctx->M, NP, ctx->gpk_D.as<float>(), ctx->gpk_DT.as<float>(),
-                         ctx->gpk_X.as<float>());
+                         ctx->Xd.as<double>(), ctx->gpk_xc.as<double>(), M, NP, ctx->gpk_D.as<float>(),
+                         ctx->gpk_DT.as<float>(), ctx->gpk_X.as<float>());
     AQT_HIP(ctx, hipGetLastError());
     ctx->gpk_prec = p->precision;
   }
   ga.pD = ctx->gpk_D.p;
   ga.pDT = ctx->gpk_DT.p;
   ga.pX = ctx->gpk_X.p;
+  ga.xc = ctx->gpk_xc.as<double>();
   aqt_status s = AQT_OK;
 #define AQT_SWEEP(np, tt, T) s = launch_sweep<np, tt, T>(ctx, ga, (K + (tt) - 1) / (tt), cus, p->segment)
   {

@@ -1238,6 +1238,8 @@ aqt_status precompute_tables(aqt_ctx* ctx, int M, int n, double tol, int method,
     Ag[g] = ctx->A_ctrl[j] * (1.0 - f) + ctx->A_ctrl[j + 1] * f;
     Bg[g] = ctx->B_ctrl[j] * (1.0 - f) + ctx->B_ctrl[j + 1] * f;
   }
+  ctx->sched_A = Ag;
+  ctx->sched_B = Bg;
   DevBuf dA, dB, dh, dJ, eZ;
   if (dA.reserve(M * 8) || dB.reserve(M * 8) || dh.reserve(nq * 8) || dJ.reserve(nq * nq * 8) || eZ.reserve(N * 8))
     return ctx->fail(AQT_ENOMEM, "precompute allocation failed");
