@@ -119,15 +119,16 @@ def lindblad_operators(T, inst, tol: float = 1e-9):
     """
     n = len(T.E)
     ops = []
+    wc = model.bath_channels(inst)[1]
     g0 = float(model.gamma_ohmic(0.0, inst.eta, inst.omega_c, inst.T))
-    for i in range(inst.n_qubits):
+    for i in range(len(T.z)):
         z = T.z[i]
         for a in range(n):
             for b in range(n):
                 if a == b:
                     continue
                 w = T.E[b] - T.E[a]
-                gam = float(model.gamma_ohmic(w, inst.eta, inst.omega_c, inst.T))
+                gam = float(model.gamma_ohmic(w, inst.eta, wc[i], inst.T))
                 L = np.zeros((n, n))
                 L[a, b] = z[a, b]
                 ops.append(np.sqrt(gam) * L)
@@ -139,9 +140,11 @@ def lamb_hamiltonian(T, inst) -> np.ndarray:
     """H_LS = sum_i sum_w S(w) A_i,w^dag A_i,w (eq. ME2-H) as a matrix, built from the
     unscaled operators of lindblad_operators' grouping (one per a != b pair, one omega = 0
     operator per qubit)."""
+    if getattr(inst, "bath_terms", None) is not None:
+        raise NotImplementedError("the Lamb shift is built for one bath spectral density")
     n = len(T.E)
     H = np.zeros((n, n))
-    for i in range(inst.n_qubits):
+    for i in range(len(T.z)):
         z = T.z[i]
         for a in range(n):
             for b in range(n):
@@ -156,23 +159,24 @@ def lamb_hamiltonian(T, inst) -> np.ndarray:
 
 
 def liouvillian_correlated(T, inst, zq) -> np.ndarray:
-    """Eq. ME2-L with gamma_ab(w) = C_ab gamma(w), written as the double sum over qubits
-    a, b of sum_w C_ab gamma(w) (L_b,w rho L_a,w^dag - {L_a,w^dag L_b,w, rho} / 2), with
+    """Eq. ME2-L with the bath model's gamma_ab(w) (model.gamma_matrix: C_ab gamma(w), or
+    a sum of such terms with their own cutoffs), written as the double sum over qubits
+    a, b of sum_w gamma_ab(w) (L_b,w rho L_a,w^dag - {L_a,w^dag L_b,w, rho} / 2), with
     the per-qubit operators of the Bohr-frequency grouping (one per a != b pair of
     levels, one omega = 0 operator) built from zq[q] = <a|sz_q|b>; no factorisation of
-    C.  Column-stacked superoperator (no Lamb shift)."""
+    gamma_ab(w).  Column-stacked superoperator (no Lamb shift)."""
     n = len(T.E)
     nq = inst.n_qubits
-    C = np.eye(nq) if getattr(inst, "bath_corr", None) is None else np.asarray(inst.bath_corr, dtype=np.float64)
     I = np.eye(n)
     H = np.diag(T.E).astype(np.complex128)
     Lsup = -1j * (np.kron(I, H) - np.kron(H.T, I))
 
-    def add(ops, gam):
+    def add(ops, w):
         nonlocal Lsup
+        G = model.gamma_matrix(inst, w)
         for qa in range(nq):
             for qb in range(nq):
-                c = C[qa, qb] * gam
+                c = G[qa, qb]
                 if c == 0.0:
                     continue
                 La, Lb = ops[qa], ops[qb]
@@ -188,8 +192,8 @@ def liouvillian_correlated(T, inst, zq) -> np.ndarray:
                 L = np.zeros((n, n))
                 L[a, b] = zq[q][a, b]
                 ops.append(L)
-            add(ops, float(model.gamma_ohmic(T.E[b] - T.E[a], inst.eta, inst.omega_c, inst.T)))
-    add([np.diag(np.diag(zq[q])) for q in range(nq)], float(model.gamma_ohmic(0.0, inst.eta, inst.omega_c, inst.T)))
+            add(ops, float(T.E[b] - T.E[a]))
+    add([np.diag(np.diag(zq[q])) for q in range(nq)], 0.0)
     return Lsup
 
 
@@ -214,7 +218,7 @@ def continuous(inst, s_eval, rtol=1e-10, atol=1e-12):
     nq, N = inst.n_qubits, inst.dim
     HX = model.hx_dense(nq)
     HZ = model.hz_dense(inst.h, inst.J)
-    SZ = [model.sz_diag(i, nq) for i in range(nq)]
+    SZ, WC = model.bath_channels(inst)                # channel operators and cutoffs
     g0 = float(model.gamma_ohmic(0.0, inst.eta, inst.omega_c, inst.T))
 
     def H_at(t):
@@ -227,10 +231,10 @@ def continuous(inst, s_eval, rtol=1e-10, atol=1e-12):
         rt = V.T @ rho @ V                      # eigenbasis
         d = -1j * (E[:, None] - E[None, :]) * rt
         omega = E[None, :] - E[:, None]
-        gam = model.gamma_ohmic(omega, inst.eta, inst.omega_c, inst.T)
-        np.fill_diagonal(gam, g0)
         p = np.real(np.diag(rt))
-        for i in range(nq):
+        for i in range(len(SZ)):
+            gam = model.gamma_ohmic(omega, inst.eta, WC[i], inst.T)
+            np.fill_diagonal(gam, g0)
             z = V.T @ (SZ[i][:, None] * V)
             R = gam * z * z                      # R[a, b]: rate b -> a (diag: g0 z_bb^2)
             zd = np.diag(z)

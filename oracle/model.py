@@ -134,15 +134,74 @@ def lamb_S_zero_temperature(omega, eta: float, omega_c: float):
     return eta * (-omega_c + w * np.exp(-w / omega_c) * ss.expi(w / omega_c))
 
 
-def channel_weights(inst) -> np.ndarray:
-    """Diagonal coupling operators of the jump channels, [n_channels, 2^n] (Sec. II eq. ME2-L
-    with gamma_ab(w) = C_ab gamma(w)).  Independent baths: sz_i of each qubit.  Correlated
-    baths: with C = L L^T (Cholesky; C positive definite) the double sum over qubits becomes
-    a sum over channels k with operators sum_a L[a, k] sz_a, each with rate gamma(w)."""
+def psd_factor(C, rel_tol: float = 1e-12) -> np.ndarray:
+    """F with C = F F^T for a symmetric positive semidefinite C: the Cholesky recursion
+    column by column in natural order, where a column whose pivot falls to
+    rel_tol * max(diag C) or below is dropped (its entries vanish for a semidefinite C),
+    so F has one column per direction of the range of C."""
+    C = np.asarray(C, dtype=np.float64)
+    q = C.shape[0]
+    tol = rel_tol * float(np.max(np.diag(C)))
+    L = np.zeros((q, q))
+    keep = []
+    for j in range(q):
+        d = C[j, j] - sum(L[j, k] ** 2 for k in keep)
+        if d <= tol:
+            continue
+        L[j, j] = math.sqrt(d)
+        for i in range(j + 1, q):
+            L[i, j] = (C[i, j] - sum(L[i, k] * L[j, k] for k in keep)) / L[j, j]
+        keep.append(j)
+    return L[:, keep]
+
+
+def bath_channels(inst):
+    """Jump channels of the bath model (Sec. II eq. ME2-L): diagonal coupling operators
+    [n_channels, 2^n] and the cutoff frequency of each channel's Ohmic rate.
+
+    Independent baths: sz_i of each qubit.  Correlated baths gamma_ab(w) = C_ab gamma(w):
+    with C = L L^T (Cholesky; C positive definite) the double sum over qubits becomes a sum
+    over channels k with operators sum_a L[a, k] sz_a, each with rate gamma(w).
+    Frequency-dependent correlations gamma_ab(w) = sum_m C_m[a, b] gamma(w; omega_c,m)
+    (the bath terms; each C_m positive semidefinite): the same construction per term with
+    C_m = F_m F_m^T (psd_factor), channels in term order, each term's columns with its own
+    cutoff.  In every case sum_k F[a, k] F[b, k] gamma_k(w) = gamma_ab(w), so the channels
+    give the dissipator of the double sum at every Bohr frequency; they stand in for the
+    frequency-dependent rotation u(w) that diagonalises gamma_ab(w)."""
     n = inst.n_qubits
     sz = np.stack([sz_diag(i, n) for i in range(n)])
+    terms = getattr(inst, "bath_terms", None)
     C = getattr(inst, "bath_corr", None)
+    if terms is not None:
+        if C is not None:
+            raise ValueError("give either a constant correlation or bath terms")
+        ws, wcs = [], []
+        for Cm, wc in terms:
+            F = psd_factor(Cm)
+            ws.append(F.T @ sz)
+            wcs += [float(wc)] * F.shape[1]
+        return np.concatenate(ws), np.array(wcs)
     if C is None:
-        return sz
+        return sz, np.full(n, float(inst.omega_c))
     L = np.linalg.cholesky(np.asarray(C, dtype=np.float64))
-    return L.T @ sz
+    return L.T @ sz, np.full(n, float(inst.omega_c))
+
+
+def channel_weights(inst) -> np.ndarray:
+    """The channels' diagonal coupling operators, [n_channels, 2^n] (bath_channels)."""
+    return bath_channels(inst)[0]
+
+
+def gamma_matrix(inst, omega: float) -> np.ndarray:
+    """gamma_ab(w) of the bath model as an n_qubits x n_qubits matrix, from its definition
+    (no factorisation): gamma(w) I, C gamma(w), or sum_m C_m gamma(w; omega_c,m)."""
+    n = inst.n_qubits
+    terms = getattr(inst, "bath_terms", None)
+    if terms is not None:
+        out = np.zeros((n, n))
+        for Cm, wc in terms:
+            out += np.asarray(Cm, dtype=np.float64) * float(gamma_ohmic(omega, inst.eta, float(wc), inst.T))
+        return out
+    C = getattr(inst, "bath_corr", None)
+    C = np.eye(n) if C is None else np.asarray(C, dtype=np.float64)
+    return C * float(gamma_ohmic(omega, inst.eta, inst.omega_c, inst.T))

@@ -163,20 +163,20 @@ def polar(M: np.ndarray, tau: float = 1e-4):
 
 
 def grid_tables(inst, E: np.ndarray, V: np.ndarray, dt: float):
-    nq = inst.n_qubits
     n = len(E)
-    w = model.channel_weights(inst)                      # [channel, x]
-    z = np.empty((nq, n, n))
-    for i in range(nq):
+    w, wc = model.bath_channels(inst)                    # [channel, x], [channel]
+    nch = len(w)
+    z = np.empty((nch, n, n))
+    for i in range(nch):
         z[i] = V.T @ (w[i][:, None] * V)
     omega = E[None, :] - E[:, None]                      # omega[a, b] = E_b - E_a
-    gam = model.gamma_ohmic(omega, inst.eta, inst.omega_c, inst.T)
-    np.fill_diagonal(gam, model.gamma_ohmic(0.0, inst.eta, inst.omega_c, inst.T))
-    R = np.empty((nq, n, n))
-    for i in range(nq):
+    R = np.empty((nch, n, n))
+    for i in range(nch):
+        gam = model.gamma_ohmic(omega, inst.eta, wc[i], inst.T)
+        np.fill_diagonal(gam, model.gamma_ohmic(0.0, inst.eta, wc[i], inst.T))
         R[i] = (gam * z[i] ** 2).T                        # R[i, b, a]
     Gamma = R.sum(axis=(0, 2))
-    zdiag = np.stack([np.diag(z[i]) for i in range(nq)])
+    zdiag = np.stack([np.diag(z[i]) for i in range(nch)])
     shift = lamb_shift(inst, E, z) if getattr(inst, "lamb_shift", False) else np.zeros(n)
     d = np.exp(-1j * (E + shift) * dt - 0.5 * Gamma * dt)
     return z, R, Gamma, zdiag, d, shift
@@ -187,6 +187,8 @@ def lamb_shift(inst, E: np.ndarray, z: np.ndarray) -> np.ndarray:
     eq. ME2-H; the operators of the Bohr-frequency reading): level b collects
     S(e_b - e_a) z_i[a,b]^2 from every a != b and S(0) z_i[b,b]^2 from the omega = 0
     operator of each qubit."""
+    if getattr(inst, "bath_terms", None) is not None:
+        raise NotImplementedError("the Lamb shift is built for one bath spectral density")
     n = len(E)
     cache = {}
 

@@ -588,6 +588,69 @@ def test_correlated_baths_split_step_equals_double_sum(rho):
             np.testing.assert_array_equal(T.R, B.R)
 
 
+def test_psd_factor_reproduces_semidefinite_matrices():
+    """C = F F^T for positive definite and rank-deficient C; a rank-r C gives r channels,
+    and a positive definite C gives the Cholesky factor."""
+    rng = np.random.default_rng(3)
+    X = rng.normal(size=(5, 5))
+    for C, r in ((X @ X.T + 0.1 * np.eye(5), 5), (0.7 * np.ones((5, 5)), 1), (X[:, :2] @ X[:, :2].T, 2)):
+        F = model.psd_factor(C)
+        assert F.shape == (5, r)
+        np.testing.assert_allclose(F @ F.T, C, atol=1e-12 * np.abs(C).max())
+    C = X @ X.T + 0.1 * np.eye(5)
+    np.testing.assert_allclose(model.psd_factor(C), np.linalg.cholesky(C), rtol=1e-12, atol=1e-14)
+
+
+@pytest.mark.parametrize("rho,xi", [(0.5, 0.5), (1.2, -0.3)])
+def test_frequency_dependent_bath_split_step_equals_double_sum(rho, xi):
+    """gamma_ab(w) = sum_m C_m[a, b] gamma(w; omega_c,m) with non-commuting C_m (local baths
+    correlated as xi^|a-b| plus a rank-one shared bath with a lower cutoff): gamma(w) has
+    w-dependent eigenvectors, and the split-step map built from the per-term channels
+    equals expm of eq. ME2-L written as the double sum over qubits with gamma_ab(w) taken
+    from its definition."""
+    terms = W.two_term_bath(3, rho=rho, xi=xi)
+    inst = W.ring_instance(3, 5, t_f=40.0, eta=3e-3, bath_terms=terms)
+    G1, G2 = model.gamma_matrix(inst, 1.0), model.gamma_matrix(inst, 20.0)
+    assert np.abs(G1 @ G2 - G2 @ G1).max() > 1e-2 * np.abs(G1).max() * np.abs(G2).max()
+    tabs = spectrum.all_tables(inst, n_grid=6, keep_V=True)
+    assert tabs[1].R.shape[0] == 4              # 3 local channels + 1 shared
+    for T in tabs[1:4]:
+        zq = [T.V.T @ (model.sz_diag(q, 3)[:, None] * T.V) for q in range(3)]
+        dt = 3.7
+        rng = np.random.default_rng(T.g)
+        X = rng.normal(size=(8, 8)) + 1j * rng.normal(size=(8, 8))
+        r0 = X @ X.conj().T
+        r0 /= np.trace(r0)
+        got = ame.step_map(r0, T, inst, dt)
+        Ls = ame.liouvillian_correlated(T, inst, zq)
+        want = (sla.expm(Ls * dt) @ r0.reshape(-1, order="F")).reshape(8, 8, order="F")
+        np.testing.assert_allclose(got, want, atol=1e-13)
+
+
+def test_single_bath_term_equals_constant_correlation():
+    """One term (C, omega_c of the bath) is the constant-correlation model."""
+    C = np.array([[1.0, 0.4, 0.1], [0.4, 1.0, 0.4], [0.1, 0.4, 1.0]])
+    inst = W.ring_instance(3, 5, t_f=40.0, eta=3e-3)
+    a = spectrum.all_tables(inst.with_(bath_corr=C), n_grid=5)
+    b = spectrum.all_tables(inst.with_(bath_terms=((C, inst.omega_c),)), n_grid=5)
+    for Ta, Tb in zip(a[1:], b[1:]):
+        np.testing.assert_allclose(Tb.R, Ta.R, rtol=1e-12, atol=1e-18)
+        np.testing.assert_allclose(Tb.Gamma, Ta.Gamma, rtol=1e-12)
+
+
+def test_trajectory_average_matches_ame_frequency_dependent_bath():
+    """Trajectories with the per-term channels average to the split-step AME."""
+    inst = W.ring_instance(3, 8, t_f=1.5, eta=0.1, n_grid=61, bath_terms=W.two_term_bath(3, rho=0.8))
+    tabs = spectrum.all_tables(inst)
+    P = ame.split_step(tabs, inst)
+    K = 2000
+    res = trajectories.run(tabs, inst, K, record=False)
+    m, se = trajectories.mean_and_stderr(res.pgs_sum, res.pgs_sumsq, K)
+    sigma = np.maximum(se, np.sqrt(np.clip(P * (1 - P), 0, None) / K))
+    assert P.min() < 0.9 and res.kind_totals.sum() > K
+    assert np.all(np.abs(m - P) <= 3 * sigma + 1e-4)
+
+
 def test_fixed_step_two_level_follows_the_discrete_chain():
     """Fixed-step unraveling (App. B): a frozen two-level system stays in eigenstates, and
     per sub-step h it jumps 0 -> 1 with probability h W10 and 1 -> 0 with h W01, so its

@@ -51,6 +51,8 @@ class Instance:
     lamb_shift: bool = False      # include the Lamb-shift Hamiltonian of the Ohmic bath
     bath_corr: Optional[np.ndarray] = None   # [n_qubits, n_qubits] correlation C of the baths
                                              # (gamma_ab(w) = C_ab gamma(w)); None = independent
+    bath_terms: Optional[tuple] = None       # ((C_m, omega_c_m), ...): gamma_ab(w) =
+                                             # sum_m C_m[a, b] gamma(w; omega_c_m), C_m PSD
     n_grid: int = 1001            # s-grid points (n_grid - 1 steps)
     n_levels: int = 0             # retained levels; 0 = full spectrum
     n_traj: int = 1000
@@ -223,3 +225,15 @@ def case0989() -> Instance:
     A, B = linear_schedule()
     return Instance(name="case0989-linear", n_qubits=8, h=-h_paper, J=J, t_f=1.0e4,
                     A_ctrl=A, B_ctrl=B, n_grid=2000, T=kelvin_to_rad_per_ns(0.012))
+
+
+def two_term_bath(n_qubits: int, rho: float = 0.5, common_cutoff: float = 2.0 * math.pi,
+                  local_cutoff: float = 8.0 * math.pi, xi: float = 0.5):
+    """A frequency-dependent bath correlation: local baths correlated as xi^|a-b| with the
+    standard cutoff, plus one bath shared by all qubits (rank one, weight rho) with a
+    lower cutoff.  The two correlation matrices do not commute, so the eigenvectors of
+    gamma_ab(w) turn with w."""
+    q = n_qubits
+    C0 = np.array([[xi ** abs(a - b) for b in range(q)] for a in range(q)])
+    C1 = rho * np.ones((q, q))
+    return ((C0, local_cutoff), (C1, common_cutoff))
