@@ -152,15 +152,18 @@ AQT_API aqt_status aqt_precompute_ex(aqt_ctx* ctx, int n_grid, int n_levels, dou
  * tables aqt_precompute builds; host arrays, FP64, row-major):
  *   E[n_grid*n]; gs[n_grid] ground-cluster sizes; O[n_grid*n*n] with O[g] the
  *   polar overlap into grid g (g >= 2, others ignored); cinit[n] initial state in
- *   the grid-1 basis; R[n_grid*nq*n*n] as R[g][i][b][a] (rate of b -> a through
- *   qubit i, a == b the omega = 0 weight gamma(0) z_bb^2); zdiag[n_grid*nq*n].
+ *   the grid-1 basis; R[n_grid*nc*n*n] as R[g][i][b][a] (rate of b -> a through
+ *   jump channel i, a == b the omega = 0 weight gamma(0) z_bb^2); zdiag[n_grid*nc*n].
+ *   nc = aqt_get_channel_count (n_qubits unless bath terms are set); AQT_EINVAL if
+ *   nc > min(64, n_levels padded to 16, 32, 64, 128 or 256).
  * Decay rates and phases are derived from them on the GPU.  Synchronises. */
 AQT_API aqt_status aqt_set_tables(aqt_ctx* ctx, int n_grid, int n_levels, const double* E,
                           const int32_t* gs, const double* O, const double* cinit,
                           const double* R, const double* zdiag);
 
 /* Copy tables back to host arrays (any may be NULL): E[M*n], gs[M], O[M*n*n],
- * cinit[n], R[M*nq*n*n], zdiag[M*nq*n], Gamma[M*n], leak[M].  Synchronises. */
+ * cinit[n], R[M*nc*n*n], zdiag[M*nc*n], Gamma[M*n], leak[M] (nc: the tables' jump
+ * channels, aqt_get_channel_count).  Synchronises. */
 AQT_API aqt_status aqt_get_tables(aqt_ctx* ctx, double* E, int32_t* gs, double* O, double* cinit,
                           double* R, double* zdiag, double* Gamma, double* leak);
 
@@ -205,6 +208,32 @@ AQT_API aqt_status aqt_run_fixed_step(aqt_ctx* ctx, const aqt_run_params* params
  * different qubit count.  AQT_ESTATE before aqt_set_hamiltonian; AQT_EINVAL if C is not
  * finite, symmetric (1e-12 relative) or positive definite. */
 AQT_API aqt_status aqt_set_bath_correlation(aqt_ctx* ctx, const double* C);
+
+/* Frequency-dependent bath correlations (Sec. II eq. ME2-L with a general gamma_ab(w),
+ * which the paper brings to diagonal form by a frequency-dependent rotation u(w)):
+ *   gamma_ab(w) = sum_m C_m[a][b] gamma(w; omega_c[m]),
+ * a sum of n_terms Ohmic spectral densities (the bath's eta and T, each term its own
+ * cutoff omega_c[m] > 0, rad/ns), each with a symmetric positive semidefinite
+ * correlation C_m (host, [n_terms][n_qubits][n_qubits] row-major).  Every C_m is
+ * factored as F_m F_m^T by the Cholesky recursion in natural order, dropping a
+ * column whose pivot is at most 1e-12 max(diag C_m); each kept column k gives a jump
+ * channel with coupling operator sum_a F_m[a][k] sz_a and rate gamma(w; omega_c[m]),
+ * channels numbered term by term.  Since sum over channels of F F^T gamma_m equals
+ * gamma_ab(w) at every w, these channels give the master equation's dissipator at
+ * every Bohr frequency (in place of u(w)); tables, jump records ("qubit" is the
+ * channel) and aqt_get_channel_count refer to them.  n_terms = 0 restores independent
+ * baths; replaces any aqt_set_bath_correlation.  Applies from the next aqt_precompute
+ * (loaded tables are invalidated).  The Lamb shift and aqt_grad_pgs need one spectral
+ * density and return AQT_EINVAL with bath terms.  AQT_ESTATE before
+ * aqt_set_hamiltonian; AQT_EINVAL for non-finite or non-symmetric (1e-12 relative)
+ * C_m, a pivot below -1e-9 max(diag C_m) (not semidefinite), a cutoff <= 0, no
+ * channel at all or more than 64; aqt_precompute returns AQT_EINVAL when the channels
+ * outnumber the padded level count. */
+AQT_API aqt_status aqt_set_bath_terms(aqt_ctx* ctx, int n_terms, const double* C, const double* omega_c);
+
+/* Jump channels of the loaded tables (before any, of the current bath settings):
+ * n_qubits for independent or constant-correlation baths. */
+AQT_API aqt_status aqt_get_channel_count(aqt_ctx* ctx, int32_t* n_channels);
 
 /* ---- Lamb shift ----------------------------------------------------------------------
  * enabled != 0 adds the Lamb-shift Hamiltonian of the Ohmic bath, H_LS = sum_i sum_w S(w)

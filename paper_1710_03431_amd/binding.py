@@ -23,7 +23,7 @@ KIND_NAMES = ("relax", "excite", "dephase")
 EXPORTED = ("aqt_create", "aqt_destroy", "aqt_last_error", "aqt_version", "aqt_set_hamiltonian",
             "aqt_set_schedule", "aqt_set_bath", "aqt_precompute", "aqt_precompute_ex", "aqt_set_tables", "aqt_get_tables",
             "aqt_get_dims", "aqt_run", "aqt_grad_pgs", "aqt_set_lamb_shift", "aqt_get_lamb_shift",
-            "aqt_set_bath_correlation", "aqt_run_fixed_step",
+            "aqt_set_bath_correlation", "aqt_set_bath_terms", "aqt_get_channel_count", "aqt_run_fixed_step",
             "aqt_batch_create", "aqt_batch_launch", "aqt_batch_tiles",
             "aqt_batch_last_error", "aqt_batch_destroy")
 BATCH_GRAPH, BATCH_AUTOTUNE = 1, 2
@@ -95,6 +95,8 @@ def load_library(path: str = LIB_PATH):
     lib.aqt_grad_pgs.argtypes = [ctx, C.POINTER(RunParams), dp, dp, dp, dp, C.c_void_p]
     lib.aqt_set_lamb_shift.argtypes = [ctx, C.c_int]
     lib.aqt_set_bath_correlation.argtypes = [ctx, dp]
+    lib.aqt_set_bath_terms.argtypes = [ctx, C.c_int, dp, dp]
+    lib.aqt_get_channel_count.argtypes = [ctx, ip]
     lib.aqt_run_fixed_step.argtypes = [ctx, C.POINTER(RunParams), C.c_int, C.POINTER(Outputs)]
     lib.aqt_get_lamb_shift.argtypes = [ctx, dp]
     lib.aqt_batch_create.argtypes = [C.POINTER(C.c_void_p), C.POINTER(C.c_void_p), C.c_int,
@@ -144,7 +146,7 @@ class Engine:
         if st != AQT_OK:
             raise AqtError(st, f"aqt_create failed on device {device} (no usable HIP device?)")
         self.ctx = h
-        self.n_grid = self.n_levels = self.n_qubits = None
+        self.n_grid = self.n_levels = self.n_qubits = self.n_channels = None
         self.n_ctrl = 0
 
     def close(self):
@@ -181,6 +183,21 @@ class Engine:
         """gamma_ab(w) = C_ab gamma(w) between the qubits' baths (None: independent)."""
         self._check(self.lib.aqt_set_bath_correlation(self.ctx, None if C is None else _dptr(_f64(C))))
 
+    def set_bath_terms(self, terms=None):
+        """gamma_ab(w) = sum_m C_m[a, b] gamma(w; omega_c_m) for terms ((C_m, omega_c_m), ...)
+        (None or empty: independent baths)."""
+        if not terms:
+            self._check(self.lib.aqt_set_bath_terms(self.ctx, 0, None, None))
+            return
+        Cs = _f64(np.stack([np.asarray(c, dtype=np.float64) for c, _ in terms]))
+        wc = _f64(np.array([float(w) for _, w in terms]))
+        self._check(self.lib.aqt_set_bath_terms(self.ctx, len(terms), _dptr(Cs), _dptr(wc)))
+
+    def channel_count(self) -> int:
+        v = C.c_int32()
+        self._check(self.lib.aqt_get_channel_count(self.ctx, C.byref(v)))
+        return v.value
+
     def set_lamb_shift(self, enabled: bool):
         self._check(self.lib.aqt_set_lamb_shift(self.ctx, int(bool(enabled))))
 
@@ -195,6 +212,8 @@ class Engine:
         self.set_schedule(inst.t_f, inst.A_ctrl, inst.B_ctrl)
         self.set_bath(inst.eta, inst.omega_c, inst.T)
         self.set_bath_correlation(getattr(inst, "bath_corr", None))
+        if getattr(inst, "bath_terms", None) is not None:
+            self.set_bath_terms(inst.bath_terms)
         self.set_lamb_shift(getattr(inst, "lamb_shift", False))
 
     def precompute(self, n_grid: int, n_levels: int, deg_tol: float = 1e-8, method: str = "auto"):
@@ -219,9 +238,10 @@ class Engine:
         a, b, c = C.c_int32(), C.c_int32(), C.c_int32()
         self._check(self.lib.aqt_get_dims(self.ctx, C.byref(a), C.byref(b), C.byref(c)))
         self.n_grid, self.n_levels, self.n_qubits = a.value, b.value, c.value
+        self.n_channels = self.channel_count()
 
     def get_tables(self, want=("E", "gs", "O", "cinit", "R", "zdiag", "Gamma", "leak")):
-        M, n, nq = self.n_grid, self.n_levels, self.n_qubits
+        M, n, nq = self.n_grid, self.n_levels, self.n_channels
         shapes = {"E": (M, n), "gs": (M,), "O": (M, n, n), "cinit": (n,), "R": (M, nq, n, n),
                   "zdiag": (M, nq, n), "Gamma": (M, n), "leak": (M,)}
         out = {k: (np.zeros(shapes[k], dtype=np.int32 if k == "gs" else np.float64) if k in want else None)

@@ -105,7 +105,10 @@ aqt_status aqt_set_hamiltonian(aqt_ctx* ctx, int n_qubits, const double* h, cons
   if (!h || !J) return ctx->fail(AQT_EINVAL, "h and J must be non-null");
   if (!finite_all(h, n_qubits) || !finite_all(J, static_cast<size_t>(n_qubits) * n_qubits))
     return ctx->fail(AQT_EINVAL, "h and J must be finite");
-  if (ctx->nq != n_qubits) ctx->chol.clear();   // a correlation matrix is per qubit count
+  if (ctx->nq != n_qubits) {   // bath correlations are per qubit count
+    ctx->chan.clear();
+    ctx->chan_wc.clear();
+  }
   ctx->nq = n_qubits;
   ctx->h.assign(h, h + n_qubits);
   ctx->J.assign(J, J + static_cast<size_t>(n_qubits) * n_qubits);
@@ -182,13 +185,15 @@ aqt_status aqt_set_tables(aqt_ctx* ctx, int n_grid, int n_levels, const double* 
     if (gs[g] < 1 || gs[g] > n_levels) return ctx->fail(AQT_EINVAL, "ground-cluster size out of range");
   aqt_status s = set_device(ctx);
   if (s != AQT_OK) return s;
-  const int n = n_levels, NP = aqt::padded_levels(n), nq = ctx->nq;
+  const int n = n_levels, NP = aqt::padded_levels(n), nq = ctx->nch();   // nq: jump channels
+  if (nq > std::min(NP, 64)) return ctx->fail(AQT_EINVAL, "more jump channels than min(64, padded levels)");
   ctx->have_tables = false;
   ctx->have_grad = false;
   ctx->last_from_solver = false;
   ctx->M = n_grid;
   ctx->n = n;
   ctx->NP = NP;
+  ctx->tab_nch = nq;
   ctx->dt = ctx->t_f / (n_grid - 1);
   if ((s = upload_padded(ctx, ctx->E, E, n_grid, n, NP, false)) != AQT_OK) return s;
   // Delta = O - I on the n x n block, zero elsewhere
@@ -235,7 +240,7 @@ aqt_status aqt_get_tables(aqt_ctx* ctx, double* E, int32_t* gs, double* O, doubl
   aqt_status s = set_device(ctx);
   if (s != AQT_OK) return s;
   AQT_HIP(ctx, hipStreamSynchronize(ctx->stream));
-  const int M = ctx->M, n = ctx->n, NP = ctx->NP, nq = ctx->nq;
+  const int M = ctx->M, n = ctx->n, NP = ctx->NP, nq = ctx->tab_nch;   // nq: jump channels
   if (E && (s = download_unpadded(ctx, E, ctx->E, M, n, NP, false)) != AQT_OK) return s;
   if (gs) AQT_HIP(ctx, hipMemcpy(gs, ctx->gs.p, M * sizeof(int32_t), hipMemcpyDeviceToHost));
   if (O) {
@@ -287,7 +292,8 @@ aqt_status aqt_set_bath_correlation(aqt_ctx* ctx, const double* C) {
   if (!ctx->have_h) return ctx->fail(AQT_ESTATE, "set_hamiltonian must come first");
   const int nq = ctx->nq;
   if (!C) {
-    ctx->chol.clear();
+    ctx->chan.clear();
+    ctx->chan_wc.clear();
   } else {
     double scale = 0.0;
     for (int i = 0; i < nq * nq; ++i) {
@@ -310,10 +316,81 @@ aqt_status aqt_set_bath_correlation(aqt_ctx* ctx, const double* C) {
         L[i * nq + j] = v / L[j * nq + j];
       }
     }
-    ctx->chol = L;
+    ctx->chan.assign(static_cast<size_t>(nq) * nq, 0.0);
+    for (int k = 0; k < nq; ++k)
+      for (int a = 0; a < nq; ++a) ctx->chan[static_cast<size_t>(k) * nq + a] = L[a * nq + k];
+    ctx->chan_wc.assign(nq, 0.0);
   }
   ctx->have_tables = false;
   ctx->have_grad = false;
+  return AQT_OK;
+}
+
+aqt_status aqt_set_bath_terms(aqt_ctx* ctx, int n_terms, const double* C, const double* omega_c) {
+  if (!ctx) return AQT_EINVAL;
+  if (!ctx->have_h) return ctx->fail(AQT_ESTATE, "set_hamiltonian must come first");
+  const int nq = ctx->nq;
+  if (n_terms == 0) {
+    ctx->chan.clear();
+    ctx->chan_wc.clear();
+    ctx->have_tables = false;
+    ctx->have_grad = false;
+    return AQT_OK;
+  }
+  if (n_terms < 0 || !C || !omega_c) return ctx->fail(AQT_EINVAL, "bath terms need C and omega_c");
+  std::vector<double> chan, wc;
+  for (int m = 0; m < n_terms; ++m) {
+    const double* Cm = C + static_cast<size_t>(m) * nq * nq;
+    if (!(omega_c[m] > 0.0) || !std::isfinite(omega_c[m]))
+      return ctx->fail(AQT_EINVAL, "bath term cutoff must be positive and finite");
+    double scale = 0.0, dmax = 0.0;
+    for (int i = 0; i < nq * nq; ++i) {
+      if (!std::isfinite(Cm[i])) return ctx->fail(AQT_EINVAL, "bath term matrix has non-finite entries");
+      scale = std::max(scale, std::fabs(Cm[i]));
+    }
+    for (int i = 0; i < nq; ++i) {
+      dmax = std::max(dmax, Cm[i * nq + i]);
+      for (int j = 0; j < i; ++j)
+        if (std::fabs(Cm[i * nq + j] - Cm[j * nq + i]) > 1e-12 * scale)
+          return ctx->fail(AQT_EINVAL, "bath term matrix is not symmetric");
+    }
+    // semidefinite Cholesky in natural order: a column whose pivot is at most
+    // 1e-12 max(diag) is dropped (for a semidefinite matrix the rest of it vanishes)
+    const double tol = 1e-12 * dmax;
+    std::vector<double> L(static_cast<size_t>(nq) * nq, 0.0);
+    std::vector<int> keep;
+    for (int j = 0; j < nq; ++j) {
+      double d = Cm[j * nq + j];
+      for (int k : keep) d -= L[j * nq + k] * L[j * nq + k];
+      if (d <= tol) {
+        if (d < -1e-9 * std::max(dmax, 1e-300)) return ctx->fail(AQT_EINVAL, "bath term matrix is not semidefinite");
+        continue;
+      }
+      L[j * nq + j] = std::sqrt(d);
+      for (int i = j + 1; i < nq; ++i) {
+        double v = Cm[i * nq + j];
+        for (int k : keep) v -= L[i * nq + k] * L[j * nq + k];
+        L[i * nq + j] = v / L[j * nq + j];
+      }
+      keep.push_back(j);
+    }
+    for (int k : keep) {
+      for (int a = 0; a < nq; ++a) chan.push_back(L[a * nq + k]);
+      wc.push_back(omega_c[m]);
+    }
+  }
+  if (wc.empty()) return ctx->fail(AQT_EINVAL, "bath terms are all zero");
+  if (wc.size() > 64) return ctx->fail(AQT_EINVAL, "more than 64 jump channels");
+  ctx->chan = chan;
+  ctx->chan_wc = wc;
+  ctx->have_tables = false;
+  ctx->have_grad = false;
+  return AQT_OK;
+}
+
+aqt_status aqt_get_channel_count(aqt_ctx* ctx, int32_t* n_channels) {
+  if (!ctx || !n_channels) return AQT_EINVAL;
+  *n_channels = ctx->have_tables ? ctx->tab_nch : ctx->nch();
   return AQT_OK;
 }
 
@@ -341,6 +418,8 @@ aqt_status aqt_grad_pgs(aqt_ctx* ctx, const aqt_run_params* p, double* value, do
   if (!p) return ctx->fail(AQT_EINVAL, "params are required");
   if (!ctx->have_tables) return ctx->fail(AQT_ESTATE, "precompute must come first");
   if (ctx->lamb) return ctx->fail(AQT_EINVAL, "the gradient does not include the Lamb shift's derivative");
+  if (!ctx->single_spectrum())
+    return ctx->fail(AQT_EINVAL, "the gradient is built for one bath spectral density (no bath terms)");
   if (!ctx->last_from_solver)
     return ctx->fail(AQT_ESTATE, "the gradient needs tables from aqt_precompute (eigenvectors), not aqt_set_tables");
   if (ctx->n != (1 << ctx->nq))

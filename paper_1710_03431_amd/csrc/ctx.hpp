@@ -25,11 +25,21 @@ struct aqt_ctx {
   double eta = 0.0, omega_c = 0.0, T = 0.0;
   bool have_bath = false;
   bool lamb = false;    // add the Lamb shift at the next precompute
-  std::vector<double> chol;   // nq x nq lower Cholesky factor of the bath correlation (empty: independent)
+  // jump channels: coupling operator sum_a chan[k][a] sz_a and the cutoff of its Ohmic rate
+  // (chan_wc[k], 0: the bath's omega_c); empty: sz of each qubit (independent baths)
+  std::vector<double> chan;      // [nch][nq]
+  std::vector<double> chan_wc;   // [nch]
+  int nch() const { return chan.empty() ? nq : static_cast<int>(chan.size() / nq); }
+  bool single_spectrum() const {
+    for (double w : chan_wc)
+      if (w != 0.0) return false;
+    return true;
+  }
 
   // ---- tables (device, FP64 masters; rows padded to NP with zeros)
   bool have_tables = false;
   int M = 0;        // grid points
+  int tab_nch = 0;  // jump channels of the loaded tables
   int n = 0;        // retained levels
   int NP = 0;       // padded level count: 16, 32, 64, 128 or 256
   double dt = 0.0;

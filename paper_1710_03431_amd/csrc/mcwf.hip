@@ -401,7 +401,7 @@ aqt_status launch_fixed_step(aqt_ctx* ctx, const aqt_run_params* p, int substeps
   fa.cap = p->record_capacity;
   fa.M = ctx->M;
   fa.n = ctx->n;
-  fa.nq = ctx->nq;
+  fa.nq = ctx->tab_nch;   // jump channels
   fa.S = substeps;
   fa.dt = ctx->dt;
   fa.K = p->n_traj;

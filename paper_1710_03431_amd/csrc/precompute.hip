@@ -582,9 +582,10 @@ __device__ double gamma_ohmic(double w, double eta, double wc, double T) {
   return 2.0 * M_PI * eta * w * exp(-fabs(w) / wc) / (-expm1(-w / T));
 }
 
-// R[g][i][b][a] and zdiag[g][i][b] from z (row-major [g-local][i][a][b], ld n).
+// R[g][i][b][a] and zdiag[g][i][b] from z (row-major [g-local][i][a][b], ld n); channel i's
+// rate has cutoff wc[i].
 __global__ void k_rates(const double* __restrict__ z, const double* __restrict__ E, int n, int NP, int nq, int g0,
-                        int count, double eta, double wc, double T, double* __restrict__ R,
+                        int count, double eta, const double* __restrict__ wc, double T, double* __restrict__ R,
                         double* __restrict__ zdiag) {
   const int64_t per = static_cast<int64_t>(nq) * NP * NP;
   const int64_t idx = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
@@ -599,7 +600,7 @@ __global__ void k_rates(const double* __restrict__ z, const double* __restrict__
   if (a < n && b < n) {
     const double zab = z[((static_cast<size_t>(c) * nq + i) * n + a) * n + b];
     const double w = (a == b) ? 0.0 : E[static_cast<size_t>(g) * NP + b] - E[static_cast<size_t>(g) * NP + a];
-    val = gamma_ohmic(w, eta, wc, T) * zab * zab;
+    val = gamma_ohmic(w, eta, wc[i], T) * zab * zab;
     if (a == b) zdiag[(static_cast<size_t>(g) * nq + i) * NP + b] = zab;
   } else if (a == b) {
     zdiag[(static_cast<size_t>(g) * nq + i) * NP + b] = 0.0;
@@ -1200,9 +1201,14 @@ aqt_status chfsi_solve(aqt_ctx* ctx, Chfsi& c, const double* eZ, double A, doubl
 aqt_status precompute_tables(aqt_ctx* ctx, int M, int n, double tol, int method, bool grad) {
   const int nq = ctx->nq;
   const int N = 1 << nq;
+  const int nch = ctx->nch();   // jump channels (nq for independent or constant-correlation baths)
   ctx->have_grad = false;
   ctx->gpk_prec = -1;
   if (grad && n != N) return ctx->fail(AQT_EINVAL, "gradient tables need the full spectrum (n_levels = 2^n_qubits)");
+  if (grad && !ctx->single_spectrum())
+    return ctx->fail(AQT_EINVAL, "the gradient is built for one bath spectral density (no bath terms)");
+  if (ctx->lamb && !ctx->single_spectrum())
+    return ctx->fail(AQT_EINVAL, "the Lamb shift is built for one bath spectral density (no bath terms)");
   const bool iterative = (method == AQT_EIG_ITERATIVE) || (method == AQT_EIG_AUTO && N > kEigMaxN);
   const int ncols = std::min(N, n + 16);   // levels solved for: n plus a guard for clusters at the cut
   int KB = 0;                              // block size of the subspace iteration
@@ -1216,6 +1222,8 @@ aqt_status precompute_tables(aqt_ctx* ctx, int M, int n, double tol, int method,
     if (n < N && n > 128) return ctx->fail(AQT_EINVAL, "truncated spectra are limited to n <= 128 levels");
   }
   const int NP = padded_levels(n);
+  if (nch > std::min(NP, 64))
+    return ctx->fail(AQT_EINVAL, "more jump channels than min(64, padded levels): keep more levels or fewer bath terms");
   hipStream_t st = ctx->stream;
   // dense path with ncols << N: bisection and inverse iteration instead of the full
   // rotation product, when the workspace (columns ncols.. of the N x N eigenvector
@@ -1255,32 +1263,39 @@ aqt_status precompute_tables(aqt_ctx* ctx, int M, int n, double tol, int method,
   ctx->M = M;
   ctx->n = n;
   ctx->NP = NP;
+  ctx->tab_nch = nch;
   ctx->dt = ctx->t_f / (M - 1);
   const size_t sNP = static_cast<size_t>(NP);
   if (ctx->E.reserve(M * sNP * 8) || ctx->gs.reserve(M * 4) || ctx->dlt.reserve(M * sNP * sNP * 8) ||
-      ctx->cinit.reserve(sNP * 8) || ctx->R.reserve(static_cast<size_t>(M) * nq * sNP * sNP * 8) ||
-      ctx->zdiag.reserve(static_cast<size_t>(M) * nq * sNP * 8) || ctx->leak.reserve(M * 8) ||
+      ctx->cinit.reserve(sNP * 8) || ctx->R.reserve(static_cast<size_t>(M) * nch * sNP * sNP * 8) ||
+      ctx->zdiag.reserve(static_cast<size_t>(M) * nch * sNP * 8) || ctx->leak.reserve(M * 8) ||
       ctx->shift.reserve(M * sNP * 8))
     return ctx->fail(AQT_ENOMEM, "table allocation failed");
   AQT_HIP(ctx, hipMemsetAsync(ctx->dlt.p, 0, M * sNP * sNP * 8, st));
-  AQT_HIP(ctx, hipMemsetAsync(ctx->R.p, 0, static_cast<size_t>(sNP) * sNP * nq * 8, st));       // g = 0 unused
-  AQT_HIP(ctx, hipMemsetAsync(ctx->zdiag.p, 0, static_cast<size_t>(sNP) * nq * 8, st));
+  AQT_HIP(ctx, hipMemsetAsync(ctx->R.p, 0, static_cast<size_t>(sNP) * sNP * nch * 8, st));       // g = 0 unused
+  AQT_HIP(ctx, hipMemsetAsync(ctx->zdiag.p, 0, static_cast<size_t>(sNP) * nch * 8, st));
   AQT_HIP(ctx, hipMemsetAsync(ctx->leak.p, 0, M * 8, st));
   AQT_HIP(ctx, hipMemsetAsync(ctx->shift.p, 0, M * sNP * 8, st));
-  // jump-channel couplings: sz of each qubit, or for correlated baths gamma_ab = C_ab gamma
-  // with C = L L^T the channels sum_a L[a][k] sz_a (Sec. II eq. ME2-L)
-  DevBuf chw;
-  if (!ctx->chol.empty()) {
-    std::vector<double> w(static_cast<size_t>(nq) * N);
-    for (int k = 0; k < nq; ++k)
+  // jump-channel couplings: sz of each qubit, or for correlated baths gamma_ab(w) =
+  // sum_m C_m[a][b] gamma(w; omega_c,m) with C_m = F_m F_m^T the channels sum_a F_m[a][k] sz_a,
+  // each with its term's cutoff (Sec. II eq. ME2-L); chan holds the F columns
+  DevBuf chw, wcv;
+  if (!ctx->chan.empty()) {
+    std::vector<double> w(static_cast<size_t>(nch) * N);
+    for (int k = 0; k < nch; ++k)
       for (int x = 0; x < N; ++x) {
         double acc = 0.0;
-        for (int a = k; a < nq; ++a) acc += ctx->chol[a * nq + k] * (((x >> a) & 1) ? -1.0 : 1.0);
+        for (int a = 0; a < nq; ++a) acc += ctx->chan[static_cast<size_t>(k) * nq + a] * (((x >> a) & 1) ? -1.0 : 1.0);
         w[static_cast<size_t>(k) * N + x] = acc;
       }
     if (chw.reserve(w.size() * 8)) return ctx->fail(AQT_ENOMEM, "channel weight allocation failed");
     AQT_HIP(ctx, hipMemcpyAsync(chw.p, w.data(), w.size() * 8, hipMemcpyHostToDevice, st));
   }
+  std::vector<double> wch(nch, ctx->omega_c);
+  for (int k = 0; k < nch && k < static_cast<int>(ctx->chan_wc.size()); ++k)
+    if (ctx->chan_wc[k] != 0.0) wch[k] = ctx->chan_wc[k];
+  if (wcv.reserve(nch * 8)) return ctx->fail(AQT_ENOMEM, "channel cutoff allocation failed");
+  AQT_HIP(ctx, hipMemcpyAsync(wcv.p, wch.data(), nch * 8, hipMemcpyHostToDevice, st));
   // Lamb-shift function table over every Bohr frequency (Gershgorin bound on |e|)
   DevBuf lambS, gl;
   LambTable ltab{nullptr, 0.0};
@@ -1327,7 +1342,7 @@ aqt_status precompute_tables(aqt_ctx* ctx, int M, int n, double tol, int method,
   const size_t per_grid = (iterative ? 0 : 2 * static_cast<size_t>(N) * N)   // H, Z (dense path)
                           + static_cast<size_t>(ncols) * N            // canonical V
                           + 2 * static_cast<size_t>(ncols) * ncols + static_cast<size_t>(ncols) * N  // canon ws
-                          + static_cast<size_t>(nq) * n * n           // z
+                          + static_cast<size_t>(nch) * n * n          // z
                           + 9 * static_cast<size_t>(n) * n            // polar ws
                           + N                                         // Eraw
                           + (grad ? static_cast<size_t>(n) * N + 2 * static_cast<size_t>(n) * n +
@@ -1339,7 +1354,7 @@ aqt_status precompute_tables(aqt_ctx* ctx, int M, int n, double tol, int method,
   if ((!iterative && (H.reserve(static_cast<size_t>(Gc) * N * N * 8) || Z.reserve(static_cast<size_t>(Gc) * N * N * 8))) ||
       Vc.reserve(static_cast<size_t>(Gc) * ncols * N * 8) || Vprev.reserve(static_cast<size_t>(ncols) * N * 8) ||
       cws.reserve(static_cast<size_t>(Gc) * (2 * static_cast<size_t>(ncols) * ncols + static_cast<size_t>(ncols) * N) * 8) ||
-      zws.reserve(static_cast<size_t>(Gc) * nq * n * n * 8) || pws.reserve(static_cast<size_t>(Gc) * 9 * n * n * 8) ||
+      zws.reserve(static_cast<size_t>(Gc) * nch * n * n * 8) || pws.reserve(static_cast<size_t>(Gc) * 9 * n * n * 8) ||
       Eraw.reserve(static_cast<size_t>(Gc) * N * 8) || perm.reserve(static_cast<size_t>(Gc) * N * 4) ||
       status.reserve(static_cast<size_t>(Gc) * 4))
     return ctx->fail(AQT_ENOMEM, "precompute workspace allocation failed");
@@ -1484,17 +1499,17 @@ aqt_status precompute_tables(aqt_ctx* ctx, int M, int n, double tol, int method,
       const int off = zg0 - g0;
       GemmArgs ga{Vc.as<double>() + off * Vstride, Vc.as<double>() + off * Vstride, zws.as<double>(),
                   static_cast<int64_t>(Vstride), static_cast<int64_t>(Vstride), static_cast<int64_t>(n) * n,
-                  n, n, N, N, N, n, chw.p ? 4 : 1, nq, 0};
+                  n, n, N, N, N, n, chw.p ? 4 : 1, nch, 0};
       ga.wvec = chw.as<double>();
-      aqt_status s = launch_gemm(ctx, ga, zcnt * nq);
+      aqt_status s = launch_gemm(ctx, ga, zcnt * nch);
       if (s != AQT_OK) return s;
-      hipLaunchKernelGGL(k_rates, dim3(nblk(static_cast<int64_t>(nq) * NP * NP * zcnt)), dim3(256), 0, st,
-                         zws.as<double>(), ctx->E.as<double>(), n, NP, nq, zg0, zcnt, ctx->eta, ctx->omega_c, ctx->T,
-                         ctx->R.as<double>(), ctx->zdiag.as<double>());
+      hipLaunchKernelGGL(k_rates, dim3(nblk(static_cast<int64_t>(nch) * NP * NP * zcnt)), dim3(256), 0, st,
+                         zws.as<double>(), ctx->E.as<double>(), n, NP, nch, zg0, zcnt, ctx->eta, wcv.as<double>(),
+                         ctx->T, ctx->R.as<double>(), ctx->zdiag.as<double>());
       AQT_HIP(ctx, hipGetLastError());
       if (ctx->lamb) {
         hipLaunchKernelGGL(k_lamb_shift, dim3(nblk(static_cast<int64_t>(zcnt) * NP)), dim3(256), 0, st,
-                           zws.as<double>(), ctx->E.as<double>(), n, NP, nq, zg0, zcnt, ltab, ctx->shift.as<double>());
+                           zws.as<double>(), ctx->E.as<double>(), n, NP, nch, zg0, zcnt, ltab, ctx->shift.as<double>());
         AQT_HIP(ctx, hipGetLastError());
       }
     }

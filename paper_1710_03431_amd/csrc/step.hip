@@ -1181,7 +1181,7 @@ aqt_status launch_run(aqt_ctx* ctx, const aqt_run_params* p, const aqt_outputs* 
   a.pgs_sum = o->pgs_sum;
   a.pgs_sumsq = o->pgs_sumsq;
   a.n = ctx->n;
-  a.nq = ctx->nq;
+  a.nq = ctx->tab_nch;   // jump channels
   a.dt = ctx->dt;
   a.K = p->n_traj;
   a.seed = p->seed;
@@ -1446,7 +1446,7 @@ aqt_status aqt_batch_create(aqt_batch** out, aqt_ctx* const* ctxs, int n, const 
     a.M = c->M;
     a.M_run = c->M;
     a.n = c->n;
-    a.nq = c->nq;
+    a.nq = c->tab_nch;   // jump channels
     a.NP = c->NP;
     a.dt = c->dt;
     a.K = params[i].n_traj;

@@ -163,11 +163,11 @@ aqt_status finish_tables(aqt_ctx* ctx) {
   const int64_t cnt = static_cast<int64_t>(ctx->M) * ctx->NP;
   if (ctx->Gamma.reserve(cnt * sizeof(double)) != hipSuccess || ctx->dre.reserve(cnt * sizeof(double)) != hipSuccess ||
       ctx->dim.reserve(cnt * sizeof(double)) != hipSuccess ||
-      ctx->Rcol.reserve(cnt * ctx->nq * 4 * sizeof(double)) != hipSuccess ||
+      ctx->Rcol.reserve(cnt * ctx->tab_nch * 4 * sizeof(double)) != hipSuccess ||
       ctx->ehalf.reserve(cnt * sizeof(double)) != hipSuccess)
     return ctx->fail(AQT_ENOMEM, "table allocation failed");
   hipLaunchKernelGGL(k_gamma_phase, dim3(blocks_for(cnt)), dim3(256), 0, ctx->stream, ctx->E.as<double>(),
-                     ctx->shift.as<double>(), ctx->R.as<double>(), ctx->M, ctx->NP, ctx->n, ctx->nq, ctx->dt, ctx->Gamma.as<double>(),
+                     ctx->shift.as<double>(), ctx->R.as<double>(), ctx->M, ctx->NP, ctx->n, ctx->tab_nch, ctx->dt, ctx->Gamma.as<double>(),
                      ctx->Rcol.as<double>(), ctx->ehalf.as<double>(), ctx->dre.as<double>(), ctx->dim.as<double>());
   AQT_HIP(ctx, hipGetLastError());
   ctx->packed_for = -1;
