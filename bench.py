@@ -1,7 +1,7 @@
 """Throughput of the GPU trajectory engine.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload a2a8|ring4|gadget16|batched|grad|fixed]
-                    [--lamb-shift] [--bath-corr RHO]
+                    [--lamb-shift] [--bath-corr RHO] [--bath-terms RHO]
                     [--cpu-traj 3072] [--cpu-grid 500] [--no-cpu]
 
 One bench step = one aqt_run: all trajectories of the workload through the whole
@@ -31,6 +31,9 @@ Workloads:
             waiting-time run timed beside it
 --lamb-shift adds the Ohmic Lamb shift to the tables (a2a8, ring4, fixed)
 --bath-corr RHO correlates the qubits' baths, C_ab = RHO^|a - b| (a2a8, ring4)
+--bath-terms RHO frequency-dependent correlations: local baths correlated as 0.5^|a - b|
+            (cutoff 8 pi) plus a bath shared by all qubits with weight RHO and cutoff
+            2 pi (one more jump channel) (a2a8, ring4)
 """
 import argparse
 import json
@@ -56,6 +59,7 @@ def parse():
     ap.add_argument("--workload", default="a2a8", choices=("a2a8", "ring4", "gadget16", "batched", "grad", "fixed"))
     ap.add_argument("--lamb-shift", action="store_true")
     ap.add_argument("--bath-corr", type=float, default=None)
+    ap.add_argument("--bath-terms", type=float, default=None)
     ap.add_argument("--substeps", type=int, default=4)
     ap.add_argument("--n-traj", type=int, default=0, help="override the workload's trajectory count")
     ap.add_argument("--cpu-traj", type=int, default=3072)
@@ -393,7 +397,10 @@ def main():
         import numpy as np
         q = inst.n_qubits
         inst = inst.with_(bath_corr=np.array([[args.bath_corr ** abs(a - b) for b in range(q)] for a in range(q)]))
-    if args.lamb_shift or args.bath_corr is not None:
+    if args.bath_terms is not None:
+        import workloads as W
+        inst = inst.with_(bath_terms=W.two_term_bath(inst.n_qubits, rho=args.bath_terms))
+    if args.lamb_shift or args.bath_corr is not None or args.bath_terms is not None:
         wl["golden"] = None   # the stored AME references are for independent baths without the Lamb shift
     K = inst.n_traj
     M = inst.n_grid
@@ -442,7 +449,9 @@ def main():
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": head["ms"], "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": head_prec, "data": "synthetic",
         "config": {"workload": wl["text"] + (", Lamb shift" if args.lamb_shift else "")
-                   + (f", bath correlation {args.bath_corr}^|a-b|" if args.bath_corr is not None else ""),
+                   + (f", bath correlation {args.bath_corr}^|a-b|" if args.bath_corr is not None else "")
+                   + (f", bath terms 0.5^|a-b| (cutoff 8 pi) + shared {args.bath_terms} (cutoff 2 pi)"
+                      if args.bath_terms is not None else ""),
                    "name": inst.name,
                    "n_traj": K, "n_levels": n, "n_grid": M, "precision": head_prec, "seed": inst.seed},
         "error_vs_fp64_ame": {"P_GS_final_ame": p_ame,
