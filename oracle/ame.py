@@ -218,7 +218,7 @@ def continuous(inst, s_eval, rtol=1e-10, atol=1e-12):
     nq, N = inst.n_qubits, inst.dim
     HX = model.hx_dense(nq)
     HZ = model.hz_dense(inst.h, inst.J)
-    SZ, WC = model.bath_channels(inst)                # channel operators and cutoffs
+    WC = model.bath_channels(inst)[1]                 # cutoff of each channel
     g0 = float(model.gamma_ohmic(0.0, inst.eta, inst.omega_c, inst.T))
 
     def H_at(t):
@@ -232,10 +232,11 @@ def continuous(inst, s_eval, rtol=1e-10, atol=1e-12):
         d = -1j * (E[:, None] - E[None, :]) * rt
         omega = E[None, :] - E[:, None]
         p = np.real(np.diag(rt))
-        for i in range(len(SZ)):
+        zs = model.channel_matrix_elements(inst, V)
+        for i in range(len(zs)):
             gam = model.gamma_ohmic(omega, inst.eta, WC[i], inst.T)
             np.fill_diagonal(gam, g0)
-            z = V.T @ (SZ[i][:, None] * V)
+            z = zs[i]
             R = gam * z * z                      # R[a, b]: rate b -> a (diag: g0 z_bb^2)
             zd = np.diag(z)
             # pair channels a != b: A = sqrt(R_ab)|a><b|

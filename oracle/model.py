@@ -172,6 +172,13 @@ def bath_channels(inst):
     sz = np.stack([sz_diag(i, n) for i in range(n)])
     terms = getattr(inst, "bath_terms", None)
     C = getattr(inst, "bath_corr", None)
+    cp = getattr(inst, "coupling", None)
+    if cp is not None:
+        if C is not None or terms is not None:
+            raise ValueError("give one of coupling, bath correlation or bath terms")
+        cz = np.asarray(cp[0], dtype=np.float64)
+        wc = np.full(len(cz), float(inst.omega_c)) if cp[2] is None else np.asarray(cp[2], dtype=np.float64)
+        return cz @ sz, wc
     if terms is not None:
         if C is not None:
             raise ValueError("give either a constant correlation or bath terms")
@@ -185,6 +192,35 @@ def bath_channels(inst):
         return sz, np.full(n, float(inst.omega_c))
     L = np.linalg.cholesky(np.asarray(C, dtype=np.float64))
     return L.T @ sz, np.full(n, float(inst.omega_c))
+
+
+def channel_sx(inst):
+    """sx coefficients of the channels' coupling operators, [n_channels, n_qubits], or None
+    when every channel couples through sz only.  A coupling (cz, cx, omega_c) gives channel
+    k the operator sum_a (cz[k, a] sz_a + cx[k, a] sx_a) (Sec. II: the system part of the
+    system-bath coupling; real, so every matrix element in the real eigenbasis is real)."""
+    cp = getattr(inst, "coupling", None)
+    if cp is None or cp[1] is None:
+        return None
+    cx = np.asarray(cp[1], dtype=np.float64)
+    return None if not np.any(cx) else cx
+
+
+def channel_matrix_elements(inst, V: np.ndarray) -> np.ndarray:
+    """z[k] = V^T O_k V for each channel operator O_k (bath_channels' diagonal part plus
+    channel_sx's sx part, sx_a V permuting the rows x -> x ^ 2^a), [n_channels, n, n]."""
+    w, _ = bath_channels(inst)
+    cx = channel_sx(inst)
+    x = np.arange(V.shape[0])
+    z = np.empty((len(w), V.shape[1], V.shape[1]))
+    for k in range(len(w)):
+        OV = w[k][:, None] * V
+        if cx is not None:
+            for a in range(inst.n_qubits):
+                if cx[k, a] != 0.0:
+                    OV = OV + cx[k, a] * V[x ^ (1 << a)]
+        z[k] = V.T @ OV
+    return z
 
 
 def channel_weights(inst) -> np.ndarray:

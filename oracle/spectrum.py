@@ -164,11 +164,9 @@ def polar(M: np.ndarray, tau: float = 1e-4):
 
 def grid_tables(inst, E: np.ndarray, V: np.ndarray, dt: float):
     n = len(E)
-    w, wc = model.bath_channels(inst)                    # [channel, x], [channel]
-    nch = len(w)
-    z = np.empty((nch, n, n))
-    for i in range(nch):
-        z[i] = V.T @ (w[i][:, None] * V)
+    wc = model.bath_channels(inst)[1]                    # cutoff of each channel
+    z = model.channel_matrix_elements(inst, V)           # [channel, a, b]
+    nch = len(z)
     omega = E[None, :] - E[:, None]                      # omega[a, b] = E_b - E_a
     R = np.empty((nch, n, n))
     for i in range(nch):

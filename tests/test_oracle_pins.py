@@ -4,6 +4,7 @@ Each test names the passage or property it checks.  None of them retypes the
 oracle's formula: they compare with closed forms, symmetries, brute-force
 constructions, independent library routines or statistical laws.
 """
+import dataclasses
 import math
 
 import numpy as np
@@ -649,6 +650,57 @@ def test_trajectory_average_matches_ame_frequency_dependent_bath():
     sigma = np.maximum(se, np.sqrt(np.clip(P * (1 - P), 0, None) / K))
     assert P.min() < 0.9 and res.kind_totals.sum() > K
     assert np.all(np.abs(m - P) <= 3 * sigma + 1e-4)
+
+
+@pytest.mark.parametrize("cz,cx", [(0.0, 1.0), (0.6, 0.8)])
+def test_two_level_sx_coupling_closed_form(cz, cx):
+    """Fixed H = -A sx coupled through cz sz + cx sx: the sx part commutes with H, so it
+    only dephases (omega = 0 operator sqrt(gamma(0)) cx diag(1, -1) in the eigenbasis,
+    coherence decay 2 cx^2 gamma(0)), and the sz part relaxes the populations at
+    kappa = cz^2 (gamma(2A) + gamma(-2A)) towards Peq = 1/(1+e^{2 beta A})."""
+    A = 0.3
+    inst = W.two_level_fixed(A=A, t_f=400.0, n_grid=81, eta=2e-3, coupling=([[cz]], [[cx]], None))
+    P0 = ame.split_step(spectrum.table_stream(inst), inst)
+    t = np.linspace(0, inst.t_f, inst.n_grid)
+    gp = model.gamma_ohmic(2 * A, inst.eta, inst.omega_c, inst.T)
+    gm = model.gamma_ohmic(-2 * A, inst.eta, inst.omega_c, inst.T)
+    g0 = float(model.gamma_ohmic(0.0, inst.eta, inst.omega_c, inst.T))
+    kappa, peq = cz ** 2 * (gp + gm), 1.0 / (1.0 + np.exp(2 * A / inst.T))
+    np.testing.assert_allclose(1.0 - P0, peq * (1.0 - np.exp(-kappa * t)), atol=1e-12)
+    T = spectrum.all_tables(inst)[3]
+    r0 = np.array([[0.7, 0.3 - 0.2j], [0.3 + 0.2j, 0.3]])
+    dt = 5.0
+    got = ame.step_map(r0, T, inst, dt)
+    if cz == 0.0:   # populations frozen, coherence: phase and exp(-2 cx^2 gamma(0) dt)
+        np.testing.assert_allclose(np.diag(got).real, np.diag(r0).real, atol=1e-15)
+        want = r0[0, 1] * np.exp(-1j * (T.E[0] - T.E[1]) * dt) * np.exp(-2.0 * cx ** 2 * g0 * dt)
+        np.testing.assert_allclose(got[0, 1], want, rtol=1e-13)
+
+
+def test_mixed_coupling_split_step_equals_lindblad_form():
+    """Channels with operators sum_a (cz sz_a + cx sx_a): the split-step map built from the
+    tables (sx applied as a row permutation) equals expm of the Lindblad form whose
+    operators come from dense Kronecker-product Pauli matrices in the eigenbasis."""
+    cz = np.array([[0.7, 0.0], [0.0, 0.0], [-0.4, 1.0]])
+    cx = np.array([[0.0, 0.5], [1.0, 0.0], [0.3, 0.0]])
+    wc = np.array([8.0 * math.pi, 4.0, 8.0 * math.pi])
+    inst = W.ring_instance(2, 3, t_f=40.0, eta=3e-3, coupling=(cz, cx, wc))
+    tabs = spectrum.all_tables(inst, n_grid=6, keep_V=True)
+    assert tabs[1].R.shape[0] == 3
+    for T in tabs[1:4]:
+        ops = [sum(cz[k, a] * model.pauli_on(model.SZ, a, 2) + cx[k, a] * model.pauli_on(model.SX, a, 2)
+                   for a in range(2)) for k in range(3)]
+        zk = np.stack([T.V.T @ O @ T.V for O in ops])
+        T2 = dataclasses.replace(T, z=zk)
+        dt = 3.7
+        rng = np.random.default_rng(T.g)
+        X = rng.normal(size=(4, 4)) + 1j * rng.normal(size=(4, 4))
+        r0 = X @ X.conj().T
+        r0 /= np.trace(r0)
+        got = ame.step_map(r0, T, inst, dt)
+        Ls = ame.liouvillian(T2, inst)
+        want = (sla.expm(Ls * dt) @ r0.reshape(-1, order="F")).reshape(4, 4, order="F")
+        np.testing.assert_allclose(got, want, atol=1e-13)
 
 
 def test_fixed_step_two_level_follows_the_discrete_chain():

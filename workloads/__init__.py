@@ -53,6 +53,9 @@ class Instance:
                                              # (gamma_ab(w) = C_ab gamma(w)); None = independent
     bath_terms: Optional[tuple] = None       # ((C_m, omega_c_m), ...): gamma_ab(w) =
                                              # sum_m C_m[a, b] gamma(w; omega_c_m), C_m PSD
+    coupling: Optional[tuple] = None         # (cz, cx, omega_c): channel k couples through
+                                             # sum_a cz[k][a] sz_a + cx[k][a] sx_a with an
+                                             # independent bath (cutoff omega_c[k]; None = omega_c)
     n_grid: int = 1001            # s-grid points (n_grid - 1 steps)
     n_levels: int = 0             # retained levels; 0 = full spectrum
     n_traj: int = 1000
