@@ -231,8 +231,26 @@ AQT_API aqt_status aqt_set_bath_correlation(aqt_ctx* ctx, const double* C);
  * outnumber the padded level count. */
 AQT_API aqt_status aqt_set_bath_terms(aqt_ctx* ctx, int n_terms, const double* C, const double* omega_c);
 
+/* General coupling operators (Sec. II: the system operators A_a of the system-bath
+ * coupling, here any real combination of single-qubit sz and sx): channel k couples
+ * through O_k = sum_a (cz[k][a] sz_a + cx[k][a] sx_a) to its own bath (independent of
+ * the other channels) with the Ohmic rate gamma(w; omega_c[k]) (omega_c NULL: the
+ * bath's cutoff for every channel).  cz, cx: host [n_channels][n_qubits] row-major,
+ * either may be NULL (zero); omega_c: host [n_channels] or NULL.  Matrix elements
+ * <a|O_k|b> in the real eigenbasis are real, so tables and kernels are those of the
+ * sz channels; jump records' "qubit" is the channel k.  n_channels = 0 restores the
+ * default (sz of each qubit).  Replaces aqt_set_bath_correlation / aqt_set_bath_terms
+ * settings and vice versa; applies from the next aqt_precompute.  The Lamb shift needs
+ * omega_c NULL; aqt_grad_pgs needs cx zero, omega_c NULL and n_channels = n_qubits.
+ * AQT_ESTATE before aqt_set_hamiltonian; AQT_EINVAL for n_channels outside [0, 64],
+ * non-finite coefficients, a channel whose operator is zero, cz and cx both NULL or a
+ * cutoff <= 0. */
+AQT_API aqt_status aqt_set_coupling(aqt_ctx* ctx, int n_channels, const double* cz, const double* cx,
+                                    const double* omega_c);
+
 /* Jump channels of the loaded tables (before any, of the current bath settings):
- * n_qubits for independent or constant-correlation baths. */
+ * n_qubits for independent or constant-correlation baths; the kept factor columns of
+ * bath terms; n_channels of aqt_set_coupling. */
 AQT_API aqt_status aqt_get_channel_count(aqt_ctx* ctx, int32_t* n_channels);
 
 /* ---- Lamb shift ----------------------------------------------------------------------

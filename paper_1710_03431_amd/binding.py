@@ -23,7 +23,8 @@ KIND_NAMES = ("relax", "excite", "dephase")
 EXPORTED = ("aqt_create", "aqt_destroy", "aqt_last_error", "aqt_version", "aqt_set_hamiltonian",
             "aqt_set_schedule", "aqt_set_bath", "aqt_precompute", "aqt_precompute_ex", "aqt_set_tables", "aqt_get_tables",
             "aqt_get_dims", "aqt_run", "aqt_grad_pgs", "aqt_set_lamb_shift", "aqt_get_lamb_shift",
-            "aqt_set_bath_correlation", "aqt_set_bath_terms", "aqt_get_channel_count", "aqt_run_fixed_step",
+            "aqt_set_bath_correlation", "aqt_set_bath_terms", "aqt_set_coupling", "aqt_get_channel_count",
+            "aqt_run_fixed_step",
             "aqt_batch_create", "aqt_batch_launch", "aqt_batch_tiles",
             "aqt_batch_last_error", "aqt_batch_destroy")
 BATCH_GRAPH, BATCH_AUTOTUNE = 1, 2
@@ -96,6 +97,7 @@ def load_library(path: str = LIB_PATH):
     lib.aqt_set_lamb_shift.argtypes = [ctx, C.c_int]
     lib.aqt_set_bath_correlation.argtypes = [ctx, dp]
     lib.aqt_set_bath_terms.argtypes = [ctx, C.c_int, dp, dp]
+    lib.aqt_set_coupling.argtypes = [ctx, C.c_int, dp, dp, dp]
     lib.aqt_get_channel_count.argtypes = [ctx, ip]
     lib.aqt_run_fixed_step.argtypes = [ctx, C.POINTER(RunParams), C.c_int, C.POINTER(Outputs)]
     lib.aqt_get_lamb_shift.argtypes = [ctx, dp]
@@ -193,6 +195,19 @@ class Engine:
         wc = _f64(np.array([float(w) for _, w in terms]))
         self._check(self.lib.aqt_set_bath_terms(self.ctx, len(terms), _dptr(Cs), _dptr(wc)))
 
+    def set_coupling(self, cz=None, cx=None, omega_c=None):
+        """Channel k couples through sum_a (cz[k][a] sz_a + cx[k][a] sx_a) with cutoff omega_c[k]
+        (None: the bath's); cz and cx [n_channels, n_qubits]; both None: sz of each qubit."""
+        if cz is None and cx is None:
+            self._check(self.lib.aqt_set_coupling(self.ctx, 0, None, None, None))
+            return
+        z = None if cz is None else _f64(np.atleast_2d(cz))
+        x = None if cx is None else _f64(np.atleast_2d(cx))
+        nch = (z if z is not None else x).shape[0]
+        w = None if omega_c is None else _f64(np.asarray(omega_c, dtype=np.float64).reshape(nch))
+        self._check(self.lib.aqt_set_coupling(self.ctx, nch, None if z is None else _dptr(z),
+                                              None if x is None else _dptr(x), None if w is None else _dptr(w)))
+
     def channel_count(self) -> int:
         v = C.c_int32()
         self._check(self.lib.aqt_get_channel_count(self.ctx, C.byref(v)))
@@ -214,6 +229,8 @@ class Engine:
         self.set_bath_correlation(getattr(inst, "bath_corr", None))
         if getattr(inst, "bath_terms", None) is not None:
             self.set_bath_terms(inst.bath_terms)
+        if getattr(inst, "coupling", None) is not None:
+            self.set_coupling(*inst.coupling)
         self.set_lamb_shift(getattr(inst, "lamb_shift", False))
 
     def precompute(self, n_grid: int, n_levels: int, deg_tol: float = 1e-8, method: str = "auto"):

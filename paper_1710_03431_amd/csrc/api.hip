@@ -108,6 +108,7 @@ aqt_status aqt_set_hamiltonian(aqt_ctx* ctx, int n_qubits, const double* h, cons
   if (ctx->nq != n_qubits) {   // bath correlations are per qubit count
     ctx->chan.clear();
     ctx->chan_wc.clear();
+    ctx->chan_x.clear();
   }
   ctx->nq = n_qubits;
   ctx->h.assign(h, h + n_qubits);
@@ -294,6 +295,7 @@ aqt_status aqt_set_bath_correlation(aqt_ctx* ctx, const double* C) {
   if (!C) {
     ctx->chan.clear();
     ctx->chan_wc.clear();
+    ctx->chan_x.clear();
   } else {
     double scale = 0.0;
     for (int i = 0; i < nq * nq; ++i) {
@@ -320,6 +322,7 @@ aqt_status aqt_set_bath_correlation(aqt_ctx* ctx, const double* C) {
     for (int k = 0; k < nq; ++k)
       for (int a = 0; a < nq; ++a) ctx->chan[static_cast<size_t>(k) * nq + a] = L[a * nq + k];
     ctx->chan_wc.assign(nq, 0.0);
+    ctx->chan_x.clear();
   }
   ctx->have_tables = false;
   ctx->have_grad = false;
@@ -333,6 +336,7 @@ aqt_status aqt_set_bath_terms(aqt_ctx* ctx, int n_terms, const double* C, const 
   if (n_terms == 0) {
     ctx->chan.clear();
     ctx->chan_wc.clear();
+    ctx->chan_x.clear();
     ctx->have_tables = false;
     ctx->have_grad = false;
     return AQT_OK;
@@ -383,6 +387,55 @@ aqt_status aqt_set_bath_terms(aqt_ctx* ctx, int n_terms, const double* C, const 
   if (wc.size() > 64) return ctx->fail(AQT_EINVAL, "more than 64 jump channels");
   ctx->chan = chan;
   ctx->chan_wc = wc;
+  ctx->chan_x.clear();
+  ctx->have_tables = false;
+  ctx->have_grad = false;
+  return AQT_OK;
+}
+
+aqt_status aqt_set_coupling(aqt_ctx* ctx, int n_channels, const double* cz, const double* cx,
+                            const double* omega_c) {
+  if (!ctx) return AQT_EINVAL;
+  if (!ctx->have_h) return ctx->fail(AQT_ESTATE, "set_hamiltonian must come first");
+  const int nq = ctx->nq;
+  if (n_channels == 0) {
+    ctx->chan.clear();
+    ctx->chan_wc.clear();
+    ctx->chan_x.clear();
+    ctx->have_tables = false;
+    ctx->have_grad = false;
+    return AQT_OK;
+  }
+  if (n_channels < 0 || n_channels > 64) return ctx->fail(AQT_EINVAL, "n_channels must be in [0, 64]");
+  if (!cz && !cx) return ctx->fail(AQT_EINVAL, "cz and cx cannot both be NULL");
+  const size_t cnt = static_cast<size_t>(n_channels) * nq;
+  std::vector<double> z(cnt, 0.0), x;
+  if (cz) z.assign(cz, cz + cnt);
+  if (cx) x.assign(cx, cx + cnt);
+  for (double v : z)
+    if (!std::isfinite(v)) return ctx->fail(AQT_EINVAL, "coupling coefficients must be finite");
+  bool any_x = false;
+  for (double v : x) {
+    if (!std::isfinite(v)) return ctx->fail(AQT_EINVAL, "coupling coefficients must be finite");
+    any_x = any_x || v != 0.0;
+  }
+  for (int k = 0; k < n_channels; ++k) {
+    bool nz = false;
+    for (int a = 0; a < nq; ++a)
+      nz = nz || z[static_cast<size_t>(k) * nq + a] != 0.0 || (!x.empty() && x[static_cast<size_t>(k) * nq + a] != 0.0);
+    if (!nz) return ctx->fail(AQT_EINVAL, "a channel has a zero coupling operator");
+  }
+  std::vector<double> wc(n_channels, 0.0);
+  if (omega_c)
+    for (int k = 0; k < n_channels; ++k) {
+      if (!(omega_c[k] > 0.0) || !std::isfinite(omega_c[k]))
+        return ctx->fail(AQT_EINVAL, "channel cutoffs must be positive and finite");
+      wc[k] = omega_c[k];
+    }
+  ctx->chan = z;
+  ctx->chan_wc = wc;
+  if (any_x) ctx->chan_x = x;
+  else ctx->chan_x.clear();
   ctx->have_tables = false;
   ctx->have_grad = false;
   return AQT_OK;
@@ -418,8 +471,8 @@ aqt_status aqt_grad_pgs(aqt_ctx* ctx, const aqt_run_params* p, double* value, do
   if (!p) return ctx->fail(AQT_EINVAL, "params are required");
   if (!ctx->have_tables) return ctx->fail(AQT_ESTATE, "precompute must come first");
   if (ctx->lamb) return ctx->fail(AQT_EINVAL, "the gradient does not include the Lamb shift's derivative");
-  if (!ctx->single_spectrum())
-    return ctx->fail(AQT_EINVAL, "the gradient is built for one bath spectral density (no bath terms)");
+  if (!ctx->single_spectrum() || ctx->nch() != ctx->nq || !ctx->chan_x.empty())
+    return ctx->fail(AQT_EINVAL, "the gradient is built for sz couplings with one bath spectral density");
   if (!ctx->last_from_solver)
     return ctx->fail(AQT_ESTATE, "the gradient needs tables from aqt_precompute (eigenvectors), not aqt_set_tables");
   if (ctx->n != (1 << ctx->nq))

@@ -29,6 +29,7 @@ struct aqt_ctx {
   // (chan_wc[k], 0: the bath's omega_c); empty: sz of each qubit (independent baths)
   std::vector<double> chan;      // [nch][nq]
   std::vector<double> chan_wc;   // [nch]
+  std::vector<double> chan_x;    // [nch][nq] sx coefficients of the channel operators (empty: none)
   int nch() const { return chan.empty() ? nq : static_cast<int>(chan.size() / nq); }
   bool single_spectrum() const {
     for (double w : chan_wc)

@@ -323,7 +323,8 @@ __global__ __launch_bounds__(kEigThreads) void k_canon(const double* __restrict_
 // C[b][i][j] (+)= sum_x w(x) A[i][x] B[j][x] for rows i < ra, j < rb: 64x64 tile
 // per workgroup, x staged through LDS in chunks of 32, 16x16x4 FP64 MFMAs.
 // wmode 0: w = 1; 1: w = sz of qubit (bz % nq) (operands of batch bz / nq); 2: w = x;
-// 3: w = wvec[x]; 4: w = wvec[(bz % nq) K + x] (channel weights; operands of batch bz / nq).  bdiv > 1: operand B of batch bz is B + sB * (bz / bdiv).
+// 3: w = wvec[x]; 4: w = wvec[(bz % nq) K + x] (channel weights; operands of batch bz / nq).  bdiv > 1: operand B of batch bz is B + sB * (bz / bdiv);
+// adiv > 1: operand A of batch bz is A + sA * (bz / adiv).
 // sub_eye: subtract the identity (stores O - I).
 struct GemmArgs {
   const double* A;
@@ -336,6 +337,7 @@ struct GemmArgs {
   int kspan = 0;    // span of kspan and writes a compact [ra][rb] partial at C + sC * blockIdx.z
   const double* wvec = nullptr;
   int bdiv = 1;
+  int adiv = 1;
 };
 
 __global__ __launch_bounds__(256) void k_gemm_f64(GemmArgs p) {
@@ -348,7 +350,7 @@ __global__ __launch_bounds__(256) void k_gemm_f64(GemmArgs p) {
   const int xend = (p.ksplit > 1) ? min(p.K, xbeg + p.kspan) : p.K;
   const int opb = (p.wmode == 1 || p.wmode == 4) ? bz / p.nq : bz;
   const int qubit = (p.wmode == 1 || p.wmode == 4) ? bz % p.nq : 0;
-  const double* A = p.A + p.sA * opb;
+  const double* A = p.A + p.sA * ((p.adiv > 1) ? bz / p.adiv : opb);
   const double* B = p.B + p.sB * ((p.bdiv > 1) ? bz / p.bdiv : opb);
   double* C = p.C + p.sC * blockIdx.z;
   const int i0 = blockIdx.y * 64, j0 = blockIdx.x * 64;
@@ -727,6 +729,27 @@ __global__ void k_lamb_shift(const double* __restrict__ z, const double* __restr
 // de_a = <a|H'|a>, dv_b = sum_a v_a X_ab with X_ab = <a|H'|b> / (e_b - e_a) for
 // levels in different clusters and 0 inside a cluster (the canonical in-cluster
 // basis is held fixed), so X is antisymmetric and dz_i = z_i X - X z_i.
+
+// Y[c][k][b][x] = (O_k v_b)[x] for channel operators O_k = diag(wz_k) + sum_a cx[k][a] sx_a
+// (sx_a v)[x] = v[x ^ 2^a], for the n rows of cnt grid points.
+__global__ void k_channel_rows(const double* __restrict__ V, int64_t vstride, int N, int nq, int n, int cnt,
+                               int nch, const double* __restrict__ wz, const double* __restrict__ cx,
+                               double* __restrict__ Y) {
+  const int64_t per = static_cast<int64_t>(n) * N;
+  const int64_t idx = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (idx >= per * nch * cnt) return;
+  const int ck = static_cast<int>(idx / per);
+  const int c = ck / nch, k = ck - c * nch;
+  const int64_t r = idx - ck * per;
+  const int b = static_cast<int>(r / N), x = static_cast<int>(r - static_cast<int64_t>(b) * N);
+  const double* v = V + c * vstride + static_cast<int64_t>(b) * N;
+  double acc = wz[static_cast<size_t>(k) * N + x] * v[x];
+  for (int a = 0; a < nq; ++a) {
+    const double w = cx[k * nq + a];
+    if (w != 0.0) acc += w * v[x ^ (1 << a)];
+  }
+  Y[idx] = acc;
+}
 
 // W[c][b][x] = (H_X v_b)[x] = -sum_i v_b[x ^ 2^i] for the n rows of cnt grid points.
 __global__ void k_hx_rows(const double* __restrict__ V, int64_t vstride, int N, int nq, int n, int cnt,
@@ -1205,8 +1228,8 @@ aqt_status precompute_tables(aqt_ctx* ctx, int M, int n, double tol, int method,
   ctx->have_grad = false;
   ctx->gpk_prec = -1;
   if (grad && n != N) return ctx->fail(AQT_EINVAL, "gradient tables need the full spectrum (n_levels = 2^n_qubits)");
-  if (grad && !ctx->single_spectrum())
-    return ctx->fail(AQT_EINVAL, "the gradient is built for one bath spectral density (no bath terms)");
+  if (grad && (!ctx->single_spectrum() || nch != nq || !ctx->chan_x.empty()))
+    return ctx->fail(AQT_EINVAL, "the gradient is built for sz couplings with one bath spectral density");
   if (ctx->lamb && !ctx->single_spectrum())
     return ctx->fail(AQT_EINVAL, "the Lamb shift is built for one bath spectral density (no bath terms)");
   const bool iterative = (method == AQT_EIG_ITERATIVE) || (method == AQT_EIG_AUTO && N > kEigMaxN);
@@ -1291,6 +1314,13 @@ aqt_status precompute_tables(aqt_ctx* ctx, int M, int n, double tol, int method,
     if (chw.reserve(w.size() * 8)) return ctx->fail(AQT_ENOMEM, "channel weight allocation failed");
     AQT_HIP(ctx, hipMemcpyAsync(chw.p, w.data(), w.size() * 8, hipMemcpyHostToDevice, st));
   }
+  // sx parts of the channel operators (general couplings): applied as row permutations
+  const bool sx = !ctx->chan_x.empty();
+  DevBuf cxv;
+  if (sx) {
+    if (cxv.reserve(ctx->chan_x.size() * 8)) return ctx->fail(AQT_ENOMEM, "channel coupling allocation failed");
+    AQT_HIP(ctx, hipMemcpyAsync(cxv.p, ctx->chan_x.data(), ctx->chan_x.size() * 8, hipMemcpyHostToDevice, st));
+  }
   std::vector<double> wch(nch, ctx->omega_c);
   for (int k = 0; k < nch && k < static_cast<int>(ctx->chan_wc.size()); ++k)
     if (ctx->chan_wc[k] != 0.0) wch[k] = ctx->chan_wc[k];
@@ -1343,6 +1373,7 @@ aqt_status precompute_tables(aqt_ctx* ctx, int M, int n, double tol, int method,
                           + static_cast<size_t>(ncols) * N            // canonical V
                           + 2 * static_cast<size_t>(ncols) * ncols + static_cast<size_t>(ncols) * N  // canon ws
                           + static_cast<size_t>(nch) * n * n          // z
+                          + (sx ? static_cast<size_t>(nch) * n * N : 0)   // channel operators on V
                           + 9 * static_cast<size_t>(n) * n            // polar ws
                           + N                                         // Eraw
                           + (grad ? static_cast<size_t>(n) * N + 2 * static_cast<size_t>(n) * n +
@@ -1350,6 +1381,7 @@ aqt_status precompute_tables(aqt_ctx* ctx, int M, int n, double tol, int method,
                                   : 0);                               // H_X rows, V H' V^T, z X^T
   const size_t budget = size_t(24) << 30;   // of 288 GB HBM: all grid points of a 10-qubit instance in one chunk
   int Gc = static_cast<int>(std::max<size_t>(1, std::min<size_t>(M, budget / (per_grid * 8))));
+  Gc = std::max(1, std::min(Gc, 65535 / std::max(nch, 2 * nq)));   // batched products: grid z <= 65535
   DevBuf H, Z, Vc, Vprev, cws, zws, pws, Eraw, perm, status;
   if ((!iterative && (H.reserve(static_cast<size_t>(Gc) * N * N * 8) || Z.reserve(static_cast<size_t>(Gc) * N * N * 8))) ||
       Vc.reserve(static_cast<size_t>(Gc) * ncols * N * 8) || Vprev.reserve(static_cast<size_t>(ncols) * N * 8) ||
@@ -1357,6 +1389,9 @@ aqt_status precompute_tables(aqt_ctx* ctx, int M, int n, double tol, int method,
       zws.reserve(static_cast<size_t>(Gc) * nch * n * n * 8) || pws.reserve(static_cast<size_t>(Gc) * 9 * n * n * 8) ||
       Eraw.reserve(static_cast<size_t>(Gc) * N * 8) || perm.reserve(static_cast<size_t>(Gc) * N * 4) ||
       status.reserve(static_cast<size_t>(Gc) * 4))
+    return ctx->fail(AQT_ENOMEM, "precompute workspace allocation failed");
+  DevBuf Yc;
+  if (sx && Yc.reserve(static_cast<size_t>(Gc) * nch * n * N * 8))
     return ctx->fail(AQT_ENOMEM, "precompute workspace allocation failed");
   DevBuf Wx, Hd, Qz;
   if (grad) {
@@ -1497,11 +1532,25 @@ aqt_status precompute_tables(aqt_ctx* ctx, int M, int n, double tol, int method,
     const int zg0 = std::max(g0, 1), zcnt = g0 + cnt - zg0;
     if (zcnt > 0) {
       const int off = zg0 - g0;
-      GemmArgs ga{Vc.as<double>() + off * Vstride, Vc.as<double>() + off * Vstride, zws.as<double>(),
-                  static_cast<int64_t>(Vstride), static_cast<int64_t>(Vstride), static_cast<int64_t>(n) * n,
-                  n, n, N, N, N, n, chw.p ? 4 : 1, nch, 0};
-      ga.wvec = chw.as<double>();
-      aqt_status s = launch_gemm(ctx, ga, zcnt * nch);
+      aqt_status s = AQT_OK;
+      if (sx) {
+        // z_k = V^T (O_k V): the operands O_k V, then one product per (grid point, channel)
+        hipLaunchKernelGGL(k_channel_rows, dim3(nblk(static_cast<int64_t>(zcnt) * nch * n * N)), dim3(256), 0, st,
+                           Vc.as<double>() + off * Vstride, static_cast<int64_t>(Vstride), N, nq, n, zcnt, nch,
+                           chw.as<double>(), cxv.as<double>(), Yc.as<double>());
+        AQT_HIP(ctx, hipGetLastError());
+        GemmArgs ga{Vc.as<double>() + off * Vstride, Yc.as<double>(), zws.as<double>(),
+                    static_cast<int64_t>(Vstride), static_cast<int64_t>(n) * N, static_cast<int64_t>(n) * n,
+                    n, n, N, N, N, n, 0, nch, 0};
+        ga.adiv = nch;
+        s = launch_gemm(ctx, ga, zcnt * nch);
+      } else {
+        GemmArgs ga{Vc.as<double>() + off * Vstride, Vc.as<double>() + off * Vstride, zws.as<double>(),
+                    static_cast<int64_t>(Vstride), static_cast<int64_t>(Vstride), static_cast<int64_t>(n) * n,
+                    n, n, N, N, N, n, chw.p ? 4 : 1, nch, 0};
+        ga.wvec = chw.as<double>();
+        s = launch_gemm(ctx, ga, zcnt * nch);
+      }
       if (s != AQT_OK) return s;
       hipLaunchKernelGGL(k_rates, dim3(nblk(static_cast<int64_t>(nch) * NP * NP * zcnt)), dim3(256), 0, st,
                          zws.as<double>(), ctx->E.as<double>(), n, NP, nch, zg0, zcnt, ctx->eta, wcv.as<double>(),
