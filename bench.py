@@ -1,7 +1,7 @@
 """Throughput of the GPU trajectory engine.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload a2a8|ring4|gadget16|batched|grad|fixed]
-                    [--lamb-shift] [--bath-corr RHO] [--bath-terms RHO]
+                    [--lamb-shift] [--bath-corr RHO] [--bath-terms RHO] [--zx-coupling]
                     [--cpu-traj 3072] [--cpu-grid 500] [--no-cpu]
 
 One bench step = one aqt_run: all trajectories of the workload through the whole
@@ -34,6 +34,8 @@ Workloads:
 --bath-terms RHO frequency-dependent correlations: local baths correlated as 0.5^|a - b|
             (cutoff 8 pi) plus a bath shared by all qubits with weight RHO and cutoff
             2 pi (one more jump channel) (a2a8, ring4)
+--zx-coupling every qubit couples through sz and through sx, each to its own bath
+            (2 n_qubits jump channels) (a2a8, ring4)
 """
 import argparse
 import json
@@ -60,6 +62,7 @@ def parse():
     ap.add_argument("--lamb-shift", action="store_true")
     ap.add_argument("--bath-corr", type=float, default=None)
     ap.add_argument("--bath-terms", type=float, default=None)
+    ap.add_argument("--zx-coupling", action="store_true")
     ap.add_argument("--substeps", type=int, default=4)
     ap.add_argument("--n-traj", type=int, default=0, help="override the workload's trajectory count")
     ap.add_argument("--cpu-traj", type=int, default=3072)
@@ -400,7 +403,12 @@ def main():
     if args.bath_terms is not None:
         import workloads as W
         inst = inst.with_(bath_terms=W.two_term_bath(inst.n_qubits, rho=args.bath_terms))
-    if args.lamb_shift or args.bath_corr is not None or args.bath_terms is not None:
+    if args.zx_coupling:
+        import numpy as np
+        q = inst.n_qubits
+        inst = inst.with_(coupling=(np.vstack([np.eye(q), np.zeros((q, q))]),
+                                    np.vstack([np.zeros((q, q)), np.eye(q)]), None))
+    if args.lamb_shift or args.bath_corr is not None or args.bath_terms is not None or args.zx_coupling:
         wl["golden"] = None   # the stored AME references are for independent baths without the Lamb shift
     K = inst.n_traj
     M = inst.n_grid
@@ -451,7 +459,8 @@ def main():
         "config": {"workload": wl["text"] + (", Lamb shift" if args.lamb_shift else "")
                    + (f", bath correlation {args.bath_corr}^|a-b|" if args.bath_corr is not None else "")
                    + (f", bath terms 0.5^|a-b| (cutoff 8 pi) + shared {args.bath_terms} (cutoff 2 pi)"
-                      if args.bath_terms is not None else ""),
+                      if args.bath_terms is not None else "")
+                   + (", sz and sx couplings (2 n_qubits channels)" if args.zx_coupling else ""),
                    "name": inst.name,
                    "n_traj": K, "n_levels": n, "n_grid": M, "precision": head_prec, "seed": inst.seed},
         "error_vs_fp64_ame": {"P_GS_final_ame": p_ame,
