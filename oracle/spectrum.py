@@ -208,6 +208,61 @@ def lamb_shift(inst, E: np.ndarray, z: np.ndarray) -> np.ndarray:
     return out
 
 
+def grid_points(inst, M: int):
+    """The instance's s-grid (None: equidistant), checked: M points from 0 to 1, increasing."""
+    sg = getattr(inst, "s_grid", None)
+    if sg is None:
+        return None
+    sg = np.asarray(sg, dtype=np.float64)
+    if len(sg) != M or sg[0] != 0.0 or sg[-1] != 1.0 or not np.all(np.diff(sg) > 0.0):
+        raise ValueError("s_grid must hold n_grid increasing points from 0 to 1")
+    return sg
+
+
+def step_bound(inst, s: np.ndarray, deg_tol: float = 1e-8) -> np.ndarray:
+    """The time-step bound of App. B (eq. B7) at the points s (full spectrum):
+    min{ |H_eff| / |dH_eff/dt|, 1 / |H_eff|, |lambda / (lambda^2 - dlambda/dt)| } with
+    |.| the operator norm.  H_eff = H - (i/2) sum A^dag A is diag(e - i Gamma / 2) in the
+    eigenbasis (the decay is diagonal there), so |H_eff| = max_b |e_b - i Gamma_b / 2|
+    and the lab-frame H_eff = V diag(e - i Gamma / 2) V^T; its time derivative is taken
+    by central differences in s (one-sided at the ends).  lambda, the jump rate, depends
+    on the trajectory's state; the bound uses its largest value, max_b Gamma_b."""
+    n = inst.dim
+    Hs, lam, nrm = [], [], []
+    for x in s:
+        E, V, _ = eigen(inst, float(x), n, deg_tol)
+        _, _, Gamma, _, _, _ = grid_tables(inst, E, V, 1.0)
+        h = E - 0.5j * Gamma
+        Hs.append((V * h[None, :]) @ V.T)
+        nrm.append(float(np.abs(h).max()))
+        lam.append(float(Gamma.max()))
+    Hs, lam, nrm = np.array(Hs), np.array(lam), np.array(nrm)
+    t = np.asarray(s, dtype=np.float64) * inst.t_f
+    dH = np.gradient(Hs, t, axis=0)
+    dlam = np.gradient(lam, t)
+    dHn = np.array([np.linalg.norm(m, 2) for m in dH])
+    with np.errstate(divide="ignore", invalid="ignore"):
+        b1 = np.where(dHn > 0.0, nrm / dHn, np.inf)
+        b2 = 1.0 / nrm
+        den = lam * lam - dlam
+        b3 = np.where(den != 0.0, np.abs(lam / den), np.inf)
+    return np.minimum(np.minimum(b1, b2), b3)
+
+
+def bound_grid(inst, n_grid: int, n_probe: int = 401, deg_tol: float = 1e-8) -> np.ndarray:
+    """An s-grid whose local step follows the App. B bound (eq. B7): the density of
+    grid points is 1 / bound(s), equidistributed -- s_g solves F(s_g) = g F(1) / (M - 1)
+    with F(s) = int_0^s ds' / bound(s'), the integral by the trapezoid rule on
+    n_probe equidistant points and the inverse by linear interpolation."""
+    sp = np.linspace(0.0, 1.0, n_probe)
+    rho = 1.0 / step_bound(inst, sp, deg_tol)
+    F = np.concatenate([[0.0], np.cumsum(0.5 * (rho[1:] + rho[:-1]) * np.diff(sp))])
+    target = np.linspace(0.0, F[-1], n_grid)
+    out = np.interp(target, F, sp)
+    out[0], out[-1] = 0.0, 1.0
+    return out
+
+
 def n_steps_dt(inst, n_grid: int):
     return n_grid - 1, inst.t_f / (n_grid - 1)
 
@@ -218,6 +273,7 @@ def table_stream(inst, n_grid: Optional[int] = None, n_levels: Optional[int] = N
     """Yield GridTables for g = 1..M-1 in order (or only those in `grids`, still in order)."""
     M = n_grid or inst.n_grid
     n = n_levels or inst.levels
+    sg = grid_points(inst, M)
     dt = inst.t_f / (M - 1)
     E0, V0, gs0 = eigen(inst, 0.0, max(n, 1), deg_tol)
     if gs0 != 1:
@@ -225,8 +281,11 @@ def table_stream(inst, n_grid: Optional[int] = None, n_levels: Optional[int] = N
     psi0 = V0[:, 0]
     Vprev = None
     for g in range(1, M):
-        s = g / (M - 1)
-        t0 = (g - 1) * dt
+        if sg is None:      # equidistant: s_g = g / (M - 1), steps of t_f / (M - 1)
+            s, s_prev, t0, dtg = g / (M - 1), (g - 1) / (M - 1), (g - 1) * dt, dt
+        else:
+            s, s_prev = float(sg[g]), float(sg[g - 1])
+            t0, dtg = inst.t_f * s_prev, inst.t_f * (s - s_prev)
         need_prev = grids is not None and (g + 1) in grids
         if grids is not None and g not in grids and not need_prev:
             Vprev = None
@@ -238,18 +297,18 @@ def table_stream(inst, n_grid: Optional[int] = None, n_levels: Optional[int] = N
             cinit, O = c / np.linalg.norm(c), None
         else:
             if Vprev is None:
-                _, Vp, _ = eigen(inst, (g - 1) / (M - 1), n, deg_tol)
+                _, Vp, _ = eigen(inst, s_prev, n, deg_tol)
             else:
                 Vp = Vprev
             O, S = polar(V.T @ Vp)
             leak = 1.0 - float(S.min()) ** 2
             cinit = None
-        z, R, Gamma, zdiag, d, shift = grid_tables(inst, E, V, dt)
+        z, R, Gamma, zdiag, d, shift = grid_tables(inst, E, V, dtg)
         Vprev = V
         if grids is None or g in grids:
             yield GridTables(g=g, s=s, E=E, gs=gs, O=O, cinit=cinit, z=z, R=R, Gamma=Gamma,
                              zdiag=zdiag, d=d, leak=leak, V=V if keep_V else None, shift=shift,
-                             dt=dt, t0=t0)
+                             dt=dtg, t0=t0)
 
 
 def all_tables(inst, **kw):

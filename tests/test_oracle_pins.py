@@ -703,6 +703,52 @@ def test_mixed_coupling_split_step_equals_lindblad_form():
         np.testing.assert_allclose(got, want, atol=1e-13)
 
 
+def test_step_bound_and_bound_grid_closed_form():
+    """One qubit, H = -A(s) sx with A = a0 (1 + s) and a vanishing bath: |H_eff| = A,
+    |dH/dt| = a0 / t_f, so the App. B bound is min(t_f (1 + s), 1 / A) = 1 / (a0 (1 + s));
+    equidistributing its inverse gives s_g + s_g^2 / 2 = 3 g / (2 (M - 1)),
+    s_g = -1 + sqrt(1 + 3 g / (M - 1))."""
+    a0, M = 1.0, 11
+    inst = W.two_level_fixed(A=a0, t_f=100.0, n_grid=M, eta=1e-10).with_(A_ctrl=np.array([a0, 2 * a0]))
+    sp = np.linspace(0.0, 1.0, 7)
+    np.testing.assert_allclose(spectrum.step_bound(inst, sp), 1.0 / (a0 * (1.0 + sp)), rtol=1e-12)
+    g = spectrum.bound_grid(inst, M, n_probe=2001)
+    np.testing.assert_allclose(g, -1.0 + np.sqrt(1.0 + 3.0 * np.arange(M) / (M - 1)), atol=1e-7)
+
+
+def test_bound_grid_of_a_frozen_hamiltonian_is_equidistant():
+    inst = W.ring_instance(3, 21, t_f=50.0, n_grid=9, eta=2e-3, A_ctrl=np.array([1.0, 1.0]),
+                           B_ctrl=np.array([1.5, 1.5]))
+    np.testing.assert_allclose(spectrum.bound_grid(inst, 9, n_probe=101), np.linspace(0.0, 1.0, 9), atol=1e-12)
+
+
+def test_explicit_equidistant_grid_matches_the_default():
+    inst = W.ring_instance(3, 8, t_f=1.5, eta=0.1, n_grid=21)
+    a = spectrum.all_tables(inst)
+    b = spectrum.all_tables(inst.with_(s_grid=np.linspace(0.0, 1.0, 21)))
+    for Ta, Tb in zip(a, b):
+        np.testing.assert_allclose(Tb.R, Ta.R, rtol=1e-11, atol=1e-13 * np.abs(Ta.R).max())
+        np.testing.assert_allclose(Tb.d, Ta.d, rtol=1e-11)
+        assert abs(Tb.t0 - Ta.t0) <= 1e-14 and abs(Tb.dt - Ta.dt) <= 1e-14
+
+
+def test_trajectory_average_matches_ame_on_the_bound_grid():
+    """Exact-mean parity does not depend on the grid: trajectories on the App. B grid
+    (steps of different lengths) average to the split-step AME on that grid."""
+    inst = W.ring_instance(3, 8, t_f=1.5, eta=0.1, n_grid=61)
+    sg = spectrum.bound_grid(inst, 61, n_probe=121)
+    steps = np.diff(sg)
+    assert steps.max() > 1.5 * steps.min()
+    inst = inst.with_(s_grid=sg)
+    tabs = spectrum.all_tables(inst)
+    P = ame.split_step(tabs, inst)
+    K = 2000
+    res = trajectories.run(tabs, inst, K, record=False)
+    m, se = trajectories.mean_and_stderr(res.pgs_sum, res.pgs_sumsq, K)
+    sigma = np.maximum(se, np.sqrt(np.clip(P * (1 - P), 0, None) / K))
+    assert np.all(np.abs(m - P) <= 3 * sigma + 1e-4)
+
+
 def test_fixed_step_two_level_follows_the_discrete_chain():
     """Fixed-step unraveling (App. B): a frozen two-level system stays in eigenstates, and
     per sub-step h it jumps 0 -> 1 with probability h W10 and 1 -> 0 with h W01, so its

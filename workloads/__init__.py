@@ -57,6 +57,8 @@ class Instance:
                                              # sum_a cz[k][a] sz_a + cx[k][a] sx_a with an
                                              # independent bath (cutoff omega_c[k]; None = omega_c)
     n_grid: int = 1001            # s-grid points (n_grid - 1 steps)
+    s_grid: Optional[np.ndarray] = None   # [n_grid] grid points 0 = s_0 < ... < s_{M-1} = 1;
+                                          # None = equidistant
     n_levels: int = 0             # retained levels; 0 = full spectrum
     n_traj: int = 1000
     seed: int = 0                 # trajectory-stream seed (Philox key word 0)
