@@ -231,6 +231,18 @@ AQT_API aqt_status aqt_set_bath_correlation(aqt_ctx* ctx, const double* C);
  * outnumber the padded level count. */
 AQT_API aqt_status aqt_set_bath_terms(aqt_ctx* ctx, int n_terms, const double* C, const double* omega_c);
 
+/* Grid points of the anneal (Sec. IV; App. B eq. B7 bounds the step and suggests
+ * adapting it to the bound's instantaneous value): s[n_grid] host, s[0] = 0 <
+ * s[1] < ... < s[n_grid-1] = 1.  Grid point g sits at t = t_f s_g; the step into it
+ * has length t_f (s_g - s_{g-1}) and starts at t_f s_{g-1} (jump record times, the
+ * no-jump propagator and the gradient's hat-function weights of the controls use
+ * them).  n_grid = 0 or s = NULL restores equidistant points, s_g = g / (n_grid - 1)
+ * with steps t_f / (n_grid - 1) starting at (g - 1) t_f / (n_grid - 1).  Applies from
+ * the next aqt_precompute or aqt_set_tables, whose n_grid must then equal this one
+ * (AQT_EINVAL otherwise); loaded tables are invalidated.  AQT_EINVAL for fewer than
+ * two points, ends other than 0 and 1, or points that do not increase. */
+AQT_API aqt_status aqt_set_grid(aqt_ctx* ctx, int n_grid, const double* s);
+
 /* General coupling operators (Sec. II: the system operators A_a of the system-bath
  * coupling, here any real combination of single-qubit sz and sx): channel k couples
  * through O_k = sum_a (cz[k][a] sz_a + cx[k][a] sx_a) to its own bath (independent of

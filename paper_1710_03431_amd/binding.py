@@ -24,7 +24,7 @@ EXPORTED = ("aqt_create", "aqt_destroy", "aqt_last_error", "aqt_version", "aqt_s
             "aqt_set_schedule", "aqt_set_bath", "aqt_precompute", "aqt_precompute_ex", "aqt_set_tables", "aqt_get_tables",
             "aqt_get_dims", "aqt_run", "aqt_grad_pgs", "aqt_set_lamb_shift", "aqt_get_lamb_shift",
             "aqt_set_bath_correlation", "aqt_set_bath_terms", "aqt_set_coupling", "aqt_get_channel_count",
-            "aqt_run_fixed_step",
+            "aqt_set_grid", "aqt_run_fixed_step",
             "aqt_batch_create", "aqt_batch_launch", "aqt_batch_tiles",
             "aqt_batch_last_error", "aqt_batch_destroy")
 BATCH_GRAPH, BATCH_AUTOTUNE = 1, 2
@@ -98,6 +98,7 @@ def load_library(path: str = LIB_PATH):
     lib.aqt_set_bath_correlation.argtypes = [ctx, dp]
     lib.aqt_set_bath_terms.argtypes = [ctx, C.c_int, dp, dp]
     lib.aqt_set_coupling.argtypes = [ctx, C.c_int, dp, dp, dp]
+    lib.aqt_set_grid.argtypes = [ctx, C.c_int, dp]
     lib.aqt_get_channel_count.argtypes = [ctx, ip]
     lib.aqt_run_fixed_step.argtypes = [ctx, C.POINTER(RunParams), C.c_int, C.POINTER(Outputs)]
     lib.aqt_get_lamb_shift.argtypes = [ctx, dp]
@@ -208,6 +209,14 @@ class Engine:
         self._check(self.lib.aqt_set_coupling(self.ctx, nch, None if z is None else _dptr(z),
                                               None if x is None else _dptr(x), None if w is None else _dptr(w)))
 
+    def set_grid(self, s=None):
+        """Grid points s_0 = 0 < ... < s_{M-1} = 1 of the anneal (None: equidistant)."""
+        if s is None:
+            self._check(self.lib.aqt_set_grid(self.ctx, 0, None))
+            return
+        s = _f64(s)
+        self._check(self.lib.aqt_set_grid(self.ctx, len(s), _dptr(s)))
+
     def channel_count(self) -> int:
         v = C.c_int32()
         self._check(self.lib.aqt_get_channel_count(self.ctx, C.byref(v)))
@@ -231,6 +240,7 @@ class Engine:
             self.set_bath_terms(inst.bath_terms)
         if getattr(inst, "coupling", None) is not None:
             self.set_coupling(*inst.coupling)
+        self.set_grid(getattr(inst, "s_grid", None))
         self.set_lamb_shift(getattr(inst, "lamb_shift", False))
 
     def precompute(self, n_grid: int, n_levels: int, deg_tol: float = 1e-8, method: str = "auto"):

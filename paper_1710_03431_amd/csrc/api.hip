@@ -181,6 +181,8 @@ aqt_status aqt_set_tables(aqt_ctx* ctx, int n_grid, int n_levels, const double* 
   if (!ctx->have_h || !ctx->have_sched)
     return ctx->fail(AQT_ESTATE, "set_hamiltonian and set_schedule must come first");
   if (n_grid < 2 || n_levels < 1 || n_levels > 256) return ctx->fail(AQT_EINVAL, "bad n_grid or n_levels");
+  if (!ctx->sgrid.empty() && static_cast<int>(ctx->sgrid.size()) != n_grid)
+    return ctx->fail(AQT_EINVAL, "n_grid differs from the point count of aqt_set_grid");
   if (!E || !gs || !O || !cinit || !R || !zdiag) return ctx->fail(AQT_EINVAL, "all table pointers are required");
   for (int g = 0; g < n_grid; ++g)
     if (gs[g] < 1 || gs[g] > n_levels) return ctx->fail(AQT_EINVAL, "ground-cluster size out of range");
@@ -436,6 +438,24 @@ aqt_status aqt_set_coupling(aqt_ctx* ctx, int n_channels, const double* cz, cons
   ctx->chan_wc = wc;
   if (any_x) ctx->chan_x = x;
   else ctx->chan_x.clear();
+  ctx->have_tables = false;
+  ctx->have_grad = false;
+  return AQT_OK;
+}
+
+aqt_status aqt_set_grid(aqt_ctx* ctx, int n_grid, const double* s) {
+  if (!ctx) return AQT_EINVAL;
+  if (n_grid == 0 || !s) {
+    ctx->sgrid.clear();
+    ctx->have_tables = false;
+    ctx->have_grad = false;
+    return AQT_OK;
+  }
+  if (n_grid < 2) return ctx->fail(AQT_EINVAL, "a grid needs at least two points");
+  if (s[0] != 0.0 || s[n_grid - 1] != 1.0) return ctx->fail(AQT_EINVAL, "grid points must run from 0 to 1");
+  for (int g = 1; g < n_grid; ++g)
+    if (!(s[g] > s[g - 1]) || !std::isfinite(s[g])) return ctx->fail(AQT_EINVAL, "grid points must increase");
+  ctx->sgrid.assign(s, s + n_grid);
   ctx->have_tables = false;
   ctx->have_grad = false;
   return AQT_OK;

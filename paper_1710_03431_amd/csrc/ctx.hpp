@@ -41,6 +41,9 @@ struct aqt_ctx {
   bool have_tables = false;
   int M = 0;        // grid points
   int tab_nch = 0;  // jump channels of the loaded tables
+  std::vector<double> sgrid;   // [M] grid points s_g of aqt_set_grid (empty: equidistant)
+  aqt::DevBuf sgd;             // [M] s_g of the loaded tables
+  aqt::DevBuf tbeg, tlen;      // [M] start time and length of the step into grid g (g >= 1)
   int n = 0;        // retained levels
   int NP = 0;       // padded level count: 16, 32, 64, 128 or 256
   double dt = 0.0;

@@ -94,7 +94,10 @@ struct GradArgs {
   int proj;              // levels of the final projector: the ground cluster, or all (path-density score)
   int* status;           // bit 0: more than kMaxJ omega = 0 jumps in one step
   int M, nq, nctrl, C, S;
-  double dt, eta;
+  double eta;
+  const double* tbeg;    // [M] start time of the step into grid g
+  const double* tlen;    // [M] its length
+  const double* sg;      // [M] grid points s_g (hat-function weights of the controls)
   int64_t K, tile0;
 };
 
@@ -187,7 +190,7 @@ __device__ void replay_step(const GradArgs& a, int g, const aqt_jump* rec, int m
     }
     return;
   }
-  const double tk = (g - 1) * a.dt;
+  const double tk = a.tbeg[g], dt = a.tlen[g];
   double tau_e = 0.0;
   for (int m = m0; m < m1; ++m) {
     const aqt_jump J = rec[m];
@@ -234,9 +237,9 @@ __device__ void replay_step(const GradArgs& a, int g, const aqt_jump* rec, int m
   for (int r = 0; r < NR; ++r) {
     const int x = lane + 64 * r;
     if (x < NP) {
-      const double dec = exp(-0.5 * a.Gam[gN + x] * (a.dt - tau_e));
+      const double dec = exp(-0.5 * a.Gam[gN + x] * (dt - tau_e));
       double sn, cs;
-      sincos(a.E[gN + x] * a.dt, &sn, &cs);
+      sincos(a.E[gN + x] * dt, &sn, &cs);
       const double ur = pr[r] * dec, ui = pi[r] * dec;
       PB[x * LD + 2 * t] = static_cast<T>(cs * ur + sn * ui);       // times exp(-i e dt)
       PB[x * LD + 2 * t + 1] = static_cast<T>(cs * ui - sn * ur);
@@ -256,7 +259,7 @@ __device__ void adjoint_step(const GradArgs& a, int g, const aqt_jump* rec, int 
   const double* dE1 = dE0 + NP;
   const double* dG0 = a.dGam + (static_cast<size_t>(g) * 2) * NP;
   const double* dG1 = dG0 + NP;
-  const double dt = a.dt, ieta = 1.0 / a.eta;
+  const double dt = a.tlen[g], ieta = 1.0 / a.eta;
   bool has_ab = false;
   int b1 = 0;
   for (int m = m0; m < m1; ++m)
@@ -267,7 +270,7 @@ __device__ void adjoint_step(const GradArgs& a, int g, const aqt_jump* rec, int 
     }
   if (has_ab) {
     // every factor of the step acts on one component: terms through f alone
-    const double tk = (g - 1) * dt;
+    const double tk = a.tbeg[g];
     int c = b1;
     double tp = 0.0, s0 = 0.0, s1 = 0.0, s2 = 0.0;
     for (int m = m0; m < m1; ++m) {
@@ -535,7 +538,7 @@ __global__ __launch_bounds__(kGThreads) void k_grad(GradArgs a) {
       __syncthreads();
       for (int t = tid; t < TT; t += kGThreads) {
         if (!active(t)) continue;
-        const double u = static_cast<double>(g) / (a.M - 1) * (a.nctrl - 1);
+        const double u = a.sg[g] * (a.nctrl - 1);
         const int j = std::min(static_cast<int>(floor(u)), a.nctrl - 2);
         const double fr = u - j;
         for (int adj = 0; adj < 2; ++adj) {
@@ -726,7 +729,9 @@ aqt_status launch_grad(aqt_ctx* ctx, const aqt_run_params* p, double* value, dou
   ga.M = ctx->M;
   ga.nq = ctx->nq;
   ga.nctrl = nctrl;
-  ga.dt = ctx->dt;
+  ga.tbeg = ctx->tbeg.as<double>();
+  ga.tlen = ctx->tlen.as<double>();
+  ga.sg = ctx->sgd.as<double>();
   ga.eta = ctx->eta;
   ga.K = K;
   if (!(ga.eta > 0.0)) return ctx->fail(AQT_EINVAL, "the gradient needs eta > 0");

@@ -50,7 +50,8 @@ struct FixArgs {
   double* final_state;   // [K][n][2] (may be null)
   int cap;
   int M, n, nq, S;
-  double dt;
+  const double* tbeg;    // [M] start time of the step into grid g
+  const double* tlen;    // [M] its length
   int64_t K;
   uint64_t seed, iid, traj0;
 };
@@ -83,7 +84,6 @@ __global__ __launch_bounds__(kGThreads) void k_fixed_step(FixArgs a) {
   __shared__ int s_kind[3];
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const int64_t tile = blockIdx.x;
-  const double h = a.dt / a.S;
   if (tid < 3) s_kind[tid] = 0;
   for (int f = tid; f < NP * LD; f += kGThreads) PB[f] = static_cast<T>(0);
   // per-trajectory registers of the handling wave (trajectories t = wave + kGW k)
@@ -94,6 +94,7 @@ __global__ __launch_bounds__(kGThreads) void k_fixed_step(FixArgs a) {
   __syncthreads();
 
   for (int g = 1; g < a.M; ++g) {
+    const double h = a.tlen[g] / a.S;   // sub-step length
     if (g == 1) {
       for (int f = tid; f < NP * NC; f += kGThreads) {
         const int x = f / NC, col = f % NC;
@@ -261,7 +262,7 @@ __global__ __launch_bounds__(kGThreads) void k_fixed_step(FixArgs a) {
         if (lane == 0) {
           if (a.jumps && cnt[k] < a.cap) {
             aqt_jump rec;
-            rec.t = (g - 1) * a.dt + s * h;
+            rec.t = a.tbeg[g] + s * h;
             rec.step = g - 1;
             rec.qubit = static_cast<int16_t>(qi);
             rec.kind = static_cast<int16_t>(kind);
@@ -403,7 +404,8 @@ aqt_status launch_fixed_step(aqt_ctx* ctx, const aqt_run_params* p, int substeps
   fa.n = ctx->n;
   fa.nq = ctx->tab_nch;   // jump channels
   fa.S = substeps;
-  fa.dt = ctx->dt;
+  fa.tbeg = ctx->tbeg.as<double>();
+  fa.tlen = ctx->tlen.as<double>();
   fa.K = p->n_traj;
   fa.seed = p->seed;
   fa.iid = p->instance_id;

@@ -1259,10 +1259,12 @@ aqt_status precompute_tables(aqt_ctx* ctx, int M, int n, double tol, int method,
   }
 
   // ---- schedule samples and Ising diagonal
+  if (!ctx->sgrid.empty() && static_cast<int>(ctx->sgrid.size()) != M)
+    return ctx->fail(AQT_EINVAL, "n_grid differs from the point count of aqt_set_grid");
   std::vector<double> Ag(M), Bg(M);
   const int nc = static_cast<int>(ctx->A_ctrl.size());
   for (int g = 0; g < M; ++g) {
-    const double s = static_cast<double>(g) / (M - 1);
+    const double s = ctx->sgrid.empty() ? static_cast<double>(g) / (M - 1) : ctx->sgrid[g];
     const double u = s * (nc - 1);
     int j = std::min(static_cast<int>(std::floor(u)), nc - 2);
     const double f = u - j;

@@ -79,7 +79,8 @@ struct StepArgs {
   int64_t tiles;         // workgroup tiles of this instance
   double* pgs_sum;       // [M] (batched runs reduce into these)
   double* pgs_sumsq;
-  double dt;
+  const double* tbeg;    // [M] start time of the step into grid g
+  const double* tlen;    // [M] its length
   int64_t K;
   uint64_t seed, iid, traj0;
   int cap;
@@ -297,7 +298,7 @@ __device__ void finish_crossing(const StepArgs& a, int g, int t, int64_t jloc, T
   constexpr int PL = NP / SEG;
   const int lane = threadIdx.x & (SEG - 1);                    // lane within the segment
   const int base = (threadIdx.x & (kWave - 1)) & ~(SEG - 1);   // first lane of the segment
-  const double dt = a.dt;
+  const double dt = a.tlen[g];
   const uint64_t traj = a.traj0 + static_cast<uint64_t>(jloc);   // Philox counter word 0
   const double* Gam = a.Gamma + static_cast<size_t>(g) * NP;
   const double* Eh = a.ehalf + static_cast<size_t>(g) * NP;
@@ -316,7 +317,7 @@ __device__ void finish_crossing(const StepArgs& a, int g, int t, int64_t jloc, T
   int cnt = s_cnt[t];
   int net = s_net[t];
   const int gsz = a.gs[g];
-  const double tk = (g - 1) * dt;
+  const double tk = a.tbeg[g];
   // the crossing test of the whole step, in FP64: sum_b |c_b|^2 e^{-G_b dt} = sum |S|^2
   double nu0 = 0.0;
 #pragma unroll
@@ -1182,7 +1183,8 @@ aqt_status launch_run(aqt_ctx* ctx, const aqt_run_params* p, const aqt_outputs* 
   a.pgs_sumsq = o->pgs_sumsq;
   a.n = ctx->n;
   a.nq = ctx->tab_nch;   // jump channels
-  a.dt = ctx->dt;
+  a.tbeg = ctx->tbeg.as<double>();
+  a.tlen = ctx->tlen.as<double>();
   a.K = p->n_traj;
   a.seed = p->seed;
   a.iid = p->instance_id;
@@ -1448,7 +1450,8 @@ aqt_status aqt_batch_create(aqt_batch** out, aqt_ctx* const* ctxs, int n, const 
     a.n = c->n;
     a.nq = c->tab_nch;   // jump channels
     a.NP = c->NP;
-    a.dt = c->dt;
+    a.tbeg = c->tbeg.as<double>();
+    a.tlen = c->tlen.as<double>();
     a.K = params[i].n_traj;
     a.seed = params[i].seed;
     a.iid = params[i].instance_id;

@@ -22,12 +22,14 @@ namespace {
 
 __global__ void k_gamma_phase(const double* __restrict__ E, const double* __restrict__ shift,
                               const double* __restrict__ R, int M, int NP, int n,
-                              int nq, double dt, double* __restrict__ Gamma, double* __restrict__ Rcol,
+                              int nq, const double* __restrict__ tlen, double* __restrict__ Gamma,
+                              double* __restrict__ Rcol,
                               double* __restrict__ ehalf, double* __restrict__ dre, double* __restrict__ dim) {
   const int64_t idx = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
   if (idx >= static_cast<int64_t>(M) * NP) return;
   const int g = static_cast<int>(idx / NP);
   const int b = static_cast<int>(idx - static_cast<int64_t>(g) * NP);
+  const double dt = tlen[g];   // length of the step into grid g
   double G = 0.0;
   for (int i = 0; i < nq; ++i) {
     double rs = 0.0, lo = 0.0, dg = 0.0;
@@ -160,14 +162,35 @@ inline unsigned blocks_for(int64_t count, int threads = 256) {
 }  // namespace
 
 aqt_status finish_tables(aqt_ctx* ctx) {
-  const int64_t cnt = static_cast<int64_t>(ctx->M) * ctx->NP;
+  const int M = ctx->M;
+  const int64_t cnt = static_cast<int64_t>(M) * ctx->NP;
+  // grid points and steps: s_g = g / (M - 1) with steps t_f / (M - 1) starting at (g - 1) dt,
+  // or the grid of aqt_set_grid with steps t_f (s_g - s_{g-1}) starting at t_f s_{g-1}
+  if (!ctx->sgrid.empty() && static_cast<int>(ctx->sgrid.size()) != M)
+    return ctx->fail(AQT_EINVAL, "the grid of aqt_set_grid has a different number of points");
+  std::vector<double> sg(M), tb(M, 0.0), tl(M, 0.0);
+  for (int g = 0; g < M; ++g) {
+    if (ctx->sgrid.empty()) {
+      sg[g] = static_cast<double>(g) / (M - 1);
+      if (g > 0) tb[g] = (g - 1) * ctx->dt, tl[g] = ctx->dt;
+    } else {
+      sg[g] = ctx->sgrid[g];
+      if (g > 0) tb[g] = ctx->t_f * ctx->sgrid[g - 1], tl[g] = ctx->t_f * (ctx->sgrid[g] - ctx->sgrid[g - 1]);
+    }
+  }
+  if (ctx->sgd.reserve(M * sizeof(double)) != hipSuccess || ctx->tbeg.reserve(M * sizeof(double)) != hipSuccess ||
+      ctx->tlen.reserve(M * sizeof(double)) != hipSuccess)
+    return ctx->fail(AQT_ENOMEM, "table allocation failed");
+  AQT_HIP(ctx, hipMemcpy(ctx->sgd.p, sg.data(), M * sizeof(double), hipMemcpyHostToDevice));
+  AQT_HIP(ctx, hipMemcpy(ctx->tbeg.p, tb.data(), M * sizeof(double), hipMemcpyHostToDevice));
+  AQT_HIP(ctx, hipMemcpy(ctx->tlen.p, tl.data(), M * sizeof(double), hipMemcpyHostToDevice));
   if (ctx->Gamma.reserve(cnt * sizeof(double)) != hipSuccess || ctx->dre.reserve(cnt * sizeof(double)) != hipSuccess ||
       ctx->dim.reserve(cnt * sizeof(double)) != hipSuccess ||
       ctx->Rcol.reserve(cnt * ctx->tab_nch * 4 * sizeof(double)) != hipSuccess ||
       ctx->ehalf.reserve(cnt * sizeof(double)) != hipSuccess)
     return ctx->fail(AQT_ENOMEM, "table allocation failed");
   hipLaunchKernelGGL(k_gamma_phase, dim3(blocks_for(cnt)), dim3(256), 0, ctx->stream, ctx->E.as<double>(),
-                     ctx->shift.as<double>(), ctx->R.as<double>(), ctx->M, ctx->NP, ctx->n, ctx->tab_nch, ctx->dt, ctx->Gamma.as<double>(),
+                     ctx->shift.as<double>(), ctx->R.as<double>(), ctx->M, ctx->NP, ctx->n, ctx->tab_nch, ctx->tlen.as<double>(), ctx->Gamma.as<double>(),
                      ctx->Rcol.as<double>(), ctx->ehalf.as<double>(), ctx->dre.as<double>(), ctx->dim.as<double>());
   AQT_HIP(ctx, hipGetLastError());
   ctx->packed_for = -1;

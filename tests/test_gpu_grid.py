@@ -1,0 +1,107 @@
+"""Non-uniform s-grids on the GPU against the FP64 oracle.
+
+The grid used here follows the App. B time-step bound (eq. B7): its local step is
+proportional to the bound's instantaneous value (the oracle's bound_grid, pinned to a
+closed form).  Steps of different lengths change the step tables, the jump times and
+the gradient's hat-function weights; exact-mean parity with the split-step AME on the
+same grid holds for any grid.
+"""
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import ame, gradient, spectrum, trajectories
+
+from gpu_common import compare_jump_records, sigma_bound
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def grid_case():
+    inst = W.ring_instance(3, 8, t_f=1.5, eta=0.1, n_grid=61)
+    inst = inst.with_(s_grid=spectrum.bound_grid(inst, 61, n_probe=121))
+    return inst, spectrum.all_tables(inst)
+
+
+def _engine(inst):
+    from paper_1710_03431_amd.binding import Engine
+    eng = Engine(0)
+    eng.set_instance(inst)
+    eng.precompute(inst.n_grid, inst.levels)
+    return eng
+
+
+def test_grid_fp64_per_trajectory(grid_case):
+    inst, tabs = grid_case
+    steps = np.diff(inst.s_grid)
+    assert steps.max() > 1.5 * steps.min()
+    K = 400
+    ref = trajectories.run(tabs, inst, K)
+    res = _engine(inst).run(K, "fp64", seed=inst.seed, instance_id=inst.instance_id, record_capacity=32)
+    frac, worst = compare_jump_records(res["jumps"], res["jump_count"], ref.jumps, inst.t_f)
+    assert frac >= 0.99, (frac, worst)
+    if frac == 1.0:
+        np.testing.assert_allclose(res["pgs_sum"], ref.pgs_sum, rtol=1e-9)
+
+
+def test_grid_average_matches_ame(grid_case):
+    inst, tabs = grid_case
+    P = ame.split_step(tabs, inst)
+    K = 1_000_000
+    res = _engine(inst).run(K, "fp32", seed=inst.seed + 9, instance_id=inst.instance_id)
+    m, se = trajectories.mean_and_stderr(res["pgs_sum"], res["pgs_sumsq"], K)
+    sig = sigma_bound(P, se, K)
+    assert np.all(np.abs(m - P) <= 3 * sig + 1e-4)
+
+
+def test_grid_fixed_step_per_trajectory(grid_case):
+    inst, tabs = grid_case
+    K, S = 200, 3
+    ref = trajectories.run_fixed_step(tabs, inst, K, S)
+    res = _engine(inst).run_fixed_step(K, S, "fp64", seed=inst.seed, instance_id=inst.instance_id,
+                                       record_capacity=64)
+    frac, worst = compare_jump_records(res["jumps"], res["jump_count"], ref.jumps, inst.t_f)
+    assert frac >= 0.99, (frac, worst)
+
+
+def test_grid_gradient_per_trajectory(grid_case):
+    """Per-trajectory gradient estimates on the non-uniform grid (5 control points, whose
+    hat functions are sampled at the grid points)."""
+    inst, _ = grid_case
+    A, B = W.linear_schedule(5)
+    inst = inst.with_(A_ctrl=A, B_ctrl=B)
+    K = 48
+    ref = gradient.trajectory_gradients(inst, K)
+    eng = _engine(inst)
+    out = eng.grad_pgs(K, "fp64", seed=inst.seed, instance_id=inst.instance_id, per_trajectory=True)
+    pt = out["per_traj"]
+    P = pt.shape[1] // 2 - 1
+    res = eng.run(K, "fp64", seed=inst.seed, instance_id=inst.instance_id, record_capacity=32)
+    same = [j for j in range(K)
+            if compare_jump_records(res["jumps"][j:j + 1], res["jump_count"][j:j + 1], ref["jumps"][j:j + 1],
+                                    inst.t_f)[0] == 1.0]
+    assert len(same) >= K - 2
+    for got, want in ((pt[same, 1:P + 1], ref["g"][same]), (pt[same, P + 2:], ref["score"][same])):
+        scale = np.maximum(np.abs(want).max(axis=0), 1e-3)
+        assert (np.abs(got - want) / scale).max() <= 2e-6
+
+
+def test_grid_argument_errors_and_equidistant_default():
+    from paper_1710_03431_amd.binding import AqtError, Engine
+    inst = W.ring_instance(3, 8, t_f=1.5, eta=0.1, n_grid=21)
+    eng = Engine(0)
+    eng.set_instance(inst)
+    for bad in ([0.0, 0.5, 0.4, 1.0], [0.1, 0.5, 1.0], [0.0, 0.5, 0.9], [0.0]):
+        with pytest.raises(AqtError):
+            eng.set_grid(np.array(bad))
+    eng.set_grid(np.linspace(0.0, 1.0, 11))
+    with pytest.raises(AqtError):            # n_grid differs from the grid's point count
+        eng.precompute(21, 8)
+    eng.set_grid(np.linspace(0.0, 1.0, 21))
+    eng.precompute(21, 8)
+    a = eng.run(256, "fp64", seed=3)
+    eng.set_grid(None)
+    eng.precompute(21, 8)
+    b = eng.run(256, "fp64", seed=3)
+    np.testing.assert_allclose(a["pgs_sum"], b["pgs_sum"], rtol=1e-9)
