@@ -727,7 +727,7 @@ aqt_status launch_grad(aqt_ctx* ctx, const aqt_run_params* p, double* value, dou
   ga.ostride = 2 * (P + 1);
   ga.status = status.as<int>();
   ga.M = ctx->M;
-  ga.nq = ctx->nq;
+  ga.nq = ctx->tab_nch;   // jump channels
   ga.nctrl = nctrl;
   ga.tbeg = ctx->tbeg.as<double>();
   ga.tlen = ctx->tlen.as<double>();

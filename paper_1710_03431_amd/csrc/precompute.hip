@@ -801,14 +801,16 @@ __device__ double dlog_gamma(double w, double wc, double T) {
   return h / T - sg / wc;
 }
 
-// From z_i (chunk-local [c][i][a][b], ld n) and Q[dir][c][i] = z_i X^T (row products):
+// Per jump channel i (rate cutoff wc[i]; any fixed coupling operator, so z_i = V^T O_i V
+// and dz_i = z_i X - X z_i), from z_i (chunk-local [c][i][a][b], ld n) and
+// Q[dir][c][i] = z_i X^T (row products):
 // dz_i = -(Q + Q^T);  dzd[g][dir][i][b] = dz_i[b][b];
 // dll[g][dir][i][b][a] = d log |l_i,ab| = (1/2) dlog_gamma(w_ab) (de_b - de_a) + dz_ab / z_ab
 // for a != b (l = sqrt(gamma(w_ab)) z_ab, the b -> a operator), 0 on the diagonal;
 // dGam[g][dir][b] = d Gamma_b = sum_i [sum_{a != b} dR_i,ab + 2 gamma(0) z_bb dz_bb].
 __global__ void k_dtables(const double* __restrict__ z, const double* __restrict__ Q, const double* __restrict__ E,
                           const double* __restrict__ dE, int n, int NP, int nq, int zg0, int zcnt, double eta,
-                          double wc, double T, double* __restrict__ dGam, double* __restrict__ dzd,
+                          const double* __restrict__ wc, double T, double* __restrict__ dGam, double* __restrict__ dzd,
                           double* __restrict__ dll) {
   const int64_t idx = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
   if (idx >= static_cast<int64_t>(zcnt) * 2 * NP) return;
@@ -844,8 +846,8 @@ __global__ void k_dtables(const double* __restrict__ z, const double* __restrict
         continue;
       }
       const double w = e[b] - e[a];
-      const double gam = gamma_ohmic(w, eta, wc, T);
-      const double lg = (w == 0.0) ? 0.5 / T : dlog_gamma(w, wc, T);
+      const double gam = gamma_ohmic(w, eta, wc[i], T);
+      const double lg = (w == 0.0) ? 0.5 / T : dlog_gamma(w, wc[i], T);
       const double dw = de[b] - de[a];
       dG += gam * (lg * dw * zab * zab + 2.0 * zab * dz);
       dl[a] = (zab != 0.0) ? 0.5 * lg * dw + dz / zab : 0.0;
@@ -1228,8 +1230,6 @@ aqt_status precompute_tables(aqt_ctx* ctx, int M, int n, double tol, int method,
   ctx->have_grad = false;
   ctx->gpk_prec = -1;
   if (grad && n != N) return ctx->fail(AQT_EINVAL, "gradient tables need the full spectrum (n_levels = 2^n_qubits)");
-  if (grad && (!ctx->single_spectrum() || nch != nq || !ctx->chan_x.empty()))
-    return ctx->fail(AQT_EINVAL, "the gradient is built for sz couplings with one bath spectral density");
   if (ctx->lamb && !ctx->single_spectrum())
     return ctx->fail(AQT_EINVAL, "the Lamb shift is built for one bath spectral density (no bath terms)");
   const bool iterative = (method == AQT_EIG_ITERATIVE) || (method == AQT_EIG_AUTO && N > kEigMaxN);
@@ -1379,7 +1379,7 @@ aqt_status precompute_tables(aqt_ctx* ctx, int M, int n, double tol, int method,
                           + 9 * static_cast<size_t>(n) * n            // polar ws
                           + N                                         // Eraw
                           + (grad ? static_cast<size_t>(n) * N + 2 * static_cast<size_t>(n) * n +
-                                        2 * static_cast<size_t>(nq) * n * n
+                                        2 * static_cast<size_t>(nch) * n * n
                                   : 0);                               // H_X rows, V H' V^T, z X^T
   const size_t budget = size_t(24) << 30;   // of 288 GB HBM: all grid points of a 10-qubit instance in one chunk
   int Gc = static_cast<int>(std::max<size_t>(1, std::min<size_t>(M, budget / (per_grid * 8))));
@@ -1398,14 +1398,14 @@ aqt_status precompute_tables(aqt_ctx* ctx, int M, int n, double tol, int method,
   DevBuf Wx, Hd, Qz;
   if (grad) {
     const size_t sn = n, sN = N, snp = NP;
-    if (Wx.reserve(Gc * sn * sN * 8) || Hd.reserve(Gc * 2 * sn * sn * 8) || Qz.reserve(Gc * 2 * nq * sn * sn * 8) ||
+    if (Wx.reserve(Gc * sn * sN * 8) || Hd.reserve(Gc * 2 * sn * sn * 8) || Qz.reserve(Gc * 2 * nch * sn * sn * 8) ||
         ctx->Xd.reserve(M * 2 * snp * snp * 8) || ctx->dE.reserve(M * 2 * snp * 8) ||
-        ctx->dGam.reserve(M * 2 * snp * 8) || ctx->dzd.reserve(M * 2 * nq * snp * 8) ||
-        ctx->dll.reserve(M * 2 * nq * snp * snp * 8) || ctx->dcin.reserve(2 * snp * 8))
+        ctx->dGam.reserve(M * 2 * snp * 8) || ctx->dzd.reserve(M * 2 * nch * snp * 8) ||
+        ctx->dll.reserve(M * 2 * nch * snp * snp * 8) || ctx->dcin.reserve(2 * snp * 8))
       return ctx->fail(AQT_ENOMEM, "gradient table allocation failed");
     AQT_HIP(ctx, hipMemsetAsync(ctx->dGam.p, 0, 2 * snp * 8, st));          // g = 0 unused
-    AQT_HIP(ctx, hipMemsetAsync(ctx->dzd.p, 0, 2 * nq * snp * 8, st));
-    AQT_HIP(ctx, hipMemsetAsync(ctx->dll.p, 0, 2 * nq * snp * snp * 8, st));
+    AQT_HIP(ctx, hipMemsetAsync(ctx->dzd.p, 0, 2 * nch * snp * 8, st));
+    AQT_HIP(ctx, hipMemsetAsync(ctx->dll.p, 0, 2 * nch * snp * snp * 8, st));
   }
   std::vector<int> hstat(Gc);
   const size_t Vstride = static_cast<size_t>(ncols) * N;
@@ -1592,14 +1592,14 @@ aqt_status precompute_tables(aqt_ctx* ctx, int M, int n, double tol, int method,
       if (zcnt > 0) {
         for (int dir = 0; dir < 2; ++dir) {
           GemmArgs gq{zws.as<double>(), ctx->Xd.as<double>() + (static_cast<size_t>(zg0) * 2 + dir) * NP * NP,
-                      Qz.as<double>() + static_cast<size_t>(dir) * zcnt * nq * nn, nn,
-                      2 * static_cast<int64_t>(NP) * NP, nn, n, n, n, n, NP, n, 0, nq, 0};
-          gq.bdiv = nq;
-          if ((s = launch_gemm(ctx, gq, zcnt * nq)) != AQT_OK) return s;
+                      Qz.as<double>() + static_cast<size_t>(dir) * zcnt * nch * nn, nn,
+                      2 * static_cast<int64_t>(NP) * NP, nn, n, n, n, n, NP, n, 0, nch, 0};
+          gq.bdiv = nch;
+          if ((s = launch_gemm(ctx, gq, zcnt * nch)) != AQT_OK) return s;
         }
         hipLaunchKernelGGL(k_dtables, dim3(nblk(static_cast<int64_t>(zcnt) * 2 * NP)), dim3(256), 0, st,
-                           zws.as<double>(), Qz.as<double>(), ctx->E.as<double>(), ctx->dE.as<double>(), n, NP, nq,
-                           zg0, zcnt, ctx->eta, ctx->omega_c, ctx->T, ctx->dGam.as<double>(), ctx->dzd.as<double>(),
+                           zws.as<double>(), Qz.as<double>(), ctx->E.as<double>(), ctx->dE.as<double>(), n, NP, nch,
+                           zg0, zcnt, ctx->eta, wcv.as<double>(), ctx->T, ctx->dGam.as<double>(), ctx->dzd.as<double>(),
                            ctx->dll.as<double>());
         AQT_HIP(ctx, hipGetLastError());
       }

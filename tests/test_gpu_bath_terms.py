@@ -81,6 +81,12 @@ def test_bath_terms_fixed_step_per_trajectory(terms_case):
     assert frac >= 0.99, (frac, worst)
 
 
+def test_bath_terms_gradient_per_trajectory(terms_case):
+    """Per-trajectory gradient estimates with the per-term channels (each rate's
+    derivative with its own cutoff) against the oracle's path-weight differences."""
+    _gradient_matches_oracle_per_trajectory(terms_case[0])
+
+
 def test_bath_terms_argument_errors():
     from paper_1710_03431_amd.binding import AqtError, Engine
     inst = W.ring_instance(3, 8, t_f=1.5, eta=0.1, n_grid=21)
@@ -100,8 +106,6 @@ def test_bath_terms_argument_errors():
         eng.precompute(21, 8)
     eng.set_lamb_shift(False)
     eng.precompute(21, 8)
-    with pytest.raises(AqtError):
-        eng.grad_pgs(16, "fp32")
     # channels beyond the padded level count (16 here): six full-rank terms, 18 channels
     eng.set_bath_terms(tuple((C0, 8.0 + m) for m in range(6)))
     assert eng.channel_count() == 18
@@ -115,3 +119,22 @@ def test_bath_terms_argument_errors():
     plain.set_instance(inst)
     plain.precompute(21, 8)
     np.testing.assert_array_equal(a, plain.get_tables(("R",))["R"])
+
+
+def _gradient_matches_oracle_per_trajectory(inst, K=48):
+    from oracle import gradient
+    A, B = W.linear_schedule(3)
+    inst = inst.with_(A_ctrl=A, B_ctrl=B)
+    ref = gradient.trajectory_gradients(inst, K)
+    eng = _engine(inst)
+    out = eng.grad_pgs(K, "fp64", seed=inst.seed, instance_id=inst.instance_id, per_trajectory=True)
+    pt = out["per_traj"]
+    P = pt.shape[1] // 2 - 1
+    res = eng.run(K, "fp64", seed=inst.seed, instance_id=inst.instance_id, record_capacity=32)
+    same = [j for j in range(K)
+            if compare_jump_records(res["jumps"][j:j + 1], res["jump_count"][j:j + 1], ref["jumps"][j:j + 1],
+                                    inst.t_f)[0] == 1.0]
+    assert len(same) >= K - 2
+    for got, want in ((pt[same, 1:P + 1], ref["g"][same]), (pt[same, P + 2:], ref["score"][same])):
+        scale = np.maximum(np.abs(want).max(axis=0), 1e-3)
+        assert (np.abs(got - want) / scale).max() <= 2e-6

@@ -82,6 +82,12 @@ def test_sx_coupling_of_a_fixed_sx_hamiltonian_only_dephases():
     np.testing.assert_allclose(np.asarray(res["pgs_sum"]) / 20000, 1.0, atol=1e-12)
 
 
+def test_coupling_gradient_per_trajectory(mixed_case):
+    """Per-trajectory gradient estimates with sz/sx channel operators (dz = z X - X z
+    for any fixed operator) against the oracle's path-weight differences."""
+    _gradient_matches_oracle_per_trajectory(mixed_case[0])
+
+
 def test_coupling_argument_errors():
     from paper_1710_03431_amd.binding import AqtError, Engine
     inst = W.ring_instance(3, 8, t_f=1.5, eta=0.1, n_grid=21)
@@ -99,8 +105,6 @@ def test_coupling_argument_errors():
         eng.precompute(21, 8)
     eng.set_lamb_shift(False)
     eng.precompute(21, 8)
-    with pytest.raises(AqtError):
-        eng.grad_pgs(16, "fp32")
     # cz = I, no sx part: the default channels bit for bit
     eng.set_coupling(np.eye(3))
     eng.precompute(21, 8)
@@ -108,3 +112,22 @@ def test_coupling_argument_errors():
     eng.set_coupling(None, None)
     eng.precompute(21, 8)
     np.testing.assert_allclose(a, eng.get_tables(("R",))["R"], rtol=1e-14, atol=1e-300)
+
+
+def _gradient_matches_oracle_per_trajectory(inst, K=48):
+    from oracle import gradient
+    A, B = W.linear_schedule(3)
+    inst = inst.with_(A_ctrl=A, B_ctrl=B)
+    ref = gradient.trajectory_gradients(inst, K)
+    eng = _engine(inst)
+    out = eng.grad_pgs(K, "fp64", seed=inst.seed, instance_id=inst.instance_id, per_trajectory=True)
+    pt = out["per_traj"]
+    P = pt.shape[1] // 2 - 1
+    res = eng.run(K, "fp64", seed=inst.seed, instance_id=inst.instance_id, record_capacity=32)
+    same = [j for j in range(K)
+            if compare_jump_records(res["jumps"][j:j + 1], res["jump_count"][j:j + 1], ref["jumps"][j:j + 1],
+                                    inst.t_f)[0] == 1.0]
+    assert len(same) >= K - 2
+    for got, want in ((pt[same, 1:P + 1], ref["g"][same]), (pt[same, P + 2:], ref["score"][same])):
+        scale = np.maximum(np.abs(want).max(axis=0), 1e-3)
+        assert (np.abs(got - want) / scale).max() <= 2e-6
