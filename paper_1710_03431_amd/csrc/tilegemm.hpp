@@ -49,7 +49,10 @@ __device__ __forceinline__ void panel_mma(const T* __restrict__ A, int rt, const
                                           typename Mfma<T>::acc_t (&acc)[NB][NC / 16]) {
   constexpr int VW = Vec<T>::W;
   constexpr int NJ = NP / (4 * VW);                // vector loads per lane for the whole panel
-  constexpr int JCH = (NJ < 8) ? NJ : 8;           // loads kept in flight
+  // loads kept in flight: the whole FP32 panel row at 256 levels (one workgroup per CU
+  // leaves little else to hide their latency), 8 in FP64 (no gain there, more registers)
+  constexpr int JMAX = (sizeof(T) == 4) ? 16 : 8;
+  constexpr int JCH = (NJ < JMAX) ? NJ : JMAX;
   using V = typename Vec<T>::t;
   const int lane = threadIdx.x & 63, q = lane >> 4, c = lane & 15;
   const V* arow = reinterpret_cast<const V*>(A + static_cast<size_t>(rt * 16 + c) * NP) + q;
