@@ -275,7 +275,8 @@ AQT_API aqt_status aqt_get_channel_count(aqt_ctx* ctx, int32_t* n_channels);
  * no-jump phases move: level b gets sum_i [sum_{a != b} S(e_b - e_a) z_ab^2 + S(0) z_bb^2];
  * Bohr frequencies, rates and jump kinds keep the energies of H_S.  Off by default; tables
  * given with aqt_set_tables are used as given.  Invalidates loaded tables (precompute
- * again).  aqt_grad_pgs returns AQT_EINVAL while it is on. */
+ * again).  aqt_grad_pgs includes it: the shift's derivative (dS/dw of the interpolated
+ * S(w) table, and 2 S z dz) enters the phase terms, and S scales with eta. */
 AQT_API aqt_status aqt_set_lamb_shift(aqt_ctx* ctx, int enabled);
 
 /* The Lamb shift of every level at every grid point (host [n_grid * n_levels], row-major;

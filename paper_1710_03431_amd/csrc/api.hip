@@ -490,7 +490,6 @@ aqt_status aqt_grad_pgs(aqt_ctx* ctx, const aqt_run_params* p, double* value, do
   if (!ctx) return AQT_EINVAL;
   if (!p) return ctx->fail(AQT_EINVAL, "params are required");
   if (!ctx->have_tables) return ctx->fail(AQT_ESTATE, "precompute must come first");
-  if (ctx->lamb) return ctx->fail(AQT_EINVAL, "the gradient does not include the Lamb shift's derivative");
   if (!ctx->last_from_solver)
     return ctx->fail(AQT_ESTATE, "the gradient needs tables from aqt_precompute (eigenvectors), not aqt_set_tables");
   if (ctx->n != (1 << ctx->nq))

@@ -71,6 +71,7 @@ struct aqt_ctx {
   aqt::DevBuf dzd;      // [M][2][nq][NP] d z_i[x][x]
   aqt::DevBuf dll;      // [M][2][nq][NP(b)][NP(a)] d log |l_i,ab|
   aqt::DevBuf dcin;     // [2][NP] derivative of the initial state through grid 0
+  aqt::DevBuf dshift;   // [M][2][NP] derivative of the Lamb shift (zeros when off)
   std::vector<double> sched_A, sched_B;   // [M] A(s_g), B(s_g) of the last aqt_precompute
   int fix_prec = -1;    // precision of the fixed-step kernel's O_g - I copy, -1 = none
   aqt::DevBuf fix_D;

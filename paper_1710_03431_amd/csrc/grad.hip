@@ -37,7 +37,9 @@
 //     stretch spent in component c.
 //   omega = 0 operator sqrt(gamma(0)) diag(z_i): 2 Re <lambda_after| diag(dz_i) |psi_before>
 //     / |diag(z_i) psi_before| (gamma(0) cancels).
-// eta scales every rate: dGamma = Gamma / eta, d log l = 1 / (2 eta), no basis change.
+// eta scales every rate: dGamma = Gamma / eta, d log l = 1 / (2 eta), no basis change;
+// it scales the Lamb shift too (phases exp(-i (e + shift) dt)), whose derivative with
+// respect to the schedule is tabulated beside de.
 // Controls enter through A(s_g) and B(s_g) with the hat-function weights of the
 // piecewise-linear schedule.
 //
@@ -82,6 +84,8 @@ struct GradArgs {
   const double* dzd;     // [M][2][nq][NP]
   const double* dll;     // [M][2][nq][NP][NP]
   const double* dcin;    // [2][NP]
+  const double* shift;   // [M][NP] Lamb shift (zeros when off): the phases use E + shift
+  const double* dshift;  // [M][2][NP] its derivative (zeros when off)
   const aqt_jump* jumps; // [K][cap]
   const int32_t* jcount; // [K]
   int cap;
@@ -239,7 +243,7 @@ __device__ void replay_step(const GradArgs& a, int g, const aqt_jump* rec, int m
     if (x < NP) {
       const double dec = exp(-0.5 * a.Gam[gN + x] * (dt - tau_e));
       double sn, cs;
-      sincos(a.E[gN + x] * dt, &sn, &cs);
+      sincos((a.E[gN + x] + a.shift[gN + x]) * dt, &sn, &cs);
       const double ur = pr[r] * dec, ui = pi[r] * dec;
       PB[x * LD + 2 * t] = static_cast<T>(cs * ur + sn * ui);       // times exp(-i e dt)
       PB[x * LD + 2 * t + 1] = static_cast<T>(cs * ui - sn * ur);
@@ -259,6 +263,8 @@ __device__ void adjoint_step(const GradArgs& a, int g, const aqt_jump* rec, int 
   const double* dE1 = dE0 + NP;
   const double* dG0 = a.dGam + (static_cast<size_t>(g) * 2) * NP;
   const double* dG1 = dG0 + NP;
+  const double* dS0 = a.dshift + (static_cast<size_t>(g) * 2) * NP;
+  const double* dS1 = dS0 + NP;
   const double dt = a.tlen[g], ieta = 1.0 / a.eta;
   bool has_ab = false;
   int b1 = 0;
@@ -326,9 +332,10 @@ __device__ void adjoint_step(const GradArgs& a, int g, const aqt_jump* rec, int 
     const double lr = static_cast<double>(LB[x * LD + 2 * t]), li = static_cast<double>(LB[x * LD + 2 * t + 1]);
     const double br = static_cast<double>(PB[x * LD + 2 * t]), bi = static_cast<double>(PB[x * LD + 2 * t + 1]);
     const double Pr = lr * br + li * bi, Pi = lr * bi - li * br;
-    s0 += 2.0 * dt * dE0[x] * Pi - dt * dG0[x] * Pr;
-    s1 += 2.0 * dt * dE1[x] * Pi - dt * dG1[x] * Pr;
-    s2 -= dt * ieta * a.Gam[gN + x] * Pr;
+    // phases exp(-i (e + shift) dt), decay exp(-Gamma dt / 2); shift and Gamma scale with eta
+    s0 += 2.0 * dt * (dE0[x] + dS0[x]) * Pi - dt * dG0[x] * Pr;
+    s1 += 2.0 * dt * (dE1[x] + dS1[x]) * Pi - dt * dG1[x] * Pr;
+    s2 += 2.0 * dt * ieta * a.shift[gN + x] * Pi - dt * ieta * a.Gam[gN + x] * Pr;
     double pr = 1.0;
     for (int k = 0; k < nj && k < kMaxJ; ++k)
       pr *= a.zdiag[(static_cast<size_t>(g) * a.nq + rec[m0 + k].qubit) * NP + x] / rho[k];
@@ -720,6 +727,8 @@ aqt_status launch_grad(aqt_ctx* ctx, const aqt_run_params* p, double* value, dou
   ga.dzd = ctx->dzd.as<double>();
   ga.dll = ctx->dll.as<double>();
   ga.dcin = ctx->dcin.as<double>();
+  ga.shift = ctx->shift.as<double>();
+  ga.dshift = ctx->dshift.as<double>();
   ga.jumps = jr.as<aqt_jump>();
   ga.jcount = jc.as<int32_t>();
   ga.cap = cap;

@@ -702,6 +702,59 @@ __device__ double lamb_S(const LambTable& t, double w) {
 }
 
 // shift[g][b] from z (chunk-local [c][i][a][b], ld n) for grid points zg0 .. zg0 + zcnt - 1.
+// dS/dw of the interpolant: the cubic's derivative in x times dx/dw.
+__device__ double lamb_dS(const LambTable& t, double w) {
+  const double sg = sinh(kLambSigma) / t.W;
+  const double y = w * sg;
+  const double x = asinh(y) / kLambSigma;
+  const double dxdw = sg / (kLambSigma * sqrt(1.0 + y * y));
+  const double dx = 2.0 / (kLambNodes - 1);
+  int k = static_cast<int>(floor((x + 1.0) / dx)) - 1;
+  k = min(max(k, 0), kLambNodes - 4);
+  const double u = (x + 1.0) / dx - k;
+  const double d0 = -((u - 2.0) * (u - 3.0) + (u - 1.0) * (u - 3.0) + (u - 1.0) * (u - 2.0)) / 6.0;
+  const double d1 = ((u - 2.0) * (u - 3.0) + u * (u - 3.0) + u * (u - 2.0)) / 2.0;
+  const double d2 = -((u - 1.0) * (u - 3.0) + u * (u - 3.0) + u * (u - 1.0)) / 2.0;
+  const double d3 = ((u - 1.0) * (u - 2.0) + u * (u - 2.0) + u * (u - 1.0)) / 6.0;
+  return (d0 * t.S[k] + d1 * t.S[k + 1] + d2 * t.S[k + 2] + d3 * t.S[k + 3]) / dx * dxdw;
+}
+
+// Derivative of the Lamb shift of level b (k_lamb_shift's sum) for both directions:
+// dshift[g][dir][b] = sum_i [sum_{a != b} (S'(w_ab) (de_b - de_a) z_ab^2 + 2 S(w_ab) z_ab dz_ab)
+//                            + 2 S(0) z_bb dz_bb],  w_ab = e_b - e_a, dz_i = -(Q + Q^T).
+__global__ void k_lamb_dshift(const double* __restrict__ z, const double* __restrict__ Q,
+                              const double* __restrict__ E, const double* __restrict__ dE, int n, int NP, int nq,
+                              int zg0, int zcnt, LambTable tab, double* __restrict__ dshift) {
+  const int64_t idx = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (idx >= static_cast<int64_t>(zcnt) * 2 * NP) return;
+  const int c = static_cast<int>(idx / (2 * NP));
+  const int dir = static_cast<int>((idx / NP) & 1);
+  const int b = static_cast<int>(idx % NP);
+  const int g = zg0 + c;
+  const size_t gd = static_cast<size_t>(g) * 2 + dir;
+  double acc = 0.0;
+  if (b < n) {
+    const double* e = E + static_cast<size_t>(g) * NP;
+    const double* de = dE + gd * NP;
+    const double s0 = lamb_S(tab, 0.0);
+    for (int i = 0; i < nq; ++i) {
+      const double* zi = z + (static_cast<size_t>(c) * nq + i) * n * n;
+      const double* Qi = Q + ((static_cast<size_t>(dir) * zcnt + c) * nq + i) * n * n;
+      for (int a = 0; a < n; ++a) {
+        const double zab = zi[a * n + b];
+        const double dz = -(Qi[a * n + b] + Qi[b * n + a]);
+        if (a == b) {
+          acc += 2.0 * s0 * zab * dz;
+        } else {
+          const double w = e[b] - e[a];
+          acc += lamb_dS(tab, w) * (de[b] - de[a]) * zab * zab + 2.0 * lamb_S(tab, w) * zab * dz;
+        }
+      }
+    }
+  }
+  dshift[gd * NP + b] = acc;
+}
+
 __global__ void k_lamb_shift(const double* __restrict__ z, const double* __restrict__ E, int n, int NP, int nq,
                              int zg0, int zcnt, LambTable tab, double* __restrict__ shift) {
   const int64_t idx = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
@@ -1401,11 +1454,13 @@ aqt_status precompute_tables(aqt_ctx* ctx, int M, int n, double tol, int method,
     if (Wx.reserve(Gc * sn * sN * 8) || Hd.reserve(Gc * 2 * sn * sn * 8) || Qz.reserve(Gc * 2 * nch * sn * sn * 8) ||
         ctx->Xd.reserve(M * 2 * snp * snp * 8) || ctx->dE.reserve(M * 2 * snp * 8) ||
         ctx->dGam.reserve(M * 2 * snp * 8) || ctx->dzd.reserve(M * 2 * nch * snp * 8) ||
-        ctx->dll.reserve(M * 2 * nch * snp * snp * 8) || ctx->dcin.reserve(2 * snp * 8))
+        ctx->dll.reserve(M * 2 * nch * snp * snp * 8) || ctx->dcin.reserve(2 * snp * 8) ||
+        ctx->dshift.reserve(M * 2 * snp * 8))
       return ctx->fail(AQT_ENOMEM, "gradient table allocation failed");
     AQT_HIP(ctx, hipMemsetAsync(ctx->dGam.p, 0, 2 * snp * 8, st));          // g = 0 unused
     AQT_HIP(ctx, hipMemsetAsync(ctx->dzd.p, 0, 2 * nch * snp * 8, st));
     AQT_HIP(ctx, hipMemsetAsync(ctx->dll.p, 0, 2 * nch * snp * snp * 8, st));
+    AQT_HIP(ctx, hipMemsetAsync(ctx->dshift.p, 0, M * 2 * snp * 8, st));   // stays zero without the Lamb shift
   }
   std::vector<int> hstat(Gc);
   const size_t Vstride = static_cast<size_t>(ncols) * N;
@@ -1602,6 +1657,12 @@ aqt_status precompute_tables(aqt_ctx* ctx, int M, int n, double tol, int method,
                            zg0, zcnt, ctx->eta, wcv.as<double>(), ctx->T, ctx->dGam.as<double>(), ctx->dzd.as<double>(),
                            ctx->dll.as<double>());
         AQT_HIP(ctx, hipGetLastError());
+        if (ctx->lamb) {
+          hipLaunchKernelGGL(k_lamb_dshift, dim3(nblk(static_cast<int64_t>(zcnt) * 2 * NP)), dim3(256), 0, st,
+                             zws.as<double>(), Qz.as<double>(), ctx->E.as<double>(), ctx->dE.as<double>(), n, NP, nch,
+                             zg0, zcnt, ltab, ctx->dshift.as<double>());
+          AQT_HIP(ctx, hipGetLastError());
+        }
       }
     }
     AQT_HIP(ctx, hipMemcpyAsync(Vprev.p, Vc.as<double>() + (cnt - 1) * Vstride, Vstride * 8, hipMemcpyDeviceToDevice, st));

@@ -71,9 +71,27 @@ def test_lamb_shift_average_matches_ame(lamb_case):
     assert np.max(np.abs(m - P0)[1:] / sig[1:]) > 8   # grid 0 is the initial state, P = 1 exactly
 
 
-def test_lamb_shift_gradient_is_refused(lamb_case):
-    from paper_1710_03431_amd.binding import AqtError
-    inst, _ = lamb_case
+def test_lamb_shift_gradient_per_trajectory():
+    """Gradient with the Lamb shift on (2-qubit ring, 3 + 3 controls): per-trajectory FP64
+    estimates against the oracle's central differences of each path's log weight, whose
+    perturbed tables re-evaluate S(w) by quadrature; the GPU differentiates the
+    interpolated S table and scales the shift with eta."""
+    from oracle import gradient
+    A, B = W.linear_schedule(3)
+    inst = W.ring_instance(2, 5, t_f=1.5, eta=0.1, n_grid=21, A_ctrl=A, B_ctrl=B, lamb_shift=True)
+    K = 32
+    ref = gradient.trajectory_gradients(inst, K)
     eng = _engine(inst)
-    with pytest.raises(AqtError):
-        eng.grad_pgs(16, "fp32")
+    out = eng.grad_pgs(K, "fp64", seed=inst.seed, instance_id=inst.instance_id, per_trajectory=True)
+    pt = out["per_traj"]
+    P = pt.shape[1] // 2 - 1
+    res = eng.run(K, "fp64", seed=inst.seed, instance_id=inst.instance_id, record_capacity=32)
+    same = [j for j in range(K)
+            if compare_jump_records(res["jumps"][j:j + 1], res["jump_count"][j:j + 1], ref["jumps"][j:j + 1],
+                                    inst.t_f)[0] == 1.0]
+    assert len(same) >= K - 1
+    np.testing.assert_allclose(pt[same, 0], ref["f"][same], atol=1e-10)
+    for got, want in ((pt[same, 1:P + 1], ref["g"][same]), (pt[same, P + 2:], ref["score"][same])):
+        scale = np.maximum(np.abs(want).max(axis=0), 1e-3)
+        err = np.abs(got - want) / scale
+        assert err.max() <= 2e-6, (err.max(axis=0), np.unravel_index(err.argmax(), err.shape))
