@@ -311,7 +311,9 @@ AQT_API aqt_status aqt_get_lamb_shift(aqt_ctx* ctx, double* shift);
  * noise that does not depend on f; its bias is O(1/n_traj)); grad_se is its standard error.
  * Needs tables from aqt_precompute with n_levels = 2^n_qubits (AQT_ESTATE after
  * aqt_set_tables, AQT_EINVAL for truncated spectra); the first call after a
- * precompute re-runs the eigensolver to add the derivative tables.  AQT_ECAPACITY if
+ * precompute re-runs the eigensolver to add the derivative tables.  Covers every bath
+ * model (aqt_set_bath_correlation, aqt_set_bath_terms, aqt_set_coupling), the Lamb shift
+ * and grids of aqt_set_grid (hat weights at the grid points).  AQT_ECAPACITY if
  * one trajectory takes more than 32 omega = 0 jumps within one step.  Synchronises. */
 AQT_API aqt_status aqt_grad_pgs(aqt_ctx* ctx, const aqt_run_params* params, double* value, double* value_se,
                                 double* grad, double* grad_se, double* per_traj);
