@@ -86,6 +86,7 @@ struct GradArgs {
   const double* dcin;    // [2][NP]
   const double* shift;   // [M][NP] Lamb shift (zeros when off): the phases use E + shift
   const double* dshift;  // [M][2][NP] its derivative (zeros when off)
+  int lamb;              // the Lamb shift is on (else both tables are skipped)
   const aqt_jump* jumps; // [K][cap]
   const int32_t* jcount; // [K]
   int cap;
@@ -243,7 +244,7 @@ __device__ void replay_step(const GradArgs& a, int g, const aqt_jump* rec, int m
     if (x < NP) {
       const double dec = exp(-0.5 * a.Gam[gN + x] * (dt - tau_e));
       double sn, cs;
-      sincos((a.E[gN + x] + a.shift[gN + x]) * dt, &sn, &cs);
+      sincos((a.E[gN + x] + (a.lamb ? a.shift[gN + x] : 0.0)) * dt, &sn, &cs);
       const double ur = pr[r] * dec, ui = pi[r] * dec;
       PB[x * LD + 2 * t] = static_cast<T>(cs * ur + sn * ui);       // times exp(-i e dt)
       PB[x * LD + 2 * t + 1] = static_cast<T>(cs * ui - sn * ur);
@@ -333,9 +334,15 @@ __device__ void adjoint_step(const GradArgs& a, int g, const aqt_jump* rec, int 
     const double br = static_cast<double>(PB[x * LD + 2 * t]), bi = static_cast<double>(PB[x * LD + 2 * t + 1]);
     const double Pr = lr * br + li * bi, Pi = lr * bi - li * br;
     // phases exp(-i (e + shift) dt), decay exp(-Gamma dt / 2); shift and Gamma scale with eta
-    s0 += 2.0 * dt * (dE0[x] + dS0[x]) * Pi - dt * dG0[x] * Pr;
-    s1 += 2.0 * dt * (dE1[x] + dS1[x]) * Pi - dt * dG1[x] * Pr;
-    s2 += 2.0 * dt * ieta * a.shift[gN + x] * Pi - dt * ieta * a.Gam[gN + x] * Pr;
+    double de0 = dE0[x], de1 = dE1[x], sh = 0.0;
+    if (a.lamb) {
+      de0 += dS0[x];
+      de1 += dS1[x];
+      sh = a.shift[gN + x];
+    }
+    s0 += 2.0 * dt * de0 * Pi - dt * dG0[x] * Pr;
+    s1 += 2.0 * dt * de1 * Pi - dt * dG1[x] * Pr;
+    s2 += 2.0 * dt * ieta * sh * Pi - dt * ieta * a.Gam[gN + x] * Pr;
     double pr = 1.0;
     for (int k = 0; k < nj && k < kMaxJ; ++k)
       pr *= a.zdiag[(static_cast<size_t>(g) * a.nq + rec[m0 + k].qubit) * NP + x] / rho[k];
@@ -729,6 +736,7 @@ aqt_status launch_grad(aqt_ctx* ctx, const aqt_run_params* p, double* value, dou
   ga.dcin = ctx->dcin.as<double>();
   ga.shift = ctx->shift.as<double>();
   ga.dshift = ctx->dshift.as<double>();
+  ga.lamb = ctx->lamb ? 1 : 0;
   ga.jumps = jr.as<aqt_jump>();
   ga.jcount = jc.as<int32_t>();
   ga.cap = cap;
