@@ -91,3 +91,32 @@ def test_bf16_sixteen_levels_matches_ame():
     res = eng.run(K, "bf16", seed=3)
     m, se = trajectories.mean_and_stderr(res["pgs_sum"], res["pgs_sumsq"], K)
     assert np.all(np.abs(m - P) <= 3 * sigma_bound(P, se, K) + 1e-4)
+
+
+def test_batch_mixes_bath_models_and_grids():
+    """Instances with bath terms (one more channel than qubits), sz/sx couplings, a
+    non-uniform grid and the Lamb shift in one FP64 batch: each reproduces its own
+    run, so the batched kernel reads every instance's channel count, step lengths and
+    phase tables."""
+    from paper_1710_03431_amd.binding import Batch
+    base = W.pm1_all_to_all(6, 11, t_f=1500.0, n_grid=120, n_levels=16)
+    cz = np.vstack([np.eye(6), np.zeros((2, 6))])
+    cx = np.zeros((8, 6))
+    cx[6, 0], cx[7, 3] = 1.0, 0.5
+    g = np.arange(base.n_grid) / (base.n_grid - 1)
+    insts = [base.with_(bath_terms=W.two_term_bath(6)),
+             base.with_(coupling=(cz, cx, None)),
+             base.with_(s_grid=0.5 * (1.0 - np.cos(np.pi * g))),
+             base.with_(lamb_shift=True)]
+    engines = [make_engine(i) for i in insts]
+    assert [e.channel_count() for e in engines] == [7, 8, 6, 6]
+    runs = [dict(n_traj=256 + 29 * k, seed=7 + k, instance_id=k, record_capacity=48) for k in range(len(insts))]
+    b = Batch(engines, runs, precision="fp64", graph=False, autotune=False)
+    b.launch()
+    got = b.results()
+    for k, (r, res, tile) in enumerate(zip(runs, got, b.tiles)):
+        K = r["n_traj"]
+        ref = engines[k].run(K, "fp64", seed=r["seed"], instance_id=k, record_capacity=48, tile=tile)
+        frac = same_records(res, ref, insts[k].t_f, 1e-9)
+        assert frac >= 0.999, (k, frac)
+        assert np.abs(res["pgs_sum"] - ref["pgs_sum"]).max() <= (1.0 - frac) * K + 1e-6 * K
