@@ -379,7 +379,7 @@ def bench_fixed(args):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(json.dumps({"error": "this engine runs on one GPU; multi-GPU runs are not part of this build",
+        print(json.dumps({"error": "this engine runs on one GPU; runs on several GPUs are not supported",
                           "n_gpus": args.gpus}))
         sys.exit(2)
     if args.workload == "batched":
