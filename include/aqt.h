@@ -223,9 +223,8 @@ AQT_API aqt_status aqt_set_bath_correlation(aqt_ctx* ctx, const double* C);
  * every Bohr frequency (in place of u(w)); tables, jump records ("qubit" is the
  * channel) and aqt_get_channel_count refer to them.  n_terms = 0 restores independent
  * baths; replaces any aqt_set_bath_correlation.  Applies from the next aqt_precompute
- * (loaded tables are invalidated).  The Lamb shift needs one spectral density
- * (aqt_precompute returns AQT_EINVAL with bath terms and the Lamb shift on); the
- * gradient covers bath terms (each channel's rate derivative uses its cutoff).  AQT_ESTATE before
+ * (loaded tables are invalidated).  The Lamb shift and the gradient cover bath terms:
+ * each channel's S(w) and rate derivative use its cutoff (one S table per cutoff).  AQT_ESTATE before
  * aqt_set_hamiltonian; AQT_EINVAL for non-finite or non-symmetric (1e-12 relative)
  * C_m, a pivot below -1e-9 max(diag C_m) (not semidefinite), a cutoff <= 0, no
  * channel at all or more than 64; aqt_precompute returns AQT_EINVAL when the channels
@@ -253,8 +252,8 @@ AQT_API aqt_status aqt_set_grid(aqt_ctx* ctx, int n_grid, const double* s);
  * <a|O_k|b> in the real eigenbasis are real, so tables and kernels are those of the
  * sz channels; jump records' "qubit" is the channel k.  n_channels = 0 restores the
  * default (sz of each qubit).  Replaces aqt_set_bath_correlation / aqt_set_bath_terms
- * settings and vice versa; applies from the next aqt_precompute.  The Lamb shift needs
- * omega_c NULL; aqt_grad_pgs covers these channels (dz_k = z_k X - X z_k holds for any
+ * settings and vice versa; applies from the next aqt_precompute.  The Lamb shift uses
+ * each channel's cutoff in S(w); aqt_grad_pgs covers these channels (dz_k = z_k X - X z_k holds for any
  * fixed coupling operator).
  * AQT_ESTATE before aqt_set_hamiltonian; AQT_EINVAL for n_channels outside [0, 64],
  * non-finite coefficients, a channel whose operator is zero, cz and cx both NULL or a

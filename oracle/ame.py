@@ -139,11 +139,10 @@ def lindblad_operators(T, inst, tol: float = 1e-9):
 def lamb_hamiltonian(T, inst) -> np.ndarray:
     """H_LS = sum_i sum_w S(w) A_i,w^dag A_i,w (eq. ME2-H) as a matrix, built from the
     unscaled operators of lindblad_operators' grouping (one per a != b pair, one omega = 0
-    operator per qubit)."""
-    if getattr(inst, "bath_terms", None) is not None:
-        raise NotImplementedError("the Lamb shift is built for one bath spectral density")
+    operator per channel; S with the channel's cutoff)."""
     n = len(T.E)
     H = np.zeros((n, n))
+    wc = model.bath_channels(inst)[1]
     for i in range(len(T.z)):
         z = T.z[i]
         for a in range(n):
@@ -152,9 +151,9 @@ def lamb_hamiltonian(T, inst) -> np.ndarray:
                     continue
                 A = np.zeros((n, n))
                 A[a, b] = z[a, b]
-                H += model.lamb_S(float(T.E[b] - T.E[a]), inst.eta, inst.omega_c, inst.T) * (A.T @ A)
+                H += model.lamb_S(float(T.E[b] - T.E[a]), inst.eta, float(wc[i]), inst.T) * (A.T @ A)
         A0 = np.diag(np.diag(z))
-        H += model.lamb_S(0.0, inst.eta, inst.omega_c, inst.T) * (A0.T @ A0)
+        H += model.lamb_S(0.0, inst.eta, float(wc[i]), inst.T) * (A0.T @ A0)
     return H
 
 

@@ -184,26 +184,24 @@ def lamb_shift(inst, E: np.ndarray, z: np.ndarray) -> np.ndarray:
     """Diagonal of H_LS = sum_i sum_w S(w) A_i,w^dag A_i,w in the eigenbasis (Sec. II,
     eq. ME2-H; the operators of the Bohr-frequency reading): level b collects
     S(e_b - e_a) z_i[a,b]^2 from every a != b and S(0) z_i[b,b]^2 from the omega = 0
-    operator of each qubit."""
-    if getattr(inst, "bath_terms", None) is not None:
-        raise NotImplementedError("the Lamb shift is built for one bath spectral density")
+    operator of each jump channel i, S taken with that channel's cutoff."""
     n = len(E)
+    wc = model.bath_channels(inst)[1]                  # each channel's S uses its cutoff
     cache = {}
 
-    def S(w):
-        if w not in cache:
-            cache[w] = model.lamb_S(w, inst.eta, inst.omega_c, inst.T)
-        return cache[w]
+    def S(w, c):
+        key = (w, float(c))
+        if key not in cache:
+            cache[key] = model.lamb_S(w, inst.eta, float(c), inst.T)
+        return cache[key]
 
     out = np.zeros(n)
-    s0 = S(0.0)
     for b in range(n):
         acc = 0.0
-        for a in range(n):
-            if a != b:
-                w2 = (z[:, a, b] ** 2).sum()
-                acc += S(float(E[b] - E[a])) * w2
-        acc += s0 * (z[:, b, b] ** 2).sum()
+        for i in range(len(z)):
+            for a in range(n):
+                w = 0.0 if a == b else float(E[b] - E[a])
+                acc += S(w, wc[i]) * z[i, a, b] ** 2
         out[b] = acc
     return out
 

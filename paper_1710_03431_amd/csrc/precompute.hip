@@ -645,9 +645,15 @@ constexpr int kLambNodes = 16385;
 constexpr double kLambSigma = 10.0;
 
 struct LambTable {
-  const double* S;   // [kLambNodes]
+  const double* S;   // [tables][kLambNodes], one table per distinct channel cutoff
   double W;          // largest |w| covered
+  const int* tix;    // [channels] table of each channel (null: table 0)
 };
+
+// The S table of jump channel i.
+__device__ inline LambTable lamb_channel(const LambTable& t, int i) {
+  return LambTable{t.S + static_cast<size_t>(t.tix ? t.tix[i] : 0) * kLambNodes, t.W, nullptr};
+}
 
 __device__ double lamb_integrand_panel(double w, double lo, double hi, double eta, double wc, double T,
                                        const double* __restrict__ glx, const double* __restrict__ glw) {
@@ -736,8 +742,9 @@ __global__ void k_lamb_dshift(const double* __restrict__ z, const double* __rest
   if (b < n) {
     const double* e = E + static_cast<size_t>(g) * NP;
     const double* de = dE + gd * NP;
-    const double s0 = lamb_S(tab, 0.0);
     for (int i = 0; i < nq; ++i) {
+      const LambTable ti = lamb_channel(tab, i);
+      const double s0 = lamb_S(ti, 0.0);
       const double* zi = z + (static_cast<size_t>(c) * nq + i) * n * n;
       const double* Qi = Q + ((static_cast<size_t>(dir) * zcnt + c) * nq + i) * n * n;
       for (int a = 0; a < n; ++a) {
@@ -747,7 +754,7 @@ __global__ void k_lamb_dshift(const double* __restrict__ z, const double* __rest
           acc += 2.0 * s0 * zab * dz;
         } else {
           const double w = e[b] - e[a];
-          acc += lamb_dS(tab, w) * (de[b] - de[a]) * zab * zab + 2.0 * lamb_S(tab, w) * zab * dz;
+          acc += lamb_dS(ti, w) * (de[b] - de[a]) * zab * zab + 2.0 * lamb_S(ti, w) * zab * dz;
         }
       }
     }
@@ -764,12 +771,13 @@ __global__ void k_lamb_shift(const double* __restrict__ z, const double* __restr
   double acc = 0.0;
   if (b < n) {
     const double* e = E + static_cast<size_t>(g) * NP;
-    const double s0 = lamb_S(tab, 0.0);
     for (int i = 0; i < nq; ++i) {
+      const LambTable ti = lamb_channel(tab, i);
+      const double s0 = lamb_S(ti, 0.0);
       const double* zi = z + (static_cast<size_t>(c) * nq + i) * n * n;
       for (int a = 0; a < n; ++a) {
         const double zab = zi[a * n + b];
-        acc += ((a == b) ? s0 : lamb_S(tab, e[b] - e[a])) * zab * zab;
+        acc += ((a == b) ? s0 : lamb_S(ti, e[b] - e[a])) * zab * zab;
       }
     }
   }
@@ -1283,8 +1291,6 @@ aqt_status precompute_tables(aqt_ctx* ctx, int M, int n, double tol, int method,
   ctx->have_grad = false;
   ctx->gpk_prec = -1;
   if (grad && n != N) return ctx->fail(AQT_EINVAL, "gradient tables need the full spectrum (n_levels = 2^n_qubits)");
-  if (ctx->lamb && !ctx->single_spectrum())
-    return ctx->fail(AQT_EINVAL, "the Lamb shift is built for one bath spectral density (no bath terms)");
   const bool iterative = (method == AQT_EIG_ITERATIVE) || (method == AQT_EIG_AUTO && N > kEigMaxN);
   const int ncols = std::min(N, n + 16);   // levels solved for: n plus a guard for clusters at the cut
   int KB = 0;                              // block size of the subspace iteration
@@ -1382,8 +1388,8 @@ aqt_status precompute_tables(aqt_ctx* ctx, int M, int n, double tol, int method,
   if (wcv.reserve(nch * 8)) return ctx->fail(AQT_ENOMEM, "channel cutoff allocation failed");
   AQT_HIP(ctx, hipMemcpyAsync(wcv.p, wch.data(), nch * 8, hipMemcpyHostToDevice, st));
   // Lamb-shift function table over every Bohr frequency (Gershgorin bound on |e|)
-  DevBuf lambS, gl;
-  LambTable ltab{nullptr, 0.0};
+  DevBuf lambS, gl, tixd;
+  LambTable ltab{nullptr, 0.0, nullptr};
   if (ctx->lamb) {
     double hsum = 0.0;
     for (double v : ctx->h) hsum += std::fabs(v);
@@ -1414,13 +1420,25 @@ aqt_status precompute_tables(aqt_ctx* ctx, int M, int n, double tol, int method,
       glh[q] = x;
       glh[16 + q] = 2.0 / ((1.0 - x * x) * dp * dp);
     }
-    if (lambS.reserve(kLambNodes * 8) || gl.reserve(32 * 8))
+    // one S table per distinct channel cutoff
+    std::vector<double> cut;
+    std::vector<int> tix(nch);
+    for (int k = 0; k < nch; ++k) {
+      const auto it = std::find(cut.begin(), cut.end(), wch[k]);
+      tix[k] = static_cast<int>(it - cut.begin());
+      if (it == cut.end()) cut.push_back(wch[k]);
+    }
+    if (lambS.reserve(cut.size() * kLambNodes * 8) || gl.reserve(32 * 8) || tixd.reserve(nch * 4))
       return ctx->fail(AQT_ENOMEM, "Lamb-shift table allocation failed");
     AQT_HIP(ctx, hipMemcpyAsync(gl.p, glh.data(), 32 * 8, hipMemcpyHostToDevice, st));
-    hipLaunchKernelGGL(k_lamb_table, dim3(nblk(kLambNodes, 64)), dim3(64), 0, st, ltab.W, ctx->eta, ctx->omega_c,
-                       ctx->T, gl.as<double>(), gl.as<double>() + 16, lambS.as<double>());
-    AQT_HIP(ctx, hipGetLastError());
+    AQT_HIP(ctx, hipMemcpyAsync(tixd.p, tix.data(), nch * 4, hipMemcpyHostToDevice, st));
+    for (size_t m = 0; m < cut.size(); ++m) {
+      hipLaunchKernelGGL(k_lamb_table, dim3(nblk(kLambNodes, 64)), dim3(64), 0, st, ltab.W, ctx->eta, cut[m],
+                         ctx->T, gl.as<double>(), gl.as<double>() + 16, lambS.as<double>() + m * kLambNodes);
+      AQT_HIP(ctx, hipGetLastError());
+    }
     ltab.S = lambS.as<double>();
+    ltab.tix = tixd.as<int>();
   }
 
   // ---- chunked workspace

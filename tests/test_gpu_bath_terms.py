@@ -87,6 +87,25 @@ def test_bath_terms_gradient_per_trajectory(terms_case):
     _gradient_matches_oracle_per_trajectory(terms_case[0])
 
 
+def test_bath_terms_with_lamb_shift():
+    """Lamb shift with per-term cutoffs (one S table per cutoff): shifts against the
+    oracle's quadrature, and FP64 trajectories against the oracle's."""
+    inst = W.ring_instance(3, 8, t_f=1.5, eta=0.1, n_grid=41, bath_terms=W.two_term_bath(3, rho=0.8),
+                           lamb_shift=True)
+    tabs = spectrum.all_tables(inst)
+    eng = _engine(inst)
+    got = eng.get_lamb_shift()
+    scale = max(np.abs(T.shift).max() for T in tabs)
+    assert scale > 1.0
+    for T in tabs:
+        np.testing.assert_allclose(got[T.g], T.shift, rtol=0, atol=1e-9 * scale)
+    K = 300
+    ref = trajectories.run(tabs, inst, K)
+    res = eng.run(K, "fp64", seed=inst.seed, instance_id=inst.instance_id, record_capacity=32)
+    frac, worst = compare_jump_records(res["jumps"], res["jump_count"], ref.jumps, inst.t_f)
+    assert frac >= 0.99, (frac, worst)
+
+
 def test_bath_terms_argument_errors():
     from paper_1710_03431_amd.binding import AqtError, Engine
     inst = W.ring_instance(3, 8, t_f=1.5, eta=0.1, n_grid=21)
@@ -101,10 +120,6 @@ def test_bath_terms_argument_errors():
         eng.set_bath_terms(((np.array([[1.0, 0.2, 0.0], [0.3, 1.0, 0.0], [0.0, 0.0, 1.0]]), 8.0),))
     eng.set_bath_terms(((C0, 8.0), (C1, 2.0)))
     assert eng.channel_count() == 4
-    eng.set_lamb_shift(True)
-    with pytest.raises(AqtError):                                             # one spectral density only
-        eng.precompute(21, 8)
-    eng.set_lamb_shift(False)
     eng.precompute(21, 8)
     # channels beyond the padded level count (16 here): six full-rank terms, 18 channels
     eng.set_bath_terms(tuple((C0, 8.0 + m) for m in range(6)))

@@ -100,10 +100,6 @@ def test_coupling_argument_errors():
     with pytest.raises(AqtError):
         eng.set_coupling(np.ones((65, 3)))                                            # too many channels
     eng.set_coupling(CZ, CX, WC)
-    eng.set_lamb_shift(True)
-    with pytest.raises(AqtError):
-        eng.precompute(21, 8)
-    eng.set_lamb_shift(False)
     eng.precompute(21, 8)
     # cz = I, no sx part: the default channels bit for bit
     eng.set_coupling(np.eye(3))

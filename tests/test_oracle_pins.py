@@ -628,6 +628,31 @@ def test_frequency_dependent_bath_split_step_equals_double_sum(rho, xi):
         np.testing.assert_allclose(got, want, atol=1e-13)
 
 
+def test_lamb_shift_of_bath_terms_equals_double_sum():
+    """Lamb shift with frequency-dependent correlations: the shift of each level from the
+    per-term channels (each S with its term's cutoff) equals the double sum over qubits
+    sum_ab S_ab(w) <a|sz_a|b><a|sz_b|b> with S_ab(w) = sum_m C_m[a, b] S(w; omega_c,m),
+    built from per-qubit operators (no factorisation); S(0) = -eta omega_c,m per term."""
+    terms = W.two_term_bath(2, rho=0.8)
+    inst = W.ring_instance(2, 3, t_f=40.0, eta=3e-3, bath_terms=terms, lamb_shift=True)
+    T = spectrum.all_tables(inst, n_grid=4, keep_V=True)[2]
+    zq = [T.V.T @ (model.sz_diag(q, 2)[:, None] * T.V) for q in range(2)]
+    n = len(T.E)
+
+    def S_ab(w):
+        return sum(np.asarray(C) * model.lamb_S(w, inst.eta, wc, inst.T) for C, wc in terms)
+
+    want = np.zeros(n)
+    for b in range(n):
+        for a in range(n):
+            G = S_ab(0.0 if a == b else float(T.E[b] - T.E[a]))
+            v = np.array([zq[q][a, b] for q in range(2)])
+            want[b] += v @ G @ v
+    np.testing.assert_allclose(T.shift, want, rtol=1e-10, atol=1e-14)
+    for C, wc in terms:
+        np.testing.assert_allclose(model.lamb_S(0.0, inst.eta, wc, inst.T), -inst.eta * wc, rtol=1e-9)
+
+
 def test_single_bath_term_equals_constant_correlation():
     """One term (C, omega_c of the bath) is the constant-correlation model."""
     C = np.array([[1.0, 0.4, 0.1], [0.4, 1.0, 0.4], [0.1, 0.4, 1.0]])
