@@ -576,8 +576,7 @@ __global__ __launch_bounds__(kGThreads) void k_grad(GradArgs a) {
       // tiles of this step; the tiles then swap roles
       if (g >= 2) {
         const T* DT = static_cast<const T*>(a.pDT) + static_cast<size_t>(g) * NP * NP;
-        gemm_kick<NP, NC, LD, T>(DT, LP, PB);
-        gemm_kick<NP, NC, LD, T>(DT, LI, PA);
+        gemm_kick2<NP, NC, LD, T>(DT, LP, PB, LI, PA);
         int tmp = iL;
         iL = iB;
         iB = tmp;

@@ -96,6 +96,31 @@ __device__ void gemm_kick(const T* __restrict__ A, const T* B, T* Y) {
   }
 }
 
+// Y1 = (I + A) B1 and Y2 = (I + A) B2 with one pass over A (the panel loads are shared);
+// each product is accumulated in the same order as gemm_kick's.
+template <int NP, int NC, int LD, class T>
+__device__ void gemm_kick2(const T* __restrict__ A, const T* B1, T* Y1, const T* B2, T* Y2) {
+  constexpr int RT = NP / 16, CT = NC / 16;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, c = lane & 15;
+  const T* const Bs[2] = {B1, B2};
+  for (int rt = wave; rt < RT; rt += kGW) {
+    typename Mfma<T>::acc_t acc[2][CT];
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int ct = 0; ct < CT; ++ct) acc[b][ct] = Mfma<T>::zero();
+    panel_mma<NP, NC, LD, T, 2>(A, rt, Bs, acc);
+#pragma unroll
+    for (int ct = 0; ct < CT; ++ct)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int r = rt * 16 + Mfma<T>::row(lane, e), col = ct * 16 + c;
+        Y1[r * LD + col] = acc[0][ct][e] + B1[r * LD + col];
+        Y2[r * LD + col] = acc[1][ct][e] + B2[r * LD + col];
+      }
+  }
+}
+
 // Copies between an LDS state tile (leading dimension LD) and a dense [NP][NC] block.
 template <int NP, int NC, int LD, class T>
 __device__ void tile_store(const T* src, T* __restrict__ dst) {
