@@ -106,41 +106,88 @@ struct GradArgs {
   int64_t K, tile0;
 };
 
-// part1[t] += Re <L1_t | X | B_t> and part2[t] += Re <L2_t | X | B_t>: one product, two
-// adjoints (columns 2t, 2t+1 = re, im); each wave adds to its own part rows.
+// part1[t] += Re <L1_t | Y_t> and part2[t] += Re <L2_t | Y_t> for the 16-row tile rt of a
+// product Y held in MFMA accumulators (columns 2t, 2t + 1 = re, im); each wave adds to
+// its own part rows.
+template <int NP, int NC, int LD, class T>
+__device__ __forceinline__ void dot2_tile(const typename Mfma<T>::acc_t (&acc)[NC / 16], int rt, const T* L1,
+                                          const T* L2, double* part1, double* part2) {
+  constexpr int CT = NC / 16;
+  const int lane = threadIdx.x & 63, c = lane & 15;
+#pragma unroll
+  for (int ct = 0; ct < CT; ++ct) {
+    double s1 = 0.0, s2 = 0.0;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int r = rt * 16 + Mfma<T>::row(lane, e), col = ct * 16 + c;
+      const double y = static_cast<double>(acc[ct][e]);
+      s1 += static_cast<double>(L1[r * LD + col]) * y;
+      s2 += static_cast<double>(L2[r * LD + col]) * y;
+    }
+    s1 += __shfl_xor(s1, 16, 64);
+    s1 += __shfl_xor(s1, 32, 64);
+    s1 += __shfl_xor(s1, 1, 64);
+    s2 += __shfl_xor(s2, 16, 64);
+    s2 += __shfl_xor(s2, 32, 64);
+    s2 += __shfl_xor(s2, 1, 64);
+    if (lane < 16 && !(lane & 1)) {
+      part1[(ct * 16 + lane) >> 1] += s1;
+      part2[(ct * 16 + lane) >> 1] += s2;
+    }
+  }
+}
+
+// part1[t] += Re <L1_t | X | B_t> and part2[t] += Re <L2_t | X | B_t>: one product, two adjoints.
 template <int NP, int NC, int LD, class T>
 __device__ void gemm_dot2(const T* __restrict__ X, const T* B, const T* L1, const T* L2, double* part1,
                           double* part2) {
   constexpr int RT = NP / 16, CT = NC / 16;
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, c = lane & 15;
+  const int wave = threadIdx.x >> 6;
   const T* const Bs[1] = {B};
   for (int rt = wave; rt < RT; rt += kGW) {
     typename Mfma<T>::acc_t acc[1][CT];
 #pragma unroll
     for (int ct = 0; ct < CT; ++ct) acc[0][ct] = Mfma<T>::zero();
     panel_mma<NP, NC, LD, T, 1>(X, rt, Bs, acc);
-#pragma unroll
-    for (int ct = 0; ct < CT; ++ct) {
-      double s1 = 0.0, s2 = 0.0;
-#pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        const int r = rt * 16 + Mfma<T>::row(lane, e), col = ct * 16 + c;
-        const double y = static_cast<double>(acc[0][ct][e]);
-        s1 += static_cast<double>(L1[r * LD + col]) * y;
-        s2 += static_cast<double>(L2[r * LD + col]) * y;
-      }
-      s1 += __shfl_xor(s1, 16, 64);
-      s1 += __shfl_xor(s1, 32, 64);
-      s1 += __shfl_xor(s1, 1, 64);
-      s2 += __shfl_xor(s2, 16, 64);
-      s2 += __shfl_xor(s2, 32, 64);
-      s2 += __shfl_xor(s2, 1, 64);
-      if (lane < 16 && !(lane & 1)) {
-        part1[(ct * 16 + lane) >> 1] += s1;
-        part2[(ct * 16 + lane) >> 1] += s2;
-      }
-    }
+    dot2_tile<NP, NC, LD, T>(acc[0], rt, L1, L2, part1, part2);
   }
+}
+
+// Row tiles of an NP-row product per wave.
+template <int NP>
+constexpr int rows_per_wave() { return (NP / 16 + kGW - 1) / kGW; }
+
+// Both X_g products of a step in one pass over X_g: X B (end of the step) contracted
+// with L1, L2 now (when dotB), X A (just after the basis change) left in accA for
+// gemm_dot2_finish once the adjoints have been carried back through the step.
+template <int NP, int NC, int LD, class T>
+__device__ void gemm_dot2_pair(const T* __restrict__ X, const T* B, const T* A, const T* L1, const T* L2,
+                               double* part1, double* part2, bool dotB,
+                               typename Mfma<T>::acc_t (&accA)[rows_per_wave<NP>()][NC / 16]) {
+  constexpr int RT = NP / 16, CT = NC / 16;
+  const int wave = threadIdx.x >> 6;
+  const T* const Bs[2] = {B, A};
+  int i = 0;
+  for (int rt = wave; rt < RT; rt += kGW, ++i) {
+    typename Mfma<T>::acc_t acc[2][CT];
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int ct = 0; ct < CT; ++ct) acc[b][ct] = Mfma<T>::zero();
+    panel_mma<NP, NC, LD, T, 2>(X, rt, Bs, acc);
+    if (dotB) dot2_tile<NP, NC, LD, T>(acc[0], rt, L1, L2, part1, part2);
+#pragma unroll
+    for (int ct = 0; ct < CT; ++ct) accA[i][ct] = acc[1][ct];
+  }
+}
+
+template <int NP, int NC, int LD, class T>
+__device__ void gemm_dot2_finish(const typename Mfma<T>::acc_t (&accA)[rows_per_wave<NP>()][NC / 16], const T* L1,
+                                 const T* L2, double* part1, double* part2) {
+  constexpr int RT = NP / 16;
+  const int wave = threadIdx.x >> 6;
+  int i = 0;
+  for (int rt = wave; rt < RT; rt += kGW, ++i) dot2_tile<NP, NC, LD, T>(accA[i], rt, L1, L2, part1, part2);
 }
 
 template <int NP, int TT, class T>
@@ -503,10 +550,17 @@ __global__ __launch_bounds__(kGThreads) void k_grad(GradArgs a) {
         }
       }
       __syncthreads();
-      // basis-change terms at the end of the step (the point before O_{g+1})
-      if (g < a.M - 1)
-        gemm_dot2<NP, NC, LD, T>(static_cast<const T*>(a.pX) + static_cast<size_t>(g) * NP * NP, PB, LP, LI,
-                                 &sh.part[wave][2][0], &sh.part[wave][3][0]);
+      // basis-change terms at the end of the step (the point before O_{g+1}); in FP64 the
+      // product for the point just after O_g comes from the same pass over X_g and is held
+      // in registers through the backward step (in FP32 holding it spills: a second pass)
+      constexpr bool kFusedX = sizeof(T) == 8;
+      const T* Xg = static_cast<const T*>(a.pX) + static_cast<size_t>(g) * NP * NP;
+      typename Mfma<T>::acc_t xa[kFusedX ? rows_per_wave<NP>() : 1][NC / 16];
+      if constexpr (kFusedX)
+        gemm_dot2_pair<NP, NC, LD, T>(Xg, PB, PA, LP, LI, &sh.part[wave][2][0], &sh.part[wave][3][0], g < a.M - 1,
+                                      xa);
+      else if (g < a.M - 1)
+        gemm_dot2<NP, NC, LD, T>(Xg, PB, LP, LI, &sh.part[wave][2][0], &sh.part[wave][3][0]);
       __syncthreads();
       // backward through the step, both adjoints in place
       for (int t = wave; t < TT; t += kGW) {
@@ -547,8 +601,10 @@ __global__ __launch_bounds__(kGThreads) void k_grad(GradArgs a) {
       }
       __syncthreads();
       // basis-change terms just after O_g
-      gemm_dot2<NP, NC, LD, T>(static_cast<const T*>(a.pX) + static_cast<size_t>(g) * NP * NP, PA, LP, LI,
-                               &sh.part[wave][0][0], &sh.part[wave][1][0]);
+      if constexpr (kFusedX)
+        gemm_dot2_finish<NP, NC, LD, T>(xa, LP, LI, &sh.part[wave][0][0], &sh.part[wave][1][0]);
+      else
+        gemm_dot2<NP, NC, LD, T>(Xg, PA, LP, LI, &sh.part[wave][0][0], &sh.part[wave][1][0]);
       __syncthreads();
       for (int t = tid; t < TT; t += kGThreads) {
         if (!active(t)) continue;
