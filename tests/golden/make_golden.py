@@ -13,7 +13,12 @@ It records
     eta) of that AME's final ground-state population with respect to the
     schedule control points and eta, for the 16-control-point version of the
     4-qubit ring (every parameter, --grad4) and of the 8-qubit instance (a
-    subset of the parameters, --grad8; each AME solve there takes minutes).
+    subset of the parameters, --grad8; each AME solve there takes minutes);
+  * the discretisation error of the eigenbasis scheme (--discretisation): the
+    split-step AME's final ground-state population on the workload grid and on
+    grids with 2x and 4x the steps, first-order Richardson extrapolations from
+    them, and for the 4-qubit ring also the continuous AME integrated in t
+    (discretisation.json).
 """
 import json
 import os
@@ -84,7 +89,39 @@ def fd_golden(inst, params, fname, workers):
                    "params": [[k, j] for k, j in params], "grad": [float(v) for v in vals]}, f, indent=1)
 
 
+def discretisation():
+    import time
+    from oracle import ame, spectrum
+    out = {"source": "oracle.ame.split_step at n_grid, 2 (n_grid - 1) + 1 and 4 (n_grid - 1) + 1 points; "
+                     "Richardson (first order) P_inf = 2 P_2M - P_M; oracle.ame.continuous for the 4-qubit ring",
+           "cases": []}
+    for inst in (workloads.config_small(), workloads.config_a2a8(10)):
+        steps = inst.n_grid - 1
+        row = {"instance": inst.name, "n_grid": inst.n_grid, "t_f": inst.t_f, "pgs": {}}
+        for mult in (1, 2, 4):
+            M = mult * steps + 1
+            t0 = time.time()
+            P = ame.split_step(spectrum.table_stream(inst.with_(n_grid=M)), inst.with_(n_grid=M))
+            row["pgs"][str(M)] = float(P[-1])
+            print(inst.name, M, float(P[-1]), "%.0f s" % (time.time() - t0), flush=True)
+        p1, p2, p4 = (row["pgs"][str(m * steps + 1)] for m in (1, 2, 4))
+        row["richardson_from_M_2M"] = 2 * p2 - p1
+        row["richardson_from_2M_4M"] = 2 * p4 - p2
+        row["error_at_workload_grid"] = p1 - (2 * p4 - p2)
+        if inst.n_qubits <= 4:
+            t0 = time.time()
+            row["continuous"] = float(ame.continuous(inst, [1.0])[-1])
+            row["error_vs_continuous"] = p1 - row["continuous"]
+            print(inst.name, "continuous", row["continuous"], "%.0f s" % (time.time() - t0), flush=True)
+        out["cases"].append(row)
+        with open(os.path.join(HERE, "discretisation.json"), "w") as f:
+            json.dump(out, f, indent=1)
+
+
 if __name__ == "__main__":
+    if "--discretisation" in sys.argv:
+        discretisation()
+        sys.exit(0)
     if "--grad4" in sys.argv:
         from oracle import gradient
         inst = workloads.config_small_ctrl()
