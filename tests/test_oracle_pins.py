@@ -806,3 +806,20 @@ def test_fixed_step_closed_system_is_the_no_jump_evolution():
     b = trajectories.run(tabs, inst, 3)
     assert a.kind_totals.sum() == 0
     np.testing.assert_allclose(a.final_state, b.final_state, atol=1e-12)
+
+
+def test_stored_discretisation_values_agree_with_the_stored_ame():
+    """The discretisation record's workload-grid values are the same split-step AME as the
+    stored references of the bench (two runs of the oracle, bit for bit), and finer grids
+    move the 4-qubit value towards the continuous AME."""
+    import json
+    import os
+    here = os.path.join(os.path.dirname(__file__), "golden")
+    d = {c["instance"]: c for c in json.load(open(os.path.join(here, "discretisation.json")))["cases"]}
+    a2a8 = json.load(open(os.path.join(here, "a2a8_ame_pgs.json")))
+    small = json.load(open(os.path.join(here, "small_ame_pgs.json")))
+    assert d[a2a8["instance"]]["pgs"][str(a2a8["n_grid"])] == a2a8["pgs"][-1]
+    assert d[small["instance"]]["pgs"][str(small["n_grid"])] == small["pgs"][-1]
+    r = d[small["instance"]]
+    errs = [abs(r["pgs"][k] - r["continuous"]) for k in sorted(r["pgs"], key=int)]
+    assert errs[0] > errs[1] > errs[2]
