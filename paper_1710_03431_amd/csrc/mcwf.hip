@@ -9,6 +9,8 @@
 // drawn with probability proportional to <A_i^dag A_i> (eq. Pi(t): source level b with
 // weight |c_b|^2 Gamma_b, then channel i and target a by R[i][b][a]) and renormalises.
 // The scheme is first order in h; its mean approaches the master equation as h -> 0.
+// The kernel carries the no-jump evolution unnormalised within a grid step (dp and the
+// jump draws are ratios, dp = h sum |c|^2 Gamma / sum |c|^2) and normalises at its end.
 //
 // Draws: sub-step u = (g - 1) S + s of trajectory j uses Philox draws 3u (eps), 3u + 1
 // (source) and 3u + 2 (channel and target).  Jump records carry the sub-step's start.
@@ -155,19 +157,13 @@ __global__ __launch_bounds__(kGThreads) void k_fixed_step(FixArgs a) {
         rate = wave_sum(rate);
         const double dp = h * rate / nn;
         if (!(eps < dp)) {
-          double n2 = 0.0;
+          // no jump: the decayed state stays unnormalised until the end of the grid step
+          // (dp and the jump draws use ratios; the decay over S sub-steps is bounded)
 #pragma unroll
           for (int r = 0; r < NR; ++r) {
             const double xr = dr[r] * cr[r] - di[r] * ci[r], xi = dr[r] * ci[r] + di[r] * cr[r];
             cr[r] = xr;
             ci[r] = xi;
-            n2 += xr * xr + xi * xi;
-          }
-          const double inv = 1.0 / sqrt(wave_sum(n2));
-#pragma unroll
-          for (int r = 0; r < NR; ++r) {
-            cr[r] *= inv;
-            ci[r] *= inv;
           }
           continue;
         }
@@ -274,22 +270,30 @@ __global__ __launch_bounds__(kGThreads) void k_fixed_step(FixArgs a) {
         }
         ++cnt[k];
       }
-      // end of the step: state for the next basis change, ground-cluster population
+      // end of the step: ground-cluster population, then the normalised state for the
+      // next basis change
       double pg = 0.0, nn = 0.0;
       const int gsz = a.gs[g];
 #pragma unroll
       for (int r = 0; r < NR; ++r) {
         const int x = lane + 64 * r;
-        if (x < NP) {
-          PB[x * LD + 2 * t] = static_cast<T>(cr[r]);
-          PB[x * LD + 2 * t + 1] = static_cast<T>(ci[r]);
-        }
         const double q = cr[r] * cr[r] + ci[r] * ci[r];
         nn += q;
         if (x < gsz) pg += q;
       }
       nn = wave_sum(nn);
       pg = wave_sum(pg);
+      const double inv = 1.0 / sqrt(nn);
+#pragma unroll
+      for (int r = 0; r < NR; ++r) {
+        const int x = lane + 64 * r;
+        cr[r] *= inv;
+        ci[r] *= inv;
+        if (x < NP) {
+          PB[x * LD + 2 * t] = static_cast<T>(cr[r]);
+          PB[x * LD + 2 * t + 1] = static_cast<T>(ci[r]);
+        }
+      }
       if (lane == 0) {
         const double p = pg / nn;
         s_p[t][0] = p;
