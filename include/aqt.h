@@ -175,8 +175,28 @@ AQT_API aqt_status aqt_get_dims(aqt_ctx* ctx, int32_t* n_grid, int32_t* n_levels
  * with key (seed, instance_id) and counter (trajectory id, draw >> 2, 0, 0);
  * draw 0 is the first threshold, jump m uses 3m+1, 3m+2, 3m+3.
  * Never synchronises.  Records beyond record_capacity are dropped; jump_count
- * still holds the true number of jumps of each trajectory. */
+ * still holds the true number of jumps of each trajectory.  AQT_ENUMERIC (nothing
+ * enqueued) if some level decays within one step by more than the state precision
+ * carries: Gamma_b dt_g above 500 for AQT_FP64, above 50 for AQT_FP32 and AQT_BF16
+ * (the same limit holds for aqt_run_fixed_step, aqt_grad_pgs and batches). */
 AQT_API aqt_status aqt_run(aqt_ctx* ctx, const aqt_run_params* params, const aqt_outputs* out);
+
+/* Run-status flags (bits of the word aqt_run_status reports). */
+#define AQT_RUN_RECORDS_TRUNCATED 1   /* a trajectory made more jumps than record_capacity */
+#define AQT_RUN_JUMP_LIMIT 2          /* a trajectory made AQT_MAX_JUMPS_PER_STEP jumps in one
+                                         step; its results are invalid (rates far too large
+                                         for the step length)                               */
+#define AQT_MAX_JUMPS_PER_STEP 4096
+
+/* Status of the runs enqueued on this context since the previous aqt_run_status call
+ * (aqt_run, aqt_run_fixed_step, a batch launch that includes the context).  The runs
+ * are stream-ordered and never synchronise, so their overflow conditions are collected
+ * in a device word of the context; this call synchronises the context's stream, stores
+ * the OR of the AQT_RUN_* flags in *flags (may be NULL) and clears the word.  Returns
+ * AQT_ENUMERIC if AQT_RUN_JUMP_LIMIT is set, else AQT_ECAPACITY if records were
+ * truncated (observables, jump_count and jump totals remain valid: jump_count holds the
+ * true counts), else AQT_OK. */
+AQT_API aqt_status aqt_run_status(aqt_ctx* ctx, int32_t* flags);
 
 /* ---- Fixed-step unraveling ------------------------------------------------------------
  * The second unraveling (App. B, "to jump or not to jump"): every grid step is cut into

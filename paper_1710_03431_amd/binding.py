@@ -24,10 +24,11 @@ EXPORTED = ("aqt_create", "aqt_destroy", "aqt_last_error", "aqt_version", "aqt_s
             "aqt_set_schedule", "aqt_set_bath", "aqt_precompute", "aqt_precompute_ex", "aqt_set_tables", "aqt_get_tables",
             "aqt_get_dims", "aqt_run", "aqt_grad_pgs", "aqt_set_lamb_shift", "aqt_get_lamb_shift",
             "aqt_set_bath_correlation", "aqt_set_bath_terms", "aqt_set_coupling", "aqt_get_channel_count",
-            "aqt_set_grid", "aqt_run_fixed_step",
+            "aqt_set_grid", "aqt_run_fixed_step", "aqt_run_status",
             "aqt_batch_create", "aqt_batch_launch", "aqt_batch_tiles",
             "aqt_batch_last_error", "aqt_batch_destroy")
 BATCH_GRAPH, BATCH_AUTOTUNE = 1, 2
+RUN_RECORDS_TRUNCATED, RUN_JUMP_LIMIT = 1, 2
 
 
 class Jump(C.Structure):
@@ -101,6 +102,7 @@ def load_library(path: str = LIB_PATH):
     lib.aqt_set_grid.argtypes = [ctx, C.c_int, dp]
     lib.aqt_get_channel_count.argtypes = [ctx, ip]
     lib.aqt_run_fixed_step.argtypes = [ctx, C.POINTER(RunParams), C.c_int, C.POINTER(Outputs)]
+    lib.aqt_run_status.argtypes = [ctx, ip]
     lib.aqt_get_lamb_shift.argtypes = [ctx, dp]
     lib.aqt_batch_create.argtypes = [C.POINTER(C.c_void_p), C.POINTER(C.c_void_p), C.c_int,
                                      C.POINTER(RunParams), C.POINTER(Outputs), C.c_int]
@@ -279,6 +281,16 @@ class Engine:
         return {k: v for k, v in out.items() if v is not None}
 
     # ---------------------------------------------------------------- run
+    def run_status(self) -> int:
+        """AQT_RUN_* flags of the runs since the last call (synchronises the stream).
+        Raises if a trajectory hit the per-step jump limit; truncated records are only
+        reported in the flags (observables and jump counts stay valid)."""
+        v = C.c_int32()
+        st = self.lib.aqt_run_status(self.ctx, C.byref(v))
+        if st not in (AQT_OK, AQT_ECAPACITY):
+            self._check(st)
+        return v.value
+
     def alloc_outputs(self, n_traj: int, record_capacity: int = 0, hist=(-64, 64), final_state=False,
                       per_trajectory=True):
         t = self.torch
@@ -321,9 +333,10 @@ class Engine:
         """Run K trajectories and return host numpy results (synchronises)."""
         outs = self.alloc_outputs(n_traj, record_capacity, hist, final_state)
         self.run_into(outs, n_traj, precision, seed, instance_id, traj_offset, record_capacity, tile)
-        self.stream.synchronize()
+        flags = self.run_status()
         res = {k: v.cpu().numpy() for k, v in outs.items() if k not in ("hist", "jumps")}
         res["hist_lo"] = hist[0]
+        res["records_truncated"] = bool(flags & RUN_RECORDS_TRUNCATED)
         if record_capacity:
             raw = outs["jumps"].cpu().numpy().view(JUMP_DTYPE).reshape(n_traj, record_capacity)
             res["jumps"] = raw
@@ -347,8 +360,9 @@ class Engine:
                     jump_count=ptr("jump_count"), jumps=ptr("jumps"), net_gs=ptr("net_gs"), net_hist=None,
                     hist_lo=0, hist_hi=0, final_state=ptr("final_state"))
         self._check(self.lib.aqt_run_fixed_step(self.ctx, C.byref(p), int(substeps), C.byref(o)))
-        self.stream.synchronize()
+        flags = self.run_status()
         res = {k: v.cpu().numpy() for k, v in outs.items() if k not in ("hist", "jumps")}
+        res["records_truncated"] = bool(flags & RUN_RECORDS_TRUNCATED)
         if record_capacity:
             res["jumps"] = outs["jumps"].cpu().numpy().view(JUMP_DTYPE).reshape(n_traj, record_capacity)
         if final_state:

@@ -85,7 +85,30 @@ aqt_status aqt_create(aqt_ctx** out, int device, void* hip_stream) {
     delete ctx;
     return AQT_EHIP;
   }
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, device) == hipSuccess && prop.multiProcessorCount > 0)
+    ctx->cus = prop.multiProcessorCount;
+  if (ctx->run_flags.reserve(sizeof(int)) != hipSuccess || hipMemset(ctx->run_flags.p, 0, sizeof(int)) != hipSuccess) {
+    delete ctx;
+    return AQT_ENOMEM;
+  }
   *out = ctx;
+  return AQT_OK;
+}
+
+aqt_status aqt_run_status(aqt_ctx* ctx, int32_t* flags) {
+  if (!ctx) return AQT_EINVAL;
+  aqt_status s = set_device(ctx);
+  if (s != AQT_OK) return s;
+  AQT_HIP(ctx, hipStreamSynchronize(ctx->stream));
+  int v = 0;
+  AQT_HIP(ctx, hipMemcpy(&v, ctx->run_flags.p, sizeof(int), hipMemcpyDeviceToHost));
+  AQT_HIP(ctx, hipMemset(ctx->run_flags.p, 0, sizeof(int)));
+  if (flags) *flags = v;
+  if (v & AQT_RUN_JUMP_LIMIT)
+    return ctx->fail(AQT_ENUMERIC, "a trajectory reached the limit of jumps within one step; rates too large for the step length");
+  if (v & AQT_RUN_RECORDS_TRUNCATED)
+    return ctx->fail(AQT_ECAPACITY, "jump records beyond record_capacity were dropped (jump_count holds the true counts)");
   return AQT_OK;
 }
 

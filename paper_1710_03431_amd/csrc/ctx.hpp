@@ -59,6 +59,7 @@ struct aqt_ctx {
   aqt::DevBuf dre, dim; // [M][NP] FP64 exp(-i e dt - Gamma dt / 2)
   aqt::DevBuf leak;     // [M]
   aqt::DevBuf shift;    // [M][NP] Lamb shift of each level (zeros when off); phases use E + shift
+  double max_gdt = 0.0; // largest Gamma_b dt_g of the loaded tables (decay over one step)
 
   // ---- derivative tables of the gradient (direction 0 = A(s_g), 1 = B(s_g)); full spectrum only
   bool have_grad = false;
@@ -86,6 +87,8 @@ struct aqt_ctx {
 
   // ---- run workspace
   aqt::DevBuf partial;      // [tiles][M][2] per-tile observable sums
+  aqt::DevBuf run_flags;    // int32 OR of AQT_RUN_* flags since the last aqt_run_status (allocated by aqt_create)
+  int cus = 0;              // compute units of the device (queried once by aqt_create)
 
   aqt_status fail(aqt_status s, const std::string& msg) {
     err = msg;
@@ -105,6 +108,9 @@ namespace aqt {
 // tables.hip: derive Gamma and d from E and R; pack the step operands.
 aqt_status finish_tables(aqt_ctx* ctx);
 aqt_status pack_for_precision(aqt_ctx* ctx, int precision);
+// AQT_ENUMERIC if a level decays by more than the state precision carries within one step
+// (max Gamma_b dt_g above 500 in FP64 runs, 50 in FP32 / BF16 runs).
+aqt_status check_step_decay(aqt_ctx* ctx, int precision);
 
 // step.hip: enqueue the trajectory kernel and the observable reduction.
 aqt_status launch_run(aqt_ctx* ctx, const aqt_run_params* p, const aqt_outputs* o);

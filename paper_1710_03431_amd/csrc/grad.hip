@@ -735,6 +735,10 @@ aqt_status launch_grad(aqt_ctx* ctx, const aqt_run_params* p, double* value, dou
   const int64_t K = p->n_traj;
   const int nctrl = static_cast<int>(ctx->A_ctrl.size());
   if (nctrl < 2) return ctx->fail(AQT_EINVAL, "the gradient needs at least two control points");
+  {
+    const aqt_status s = check_step_decay(ctx, p->precision);
+    if (s != AQT_OK) return s;
+  }
   const int P = 2 * nctrl + 1;
   const int NP = ctx->NP;
   hipStream_t st = ctx->stream;
@@ -809,14 +813,7 @@ aqt_status launch_grad(aqt_ctx* ctx, const aqt_run_params* p, double* value, dou
   if (!(ga.eta > 0.0)) return ctx->fail(AQT_EINVAL, "the gradient needs eta > 0");
 
   const bool f64 = p->precision == AQT_FP64;
-  int cus = 256;
-  {
-    int dev = 0;
-    hipDeviceProp_t prop;
-    if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess &&
-        prop.multiProcessorCount > 0)
-      cus = prop.multiProcessorCount;
-  }
+  const int cus = ctx->cus > 0 ? ctx->cus : 256;
   if (ctx->gpk_prec != p->precision) {
     const int M = ctx->M;
     if (static_cast<int>(ctx->sched_A.size()) != M || static_cast<int>(ctx->sched_B.size()) != M)

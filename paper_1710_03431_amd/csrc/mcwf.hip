@@ -51,6 +51,7 @@ struct FixArgs {
   int32_t* net_gs;       // [K] (may be null)
   double* final_state;   // [K][n][2] (may be null)
   int cap;
+  int* flags;            // AQT_RUN_* flags of the context (OR-ed)
   int M, n, nq, S;
   const double* tbeg;    // [M] start time of the step into grid g
   const double* tlen;    // [M] its length
@@ -256,6 +257,7 @@ __global__ __launch_bounds__(kGThreads) void k_fixed_step(FixArgs a) {
           kind = AQT_KIND_DEPHASE;
         }
         if (lane == 0) {
+          if (a.jumps && cnt[k] >= a.cap) atomicOr(a.flags, AQT_RUN_RECORDS_TRUNCATED);
           if (a.jumps && cnt[k] < a.cap) {
             aqt_jump rec;
             rec.t = a.tbeg[g] + s * h;
@@ -367,6 +369,10 @@ __global__ void k_pack_delta(const double* __restrict__ dlt, int64_t count, T* _
 }  // namespace
 
 aqt_status launch_fixed_step(aqt_ctx* ctx, const aqt_run_params* p, int substeps, const aqt_outputs* o) {
+  {
+    const aqt_status s = check_step_decay(ctx, p->precision);
+    if (s != AQT_OK) return s;
+  }
   const int NP = ctx->NP;
   const bool f64 = p->precision == AQT_FP64;
   constexpr int TT = 16;
@@ -404,6 +410,7 @@ aqt_status launch_fixed_step(aqt_ctx* ctx, const aqt_run_params* p, int substeps
   fa.net_gs = o->net_gs;
   fa.final_state = o->final_state;
   fa.cap = p->record_capacity;
+  fa.flags = ctx->run_flags.as<int>();
   fa.M = ctx->M;
   fa.n = ctx->n;
   fa.nq = ctx->tab_nch;   // jump channels

@@ -27,6 +27,7 @@
 #include <cstdint>
 #include <type_traits>
 #include <algorithm>
+#include <limits>
 #include <new>
 #include <string>
 #include <vector>
@@ -106,6 +107,7 @@ struct StepArgs {
   int64_t* net_hist;
   int hist_lo, hist_hi;
   double* final_state;
+  int* flags;            // AQT_RUN_* flags of the context (OR-ed)
 };
 
 __device__ __forceinline__ d4 mfma_k4(double a, double b, d4 c) {
@@ -232,17 +234,17 @@ __device__ __forceinline__ double xor8(double v) {
 // A crossing is handled by a segment of SEG consecutive lanes (SEG = NP when
 // NP <= 32, else the whole wavefront): a wavefront serves 64 / SEG crossings at
 // once.  Reductions, scans, ballots and broadcasts stay inside the segment.
-template <int SEG>
-__device__ __forceinline__ double seg_sum(double v) {
+template <int SEG, class V>
+__device__ __forceinline__ V seg_sum(V v) {
 #pragma unroll
   for (int o = SEG / 2; o >= 1; o >>= 1) v += __shfl_xor(v, o, kWave);
   return v;
 }
-template <int SEG>
-__device__ __forceinline__ double seg_scan(double v, int sl) {
+template <int SEG, class V>
+__device__ __forceinline__ V seg_scan(V v, int sl) {
 #pragma unroll
   for (int o = 1; o < SEG; o <<= 1) {
-    const double u = __shfl_up(v, o, SEG);
+    const V u = __shfl_up(v, o, SEG);
     if (sl >= o) v += u;
   }
   return v;
@@ -287,13 +289,24 @@ struct DrawCache {
   }
 };
 
+// Convergence of the crossing-time iteration: a step below tol * dt ends it.
+template <class H>
+__device__ constexpr H newton_tol() {
+  return sizeof(H) == 8 ? H(1e-15) : H(4.0f * 1.1920929e-7f);
+}
+
 // One wavefront finishes step g for local trajectory t whose amplitudes after
-// the fused propagator are in S (the threshold pass found sum |S|^2 <= r in the
-// state precision).  Works in FP64.
+// the fused propagator are in S (the threshold pass found the FP64 sum of |S|^2
+// at or below r).  The handler computes in the state precision H = T: FP64 runs
+// keep every step in FP64 (jump times and channels as the FP64 oracle's), mixed-
+// precision runs take the crossing time, the channel scans and the renormalisation
+// in FP32 (native exponentials, 32-bit shuffles).  The crossing test itself and
+// the observable sums stay in FP64 in every mode.
 template <int NP, class T>
 __device__ void finish_crossing(const StepArgs& a, int g, int t, int64_t jloc, TileCols<NP, T>* S,
                                 double* s_r, int* s_m, int* s_cnt, int* s_net, double* s_p,
                                 int* s_kind) {
+  using H = T;
   constexpr int SEG = (NP < kWave) ? NP : kWave;
   constexpr int PL = NP / SEG;
   const int lane = threadIdx.x & (SEG - 1);                    // lane within the segment
@@ -302,15 +315,15 @@ __device__ void finish_crossing(const StepArgs& a, int g, int t, int64_t jloc, T
   const uint64_t traj = a.traj0 + static_cast<uint64_t>(jloc);   // Philox counter word 0
   const double* Gam = a.Gamma + static_cast<size_t>(g) * NP;
   const double* Eh = a.ehalf + static_cast<size_t>(g) * NP;
-  double sr[PL], si[PL], G[PL], up[PL];
+  H sr[PL], si[PL], G[PL], up[PL];
 #pragma unroll
   for (int j = 0; j < PL; ++j) {
     const int x = lane + SEG * j;
     const bool in = x < NP;
-    G[j] = in ? Gam[x] : 0.0;
-    up[j] = in ? Eh[x] : 0.0;
-    sr[j] = in ? static_cast<double>(amp<NP, T>(S, t, 0, x)) : 0.0;
-    si[j] = in ? static_cast<double>(amp<NP, T>(S, t, 1, x)) : 0.0;
+    G[j] = in ? static_cast<H>(Gam[x]) : H(0);
+    up[j] = in ? static_cast<H>(Eh[x]) : H(0);
+    sr[j] = in ? static_cast<H>(amp<NP, T>(S, t, 0, x)) : H(0);
+    si[j] = in ? static_cast<H>(amp<NP, T>(S, t, 1, x)) : H(0);
   }
   double r = s_r[t];
   int m = s_m[t];
@@ -318,17 +331,21 @@ __device__ void finish_crossing(const StepArgs& a, int g, int t, int64_t jloc, T
   int net = s_net[t];
   const int gsz = a.gs[g];
   const double tk = a.tbeg[g];
-  // the crossing test of the whole step, in FP64: sum_b |c_b|^2 e^{-G_b dt} = sum |S|^2
+  // the crossing test of the whole step, in FP64 as in the threshold pass:
+  // sum_b |c_b|^2 e^{-G_b dt} = sum |S|^2
   double nu0 = 0.0;
 #pragma unroll
-  for (int j = 0; j < PL; ++j) nu0 += sr[j] * sr[j] + si[j] * si[j];
+  for (int j = 0; j < PL; ++j) {
+    const double xr = sr[j], xi = si[j];
+    nu0 = fma(xr, xr, fma(xi, xi, nu0));
+  }
   nu0 = seg_sum<SEG>(nu0);
   if (nu0 > r) {
-    // no crossing after all (the state-precision test was within rounding): S stays
+    // no crossing after all (the threshold pass summed in another order): S stays
     double pg = 0.0;
 #pragma unroll
     for (int j = 0; j < PL; ++j)
-      if (lane + SEG * j < gsz) pg += sr[j] * sr[j] + si[j] * si[j];
+      if (lane + SEG * j < gsz) pg += static_cast<double>(sr[j]) * sr[j] + static_cast<double>(si[j]) * si[j];
     pg = seg_sum<SEG>(pg);
     if (lane == 0) s_p[t] = pg / nu0;
     return;
@@ -336,7 +353,7 @@ __device__ void finish_crossing(const StepArgs& a, int g, int t, int64_t jloc, T
   DrawCache<SEG> draw;
   draw.fill(a.seed, a.iid, traj, 3ull * m + 1, base, lane);
   // amplitudes at the start of the step's decay: undo the fused e^{-G dt / 2}
-  double cr[PL], ci[PL];
+  H cr[PL], ci[PL];
 #pragma unroll
   for (int j = 0; j < PL; ++j) {
     cr[j] = sr[j] * up[j];
@@ -344,18 +361,19 @@ __device__ void finish_crossing(const StepArgs& a, int g, int t, int64_t jloc, T
   }
   const double* Rc = a.Rcol + static_cast<size_t>(g) * a.nq * NP * 4;
   double tau_e = 0.0;
-  for (int guard = 0; guard < 4096; ++guard) {   // jumps within one step
-    const double rem = dt - tau_e;
+  int guard = 0;
+  for (; guard < AQT_MAX_JUMPS_PER_STEP; ++guard) {   // jumps within one step
+    const H rem = static_cast<H>(dt - tau_e);
     if (guard > 0) {
       // after a jump: does the norm reach the next threshold within the rest of the step?
-      double h[PL], part = 0.0;
+      H h[PL], part = H(0);
 #pragma unroll
       for (int j = 0; j < PL; ++j) {
-        h[j] = exp(-0.5 * G[j] * rem);
+        h[j] = exp(H(-0.5) * G[j] * rem);
         part += (cr[j] * cr[j] + ci[j] * ci[j]) * (h[j] * h[j]);
       }
-      const double nu_end = seg_sum<SEG>(part);
-      if (nu_end > r) {
+      const H nu_end = seg_sum<SEG>(part);
+      if (static_cast<double>(nu_end) > r) {
 #pragma unroll
         for (int j = 0; j < PL; ++j) {
           cr[j] *= h[j];
@@ -365,42 +383,42 @@ __device__ void finish_crossing(const StepArgs& a, int g, int t, int64_t jloc, T
       }
     }
     // crossing time: Newton on log sum_b w_b e^{-G_b tau} = log r from tau = 0
-    double w[PL], hf[PL];
+    H w[PL], hf[PL];
 #pragma unroll
     for (int j = 0; j < PL; ++j) {
       w[j] = cr[j] * cr[j] + ci[j] * ci[j];
-      hf[j] = 1.0;
+      hf[j] = H(1);
     }
-    double tau = 0.0;
-    const double logr = log(r);
+    H tau = H(0);
+    const H logr = static_cast<H>(log(r));
     for (int it = 0; it < 100; ++it) {
-      double s0 = 0.0, s1 = 0.0;
+      H s0 = H(0), s1 = H(0);
 #pragma unroll
       for (int j = 0; j < PL; ++j) {
-        const double e = w[j] * (hf[j] * hf[j]);
+        const H e = w[j] * (hf[j] * hf[j]);
         s0 += e;
         s1 += G[j] * e;
       }
       s0 = seg_sum<SEG>(s0);
       s1 = seg_sum<SEG>(s1);
-      const double f = log(s0) - logr;
+      const H f = log(s0) - logr;
       // converged once the log-ratio is at rounding level: further steps only follow
-      // the noise of the sums (for a slowly decaying level that noise exceeds 1e-15 dt)
-      if (fabs(f) <= 8.0 * 2.220446049250313e-16) break;
-      const double fp = -s1 / s0;
-      if (fp == 0.0) {
+      // the noise of the sums (for a slowly decaying level that noise exceeds tol dt)
+      if (fabs(f) <= H(8) * std::numeric_limits<H>::epsilon()) break;
+      const H fp = -s1 / s0;
+      if (fp == H(0)) {
         tau = rem;
 #pragma unroll
-        for (int j = 0; j < PL; ++j) hf[j] = exp(-0.5 * G[j] * tau);
+        for (int j = 0; j < PL; ++j) hf[j] = exp(H(-0.5) * G[j] * tau);
         break;
       }
-      const double stp = -f / fp;
-      if (!(stp > 0.0)) break;
-      const double tn = fmin(tau + stp, rem);
-      const bool done = (tn - tau <= 1e-15 * dt) || (tn >= rem);
+      const H stp = -f / fp;
+      if (!(stp > H(0))) break;
+      const H tn = fmin(tau + stp, rem);
+      const bool done = (tn - tau <= newton_tol<H>() * static_cast<H>(dt)) || (tn >= rem);
       tau = tn;
 #pragma unroll
-      for (int j = 0; j < PL; ++j) hf[j] = exp(-0.5 * G[j] * tau);
+      for (int j = 0; j < PL; ++j) hf[j] = exp(H(-0.5) * G[j] * tau);
       if (done) break;
     }
 #pragma unroll
@@ -408,28 +426,28 @@ __device__ void finish_crossing(const StepArgs& a, int g, int t, int64_t jloc, T
       cr[j] *= hf[j];
       ci[j] *= hf[j];
     }
-    tau_e += tau;
-    const double u1 = draw(3ull * m + 1);
-    const double u2 = draw(3ull * m + 2);
+    tau_e += static_cast<double>(tau);
+    const H u1 = static_cast<H>(draw(3ull * m + 1));
+    const H u2 = static_cast<H>(draw(3ull * m + 2));
     // source level b: first index whose running sum of q_b Gamma_b exceeds u1 * total
     int b = -1;
     {
-      double wq[PL], carry = 0.0;
+      H wq[PL], carry = H(0);
 #pragma unroll
       for (int j = 0; j < PL; ++j) wq[j] = (cr[j] * cr[j] + ci[j] * ci[j]) * G[j];
-      double tot = 0.0;
+      H tot = H(0);
 #pragma unroll
       for (int j = 0; j < PL; ++j) tot += wq[j];
       tot = seg_sum<SEG>(tot);
-      const double thr = u1 * tot;
+      const H thr = u1 * tot;
       int lastpos = -1;
 #pragma unroll
       for (int j = 0; j < PL; ++j) {
-        const double cum = seg_scan<SEG>(wq[j], lane) + carry;
+        const H cum = seg_scan<SEG>(wq[j], lane) + carry;
         carry = __shfl(cum, base + SEG - 1, kWave);
         const uint64_t hit = seg_ballot<SEG>(cum > thr, base);
         if (b < 0 && hit) b = first_set_lane(hit) + SEG * j;
-        const uint64_t pos = seg_ballot<SEG>(wq[j] > 0.0, base);
+        const uint64_t pos = seg_ballot<SEG>(wq[j] > H(0), base);
         if (pos) lastpos = last_set_lane(pos) + SEG * j;
       }
       if (b < 0) b = lastpos;
@@ -438,7 +456,7 @@ __device__ void finish_crossing(const StepArgs& a, int g, int t, int64_t jloc, T
       // no populated level decays (a rounding-level crossing): nothing can jump
 #pragma unroll
       for (int j = 0; j < PL; ++j) {
-        const double f = exp(-0.5 * G[j] * (dt - tau_e));
+        const H f = exp(H(-0.5) * G[j] * static_cast<H>(dt - tau_e));
         cr[j] *= f;
         ci[j] *= f;
       }
@@ -450,40 +468,40 @@ __device__ void finish_crossing(const StepArgs& a, int g, int t, int64_t jloc, T
     // which selects the same (i, a) as one pass over the whole list.
     int qi = 0, ta = b;
     {
-      double rs = 0.0, rlo = 0.0, rdg = 0.0;
+      H rs = H(0), rlo = H(0), rdg = H(0);
       if (lane < a.nq) {
         const double* c4 = Rc + (static_cast<size_t>(lane) * NP + b) * 4;
-        rs = c4[0];
-        rlo = c4[1];
-        rdg = c4[2];
+        rs = static_cast<H>(c4[0]);
+        rlo = static_cast<H>(c4[1]);
+        rdg = static_cast<H>(c4[2]);
       }
-      const double cum_i = seg_scan<SEG>(rs, lane);
-      const double tot = __shfl(cum_i, base + SEG - 1, kWave);
-      const double thr = u2 * tot;
+      const H cum_i = seg_scan<SEG>(rs, lane);
+      const H tot = __shfl(cum_i, base + SEG - 1, kWave);
+      const H thr = u2 * tot;
       const uint64_t hit_i = seg_ballot<SEG>(cum_i > thr && lane < a.nq, base);
-      const uint64_t pos_i = seg_ballot<SEG>(rs > 0.0, base);
+      const uint64_t pos_i = seg_ballot<SEG>(rs > H(0), base);
       qi = hit_i ? first_set_lane(hit_i) : last_set_lane(pos_i);
       if (qi < 0) qi = 0;
-      const double before = (qi > 0) ? __shfl(cum_i, base + qi - 1, kWave) : 0.0;
-      const double lo_q = __shfl(rlo, base + qi, kWave), dg_q = __shfl(rdg, base + qi, kWave);
-      const double rel = thr - before;
+      const H before = (qi > 0) ? __shfl(cum_i, base + qi - 1, kWave) : H(0);
+      const H lo_q = __shfl(rlo, base + qi, kWave), dg_q = __shfl(rdg, base + qi, kWave);
+      const H rel = thr - before;
       if (!(rel >= lo_q && rel < lo_q + dg_q)) {
         const double* row = a.R + ((static_cast<size_t>(g) * a.nq + qi) * NP + b) * NP;
-        double v[PL];
+        H v[PL];
 #pragma unroll
         for (int j = 0; j < PL; ++j) {
           const int x = lane + SEG * j;
-          v[j] = (x < NP) ? row[x] : 0.0;
+          v[j] = (x < NP) ? static_cast<H>(row[x]) : H(0);
         }
-        double carry = before;
+        H carry = before;
         int hit = -1, lastpos = -1;
 #pragma unroll
         for (int j = 0; j < PL; ++j) {
-          const double cum = seg_scan<SEG>(v[j], lane) + carry;
+          const H cum = seg_scan<SEG>(v[j], lane) + carry;
           carry = __shfl(cum, base + SEG - 1, kWave);
           const uint64_t h = seg_ballot<SEG>(cum > thr, base);
           if (hit < 0 && h) hit = first_set_lane(h) + SEG * j;
-          const uint64_t pz = seg_ballot<SEG>(v[j] > 0.0, base);
+          const uint64_t pz = seg_ballot<SEG>(v[j] > H(0), base);
           if (pz) lastpos = last_set_lane(pz) + SEG * j;
         }
         ta = (hit >= 0) ? hit : (lastpos >= 0 ? lastpos : b);
@@ -498,8 +516,8 @@ __device__ void finish_crossing(const StepArgs& a, int g, int t, int64_t jloc, T
 #pragma unroll
       for (int j = 0; j < PL; ++j) {
         const int x = lane + SEG * j;
-        cr[j] = (x == ta) ? pr * inv : 0.0;
-        ci[j] = (x == ta) ? pim * inv : 0.0;
+        cr[j] = (x == ta) ? static_cast<H>(pr * inv) : H(0);
+        ci[j] = (x == ta) ? static_cast<H>(pim * inv) : H(0);
       }
       const double* Eg = a.E + static_cast<size_t>(g) * NP;
       kind = (Eg[ta] <= Eg[b]) ? AQT_KIND_RELAX : AQT_KIND_EXCITE;
@@ -510,23 +528,24 @@ __device__ void finish_crossing(const StepArgs& a, int g, int t, int64_t jloc, T
 #pragma unroll
       for (int j = 0; j < PL; ++j) {
         const int x = lane + SEG * j;
-        const double z = (x < NP) ? zd[x] : 0.0;
+        const H z = (x < NP) ? static_cast<H>(zd[x]) : H(0);
         cr[j] *= z;
         ci[j] *= z;
       }
       kind = AQT_KIND_DEPHASE;
     }
-    double nrm = 0.0;
+    H nrm = H(0);
 #pragma unroll
     for (int j = 0; j < PL; ++j) nrm += cr[j] * cr[j] + ci[j] * ci[j];
     nrm = seg_sum<SEG>(nrm);
-    const double inv = 1.0 / sqrt(nrm);
+    const H inv = H(1) / sqrt(nrm);
 #pragma unroll
     for (int j = 0; j < PL; ++j) {
       cr[j] *= inv;
       ci[j] *= inv;
     }
     if (lane == 0) {
+      if (a.jumps && cnt >= a.cap) atomicOr(a.flags, AQT_RUN_RECORDS_TRUNCATED);
       if (cnt < a.cap && a.jumps) {
         aqt_jump rec;
         rec.t = tk + tau_e;
@@ -543,11 +562,13 @@ __device__ void finish_crossing(const StepArgs& a, int g, int t, int64_t jloc, T
     ++m;
     r = draw(3ull * m);
   }
+  if (guard == AQT_MAX_JUMPS_PER_STEP && lane == 0) atomicOr(a.flags, AQT_RUN_JUMP_LIMIT);
   double pg = 0.0, pt = 0.0;
 #pragma unroll
   for (int j = 0; j < PL; ++j) {
     const int x = lane + SEG * j;
-    const double w2 = cr[j] * cr[j] + ci[j] * ci[j];
+    const double xr = cr[j], xi = ci[j];
+    const double w2 = xr * xr + xi * xi;
     pt += w2;
     if (x < gsz) pg += w2;
     if (x < NP) {
@@ -578,7 +599,7 @@ struct TileShared {
   static constexpr int TT = 8 * TQ;
   static constexpr int NSLOT = (NRT >= WV) ? WV : NRT;   // partial squared norms per trajectory
   TileCols<NP, T> S[TQ];
-  T nu[NSLOT][TT];
+  double nu[NSLOT][TT];   // partial squared norms, accumulated in FP64
   double r[TT];
   double p[TT];
   int m[TT], cnt[TT], net[TT];
@@ -816,13 +837,17 @@ __device__ void run_tile(const StepArgs& a, int64_t tile, TileShared<NP, TQ, typ
       }
     }
     __syncthreads();   // every wave has finished reading S
-    // ---- 2. C' = d o C and the squared norms (partial sums per wave or row tile)
+    // ---- 2. C' = d o C and the squared norms (partial sums per wave or row tile).
+    // The squares of state-precision amplitudes are exact in FP64 and every sum of
+    // them (per lane, across lanes, across slots) is taken in FP64, so the threshold
+    // test sees the norm of the stored state to FP64 rounding whatever the state
+    // precision: a compensated norm, not a state-precision running sum.
     {
       const T* dr = static_cast<const T*>(a.dre) + static_cast<size_t>(g) * NP;
       const T* di = static_cast<const T*>(a.dim) + static_cast<size_t>(g) * NP;
-      T nacc[QG];
+      double nacc[QG];
 #pragma unroll
-      for (int qq = 0; qq < QG; ++qq) nacc[qq] = T(0);
+      for (int qq = 0; qq < QG; ++qq) nacc[qq] = 0.0;
 #pragma unroll
       for (int u = 0; u < UPW; ++u) {
         if (!ok_u[u]) continue;
@@ -835,7 +860,7 @@ __device__ void run_tile(const StepArgs& a, int64_t tile, TileShared<NP, TQ, typ
         }
 #pragma unroll
         for (int qq = 0; qq < QG; ++qq) {
-          T nrm = T(0);
+          double nrm = 0.0;
 #pragma unroll
           for (int i = 0; i < 4; ++i) {
             const T y = acc[u][qq][i];
@@ -843,7 +868,8 @@ __device__ void run_tile(const StepArgs& a, int64_t tile, TileShared<NP, TQ, typ
             const T yr = part ? yp : y, yi = part ? y : yp;
             const T c = part ? (drv[i] * yi + div[i] * yr) : (drv[i] * yr - div[i] * yi);
             acc[u][qq][i] = c;
-            nrm += c * c;
+            const double cd = static_cast<double>(c);
+            nrm = fma(cd, cd, nrm);
           }
           acc_store(q0(u) + qq, rt, acc[u][qq]);
           if constexpr (kSharedQ) {
@@ -859,7 +885,7 @@ __device__ void run_tile(const StepArgs& a, int64_t tile, TileShared<NP, TQ, typ
       if constexpr (kSharedQ) {
 #pragma unroll
         for (int qq = 0; qq < QG; ++qq) {
-          T nrm = nacc[qq];
+          double nrm = nacc[qq];
           nrm += xor8(nrm);
           nrm += __shfl_xor(nrm, 16, kWave);
           nrm += __shfl_xor(nrm, 32, kWave);
@@ -874,7 +900,7 @@ __device__ void run_tile(const StepArgs& a, int64_t tile, TileShared<NP, TQ, typ
       const bool valid = tb + tid < a.K;
       double nu = 0.0;
 #pragma unroll
-      for (int sl = 0; sl < NSLOT; ++sl) nu += static_cast<double>(s_nu[sl][tid]);
+      for (int sl = 0; sl < NSLOT; ++sl) nu += s_nu[sl][tid];
       if (valid) {
         if (nu <= s_r[tid]) {
           s_list[atomicAdd(&s_nlist, 1)] = tid;
@@ -1154,16 +1180,11 @@ int choose_tq(int NP, int precision, int64_t K, int cus) {
 
 aqt_status launch_run(aqt_ctx* ctx, const aqt_run_params* p, const aqt_outputs* o) {
   const int prec = p->precision;
-  aqt_status s = pack_for_precision(ctx, prec);
+  aqt_status s = check_step_decay(ctx, prec);
   if (s != AQT_OK) return s;
-  int cus = 256;
-  {
-    int dev = 0;
-    hipDeviceProp_t prop;
-    if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess &&
-        prop.multiProcessorCount > 0)
-      cus = prop.multiProcessorCount;
-  }
+  s = pack_for_precision(ctx, prec);
+  if (s != AQT_OK) return s;
+  const int cus = ctx->cus > 0 ? ctx->cus : 256;
   const int tq = p->tile ? p->tile / 8 : choose_tq(ctx->NP, prec, p->n_traj, cus);
   if (p->tile && (p->tile % 8 || !(tq == 1 || tq == 2 || tq == 4 || tq == 5 || tq == 8) ||
                   !tq_allowed(ctx->NP, tq, prec == AQT_FP64)))
@@ -1213,6 +1234,7 @@ aqt_status launch_run(aqt_ctx* ctx, const aqt_run_params* p, const aqt_outputs* 
   a.hist_lo = o->hist_lo;
   a.hist_hi = o->hist_hi;
   a.final_state = o->final_state;
+  a.flags = ctx->run_flags.as<int>();
 
   hipError_t e;
   if (prec == AQT_FP64) e = launch_mode<ModeF64>(ctx->NP, tq, a, tiles, ctx->stream);
@@ -1434,7 +1456,8 @@ aqt_status aqt_batch_create(aqt_batch** out, aqt_ctx* const* ctxs, int n, const 
     if (params[i].tile && (params[i].tile % 8 || !batch_tq_ok(c->NP, params[i].tile / 8, b->precision)))
       return bail(b->fail(AQT_EINVAL, "unsupported tile size in batch"));
     b->max_np = std::max(b->max_np, c->NP);
-    aqt_status s = pack_for_precision(c, b->precision);
+    aqt_status s = check_step_decay(c, b->precision);
+    if (s == AQT_OK) s = pack_for_precision(c, b->precision);
     if (s != AQT_OK) return bail(b->fail(s, c->err));
   }
   if (hipStreamSynchronize(b->stream) != hipSuccess) return bail(b->fail(AQT_EHIP, "packing failed"));
@@ -1481,16 +1504,12 @@ aqt_status aqt_batch_create(aqt_batch** out, aqt_ctx* const* ctxs, int n, const 
     a.final_state = outs[i].final_state;
     a.pgs_sum = outs[i].pgs_sum;
     a.pgs_sumsq = outs[i].pgs_sumsq;
+    a.flags = c->run_flags.as<int>();
     a.TQ = 1;
     a.tiles = (a.K + 7) / 8;
     b->hargs[i] = a;
   }
-  int cus = 256;
-  {
-    hipDeviceProp_t prop;
-    if (hipGetDeviceProperties(&prop, b->device) == hipSuccess && prop.multiProcessorCount > 0)
-      cus = prop.multiProcessorCount;
-  }
+  const int cus = ctxs[0]->cus > 0 ? ctxs[0]->cus : 256;
   int occ = 1;
   const bool big = b->max_np > 64;
   if (b->precision == AQT_FP64) occ = big ? batch_occupancy<256, ModeF64>() : batch_occupancy<64, ModeF64>();

@@ -13,6 +13,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <string>
 
 #include "common.hpp"
 #include "ctx.hpp"
@@ -161,6 +162,32 @@ inline unsigned blocks_for(int64_t count, int threads = 256) {
 
 }  // namespace
 
+// Largest Gamma_b dt_g over all grid points g >= 1 and levels (one workgroup; Gamma >= 0,
+// so the maximum of the bit patterns is the maximum of the values).
+__global__ void k_max_gdt(const double* __restrict__ Gamma, const double* __restrict__ tlen, int M, int NP,
+                          double* __restrict__ out) {
+  __shared__ double red[256];
+  double v = 0.0;
+  for (int64_t i = static_cast<int64_t>(NP) + threadIdx.x; i < static_cast<int64_t>(M) * NP; i += blockDim.x)
+    v = fmax(v, Gamma[i] * tlen[i / NP]);
+  red[threadIdx.x] = v;
+  __syncthreads();
+  for (int o = blockDim.x / 2; o > 0; o >>= 1) {
+    if (threadIdx.x < o) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + o]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *out = red[0];
+}
+
+aqt_status check_step_decay(aqt_ctx* ctx, int precision) {
+  const double lim = precision == AQT_FP64 ? 500.0 : 50.0;
+  if (!(ctx->max_gdt <= lim))
+    return ctx->fail(AQT_ENUMERIC, "a level decays by Gamma dt = " + std::to_string(ctx->max_gdt) +
+                                       " within one step, beyond the " + std::to_string(lim) +
+                                       " this precision carries; use more grid points");
+  return AQT_OK;
+}
+
 aqt_status finish_tables(aqt_ctx* ctx) {
   const int M = ctx->M;
   const int64_t cnt = static_cast<int64_t>(M) * ctx->NP;
@@ -193,6 +220,15 @@ aqt_status finish_tables(aqt_ctx* ctx) {
                      ctx->shift.as<double>(), ctx->R.as<double>(), ctx->M, ctx->NP, ctx->n, ctx->tab_nch, ctx->tlen.as<double>(), ctx->Gamma.as<double>(),
                      ctx->Rcol.as<double>(), ctx->ehalf.as<double>(), ctx->dre.as<double>(), ctx->dim.as<double>());
   AQT_HIP(ctx, hipGetLastError());
+  {
+    DevBuf mx;
+    if (mx.reserve(sizeof(double)) != hipSuccess) return ctx->fail(AQT_ENOMEM, "table allocation failed");
+    hipLaunchKernelGGL(k_max_gdt, dim3(1), dim3(256), 0, ctx->stream, ctx->Gamma.as<double>(), ctx->tlen.as<double>(),
+                       ctx->M, ctx->NP, mx.as<double>());
+    AQT_HIP(ctx, hipGetLastError());
+    AQT_HIP(ctx, hipMemcpyAsync(&ctx->max_gdt, mx.p, sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+    AQT_HIP(ctx, hipStreamSynchronize(ctx->stream));
+  }
   ctx->packed_for = -1;
   ctx->fix_prec = -1;
   return AQT_OK;
