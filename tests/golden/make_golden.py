@@ -14,6 +14,13 @@ It records
     schedule control points and eta, for the 16-control-point version of the
     4-qubit ring (every parameter, --grad4) and of the 8-qubit instance (a
     subset of the parameters, --grad8; each AME solve there takes minutes);
+  * the oracle's own trajectories of the 8-qubit workload (--a2a8-traj): 10^4
+    trajectories with the workload's seed on its 2000-point grid, summarised as
+    jump totals by kind, the histograms of net jumps into the ground cluster and
+    of jump counts, the ground-cluster population sums at every grid point and
+    the full jump records of a few trajectories from both ends of the batch; and
+    the split-step AME's expected jumps per trajectory by kind (Sec. III,
+    E[dN] = <A^dag A> dt) on the same grid (a2a8_traj.json);
   * the discretisation error of the eigenbasis scheme (--discretisation): the
     split-step AME's final ground-state population on the workload grid and on
     grids with 2x and 4x the steps, first-order Richardson extrapolations from
@@ -89,6 +96,37 @@ def fd_golden(inst, params, fname, workers):
                    "params": [[k, j] for k, j in params], "grad": [float(v) for v in vals]}, f, indent=1)
 
 
+def traj_a2a8(n_traj=10_000, sample=(0, 1, 2, 3, 9996, 9997, 9998, 9999)):
+    import time
+    from oracle import ame, spectrum, trajectories
+    inst = workloads.config_a2a8(n_traj)
+    t0 = time.time()
+    res = trajectories.run(spectrum.table_stream(inst), inst, n_traj, seed=inst.seed,
+                           instance_id=inst.instance_id)
+    print("trajectories %.0f s" % (time.time() - t0), flush=True)
+    t0 = time.time()
+    expected = ame.expected_jumps(spectrum.table_stream(inst), inst)
+    print("expected jumps %.0f s" % (time.time() - t0), flush=True)
+    counts = np.array([len(j) for j in res.jumps])
+    net_vals, net_n = np.unique(res.net_gs, return_counts=True)
+    cnt_vals, cnt_n = np.unique(counts, return_counts=True)
+    out = {"source": "oracle.trajectories.run and oracle.ame.expected_jumps over "
+                     "oracle.spectrum.table_stream(workloads.config_a2a8())",
+           "instance": inst.name, "n_grid": inst.n_grid, "t_f": inst.t_f, "n_traj": n_traj,
+           "seed": inst.seed, "instance_id": inst.instance_id,
+           "kind_totals": [int(v) for v in res.kind_totals],
+           "expected_jumps_per_traj": [float(v) for v in expected],
+           "net_hist": {str(int(v)): int(c) for v, c in zip(net_vals, net_n)},
+           "count_hist": {str(int(v)): int(c) for v, c in zip(cnt_vals, cnt_n)},
+           "count_var": float(counts.var(ddof=1)),
+           "pgs_sum": [float(v) for v in res.pgs_sum],
+           "pgs_sumsq": [float(v) for v in res.pgs_sumsq],
+           "sample_jumps": {str(j): [[float(r[0]), int(r[1]), int(r[2]), int(r[3]), int(r[4]), int(r[5])]
+                                     for r in res.jumps[j]] for j in sample}}
+    with open(os.path.join(HERE, "a2a8_traj.json"), "w") as f:
+        json.dump(out, f)
+
+
 def discretisation():
     import time
     from oracle import ame, spectrum
@@ -119,6 +157,9 @@ def discretisation():
 
 
 if __name__ == "__main__":
+    if "--a2a8-traj" in sys.argv:
+        traj_a2a8()
+        sys.exit(0)
     if "--discretisation" in sys.argv:
         discretisation()
         sys.exit(0)

@@ -66,3 +66,27 @@ def sigma_bound(P, se, K):
     """Standard error of the mean, floored by the Bernoulli bound sqrt(P(1-P)/K)
     (a sample with no events yet has zero sample variance)."""
     return np.maximum(se, np.sqrt(np.clip(P * (1 - P), 0, None) / K))
+
+
+def family_z(n_points, alpha=1e-3):
+    """Two-sided normal critical value for n_points comparisons at family-wise false-alarm
+    rate alpha (Bonferroni): 4.06 for 200 points, 4.56 for 2000."""
+    from scipy.stats import norm
+    return float(norm.isf(alpha / (2.0 * n_points)))
+
+
+def assert_mean_matches(m, se, P, K, what=""):
+    """Trajectory means m (standard errors se, K trajectories) against exact means P.
+
+    Every grid point: |m - P| <= z_M sigma + 1e-4, with z_M the Bonferroni critical value
+    for the M points at a family-wise false-alarm rate of 1e-3 (the points share their
+    trajectories, so the bound is conservative); the final point, the reported value:
+    |m - P| <= 3 sigma + 1e-4.  sigma is the sample standard error floored by the
+    Bernoulli bound sqrt(P(1-P)/K), since a sample in which a rare event has not yet
+    happened has zero sample variance but not zero uncertainty."""
+    sig = sigma_bound(P, se, K)
+    err = np.abs(m - P)
+    z = family_z(len(P))
+    bad = np.nonzero(err > z * sig + 1e-4)[0]
+    assert len(bad) == 0, (what, "grid points", bad[:10], err[bad[:10]], sig[bad[:10]], z)
+    assert err[-1] <= 3.0 * sig[-1] + 1e-4, (what, "final", m[-1], P[-1], sig[-1])

@@ -120,3 +120,60 @@ def test_batch_mixes_bath_models_and_grids():
         frac = same_records(res, ref, insts[k].t_f, 1e-9)
         assert frac >= 0.999, (k, frac)
         assert np.abs(res["pgs_sum"] - ref["pgs_sum"]).max() <= (1.0 - frac) * K + 1e-6 * K
+
+
+@pytest.fixture(scope="module")
+def oracle_batch():
+    """Instances of 16 (truncated), 32 (truncated), 64 and 128 levels and the 4-qubit ring,
+    each with oracle tables handed over through aqt_set_tables."""
+    from gpu_common import engine_with_oracle_tables
+    insts = [W.pm1_all_to_all(6, 11, t_f=1500.0, n_grid=120, n_levels=16),
+             W.pm1_all_to_all(7, 12, t_f=3000.0, n_grid=150, n_levels=32),
+             W.pm1_all_to_all(6, 13, t_f=4000.0, n_grid=100),
+             W.pm1_all_to_all(7, 14, t_f=4000.0, n_grid=80),
+             W.ring_instance(4, 1001, n_grid=200)]
+    tabs = [spectrum.all_tables(i) for i in insts]
+    return insts, tabs, [engine_with_oracle_tables(i, t) for i, t in zip(insts, tabs)]
+
+
+def test_batch_fp64_matches_oracle_trajectories(oracle_batch):
+    """FP64 batch of five instances (the 64- and 128-level ones run under eight wavefronts
+    in the batched kernel) against oracle.trajectories.run on the same Philox streams
+    (key (seed, instance id)): jump records per trajectory, totals and population sums."""
+    from paper_1710_03431_amd.binding import Batch
+    from gpu_common import compare_jump_records
+    insts, tabs, engines = oracle_batch
+    runs = [dict(n_traj=200 + 41 * k, seed=31 + k, instance_id=k, record_capacity=96) for k in range(len(insts))]
+    b = Batch(engines, runs, precision="fp64", graph=True, autotune=False)
+    b.launch()
+    got = b.results()
+    for k, (r, res) in enumerate(zip(runs, got)):
+        K = r["n_traj"]
+        ref = trajectories.run(tabs[k], insts[k], K, seed=r["seed"], instance_id=k)
+        assert max(len(j) for j in ref.jumps) < r["record_capacity"]
+        frac, worst = compare_jump_records(res["jumps"], res["jump_count"], ref.jumps, insts[k].t_f)
+        assert frac >= 0.999, (k, frac, worst)
+        assert np.abs(res["pgs_sum"] - ref.pgs_sum).max() <= (1.0 - frac) * K + 1e-9 * K, k
+        if frac == 1.0:
+            np.testing.assert_array_equal(res["jump_totals"], ref.kind_totals)
+            np.testing.assert_array_equal(res["net_gs"], ref.net_gs)
+    b.close()
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+def test_batch_mixed_precision_matches_split_step_ame(oracle_batch, prec):
+    """Mixed-precision batch (graph-captured, autotuned tiles): every instance's mean at
+    every grid point against its split-step AME (bound of gpu_common.assert_mean_matches)."""
+    from paper_1710_03431_amd.binding import Batch
+    from gpu_common import assert_mean_matches
+    insts, tabs, engines = oracle_batch
+    runs = [dict(n_traj=3000 + 64 * k, seed=41 + k, instance_id=k) for k in range(len(insts))]
+    b = Batch(engines, runs, precision=prec, graph=True, autotune=True)
+    b.launch()
+    got = b.results()
+    for k, (r, res) in enumerate(zip(runs, got)):
+        K = r["n_traj"]
+        P = ame.split_step(tabs[k], insts[k])
+        m, se = trajectories.mean_and_stderr(res["pgs_sum"], res["pgs_sumsq"], K)
+        assert_mean_matches(m, se, P, K, (k, prec))
+    b.close()

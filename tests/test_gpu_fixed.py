@@ -91,3 +91,52 @@ def test_fixed_step_argument_errors(fast):
         eng.run_fixed_step(8, 0, "fp64")
     with pytest.raises(AqtError):
         eng.run_fixed_step(8, 2, "bf16")
+
+
+
+@pytest.fixture(scope="module", params=[7, 8], ids=["n128", "n256"])
+def full_fixed(request):
+    """128 and 256 levels (2 and 4 levels per lane in the sub-step loop, whose scans carry
+    across lane chunks), 4 sub-steps per grid step, 1003 trajectories, oracle tables."""
+    nq = request.param
+    inst = W.pm1_all_to_all(nq, 10 + nq - 5, t_f=1.0e4, n_grid=120)
+    tabs = spectrum.all_tables(inst)
+    K, S = 1003, 4
+    ref = trajectories.run_fixed_step(tabs, inst, K, S)
+    return inst, tabs, ref, K, S
+
+
+def test_fixed_step_fp64_per_trajectory_full_spectrum(full_fixed):
+    """Identical jump sequences in >= 99.9% of trajectories, final populations of those,
+    sums and totals through the differing ones."""
+    from gpu_common import engine_with_oracle_tables
+    inst, tabs, ref, K, S = full_fixed
+    assert ref.kind_totals[0] > 0 and ref.kind_totals[1] > 0
+    cap = max(len(j) for j in ref.jumps) + 1
+    eng = engine_with_oracle_tables(inst, tabs)
+    res = eng.run_fixed_step(K, S, "fp64", seed=inst.seed, instance_id=inst.instance_id, record_capacity=cap,
+                             final_state=True)
+    frac, worst = compare_jump_records(res["jumps"], res["jump_count"], ref.jumps, inst.t_f)
+    assert frac >= 0.999, (frac, worst)
+    bad = int(round((1.0 - frac) * K))
+    assert np.abs(res["pgs_sum"] - ref.pgs_sum).max() <= bad + 1e-9 * K
+    same = [j for j in range(K) if res["jump_count"][j] == len(ref.jumps[j])]
+    pop = (res["final_state"] ** 2).sum(axis=2).T
+    np.testing.assert_allclose(pop[:, same], (np.abs(ref.final_state) ** 2)[:, same], atol=1e-9)
+    if bad == 0:
+        np.testing.assert_array_equal(res["jump_totals"], ref.kind_totals)
+        np.testing.assert_array_equal(res["net_gs"], ref.net_gs)
+
+
+def test_fixed_step_fp32_full_spectrum_follows_oracle(full_fixed):
+    """FP32 (the benchmarked precision) on the oracle's draws: at least 97% of the
+    trajectories repeat the oracle's jump channels with sub-step start times to 1e-4
+    relative; the population sums move only through the others."""
+    from gpu_common import engine_with_oracle_tables
+    inst, tabs, ref, K, S = full_fixed
+    cap = max(len(j) for j in ref.jumps) + 1
+    eng = engine_with_oracle_tables(inst, tabs)
+    res = eng.run_fixed_step(K, S, "fp32", seed=inst.seed, instance_id=inst.instance_id, record_capacity=cap)
+    frac, _ = compare_jump_records(res["jumps"], res["jump_count"], ref.jumps, inst.t_f, rel=1e-4)
+    assert frac >= 0.97, frac
+    assert np.abs(res["pgs_sum"] - ref.pgs_sum).max() <= (1.0 - frac) * K + 1e-4 * K

@@ -107,6 +107,31 @@ def test_record_capacity_overflow_keeps_counts(small):
     np.testing.assert_array_equal(full["jump_count"], part["jump_count"])
     has = full["jump_count"] > 0
     np.testing.assert_array_equal(part["jumps"][has, 0], full["jumps"][has, 0])
+    # the overflow is reported through the context's run status (aqt_run_status)
+    assert full["jump_count"].max() > 1
+    assert not full["records_truncated"] and part["records_truncated"]
+
+
+def test_step_decay_beyond_the_precision_is_rejected():
+    """Rates far too large for the step (Gamma dt about 4e4): the decay of one step
+    underflows the state, so every run entry point refuses the tables with AQT_ENUMERIC
+    instead of stepping; a grid fine enough for the rates runs."""
+    from paper_1710_03431_amd.binding import AQT_ENUMERIC, AqtError
+    inst = W.two_level_fixed(A=0.3, t_f=1.0e4, n_grid=3, eta=1.0)
+    tabs = spectrum.all_tables(inst)
+    assert tabs[-1].Gamma.max() * tabs[-1].dt > 1e4
+    eng = engine_with_oracle_tables(inst, tabs)
+    for prec in ("fp64", "fp32"):
+        with pytest.raises(AqtError) as e:
+            eng.run(8, prec, seed=1)
+        assert e.value.status == AQT_ENUMERIC
+        with pytest.raises(AqtError) as e:
+            eng.run_fixed_step(8, 2, prec, seed=1)
+        assert e.value.status == AQT_ENUMERIC
+    fine = inst.with_(t_f=200.0, n_grid=101)
+    eng2 = engine_with_oracle_tables(fine, spectrum.all_tables(fine))
+    res = eng2.run(64, "fp32", seed=1)
+    assert res["jump_totals"].sum() > 64 and np.all(np.isfinite(res["pgs_sum"]))
 
 
 @pytest.mark.parametrize("prec", ["fp32", "bf16"])
