@@ -181,6 +181,25 @@ AQT_API aqt_status aqt_get_dims(aqt_ctx* ctx, int32_t* n_grid, int32_t* n_levels
  * (the same limit holds for aqt_run_fixed_step, aqt_grad_pgs and batches). */
 AQT_API aqt_status aqt_run(aqt_ctx* ctx, const aqt_run_params* params, const aqt_outputs* out);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc): aqt_run without any allocation.  The
+ * per-tile observable sums go to a fixed buffer of AQT_NOALLOC_SCRATCH_BYTES in device
+ * memory, one per device, set up by aqt_create and held until the process ends.
+ * Same arguments, outputs, kernels, results and stream ordering as aqt_run; the caller
+ * still provides every output buffer.  Calls no hipMalloc, hipFree or allocating
+ * library routine.  Errors (nothing enqueued):
+ *   AQT_ESTATE  the step operands of params->precision are not resident (aqt_run packs
+ *               them on its first call in a precision after the tables were loaded);
+ *   AQT_EINVAL  the run's per-tile sums, tiles x n_grid x 16 bytes with
+ *               tiles = ceil(n_traj / trajectories per workgroup), exceed the buffer
+ *               (the 8-qubit workload: 250 tiles x 2000 points = 8 MB in FP32);
+ *   otherwise as aqt_run.
+ * Every call on one device shares that device's buffer and leaves its contents from the
+ * last call (every entry a run reads it writes first): calls that overlap in time on one
+ * device (for instance on two streams) race, and must be serialised by the caller. */
+#define AQT_NOALLOC_SCRATCH_BYTES (64 * 1024 * 1024)
+AQT_API aqt_status aqt_run_noalloc(aqt_ctx* ctx, const aqt_run_params* params, const aqt_outputs* out);
+
 /* Run-status flags (bits of the word aqt_run_status reports). */
 #define AQT_RUN_RECORDS_TRUNCATED 1   /* a trajectory made more jumps than record_capacity */
 #define AQT_RUN_JUMP_LIMIT 2          /* a trajectory made AQT_MAX_JUMPS_PER_STEP jumps in one

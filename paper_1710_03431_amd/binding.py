@@ -24,7 +24,7 @@ EXPORTED = ("aqt_create", "aqt_destroy", "aqt_last_error", "aqt_version", "aqt_s
             "aqt_set_schedule", "aqt_set_bath", "aqt_precompute", "aqt_precompute_ex", "aqt_set_tables", "aqt_get_tables",
             "aqt_get_dims", "aqt_run", "aqt_grad_pgs", "aqt_set_lamb_shift", "aqt_get_lamb_shift",
             "aqt_set_bath_correlation", "aqt_set_bath_terms", "aqt_set_coupling", "aqt_get_channel_count",
-            "aqt_set_grid", "aqt_run_fixed_step", "aqt_run_status",
+            "aqt_set_grid", "aqt_run_fixed_step", "aqt_run_status", "aqt_run_noalloc",
             "aqt_batch_create", "aqt_batch_launch", "aqt_batch_tiles",
             "aqt_batch_last_error", "aqt_batch_destroy")
 BATCH_GRAPH, BATCH_AUTOTUNE = 1, 2
@@ -103,6 +103,7 @@ def load_library(path: str = LIB_PATH):
     lib.aqt_get_channel_count.argtypes = [ctx, ip]
     lib.aqt_run_fixed_step.argtypes = [ctx, C.POINTER(RunParams), C.c_int, C.POINTER(Outputs)]
     lib.aqt_run_status.argtypes = [ctx, ip]
+    lib.aqt_run_noalloc.argtypes = [ctx, C.POINTER(RunParams), C.POINTER(Outputs)]
     lib.aqt_get_lamb_shift.argtypes = [ctx, dp]
     lib.aqt_batch_create.argtypes = [C.POINTER(C.c_void_p), C.POINTER(C.c_void_p), C.c_int,
                                      C.POINTER(RunParams), C.POINTER(Outputs), C.c_int]
@@ -327,6 +328,12 @@ class Engine:
                     net_hist=ptr("net_hist"), hist_lo=int(outs["hist"][0]), hist_hi=int(outs["hist"][1]),
                     final_state=ptr("final_state"))
         self._check(self.lib.aqt_run(self.ctx, C.byref(p), C.byref(o)))
+
+    def run_noalloc_into(self, outs: dict, n_traj: int, precision="fp64", seed=0, instance_id=0, traj_offset=0,
+                         record_capacity=0, tile=0):
+        """As run_into, through aqt_run_noalloc (no device allocation by the library)."""
+        p = _params(n_traj, precision, seed, instance_id, traj_offset, record_capacity, tile)
+        self._check(self.lib.aqt_run_noalloc(self.ctx, C.byref(p), C.byref(_outputs(outs))))
 
     def run(self, n_traj: int, precision="fp64", seed=0, instance_id=0, traj_offset=0, record_capacity=0,
             tile=0, final_state=False, hist=(-64, 64)):

@@ -92,6 +92,9 @@ aqt_status aqt_create(aqt_ctx** out, int device, void* hip_stream) {
     delete ctx;
     return AQT_ENOMEM;
   }
+  // address of this device's no-allocation buffer (a failure only disables aqt_run_noalloc)
+  (void)aqt::setup_noalloc_scratch(ctx);
+  ctx->err.clear();
   *out = ctx;
   return AQT_OK;
 }
@@ -295,6 +298,20 @@ aqt_status aqt_run(aqt_ctx* ctx, const aqt_run_params* p, const aqt_outputs* o) 
   aqt_status s = set_device(ctx);
   if (s != AQT_OK) return s;
   return aqt::launch_run(ctx, p, o);
+}
+
+aqt_status aqt_run_noalloc(aqt_ctx* ctx, const aqt_run_params* p, const aqt_outputs* o) {
+  if (!ctx) return AQT_EINVAL;
+  if (!p || !o) return ctx->fail(AQT_EINVAL, "params and outputs are required");
+  if (!ctx->have_tables) return ctx->fail(AQT_ESTATE, "precompute or set_tables must come first");
+  if (p->n_traj < 1) return ctx->fail(AQT_EINVAL, "n_traj must be >= 1");
+  if (p->precision < AQT_FP64 || p->precision > AQT_BF16) return ctx->fail(AQT_EINVAL, "unknown precision");
+  if (p->record_capacity < 0) return ctx->fail(AQT_EINVAL, "record_capacity must be >= 0");
+  if (p->record_capacity > 0 && !o->jumps) return ctx->fail(AQT_EINVAL, "record_capacity > 0 needs a jumps buffer");
+  if (o->net_hist && o->hist_hi < o->hist_lo) return ctx->fail(AQT_EINVAL, "hist_hi < hist_lo");
+  aqt_status s = set_device(ctx);
+  if (s != AQT_OK) return s;
+  return aqt::launch_run_noalloc(ctx, p, o);
 }
 
 aqt_status aqt_run_fixed_step(aqt_ctx* ctx, const aqt_run_params* p, int substeps, const aqt_outputs* o) {

@@ -114,6 +114,10 @@ aqt_status check_step_decay(aqt_ctx* ctx, int precision);
 
 // step.hip: enqueue the trajectory kernel and the observable reduction.
 aqt_status launch_run(aqt_ctx* ctx, const aqt_run_params* p, const aqt_outputs* o);
+// step.hip: the same with the per-tile sums in the library's fixed device buffer (no
+// allocation); setup_noalloc_scratch takes the buffer's address once per device.
+aqt_status launch_run_noalloc(aqt_ctx* ctx, const aqt_run_params* p, const aqt_outputs* o);
+aqt_status setup_noalloc_scratch(aqt_ctx* ctx);
 
 // precompute.hip: GPU eigensystem and tables.
 aqt_status precompute_tables(aqt_ctx* ctx, int n_grid, int n_levels, double deg_tol, int method, bool grad = false);

@@ -28,6 +28,7 @@
 #include <type_traits>
 #include <algorithm>
 #include <limits>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -1178,22 +1179,25 @@ int choose_tq(int NP, int precision, int64_t K, int cus) {
   return best;
 }
 
-aqt_status launch_run(aqt_ctx* ctx, const aqt_run_params* p, const aqt_outputs* o) {
+namespace {
+
+// Column tiles per workgroup of a run (explicit or chosen); 0 for an unsupported tile.
+int run_tq(const aqt_ctx* ctx, const aqt_run_params* p) {
   const int prec = p->precision;
-  aqt_status s = check_step_decay(ctx, prec);
-  if (s != AQT_OK) return s;
-  s = pack_for_precision(ctx, prec);
-  if (s != AQT_OK) return s;
   const int cus = ctx->cus > 0 ? ctx->cus : 256;
   const int tq = p->tile ? p->tile / 8 : choose_tq(ctx->NP, prec, p->n_traj, cus);
   if (p->tile && (p->tile % 8 || !(tq == 1 || tq == 2 || tq == 4 || tq == 5 || tq == 8) ||
                   !tq_allowed(ctx->NP, tq, prec == AQT_FP64)))
-    return ctx->fail(AQT_EINVAL, "unsupported tile size for this level count and precision");
+    return 0;
+  return tq;
+}
+
+// Enqueues the trajectory kernel and the observable reduction with the per-tile sums
+// in `partial` ([tiles][M][2] doubles; every entry g >= 1 is written before it is read).
+aqt_status enqueue_run(aqt_ctx* ctx, const aqt_run_params* p, const aqt_outputs* o, int tq, double* partial) {
+  const int prec = p->precision;
   const int64_t TT = 8 * tq;
   const int64_t tiles = (p->n_traj + TT - 1) / TT;
-  const size_t need = static_cast<size_t>(tiles) * ctx->M * 2 * sizeof(double);
-  if (ctx->partial.reserve(need) != hipSuccess) return ctx->fail(AQT_ENOMEM, "workspace allocation failed");
-
   StepArgs a{};
   a.M = ctx->M;
   a.M_run = ctx->M;
@@ -1225,7 +1229,7 @@ aqt_status launch_run(aqt_ctx* ctx, const aqt_run_params* p, const aqt_outputs* 
   a.zdiag = ctx->zdiag.as<double>();
   a.E = ctx->E.as<double>();
   a.gs = ctx->gs.as<int>();
-  a.partial = ctx->partial.as<double>();
+  a.partial = partial;
   a.jump_totals = o->jump_totals;
   a.jump_count = o->jump_count;
   a.jumps = o->jumps;
@@ -1243,12 +1247,80 @@ aqt_status launch_run(aqt_ctx* ctx, const aqt_run_params* p, const aqt_outputs* 
   if (e != hipSuccess) return ctx->fail(AQT_EHIP, std::string("trajectory kernel launch: ") + hipGetErrorString(e));
   if (o->pgs_sum || o->pgs_sumsq) {
     hipLaunchKernelGGL(k_reduce_partials, dim3((ctx->M + 255) / 256), dim3(256), 0, ctx->stream,
-                       ctx->partial.as<double>(), tiles, ctx->M, static_cast<double>(p->n_traj), o->pgs_sum,
-                       o->pgs_sumsq);
+                       partial, tiles, ctx->M, static_cast<double>(p->n_traj), o->pgs_sum, o->pgs_sumsq);
     e = hipGetLastError();
     if (e != hipSuccess) return ctx->fail(AQT_EHIP, std::string("reduction launch: ") + hipGetErrorString(e));
   }
   return AQT_OK;
+}
+
+// ---------------------------------------------------------- no allocation ----
+// Per-tile observable sums of aqt_run_noalloc: a fixed buffer in device memory, one
+// copy per device (held until the process ends).  Host code never passes `scratch`
+// itself to a kernel: its device address comes from hipGetSymbolAddress, taken once
+// per device with that device current, and only that address is used.
+constexpr size_t kScratchBytes = static_cast<size_t>(AQT_NOALLOC_SCRATCH_BYTES);
+static __device__ __align__(256) double scratch[kScratchBytes / sizeof(double)];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mutex;
+void* g_scratch_ptr[kMaxDevices] = {};
+hipError_t g_scratch_err[kMaxDevices] = {};
+bool g_scratch_done[kMaxDevices] = {};
+
+}  // namespace
+
+aqt_status launch_run(aqt_ctx* ctx, const aqt_run_params* p, const aqt_outputs* o) {
+  const int prec = p->precision;
+  aqt_status s = check_step_decay(ctx, prec);
+  if (s != AQT_OK) return s;
+  s = pack_for_precision(ctx, prec);
+  if (s != AQT_OK) return s;
+  const int tq = run_tq(ctx, p);
+  if (!tq) return ctx->fail(AQT_EINVAL, "unsupported tile size for this level count and precision");
+  const int64_t tiles = (p->n_traj + 8 * tq - 1) / (8 * tq);
+  const size_t need = static_cast<size_t>(tiles) * ctx->M * 2 * sizeof(double);
+  if (ctx->partial.reserve(need) != hipSuccess) return ctx->fail(AQT_ENOMEM, "workspace allocation failed");
+  return enqueue_run(ctx, p, o, tq, ctx->partial.as<double>());
+}
+
+aqt_status setup_noalloc_scratch(aqt_ctx* ctx) {
+  const int dev = ctx->device;
+  if (dev < 0 || dev >= kMaxDevices) return ctx->fail(AQT_EINVAL, "device index beyond the scratch table");
+  std::lock_guard<std::mutex> lock(g_scratch_mutex);
+  if (!g_scratch_done[dev]) {
+    void* ptr = nullptr;
+    g_scratch_err[dev] = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));   // the device is current
+    g_scratch_ptr[dev] = (g_scratch_err[dev] == hipSuccess) ? ptr : nullptr;
+    g_scratch_done[dev] = true;
+  }
+  if (g_scratch_err[dev] != hipSuccess)
+    return ctx->fail(AQT_EHIP, std::string("scratch address: ") + hipGetErrorString(g_scratch_err[dev]));
+  return AQT_OK;
+}
+
+aqt_status launch_run_noalloc(aqt_ctx* ctx, const aqt_run_params* p, const aqt_outputs* o) {
+  const int prec = p->precision;
+  aqt_status s = check_step_decay(ctx, prec);
+  if (s != AQT_OK) return s;
+  if (ctx->packed_for != prec)
+    return ctx->fail(AQT_ESTATE, "the step operands of this precision are not resident; one aqt_run in this "
+                                 "precision after the tables were loaded packs them");
+  void* base = nullptr;
+  {
+    std::lock_guard<std::mutex> lock(g_scratch_mutex);
+    if (ctx->device >= 0 && ctx->device < kMaxDevices) base = g_scratch_ptr[ctx->device];
+  }
+  if (!base) return ctx->fail(AQT_ESTATE, "the device scratch buffer has no address (aqt_create did not set it up)");
+  const int tq = run_tq(ctx, p);
+  if (!tq) return ctx->fail(AQT_EINVAL, "unsupported tile size for this level count and precision");
+  const int64_t tiles = (p->n_traj + 8 * tq - 1) / (8 * tq);
+  const double need = static_cast<double>(tiles) * ctx->M * 2 * sizeof(double);
+  if (need > static_cast<double>(kScratchBytes))
+    return ctx->fail(AQT_EINVAL, "the run needs " + std::to_string(static_cast<long long>(need)) +
+                                     " bytes of per-tile sums (tiles x n_grid x 16), more than the " +
+                                     std::to_string(kScratchBytes) + "-byte no-allocation buffer");
+  return enqueue_run(ctx, p, o, tq, static_cast<double*>(base));
 }
 
 }  // namespace aqt
