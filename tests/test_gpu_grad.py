@@ -180,3 +180,66 @@ def test_autograd_function_matches_the_entry_point():
     np.testing.assert_allclose(A.grad.numpy(), 3.0 * ref["grad"][:m], rtol=1e-12, atol=1e-15)
     np.testing.assert_allclose(B.grad.numpy(), 3.0 * ref["grad"][m:2 * m], rtol=1e-12, atol=1e-15)
     np.testing.assert_allclose(float(eta.grad), 3.0 * ref["grad"][2 * m], rtol=1e-12)
+
+
+def _ring8():
+    """8-qubit ring (256 levels, U[-1,1] couplings) on a fast anneal with three control
+    points per schedule, B(0) > 0 and A(1) well away from zero: the smallest gap on the
+    grid is about 8e-4 rad/ns, so the oracle's central differences at h = 1e-4 are in the
+    linear regime (halving h moves every estimate by less than 1e-7 of its scale)."""
+    A = np.array([2.0 * np.pi, np.pi, 2.5])
+    B = np.array([0.6, np.pi, 2.0 * np.pi])
+    return W.ring_instance(8, 3, t_f=40.0, eta=2e-2, n_grid=30, A_ctrl=A, B_ctrl=B)
+
+
+@pytest.fixture(scope="module")
+def ring8():
+    inst = _ring8()
+    K = 27     # a ragged last tile for the FP64 (8) and FP32 (16) sweeps
+    return inst, K, gradient.trajectory_gradients(inst, K)
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", 2e-6), ("fp32", 2e-4)])
+def test_per_trajectory_gradient_256_levels(ring8, prec, tol):
+    """The 256-level sweeps (eight FP64 or sixteen FP32 trajectories per workgroup, four
+    rows per lane, chunked operand loads) per trajectory against the oracle's estimates,
+    on the trajectories whose jump sequences agree.  FP32 tolerance: unit roundoff 6e-8
+    grown over 256-term sums, 29 steps and five products per step, with a margin."""
+    inst, K, ref = ring8
+    eng = _engine(inst)
+    out = eng.grad_pgs(K, prec, seed=inst.seed, instance_id=inst.instance_id, per_trajectory=True)
+    pt = out["per_traj"]
+    P = pt.shape[1] // 2 - 1
+    assert P == len(ref["params"])
+    cap = max(len(j) for j in ref["jumps"]) + 1
+    res = eng.run(K, prec, seed=inst.seed, instance_id=inst.instance_id, record_capacity=cap)
+    rel = 1e-9 if prec == "fp64" else 1e-4
+    same = [j for j in range(K)
+            if compare_jump_records(res["jumps"][j:j + 1], res["jump_count"][j:j + 1], ref["jumps"][j:j + 1],
+                                    inst.t_f, rel=rel)[0] == 1.0]
+    assert len(same) >= (K if prec == "fp64" else K - 2), len(same)
+    assert sum(len(ref["jumps"][j]) for j in same) > 10 * len(same)
+    np.testing.assert_allclose(pt[same, 0], ref["f"][same], atol=1e-10 if prec == "fp64" else 1e-5)
+    for got, want in ((pt[same, 1:P + 1], ref["g"][same]), (pt[same, P + 2:], ref["score"][same])):
+        scale = np.maximum(np.abs(want).max(axis=0), 1e-3)
+        err = np.abs(got - want) / scale
+        assert err.max() <= tol, (err.max(axis=0), np.unravel_index(err.argmax(), err.shape))
+
+
+def test_gradient_matches_stored_ame_differences_8q():
+    """The 8-qubit workload with 16 + 16 control points (config 5): the FP32 estimate from
+    10^5 trajectories against the stored central differences of the FP64 split-step AME
+    for five parameters (tests/golden/make_golden.py --grad8), within four standard
+    errors each.  At 10^5 trajectories only eta is resolved (about 2.5 standard errors),
+    which keeps the comparison from being vacuous."""
+    import json
+    import os
+    ref = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "a2a8_ctrl16_fd_gradient.json")))
+    inst = W.config_gradient(100_000)
+    eng = _engine(inst)
+    out = eng.grad_pgs(inst.n_traj, "fp32", seed=inst.seed, instance_id=inst.instance_id)
+    m = len(inst.A_ctrl)
+    idx = [j if k == "A" else (m + j if k == "B" else 2 * m) for k, j in ref["params"]]
+    got, se, fd = out["grad"][idx], out["grad_se"][idx], np.array(ref["grad"])
+    assert np.all(np.abs(got - fd) <= 4.0 * se), (got, fd, se)
+    assert np.abs(fd[-1]) > 2.0 * se[-1]
