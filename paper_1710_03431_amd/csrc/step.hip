@@ -232,28 +232,129 @@ __device__ __forceinline__ double xor8(double v) {
   return __builtin_bit_cast(double, (static_cast<uint64_t>(static_cast<uint32_t>(hi)) << 32) | static_cast<uint32_t>(lo));
 }
 
-// A crossing is handled by a segment of SEG consecutive lanes (SEG = NP when
-// NP <= 32, else the whole wavefront): a wavefront serves 64 / SEG crossings at
-// once.  Reductions, scans, ballots and broadcasts stay inside the segment.
-template <int SEG, class V>
-__device__ __forceinline__ V seg_sum(V v) {
-#pragma unroll
-  for (int o = SEG / 2; o >= 1; o >>= 1) v += __shfl_xor(v, o, kWave);
-  return v;
+// A crossing is handled by a segment of SEG consecutive lanes (seg_width): a
+// wavefront serves 64 / SEG crossings at once.  Reductions, scans, ballots and broadcasts stay inside the segment, and
+// are built from DPP row operations (rows of 16 lanes) and row-pair swaps rather
+// than LDS-routed shuffles; every lane of a segment receives a bit-identical sum.
+template <int CTRL, int ROWS = 0xf, bool BOUND = false>
+__device__ __forceinline__ float dpp(float v) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), CTRL, ROWS, 0xf, BOUND));
+}
+template <int CTRL, int ROWS = 0xf, bool BOUND = false>
+__device__ __forceinline__ double dpp(double v) {
+  const uint64_t u = __builtin_bit_cast(uint64_t, v);
+  const int lo = __builtin_amdgcn_update_dpp(0, static_cast<int>(u & 0xffffffffu), CTRL, ROWS, 0xf, BOUND);
+  const int hi = __builtin_amdgcn_update_dpp(0, static_cast<int>(u >> 32), CTRL, ROWS, 0xf, BOUND);
+  return __builtin_bit_cast(double, (static_cast<uint64_t>(static_cast<uint32_t>(hi)) << 32) | static_cast<uint32_t>(lo));
+}
+// v + (the same register of the partner row): rows 0+1 and 2+3 (W = 16), or the two
+// halves of the wavefront (W = 32); both operands of the swap are v, so the two
+// results hold the pair's values in every lane and their sum needs no select.
+template <int W>
+__device__ __forceinline__ float swap_add(float v) {
+  const int x = __builtin_bit_cast(int, v);
+  const auto s = (W == 16) ? __builtin_amdgcn_permlane16_swap(x, x, false, false)
+                           : __builtin_amdgcn_permlane32_swap(x, x, false, false);
+  return __builtin_bit_cast(float, static_cast<int>(s[0])) + __builtin_bit_cast(float, static_cast<int>(s[1]));
+}
+template <int W>
+__device__ __forceinline__ double swap_add(double v) {
+  const uint64_t u = __builtin_bit_cast(uint64_t, v);
+  const int lo = static_cast<int>(u & 0xffffffffu), hi = static_cast<int>(u >> 32);
+  const auto sl = (W == 16) ? __builtin_amdgcn_permlane16_swap(lo, lo, false, false)
+                            : __builtin_amdgcn_permlane32_swap(lo, lo, false, false);
+  const auto sh = (W == 16) ? __builtin_amdgcn_permlane16_swap(hi, hi, false, false)
+                            : __builtin_amdgcn_permlane32_swap(hi, hi, false, false);
+  const double a = __builtin_bit_cast(double, (static_cast<uint64_t>(static_cast<uint32_t>(sh[0])) << 32) |
+                                                  static_cast<uint32_t>(sl[0]));
+  const double b = __builtin_bit_cast(double, (static_cast<uint64_t>(static_cast<uint32_t>(sh[1])) << 32) |
+                                                  static_cast<uint32_t>(sl[1]));
+  return a + b;
 }
 template <int SEG, class V>
-__device__ __forceinline__ V seg_scan(V v, int sl) {
-#pragma unroll
-  for (int o = 1; o < SEG; o <<= 1) {
-    const V u = __shfl_up(v, o, SEG);
-    if (sl >= o) v += u;
-  }
+__device__ __forceinline__ V seg_sum(V v) {
+  static_assert(SEG == 16 || SEG == 32 || SEG == 64, "segments are whole rows");
+  v += dpp<0xB1>(v);    // quad_perm [1,0,3,2]
+  v += dpp<0x4E>(v);    // quad_perm [2,3,0,1]
+  v += dpp<0x141>(v);   // row_half_mirror
+  v += dpp<0x140>(v);   // row_mirror: the row total in every lane of the row
+  if constexpr (SEG >= 32) v = swap_add<16>(v);
+  if constexpr (SEG == 64) v = swap_add<32>(v);
   return v;
+}
+// Inclusive scan over the segment's lanes in lane order.
+template <int SEG, class V>
+__device__ __forceinline__ V seg_scan(V v) {
+  static_assert(SEG == 16 || SEG == 32 || SEG == 64, "segments are whole rows");
+  v += dpp<0x111, 0xf, true>(v);   // row_shr:1 (zero shifted in)
+  v += dpp<0x112, 0xf, true>(v);   // row_shr:2
+  v += dpp<0x114, 0xf, true>(v);   // row_shr:4
+  v += dpp<0x118, 0xf, true>(v);   // row_shr:8: inclusive scan of each row
+  if constexpr (SEG >= 32) v += dpp<0x142, 0xa>(v);   // row_bcast:15 into rows 1 and 3
+  if constexpr (SEG == 64) v += dpp<0x143, 0xc>(v);   // row_bcast:31 into rows 2 and 3
+  return v;
+}
+// Lanes per crossing: one 16-lane row for up to 32 levels (four crossings per
+// wavefront), half a wavefront for 64 levels, the whole wavefront above.
+template <int NP>
+__host__ __device__ constexpr int seg_width() {
+  return NP <= 32 ? 16 : (NP == 64 ? 32 : kWave);
 }
 template <int SEG>
 __device__ __forceinline__ uint64_t seg_ballot(bool pred, int base) {
   const uint64_t m = __ballot(pred);
   return (SEG == 64) ? m : (m >> base) & ((1ull << SEG) - 1ull);
+}
+// Value of segment lane `idx` (segment-uniform) in every lane of the segment.
+template <int SEG>
+__device__ __forceinline__ float seg_read(float v, int idx, int base) {
+  if constexpr (SEG == 64) return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), idx));
+  else return __shfl(v, base + idx, kWave);
+}
+template <int SEG>
+__device__ __forceinline__ double seg_read(double v, int idx, int base) {
+  if constexpr (SEG == 64) {
+    const uint64_t u = __builtin_bit_cast(uint64_t, v);
+    const uint32_t lo = static_cast<uint32_t>(__builtin_amdgcn_readlane(static_cast<int>(u & 0xffffffffu), idx));
+    const uint32_t hi = static_cast<uint32_t>(__builtin_amdgcn_readlane(static_cast<int>(u >> 32), idx));
+    return __builtin_bit_cast(double, (static_cast<uint64_t>(hi) << 32) | lo);
+  } else {
+    return __shfl(v, base + idx, kWave);
+  }
+}
+template <int SEG>
+__device__ __forceinline__ uint32_t seg_read(uint32_t v, int idx, int base) {
+  if constexpr (SEG == 64) return static_cast<uint32_t>(__builtin_amdgcn_readlane(static_cast<int>(v), idx));
+  else return __shfl(v, base + idx, kWave);
+}
+
+// First index x = lane + SEG j (chunk-major order) whose running sum of w exceeds thr,
+// with `start` added in front; -1 if none.  Chunk totals first (independent sums),
+// then one scan of the chunk the threshold falls in (the next chunk if rounding of
+// the scan keeps it below).  Also returns the last index with w > 0 in *lastpos.
+template <int SEG, int PL, class H>
+__device__ __forceinline__ int seg_pick(const H (&w)[PL], H thr, H start, int base, int* lastpos) {
+  H tot[PL];
+#pragma unroll
+  for (int j = 0; j < PL; ++j) tot[j] = seg_sum<SEG>(w[j]);
+  H prefix = start;
+  int hit = -1, last = -1;
+#pragma unroll
+  for (int j = 0; j < PL; ++j) {
+    if (hit < 0 && prefix + tot[j] > thr) {
+      const H cum = seg_scan<SEG>(w[j]) + prefix;
+      // cum is non-decreasing, so the first index exceeding thr carries weight; the
+      // weight test only keeps a scan rounded below the chunk total from picking the
+      // next chunk's (possibly empty) first level
+      const uint64_t h = seg_ballot<SEG>(cum > thr && w[j] > H(0), base);
+      if (h) hit = first_set_lane(h) + SEG * j;
+    }
+    prefix += tot[j];
+    const uint64_t pz = seg_ballot<SEG>(w[j] > H(0), base);
+    if (pz) last = last_set_lane(pz) + SEG * j;
+  }
+  *lastpos = last;
+  return hit;
 }
 
 // Uniform draws of one trajectory served from Philox blocks computed in parallel:
@@ -283,12 +384,42 @@ struct DrawCache {
     if (rel >= static_cast<uint64_t>(SEG)) return draw_uniform(seed, iid, traj, d);
     const unsigned k = static_cast<unsigned>(d & 3);
     const uint64_t mine = k == 0 ? w0 : (k == 1 ? w1 : (k == 2 ? w2 : w3));
-    const int src = base + static_cast<int>(rel);
-    const uint32_t lo = __shfl(static_cast<uint32_t>(mine & 0xffffffffu), src, kWave);
-    const uint32_t hi = __shfl(static_cast<uint32_t>(mine >> 32), src, kWave);
+    const uint32_t lo = seg_read<SEG>(static_cast<uint32_t>(mine & 0xffffffffu), static_cast<int>(rel), base);
+    const uint32_t hi = seg_read<SEG>(static_cast<uint32_t>(mine >> 32), static_cast<int>(rel), base);
     return uniform_open01((static_cast<uint64_t>(hi) << 32) | lo);
   }
 };
+
+// Per-trajectory cache of Philox blocks in LDS: blocks rngb[t] and rngb[t] + 1 of
+// trajectory t's stream, refreshed after each crossing to B = (3 m + 1) / 4 so that the
+// draws of the next jump (3m+1, 3m+2 and the threshold 3m+3) are waiting there.  The
+// refresh of the trajectories listed after a step runs on one wavefront at the start of
+// the next step, off the crossing handler's path.
+struct RngCache {
+  uint64_t (*w)[8];
+  uint64_t* b;
+  int* list;
+  int* n;
+};
+
+// Blocks B and B + 1, B = (3 m + 1) / 4, for n trajectories (list, or 0..n-1 when list
+// is null; m = 0 when m_of is null): one wavefront, two lanes per trajectory.
+__device__ void rng_refill(const StepArgs& a, int64_t tb, int n, const int* list, const int* m_of, RngCache rc,
+                           int lane) {
+  for (int i0 = 0; i0 < 2 * n; i0 += kWave) {
+    const int i = i0 + lane;
+    if (i < 2 * n) {
+      const int t = list ? list[i >> 1] : (i >> 1);
+      const int half = i & 1;
+      const uint64_t mm = m_of ? static_cast<uint64_t>(m_of[t]) : 0ull;
+      const uint64_t B = (3ull * mm + 1ull) >> 2;
+      const Philox4 r = philox4x64_10(a.traj0 + static_cast<uint64_t>(tb + t), B + half, 0, 0, a.seed, a.iid);
+#pragma unroll
+      for (int k = 0; k < 4; ++k) rc.w[t][4 * half + k] = r.w[k];
+      if (half == 0) rc.b[t] = B;
+    }
+  }
+}
 
 // Convergence of the crossing-time iteration: a step below tol * dt ends it.
 template <class H>
@@ -306,9 +437,9 @@ __device__ constexpr H newton_tol() {
 template <int NP, class T>
 __device__ void finish_crossing(const StepArgs& a, int g, int t, int64_t jloc, TileCols<NP, T>* S,
                                 double* s_r, int* s_m, int* s_cnt, int* s_net, double* s_p,
-                                int* s_kind) {
+                                int* s_kind, RngCache rc) {
   using H = T;
-  constexpr int SEG = (NP < kWave) ? NP : kWave;
+  constexpr int SEG = seg_width<NP>();
   constexpr int PL = NP / SEG;
   const int lane = threadIdx.x & (SEG - 1);                    // lane within the segment
   const int base = (threadIdx.x & (kWave - 1)) & ~(SEG - 1);   // first lane of the segment
@@ -351,8 +482,19 @@ __device__ void finish_crossing(const StepArgs& a, int g, int t, int64_t jloc, T
     if (lane == 0) s_p[t] = pg / nu0;
     return;
   }
-  DrawCache<SEG> draw;
-  draw.fill(a.seed, a.iid, traj, 3ull * m + 1, base, lane);
+  // draws: the two cached blocks, else Philox blocks evaluated across the segment's lanes
+  const uint64_t Bc = rc.b[t];
+  DrawCache<SEG> far;
+  bool far_ready = false;
+  auto draw = [&](uint64_t d) -> double {
+    const uint64_t rel = (d >> 2) - Bc;
+    if (rel < 2) return uniform_open01(rc.w[t][4 * rel + (d & 3)]);
+    if (!far_ready) {
+      far.fill(a.seed, a.iid, traj, d, base, lane);
+      far_ready = true;
+    }
+    return far(d);
+  };
   // amplitudes at the start of the step's decay: undo the fused e^{-G dt / 2}
   H cr[PL], ci[PL];
 #pragma unroll
@@ -433,24 +575,15 @@ __device__ void finish_crossing(const StepArgs& a, int g, int t, int64_t jloc, T
     // source level b: first index whose running sum of q_b Gamma_b exceeds u1 * total
     int b = -1;
     {
-      H wq[PL], carry = H(0);
+      H wq[PL];
 #pragma unroll
       for (int j = 0; j < PL; ++j) wq[j] = (cr[j] * cr[j] + ci[j] * ci[j]) * G[j];
       H tot = H(0);
 #pragma unroll
       for (int j = 0; j < PL; ++j) tot += wq[j];
       tot = seg_sum<SEG>(tot);
-      const H thr = u1 * tot;
       int lastpos = -1;
-#pragma unroll
-      for (int j = 0; j < PL; ++j) {
-        const H cum = seg_scan<SEG>(wq[j], lane) + carry;
-        carry = __shfl(cum, base + SEG - 1, kWave);
-        const uint64_t hit = seg_ballot<SEG>(cum > thr, base);
-        if (b < 0 && hit) b = first_set_lane(hit) + SEG * j;
-        const uint64_t pos = seg_ballot<SEG>(wq[j] > H(0), base);
-        if (pos) lastpos = last_set_lane(pos) + SEG * j;
-      }
+      b = seg_pick<SEG, PL, H>(wq, u1 * tot, H(0), base, &lastpos);
       if (b < 0) b = lastpos;
     }
     if (b < 0) {
@@ -476,15 +609,15 @@ __device__ void finish_crossing(const StepArgs& a, int g, int t, int64_t jloc, T
         rlo = static_cast<H>(c4[1]);
         rdg = static_cast<H>(c4[2]);
       }
-      const H cum_i = seg_scan<SEG>(rs, lane);
-      const H tot = __shfl(cum_i, base + SEG - 1, kWave);
+      const H cum_i = seg_scan<SEG>(rs);
+      const H tot = seg_read<SEG>(cum_i, SEG - 1, base);
       const H thr = u2 * tot;
       const uint64_t hit_i = seg_ballot<SEG>(cum_i > thr && lane < a.nq, base);
       const uint64_t pos_i = seg_ballot<SEG>(rs > H(0), base);
       qi = hit_i ? first_set_lane(hit_i) : last_set_lane(pos_i);
       if (qi < 0) qi = 0;
-      const H before = (qi > 0) ? __shfl(cum_i, base + qi - 1, kWave) : H(0);
-      const H lo_q = __shfl(rlo, base + qi, kWave), dg_q = __shfl(rdg, base + qi, kWave);
+      const H before = (qi > 0) ? seg_read<SEG>(cum_i, qi - 1, base) : H(0);
+      const H lo_q = seg_read<SEG>(rlo, qi, base), dg_q = seg_read<SEG>(rdg, qi, base);
       const H rel = thr - before;
       if (!(rel >= lo_q && rel < lo_q + dg_q)) {
         const double* row = a.R + ((static_cast<size_t>(g) * a.nq + qi) * NP + b) * NP;
@@ -494,17 +627,8 @@ __device__ void finish_crossing(const StepArgs& a, int g, int t, int64_t jloc, T
           const int x = lane + SEG * j;
           v[j] = (x < NP) ? static_cast<H>(row[x]) : H(0);
         }
-        H carry = before;
-        int hit = -1, lastpos = -1;
-#pragma unroll
-        for (int j = 0; j < PL; ++j) {
-          const H cum = seg_scan<SEG>(v[j], lane) + carry;
-          carry = __shfl(cum, base + SEG - 1, kWave);
-          const uint64_t h = seg_ballot<SEG>(cum > thr, base);
-          if (hit < 0 && h) hit = first_set_lane(h) + SEG * j;
-          const uint64_t pz = seg_ballot<SEG>(v[j] > H(0), base);
-          if (pz) lastpos = last_set_lane(pz) + SEG * j;
-        }
+        int lastpos = -1;
+        const int hit = seg_pick<SEG, PL, H>(v, thr, before, base, &lastpos);
         ta = (hit >= 0) ? hit : (lastpos >= 0 ? lastpos : b);
       }
     }
@@ -585,6 +709,7 @@ __device__ void finish_crossing(const StepArgs& a, int g, int t, int64_t jloc, T
     s_m[t] = m;
     s_cnt[t] = cnt;
     s_net[t] = net;
+    if (((3ull * static_cast<uint64_t>(m) + 1ull) >> 2) != Bc) rc.list[atomicAdd(rc.n, 1)] = t;
   }
 }
 
@@ -607,6 +732,10 @@ struct TileShared {
   int list[TT];
   int nlist;
   int kind[3];
+  uint64_t rng[TT][8];   // Philox blocks of each trajectory's next draws (RngCache)
+  uint64_t rngb[TT];
+  int rfl[TT];           // trajectories whose blocks are to be refreshed
+  int nrfl;
 };
 
 template <int NP, int TQ, class Mode, int WV>
@@ -640,6 +769,7 @@ __device__ void run_tile(const StepArgs& a, int64_t tile, TileShared<NP, TQ, typ
   const int lc = lane & 15;          // MFMA output column
   const int part = (lane >> 3) & 1;  // 0: real part, 1: imaginary part
 
+  const RngCache rc{sh.rng, sh.rngb, sh.rfl, &sh.nrfl};
   if (tid < TT) {
     const int64_t j = tb + tid;
     s_r[tid] = (j < a.K) ? draw_uniform(a.seed, a.iid, a.traj0 + j, 0) : 2.0;
@@ -648,6 +778,8 @@ __device__ void run_tile(const StepArgs& a, int64_t tile, TileShared<NP, TQ, typ
     s_net[tid] = 0;
   }
   if (tid < 3) s_kind[tid] = 0;
+  if (tid == 0) sh.nrfl = 0;
+  if (wave == WV - 1) rng_refill(a, tb, TT, nullptr, nullptr, rc, lane);   // m = 0: blocks 0 and 1
 
   int rt_u[UPW], q0_u[UPW];
   bool ok_u[UPW];
@@ -706,6 +838,16 @@ __device__ void run_tile(const StepArgs& a, int64_t tile, TileShared<NP, TQ, typ
 
   for (int g = 1; g < a.M_run; ++g) {
     const int gsz = a.gs[g];
+    // Philox blocks for the trajectories that jumped in the previous step (their
+    // handlers listed them before the last barrier; this step's handlers read the
+    // blocks only after the barrier that follows the GEMM)
+    if (g > 1 && wave == 0) {
+      const int nr = __builtin_amdgcn_readfirstlane(sh.nrfl);
+      if (nr) {
+        rng_refill(a, tb, nr, sh.rfl, s_m, rc, lane);
+        if (lane == 0) sh.nrfl = 0;
+      }
+    }
     // ---- 1. C + Delta C (or the initial state at g = 1)
     if (g == 1) {
 #pragma unroll
@@ -877,8 +1019,8 @@ __device__ void run_tile(const StepArgs& a, int64_t tile, TileShared<NP, TQ, typ
             nacc[qq] += nrm;
           } else {
             nrm += xor8(nrm);
-            nrm += __shfl_xor(nrm, 16, kWave);
-            nrm += __shfl_xor(nrm, 32, kWave);
+            nrm = swap_add<16>(nrm);
+            nrm = swap_add<32>(nrm);
             if (lane < 8) s_nu[rt][(q0(u) + qq) * 8 + lane] = nrm;
           }
         }
@@ -888,8 +1030,8 @@ __device__ void run_tile(const StepArgs& a, int64_t tile, TileShared<NP, TQ, typ
         for (int qq = 0; qq < QG; ++qq) {
           double nrm = nacc[qq];
           nrm += xor8(nrm);
-          nrm += __shfl_xor(nrm, 16, kWave);
-          nrm += __shfl_xor(nrm, 32, kWave);
+          nrm = swap_add<16>(nrm);
+          nrm = swap_add<32>(nrm);
           if (lane < 8) s_nu[wave][qq * 8 + lane] = nrm;
         }
       }
@@ -923,14 +1065,14 @@ __device__ void run_tile(const StepArgs& a, int64_t tile, TileShared<NP, TQ, typ
     const int ncross = __builtin_amdgcn_readfirstlane(s_nlist);
     {
       // 64 / SEG crossings per wavefront, one per segment of SEG lanes
-      constexpr int SEG = (NP < kWave) ? NP : kWave;
+      constexpr int SEG = seg_width<NP>();
       constexpr int NSEG = kWave / SEG;
       const int seg = (tid & (kWave - 1)) / SEG;
       for (int e0 = wave * NSEG; e0 < ncross; e0 += WV * NSEG) {
         const int e = e0 + seg;
         if (e < ncross) {
           const int t = s_list[e];
-          finish_crossing<NP, T>(a, g, t, tb + t, S, s_r, s_m, s_cnt, s_net, s_p, s_kind);
+          finish_crossing<NP, T>(a, g, t, tb + t, S, s_r, s_m, s_cnt, s_net, s_p, s_kind, rc);
         }
       }
     }
@@ -941,8 +1083,8 @@ __device__ void run_tile(const StepArgs& a, int64_t tile, TileShared<NP, TQ, typ
     // ---- 4. per-tile observable sums (wave 0)
     if (wave == 0) {
       const double p = (lane < TT) ? s_p[lane] : 0.0;
-      const double sp = wave_sum(p);
-      const double sq = wave_sum(p * p);
+      const double sp = seg_sum<64>(p);
+      const double sq = seg_sum<64>(p * p);
       if (lane == 0) {
         double* dst = a.partial + (static_cast<size_t>(tile) * a.M + g) * 2;
         dst[0] = sp;
