@@ -235,6 +235,27 @@ AQT_API aqt_status aqt_run_status(aqt_ctx* ctx, int32_t* flags);
 AQT_API aqt_status aqt_run_fixed_step(aqt_ctx* ctx, const aqt_run_params* params, int substeps,
                                       const aqt_outputs* out);
 
+/* ---- Time-step bound and bound-following grids -------------------------------------------
+ * The bound of App. B (eq. B7) on the step of a trajectory integrator at time t:
+ *   min{ |H_eff| / |dH_eff/dt|, 1 / |H_eff|, |lambda / (lambda^2 - dlambda/dt)| },
+ * operator norms, H_eff = H - (i/2) sum_k A_k^dag A_k (Sec. III eq. Heff).  Readings: in the
+ * eigenbasis H_eff = diag(e - i Gamma / 2); lambda, the jump rate of a trajectory, is taken
+ * at its largest value max_b Gamma_b; time derivatives are finite differences over the
+ * probes (central inside, one-sided at the ends); no Lamb shift.  Evaluated from a
+ * full-spectrum FP64 precompute on n_probe equidistant points s_p = p / (n_probe - 1) in a
+ * scratch context (the context's own tables are left as they are), so the instance must
+ * have at most 256 basis states; clusters closer than 1e-8 rad/ns take the canonical basis
+ * of aqt_precompute.  Needs set_hamiltonian, set_schedule and set_bath (and the bath and
+ * coupling choices, which enter Gamma).  Synchronises.
+ * aqt_step_bound: bound[n_probe] (host, ns) at the probes.
+ * aqt_bound_grid: s[n_grid] (host), 0 = s_0 < ... < s_{n_grid-1} = 1, with local density
+ * proportional to 1 / bound: s_g solves F(s_g) = g F(1) / (n_grid - 1), F the trapezoid
+ * integral of 1 / bound over the probes, inverted by linear interpolation.  Pass it to
+ * aqt_set_grid before aqt_precompute.  AQT_ENUMERIC if the bound is not positive and finite
+ * or the grid does not increase (use more probes). */
+AQT_API aqt_status aqt_step_bound(aqt_ctx* ctx, int n_probe, double* bound);
+AQT_API aqt_status aqt_bound_grid(aqt_ctx* ctx, int n_grid, int n_probe, double* s);
+
 /* ---- Correlated baths -----------------------------------------------------------------
  * Baths with gamma_ab(w) = C_ab gamma(w) (Sec. II eq. ME2-L with a frequency-independent
  * correlation between the qubits' baths; the Lamb shift, when on, uses C_ab S(w) alike).

@@ -25,6 +25,7 @@ EXPORTED = ("aqt_create", "aqt_destroy", "aqt_last_error", "aqt_version", "aqt_s
             "aqt_get_dims", "aqt_run", "aqt_grad_pgs", "aqt_set_lamb_shift", "aqt_get_lamb_shift",
             "aqt_set_bath_correlation", "aqt_set_bath_terms", "aqt_set_coupling", "aqt_get_channel_count",
             "aqt_set_grid", "aqt_run_fixed_step", "aqt_run_status", "aqt_run_noalloc",
+            "aqt_step_bound", "aqt_bound_grid",
             "aqt_batch_create", "aqt_batch_launch", "aqt_batch_tiles",
             "aqt_batch_last_error", "aqt_batch_destroy")
 BATCH_GRAPH, BATCH_AUTOTUNE = 1, 2
@@ -104,6 +105,8 @@ def load_library(path: str = LIB_PATH):
     lib.aqt_run_fixed_step.argtypes = [ctx, C.POINTER(RunParams), C.c_int, C.POINTER(Outputs)]
     lib.aqt_run_status.argtypes = [ctx, ip]
     lib.aqt_run_noalloc.argtypes = [ctx, C.POINTER(RunParams), C.POINTER(Outputs)]
+    lib.aqt_step_bound.argtypes = [ctx, C.c_int, dp]
+    lib.aqt_bound_grid.argtypes = [ctx, C.c_int, C.c_int, dp]
     lib.aqt_get_lamb_shift.argtypes = [ctx, dp]
     lib.aqt_batch_create.argtypes = [C.POINTER(C.c_void_p), C.POINTER(C.c_void_p), C.c_int,
                                      C.POINTER(RunParams), C.POINTER(Outputs), C.c_int]
@@ -219,6 +222,18 @@ class Engine:
             return
         s = _f64(s)
         self._check(self.lib.aqt_set_grid(self.ctx, len(s), _dptr(s)))
+
+    def step_bound(self, n_probe: int):
+        """App. B time-step bound (ns) at n_probe equidistant s points (aqt_step_bound)."""
+        out = np.zeros(int(n_probe))
+        self._check(self.lib.aqt_step_bound(self.ctx, int(n_probe), _dptr(out)))
+        return out
+
+    def bound_grid(self, n_grid: int, n_probe: int = 401):
+        """Grid of n_grid points following the App. B bound (aqt_bound_grid); not applied."""
+        out = np.zeros(int(n_grid))
+        self._check(self.lib.aqt_bound_grid(self.ctx, int(n_grid), int(n_probe), _dptr(out)))
+        return out
 
     def channel_count(self) -> int:
         v = C.c_int32()

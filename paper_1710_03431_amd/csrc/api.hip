@@ -501,6 +501,39 @@ aqt_status aqt_set_grid(aqt_ctx* ctx, int n_grid, const double* s) {
   return AQT_OK;
 }
 
+static aqt_status bound_checks(aqt_ctx* ctx, int n_probe) {
+  if (!ctx->have_h || !ctx->have_sched || !ctx->have_bath)
+    return ctx->fail(AQT_ESTATE, "set_hamiltonian, set_schedule and set_bath must come first");
+  if (ctx->nq > 8) return ctx->fail(AQT_EINVAL, "the step bound needs the full spectrum: at most 8 qubits");
+  if (n_probe < 3 || n_probe > 100000) return ctx->fail(AQT_EINVAL, "n_probe must be in [3, 100000]");
+  return set_device(ctx);
+}
+
+aqt_status aqt_step_bound(aqt_ctx* ctx, int n_probe, double* bound) {
+  if (!ctx) return AQT_EINVAL;
+  if (!bound) return ctx->fail(AQT_EINVAL, "bound must not be null");
+  aqt_status s = bound_checks(ctx, n_probe);
+  if (s != AQT_OK) return s;
+  std::vector<double> b;
+  s = aqt::step_bound(ctx, n_probe, 1e-8, b);
+  if (s != AQT_OK) return s;
+  std::copy(b.begin(), b.end(), bound);
+  return AQT_OK;
+}
+
+aqt_status aqt_bound_grid(aqt_ctx* ctx, int n_grid, int n_probe, double* sg) {
+  if (!ctx) return AQT_EINVAL;
+  if (!sg) return ctx->fail(AQT_EINVAL, "s must not be null");
+  if (n_grid < 2) return ctx->fail(AQT_EINVAL, "n_grid must be >= 2");
+  aqt_status s = bound_checks(ctx, n_probe);
+  if (s != AQT_OK) return s;
+  std::vector<double> out(n_grid);
+  s = aqt::bound_grid(ctx, n_grid, n_probe, 1e-8, out.data());
+  if (s != AQT_OK) return s;
+  std::copy(out.begin(), out.end(), sg);
+  return AQT_OK;
+}
+
 aqt_status aqt_get_channel_count(aqt_ctx* ctx, int32_t* n_channels) {
   if (!ctx || !n_channels) return AQT_EINVAL;
   *n_channels = ctx->have_tables ? ctx->tab_nch : ctx->nch();

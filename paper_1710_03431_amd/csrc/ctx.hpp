@@ -122,6 +122,11 @@ aqt_status setup_noalloc_scratch(aqt_ctx* ctx);
 // precompute.hip: GPU eigensystem and tables.
 aqt_status precompute_tables(aqt_ctx* ctx, int n_grid, int n_levels, double deg_tol, int method, bool grad = false);
 
+// grid.hip: the App. B time-step bound at n_probe equidistant points (full spectrum,
+// from a scratch precompute) and the grid that equidistributes it.
+aqt_status step_bound(aqt_ctx* ctx, int n_probe, double deg_tol, std::vector<double>& bound);
+aqt_status bound_grid(aqt_ctx* ctx, int n_grid, int n_probe, double deg_tol, double* s_out);
+
 // mcwf.hip: fixed-step unraveling.
 aqt_status launch_fixed_step(aqt_ctx* ctx, const aqt_run_params* p, int substeps, const aqt_outputs* o);
 

@@ -105,3 +105,46 @@ def test_grid_argument_errors_and_equidistant_default():
     eng.precompute(21, 8)
     b = eng.run(256, "fp64", seed=3)
     np.testing.assert_allclose(a["pgs_sum"], b["pgs_sum"], rtol=1e-9)
+
+
+@pytest.mark.parametrize("case", ["ring3", "pm1_6q", "ring4_bath_terms"])
+def test_library_step_bound_and_grid_match_the_oracle(case):
+    """aqt_step_bound and aqt_bound_grid (App. B eq. B7) against oracle.spectrum.step_bound
+    and bound_grid: the bound at every probe to 1e-8 relative (the library's operator norm
+    comes from a power iteration stopped at 1e-13 in the squared norm), the grid points to
+    1e-8.  Bath terms enter through the decay rates."""
+    insts = {"ring3": W.ring_instance(3, 8, t_f=1.5, eta=0.1, n_grid=61),
+             "pm1_6q": W.pm1_all_to_all(6, 11, t_f=40.0, eta=1e-3, n_grid=61),
+             "ring4_bath_terms": W.ring_instance(4, 1001, t_f=30.0, eta=1e-2, n_grid=41,
+                                                 bath_terms=W.two_term_bath(4))}
+    inst = insts[case]
+    P = 121
+    from paper_1710_03431_amd.binding import Engine
+    eng = Engine(0)
+    eng.set_instance(inst)
+    got = eng.step_bound(P)
+    want = spectrum.step_bound(inst, np.linspace(0.0, 1.0, P))
+    np.testing.assert_allclose(got, want, rtol=1e-8)
+    g = eng.bound_grid(inst.n_grid, P)
+    np.testing.assert_allclose(g, spectrum.bound_grid(inst, inst.n_grid, n_probe=P), rtol=0, atol=1e-8)
+    assert np.diff(g).max() > 1.2 * np.diff(g).min()
+    # the grid is only returned: the context's own grid and tables are untouched
+    eng.set_grid(g)
+    eng.precompute(inst.n_grid, inst.levels)
+    assert eng.get_tables(("E",))["E"].shape == (inst.n_grid, inst.levels)
+
+
+def test_library_bound_grid_argument_errors():
+    from paper_1710_03431_amd.binding import AqtError, Engine
+    eng = Engine(0)
+    with pytest.raises(AqtError):
+        eng.step_bound(11)                          # nothing set
+    inst = W.pm1_all_to_all(9, 11, t_f=40.0, n_grid=11)
+    eng.set_instance(inst)
+    with pytest.raises(AqtError):
+        eng.step_bound(11)                          # 512 basis states: beyond the full-spectrum limit
+    eng.set_instance(W.ring_instance(3, 8, t_f=1.5, eta=0.1, n_grid=61))
+    with pytest.raises(AqtError):
+        eng.step_bound(2)
+    with pytest.raises(AqtError):
+        eng.bound_grid(1, 11)
