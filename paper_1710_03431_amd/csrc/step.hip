@@ -870,12 +870,29 @@ __device__ void run_tile(const StepArgs& a, int64_t tile, TileShared<NP, TQ, typ
           if ((dirty >> (q0(u) + qq)) & 1u) acc_load(q0(u) + qq, rt_u[u], acc[u][qq]);
       }
     }
+    // the step's phase factors, loaded ahead of the GEMM (used by the epilogue)
+    T dpre[UPW][4], dpim[UPW][4];
+    {
+      const T* dr = static_cast<const T*>(a.dre) + static_cast<size_t>(g) * NP;
+      const T* di = static_cast<const T*>(a.dim) + static_cast<size_t>(g) * NP;
+#pragma unroll
+      for (int u = 0; u < UPW; ++u)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          dpre[u][i] = dr[rt_u[u] * 16 + Mode::row(lane, i)];
+          dpim[u][i] = di[rt_u[u] * 16 + Mode::row(lane, i)];
+        }
+    }
     if (g > 1) {
       T bnx[QG];
       if constexpr (Mode::KC == 4 && kSharedQ) {
 #pragma unroll
         for (int qq = 0; qq < QG; ++qq) bnx[qq] = S[qq][lc][lane >> 4];
       }
+      // two FP32 wavefronts share each SIMD: the scheduler favours the older one, which then
+      // finishes its share early and leaves the younger one to run the tail of the GEMM
+      // alone; raising the younger one's priority keeps both issuing to the end
+      if (WV == 8 && sizeof(T) == 4 && wave >= 4) __builtin_amdgcn_s_setprio(1);
       for (int kc = 0; kc < NKC; kc += PF) {
 #pragma unroll
         for (int s2 = 0; s2 < PF; ++s2) {
@@ -979,6 +996,7 @@ __device__ void run_tile(const StepArgs& a, int64_t tile, TileShared<NP, TQ, typ
         }
       }
     }
+    if (WV == 8 && sizeof(T) == 4) __builtin_amdgcn_s_setprio(0);
     __syncthreads();   // every wave has finished reading S
     // ---- 2. C' = d o C and the squared norms (partial sums per wave or row tile).
     // The squares of state-precision amplitudes are exact in FP64 and every sum of
@@ -986,8 +1004,6 @@ __device__ void run_tile(const StepArgs& a, int64_t tile, TileShared<NP, TQ, typ
     // test sees the norm of the stored state to FP64 rounding whatever the state
     // precision: a compensated norm, not a state-precision running sum.
     {
-      const T* dr = static_cast<const T*>(a.dre) + static_cast<size_t>(g) * NP;
-      const T* di = static_cast<const T*>(a.dim) + static_cast<size_t>(g) * NP;
       double nacc[QG];
 #pragma unroll
       for (int qq = 0; qq < QG; ++qq) nacc[qq] = 0.0;
@@ -998,8 +1014,8 @@ __device__ void run_tile(const StepArgs& a, int64_t tile, TileShared<NP, TQ, typ
         T drv[4], div[4];
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
-          drv[i] = dr[rt * 16 + Mode::row(lane, i)];
-          div[i] = di[rt * 16 + Mode::row(lane, i)];
+          drv[i] = dpre[u][i];
+          div[i] = dpim[u][i];
         }
 #pragma unroll
         for (int qq = 0; qq < QG; ++qq) {

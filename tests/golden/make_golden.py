@@ -21,6 +21,13 @@ It records
     the full jump records of a few trajectories from both ends of the batch; and
     the split-step AME's expected jumps per trajectory by kind (Sec. III,
     E[dN] = <A^dag A> dt) on the same grid (a2a8_traj.json);
+  * the split-step AME ground-state population of the first eight instances of the
+    batched workload (every tenth grid point and the last), the reference for the
+    batched launch's per-instance errors (--batched; batched_ame_pgs.json);
+  * the split-step AME ground-cluster population of the 16-qubit gadget truncated to its
+    32 lowest canonical levels, on its 500-point grid (--gadget; gadget16_ame_pgs.json):
+    the same tables as oracle.spectrum.table_stream, with the per-grid-point Lanczos
+    solves spread over worker processes;
   * the discretisation error of the eigenbasis scheme (--discretisation): the
     split-step AME's final ground-state population on the workload grid and on
     grids with 2x and 4x the steps, first-order Richardson extrapolations from
@@ -127,6 +134,83 @@ def traj_a2a8(n_traj=10_000, sample=(0, 1, 2, 3, 9996, 9997, 9998, 9999)):
         json.dump(out, f)
 
 
+def _batched_worker(k):
+    os.environ.setdefault("OMP_NUM_THREADS", "1")
+    from oracle import ame, spectrum
+    inst = workloads.config_batched()[k]
+    P = ame.split_step(spectrum.table_stream(inst), inst)
+    return k, inst.name, [float(v) for v in P]
+
+
+def batched_ame(count=8):
+    from concurrent.futures import ProcessPoolExecutor
+    with ProcessPoolExecutor(max_workers=count) as ex:
+        rows = list(ex.map(_batched_worker, range(count)))
+    insts = workloads.config_batched()
+    out = {"source": "oracle.ame.split_step over oracle.spectrum.table_stream(workloads.config_batched()[k])",
+           "stride": 10, "instances": []}
+    for k, name, P in rows:
+        M = insts[k].n_grid
+        idx = list(range(0, M, 10)) + ([M - 1] if (M - 1) % 10 else [])
+        out["instances"].append({"index": k, "name": name, "n_grid": M, "t_f": insts[k].t_f,
+                                 "grid_points": idx, "pgs": [P[i] for i in idx]})
+    with open(os.path.join(HERE, "batched_ame_pgs.json"), "w") as f:
+        json.dump(out, f, indent=0)
+
+
+def _gadget_eigen(args):
+    os.environ.setdefault("OMP_NUM_THREADS", "1")
+    inst, s, n = args
+    from oracle import spectrum
+    E, V, gs = spectrum.eigen(inst, s, n, 1e-8)
+    return E, V, gs
+
+
+def gadget_ame(workers=8):
+    """oracle.ame.split_step over the tables oracle.spectrum.table_stream builds for the
+    gadget, with the eigensolves of the grid points computed ahead in worker processes
+    (same function, same arguments, consumed in grid order)."""
+    import time
+    from concurrent.futures import ProcessPoolExecutor
+    from oracle import ame, spectrum
+    inst = workloads.config_gadget(10)
+    M, n = inst.n_grid, inst.levels
+    dt = inst.t_f / (M - 1)
+
+    def tables():
+        with ProcessPoolExecutor(max_workers=workers) as ex:
+            it = ex.map(_gadget_eigen, [(inst, g / (M - 1), max(n, 1)) for g in range(M)], chunksize=1)
+            E0, V0, gs0 = next(it)
+            if gs0 != 1:
+                raise ValueError("degenerate ground state at s = 0")
+            psi0 = V0[:, 0]
+            Vprev = None
+            t0 = time.time()
+            for g, (E, V, gs) in enumerate(it, start=1):
+                if g == 1:
+                    c = V.T @ psi0
+                    leak = 1.0 - float(c @ c)
+                    cinit, O = c / np.linalg.norm(c), None
+                else:
+                    O, S = spectrum.polar(V.T @ Vprev)
+                    leak = 1.0 - float(S.min()) ** 2
+                    cinit = None
+                z, R, Gamma, zdiag, d, shift = spectrum.grid_tables(inst, E, V, dt)
+                Vprev = V
+                if g % 25 == 0:
+                    print("gadget grid point %d of %d, %.0f s" % (g, M - 1, time.time() - t0), flush=True)
+                yield spectrum.GridTables(g=g, s=g / (M - 1), E=E, gs=gs, O=O, cinit=cinit, z=z, R=R, Gamma=Gamma,
+                                          zdiag=zdiag, d=d, leak=leak, V=None, shift=shift, dt=dt,
+                                          t0=(g - 1) * dt)
+
+    P, leaks = [], []
+    pgs = ame.split_step(tables(), inst)
+    with open(os.path.join(HERE, "gadget16_ame_pgs.json"), "w") as f:
+        json.dump({"source": "oracle.ame.split_step over the tables of oracle.spectrum.table_stream("
+                             "workloads.config_gadget())", "instance": inst.name, "n_grid": M, "n_levels": n,
+                   "t_f": inst.t_f, "pgs": [float(v) for v in pgs]}, f)
+
+
 def discretisation():
     import time
     from oracle import ame, spectrum
@@ -157,6 +241,12 @@ def discretisation():
 
 
 if __name__ == "__main__":
+    if "--gadget" in sys.argv:
+        gadget_ame()
+        sys.exit(0)
+    if "--batched" in sys.argv:
+        batched_ame()
+        sys.exit(0)
     if "--a2a8-traj" in sys.argv:
         traj_a2a8()
         sys.exit(0)
