@@ -101,6 +101,11 @@ def load_ame_reference(name):
         return json.load(f)
 
 
+def same_grid_as_models(inst):
+    """The stored model references are on the workload's own grid."""
+    return inst.n_grid == 2000 and inst.t_f == 1.0e4
+
+
 def converged_error(inst, results):
     """Error of each path's P_GS(1) against the grid-converged AME: the first-order
     Richardson value from the split-step AME on 2x and 4x the steps
@@ -448,8 +453,17 @@ def main():
         q = inst.n_qubits
         inst = inst.with_(coupling=(np.vstack([np.eye(q), np.zeros((q, q))]),
                                     np.vstack([np.zeros((q, q)), np.eye(q)]), None))
-    if args.lamb_shift or args.bath_corr is not None or args.bath_terms is not None or args.zx_coupling:
-        wl["golden"] = None   # the stored AME references are for independent baths without the Lamb shift
+    switches = [k for k, on in (("lamb_shift", args.lamb_shift), (f"bath_corr_{args.bath_corr}", args.bath_corr is not None),
+                                (f"bath_terms_{args.bath_terms}", args.bath_terms is not None),
+                                ("zx_coupling", args.zx_coupling)) if on]
+    model_ref = None
+    if switches:
+        # the default references hold independent baths without the Lamb shift; one switch on
+        # the 8-qubit workload has its own stored AME (tests/golden/a2a8_models_ame_pgs.json)
+        wl["golden"] = None
+        models = load_ame_reference("a2a8_models_ame_pgs.json") if args.workload == "a2a8" else None
+        if models and len(switches) == 1 and switches[0] in models["models"] and same_grid_as_models(inst):
+            model_ref = models["models"][switches[0]][-1]
     K = inst.n_traj
     M = inst.n_grid
     n = inst.levels
@@ -461,7 +475,7 @@ def main():
     print(f"# precompute {precompute_s:.2f} s ({inst.name}, n={n}, M={M})", file=sys.stderr, flush=True)
 
     ref = load_ame_reference(wl["golden"])
-    p_ame = ref["pgs"][-1] if ref else None
+    p_ame = ref["pgs"][-1] if ref else model_ref
     results = {}
     for prec in (args.precisions or wl["precisions"]).split(","):
         r = time_precision(eng, torch, K, prec, args.steps, args.warmup, seed=inst.seed)

@@ -1534,7 +1534,9 @@ hipError_t enqueue_batch(const aqt_batch* b, const StepArgs* dargs, const BatchI
 template <int MaxNP, class Mode>
 int batch_occupancy() {
   int blocks = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_batch<MaxNP, Mode>, 256, 0) != hipSuccess) return 1;
+  // occupancy of the block size the launch uses (kBatchWaves wavefronts)
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_batch<MaxNP, Mode>, kBatchWaves * 64, 0) != hipSuccess)
+    return 1;
   return blocks > 0 ? blocks : 1;
 }
 

@@ -28,6 +28,10 @@ It records
     32 lowest canonical levels, on its 500-point grid (--gadget; gadget16_ame_pgs.json):
     the same tables as oracle.spectrum.table_stream, with the per-grid-point Lanczos
     solves spread over worker processes;
+  * the split-step AME of the 8-qubit workload under the bench's model switches -- Lamb
+    shift, correlated baths 0.5^|a-b|, bath terms (rho = 0.5), sz and sx couplings on
+    every qubit (--a2a8-models; a2a8_models_ame_pgs.json: every tenth grid point and the
+    last);
   * the discretisation error of the eigenbasis scheme (--discretisation): the
     split-step AME's final ground-state population on the workload grid and on
     grids with 2x and 4x the steps, first-order Richardson extrapolations from
@@ -211,6 +215,47 @@ def gadget_ame(workers=8):
                    "t_f": inst.t_f, "pgs": [float(v) for v in pgs]}, f)
 
 
+def a2a8_model(key):
+    """The 8-qubit workload under one of the bench's model switches (same construction as
+    bench.py's --lamb-shift, --bath-corr 0.5, --bath-terms 0.5, --zx-coupling)."""
+    inst = workloads.config_a2a8(10)
+    q = inst.n_qubits
+    if key == "lamb_shift":
+        return inst.with_(lamb_shift=True)
+    if key == "bath_corr_0.5":
+        return inst.with_(bath_corr=np.array([[0.5 ** abs(a - b) for b in range(q)] for a in range(q)]))
+    if key == "bath_terms_0.5":
+        return inst.with_(bath_terms=workloads.two_term_bath(q, rho=0.5))
+    if key == "zx_coupling":
+        return inst.with_(coupling=(np.vstack([np.eye(q), np.zeros((q, q))]), np.vstack([np.zeros((q, q)), np.eye(q)]),
+                                    None))
+    raise KeyError(key)
+
+
+A2A8_MODELS = ("lamb_shift", "bath_corr_0.5", "bath_terms_0.5", "zx_coupling")
+
+
+def _model_worker(key):
+    from oracle import ame, spectrum
+    inst = a2a8_model(key)
+    P = ame.split_step(spectrum.table_stream(inst), inst)
+    return key, [float(v) for v in P]
+
+
+def a2a8_models():
+    from concurrent.futures import ProcessPoolExecutor
+    with ProcessPoolExecutor(max_workers=len(A2A8_MODELS)) as ex:
+        rows = list(ex.map(_model_worker, A2A8_MODELS))
+    inst = workloads.config_a2a8(10)
+    M = inst.n_grid
+    idx = list(range(0, M, 10)) + ([M - 1] if (M - 1) % 10 else [])
+    out = {"source": "oracle.ame.split_step over oracle.spectrum.table_stream of workloads.config_a2a8() with "
+                     "each model switch (make_golden.a2a8_model)", "instance": inst.name, "n_grid": M,
+           "grid_points": idx, "models": {k: [P[i] for i in idx] for k, P in rows}}
+    with open(os.path.join(HERE, "a2a8_models_ame_pgs.json"), "w") as f:
+        json.dump(out, f)
+
+
 def discretisation():
     import time
     from oracle import ame, spectrum
@@ -241,6 +286,9 @@ def discretisation():
 
 
 if __name__ == "__main__":
+    if "--a2a8-models" in sys.argv:
+        a2a8_models()
+        sys.exit(0)
     if "--gadget" in sys.argv:
         gadget_ame()
         sys.exit(0)
