@@ -214,8 +214,7 @@ __global__ __launch_bounds__(kEigThreads) void k_canon(const double* __restrict_
                                                        const double* __restrict__ Eraw, int N, int ncols, int n,
                                                        int NP, double tol, int g0, double* __restrict__ Vout,
                                                        double* __restrict__ Etab, int* __restrict__ gstab,
-                                                       double* __restrict__ ws, int* __restrict__ status,
-                                                       const double* __restrict__ Gfull) {
+                                                       double* __restrict__ ws, int* __restrict__ status) {
   __shared__ EigShared sh;
   __shared__ double s_E[kEigMaxN];
   __shared__ int s_cs[kEigMaxN + 1];
@@ -249,22 +248,15 @@ __global__ __launch_bounds__(kEigThreads) void k_canon(const double* __restrict_
   for (int q = 0; q < ncl; ++q) {
     const int a0 = s_cs[q], a1 = s_cs[q + 1], cs = a1 - a0;
     if (cs < 2) continue;
-    // G[i][j] = sum_x x V[a0+i][x] V[a0+j][x] (precomputed for all ncols levels when Gfull is given)
-    if (Gfull) {
-      for (int p = tid; p < cs * cs; p += blockDim.x) {
-        const int i = p / cs, j = p - i * cs;
-        G[p] = Gfull[(static_cast<size_t>(c) * ncols + a0 + i) * ncols + a0 + j];
-      }
-    } else {
-      for (int p = wave; p < cs * cs; p += kEigThreads / kWave) {
-        const int i = p / cs, j = p - i * cs;
-        const double* vi = V + static_cast<size_t>(a0 + i) * N;
-        const double* vj = V + static_cast<size_t>(a0 + j) * N;
-        double acc = 0.0;
-        for (int x = lane; x < N; x += kWave) acc += static_cast<double>(x) * vi[x] * vj[x];
-        acc = wave_sum(acc);
-        if (lane == 0) G[i * cs + j] = acc;
-      }
+    // G[i][j] = sum_x x V[a0+i][x] V[a0+j][x]
+    for (int p = wave; p < cs * cs; p += kEigThreads / kWave) {
+      const int i = p / cs, j = p - i * cs;
+      const double* vi = V + static_cast<size_t>(a0 + i) * N;
+      const double* vj = V + static_cast<size_t>(a0 + j) * N;
+      double acc = 0.0;
+      for (int x = lane; x < N; x += kWave) acc += static_cast<double>(x) * vi[x] * vj[x];
+      acc = wave_sum(acc);
+      if (lane == 0) G[i * cs + j] = acc;
     }
     __syncthreads();
     wg_tridiagonalize(G, cs, cs, sh);
@@ -338,6 +330,7 @@ struct GemmArgs {
   const double* wvec = nullptr;
   int bdiv = 1;
   int adiv = 1;
+  const int* bmask = nullptr;   // non-null: batch bz is computed only where bmask[bz] != 0
 };
 
 __global__ __launch_bounds__(256) void k_gemm_f64(GemmArgs p) {
@@ -345,6 +338,7 @@ __global__ __launch_bounds__(256) void k_gemm_f64(GemmArgs p) {
   __shared__ double Bs[64][33];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int bz = blockIdx.z / p.ksplit;
+  if (p.bmask && !p.bmask[bz]) return;
   const int kpart = blockIdx.z - bz * p.ksplit;
   const int xbeg = (p.ksplit > 1) ? kpart * p.kspan : 0;
   const int xend = (p.ksplit > 1) ? min(p.K, xbeg + p.kspan) : p.K;
@@ -954,23 +948,41 @@ aqt_status launch_gemm(aqt_ctx* ctx, const GemmArgs& g, int batch) {
 // ------------------------------------------------------------------------
 // Lowest eigenpairs of large H(s) (2^n_qubits > 1024): Chebyshev-filtered
 // subspace iteration on a block of KB vectors with Rayleigh-Ritz steps
-// (Zhou and Saad's filtered subspace iteration), warm-started from the
-// previous grid point's Ritz vectors.  H is applied matrix-free: (H v)[x] =
-// -A sum_i v[x ^ 2^i] + B e_Z[x] v[x].  Vectors are rows of length N.
+// (Zhou and Saad's filtered subspace iteration), each grid point warm-started
+// from the Ritz vectors of the grid point before it.  H is applied matrix-free:
+// (H v)[x] = -A sum_i v[x ^ 2^i] + B e_Z[x] v[x].  Vectors are rows of length N.
+//
+// The grid is cut into contiguous chains of grid points, one per block slot.
+// The slots iterate in lock step: each kernel below takes the slot as a grid
+// dimension, so one launch serves every chain, and a slot whose solve has
+// converged (or that has no grid point at this step) is masked out.
 
-constexpr int kHxChunk = 4096;   // x per workgroup of the block product (LDS-resident)
+constexpr int kHxChunk = 4096;        // x per workgroup of the block product (LDS-resident)
+constexpr int kMaxFilterDegree = 256;  // Chebyshev filter degree, at most
+constexpr int kMaxChains = 16;         // block slots of the lock-step chains, at most
 
-// Y_j = alpha (H X_j) + beta X_j + gamma Z_j for the KB rows j (Z may be null).
+// Per-slot coefficients of one block product.
+struct HxCoef {
+  double A, B;                 // H = A H_X + B diag(e_Z)
+  double alpha, beta, gamma;   // Y = alpha H X + beta X + gamma Z
+  int active;
+  int pad;
+};
+
+// Y_j = alpha (H X_j) + beta X_j + gamma Z_j for the KB rows j of every active
+// slot (blockIdx.z; a slot is KB*N doubles of each buffer; Z may be null).
 __global__ __launch_bounds__(256) void k_hx_block(const double* __restrict__ X, const double* __restrict__ Zin,
                                                   double* __restrict__ Y, const double* __restrict__ eZ, int nq,
-                                                  double A, double B, double alpha, double beta, double gamma) {
+                                                  int KB, const HxCoef* __restrict__ coef) {
+  const HxCoef cf = coef[blockIdx.z];
+  if (!cf.active) return;
   __shared__ double sx[kHxChunk];
   const int N = 1 << nq;
   const int CH = N < kHxChunk ? N : kHxChunk;
   const int lch = 31 - __clz(CH);
-  const int j = blockIdx.y;
+  const size_t row = (static_cast<size_t>(blockIdx.z) * KB + blockIdx.y) * N;
   const int x0 = blockIdx.x * CH;
-  const double* v = X + static_cast<size_t>(j) * N;
+  const double* v = X + row;
   for (int t = threadIdx.x; t < CH; t += blockDim.x) sx[t] = v[x0 + t];
   __syncthreads();
   const int nlow = nq < lch ? nq : lch;
@@ -980,31 +992,42 @@ __global__ __launch_bounds__(256) void k_hx_block(const double* __restrict__ X, 
     for (int i = 0; i < nlow; ++i) flip += sx[t ^ (1 << i)];
     for (int i = lch; i < nq; ++i) flip += v[x ^ (1 << i)];
     const double own = sx[t];
-    double out = alpha * (B * eZ[x] * own - A * flip) + beta * own;
-    if (Zin) out += gamma * Zin[static_cast<size_t>(j) * N + x];
-    Y[static_cast<size_t>(j) * N + x] = out;
+    double out = cf.alpha * (cf.B * eZ[x] * own - cf.A * flip) + cf.beta * own;
+    if (Zin) out += cf.gamma * Zin[row + x];
+    Y[row + x] = out;
   }
 }
 
-// Y_j = sum_i C[i][j] X_i (C row-major KB x KB): the block times a small matrix.
+// Y_j = sum_i C[i][j] X_i (C row-major KB x KB) in every slot (blockIdx.y): the
+// block times a small matrix.  A masked slot is skipped, or copied (Y = X) when
+// copy_masked is set.
 template <int KB>
 __global__ __launch_bounds__(256) void k_combine(const double* __restrict__ X, const double* __restrict__ C,
-                                                 double* __restrict__ Y, int N) {
-  __shared__ double sC[KB * KB];
-  for (int f = threadIdx.x; f < KB * KB; f += blockDim.x) sC[f] = C[f];
-  __syncthreads();
+                                                 double* __restrict__ Y, int N, const int* __restrict__ act,
+                                                 int copy_masked) {
+  const int b = blockIdx.y;
+  const size_t off = static_cast<size_t>(b) * KB * N;
   const int x = blockIdx.x * blockDim.x + threadIdx.x;
+  if (!act[b]) {
+    if (copy_masked && x < N)
+      for (int jj = 0; jj < KB; ++jj) Y[off + static_cast<size_t>(jj) * N + x] = X[off + static_cast<size_t>(jj) * N + x];
+    return;
+  }
+  __shared__ double sC[KB * KB];
+  const double* Cb = C + static_cast<size_t>(b) * KB * KB;
+  for (int f = threadIdx.x; f < KB * KB; f += blockDim.x) sC[f] = Cb[f];
+  __syncthreads();
   if (x >= N) return;
   double acc[KB];
 #pragma unroll
   for (int jj = 0; jj < KB; ++jj) acc[jj] = 0.0;
   for (int i = 0; i < KB; ++i) {
-    const double xi = X[static_cast<size_t>(i) * N + x];
+    const double xi = X[off + static_cast<size_t>(i) * N + x];
 #pragma unroll
     for (int jj = 0; jj < KB; ++jj) acc[jj] += sC[i * KB + jj] * xi;
   }
 #pragma unroll
-  for (int jj = 0; jj < KB; ++jj) Y[static_cast<size_t>(jj) * N + x] = acc[jj];
+  for (int jj = 0; jj < KB; ++jj) Y[off + static_cast<size_t>(jj) * N + x] = acc[jj];
 }
 
 // Deterministic start block: entries in [-1, 1) from a counter hash.
@@ -1018,19 +1041,29 @@ __global__ void k_random_block(double* X, int64_t count) {
   X[idx] = static_cast<double>(z >> 11) * 0x1.0p-52 - 1.0;
 }
 
-// One workgroup, KB x KB symmetric S (row-major, symmetrised here):
+// One workgroup per unmasked slot (blockIdx.x), KB x KB symmetric S (row-major,
+// symmetrised here):
 //   mode 0 (Rayleigh-Ritz): C = eigenvectors of S as columns, ascending; theta.
 //   mode 1 (orthonormalisation of a Gram matrix): with D = diag(S)^(1/2) and
 //     D^-1 S D^-1 = U L U^T, C = D^-1 U L^-1/2 so that X C has orthonormal rows;
 //   mode 2: the same by Cholesky, D^-1 S D^-1 = L L^T and C = D^-1 L^-T, with
 //     mode 1 as the fallback for a small pivot.
-// ws: 2 KB^2 doubles.  status bit 1: eigensolver failed, bit 2: non-finite input.
+// Per slot: S, C KB^2 doubles, theta KB, ws 2 KB^2, status one int (bit 1:
+// eigensolver failed, bit 2: non-finite input).
 __global__ __launch_bounds__(kEigThreads) void k_small_eig(const double* __restrict__ S, int KB, int mode,
                                                            double* __restrict__ C, double* __restrict__ theta,
-                                                           double* __restrict__ ws, int* __restrict__ status) {
+                                                           double* __restrict__ ws, int* __restrict__ status,
+                                                           const int* __restrict__ act) {
+  const int b = blockIdx.x;
+  if (!act[b]) return;
   __shared__ EigShared sh;
   __shared__ int s_perm[kEigMaxN];
   __shared__ double s_dinv[kEigMaxN];
+  S += static_cast<size_t>(b) * KB * KB;
+  C += static_cast<size_t>(b) * KB * KB;
+  theta += static_cast<size_t>(b) * KB;
+  ws += static_cast<size_t>(b) * 2 * KB * KB;
+  status += b;
   double* A = ws;
   double* Z = ws + static_cast<size_t>(KB) * KB;
   for (int a = threadIdx.x; a < KB; a += blockDim.x)
@@ -1115,14 +1148,19 @@ __global__ __launch_bounds__(kEigThreads) void k_small_eig(const double* __restr
   if (threadIdx.x == 0 && bad) atomicOr(status, ok ? 2 : 1);
 }
 
-// res_j = |W_j - theta_j X_j| (one workgroup per row).
+// res_j = |W_j - theta_j X_j| for the KB rows j (blockIdx.x) of every unmasked
+// slot (blockIdx.y).
 __global__ __launch_bounds__(256) void k_resid(const double* __restrict__ X, const double* __restrict__ W,
-                                               const double* __restrict__ theta, int N, double* __restrict__ res) {
+                                               const double* __restrict__ theta, int N, int KB,
+                                               const int* __restrict__ act, double* __restrict__ res) {
+  const int b = blockIdx.y;
+  if (!act[b]) return;
   __shared__ double red[4];
   const int j = blockIdx.x;
-  const double th = theta[j];
-  const double* xj = X + static_cast<size_t>(j) * N;
-  const double* wj = W + static_cast<size_t>(j) * N;
+  const size_t row = (static_cast<size_t>(b) * KB + j) * N;
+  const double th = theta[static_cast<size_t>(b) * KB + j];
+  const double* xj = X + row;
+  const double* wj = W + row;
   double acc = 0.0;
   for (int x = threadIdx.x; x < N; x += blockDim.x) {
     const double r = wj[x] - th * xj[x];
@@ -1131,154 +1169,479 @@ __global__ __launch_bounds__(256) void k_resid(const double* __restrict__ X, con
   acc = wave_sum(acc);
   if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
   __syncthreads();
-  if (threadIdx.x == 0) res[j] = sqrt(red[0] + red[1] + red[2] + red[3]);
+  if (threadIdx.x == 0) res[static_cast<size_t>(b) * KB + j] = sqrt(red[0] + red[1] + red[2] + red[3]);
+}
+
+// Canonical basis of a converged Ritz block, in three launches over all slots
+// whose info entry (chunk index c, grid point g) has c >= 0.  The levels a < ncols
+// (Ritz values theta, ascending) form clusters where consecutive values differ by
+// less than tol; within a cluster of two or more levels the vectors are rotated to
+// the eigenvectors of diag(x) (ascending), then every level a < n gets the sign rule.
+
+// Cluster rotations, one workgroup per slot.  Gfull: <v_i| diag(x) |v_j> over the
+// ncols levels (ld ncols).  Writes R (row-major, ld ncols: new_j = sum_i R[j][i]
+// old_i, the identity outside clusters), cl (per level: cluster start, then at +KB
+// its size), E[g] (level energies, padded to NP with zeros), gs[g] (levels of the
+// lowest cluster, at most n) and status[c] bit 2 if a cluster eigensolve failed.
+__global__ __launch_bounds__(kEigThreads) void k_canon_rot(const double* __restrict__ Gfull, int KB,
+                                                           const double* __restrict__ theta, int ncols, int n,
+                                                           int NP, double tol, const int* __restrict__ info,
+                                                           double* __restrict__ Etab, int* __restrict__ gstab,
+                                                           double* __restrict__ R, int* __restrict__ cl,
+                                                           double* __restrict__ ws, int* __restrict__ status) {
+  const int b = blockIdx.x;
+  const int c = info[2 * b], g = info[2 * b + 1];
+  if (c < 0) return;
+  __shared__ EigShared sh;
+  __shared__ double s_E[kEigMaxN];
+  __shared__ int s_cs[kEigMaxN + 1];
+  __shared__ int s_ncl;
+  __shared__ int s_perm2[kEigMaxN];
+  const int tid = threadIdx.x;
+  Gfull += static_cast<size_t>(b) * KB * KB;
+  theta += static_cast<size_t>(b) * KB;
+  R += static_cast<size_t>(b) * KB * KB;
+  cl += static_cast<size_t>(b) * 2 * KB;
+  ws += static_cast<size_t>(b) * 2 * KB * KB;
+  for (int a = tid; a < ncols; a += blockDim.x) s_E[a] = theta[a];
+  for (int f = tid; f < ncols * ncols; f += blockDim.x) R[f] = (f / ncols == f % ncols) ? 1.0 : 0.0;
+  __syncthreads();
+  if (tid == 0) {
+    int k = 0;
+    s_cs[k++] = 0;
+    for (int a = 1; a < ncols; ++a)
+      if (s_E[a] - s_E[a - 1] >= tol) s_cs[k++] = a;
+    s_cs[k] = ncols;
+    s_ncl = k;
+  }
+  __syncthreads();
+  const int ncl = s_ncl;
+  for (int q = tid; q < ncl; q += blockDim.x)
+    for (int a = s_cs[q]; a < s_cs[q + 1]; ++a) {
+      cl[a] = s_cs[q];
+      cl[KB + a] = s_cs[q + 1] - s_cs[q];
+    }
+  bool ok = true;
+  for (int q = 0; q < ncl; ++q) {
+    const int a0 = s_cs[q], cs = s_cs[q + 1] - a0;
+    if (cs < 2) continue;
+    double* G = ws;
+    double* ZG = ws + static_cast<size_t>(cs) * cs;
+    for (int p = tid; p < cs * cs; p += blockDim.x) {
+      const int i = p / cs, j = p - i * cs;
+      G[p] = Gfull[static_cast<size_t>(a0 + i) * ncols + a0 + j];
+    }
+    __syncthreads();
+    wg_tridiagonalize(G, cs, cs, sh);
+    ok = wg_band_qr(ZG, cs, cs, sh) && ok;
+    wg_rank_ascending(sh.d, cs, s_perm2);
+    wg_back_transform(G, cs, cs, ZG, cs, s_perm2, cs, sh);
+    // new_j = sum_i Q[i][j] old_i with Q[i][j] = ZG[perm2[j]][i]
+    for (int p = tid; p < cs * cs; p += blockDim.x) {
+      const int j = p / cs, i = p - j * cs;
+      R[static_cast<size_t>(a0 + j) * ncols + a0 + i] = ZG[static_cast<size_t>(s_perm2[j]) * cs + i];
+    }
+    for (int j = tid; j < cs; j += blockDim.x) {
+      const double* qj = ZG + static_cast<size_t>(s_perm2[j]) * cs;
+      double e = 0.0;
+      for (int i = 0; i < cs; ++i) e += qj[i] * qj[i] * s_E[a0 + i];
+      sh.w[j] = e;
+    }
+    __syncthreads();
+    for (int j = tid; j < cs; j += blockDim.x) s_E[a0 + j] = sh.w[j];
+    __syncthreads();
+  }
+  for (int a = tid; a < NP; a += blockDim.x) Etab[static_cast<size_t>(g) * NP + a] = (a < n) ? s_E[a] : 0.0;
+  if (tid == 0) {
+    gstab[g] = min(n, ncl > 1 ? s_cs[1] : ncols);
+    if (!ok) status[c] |= 2;
+  }
+}
+
+// V_j = sum_i R[j][i] X_i over the cluster of level j (blockIdx.y < ncols), x in
+// blockIdx.x, slot in blockIdx.z; written as row j of chunk entry c of Vout.
+__global__ __launch_bounds__(256) void k_canon_apply(const double* __restrict__ X, size_t blk,
+                                                     const double* __restrict__ R, int KB,
+                                                     const int* __restrict__ cl, const int* __restrict__ info,
+                                                     int ncols, int N, double* __restrict__ Vout, size_t Vstride) {
+  const int b = blockIdx.z;
+  const int c = info[2 * b];
+  if (c < 0) return;
+  const int j = blockIdx.y;
+  const int x = blockIdx.x * blockDim.x + threadIdx.x;
+  if (x >= N) return;
+  const int a0 = cl[static_cast<size_t>(b) * 2 * KB + j], cs = cl[static_cast<size_t>(b) * 2 * KB + KB + j];
+  const double* Rj = R + static_cast<size_t>(b) * KB * KB + static_cast<size_t>(j) * ncols + a0;
+  const double* Xb = X + static_cast<size_t>(b) * blk + static_cast<size_t>(a0) * N + x;
+  double acc = 0.0;
+  for (int i = 0; i < cs; ++i) acc += Rj[i] * Xb[static_cast<size_t>(i) * N];
+  Vout[static_cast<size_t>(c) * Vstride + static_cast<size_t>(j) * N + x] = acc;
+}
+
+// Sign rule for level blockIdx.x of every slot's canonical rows (blockIdx.y): the
+// first entry within 1e-9 of the largest magnitude is made positive.
+__global__ __launch_bounds__(256) void k_canon_signs(double* __restrict__ Vout, size_t Vstride,
+                                                     const int* __restrict__ info, int N) {
+  const int b = blockIdx.y;
+  const int c = info[2 * b];
+  if (c < 0) return;
+  __shared__ double s_mx[4];
+  __shared__ int s_first[4];
+  __shared__ int s_flip;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  double* va = Vout + static_cast<size_t>(c) * Vstride + static_cast<size_t>(blockIdx.x) * N;
+  double mx = 0.0;
+  for (int x = tid; x < N; x += blockDim.x) mx = fmax(mx, fabs(va[x]));
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) mx = fmax(mx, __shfl_xor(mx, o, 64));
+  if (lane == 0) s_mx[wave] = mx;
+  __syncthreads();
+  mx = fmax(fmax(s_mx[0], s_mx[1]), fmax(s_mx[2], s_mx[3]));
+  int first = N;
+  for (int x = tid; x < N; x += blockDim.x)
+    if (fabs(va[x]) >= (1.0 - 1e-9) * mx) {
+      first = x;
+      break;
+    }
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) first = min(first, __shfl_xor(first, o, 64));
+  if (lane == 0) s_first[wave] = first;
+  __syncthreads();
+  if (tid == 0) {
+    int f = min(min(s_first[0], s_first[1]), min(s_first[2], s_first[3]));
+    if (f >= N) f = 0;   // no entry qualified (non-finite vector): stay in range
+    s_flip = va[f] < 0.0;
+  }
+  __syncthreads();
+  if (s_flip)
+    for (int x = tid; x < N; x += blockDim.x) va[x] = -va[x];
 }
 
 struct Chfsi {
   int nq = 0, N = 0, KB = 0, ksplit = 1;
-  DevBuf X, Y1, Y2, W, part, S, C, theta, res, ws, status;
+  int nb = 1;        // block slots (chains advanced together)
+  size_t blk = 0;    // doubles per slot of X, Y1, Y2, W (KB * N)
+  DevBuf X, Y1, Y2, W, part, S, C, theta, res, ws, status, act, coef, info, cl;
   std::vector<double> h_theta, h_res;
-  bool warm = false;
-  double hub = 0.0;   // upper bound of the spectrum (Gershgorin)
+  std::vector<int> h_status, h_act, h_info;
+  std::vector<HxCoef> h_coef;
+  std::vector<char> warm;   // per slot: X holds the Ritz block of a nearby grid point
+  double hub = 0.0;         // upper bound of the spectrum (Gershgorin)
+  double* at(const DevBuf& b, int j) const { return b.as<double>() + static_cast<size_t>(j) * blk; }
 };
 
-aqt_status chfsi_gram(aqt_ctx* ctx, Chfsi& c, const double* P, const double* Q) {
-  // S = P Q^T over x (KB x KB), split over x
+// Control data for the next launches (host buffers are reused: wait for the copy).
+aqt_status chfsi_upload(aqt_ctx* ctx, void* dst, const void* src, size_t bytes) {
+  AQT_HIP(ctx, hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, ctx->stream));
+  AQT_HIP(ctx, hipStreamSynchronize(ctx->stream));
+  return AQT_OK;
+}
+
+aqt_status chfsi_set_mask(aqt_ctx* ctx, Chfsi& c, const std::vector<int>& m) {
+  c.h_act = m;
+  return chfsi_upload(ctx, c.act.p, c.h_act.data(), static_cast<size_t>(c.nb) * 4);
+}
+
+// S_b = P_b Q_b^T (rows x rows, weight w(x) of GEMM mode wmode) over x in every
+// unmasked slot, split over x; stored compact (ld rows) at slot b of c.S.
+aqt_status chfsi_gram(aqt_ctx* ctx, Chfsi& c, const double* P, const double* Q, int rows, int wmode) {
   const int kspan = (c.N + c.ksplit - 1) / c.ksplit;
-  GemmArgs ga{P, Q, c.part.as<double>(), 0, 0, static_cast<int64_t>(c.KB) * c.KB, c.KB, c.KB, c.N, c.N, c.N, c.KB,
-              0, c.nq, 0, c.ksplit, kspan};
-  aqt_status st = launch_gemm(ctx, ga, c.ksplit);
+  GemmArgs ga{P, Q, c.part.as<double>(), static_cast<int64_t>(c.blk), static_cast<int64_t>(c.blk),
+              static_cast<int64_t>(rows) * rows, rows, rows, c.N, c.N, c.N, rows, wmode, c.nq, 0, c.ksplit, kspan};
+  ga.bmask = c.act.as<int>();
+  aqt_status st = launch_gemm(ctx, ga, c.nb * c.ksplit);
   if (st != AQT_OK) return st;
-  hipLaunchKernelGGL(k_splitk_reduce, dim3(nblk(static_cast<int64_t>(c.KB) * c.KB)), dim3(256), 0, ctx->stream,
-                     c.part.as<double>(), c.ksplit, c.KB, c.KB, 1, c.S.as<double>(), 0, c.KB, 0);
+  hipLaunchKernelGGL(k_splitk_reduce, dim3(nblk(static_cast<int64_t>(rows) * rows * c.nb)), dim3(256), 0,
+                     ctx->stream, c.part.as<double>(), c.ksplit, rows, rows, c.nb, c.S.as<double>(),
+                     static_cast<int64_t>(c.KB) * c.KB, rows, 0);
   AQT_HIP(ctx, hipGetLastError());
   return AQT_OK;
 }
 
-aqt_status chfsi_combine(aqt_ctx* ctx, Chfsi& c, const double* in, double* out) {
+aqt_status chfsi_combine(aqt_ctx* ctx, Chfsi& c, const double* in, double* out, int copy_masked) {
+  const dim3 grid(static_cast<unsigned>(nblk(c.N)), static_cast<unsigned>(c.nb));
   if (c.KB == 64)
-    hipLaunchKernelGGL(k_combine<64>, dim3(nblk(c.N)), dim3(256), 0, ctx->stream, in, c.C.as<double>(), out, c.N);
+    hipLaunchKernelGGL(k_combine<64>, grid, dim3(256), 0, ctx->stream, in, c.C.as<double>(), out, c.N,
+                       c.act.as<int>(), copy_masked);
   else
-    hipLaunchKernelGGL(k_combine<128>, dim3(nblk(c.N)), dim3(256), 0, ctx->stream, in, c.C.as<double>(), out, c.N);
+    hipLaunchKernelGGL(k_combine<128>, grid, dim3(256), 0, ctx->stream, in, c.C.as<double>(), out, c.N,
+                       c.act.as<int>(), copy_masked);
   AQT_HIP(ctx, hipGetLastError());
   return AQT_OK;
 }
 
-aqt_status chfsi_hx(aqt_ctx* ctx, Chfsi& c, const double* eZ, double A, double B, const double* in, const double* z,
-                    double* out, double alpha, double beta, double gamma) {
+aqt_status chfsi_hx(aqt_ctx* ctx, Chfsi& c, const double* eZ, const HxCoef* coef, const double* in, const double* z,
+                    double* out) {
   const int CH = std::min(c.N, kHxChunk);
-  hipLaunchKernelGGL(k_hx_block, dim3(c.N / CH, c.KB), dim3(256), 0, ctx->stream, in, z, out, eZ, c.nq, A, B, alpha,
-                     beta, gamma);
+  hipLaunchKernelGGL(k_hx_block, dim3(c.N / CH, c.KB, c.nb), dim3(256), 0, ctx->stream, in, z, out, eZ, c.nq, c.KB,
+                     coef);
   AQT_HIP(ctx, hipGetLastError());
   return AQT_OK;
 }
 
-// Orthonormalise the rows of `in` into c.X (column scaling, then the inverse
-// square root of the Gram matrix, twice).
+aqt_status chfsi_small_eig(aqt_ctx* ctx, Chfsi& c, int mode) {
+  hipLaunchKernelGGL(k_small_eig, dim3(c.nb), dim3(kEigThreads), 0, ctx->stream, c.S.as<double>(), c.KB, mode,
+                     c.C.as<double>(), c.theta.as<double>(), c.ws.as<double>(), c.status.as<int>(),
+                     c.act.as<int>());
+  AQT_HIP(ctx, hipGetLastError());
+  return AQT_OK;
+}
+
+// Orthonormalise, in every unmasked slot, the rows of `in` into c.X (column
+// scaling, then the inverse square root of the Gram matrix, twice).
 aqt_status chfsi_orth(aqt_ctx* ctx, Chfsi& c, double* in) {
   double* src = in;
   for (int pass = 0; pass < 2; ++pass) {
-    aqt_status st = chfsi_gram(ctx, c, src, src);
+    aqt_status st = chfsi_gram(ctx, c, src, src, c.KB, 0);
+    if (st == AQT_OK) st = chfsi_small_eig(ctx, c, 2);
     if (st != AQT_OK) return st;
-    hipLaunchKernelGGL(k_small_eig, dim3(1), dim3(kEigThreads), 0, ctx->stream, c.S.as<double>(), c.KB, 2,
-                       c.C.as<double>(), c.theta.as<double>(), c.ws.as<double>(), c.status.as<int>());
-    AQT_HIP(ctx, hipGetLastError());
     double* dst = (pass == 0) ? c.Y2.as<double>() : c.X.as<double>();
     if (dst == src) dst = c.W.as<double>();
-    st = chfsi_combine(ctx, c, src, dst);
-    if (st != AQT_OK) return st;
+    if ((st = chfsi_combine(ctx, c, src, dst, 0)) != AQT_OK) return st;
     src = dst;
   }
   if (src != c.X.as<double>())
-    AQT_HIP(ctx, hipMemcpyAsync(c.X.p, src, static_cast<size_t>(c.KB) * c.N * 8, hipMemcpyDeviceToDevice, ctx->stream));
+    for (int j = 0; j < c.nb; ++j)
+      if (c.h_act[j])
+        AQT_HIP(ctx, hipMemcpyAsync(c.at(c.X, j), src + static_cast<size_t>(j) * c.blk, c.blk * 8,
+                                    hipMemcpyDeviceToDevice, ctx->stream));
   return AQT_OK;
 }
 
-// Converge the lowest `nconv` Ritz pairs of H(s) = A H_X + B diag(e_Z) to
-// residual <= tol * hub.  On return c.X holds the KB Ritz vectors (ascending
-// Ritz values in c.theta).
-aqt_status chfsi_solve(aqt_ctx* ctx, Chfsi& c, const double* eZ, double A, double B, int nconv, double tol,
-                       const std::string& where) {
+// Converge, in every slot j with nconv[j] > 0, the lowest nconv[j] Ritz pairs of
+// H(s_g) = A_g H_X + B_g diag(e_Z), g = gidx[j], to residual <= tol * hub.  On
+// return slot j of c.X holds its KB Ritz vectors (ascending Ritz values in slot j
+// of c.theta); the other slots keep their contents.
+aqt_status chfsi_solve(aqt_ctx* ctx, Chfsi& c, const double* eZ, const std::vector<double>& Ag,
+                       const std::vector<double>& Bg, const std::vector<int>& gidx, const std::vector<int>& nconv,
+                       double tol) {
   hipStream_t st = ctx->stream;
-  AQT_HIP(ctx, hipMemsetAsync(c.status.p, 0, 4, st));
-  if (!c.warm) {
-    hipLaunchKernelGGL(k_random_block, dim3(nblk(static_cast<int64_t>(c.KB) * c.N)), dim3(256), 0, st,
-                       c.X.as<double>(), static_cast<int64_t>(c.KB) * c.N);
-    AQT_HIP(ctx, hipGetLastError());
-    aqt_status s = chfsi_orth(ctx, c, c.X.as<double>());
-    if (s != AQT_OK) return s;
+  const int nb = c.nb, KB = c.KB;
+  std::vector<int> live(nb, 0), cold(nb, 0), iters(nb, 0), maxit(nb, 0), degree(nb, 0);
+  bool anycold = false;
+  for (int j = 0; j < nb; ++j) {
+    live[j] = nconv[j] > 0;
+    cold[j] = live[j] && !c.warm[j];
+    anycold = anycold || cold[j];
+    maxit[j] = c.warm[j] ? 80 : 150;
   }
-  const int maxit = c.warm ? 80 : 150;
-  int hstat = 0;
-  for (int it = 0;; ++it) {
-    // Rayleigh-Ritz
-    aqt_status s = chfsi_hx(ctx, c, eZ, A, B, c.X.as<double>(), nullptr, c.W.as<double>(), 1.0, 0.0, 0.0);
-    if (s != AQT_OK) return s;
-    s = chfsi_gram(ctx, c, c.X.as<double>(), c.W.as<double>());
-    if (s != AQT_OK) return s;
-    hipLaunchKernelGGL(k_small_eig, dim3(1), dim3(kEigThreads), 0, st, c.S.as<double>(), c.KB, 0, c.C.as<double>(),
-                       c.theta.as<double>(), c.ws.as<double>(), c.status.as<int>());
-    AQT_HIP(ctx, hipGetLastError());
-    if ((s = chfsi_combine(ctx, c, c.X.as<double>(), c.Y1.as<double>())) != AQT_OK) return s;
-    if ((s = chfsi_combine(ctx, c, c.W.as<double>(), c.Y2.as<double>())) != AQT_OK) return s;
+  auto where = [&](int j) { return "at grid point " + std::to_string(gidx[j]); };
+  AQT_HIP(ctx, hipMemsetAsync(c.status.p, 0, static_cast<size_t>(nb) * 4, st));
+  aqt_status s = AQT_OK;
+  if (anycold) {
+    for (int j = 0; j < nb; ++j)
+      if (cold[j]) {
+        hipLaunchKernelGGL(k_random_block, dim3(nblk(static_cast<int64_t>(c.blk))), dim3(256), 0, st, c.at(c.X, j),
+                           static_cast<int64_t>(c.blk));
+        AQT_HIP(ctx, hipGetLastError());
+      }
+    if ((s = chfsi_set_mask(ctx, c, cold)) != AQT_OK || (s = chfsi_orth(ctx, c, c.X.as<double>())) != AQT_OK) return s;
+  }
+  for (;;) {
+    // Rayleigh-Ritz in every live slot
+    if ((s = chfsi_set_mask(ctx, c, live)) != AQT_OK) return s;
+    c.h_coef.assign(nb, HxCoef{0.0, 0.0, 1.0, 0.0, 0.0, 0, 0});
+    for (int j = 0; j < nb; ++j)
+      if (live[j]) {
+        c.h_coef[j].A = Ag[gidx[j]];
+        c.h_coef[j].B = Bg[gidx[j]];
+        c.h_coef[j].active = 1;
+      }
+    if ((s = chfsi_upload(ctx, c.coef.p, c.h_coef.data(), nb * sizeof(HxCoef))) != AQT_OK) return s;
+    const HxCoef* drr = c.coef.as<HxCoef>();
+    if ((s = chfsi_hx(ctx, c, eZ, drr, c.X.as<double>(), nullptr, c.W.as<double>())) != AQT_OK) return s;
+    if ((s = chfsi_gram(ctx, c, c.X.as<double>(), c.W.as<double>(), KB, 0)) != AQT_OK) return s;
+    if ((s = chfsi_small_eig(ctx, c, 0)) != AQT_OK) return s;
+    // masked slots are copied, so that the buffer swap keeps their blocks
+    if ((s = chfsi_combine(ctx, c, c.X.as<double>(), c.Y1.as<double>(), 1)) != AQT_OK) return s;
+    if ((s = chfsi_combine(ctx, c, c.W.as<double>(), c.Y2.as<double>(), 1)) != AQT_OK) return s;
     std::swap(c.X.p, c.Y1.p);
     std::swap(c.W.p, c.Y2.p);
-    hipLaunchKernelGGL(k_resid, dim3(c.KB), dim3(256), 0, st, c.X.as<double>(), c.W.as<double>(),
-                       c.theta.as<double>(), c.N, c.res.as<double>());
+    hipLaunchKernelGGL(k_resid, dim3(KB, nb), dim3(256), 0, st, c.X.as<double>(), c.W.as<double>(),
+                       c.theta.as<double>(), c.N, KB, c.act.as<int>(), c.res.as<double>());
     AQT_HIP(ctx, hipGetLastError());
-    AQT_HIP(ctx, hipMemcpyAsync(c.h_theta.data(), c.theta.p, c.KB * 8, hipMemcpyDeviceToHost, st));
-    AQT_HIP(ctx, hipMemcpyAsync(c.h_res.data(), c.res.p, c.KB * 8, hipMemcpyDeviceToHost, st));
-    AQT_HIP(ctx, hipMemcpyAsync(&hstat, c.status.p, 4, hipMemcpyDeviceToHost, st));
+    AQT_HIP(ctx, hipMemcpyAsync(c.h_theta.data(), c.theta.p, static_cast<size_t>(nb) * KB * 8, hipMemcpyDeviceToHost, st));
+    AQT_HIP(ctx, hipMemcpyAsync(c.h_res.data(), c.res.p, static_cast<size_t>(nb) * KB * 8, hipMemcpyDeviceToHost, st));
+    AQT_HIP(ctx, hipMemcpyAsync(c.h_status.data(), c.status.p, static_cast<size_t>(nb) * 4, hipMemcpyDeviceToHost, st));
     AQT_HIP(ctx, hipStreamSynchronize(st));
-    if (hstat) return ctx->fail(AQT_ENUMERIC, "subspace iteration: small eigensolver failed " + where);
-    double worst = 0.0;
-    for (int j = 0; j < nconv; ++j) worst = std::max(worst, c.h_res[j]);
-    if (!(worst == worst)) return ctx->fail(AQT_ENUMERIC, "subspace iteration produced NaN " + where);
-    if (worst <= tol * c.hub) break;
-    if (it >= maxit)
-      return ctx->fail(AQT_ENUMERIC, "subspace iteration did not converge " + where + " (residual " +
-                                         std::to_string(worst / c.hub) + " of |H|)");
-    // Chebyshev filter damping [theta_last, hub], scaled at theta_0; the degree
-    // makes the slowest wanted level gain about 10^3 over the damped interval
-    const double lo = c.h_theta[0], cut = c.h_theta[c.KB - 1];
-    const double e = 0.5 * (c.hub - cut), cen = 0.5 * (c.hub + cut);
-    const double xw = std::fabs((c.h_theta[nconv - 1] - cen) / e);
-    const double xl = std::fabs((lo - cen) / e);
-    int degree = 256;
-    if (xw > 1.0 + 1e-12) degree = static_cast<int>(std::ceil(std::acosh(1e3) / std::acosh(xw)));
-    // amplification of the lowest level over the damped interval, T_d(x_lo) ~ e^{d acosh x_lo},
-    // kept below 1e10: beyond that the filtered block loses the directions it amplifies
-    // least to rounding (its Gram matrix becomes numerically singular)
-    if (xl > 1.0) degree = std::min(degree, static_cast<int>(std::log(1e10) / std::acosh(xl)));
-    degree = std::max(2, std::min(256, degree));
-    double sigma = e / (lo - cen);
-    const double tau = 2.0 / sigma;
-    double* x0 = c.X.as<double>();
-    double* y1 = c.Y1.as<double>();
-    double* y2 = c.Y2.as<double>();
-    if ((s = chfsi_hx(ctx, c, eZ, A, B, x0, nullptr, y1, sigma / e, -cen * sigma / e, 0.0)) != AQT_OK) return s;
-    for (int k = 2; k <= degree; ++k) {
-      const double sn = 1.0 / (tau - sigma);
-      if ((s = chfsi_hx(ctx, c, eZ, A, B, y1, x0, y2, 2.0 * sn / e, -2.0 * cen * sn / e, -sigma * sn)) != AQT_OK)
-        return s;
+    bool any = false;
+    for (int j = 0; j < nb; ++j) {
+      if (!live[j]) continue;
+      if (c.h_status[j]) return ctx->fail(AQT_ENUMERIC, "subspace iteration: small eigensolver failed " + where(j));
+      const double* res = c.h_res.data() + static_cast<size_t>(j) * KB;
+      double worst = 0.0;
+      for (int a = 0; a < nconv[j]; ++a) worst = std::max(worst, res[a]);
+      if (!(worst == worst)) return ctx->fail(AQT_ENUMERIC, "subspace iteration produced NaN " + where(j));
+      if (worst <= tol * c.hub) {
+        live[j] = 0;
+        continue;
+      }
+      if (iters[j] >= maxit[j])
+        return ctx->fail(AQT_ENUMERIC, "subspace iteration did not converge " + where(j) + " (residual " +
+                                           std::to_string(worst / c.hub) + " of |H|)");
+      ++iters[j];
+      any = true;
+    }
+    if (!any) break;
+    // Chebyshev filter damping [theta_last, hub], scaled at theta_0, per live slot; the
+    // degree makes the slowest wanted level gain about 10^3 over the damped interval
+    int dmax = 0;
+    std::vector<double> fe(nb), fcen(nb), fsig(nb);
+    for (int j = 0; j < nb; ++j) {
+      degree[j] = 0;
+      if (!live[j]) continue;
+      const double* th = c.h_theta.data() + static_cast<size_t>(j) * KB;
+      const double lo = th[0], cut = th[KB - 1];
+      const double e = 0.5 * (c.hub - cut), cen = 0.5 * (c.hub + cut);
+      const double xw = std::fabs((th[nconv[j] - 1] - cen) / e);
+      const double xl = std::fabs((lo - cen) / e);
+      int d = 256;
+      if (xw > 1.0 + 1e-12) d = static_cast<int>(std::ceil(std::acosh(1e3) / std::acosh(xw)));
+      // amplification of the lowest level over the damped interval, T_d(x_lo) ~ e^{d acosh x_lo},
+      // kept below 1e10: beyond that the filtered block loses the directions it amplifies
+      // least to rounding (its Gram matrix becomes numerically singular)
+      if (xl > 1.0) d = std::min(d, static_cast<int>(std::log(1e10) / std::acosh(xl)));
+      degree[j] = std::max(2, std::min(kMaxFilterDegree, d));
+      dmax = std::max(dmax, degree[j]);
+      fe[j] = e;
+      fcen[j] = cen;
+      fsig[j] = e / (lo - cen);
+    }
+    // three-term recurrence coefficients, row k-1 for step k; a slot past its degree is masked
+    c.h_coef.assign(static_cast<size_t>(dmax) * nb, HxCoef{0.0, 0.0, 0.0, 0.0, 0.0, 0, 0});
+    for (int j = 0; j < nb; ++j) {
+      if (!live[j]) continue;
+      const double e = fe[j], cen = fcen[j];
+      double sigma = fsig[j];
+      const double tau = 2.0 / sigma;
+      for (int k = 1; k <= degree[j]; ++k) {
+        HxCoef& h = c.h_coef[static_cast<size_t>(k - 1) * nb + j];
+        h.A = Ag[gidx[j]];
+        h.B = Bg[gidx[j]];
+        h.active = 1;
+        if (k == 1) {
+          h.alpha = sigma / e;
+          h.beta = -cen * sigma / e;
+        } else {
+          const double sn = 1.0 / (tau - sigma);
+          h.alpha = 2.0 * sn / e;
+          h.beta = -2.0 * cen * sn / e;
+          h.gamma = -sigma * sn;
+          sigma = sn;
+        }
+      }
+    }
+    HxCoef* dfc = c.coef.as<HxCoef>() + nb;
+    if ((s = chfsi_upload(ctx, dfc, c.h_coef.data(), c.h_coef.size() * sizeof(HxCoef))) != AQT_OK) return s;
+    double* const P[3] = {c.X.as<double>(), c.Y1.as<double>(), c.Y2.as<double>()};
+    double* x0 = P[0];
+    double* y1 = P[1];
+    double* y2 = P[2];
+    if ((s = chfsi_hx(ctx, c, eZ, dfc, x0, nullptr, y1)) != AQT_OK) return s;
+    for (int k = 2; k <= dmax; ++k) {
+      if ((s = chfsi_hx(ctx, c, eZ, dfc + static_cast<size_t>(k - 1) * nb, y1, x0, y2)) != AQT_OK) return s;
       double* t = x0;
       x0 = y1;
       y1 = y2;
       y2 = t;
-      sigma = sn;
     }
-    // result in y1; orthonormalise into X (X may be one of the rotated buffers)
-    {
-      // make sure chfsi_orth's scratch (Y2, W) does not alias the filtered block
-      double* filt = y1;
-      if (filt != c.Y1.as<double>()) {
-        AQT_HIP(ctx, hipMemcpyAsync(c.Y1.p, filt, static_cast<size_t>(c.KB) * c.N * 8, hipMemcpyDeviceToDevice, st));
-        filt = c.Y1.as<double>();
-      }
-      if ((s = chfsi_orth(ctx, c, filt)) != AQT_OK) return s;
+    // step k writes buffer P[k % 3]: gather every slot's filtered block into Y1, then
+    // orthonormalise into X (Y2 and W are the scratch of the orthonormalisation)
+    for (int j = 0; j < nb; ++j)
+      if (live[j] && degree[j] % 3 != 1)
+        AQT_HIP(ctx, hipMemcpyAsync(c.at(c.Y1, j), P[degree[j] % 3] + static_cast<size_t>(j) * c.blk, c.blk * 8,
+                                    hipMemcpyDeviceToDevice, st));
+    if ((s = chfsi_orth(ctx, c, c.Y1.as<double>())) != AQT_OK) return s;
+  }
+  for (int j = 0; j < nb; ++j)
+    if (nconv[j] > 0) c.warm[j] = 1;
+  return AQT_OK;
+}
+
+// Canonical vectors, energies and ground-state multiplicities of the slots with
+// gidx[j] >= 0 (grid point gidx[j], chunk entry gidx[j] - g0 of Vout).
+aqt_status chfsi_canon(aqt_ctx* ctx, Chfsi& c, const std::vector<int>& gidx, int g0, int ncols, int n, int NP,
+                       double tol, double* Vout, size_t Vstride, int* status) {
+  hipStream_t st = ctx->stream;
+  const int nb = c.nb;
+  std::vector<int> m(nb);
+  c.h_info.assign(2 * static_cast<size_t>(nb), -1);
+  for (int j = 0; j < nb; ++j) {
+    m[j] = gidx[j] >= 0;
+    if (m[j]) {
+      c.h_info[2 * j] = gidx[j] - g0;
+      c.h_info[2 * j + 1] = gidx[j];
     }
   }
-  c.warm = true;
+  aqt_status s = chfsi_set_mask(ctx, c, m);
+  if (s == AQT_OK) s = chfsi_upload(ctx, c.info.p, c.h_info.data(), c.h_info.size() * 4);
+  // Gram matrix of diag(x) over the ncols Ritz vectors (cluster rotations)
+  if (s == AQT_OK) s = chfsi_gram(ctx, c, c.X.as<double>(), c.X.as<double>(), ncols, 2);
+  if (s != AQT_OK) return s;
+  hipLaunchKernelGGL(k_canon_rot, dim3(nb), dim3(kEigThreads), 0, st, c.S.as<double>(), c.KB, c.theta.as<double>(),
+                     ncols, n, NP, tol, c.info.as<int>(), ctx->E.as<double>(), ctx->gs.as<int>(), c.C.as<double>(),
+                     c.cl.as<int>(), c.ws.as<double>(), status);
+  AQT_HIP(ctx, hipGetLastError());
+  hipLaunchKernelGGL(k_canon_apply, dim3(nblk(c.N), ncols, nb), dim3(256), 0, st, c.X.as<double>(), c.blk,
+                     c.C.as<double>(), c.KB, c.cl.as<int>(), c.info.as<int>(), ncols, c.N, Vout, Vstride);
+  AQT_HIP(ctx, hipGetLastError());
+  hipLaunchKernelGGL(k_canon_signs, dim3(n, nb), dim3(256), 0, st, Vout, Vstride, c.info.as<int>(), c.N);
+  AQT_HIP(ctx, hipGetLastError());
+  return AQT_OK;
+}
+
+constexpr int kChainMinRun = 8;   // grid points per chain, at least
+
+// Eigenpairs and canonical vectors of grid points g0 .. g0+cnt-1 (chunk entries
+// 0 .. cnt-1 of Vout).  The run is cut into up to c.nb contiguous chains.  The
+// chain heads are solved one after another, each warm-started from the head before
+// it (the first from the last grid point solved before), then the chains advance
+// one grid point per step in lock step.
+aqt_status chfsi_chunk(aqt_ctx* ctx, Chfsi& c, const double* eZ, const std::vector<double>& Ag,
+                       const std::vector<double>& Bg, int g0, int cnt, int ncols, int n, int NP, double tol,
+                       double* Vout, size_t Vstride, int* status) {
+  const int nb = c.nb;
+  const int nc = std::max(1, std::min(nb, cnt / kChainMinRun));
+  std::vector<int> head(nc + 1);
+  for (int j = 0; j <= nc; ++j) head[j] = g0 + static_cast<int>(static_cast<int64_t>(j) * cnt / nc);
+  // grid 0 only supplies the initial state (its ground state, checked to be
+  // non-degenerate); H(0) is typically highly degenerate, so only the two lowest
+  // levels are converged there
+  auto nconv_at = [&](int g) { return (g == 0) ? std::min(2, ncols) : ncols; };
+  std::vector<int> gidx(nb, -1), nconv(nb, 0);
+  aqt_status s = AQT_OK;
+  for (int j = 0; j < nc; ++j) {
+    if (j > 0) {
+      AQT_HIP(ctx, hipMemcpyAsync(c.at(c.X, j), c.at(c.X, j - 1), c.blk * 8, hipMemcpyDeviceToDevice, ctx->stream));
+      c.warm[j] = 1;
+    }
+    std::fill(gidx.begin(), gidx.end(), -1);
+    std::fill(nconv.begin(), nconv.end(), 0);
+    gidx[j] = head[j];
+    nconv[j] = nconv_at(head[j]);
+    if ((s = chfsi_solve(ctx, c, eZ, Ag, Bg, gidx, nconv, 1e-12)) != AQT_OK) return s;
+  }
+  std::fill(gidx.begin(), gidx.end(), -1);
+  int len = 0;
+  for (int j = 0; j < nc; ++j) {
+    gidx[j] = head[j];
+    len = std::max(len, head[j + 1] - head[j]);
+  }
+  if ((s = chfsi_canon(ctx, c, gidx, g0, ncols, n, NP, tol, Vout, Vstride, status)) != AQT_OK) return s;
+  for (int t = 1; t < len; ++t) {
+    for (int j = 0; j < nb; ++j) {
+      const bool on = j < nc && head[j] + t < head[j + 1];
+      gidx[j] = on ? head[j] + t : -1;
+      nconv[j] = on ? nconv_at(gidx[j]) : 0;
+    }
+    if ((s = chfsi_solve(ctx, c, eZ, Ag, Bg, gidx, nconv, 1e-12)) != AQT_OK) return s;
+    if ((s = chfsi_canon(ctx, c, gidx, g0, ncols, n, NP, tol, Vout, Vstride, status)) != AQT_OK) return s;
+  }
+  // the next chunk starts from the last grid point of this one
+  if (nc > 1) {
+    AQT_HIP(ctx, hipMemcpyAsync(c.at(c.X, 0), c.at(c.X, nc - 1), c.blk * 8, hipMemcpyDeviceToDevice, ctx->stream));
+    c.warm[0] = 1;
+  }
   return AQT_OK;
 }
 
@@ -1444,7 +1807,7 @@ aqt_status precompute_tables(aqt_ctx* ctx, int M, int n, double tol, int method,
   // ---- chunked workspace
   const size_t per_grid = (iterative ? 0 : 2 * static_cast<size_t>(N) * N)   // H, Z (dense path)
                           + static_cast<size_t>(ncols) * N            // canonical V
-                          + 2 * static_cast<size_t>(ncols) * ncols + static_cast<size_t>(ncols) * N  // canon ws
+                          + (iterative ? 0 : 2 * static_cast<size_t>(ncols) * ncols + static_cast<size_t>(ncols) * N)  // canon ws
                           + static_cast<size_t>(nch) * n * n          // z
                           + (sx ? static_cast<size_t>(nch) * n * N : 0)   // channel operators on V
                           + 9 * static_cast<size_t>(n) * n            // polar ws
@@ -1458,7 +1821,7 @@ aqt_status precompute_tables(aqt_ctx* ctx, int M, int n, double tol, int method,
   DevBuf H, Z, Vc, Vprev, cws, zws, pws, Eraw, perm, status;
   if ((!iterative && (H.reserve(static_cast<size_t>(Gc) * N * N * 8) || Z.reserve(static_cast<size_t>(Gc) * N * N * 8))) ||
       Vc.reserve(static_cast<size_t>(Gc) * ncols * N * 8) || Vprev.reserve(static_cast<size_t>(ncols) * N * 8) ||
-      cws.reserve(static_cast<size_t>(Gc) * (2 * static_cast<size_t>(ncols) * ncols + static_cast<size_t>(ncols) * N) * 8) ||
+      (!iterative && cws.reserve(static_cast<size_t>(Gc) * (2 * static_cast<size_t>(ncols) * ncols + static_cast<size_t>(ncols) * N) * 8)) ||
       zws.reserve(static_cast<size_t>(Gc) * nch * n * n * 8) || pws.reserve(static_cast<size_t>(Gc) * 9 * n * n * 8) ||
       Eraw.reserve(static_cast<size_t>(Gc) * N * 8) || perm.reserve(static_cast<size_t>(Gc) * N * 4) ||
       status.reserve(static_cast<size_t>(Gc) * 4))
@@ -1483,23 +1846,28 @@ aqt_status precompute_tables(aqt_ctx* ctx, int M, int n, double tol, int method,
   std::vector<int> hstat(Gc);
   const size_t Vstride = static_cast<size_t>(ncols) * N;
   Chfsi ch;
-  DevBuf ident;
   if (iterative) {
     ch.nq = nq;
     ch.N = N;
     ch.KB = KB;
     ch.ksplit = std::max(1, std::min(256, N / 256));
-    const size_t blk = static_cast<size_t>(KB) * N * 8;
-    if (ch.X.reserve(blk) || ch.Y1.reserve(blk) || ch.Y2.reserve(blk) || ch.W.reserve(blk) ||
-        ch.part.reserve(static_cast<size_t>(ch.ksplit) * KB * KB * 8) || ch.S.reserve(KB * KB * 8) ||
-        ch.C.reserve(KB * KB * 8) || ch.theta.reserve(KB * 8) || ch.res.reserve(KB * 8) ||
-        ch.ws.reserve(2 * KB * KB * 8) || ch.status.reserve(4) || ident.reserve(KB * 4))
+    ch.blk = static_cast<size_t>(KB) * N;
+    const size_t kk = static_cast<size_t>(KB) * KB;
+    // slots (chains solved together): up to kMaxChains, within 8 GiB of workspace
+    const size_t per_slot = (4 * ch.blk + static_cast<size_t>(ch.ksplit) * kk + 5 * kk + 2 * KB) * 8;
+    ch.nb = static_cast<int>(std::max<size_t>(1, std::min<size_t>(kMaxChains, (size_t(8) << 30) / per_slot)));
+    const size_t nb = ch.nb;
+    if (ch.X.reserve(nb * ch.blk * 8) || ch.Y1.reserve(nb * ch.blk * 8) || ch.Y2.reserve(nb * ch.blk * 8) ||
+        ch.W.reserve(nb * ch.blk * 8) || ch.part.reserve(nb * ch.ksplit * kk * 8) || ch.S.reserve(nb * kk * 8) ||
+        ch.C.reserve(nb * kk * 8) || ch.theta.reserve(nb * KB * 8) || ch.res.reserve(nb * KB * 8) ||
+        ch.ws.reserve(nb * 2 * kk * 8) || ch.status.reserve(nb * 4) || ch.act.reserve(nb * 4) ||
+        ch.coef.reserve(nb * (1 + kMaxFilterDegree) * sizeof(HxCoef)) || ch.info.reserve(nb * 2 * 4) ||
+        ch.cl.reserve(nb * 2 * KB * 4))
       return ctx->fail(AQT_ENOMEM, "subspace iteration workspace allocation failed");
-    ch.h_theta.resize(KB);
-    ch.h_res.resize(KB);
-    std::vector<int> id(KB);
-    for (int a = 0; a < KB; ++a) id[a] = a;
-    AQT_HIP(ctx, hipMemcpyAsync(ident.p, id.data(), KB * 4, hipMemcpyHostToDevice, st));
+    ch.h_theta.resize(nb * KB);
+    ch.h_res.resize(nb * KB);
+    ch.h_status.resize(nb);
+    ch.warm.assign(nb, 0);
     std::vector<double> hz(N);
     AQT_HIP(ctx, hipMemcpyAsync(hz.data(), eZ.p, N * 8, hipMemcpyDeviceToHost, st));
     AQT_HIP(ctx, hipStreamSynchronize(st));
@@ -1524,36 +1892,13 @@ aqt_status precompute_tables(aqt_ctx* ctx, int M, int n, double tol, int method,
       AQT_HIP(ctx, hipGetLastError());
       hipLaunchKernelGGL(k_canon, dim3(cnt), dim3(kEigThreads), 0, st, Z.as<double>(), perm.as<int>(),
                          Eraw.as<double>(), N, ncols, n, NP, tol, g0, Vc.as<double>(), ctx->E.as<double>(),
-                         ctx->gs.as<int>(), cws.as<double>(), status.as<int>(), nullptr);
+                         ctx->gs.as<int>(), cws.as<double>(), status.as<int>());
       AQT_HIP(ctx, hipGetLastError());
     } else {
       AQT_HIP(ctx, hipMemsetAsync(status.p, 0, cnt * 4, st));
-      for (int c = 0; c < cnt; ++c) {
-        const int g = g0 + c;
-        // grid 0 only supplies the initial state (its ground state, checked to be
-        // non-degenerate); H(0) is typically highly degenerate, so only the two
-        // lowest levels are converged there
-        const int nconv = (g == 0) ? std::min(2, ncols) : ncols;
-        aqt_status s = chfsi_solve(ctx, ch, eZ.as<double>(), Ag[g], Bg[g], nconv, 1e-12,
-                                   "at grid point " + std::to_string(g));
-        if (s != AQT_OK) return s;
-        {
-          // Gram matrix of diag(x) over the ncols Ritz vectors (cluster rotations), split over x
-          const int kspan = (N + ch.ksplit - 1) / ch.ksplit;
-          GemmArgs ga{ch.X.as<double>(), ch.X.as<double>(), ch.part.as<double>(), 0, 0,
-                      static_cast<int64_t>(ncols) * ncols, ncols, ncols, N, N, N, ncols, 2, nq, 0, ch.ksplit, kspan};
-          aqt_status s2 = launch_gemm(ctx, ga, ch.ksplit);
-          if (s2 != AQT_OK) return s2;
-          hipLaunchKernelGGL(k_splitk_reduce, dim3(nblk(static_cast<int64_t>(ncols) * ncols)), dim3(256), 0, st,
-                             ch.part.as<double>(), ch.ksplit, ncols, ncols, 1, ch.S.as<double>(), 0, ncols, 0);
-          AQT_HIP(ctx, hipGetLastError());
-        }
-        hipLaunchKernelGGL(k_canon, dim3(1), dim3(kEigThreads), 0, st, ch.X.as<double>(), ident.as<int>(),
-                           ch.theta.as<double>(), N, ncols, n, NP, tol, g, Vc.as<double>() + c * Vstride,
-                           ctx->E.as<double>(), ctx->gs.as<int>(), cws.as<double>(), status.as<int>() + c,
-                           ch.S.as<double>());
-        AQT_HIP(ctx, hipGetLastError());
-      }
+      aqt_status s = chfsi_chunk(ctx, ch, eZ.as<double>(), Ag, Bg, g0, cnt, ncols, n, NP, tol, Vc.as<double>(),
+                                 Vstride, status.as<int>());
+      if (s != AQT_OK) return s;
     }
     AQT_HIP(ctx, hipMemcpyAsync(hstat.data(), status.p, cnt * 4, hipMemcpyDeviceToHost, st));
     AQT_HIP(ctx, hipStreamSynchronize(st));
