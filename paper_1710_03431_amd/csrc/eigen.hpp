@@ -27,17 +27,20 @@ namespace aqt {
 constexpr int kEigThreads = 256;
 constexpr int kEigMaxN = 1024;
 
-struct EigShared {
-  double v[kEigMaxN];     // Householder vector / scratch
-  double w[kEigMaxN];     // p, then w
-  double d[kEigMaxN];     // band diagonal
-  double e[kEigMaxN];     // band off-diagonal
-  double beta[kEigMaxN];  // reflection coefficients
-  double c[kEigMaxN];     // rotation cosines of one sweep
-  double s[kEigMaxN];     // rotation sines of one sweep
+// LDS state of the solver for matrices of order up to MaxN.
+template <int MaxN>
+struct EigSharedN {
+  double v[MaxN];     // Householder vector / scratch
+  double w[MaxN];     // p, then w
+  double d[MaxN];     // band diagonal
+  double e[MaxN];     // band off-diagonal
+  double beta[MaxN];  // reflection coefficients
+  double c[MaxN];     // rotation cosines of one sweep
+  double s[MaxN];     // rotation sines of one sweep
   double red[kEigThreads / kWave];
   int lo, hi, done, fail;
 };
+using EigShared = EigSharedN<kEigMaxN>;
 
 __device__ __forceinline__ double block_sum(double v, double* red) {
   const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x >> 6;
@@ -54,7 +57,8 @@ __device__ __forceinline__ double block_sum(double v, double* red) {
 // Reduce symmetric A (row-major, leading dimension lda) to tridiagonal form.
 // On exit sh.d/sh.e hold the band, sh.beta the reflection coefficients and row
 // j of A, right of the diagonal, the Householder vector of step j.
-__device__ void wg_tridiagonalize(double* A, int N, int lda, EigShared& sh) {
+template <class Sh>
+__device__ void wg_tridiagonalize(double* A, int N, int lda, Sh& sh) {
   const int tid = threadIdx.x;
   const int lane = tid & (kWave - 1), wave = tid >> 6;
   for (int j = 0; j + 2 < N; ++j) {
@@ -119,12 +123,16 @@ __device__ void wg_tridiagonalize(double* A, int N, int lda, EigShared& sh) {
 }
 
 // Implicit symmetric QR on the band in sh.d/sh.e; rotations accumulated into
-// Z (column-major N x N, leading dimension ldz, initialised to I here).
+// Z (column-major N x N, leading dimension ldz), which is initialised to I here
+// unless from_z is set (then Z's columns are rotated as given: starting from the
+// reflection product, Z ends up holding the eigenvectors of the full matrix).
 // Returns false if the iteration budget is exhausted.
-__device__ bool wg_band_qr(double* Z, int N, int ldz, EigShared& sh) {
+template <class Sh>
+__device__ bool wg_band_qr(double* Z, int N, int ldz, Sh& sh, bool from_z = false) {
   const int tid = threadIdx.x;
-  for (int c = 0; c < N; ++c)
-    for (int r = tid; r < N; r += kEigThreads) Z[static_cast<size_t>(c) * ldz + r] = (r == c) ? 1.0 : 0.0;
+  if (!from_z)
+    for (int c = 0; c < N; ++c)
+      for (int r = tid; r < N; r += kEigThreads) Z[static_cast<size_t>(c) * ldz + r] = (r == c) ? 1.0 : 0.0;
   if (tid == 0) {
     sh.done = 0;
     sh.fail = 0;
@@ -133,50 +141,85 @@ __device__ bool wg_band_qr(double* Z, int N, int ldz, EigShared& sh) {
   __syncthreads();
   const long budget = 64L * N + 64;
   for (long sweep = 0;; ++sweep) {
-    if (tid == 0) {
-      int m = sh.hi;
-      int l = 0;
-      bool have = false;
-      while (m > 0) {
-        for (int k = 0; k < m; ++k)
-          if (fabs(sh.e[k]) <= 2.220446049250313e-16 * (fabs(sh.d[k]) + fabs(sh.d[k + 1]))) sh.e[k] = 0.0;
-        if (sh.e[m - 1] == 0.0) {
-          --m;
-          continue;
+    if (tid < kWave) {
+      // wavefront 0: deflation.  Negligible off-diagonal entries below hi are zeroed;
+      // the window [l, m] is the unreduced block that ends at the highest nonzero e.
+      const int m0 = sh.hi;
+      for (int k = tid; k < m0; k += kWave)
+        if (fabs(sh.e[k]) <= 2.220446049250313e-16 * (fabs(sh.d[k]) + fabs(sh.d[k + 1]))) sh.e[k] = 0.0;
+      int m = 0;
+      for (int c = (m0 - 1) / kWave; c >= 0 && m0 > 0; --c) {
+        const int k = c * kWave + tid;
+        const unsigned long long nz = __ballot(k < m0 && sh.e[k] != 0.0);
+        if (nz) {
+          m = c * kWave + (63 - __clzll(nz)) + 1;
+          break;
         }
-        l = m - 1;
-        while (l > 0 && sh.e[l - 1] != 0.0) --l;
-        have = true;
-        break;
       }
-      sh.hi = m;
-      if (!have || sweep >= budget) {
-        sh.done = 1;
-        sh.fail = have ? 1 : 0;
-      } else {
-        // Wilkinson shift from the trailing 2x2 block of the window [l, m]
-        const double delta = 0.5 * (sh.d[m - 1] - sh.d[m]);
-        const double bb = sh.e[m - 1];
-        const double den = delta + copysign(hypot(delta, bb), delta >= 0.0 ? 1.0 : -1.0);
-        const double mu = sh.d[m] - bb * bb / den;
-        double x = sh.d[l] - mu, z = sh.e[l];
-        for (int k = l; k < m; ++k) {
-          const double r = hypot(x, z);
-          const double c = x / r, s = z / r;
-          if (k > l) sh.e[k - 1] = r;
-          const double a = sh.d[k], b = sh.e[k], cc = sh.d[k + 1];
-          sh.d[k] = c * c * a + 2.0 * c * s * b + s * s * cc;
-          sh.d[k + 1] = s * s * a - 2.0 * c * s * b + c * c * cc;
-          sh.e[k] = c * s * (cc - a) + (c * c - s * s) * b;
-          if (k + 1 < m) {
-            z = s * sh.e[k + 1];
-            sh.e[k + 1] *= c;
-          }
-          x = sh.e[k];
-          sh.c[k] = c;
-          sh.s[k] = s;
+      int l = 0;
+      for (int c = (m - 2) / kWave; c >= 0 && m >= 2; --c) {
+        const int k = c * kWave + tid;
+        const unsigned long long zr = __ballot(k < m - 1 && sh.e[k] == 0.0);
+        if (zr) {
+          l = c * kWave + (63 - __clzll(zr)) + 1;
+          break;
         }
-        sh.lo = l;
+      }
+      const bool have = m > 0;
+      if (tid == 0) {
+        sh.hi = m;
+        if (!have || sweep >= budget) {
+          sh.done = 1;
+          sh.fail = have ? 1 : 0;
+        } else {
+          // Wilkinson shift from the trailing 2x2 block of the window [l, m]
+          const double delta = 0.5 * (sh.d[m - 1] - sh.d[m]);
+          const double bb = sh.e[m - 1];
+          const double den = delta + copysign(hypot(delta, bb), delta >= 0.0 ? 1.0 : -1.0);
+          const double mu = sh.d[m] - bb * bb / den;
+          // bulge chase; the running diagonal (dk), the scaled off-diagonal (bk) and the
+          // untouched next diagonal (dn) stay in registers, the next band entries are
+          // loaded one rotation ahead.  1/r by Newton's iteration for the reciprocal
+          // square root (two steps from the hardware estimate), squares in range.
+          double x = sh.d[l] - mu, z = sh.e[l];
+          double dk = sh.d[l], bk = sh.e[l], dn = sh.d[l + 1];
+          double ek = 0.0;
+          for (int k = l; k < m; ++k) {
+            const bool more = k + 1 < m;
+            const double en = more ? sh.e[k + 1] : 0.0;
+            const double dnn = more ? sh.d[k + 2] : 0.0;
+            const double q = fma(x, x, z * z);
+            double r, ri;
+            if (q > 1e-300 && q < 1e300) {
+              double y = __builtin_amdgcn_rsq(q);
+              const double hq = 0.5 * q;
+              y = y * fma(-hq * y, y, 1.5);
+              y = y * fma(-hq * y, y, 1.5);
+              ri = y;
+              r = q * y;
+            } else {
+              r = hypot(x, z);
+              ri = 1.0 / r;
+            }
+            const double c = x * ri, s = z * ri;
+            if (k > l) sh.e[k - 1] = r;
+            const double a = dk, b = bk, cc = dn;
+            sh.d[k] = c * c * a + 2.0 * c * s * b + s * s * cc;
+            dk = s * s * a - 2.0 * c * s * b + c * c * cc;
+            ek = c * s * (cc - a) + (c * c - s * s) * b;
+            if (more) {
+              z = s * en;
+              bk = c * en;
+              dn = dnn;
+            }
+            x = ek;
+            sh.c[k] = c;
+            sh.s[k] = s;
+          }
+          sh.d[m] = dk;
+          sh.e[m - 1] = ek;
+          sh.lo = l;
+        }
       }
     }
     __syncthreads();
@@ -184,7 +227,21 @@ __device__ bool wg_band_qr(double* Z, int N, int ldz, EigShared& sh) {
     const int l = sh.lo, m = sh.hi;
     for (int r = tid; r < N; r += kEigThreads) {
       double zk = Z[static_cast<size_t>(l) * ldz + r];
-      for (int k = l; k < m; ++k) {
+      int k = l;
+      // eight columns loaded ahead of their rotations: each column is read before the
+      // rotation that rewrites it, and the loads are in flight together
+      for (; k + 8 <= m; k += 8) {
+        double z1[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) z1[u] = Z[static_cast<size_t>(k + 1 + u) * ldz + r];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          const double c = sh.c[k + u], s = sh.s[k + u];
+          Z[static_cast<size_t>(k + u) * ldz + r] = c * zk + s * z1[u];
+          zk = -s * zk + c * z1[u];
+        }
+      }
+      for (; k < m; ++k) {
         const double zk1 = Z[static_cast<size_t>(k + 1) * ldz + r];
         const double c = sh.c[k], s = sh.s[k];
         Z[static_cast<size_t>(k) * ldz + r] = c * zk + s * zk1;
@@ -201,8 +258,9 @@ __device__ bool wg_band_qr(double* Z, int N, int ldz, EigShared& sh) {
 
 // Apply the stored reflections to the columns of Z listed in cols[0..ncols-1]
 // (column-major), turning band eigenvectors into eigenvectors of A.
+template <class Sh>
 __device__ void wg_back_transform(const double* A, int N, int lda, double* Z, int ldz, const int* cols, int ncols,
-                                  EigShared& sh) {
+                                  Sh& sh) {
   const int tid = threadIdx.x;
   const int lane = tid & (kWave - 1), wave = tid >> 6;
   for (int j = N - 3; j >= 0; --j) {
@@ -246,6 +304,136 @@ __device__ void wg_rank_ascending(const double* d, int N, int* perm) {
   __syncthreads();
 }
 
+
+// ---- small matrices resident in LDS (order N <= kEigThreads) -------------------
+// One thread per row (or column) walks it serially: no block reductions in the
+// inner loops, and a leading dimension that is odd in doubles keeps the threads of
+// a wavefront on different banks.
+
+// sum_k a[k] b[k] over k < L, eight independent loads and partial sums in flight
+__device__ __forceinline__ double lds_dot(const double* a, const double* b, int L) {
+  double acc[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  int k = 0;
+  for (; k + 8 <= L; k += 8) {
+    double x[8], y[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      x[u] = a[k + u];
+      y[u] = b[k + u];
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) acc[u] = fma(x[u], y[u], acc[u]);
+  }
+  for (; k < L; ++k) acc[0] = fma(a[k], b[k], acc[0]);
+  return ((acc[0] + acc[1]) + (acc[2] + acc[3])) + ((acc[4] + acc[5]) + (acc[6] + acc[7]));
+}
+
+// y[k] -= alpha * x[k] + beta * z[k] over k < L, eight entries per batch
+__device__ __forceinline__ void lds_axpy2(double* y, double alpha, const double* x, double beta, const double* z,
+                                          int L) {
+  int k = 0;
+  for (; k + 8 <= L; k += 8) {
+    double yy[8], xx[8], zz[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      yy[u] = y[k + u];
+      xx[u] = x[k + u];
+      zz[u] = z[k + u];
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) y[k + u] = yy[u] - (alpha * xx[u] + beta * zz[u]);
+  }
+  for (; k < L; ++k) y[k] -= alpha * x[k] + beta * z[k];
+}
+
+// Householder tridiagonalisation as wg_tridiagonalize, A row-major in LDS.
+template <class Sh>
+__device__ void lds_tridiagonalize(double* A, int N, int lda, Sh& sh) {
+  const int tid = threadIdx.x;
+  for (int j = 0; j + 2 < N; ++j) {
+    const int L = N - j - 1;
+    double* row = A + j * lda + j + 1;
+    if (tid < kWave) {
+      double part = 0.0;
+      for (int i = tid + 1; i < L; i += kWave) part += row[i] * row[i];
+      part = wave_sum(part);
+      if (tid == 0) sh.red[j & 1] = part;   // alternating slot: readers of step j-1 may lag
+    }
+    __syncthreads();
+    const double tail = sh.red[j & 1];
+    const double x0 = row[0];
+    if (tid == 0) sh.d[j] = A[j * lda + j];
+    if (tail == 0.0) {
+      if (tid == 0) {
+        sh.e[j] = x0;
+        sh.beta[j] = 0.0;
+      }
+      __syncthreads();
+      continue;
+    }
+    const double sigma = sqrt(x0 * x0 + tail);
+    const double alpha = (x0 >= 0.0) ? -sigma : sigma;
+    const double v0 = x0 - alpha;
+    const double beta = 2.0 / (v0 * v0 + tail);
+    for (int i = tid; i < L; i += blockDim.x) sh.v[i] = (i == 0) ? v0 : row[i];
+    __syncthreads();
+    // p = beta * S v, one thread per row of the trailing block S
+    for (int i = tid; i < L; i += blockDim.x) sh.w[i] = beta * lds_dot(A + (j + 1 + i) * lda + j + 1, sh.v, L);
+    __syncthreads();
+    // Kc = beta/2 v.p (every thread, broadcast reads); with w = p - Kc v the update is
+    // S_ik -= v_i w_k + w_i v_k = v_i p_k + (w_i - Kc v_i) v_k
+    const double Kc = 0.5 * beta * lds_dot(sh.v, sh.w, L);
+    for (int i = tid; i < L; i += blockDim.x) {
+      const double vi = sh.v[i], wi = sh.w[i] - Kc * vi;
+      lds_axpy2(A + (j + 1 + i) * lda + j + 1, vi, sh.w, wi - Kc * vi, sh.v, L);
+      row[i] = vi;
+    }
+    if (tid == 0) {
+      sh.e[j] = alpha;
+      sh.beta[j] = beta;
+    }
+    __syncthreads();
+  }
+  if (tid == 0) {
+    if (N >= 2) {
+      sh.d[N - 2] = A[(N - 2) * lda + N - 2];
+      sh.e[N - 2] = A[(N - 2) * lda + N - 1];
+      sh.beta[N - 2] = 0.0;
+    }
+    sh.d[N - 1] = A[(N - 1) * lda + N - 1];
+    sh.e[N - 1] = 0.0;
+    sh.beta[N - 1] = 0.0;
+  }
+  __syncthreads();
+}
+
+// Z = H_0 H_1 ... H_{N-3}, the product of the reflections of lds_tridiagonalize
+// (vectors in Hv, row j right of the diagonal, leading dimension ldh; coefficients in
+// sh.beta), column-major in LDS (leading dimension ldz), one thread per column.
+// Columns q <= j are still unit vectors when H_j is applied, so only q > j are touched.
+template <class Sh>
+__device__ void lds_form_q(const double* Hv, int ldh, int N, double* Z, int ldz, Sh& sh) {
+  const int tid = threadIdx.x;
+  for (int f = tid; f < N * N; f += blockDim.x) {
+    const int c = f / N, r = f - c * N;
+    Z[c * ldz + r] = (r == c) ? 1.0 : 0.0;
+  }
+  for (int j = N - 3; j >= 0; --j) {
+    const double beta = sh.beta[j];
+    if (beta == 0.0) continue;
+    const int L = N - j - 1;
+    const double* vrow = Hv + static_cast<size_t>(j) * ldh + j + 1;
+    __syncthreads();   // previous step's readers of sh.v are done (and Z's first fill)
+    for (int i = tid; i < L; i += blockDim.x) sh.v[i] = vrow[i];
+    __syncthreads();
+    for (int q = j + 1 + tid; q < N; q += blockDim.x) {
+      double* zc = Z + q * ldz + j + 1;
+      const double w = beta * lds_dot(sh.v, zc, L);
+      lds_axpy2(zc, w, sh.v, 0.0, sh.v, L);
+    }
+  }
+  __syncthreads();
+}
 
 // ---- lowest eigenpairs of the band without the full rotation product --------
 // Number of eigenvalues of the symmetric tridiagonal (d, e) below x (Sturm count

@@ -958,6 +958,7 @@ aqt_status launch_gemm(aqt_ctx* ctx, const GemmArgs& g, int batch) {
 // converged (or that has no grid point at this step) is masked out.
 
 constexpr int kHxChunk = 4096;        // x per workgroup of the block product (LDS-resident)
+constexpr int kSmallEigMax = 128;     // block size of the subspace iteration, at most
 constexpr int kMaxFilterDegree = 256;  // Chebyshev filter degree, at most
 constexpr int kMaxChains = 16;         // block slots of the lock-step chains, at most
 
@@ -999,35 +1000,55 @@ __global__ __launch_bounds__(256) void k_hx_block(const double* __restrict__ X, 
 }
 
 // Y_j = sum_i C[i][j] X_i (C row-major KB x KB) in every slot (blockIdx.y): the
-// block times a small matrix.  A masked slot is skipped, or copied (Y = X) when
+// block times a small matrix, on FP64 MFMAs.  C is staged in LDS (rows padded by 16
+// doubles, so the four k-rows a wavefront reads at once start 128 bytes apart); each
+// wavefront owns 16 columns x of the workgroup's 128 and all KB rows j, and reads its
+// X columns once, as the B operand.  A masked slot is skipped, or copied (Y = X) when
 // copy_masked is set.
+constexpr int kCombineCols = 128;   // columns x per workgroup (8 wavefronts x 16)
 template <int KB>
-__global__ __launch_bounds__(256) void k_combine(const double* __restrict__ X, const double* __restrict__ C,
+__global__ __launch_bounds__(512) void k_combine(const double* __restrict__ X, const double* __restrict__ C,
                                                  double* __restrict__ Y, int N, const int* __restrict__ act,
                                                  int copy_masked) {
+  constexpr int LDC = KB + 16;
+  constexpr int T = KB / 16;   // 16-row output tiles per wavefront
   const int b = blockIdx.y;
   const size_t off = static_cast<size_t>(b) * KB * N;
-  const int x = blockIdx.x * blockDim.x + threadIdx.x;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int x0 = blockIdx.x * kCombineCols;
   if (!act[b]) {
-    if (copy_masked && x < N)
-      for (int jj = 0; jj < KB; ++jj) Y[off + static_cast<size_t>(jj) * N + x] = X[off + static_cast<size_t>(jj) * N + x];
+    if (copy_masked)
+      for (int f = tid; f < KB * kCombineCols; f += blockDim.x) {
+        const int r = f / kCombineCols, x = x0 + f % kCombineCols;
+        if (x < N) Y[off + static_cast<size_t>(r) * N + x] = X[off + static_cast<size_t>(r) * N + x];
+      }
     return;
   }
-  __shared__ double sC[KB * KB];
+  __shared__ double sC[KB * LDC];
   const double* Cb = C + static_cast<size_t>(b) * KB * KB;
-  for (int f = threadIdx.x; f < KB * KB; f += blockDim.x) sC[f] = Cb[f];
+  for (int f = tid; f < KB * KB; f += blockDim.x) sC[(f / KB) * LDC + f % KB] = Cb[f];
   __syncthreads();
-  if (x >= N) return;
-  double acc[KB];
+  const int xw = x0 + 16 * wave;
+  if (xw >= N) return;   // N >= 64 and a power of two: a wavefront's 16 columns are all in range or all out
+  const int col = lane & 15, kq = lane >> 4;
+  // FP64 16x16x4 operands: lane l supplies A[l % 16][l / 16] and B[l / 16][l % 16]
+  const double* xb = X + off + xw + col;
+  d4 acc[T];
 #pragma unroll
-  for (int jj = 0; jj < KB; ++jj) acc[jj] = 0.0;
-  for (int i = 0; i < KB; ++i) {
-    const double xi = X[off + static_cast<size_t>(i) * N + x];
+  for (int t = 0; t < T; ++t) acc[t] = d4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll 8
+  for (int i0 = 0; i0 < KB; i0 += 4) {
+    const int i = i0 + kq;
+    const double bv = xb[static_cast<size_t>(i) * N];
 #pragma unroll
-    for (int jj = 0; jj < KB; ++jj) acc[jj] += sC[i * KB + jj] * xi;
+    for (int t = 0; t < T; ++t)
+      acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(sC[i * LDC + 16 * t + col], bv, acc[t], 0, 0, 0);
   }
+  // accumulator: lane l, element e holds row l/16 + 4e, column l%16 of the tile
 #pragma unroll
-  for (int jj = 0; jj < KB; ++jj) Y[off + static_cast<size_t>(jj) * N + x] = acc[jj];
+  for (int t = 0; t < T; ++t)
+#pragma unroll
+    for (int e = 0; e < 4; ++e) Y[off + static_cast<size_t>(16 * t + kq + 4 * e) * N + xw + col] = acc[t][e];
 }
 
 // Deterministic start block: entries in [-1, 1) from a counter hash.
@@ -1056,22 +1077,26 @@ __global__ __launch_bounds__(kEigThreads) void k_small_eig(const double* __restr
                                                            const int* __restrict__ act) {
   const int b = blockIdx.x;
   if (!act[b]) return;
-  __shared__ EigShared sh;
-  __shared__ int s_perm[kEigMaxN];
-  __shared__ double s_dinv[kEigMaxN];
+  // the matrix lives in LDS (KB <= kSmallEigMax, rows padded to an odd length); ws
+  // holds the reflection vectors of the eigen route
+  constexpr int LDS_LD = kSmallEigMax + 1;
+  __shared__ EigSharedN<kSmallEigMax> sh;
+  __shared__ double sA[kSmallEigMax * LDS_LD];
+  __shared__ int s_perm[kSmallEigMax];
+  __shared__ double s_dinv[kSmallEigMax];
   S += static_cast<size_t>(b) * KB * KB;
   C += static_cast<size_t>(b) * KB * KB;
   theta += static_cast<size_t>(b) * KB;
   ws += static_cast<size_t>(b) * 2 * KB * KB;
   status += b;
-  double* A = ws;
-  double* Z = ws + static_cast<size_t>(KB) * KB;
+  const int lda = KB + 1;
+  double* A = sA;
   for (int a = threadIdx.x; a < KB; a += blockDim.x)
     s_dinv[a] = (mode >= 1) ? 1.0 / sqrt(fmax(S[a * KB + a], 1e-300)) : 1.0;
   __syncthreads();
   for (int f = threadIdx.x; f < KB * KB; f += blockDim.x) {
     const int i = f / KB, j = f - i * KB;
-    A[f] = 0.5 * (S[f] + S[j * KB + i]) * s_dinv[i] * s_dinv[j];
+    A[i * lda + j] = 0.5 * (S[f] + S[j * KB + i]) * s_dinv[i] * s_dinv[j];
   }
   __syncthreads();
   if (mode == 2) {
@@ -1079,52 +1104,74 @@ __global__ __launch_bounds__(kEigThreads) void k_small_eig(const double* __restr
     // to the eigen route (mode 1) when a pivot is small (ill-conditioned block).
     bool okc = true;
     for (int k = 0; k < KB; ++k) {
-      const double piv = A[k * KB + k];
+      const double piv = A[k * lda + k];
       if (!(piv > 1e-10)) {
         okc = false;
         break;
       }
       const double lkk = sqrt(piv);
       __syncthreads();
-      for (int i = k + threadIdx.x; i < KB; i += blockDim.x) A[i * KB + k] = (i == k) ? lkk : A[i * KB + k] / lkk;
+      for (int i = k + threadIdx.x; i < KB; i += blockDim.x) A[i * lda + k] = (i == k) ? lkk : A[i * lda + k] / lkk;
       __syncthreads();
-      const int m = KB - k - 1;
-      for (int f = threadIdx.x; f < m * m; f += blockDim.x) {
-        const int i = k + 1 + f / m, j = k + 1 + f % m;
-        if (j <= i) A[i * KB + j] -= A[i * KB + k] * A[j * KB + k];
+      // trailing update, one thread per row, eight column entries loaded per batch
+      for (int i = k + 1 + threadIdx.x; i < KB; i += blockDim.x) {
+        const double lik = A[i * lda + k];
+        double* Ai = A + i * lda;
+        int j = k + 1;
+        for (; j + 8 <= i + 1; j += 8) {
+          double ajk[8], aij[8];
+#pragma unroll
+          for (int u = 0; u < 8; ++u) {
+            ajk[u] = A[(j + u) * lda + k];
+            aij[u] = Ai[j + u];
+          }
+#pragma unroll
+          for (int u = 0; u < 8; ++u) Ai[j + u] = aij[u] - lik * ajk[u];
+        }
+        for (; j <= i; ++j) Ai[j] -= lik * A[j * lda + k];
       }
       __syncthreads();
     }
     if (okc) {
-      // L^-1 by forward substitution, one column per thread
-      for (int j = threadIdx.x; j < KB; j += blockDim.x)
-        for (int i = 0; i < KB; ++i) {
-          if (i < j) {
-            Z[i * KB + j] = 0.0;
-            continue;
-          }
-          double v = (i == j) ? 1.0 : 0.0;
-          for (int k = j; k < i; ++k) v -= A[i * KB + k] * Z[k * KB + j];
-          Z[i * KB + j] = v / A[i * KB + i];
-        }
+      // L^-1 in place, columns right to left: with x = L[j+1:, j], column j of the inverse
+      // is 1/L_jj on the diagonal and -(1/L_jj) Linv[j+1:, j+1:] x below it
+      for (int j = KB - 1; j >= 0; --j) {
+        for (int i = j + 1 + threadIdx.x; i < KB; i += blockDim.x) sh.v[i] = A[i * lda + j];
+        __syncthreads();
+        const double djj = 1.0 / A[j * lda + j];
+        for (int i = j + 1 + threadIdx.x; i < KB; i += blockDim.x)
+          A[i * lda + j] = -djj * lds_dot(A + i * lda + j + 1, sh.v + j + 1, i - j);
+        __syncthreads();
+        if (threadIdx.x == 0) A[j * lda + j] = djj;
+      }
       __syncthreads();
+      // C = D^-1 L^-T
       for (int f = threadIdx.x; f < KB * KB; f += blockDim.x) {
         const int i = f / KB, j = f - i * KB;
-        C[f] = s_dinv[i] * Z[j * KB + i];
+        C[f] = (j >= i) ? s_dinv[i] * A[j * lda + i] : 0.0;
       }
       return;
     }
     __syncthreads();
     for (int f = threadIdx.x; f < KB * KB; f += blockDim.x) {
       const int i = f / KB, j = f - i * KB;
-      A[f] = 0.5 * (S[f] + S[j * KB + i]) * s_dinv[i] * s_dinv[j];
+      A[i * lda + j] = 0.5 * (S[f] + S[j * KB + i]) * s_dinv[i] * s_dinv[j];
     }
     __syncthreads();
   }
-  wg_tridiagonalize(A, KB, KB, sh);
-  const bool ok = wg_band_qr(Z, KB, KB, sh);
+  lds_tridiagonalize(A, KB, lda, sh);
+  // the reflection vectors (rows j right of the diagonal) go to ws; the LDS matrix then
+  // becomes the reflection product Q (column-major), and the QR rotations are applied to
+  // Q itself, which leaves the eigenvectors of the full matrix in LDS
+  double* Hv = ws;
+  for (int f = threadIdx.x; f < KB * KB; f += blockDim.x) {
+    const int i = f / KB, j = f - i * KB;
+    Hv[f] = A[i * lda + j];
+  }
+  __syncthreads();
+  lds_form_q(Hv, KB, KB, A, lda, sh);
+  const bool ok = wg_band_qr(A, KB, lda, sh, true);
   wg_rank_ascending(sh.d, KB, s_perm);
-  wg_back_transform(A, KB, KB, Z, KB, s_perm, KB, sh);
   double lmax = 0.0, lmin = 1e300;
   bool finite = true;
   for (int a = 0; a < KB; ++a) {
@@ -1139,7 +1186,7 @@ __global__ __launch_bounds__(kEigThreads) void k_small_eig(const double* __restr
   const double floor_l = 1e-15 * lmax;
   for (int f = threadIdx.x; f < KB * KB; f += blockDim.x) {
     const int i = f / KB, j = f - i * KB;   // C[i][j] = component i of vector j
-    const double zij = Z[static_cast<size_t>(s_perm[j]) * KB + i];
+    const double zij = A[s_perm[j] * lda + i];
     if (bad) C[f] = (i == j) ? 1.0 : 0.0;
     else C[f] = (mode >= 1) ? s_dinv[i] * zij / sqrt(fmax(sh.d[s_perm[j]], floor_l)) : zij;
   }
@@ -1359,12 +1406,12 @@ aqt_status chfsi_gram(aqt_ctx* ctx, Chfsi& c, const double* P, const double* Q, 
 }
 
 aqt_status chfsi_combine(aqt_ctx* ctx, Chfsi& c, const double* in, double* out, int copy_masked) {
-  const dim3 grid(static_cast<unsigned>(nblk(c.N)), static_cast<unsigned>(c.nb));
+  const dim3 grid(static_cast<unsigned>((c.N + kCombineCols - 1) / kCombineCols), static_cast<unsigned>(c.nb));
   if (c.KB == 64)
-    hipLaunchKernelGGL(k_combine<64>, grid, dim3(256), 0, ctx->stream, in, c.C.as<double>(), out, c.N,
+    hipLaunchKernelGGL(k_combine<64>, grid, dim3(512), 0, ctx->stream, in, c.C.as<double>(), out, c.N,
                        c.act.as<int>(), copy_masked);
   else
-    hipLaunchKernelGGL(k_combine<128>, grid, dim3(256), 0, ctx->stream, in, c.C.as<double>(), out, c.N,
+    hipLaunchKernelGGL(k_combine<128>, grid, dim3(512), 0, ctx->stream, in, c.C.as<double>(), out, c.N,
                        c.act.as<int>(), copy_masked);
   AQT_HIP(ctx, hipGetLastError());
   return AQT_OK;
