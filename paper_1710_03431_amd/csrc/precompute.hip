@@ -971,31 +971,72 @@ struct HxCoef {
 };
 
 // Y_j = alpha (H X_j) + beta X_j + gamma Z_j for the KB rows j of every active
-// slot (blockIdx.z; a slot is KB*N doubles of each buffer; Z may be null).
+// slot (a slot is KB*N doubles of each buffer; Z may be null).  One workgroup per
+// (row, chunk of CH entries); the chunk is staged in LDS for the flips of its low
+// bits, flips of higher bits read the row's other chunks.  Workgroups are handed to
+// the 8 XCDs round-robin by index, so the index is decoded such that all chunks of
+// a row land on one XCD, one after another, and those reads hit that XCD's L2.
 __global__ __launch_bounds__(256) void k_hx_block(const double* __restrict__ X, const double* __restrict__ Zin,
                                                   double* __restrict__ Y, const double* __restrict__ eZ, int nq,
                                                   int KB, const HxCoef* __restrict__ coef) {
-  const HxCoef cf = coef[blockIdx.z];
-  if (!cf.active) return;
-  __shared__ double sx[kHxChunk];
   const int N = 1 << nq;
   const int CH = N < kHxChunk ? N : kHxChunk;
+  const int nchunk = N / CH;
+  const int id = blockIdx.x;
+  const int local = id >> 3;                              // rows (KB * slots) are a multiple of 8
+  const int r = (local / nchunk) * 8 + (id & 7);          // row over all slots
+  const int slot = r / KB;
+  const HxCoef cf = coef[slot];
+  if (!cf.active) return;
+  __shared__ double sx[kHxChunk];
   const int lch = 31 - __clz(CH);
-  const size_t row = (static_cast<size_t>(blockIdx.z) * KB + blockIdx.y) * N;
-  const int x0 = blockIdx.x * CH;
+  const size_t row = static_cast<size_t>(r) * N;
+  const int x0 = (local % nchunk) * CH;
   const double* v = X + row;
   for (int t = threadIdx.x; t < CH; t += blockDim.x) sx[t] = v[x0 + t];
   __syncthreads();
   const int nlow = nq < lch ? nq : lch;
-  for (int t = threadIdx.x; t < CH; t += blockDim.x) {
-    const int x = x0 + t;
-    double flip = 0.0;
-    for (int i = 0; i < nlow; ++i) flip += sx[t ^ (1 << i)];
-    for (int i = lch; i < nq; ++i) flip += v[x ^ (1 << i)];
-    const double own = sx[t];
-    double out = cf.alpha * (cf.B * eZ[x] * own - cf.A * flip) + cf.beta * own;
-    if (Zin) out += cf.gamma * Zin[row + x];
-    Y[row + x] = out;
+  const int nfar = nq - nlow;   // flips of bits beyond the chunk
+  // four entries per thread and pass, their global loads (e_Z, Z, far flips) issued
+  // together, the far flips four bits per batch
+  for (int t0 = threadIdx.x; t0 < CH; t0 += 4 * 256) {
+    double own[4], fl[4], ez[4], zz[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int t = t0 + 256 * u;
+      own[u] = fl[u] = ez[u] = zz[u] = 0.0;
+      if (t < CH) {
+        const int x = x0 + t;
+        ez[u] = eZ[x];
+        if (Zin) zz[u] = Zin[row + x];
+        own[u] = sx[t];
+        double f = 0.0;
+#pragma unroll 4
+        for (int i = 0; i < nlow; ++i) f += sx[t ^ (1 << i)];
+        fl[u] = f;
+      }
+    }
+    for (int k0 = 0; k0 < nfar; k0 += 4) {
+      double a[4][4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int kk = 0; kk < 4; ++kk) {
+          const int t = t0 + 256 * u, k = k0 + kk;
+          a[u][kk] = (t < CH && k < nfar) ? v[(x0 + t) ^ (1 << (lch + k))] : 0.0;
+        }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) fl[u] += (a[u][0] + a[u][1]) + (a[u][2] + a[u][3]);
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int t = t0 + 256 * u;
+      if (t < CH) {
+        double out = cf.alpha * (cf.B * ez[u] * own[u] - cf.A * fl[u]) + cf.beta * own[u];
+        if (Zin) out += cf.gamma * zz[u];
+        Y[row + x0 + t] = out;
+      }
+    }
   }
 }
 
@@ -1420,8 +1461,10 @@ aqt_status chfsi_combine(aqt_ctx* ctx, Chfsi& c, const double* in, double* out, 
 aqt_status chfsi_hx(aqt_ctx* ctx, Chfsi& c, const double* eZ, const HxCoef* coef, const double* in, const double* z,
                     double* out) {
   const int CH = std::min(c.N, kHxChunk);
-  hipLaunchKernelGGL(k_hx_block, dim3(c.N / CH, c.KB, c.nb), dim3(256), 0, ctx->stream, in, z, out, eZ, c.nq, c.KB,
-                     coef);
+  // one workgroup per (row, chunk); the decode in the kernel needs KB * nb % 8 == 0
+  const int64_t wgs = static_cast<int64_t>(c.N / CH) * c.KB * c.nb;
+  hipLaunchKernelGGL(k_hx_block, dim3(static_cast<unsigned>(wgs)), dim3(256), 0, ctx->stream, in, z, out, eZ, c.nq,
+                     c.KB, coef);
   AQT_HIP(ctx, hipGetLastError());
   return AQT_OK;
 }
