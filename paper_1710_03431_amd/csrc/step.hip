@@ -602,22 +602,61 @@ __device__ void finish_crossing(const StepArgs& a, int g, int t, int64_t jloc, T
     // which selects the same (i, a) as one pass over the whole list.
     int qi = 0, ta = b;
     {
-      H rs = H(0), rlo = H(0), rdg = H(0);
-      if (lane < a.nq) {
-        const double* c4 = Rc + (static_cast<size_t>(lane) * NP + b) * 4;
-        rs = static_cast<H>(c4[0]);
-        rlo = static_cast<H>(c4[1]);
-        rdg = static_cast<H>(c4[2]);
+      H thr, before, lo_q, dg_q;
+      if (a.nq <= SEG) {
+        // one channel per lane
+        H rs = H(0), rlo = H(0), rdg = H(0);
+        if (lane < a.nq) {
+          const double* c4 = Rc + (static_cast<size_t>(lane) * NP + b) * 4;
+          rs = static_cast<H>(c4[0]);
+          rlo = static_cast<H>(c4[1]);
+          rdg = static_cast<H>(c4[2]);
+        }
+        const H cum_i = seg_scan<SEG>(rs);
+        const H tot = seg_read<SEG>(cum_i, SEG - 1, base);
+        thr = u2 * tot;
+        const uint64_t hit_i = seg_ballot<SEG>(cum_i > thr && lane < a.nq, base);
+        const uint64_t pos_i = seg_ballot<SEG>(rs > H(0), base);
+        qi = hit_i ? first_set_lane(hit_i) : last_set_lane(pos_i);
+        if (qi < 0) qi = 0;
+        before = (qi > 0) ? seg_read<SEG>(cum_i, qi - 1, base) : H(0);
+        lo_q = seg_read<SEG>(rlo, qi, base);
+        dg_q = seg_read<SEG>(rdg, qi, base);
+      } else {
+        // more channels than lanes: channel lane + SEG j sits in chunk j
+        constexpr int CQ = kWave / SEG;
+        H rs[CQ], rlo[CQ], rdg[CQ];
+#pragma unroll
+        for (int j = 0; j < CQ; ++j) {
+          const int ch = lane + SEG * j;
+          rs[j] = rlo[j] = rdg[j] = H(0);
+          if (ch < a.nq) {
+            const double* c4 = Rc + (static_cast<size_t>(ch) * NP + b) * 4;
+            rs[j] = static_cast<H>(c4[0]);
+            rlo[j] = static_cast<H>(c4[1]);
+            rdg[j] = static_cast<H>(c4[2]);
+          }
+        }
+        H tot = H(0);
+#pragma unroll
+        for (int j = 0; j < CQ; ++j) tot += seg_sum<SEG>(rs[j]);
+        thr = u2 * tot;
+        int lastq = -1;
+        qi = seg_pick<SEG, CQ, H>(rs, thr, H(0), base, &lastq);
+        if (qi < 0) qi = lastq;
+        if (qi < 0) qi = 0;
+        const int jq = qi / SEG, lq = qi % SEG;
+        before = lo_q = dg_q = H(0);
+#pragma unroll
+        for (int j = 0; j < CQ; ++j) {
+          before += seg_sum<SEG>((lane + SEG * j < qi) ? rs[j] : H(0));
+          const H l = seg_read<SEG>(rlo[j], lq, base), d = seg_read<SEG>(rdg[j], lq, base);
+          if (j == jq) {
+            lo_q = l;
+            dg_q = d;
+          }
+        }
       }
-      const H cum_i = seg_scan<SEG>(rs);
-      const H tot = seg_read<SEG>(cum_i, SEG - 1, base);
-      const H thr = u2 * tot;
-      const uint64_t hit_i = seg_ballot<SEG>(cum_i > thr && lane < a.nq, base);
-      const uint64_t pos_i = seg_ballot<SEG>(rs > H(0), base);
-      qi = hit_i ? first_set_lane(hit_i) : last_set_lane(pos_i);
-      if (qi < 0) qi = 0;
-      const H before = (qi > 0) ? seg_read<SEG>(cum_i, qi - 1, base) : H(0);
-      const H lo_q = seg_read<SEG>(rlo, qi, base), dg_q = seg_read<SEG>(rdg, qi, base);
       const H rel = thr - before;
       if (!(rel >= lo_q && rel < lo_q + dg_q)) {
         const double* row = a.R + ((static_cast<size_t>(g) * a.nq + qi) * NP + b) * NP;

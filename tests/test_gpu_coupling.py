@@ -72,6 +72,47 @@ def test_coupling_average_matches_ame(mixed_case):
     assert np.max(np.abs(m - P0)[1:] / sig[1:]) > 8
 
 
+@pytest.fixture(scope="module")
+def wide_case():
+    """Twenty channels on a 5-qubit ring kept at all 32 levels: a crossing is handled
+    by 16 lanes, so the channel draw spans two chunks of lanes."""
+    nq, nch = 5, 20
+    rng = np.random.default_rng(5)
+    cz, cx = np.zeros((nch, nq)), np.zeros((nch, nq))
+    for k in range(nq):
+        cz[k, k] = 1.0
+        cx[nq + k, k] = 1.0
+    cz[2 * nq:] = rng.uniform(-0.5, 0.5, (nch - 2 * nq, nq))
+    cx[2 * nq:] = rng.uniform(-0.5, 0.5, (nch - 2 * nq, nq))
+    inst = W.ring_instance(nq, 8, t_f=1.5, eta=0.1, n_grid=101, coupling=(cz, cx, np.full(nch, 8.0 * math.pi)))
+    return inst, spectrum.all_tables(inst)
+
+
+def test_more_channels_than_handler_lanes_per_trajectory(wide_case):
+    """FP64 jump records against the oracle trajectory by trajectory; channels beyond
+    the first 16 are among those drawn."""
+    inst, tabs = wide_case
+    K = 400
+    ref = trajectories.run(tabs, inst, K)
+    eng = _engine(inst)
+    assert eng.channel_count() == 20
+    res = eng.run(K, "fp64", seed=inst.seed, instance_id=inst.instance_id, record_capacity=64)
+    frac, worst = compare_jump_records(res["jumps"], res["jump_count"], ref.jumps, inst.t_f)
+    assert frac >= 0.99, (frac, worst)
+    drawn = {int(res["jumps"][j, m]["qubit"]) for j in range(K) for m in range(min(int(res["jump_count"][j]), 64))}
+    assert max(drawn) >= 16 and len(drawn) == 20, sorted(drawn)
+
+
+def test_more_channels_than_handler_lanes_average(wide_case):
+    """10^5 FP32 trajectories of the same instance within 3 sigma + 1e-4 of the split-step AME."""
+    inst, tabs = wide_case
+    P = ame.split_step(tabs, inst)
+    K = 100_000
+    res = _engine(inst).run(K, "fp32", seed=inst.seed + 3, instance_id=inst.instance_id)
+    m, se = trajectories.mean_and_stderr(res["pgs_sum"], res["pgs_sumsq"], K)
+    assert np.all(np.abs(m - P) <= 3 * sigma_bound(P, se, K) + 1e-4)
+
+
 def test_sx_coupling_of_a_fixed_sx_hamiltonian_only_dephases():
     """H = -A sx fixed and coupling sx: the coupling commutes with H, every jump is an
     omega = 0 jump and the ground-state population stays 1."""
