@@ -623,19 +623,14 @@ __device__ void finish_crossing(const StepArgs& a, int g, int t, int64_t jloc, T
         lo_q = seg_read<SEG>(rlo, qi, base);
         dg_q = seg_read<SEG>(rdg, qi, base);
       } else {
-        // more channels than lanes: channel lane + SEG j sits in chunk j
+        // more channels than lanes: channel lane + SEG j sits in chunk j; the chosen
+        // channel's diagonal bounds are read once it is known
         constexpr int CQ = kWave / SEG;
-        H rs[CQ], rlo[CQ], rdg[CQ];
+        H rs[CQ];
 #pragma unroll
         for (int j = 0; j < CQ; ++j) {
           const int ch = lane + SEG * j;
-          rs[j] = rlo[j] = rdg[j] = H(0);
-          if (ch < a.nq) {
-            const double* c4 = Rc + (static_cast<size_t>(ch) * NP + b) * 4;
-            rs[j] = static_cast<H>(c4[0]);
-            rlo[j] = static_cast<H>(c4[1]);
-            rdg[j] = static_cast<H>(c4[2]);
-          }
+          rs[j] = (ch < a.nq) ? static_cast<H>(Rc[(static_cast<size_t>(ch) * NP + b) * 4]) : H(0);
         }
         H tot = H(0);
 #pragma unroll
@@ -645,17 +640,12 @@ __device__ void finish_crossing(const StepArgs& a, int g, int t, int64_t jloc, T
         qi = seg_pick<SEG, CQ, H>(rs, thr, H(0), base, &lastq);
         if (qi < 0) qi = lastq;
         if (qi < 0) qi = 0;
-        const int jq = qi / SEG, lq = qi % SEG;
-        before = lo_q = dg_q = H(0);
+        const double* c4 = Rc + (static_cast<size_t>(qi) * NP + b) * 4;
+        lo_q = static_cast<H>(c4[1]);
+        dg_q = static_cast<H>(c4[2]);
+        before = H(0);
 #pragma unroll
-        for (int j = 0; j < CQ; ++j) {
-          before += seg_sum<SEG>((lane + SEG * j < qi) ? rs[j] : H(0));
-          const H l = seg_read<SEG>(rlo[j], lq, base), d = seg_read<SEG>(rdg[j], lq, base);
-          if (j == jq) {
-            lo_q = l;
-            dg_q = d;
-          }
-        }
+        for (int j = 0; j < CQ; ++j) before += seg_sum<SEG>((lane + SEG * j < qi) ? rs[j] : H(0));
       }
       const H rel = thr - before;
       if (!(rel >= lo_q && rel < lo_q + dg_q)) {
@@ -1176,8 +1166,18 @@ __device__ void run_tile(const StepArgs& a, int64_t tile, TileShared<NP, TQ, typ
 #undef frag_index
 }
 
+// Wavefronts per SIMD the register allocation must leave room for: the small-level
+// FP32/BF16 kernels are latency-bound (jump handling), and three or four resident
+// wavefronts per SIMD hide more of it than the registers the compiler would
+// otherwise keep; the large-level and FP64 kernels keep the compiler's choice.
+template <int NP, class Mode>
+constexpr int min_waves_per_simd() {
+  return (sizeof(typename Mode::T) == 8 || NP > 64) ? 1 : (NP <= 16 ? 4 : 3);
+}
+
 template <int NP, int TQ, class Mode>
-__global__ __launch_bounds__((waves_for<NP, Mode>() * 64)) void k_trajectories(StepArgs a) {
+__global__ __launch_bounds__((waves_for<NP, Mode>() * 64))
+__attribute__((amdgpu_waves_per_eu(min_waves_per_simd<NP, Mode>()))) void k_trajectories(StepArgs a) {
   constexpr int WV = waves_for<NP, Mode>();
   __shared__ TileShared<NP, TQ, typename Mode::T, WV> sh;
   run_tile<NP, TQ, Mode, WV>(a, blockIdx.x, sh);
