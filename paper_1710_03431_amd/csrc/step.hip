@@ -211,7 +211,6 @@ template <int NP, class Mode>
 constexpr int waves_for() {
   return (NP >= 128 && Mode::KC == 4) ? 8 : 4;
 }
-constexpr int kBatchWaves = 8;
 template <int NP, class T>
 using TileCols = T[16][NP + kPad];
 
@@ -303,7 +302,7 @@ __host__ __device__ constexpr int seg_width() {
 template <int SEG>
 __device__ __forceinline__ uint64_t seg_ballot(bool pred, int base) {
   const uint64_t m = __ballot(pred);
-  return (SEG == 64) ? m : (m >> base) & ((1ull << SEG) - 1ull);
+  return (SEG == 64) ? m : (m >> base) & ((1ull << (SEG & 63)) - 1ull);
 }
 // Value of segment lane `idx` (segment-uniform) in every lane of the segment.
 template <int SEG>
@@ -1210,82 +1209,53 @@ __host__ __device__ constexpr bool tq_allowed(int NP, int TQ, bool f64) {
 }
 
 // ------------------------------------------------------------- batched ----
-// Many instances in one persistent launch: workgroups pull (instance, tile)
-// items from an atomic queue (items sorted longest first) and run each with
-// the same per-tile body; the LDS tile state is one raw buffer sized for the
-// largest (levels, tile) combination of the launch.
+// Many instances in few persistent launches.  Items (instance, tile) are grouped by
+// padded level count and tile width; one launch per group (largest levels first)
+// has its workgroups pull the group's items from an atomic queue (longest first)
+// and run each with the trajectory kernel's tile body, wavefront count and
+// occupancy floor.
 struct BatchItem {
   int inst;
   int tile;
 };
 
-__global__ void k_batch_reset(int* counter) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) *counter = 0;
+constexpr int kLevelClasses[] = {256, 128, 64, 32, 16};   // launch order
+constexpr int kTileClasses[] = {1, 2, 4, 8};              // column tiles
+constexpr int kNumClasses = 20;                           // (levels, tile) groups
+
+__global__ void k_batch_reset(int* counter, int n) {
+  if (blockIdx.x == 0 && static_cast<int>(threadIdx.x) < n) counter[threadIdx.x] = 0;
+}
+
+// BF16 runs of 16-level instances use the K = 16 MFMA, as in the single-instance launch
+template <int NP, class Mode>
+using BatchMode = typename std::conditional<NP == 16 && Mode::KC == 32, ModeBF16K16, Mode>::type;
+
+// column tiles a batch may use: 1, 2, 4, 8 up to 64 levels, 1, 2 above
+__host__ __device__ constexpr bool batch_tq(int NP, int TQ, bool f64) {
+  return tq_allowed(NP, TQ, f64) && ((NP <= 64) ? (TQ == 1 || TQ == 2 || TQ == 4 || TQ == 8) : (TQ == 1 || TQ == 2));
 }
 
 template <int NP, int TQ, class Mode>
-__device__ constexpr size_t tile_lds() {
-  return sizeof(TileShared<NP, TQ, typename Mode::T, kBatchWaves>);
-}
-
-template <int MaxNP, class Mode>
-__device__ constexpr size_t batch_lds() {
-  size_t m = 0;
-  constexpr bool f64 = sizeof(typename Mode::T) == 8;
-  if constexpr (tq_allowed(16, 8, f64)) m = m > tile_lds<16, 8, Mode>() ? m : tile_lds<16, 8, Mode>();
-  if constexpr (tq_allowed(32, 8, f64)) m = m > tile_lds<32, 8, Mode>() ? m : tile_lds<32, 8, Mode>();
-  if constexpr (MaxNP >= 64) {
-    if constexpr (tq_allowed(64, 8, f64)) m = m > tile_lds<64, 8, Mode>() ? m : tile_lds<64, 8, Mode>();
-    m = m > tile_lds<64, 4, Mode>() ? m : tile_lds<64, 4, Mode>();
-  }
-  if constexpr (MaxNP >= 128) m = m > tile_lds<128, 2, Mode>() ? m : tile_lds<128, 2, Mode>();
-  if constexpr (MaxNP >= 256) m = m > tile_lds<256, 2, Mode>() ? m : tile_lds<256, 2, Mode>();
-  return m;
-}
-
-template <int NP, int TQ, class Mode, class BufT>
-__device__ __forceinline__ bool try_tile(const StepArgs& a, int tile, BufT* raw) {
-  constexpr bool f64 = sizeof(typename Mode::T) == 8;
-  if constexpr (tq_allowed(NP, TQ, f64) && (NP != 16 || Mode::KC != 32)) {
-    if (a.NP == NP && a.TQ == TQ) {
-      run_tile<NP, TQ, Mode, kBatchWaves>(a, tile, *reinterpret_cast<TileShared<NP, TQ, typename Mode::T, kBatchWaves>*>(raw));
-      return true;
-    }
-  }
-  return false;
-}
-
-template <int MaxNP, class Mode>
-__global__ __launch_bounds__(kBatchWaves * 64) void k_batch(const StepArgs* __restrict__ args, const BatchItem* __restrict__ items,
-                                              int n_items, int* counter) {
-  __shared__ __align__(16) unsigned char raw[batch_lds<MaxNP, Mode>()];
+__global__ __launch_bounds__((waves_for<NP, BatchMode<NP, Mode>>() * 64))
+__attribute__((amdgpu_waves_per_eu(min_waves_per_simd<NP, BatchMode<NP, Mode>>()))) void k_batch(
+    const StepArgs* __restrict__ args, const BatchItem* __restrict__ items, int n_items, int* counter) {
+  using M = BatchMode<NP, Mode>;
+  constexpr int WV = waves_for<NP, M>();
+  __shared__ TileShared<NP, TQ, typename M::T, WV> sh;
   __shared__ int s_item;
-  // BF16 runs of 16-level instances use the K = 16 MFMA
-  using M16 = typename std::conditional<Mode::KC == 32, ModeBF16K16, Mode>::type;
   for (;;) {
     if (threadIdx.x == 0) s_item = atomicAdd(counter, 1);
     __syncthreads();
     const int it = __builtin_amdgcn_readfirstlane(s_item);
     __syncthreads();
     if (it >= n_items) break;
-    const BatchItem item{__builtin_amdgcn_readfirstlane(items[it].inst), __builtin_amdgcn_readfirstlane(items[it].tile)};
-    const StepArgs& a = args[item.inst];
-    bool done = try_tile<16, 1, M16>(a, item.tile, raw) || try_tile<16, 2, M16>(a, item.tile, raw) ||
-                try_tile<16, 4, M16>(a, item.tile, raw) || try_tile<16, 8, M16>(a, item.tile, raw) ||
-                try_tile<32, 1, Mode>(a, item.tile, raw) || try_tile<32, 2, Mode>(a, item.tile, raw) ||
-                try_tile<32, 4, Mode>(a, item.tile, raw) || try_tile<32, 8, Mode>(a, item.tile, raw);
-    if constexpr (MaxNP >= 64)
-      done = done || try_tile<64, 1, Mode>(a, item.tile, raw) || try_tile<64, 2, Mode>(a, item.tile, raw) ||
-             try_tile<64, 4, Mode>(a, item.tile, raw) || try_tile<64, 8, Mode>(a, item.tile, raw);
-    if constexpr (MaxNP >= 128)
-      done = done || try_tile<128, 1, Mode>(a, item.tile, raw) || try_tile<128, 2, Mode>(a, item.tile, raw);
-    if constexpr (MaxNP >= 256)
-      done = done || try_tile<256, 1, Mode>(a, item.tile, raw) || try_tile<256, 2, Mode>(a, item.tile, raw);
-    (void)done;
+    const int inst = __builtin_amdgcn_readfirstlane(items[it].inst);
+    const int tile = __builtin_amdgcn_readfirstlane(items[it].tile);
+    run_tile<NP, TQ, M, WV>(args[inst], tile, sh);
   }
 }
 
-// Fixed-order reduction of every instance's per-tile sums (blockIdx.y = instance).
 __global__ void k_reduce_batch(const StepArgs* __restrict__ args) {
   const StepArgs& a = args[blockIdx.y];
   const int g = blockIdx.x * blockDim.x + threadIdx.x;
@@ -1529,14 +1499,20 @@ struct aqt_batch {
   hipStream_t stream = nullptr;           // launch stream (the first context's)
   std::string err;
   int precision = AQT_FP32;
-  int max_np = 16;
   int n = 0;
   std::vector<aqt_ctx*> ctxs;
   std::vector<aqt::StepArgs> hargs;
   std::vector<int> tiles_per_inst;        // trajectories per workgroup tile chosen per instance
   aqt::DevBuf dargs, ditems, dcounter;
   int n_items = 0;
-  int grid = 0;
+  int class_off[20] = {};                 // items of each (levels, tile) group
+  int class_cnt[20] = {};
+  int class_grid[20] = {};                // persistent workgroups per group launch
+  // groups after the first run on side streams forked from and joined back into the
+  // launch stream, so that one group's tail overlaps the next group's work
+  hipStream_t side[3] = {nullptr, nullptr, nullptr};
+  hipEvent_t fork = nullptr;
+  hipEvent_t join[3] = {nullptr, nullptr, nullptr};
   bool use_graph = false;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
@@ -1549,54 +1525,150 @@ struct aqt_batch {
 namespace aqt {
 namespace {
 
-template <int MaxNP, class Mode>
-hipError_t enqueue_batch_kernel(const aqt_batch* b, const StepArgs* dargs, const BatchItem* items, int n_items,
-                                int* counter, int grid, hipStream_t st) {
-  hipLaunchKernelGGL(k_batch_reset, dim3(1), dim3(64), 0, st, counter);
-  hipLaunchKernelGGL((k_batch<MaxNP, Mode>), dim3(grid), dim3(kBatchWaves * 64), 0, st, dargs, items, n_items, counter);
-  return hipGetLastError();
+// Items of a launch per (levels, tile) group: [off, off + cnt) of the item array.
+struct ClassSpans {
+  int off[kNumClasses] = {};
+  int cnt[kNumClasses] = {};
+};
+
+int batch_class(int NP, int TQ) {
+  int l = -1, t = -1;
+  for (int c = 0; c < 5; ++c)
+    if (kLevelClasses[c] == NP) l = c;
+  for (int c = 0; c < 4; ++c)
+    if (kTileClasses[c] == TQ) t = c;
+  return (l < 0 || t < 0) ? -1 : 4 * l + t;
 }
 
-hipError_t enqueue_batch(const aqt_batch* b, const StepArgs* dargs, const BatchItem* items, int n_items,
+// Calls f.template operator()<NP, TQ>() for the (levels, tile) group c, if the batch allows it.
+template <class Mode, class F>
+hipError_t with_class(int c, const F& f) {
+  constexpr bool f64 = sizeof(typename Mode::T) == 8;
+  hipError_t e = hipErrorInvalidValue;
+  auto tq = [&](auto np_tag) {
+    constexpr int NP = decltype(np_tag)::value;
+    switch (kTileClasses[c % 4]) {
+      case 1: if constexpr (batch_tq(NP, 1, f64)) e = f.template operator()<NP, 1>(); break;
+      case 2: if constexpr (batch_tq(NP, 2, f64)) e = f.template operator()<NP, 2>(); break;
+      case 4: if constexpr (batch_tq(NP, 4, f64)) e = f.template operator()<NP, 4>(); break;
+      default: if constexpr (batch_tq(NP, 8, f64)) e = f.template operator()<NP, 8>(); break;
+    }
+  };
+  switch (kLevelClasses[c / 4]) {
+    case 256: tq(std::integral_constant<int, 256>{}); break;
+    case 128: tq(std::integral_constant<int, 128>{}); break;
+    case 64: tq(std::integral_constant<int, 64>{}); break;
+    case 32: tq(std::integral_constant<int, 32>{}); break;
+    default: tq(std::integral_constant<int, 16>{}); break;
+  }
+  return e;
+}
+
+template <class Mode>
+struct LaunchGroup {
+  const StepArgs* dargs;
+  const BatchItem* items;
+  int n;
+  int* counter;
+  int grid;
+  hipStream_t st;
+  template <int NP, int TQ>
+  hipError_t operator()() const {
+    hipLaunchKernelGGL((k_batch<NP, TQ, Mode>), dim3(grid), dim3(waves_for<NP, BatchMode<NP, Mode>>() * 64), 0, st,
+                       dargs, items, n, counter);
+    return hipGetLastError();
+  }
+};
+
+template <class Mode>
+struct GroupOccupancy {
+  int* blocks;
+  template <int NP, int TQ>
+  hipError_t operator()() const {
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, k_batch<NP, TQ, Mode>,
+                                                        waves_for<NP, BatchMode<NP, Mode>>() * 64, 0);
+  }
+};
+
+// One reset of the group counters, then one persistent launch per non-empty group:
+// the first on st, the others on the side streams (forked after the reset, joined
+// back into st), so the groups run concurrently.
+template <class Mode>
+hipError_t enqueue_mode(const aqt_batch* b, const StepArgs* dargs, const BatchItem* items, const ClassSpans& sp,
+                        int* counter, hipStream_t st) {
+  hipLaunchKernelGGL(k_batch_reset, dim3(1), dim3(64), 0, st, counter, kNumClasses);
+  hipError_t e = hipGetLastError();
+  bool forked = false, used[3] = {false, false, false};
+  int k = 0;   // non-empty groups so far
+  for (int c = 0; c < kNumClasses && e == hipSuccess; ++c) {
+    if (!sp.cnt[c]) continue;
+    hipStream_t s = st;
+    if (k > 0 && b->side[0]) {
+      if (!forked) {
+        e = hipEventRecord(b->fork, st);
+        forked = true;
+      }
+      const int j = (k - 1) % 3;
+      if (e == hipSuccess && !used[j]) {
+        e = hipStreamWaitEvent(b->side[j], b->fork, 0);
+        used[j] = true;
+      }
+      s = b->side[j];
+    }
+    ++k;
+    if (e != hipSuccess) break;
+    e = with_class<Mode>(c, LaunchGroup<Mode>{dargs, items + sp.off[c], sp.cnt[c], counter + c, b->class_grid[c], s});
+  }
+  for (int j = 0; j < 3 && e == hipSuccess; ++j)
+    if (used[j]) {
+      e = hipEventRecord(b->join[j], b->side[j]);
+      if (e == hipSuccess) e = hipStreamWaitEvent(st, b->join[j], 0);
+    }
+  return e;
+}
+
+hipError_t enqueue_batch(const aqt_batch* b, const StepArgs* dargs, const BatchItem* items, const ClassSpans& sp,
                          int* counter, hipStream_t st) {
-  const bool big = b->max_np > 64;
-  if (b->precision == AQT_FP64)
-    return big ? enqueue_batch_kernel<256, ModeF64>(b, dargs, items, n_items, counter, b->grid, st)
-               : enqueue_batch_kernel<64, ModeF64>(b, dargs, items, n_items, counter, b->grid, st);
-  if (b->precision == AQT_FP32)
-    return big ? enqueue_batch_kernel<256, ModeF32>(b, dargs, items, n_items, counter, b->grid, st)
-               : enqueue_batch_kernel<64, ModeF32>(b, dargs, items, n_items, counter, b->grid, st);
-  return big ? enqueue_batch_kernel<256, ModeBF16>(b, dargs, items, n_items, counter, b->grid, st)
-             : enqueue_batch_kernel<64, ModeBF16>(b, dargs, items, n_items, counter, b->grid, st);
+  if (b->precision == AQT_FP64) return enqueue_mode<ModeF64>(b, dargs, items, sp, counter, st);
+  if (b->precision == AQT_FP32) return enqueue_mode<ModeF32>(b, dargs, items, sp, counter, st);
+  return enqueue_mode<ModeBF16>(b, dargs, items, sp, counter, st);
 }
 
-template <int MaxNP, class Mode>
-int batch_occupancy() {
+// Resident workgroups per CU of group c's kernel (0 if the group is not allowed).
+template <class Mode>
+int class_occupancy(int c) {
   int blocks = 0;
-  // occupancy of the block size the launch uses (kBatchWaves wavefronts)
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_batch<MaxNP, Mode>, kBatchWaves * 64, 0) != hipSuccess)
-    return 1;
-  return blocks > 0 ? blocks : 1;
+  const hipError_t e = with_class<Mode>(c, GroupOccupancy<Mode>{&blocks});
+  return e == hipSuccess ? (blocks > 0 ? blocks : 1) : 0;
+}
+
+int class_occupancy_for(int c, int precision) {
+  if (precision == AQT_FP64) return class_occupancy<ModeF64>(c);
+  if (precision == AQT_FP32) return class_occupancy<ModeF32>(c);
+  return class_occupancy<ModeBF16>(c);
 }
 
 bool batch_tq_ok(int NP, int tq, int precision) {
-  if (!tq_allowed(NP, tq, precision == AQT_FP64)) return false;
-  if (NP <= 64) return tq == 1 || tq == 2 || tq == 4 || tq == 8;
-  return tq == 1 || tq == 2;
+  return batch_class(NP, tq) >= 0 && batch_tq(NP, tq, precision == AQT_FP64);
 }
 
-// Items of all instances, longest first (work per item ~ TQ * (M-1) * NP^2).
-std::vector<BatchItem> build_items(const std::vector<StepArgs>& args) {
-  std::vector<std::pair<double, BatchItem>> v;
+// Items of all instances grouped by (levels, tile), largest levels first, longest first
+// within a group (work per item ~ TQ * (M-1) * NP^2).
+std::vector<BatchItem> build_items(const std::vector<StepArgs>& args, ClassSpans* sp) {
+  std::vector<std::pair<double, BatchItem>> v[kNumClasses];
   for (int i = 0; i < static_cast<int>(args.size()); ++i) {
     const StepArgs& a = args[i];
     const double w = static_cast<double>(a.TQ) * (a.M_run - 1) * (64.0 + static_cast<double>(a.NP) * a.NP);
-    for (int64_t t = 0; t < a.tiles; ++t) v.push_back({w, BatchItem{i, static_cast<int>(t)}});
+    const int c = batch_class(a.NP, a.TQ);
+    for (int64_t t = 0; t < a.tiles; ++t) v[c].push_back({w, BatchItem{i, static_cast<int>(t)}});
   }
-  std::stable_sort(v.begin(), v.end(), [](const auto& x, const auto& y) { return x.first > y.first; });
   std::vector<BatchItem> out;
-  out.reserve(v.size());
-  for (auto& p : v) out.push_back(p.second);
+  for (int c = 0; c < kNumClasses; ++c) {
+    std::stable_sort(v[c].begin(), v[c].end(), [](const auto& x, const auto& y) { return x.first > y.first; });
+    sp->off[c] = static_cast<int>(out.size());
+    sp->cnt[c] = static_cast<int>(v[c].size());
+    for (auto& p : v[c]) out.push_back(p.second);
+  }
   return out;
 }
 
@@ -1612,7 +1684,7 @@ aqt_status autotune(aqt_batch* b) {
     return b->fail(AQT_EHIP, "event creation failed");
   aqt_status st = AQT_OK;
   DevBuf dargs, ditems, dctr, scratch;
-  if (dctr.reserve(sizeof(int)) != hipSuccess) st = b->fail(AQT_ENOMEM, "tuning allocation failed");
+  if (dctr.reserve(kNumClasses * sizeof(int)) != hipSuccess) st = b->fail(AQT_ENOMEM, "tuning allocation failed");
   for (int np : nps) {
     if (st != AQT_OK) break;
     double best_t = 1e300;
@@ -1645,7 +1717,8 @@ aqt_status autotune(aqt_batch* b) {
         break;
       }
       for (auto& a : ta) a.partial = scratch.as<double>();   // shared scratch, contents discarded
-      std::vector<BatchItem> items = build_items(ta);
+      ClassSpans sp;
+      std::vector<BatchItem> items = build_items(ta, &sp);
       if (dargs.reserve(ta.size() * sizeof(StepArgs)) != hipSuccess ||
           ditems.reserve(items.size() * sizeof(BatchItem)) != hipSuccess) {
         st = b->fail(AQT_ENOMEM, "tuning allocation failed");
@@ -1656,8 +1729,8 @@ aqt_status autotune(aqt_batch* b) {
       double t_ms = 1e300;
       for (int rep = 0; rep < 2; ++rep) {
         (void)hipEventRecord(e0, b->stream);
-        if (enqueue_batch(b, dargs.as<StepArgs>(), ditems.as<BatchItem>(), static_cast<int>(items.size()),
-                          dctr.as<int>(), b->stream) != hipSuccess) {
+        if (enqueue_batch(b, dargs.as<StepArgs>(), ditems.as<BatchItem>(), sp, dctr.as<int>(), b->stream) !=
+            hipSuccess) {
           st = b->fail(AQT_EHIP, "tuning launch failed");
           break;
         }
@@ -1714,6 +1787,12 @@ aqt_status aqt_batch_create(aqt_batch** out, aqt_ctx* const* ctxs, int n, const 
   b->use_graph = (flags & 1) != 0;
   const bool tune = (flags & 2) != 0;
   if (hipSetDevice(b->device) != hipSuccess) return bail(b->fail(AQT_EHIP, "hipSetDevice failed"));
+  if (hipEventCreateWithFlags(&b->fork, hipEventDisableTiming) != hipSuccess)
+    return bail(b->fail(AQT_EHIP, "event creation failed"));
+  for (int j = 0; j < 3; ++j)
+    if (hipStreamCreateWithFlags(&b->side[j], hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&b->join[j], hipEventDisableTiming) != hipSuccess)
+      return bail(b->fail(AQT_EHIP, "stream creation failed"));
   for (int i = 0; i < n; ++i) {
     aqt_ctx* c = ctxs[i];
     if (!c) return bail(b->fail(AQT_EINVAL, "null context in batch"));
@@ -1726,7 +1805,7 @@ aqt_status aqt_batch_create(aqt_batch** out, aqt_ctx* const* ctxs, int n, const 
     if (outs[i].net_hist && outs[i].hist_hi < outs[i].hist_lo) return bail(b->fail(AQT_EINVAL, "hist_hi < hist_lo"));
     if (params[i].tile && (params[i].tile % 8 || !batch_tq_ok(c->NP, params[i].tile / 8, b->precision)))
       return bail(b->fail(AQT_EINVAL, "unsupported tile size in batch"));
-    b->max_np = std::max(b->max_np, c->NP);
+    if (batch_class(c->NP, 1) < 0) return bail(b->fail(AQT_EINVAL, "unsupported level count in batch"));
     aqt_status s = check_step_decay(c, b->precision);
     if (s == AQT_OK) s = pack_for_precision(c, b->precision);
     if (s != AQT_OK) return bail(b->fail(s, c->err));
@@ -1781,12 +1860,7 @@ aqt_status aqt_batch_create(aqt_batch** out, aqt_ctx* const* ctxs, int n, const 
     b->hargs[i] = a;
   }
   const int cus = ctxs[0]->cus > 0 ? ctxs[0]->cus : 256;
-  int occ = 1;
-  const bool big = b->max_np > 64;
-  if (b->precision == AQT_FP64) occ = big ? batch_occupancy<256, ModeF64>() : batch_occupancy<64, ModeF64>();
-  else if (b->precision == AQT_FP32) occ = big ? batch_occupancy<256, ModeF32>() : batch_occupancy<64, ModeF32>();
-  else occ = big ? batch_occupancy<256, ModeBF16>() : batch_occupancy<64, ModeBF16>();
-  b->grid = cus * occ;
+  for (int c = 0; c < kNumClasses; ++c) b->class_grid[c] = cus * class_occupancy_for(c, b->precision);
   if (tune) {
     aqt_status s = autotune(b);
     if (s != AQT_OK) return bail(s);
@@ -1807,10 +1881,16 @@ aqt_status aqt_batch_create(aqt_batch** out, aqt_ctx* const* ctxs, int n, const 
     if (c->partial.reserve(need) != hipSuccess) return bail(b->fail(AQT_ENOMEM, "workspace allocation failed"));
     a.partial = c->partial.as<double>();
   }
-  std::vector<BatchItem> items = build_items(b->hargs);
+  ClassSpans sp;
+  std::vector<BatchItem> items = build_items(b->hargs, &sp);
   b->n_items = static_cast<int>(items.size());
+  for (int c = 0; c < kNumClasses; ++c) {
+    b->class_off[c] = sp.off[c];
+    b->class_cnt[c] = sp.cnt[c];
+  }
   if (b->dargs.reserve(n * sizeof(StepArgs)) != hipSuccess ||
-      b->ditems.reserve(items.size() * sizeof(BatchItem)) != hipSuccess || b->dcounter.reserve(sizeof(int)) != hipSuccess)
+      b->ditems.reserve(items.size() * sizeof(BatchItem)) != hipSuccess ||
+      b->dcounter.reserve(kNumClasses * sizeof(int)) != hipSuccess)
     return bail(b->fail(AQT_ENOMEM, "batch allocation failed"));
   if (hipMemcpy(b->dargs.p, b->hargs.data(), n * sizeof(StepArgs), hipMemcpyHostToDevice) != hipSuccess ||
       hipMemcpy(b->ditems.p, items.data(), items.size() * sizeof(BatchItem), hipMemcpyHostToDevice) != hipSuccess)
@@ -1819,8 +1899,8 @@ aqt_status aqt_batch_create(aqt_batch** out, aqt_ctx* const* ctxs, int n, const 
     if (hipStreamCreate(&b->capture_stream) != hipSuccess) return bail(b->fail(AQT_EHIP, "stream creation failed"));
     if (hipStreamBeginCapture(b->capture_stream, hipStreamCaptureModeThreadLocal) != hipSuccess)
       return bail(b->fail(AQT_EHIP, "graph capture failed to start"));
-    hipError_t e = enqueue_batch(b, b->dargs.as<StepArgs>(), b->ditems.as<BatchItem>(), b->n_items,
-                                 b->dcounter.as<int>(), b->capture_stream);
+    hipError_t e = enqueue_batch(b, b->dargs.as<StepArgs>(), b->ditems.as<BatchItem>(), sp, b->dcounter.as<int>(),
+                                 b->capture_stream);
     int maxM = 0;
     for (auto& a : b->hargs) maxM = std::max(maxM, a.M);
     hipLaunchKernelGGL(k_reduce_batch, dim3((maxM + 255) / 256, n), dim3(256), 0, b->capture_stream,
@@ -1845,8 +1925,13 @@ aqt_status aqt_batch_launch(aqt_batch* b) {
     if (hipGraphLaunch(b->exec, b->stream) != hipSuccess) return b->fail(AQT_EHIP, "graph launch failed");
     return AQT_OK;
   }
-  if (enqueue_batch(b, b->dargs.as<StepArgs>(), b->ditems.as<BatchItem>(), b->n_items, b->dcounter.as<int>(),
-                    b->stream) != hipSuccess)
+  ClassSpans sp;
+  for (int c = 0; c < kNumClasses; ++c) {
+    sp.off[c] = b->class_off[c];
+    sp.cnt[c] = b->class_cnt[c];
+  }
+  if (enqueue_batch(b, b->dargs.as<StepArgs>(), b->ditems.as<BatchItem>(), sp, b->dcounter.as<int>(), b->stream) !=
+      hipSuccess)
     return b->fail(AQT_EHIP, "batch launch failed");
   int maxM = 0;
   for (auto& a : b->hargs) maxM = std::max(maxM, a.M);
@@ -1871,6 +1956,12 @@ void aqt_batch_destroy(aqt_batch* b) {
   if (b->exec) (void)hipGraphExecDestroy(b->exec);
   if (b->graph) (void)hipGraphDestroy(b->graph);
   if (b->capture_stream) (void)hipStreamDestroy(b->capture_stream);
+  for (int j = 0; j < 3; ++j) {
+    if (b->side[j]) (void)hipStreamSynchronize(b->side[j]);
+    if (b->side[j]) (void)hipStreamDestroy(b->side[j]);
+    if (b->join[j]) (void)hipEventDestroy(b->join[j]);
+  }
+  if (b->fork) (void)hipEventDestroy(b->fork);
   delete b;
 }
 
