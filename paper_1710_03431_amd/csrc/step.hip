@@ -203,6 +203,7 @@ constexpr int prefetch_depth() {
 // (part 1) part of local trajectory t = 8 q + (c & 7).  Columns are padded to
 // NP + kPad elements so the 16 columns of an MFMA operand fall in distinct banks.
 constexpr int kPad = 4;   // >= 4: the B read-ahead touches padding rows NP..NP+3
+constexpr int kStepTables = 5;
 // Wavefronts per workgroup.  Eight (two per SIMD) let one wave's LDS and load waits
 // hide behind the other's MFMAs where each wave still has a large share of the
 // GEMM (>= 128 levels, FP32/FP64 and the batched kernel); small tiles and the
@@ -433,10 +434,10 @@ __device__ constexpr H newton_tol() {
 // precision runs take the crossing time, the channel scans and the renormalisation
 // in FP32 (native exponentials, 32-bit shuffles).  The crossing test itself and
 // the observable sums stay in FP64 in every mode.
-template <int NP, class T>
+template <int NP, class T, bool STAGED>
 __device__ void finish_crossing(const StepArgs& a, int g, int t, int64_t jloc, TileCols<NP, T>* S,
                                 double* s_r, int* s_m, int* s_cnt, int* s_net, double* s_p,
-                                int* s_kind, RngCache rc) {
+                                int* s_kind, RngCache rc, const double* tg) {
   using H = T;
   constexpr int SEG = seg_width<NP>();
   constexpr int PL = NP / SEG;
@@ -444,8 +445,14 @@ __device__ void finish_crossing(const StepArgs& a, int g, int t, int64_t jloc, T
   const int base = (threadIdx.x & (kWave - 1)) & ~(SEG - 1);   // first lane of the segment
   const double dt = a.tlen[g];
   const uint64_t traj = a.traj0 + static_cast<uint64_t>(jloc);   // Philox counter word 0
-  const double* Gam = a.Gamma + static_cast<size_t>(g) * NP;
-  const double* Eh = a.ehalf + static_cast<size_t>(g) * NP;
+  // grid point g's Gamma, e^{G dt/2}, E and phase factors: staged in LDS (kStepTables rows
+  // of NP) or read from the tables
+  const size_t gofs = static_cast<size_t>(g) * NP;
+  const double* Gam = STAGED ? tg : a.Gamma + gofs;
+  const double* Eh = STAGED ? tg + NP : a.ehalf + gofs;
+  const double* Eg = STAGED ? tg + 2 * NP : a.E + gofs;
+  const double* Pre = STAGED ? tg + 3 * NP : a.d64re + gofs;
+  const double* Pim = STAGED ? tg + 4 * NP : a.d64im + gofs;
   H sr[PL], si[PL], G[PL], up[PL];
 #pragma unroll
   for (int j = 0; j < PL; ++j) {
@@ -663,8 +670,8 @@ __device__ void finish_crossing(const StepArgs& a, int g, int t, int64_t jloc, T
     int kind;
     if (ta != b) {
       // collapse to level ta, carrying the step phase e^{-i e_a dt}
-      const double pr = a.d64re[static_cast<size_t>(g) * NP + ta];
-      const double pim = a.d64im[static_cast<size_t>(g) * NP + ta];
+      const double pr = Pre[ta];
+      const double pim = Pim[ta];
       const double inv = 1.0 / sqrt(pr * pr + pim * pim);
 #pragma unroll
       for (int j = 0; j < PL; ++j) {
@@ -672,7 +679,6 @@ __device__ void finish_crossing(const StepArgs& a, int g, int t, int64_t jloc, T
         cr[j] = (x == ta) ? static_cast<H>(pr * inv) : H(0);
         ci[j] = (x == ta) ? static_cast<H>(pim * inv) : H(0);
       }
-      const double* Eg = a.E + static_cast<size_t>(g) * NP;
       kind = (Eg[ta] <= Eg[b]) ? AQT_KIND_RELAX : AQT_KIND_EXCITE;
       if (ta < gsz && b >= gsz) ++net;
       else if (b < gsz && ta >= gsz) --net;
@@ -764,7 +770,20 @@ struct TileShared {
   uint64_t rngb[TT];
   int rfl[TT];           // trajectories whose blocks are to be refreshed
   int nrfl;
+  double tg[kStepTables][NP];   // the step's Gamma, e^{G dt/2}, E, phase re/im (jump handler)
 };
+
+// Per-grid-point tables the jump handler reads, staged in LDS each step in the FP32
+// kernels: loaded from HBM/L2 ahead of the GEMM, stored after it, so a crossing finds
+// them at LDS latency.  (The BF16 and FP64 kernels run out of registers holding them
+// across the GEMM and read them from the tables.)
+template <class Mode>
+constexpr bool stage_tables() {
+  return Mode::KC == 4 && sizeof(typename Mode::T) == 4;
+}
+__device__ __forceinline__ const double* step_table(const StepArgs& a, int which) {
+  return which == 0 ? a.Gamma : which == 1 ? a.ehalf : which == 2 ? a.E : which == 3 ? a.d64re : a.d64im;
+}
 
 template <int NP, int TQ, class Mode, int WV>
 __device__ void run_tile(const StepArgs& a, int64_t tile, TileShared<NP, TQ, typename Mode::T, WV>& sh) {
@@ -911,6 +930,14 @@ __device__ void run_tile(const StepArgs& a, int64_t tile, TileShared<NP, TQ, typ
           dpim[u][i] = di[rt_u[u] * 16 + Mode::row(lane, i)];
         }
     }
+    constexpr bool STAGED = stage_tables<Mode>();
+    constexpr int NTG = kStepTables * NP, TGPT = STAGED ? (NTG + WV * 64 - 1) / (WV * 64) : 1;
+    double tgv[TGPT];
+#pragma unroll
+    for (int k = 0; k < TGPT; ++k) {
+      const int f = tid + k * WV * 64;
+      tgv[k] = (STAGED && f < NTG) ? step_table(a, f / NP)[static_cast<size_t>(g) * NP + f % NP] : 0.0;
+    }
     if (g > 1) {
       T bnx[QG];
       if constexpr (Mode::KC == 4 && kSharedQ) {
@@ -1025,6 +1052,14 @@ __device__ void run_tile(const StepArgs& a, int64_t tile, TileShared<NP, TQ, typ
       }
     }
     if (WV == 8 && sizeof(T) == 4) __builtin_amdgcn_s_setprio(0);
+    // the step tables for this step's handlers (the previous step's handlers are done)
+    if constexpr (STAGED) {
+#pragma unroll
+      for (int k = 0; k < TGPT; ++k) {
+        const int f = tid + k * WV * 64;
+        if (f < NTG) sh.tg[f / NP][f % NP] = tgv[k];
+      }
+    }
     __syncthreads();   // every wave has finished reading S
     // ---- 2. C' = d o C and the squared norms (partial sums per wave or row tile).
     // The squares of state-precision amplitudes are exact in FP64 and every sum of
@@ -1116,7 +1151,7 @@ __device__ void run_tile(const StepArgs& a, int64_t tile, TileShared<NP, TQ, typ
         const int e = e0 + seg;
         if (e < ncross) {
           const int t = s_list[e];
-          finish_crossing<NP, T>(a, g, t, tb + t, S, s_r, s_m, s_cnt, s_net, s_p, s_kind, rc);
+          finish_crossing<NP, T, STAGED>(a, g, t, tb + t, S, s_r, s_m, s_cnt, s_net, s_p, s_kind, rc, &sh.tg[0][0]);
         }
       }
     }
