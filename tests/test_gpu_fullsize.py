@@ -210,3 +210,33 @@ def test_workload_jump_statistics(a2a8, prec):
     assert agree >= 0.97, agree
     diff = np.abs(res["net_hist"] - _hist(traj["net_hist"], -64, 64)).sum()
     assert diff <= 2 * (1.0 - agree) * K + 2, diff
+
+
+def _golden_models():
+    import importlib.util
+    spec = importlib.util.spec_from_file_location("make_golden", os.path.join(GOLDEN, "make_golden.py"))
+    mg = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(mg)
+    return mg
+
+
+@pytest.mark.parametrize("model", ["bath_corr_0.5", "bath_terms_0.5", "zx_coupling"])
+def test_workload_model_switches_match_stored_ame(model):
+    """The 8-qubit workload under the benchmark's bath-model switches (baths correlated as
+    0.5^|a-b|, two bath terms per qubit at rho = 0.5, sz and sx couplings on every qubit;
+    the instances are built by the same function that wrote the references), GPU
+    precompute, 10^4 FP32 trajectories: the mean at the stored grid points (every tenth
+    and the last) against the oracle's split-step AME of the same model
+    (tests/golden/a2a8_models_ame_pgs.json), bound of gpu_common.assert_mean_matches."""
+    from paper_1710_03431_amd.binding import Engine
+    ref = json.load(open(os.path.join(GOLDEN, "a2a8_models_ame_pgs.json")))
+    inst = _golden_models().a2a8_model(model)
+    assert ref["n_grid"] == inst.n_grid
+    eng = Engine(0)
+    eng.set_instance(inst)
+    eng.precompute(inst.n_grid, inst.levels)
+    K = 10_000
+    res = eng.run(K, "fp32", seed=inst.seed + 29, instance_id=inst.instance_id)
+    m, se = trajectories.mean_and_stderr(res["pgs_sum"], res["pgs_sumsq"], K)
+    idx = np.array(ref["grid_points"])
+    assert_mean_matches(m[idx], se[idx], np.array(ref["models"][model]), K, model)
