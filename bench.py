@@ -524,7 +524,10 @@ def main():
                                                "abs_err": v["err_vs_ame"]} for p, v in results.items()}},
         # context: the scheme's own discretisation error, against the grid-converged AME
         "error_vs_converged_ame": converged_error(inst, results),
-        "paths": {p: {"value": v["value"], "ms_per_step": v["ms"], "jumps_per_traj": v["jumps_per_traj"]}
+        # jumps per second: the throughput of the jump handler, which binds the runs with
+        # few levels and many jumps (their MFMA share is small)
+        "paths": {p: {"value": v["value"], "ms_per_step": v["ms"], "jumps_per_traj": v["jumps_per_traj"],
+                      "jumps_per_s": v["jumps_per_traj"] * K / (v["ms"] / 1e3)}
                   for p, v in results.items()},
         "precompute_s": precompute_s,
         "roofline": roof,
