@@ -1414,6 +1414,7 @@ struct Chfsi {
   std::vector<int> h_status, h_act, h_info;
   std::vector<HxCoef> h_coef;
   std::vector<char> warm;   // per slot: X holds the Ritz block of a nearby grid point
+  std::vector<char> far;    // per slot: ... of a grid point a chain length away (chain heads)
   double hub = 0.0;         // upper bound of the spectrum (Gershgorin)
   double* at(const DevBuf& b, int j) const { return b.as<double>() + static_cast<size_t>(j) * blk; }
 };
@@ -1513,7 +1514,10 @@ aqt_status chfsi_solve(aqt_ctx* ctx, Chfsi& c, const double* eZ, const std::vect
     live[j] = nconv[j] > 0;
     cold[j] = live[j] && !c.warm[j];
     anycold = anycold || cold[j];
-    maxit[j] = c.warm[j] ? 80 : 150;
+    // a start from the neighbouring grid point converges in a few iterations; a chain head
+    // starts from the previous head, a chain length away, where the spectrum near the cut
+    // may have rearranged, and gets the budget of a cold start twice over
+    maxit[j] = !c.warm[j] ? 150 : (c.far[j] ? 300 : 80);
   }
   auto where = [&](int j) { return "at grid point " + std::to_string(gidx[j]); };
   AQT_HIP(ctx, hipMemsetAsync(c.status.p, 0, static_cast<size_t>(nb) * 4, st));
@@ -1644,7 +1648,10 @@ aqt_status chfsi_solve(aqt_ctx* ctx, Chfsi& c, const double* eZ, const std::vect
     if ((s = chfsi_orth(ctx, c, c.Y1.as<double>())) != AQT_OK) return s;
   }
   for (int j = 0; j < nb; ++j)
-    if (nconv[j] > 0) c.warm[j] = 1;
+    if (nconv[j] > 0) {
+      c.warm[j] = 1;
+      c.far[j] = 0;
+    }
   return AQT_OK;
 }
 
@@ -1704,12 +1711,16 @@ aqt_status chfsi_chunk(aqt_ctx* ctx, Chfsi& c, const double* eZ, const std::vect
     if (j > 0) {
       AQT_HIP(ctx, hipMemcpyAsync(c.at(c.X, j), c.at(c.X, j - 1), c.blk * 8, hipMemcpyDeviceToDevice, ctx->stream));
       c.warm[j] = 1;
+      c.far[j] = 1;
     }
     std::fill(gidx.begin(), gidx.end(), -1);
     std::fill(nconv.begin(), nconv.end(), 0);
     gidx[j] = head[j];
     nconv[j] = nconv_at(head[j]);
     if ((s = chfsi_solve(ctx, c, eZ, Ag, Bg, gidx, nconv, 1e-12)) != AQT_OK) return s;
+    // at s = 0 only the lowest levels converged: the next solve from this block starts
+    // nearly cold
+    if (head[j] == 0) c.far[j] = 1;
   }
   std::fill(gidx.begin(), gidx.end(), -1);
   int len = 0;
@@ -1958,6 +1969,7 @@ aqt_status precompute_tables(aqt_ctx* ctx, int M, int n, double tol, int method,
     ch.h_res.resize(nb * KB);
     ch.h_status.resize(nb);
     ch.warm.assign(nb, 0);
+    ch.far.assign(nb, 0);
     std::vector<double> hz(N);
     AQT_HIP(ctx, hipMemcpyAsync(hz.data(), eZ.p, N * 8, hipMemcpyDeviceToHost, st));
     AQT_HIP(ctx, hipStreamSynchronize(st));
