@@ -823,3 +823,18 @@ def test_stored_discretisation_values_agree_with_the_stored_ame():
     r = d[small["instance"]]
     errs = [abs(r["pgs"][k] - r["continuous"]) for k in sorted(r["pgs"], key=int)]
     assert errs[0] > errs[1] > errs[2]
+
+
+def test_stored_batched_reference_is_the_oracles():
+    """The stored AME reference of the batched workload (tests/golden/batched_ame_pgs.json,
+    written by make_golden.py --batched) for its smallest instance (6 qubits, 16 levels,
+    1000 grid points) is what the oracle's split-step AME gives now."""
+    import json
+    import os
+    import workloads
+    ref = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "batched_ame_pgs.json")))
+    row = next(r for r in ref["instances"] if r["name"].startswith("batch2-"))
+    inst = workloads.config_batched()[row["index"]]
+    assert inst.name == row["name"] and inst.n_grid == row["n_grid"]
+    P = ame.split_step(spectrum.table_stream(inst), inst)
+    np.testing.assert_allclose(P[np.array(row["grid_points"])], row["pgs"], rtol=1e-10, atol=1e-12)
