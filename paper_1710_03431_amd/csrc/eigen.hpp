@@ -30,6 +30,7 @@ constexpr int kEigMaxN = 1024;
 // LDS state of the solver for matrices of order up to MaxN.
 template <int MaxN>
 struct EigSharedN {
+  static constexpr int kMax = MaxN;
   double v[MaxN];     // Householder vector / scratch
   double w[MaxN];     // p, then w
   double d[MaxN];     // band diagonal
@@ -56,7 +57,9 @@ __device__ __forceinline__ double block_sum(double v, double* red) {
 
 // Reduce symmetric A (row-major, leading dimension lda) to tridiagonal form.
 // On exit sh.d/sh.e hold the band, sh.beta the reflection coefficients and row
-// j of A, right of the diagonal, the Householder vector of step j.
+// j of A, right of the diagonal, the Householder vector of step j.  Per step the
+// product with the Householder vector and the rank-2 update of the whole trailing
+// block, reading both triangles: for matrices that stay in the caches.
 template <class Sh>
 __device__ void wg_tridiagonalize(double* A, int N, int lda, Sh& sh) {
   const int tid = threadIdx.x;
@@ -116,6 +119,137 @@ __device__ void wg_tridiagonalize(double* A, int N, int lda, Sh& sh) {
       sh.beta[N - 2] = 0.0;
     }
     sh.d[N - 1] = A[static_cast<size_t>(N - 1) * lda + N - 1];
+    sh.e[N - 1] = 0.0;
+    sh.beta[N - 1] = 0.0;
+  }
+  __syncthreads();
+}
+
+// wg_tridiagonalize for a matrix too large for the caches, where the reduction is
+// bound by HBM bandwidth (same results on exit; the rest of A is overwritten).
+// Only the lower triangle is read.  Each step passes over
+// the lower triangle of the trailing block once: the rank-2 update of the step
+// before, held back until now (its v and w in sh.c / sh.s, which are free until
+// the QR sweep), is applied and written back, and the updated entries feed the
+// symmetric product with this step's vector -- row sums by wavefront reductions,
+// the transposed half accumulated per lane and combined across wavefronts in a
+// fixed order: a third of the traffic of wg_tridiagonalize.
+template <class Sh>
+__device__ void wg_tridiagonalize_streamed(double* A, int N, int lda, Sh& sh) {
+  constexpr int NT = (Sh::kMax + kWave - 1) / kWave;   // column slots per lane
+  constexpr int NW = kEigThreads / kWave;
+  const int tid = threadIdx.x;
+  const int lane = tid & (kWave - 1), wave = tid >> 6;
+  double* pv = sh.c;   // held-back update: S -= pv pw^T + pw pv^T
+  double* pw = sh.s;
+  for (int i = tid; i < N; i += kEigThreads) {
+    pv[i] = 0.0;
+    pw[i] = 0.0;
+  }
+  __syncthreads();
+  bool pend = false;
+  for (int j = 0; j + 2 < N; ++j) {
+    const int c0 = j + 1;
+    const double pvj = pv[j], pwj = pw[j];
+    // column j below the diagonal, updated
+    double part = 0.0;
+    for (int i = c0 + tid; i < N; i += kEigThreads) {
+      const double x = A[static_cast<size_t>(i) * lda + j] - (pv[i] * pwj + pw[i] * pvj);
+      sh.v[i] = x;
+      if (i > c0) part += x * x;
+    }
+    const double tail = block_sum(part, sh.red);
+    const double x0 = sh.v[c0];
+    const bool refl = tail != 0.0;
+    const double sigma = sqrt(x0 * x0 + tail);
+    const double alpha = (x0 >= 0.0) ? -sigma : sigma;
+    const double v0 = x0 - alpha;
+    const double bet = refl ? 2.0 / (v0 * v0 + tail) : 0.0;
+    __syncthreads();   // every thread has read x0
+    if (tid == 0) {
+      sh.d[j] = A[static_cast<size_t>(j) * lda + j] - 2.0 * pvj * pwj;
+      sh.e[j] = refl ? alpha : x0;
+      sh.beta[j] = bet;
+      if (refl) sh.v[c0] = v0;
+    }
+    __syncthreads();
+    if (refl)
+      for (int i = c0 + tid; i < N; i += kEigThreads) A[static_cast<size_t>(j) * lda + i] = sh.v[i];
+    if (!pend && !refl) continue;   // nothing to apply, nothing to multiply
+    double q[NT];
+#pragma unroll
+    for (int t = 0; t < NT; ++t) q[t] = 0.0;
+    for (int i = c0 + wave; i < N; i += NW) {
+      double* row = A + static_cast<size_t>(i) * lda;
+      const double pvi = pv[i], pwi = pw[i];
+      const double vi = refl ? sh.v[i] : 0.0;
+      double a[NT];
+#pragma unroll
+      for (int t = 0; t < NT; ++t) {
+        const int k = c0 + lane + kWave * t;
+        a[t] = (c0 + kWave * t <= i && k <= i) ? row[k] : 0.0;
+      }
+      double acc = 0.0;
+#pragma unroll
+      for (int t = 0; t < NT; ++t) {
+        const int k = c0 + lane + kWave * t;
+        if (c0 + kWave * t <= i && k <= i) {
+          double x = a[t];
+          if (pend) {
+            x -= pvi * pw[k] + pwi * pv[k];
+            row[k] = x;
+          }
+          if (refl) {
+            acc += x * sh.v[k];
+            if (k < i) q[t] += x * vi;
+          }
+        }
+      }
+      if (refl) {
+        acc = wave_sum(acc);
+        if (lane == 0) sh.w[i] = acc;
+      }
+    }
+    __syncthreads();   // pass done: row sums in sh.w, old pv / pw no longer read
+    if (refl) {
+      for (int r = 0; r < NW; ++r) {
+        if (wave == r) {
+#pragma unroll
+          for (int t = 0; t < NT; ++t) {
+            const int k = c0 + lane + kWave * t;
+            if (k < N) sh.w[k] += q[t];
+          }
+        }
+        __syncthreads();
+      }
+      double pp = 0.0;
+      for (int i = c0 + tid; i < N; i += kEigThreads) {
+        const double wi = bet * sh.w[i];
+        sh.w[i] = wi;
+        pp += sh.v[i] * wi;
+      }
+      const double Kc = 0.5 * bet * block_sum(pp, sh.red);
+      for (int i = c0 + tid; i < N; i += kEigThreads) {
+        pv[i] = sh.v[i];
+        pw[i] = sh.w[i] - Kc * sh.v[i];
+      }
+    } else {
+      for (int i = c0 + tid; i < N; i += kEigThreads) {
+        pv[i] = 0.0;
+        pw[i] = 0.0;
+      }
+    }
+    pend = refl;
+    __syncthreads();
+  }
+  if (tid == 0) {
+    if (N >= 2) {
+      const int a = N - 2, b = N - 1;
+      sh.d[a] = A[static_cast<size_t>(a) * lda + a] - 2.0 * pv[a] * pw[a];
+      sh.e[a] = A[static_cast<size_t>(b) * lda + a] - (pv[b] * pw[a] + pw[b] * pv[a]);
+      sh.beta[a] = 0.0;
+    }
+    sh.d[N - 1] = A[static_cast<size_t>(N - 1) * lda + N - 1] - 2.0 * pv[N - 1] * pw[N - 1];
     sh.e[N - 1] = 0.0;
     sh.beta[N - 1] = 0.0;
   }
@@ -257,7 +391,9 @@ __device__ bool wg_band_qr(double* Z, int N, int ldz, Sh& sh, bool from_z = fals
 }
 
 // Apply the stored reflections to the columns of Z listed in cols[0..ncols-1]
-// (column-major), turning band eigenvectors into eigenvectors of A.
+// (column-major), turning band eigenvectors into eigenvectors of A.  Per
+// reflection one pass for the dot products with the columns and one for their
+// update: for matrices that stay in the caches.
 template <class Sh>
 __device__ void wg_back_transform(const double* A, int N, int lda, double* Z, int ldz, const int* cols, int ncols,
                                   Sh& sh) {
@@ -285,6 +421,67 @@ __device__ void wg_back_transform(const double* A, int N, int lda, double* Z, in
     }
     __syncthreads();
   }
+}
+
+// wg_back_transform for matrices too large for the caches: each wavefront holds a
+// group of kBtCols columns of Z in registers (row lane + 64 t in slot t) while every
+// reflection is applied to them, so Z is read and written once and each reflection
+// is read once per group (wg_back_transform moves Z three times per reflection).
+constexpr int kBtCols = 2;
+template <class Sh>
+__device__ void wg_back_transform_streamed(const double* A, int N, int lda, double* Z, int ldz, const int* cols,
+                                           int ncols, Sh& sh) {
+  constexpr int NT = (Sh::kMax + kWave - 1) / kWave;
+  constexpr int NW = kEigThreads / kWave;
+  const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x >> 6;
+  const int ngrp = (ncols + kBtCols - 1) / kBtCols;
+  for (int gi = wave; gi < ngrp; gi += NW) {
+    double* zc[kBtCols];
+    double z[kBtCols][NT];
+#pragma unroll
+    for (int c = 0; c < kBtCols; ++c) {
+      const int q = gi * kBtCols + c;
+      zc[c] = (q < ncols) ? Z + static_cast<size_t>(cols[q]) * ldz : nullptr;
+#pragma unroll
+      for (int t = 0; t < NT; ++t) {
+        const int r = lane + kWave * t;
+        z[c][t] = (zc[c] != nullptr && r < N) ? zc[c][r] : 0.0;
+      }
+    }
+    for (int j = N - 3; j >= 0; --j) {
+      const double beta = sh.beta[j];
+      if (beta == 0.0) continue;
+      const double* vrow = A + static_cast<size_t>(j) * lda;   // v_j at rows j+1 .. N-1
+      double v[NT];
+#pragma unroll
+      for (int t = 0; t < NT; ++t) {
+        const int r = lane + kWave * t;
+        v[t] = (r > j && r < N) ? vrow[r] : 0.0;
+      }
+      double dot[kBtCols];
+#pragma unroll
+      for (int c = 0; c < kBtCols; ++c) {
+        double acc = 0.0;
+#pragma unroll
+        for (int t = 0; t < NT; ++t) acc = fma(v[t], z[c][t], acc);
+        dot[c] = acc;
+      }
+#pragma unroll
+      for (int c = 0; c < kBtCols; ++c) dot[c] = beta * wave_sum(dot[c]);
+#pragma unroll
+      for (int c = 0; c < kBtCols; ++c)
+#pragma unroll
+        for (int t = 0; t < NT; ++t) z[c][t] = fma(-dot[c], v[t], z[c][t]);
+    }
+#pragma unroll
+    for (int c = 0; c < kBtCols; ++c)
+#pragma unroll
+      for (int t = 0; t < NT; ++t) {
+        const int r = lane + kWave * t;
+        if (zc[c] != nullptr && r < N) zc[c][r] = z[c][t];
+      }
+  }
+  __syncthreads();
 }
 
 // Stable ascending rank of the eigenvalues: perm[rank] = index.  A NaN ranks as

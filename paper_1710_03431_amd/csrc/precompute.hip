@@ -71,6 +71,12 @@ __global__ void k_build_dense(const double* __restrict__ eZ, int nq, const doubl
 
 // One workgroup per matrix: eigenvalues (ascending, stable) and eigenvectors.
 // Z is column-major: Z[col * N + row]; perm[a] is the column of level a.
+// STREAMED: the order is at least kStreamedEigMin, so the matrix lives in HBM
+// rather than the caches, and the reduction and back transform take their
+// bandwidth-saving forms (a separate instantiation, as their register needs
+// would lower the occupancy of the cached form).
+constexpr int kStreamedEigMin = 512;
+template <bool STREAMED>
 __global__ __launch_bounds__(kEigThreads) void k_dense_eig(double* H, double* Z, int N, int ncols, int partial,
                                                            double* __restrict__ Eraw, int* __restrict__ perm,
                                                            int* __restrict__ status) {
@@ -81,11 +87,13 @@ __global__ __launch_bounds__(kEigThreads) void k_dense_eig(double* H, double* Z,
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   double* A = H + static_cast<size_t>(c) * N * N;
   double* Zc = Z + static_cast<size_t>(c) * N * N;
-  wg_tridiagonalize(A, N, N, sh);
+  if (STREAMED) wg_tridiagonalize_streamed(A, N, N, sh);
+  else wg_tridiagonalize(A, N, N, sh);
   if (!partial) {
     const bool ok = wg_band_qr(Zc, N, N, sh);
     wg_rank_ascending(sh.d, N, s_perm);
-    wg_back_transform(A, N, N, Zc, N, s_perm, ncols, sh);
+    if (STREAMED) wg_back_transform_streamed(A, N, N, Zc, N, s_perm, ncols, sh);
+    else wg_back_transform(A, N, N, Zc, N, s_perm, ncols, sh);
     for (int a = tid; a < N; a += blockDim.x) {
       perm[static_cast<size_t>(c) * N + a] = s_perm[a];
       Eraw[static_cast<size_t>(c) * N + a] = sh.d[s_perm[a]];
@@ -198,7 +206,8 @@ __global__ __launch_bounds__(kEigThreads) void k_dense_eig(double* H, double* Z,
   for (int i = tid; i < N; i += blockDim.x) sh.beta[i] = Bsv[i];
   for (int a = tid; a < nc; a += blockDim.x) s_perm[a] = a;
   __syncthreads();
-  wg_back_transform(A, N, N, X, N, s_perm, nc, sh);
+  if (STREAMED) wg_back_transform_streamed(A, N, N, X, N, s_perm, nc, sh);
+  else wg_back_transform(A, N, N, X, N, s_perm, nc, sh);
   for (int a = tid; a < N; a += blockDim.x) {
     perm[static_cast<size_t>(c) * N + a] = a;
     Eraw[static_cast<size_t>(c) * N + a] = (a < nc) ? lam[a] : 0.0;
@@ -1989,8 +1998,12 @@ aqt_status precompute_tables(aqt_ctx* ctx, int M, int n, double tol, int method,
       hipLaunchKernelGGL(k_build_dense, dim3(nblk(static_cast<int64_t>(N) * N * cnt)), dim3(256), 0, st,
                          eZ.as<double>(), nq, dA.as<double>(), dB.as<double>(), g0, cnt, H.as<double>());
       AQT_HIP(ctx, hipGetLastError());
-      hipLaunchKernelGGL(k_dense_eig, dim3(cnt), dim3(kEigThreads), 0, st, H.as<double>(), Z.as<double>(), N, ncols,
-                         partial ? 1 : 0, Eraw.as<double>(), perm.as<int>(), status.as<int>());
+      if (N >= kStreamedEigMin)
+        hipLaunchKernelGGL(k_dense_eig<true>, dim3(cnt), dim3(kEigThreads), 0, st, H.as<double>(), Z.as<double>(), N,
+                           ncols, partial ? 1 : 0, Eraw.as<double>(), perm.as<int>(), status.as<int>());
+      else
+        hipLaunchKernelGGL(k_dense_eig<false>, dim3(cnt), dim3(kEigThreads), 0, st, H.as<double>(), Z.as<double>(), N,
+                           ncols, partial ? 1 : 0, Eraw.as<double>(), perm.as<int>(), status.as<int>());
       AQT_HIP(ctx, hipGetLastError());
       hipLaunchKernelGGL(k_canon, dim3(cnt), dim3(kEigThreads), 0, st, Z.as<double>(), perm.as<int>(),
                          Eraw.as<double>(), N, ncols, n, NP, tol, g0, Vc.as<double>(), ctx->E.as<double>(),
