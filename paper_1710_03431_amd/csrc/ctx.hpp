@@ -84,6 +84,7 @@ struct aqt_ctx {
   int packed_for = -1;      // aqt_precision the packs below hold, -1 = none
   aqt::DevBuf pk_a, pk_b;   // Delta fragments (hi / lo for BF16)
   aqt::DevBuf pk_dre, pk_dim;  // d in the state precision
+  aqt::DevBuf pk_ch;            // FP32 runs: [M][nq][NP] float4 (R row sum, sum below the diagonal, diagonal, z_bb)
 
   // ---- run workspace
   aqt::DevBuf partial;      // [tiles][M][2] per-tile observable sums

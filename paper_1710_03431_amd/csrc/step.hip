@@ -98,6 +98,7 @@ struct StepArgs {
   const double* Rcol;    // [M][nq][NP][4] row sum, sum below the diagonal, diagonal of R
   const double* ehalf;   // [M][NP] exp(+Gamma dt / 2)
   const double* zdiag;   // [M][nq][NP]
+  const float4* chf;     // FP32 runs: [M][nq][NP] (row sum, sum below the diagonal, diagonal, z_bb), else null
   const double* E;       // [M][NP]
   const int* gs;         // [M]
   double* partial;       // [tiles][M][2]
@@ -436,8 +437,8 @@ __device__ constexpr H newton_tol() {
 // the observable sums stay in FP64 in every mode.
 template <int NP, class T, bool STAGED>
 __device__ void finish_crossing(const StepArgs& a, int g, int t, int64_t jloc, TileCols<NP, T>* S,
-                                double* s_r, int* s_m, int* s_cnt, int* s_net, double* s_p,
-                                int* s_kind, RngCache rc, const double* tg) {
+                                const double* s_r, double* s_rn, int* s_m, int* s_cnt, int* s_net, double* s_p,
+                                int* s_kind, RngCache rc, const double* tg, const float4* chs) {
   using H = T;
   constexpr int SEG = seg_width<NP>();
   constexpr int PL = NP / SEG;
@@ -485,7 +486,10 @@ __device__ void finish_crossing(const StepArgs& a, int g, int t, int64_t jloc, T
     for (int j = 0; j < PL; ++j)
       if (lane + SEG * j < gsz) pg += static_cast<double>(sr[j]) * sr[j] + static_cast<double>(si[j]) * si[j];
     pg = seg_sum<SEG>(pg);
-    if (lane == 0) s_p[t] = pg / nu0;
+    if (lane == 0) {
+      s_p[t] = pg / nu0;
+      s_rn[t] = r;
+    }
     return;
   }
   // draws: the two cached blocks, else Philox blocks evaluated across the segment's lanes
@@ -613,10 +617,17 @@ __device__ void finish_crossing(const StepArgs& a, int g, int t, int64_t jloc, T
         // one channel per lane
         H rs = H(0), rlo = H(0), rdg = H(0);
         if (lane < a.nq) {
-          const double* c4 = Rc + (static_cast<size_t>(lane) * NP + b) * 4;
-          rs = static_cast<H>(c4[0]);
-          rlo = static_cast<H>(c4[1]);
-          rdg = static_cast<H>(c4[2]);
+          if (chs) {   // staged in LDS
+            const float4 c4 = chs[lane * NP + b];
+            rs = static_cast<H>(c4.x);
+            rlo = static_cast<H>(c4.y);
+            rdg = static_cast<H>(c4.z);
+          } else {
+            const double* c4 = Rc + (static_cast<size_t>(lane) * NP + b) * 4;
+            rs = static_cast<H>(c4[0]);
+            rlo = static_cast<H>(c4[1]);
+            rdg = static_cast<H>(c4[2]);
+          }
         }
         const H cum_i = seg_scan<SEG>(rs);
         const H tot = seg_read<SEG>(cum_i, SEG - 1, base);
@@ -684,12 +695,24 @@ __device__ void finish_crossing(const StepArgs& a, int g, int t, int64_t jloc, T
       else if (b < gsz && ta >= gsz) --net;
     } else {
       const double* zd = a.zdiag + (static_cast<size_t>(g) * a.nq + qi) * NP;
+      H z[PL];
+      if (chs) {
+#pragma unroll
+        for (int j = 0; j < PL; ++j) {
+          const int x = lane + SEG * j;
+          z[j] = (x < NP) ? static_cast<H>(chs[qi * NP + x].w) : H(0);
+        }
+      } else {
+#pragma unroll
+        for (int j = 0; j < PL; ++j) {
+          const int x = lane + SEG * j;
+          z[j] = (x < NP) ? static_cast<H>(zd[x]) : H(0);
+        }
+      }
 #pragma unroll
       for (int j = 0; j < PL; ++j) {
-        const int x = lane + SEG * j;
-        const H z = (x < NP) ? static_cast<H>(zd[x]) : H(0);
-        cr[j] *= z;
-        ci[j] *= z;
+        cr[j] *= z[j];
+        ci[j] *= z[j];
       }
       kind = AQT_KIND_DEPHASE;
     }
@@ -739,39 +762,13 @@ __device__ void finish_crossing(const StepArgs& a, int g, int t, int64_t jloc, T
   pt = seg_sum<SEG>(pt);
   if (lane == 0) {
     s_p[t] = pg / pt;
-    s_r[t] = r;
+    s_rn[t] = r;
     s_m[t] = m;
     s_cnt[t] = cnt;
     s_net[t] = net;
     if (((3ull * static_cast<uint64_t>(m) + 1ull) >> 2) != Bc) rc.list[atomicAdd(rc.n, 1)] = t;
   }
 }
-
-// --------------------------------------------------------------- kernel ----
-// Work split of the overlap GEMM over the WV wavefronts: with WV or more row
-// tiles each wave owns the row tiles rt = wave (mod WV) for every column tile
-// (one A fragment feeds TQ MFMAs); with fewer, waves take (row tile, column
-// tile) pairs.  The k loop is outermost so each wave keeps UPW*QG independent
-// accumulator chains in flight.
-template <int NP, int TQ, class T, int WV>
-struct TileShared {
-  static constexpr int NRT = NP / 16;
-  static constexpr int TT = 8 * TQ;
-  static constexpr int NSLOT = (NRT >= WV) ? WV : NRT;   // partial squared norms per trajectory
-  TileCols<NP, T> S[TQ];
-  double nu[NSLOT][TT];   // partial squared norms, accumulated in FP64
-  double r[TT];
-  double p[TT];
-  int m[TT], cnt[TT], net[TT];
-  int list[TT];
-  int nlist;
-  int kind[3];
-  uint64_t rng[TT][8];   // Philox blocks of each trajectory's next draws (RngCache)
-  uint64_t rngb[TT];
-  int rfl[TT];           // trajectories whose blocks are to be refreshed
-  int nrfl;
-  double tg[kStepTables][NP];   // the step's Gamma, e^{G dt/2}, E, phase re/im (jump handler)
-};
 
 // Per-grid-point tables the jump handler reads, staged in LDS each step in the FP32
 // kernels: loaded from HBM/L2 ahead of the GEMM, stored after it, so a crossing finds
@@ -781,12 +778,49 @@ template <class Mode>
 constexpr bool stage_tables() {
   return Mode::KC == 4 && sizeof(typename Mode::T) == 4;
 }
+// The channel entries of a grid point (per channel and level: R's row sum, its part
+// below the diagonal, its diagonal, z_bb) as well, in the FP32 kernels with 128 or
+// more levels when they fit kChanStage entries: the channel draw and the dephasing
+// factors of a crossing then need no dependent global load.  (The smaller-level
+// kernels keep their LDS for more resident workgroups.)
+constexpr int kChanStage = 2048;
+template <class Mode, int NP>
+constexpr bool stage_channels() {
+  return stage_tables<Mode>() && NP >= 128;
+}
+
+// --------------------------------------------------------------- kernel ----
+// Work split of the overlap GEMM over the WV wavefronts: with WV or more row
+// tiles each wave owns the row tiles rt = wave (mod WV) for every column tile
+// (one A fragment feeds TQ MFMAs); with fewer, waves take (row tile, column
+// tile) pairs.  The k loop is outermost so each wave keeps UPW*QG independent
+// accumulator chains in flight.
+template <int NP, int TQ, class Mode, int WV>
+struct TileShared {
+  using T = typename Mode::T;
+  static constexpr int NRT = NP / 16;
+  static constexpr int TT = 8 * TQ;
+  static constexpr int NSLOT = (NRT >= WV) ? WV : NRT;   // partial squared norms per trajectory
+  TileCols<NP, T> S[TQ];
+  double nu[NSLOT][TT];   // partial squared norms, accumulated in FP64
+  double r[2][TT];   // waiting-time thresholds: read from r[g & 1], written to r[(g + 1) & 1]
+  double p[TT];
+  int m[TT], cnt[TT], net[TT];
+  int kind[3];
+  uint64_t rng[TT][8];   // Philox blocks of each trajectory's next draws (RngCache)
+  uint64_t rngb[TT];
+  int rfl[TT];           // trajectories whose blocks are to be refreshed
+  int nrfl;
+  double tg[kStepTables][NP];   // the step's Gamma, e^{G dt/2}, E, phase re/im (jump handler)
+  float4 chs[stage_channels<Mode, NP>() ? kChanStage : 1];   // the step's channel entries (jump handler)
+};
+
 __device__ __forceinline__ const double* step_table(const StepArgs& a, int which) {
   return which == 0 ? a.Gamma : which == 1 ? a.ehalf : which == 2 ? a.E : which == 3 ? a.d64re : a.d64im;
 }
 
 template <int NP, int TQ, class Mode, int WV>
-__device__ void run_tile(const StepArgs& a, int64_t tile, TileShared<NP, TQ, typename Mode::T, WV>& sh) {
+__device__ void run_tile(const StepArgs& a, int64_t tile, TileShared<NP, TQ, Mode, WV>& sh) {
   using T = typename Mode::T;
   using Acc = typename Mode::Acc;
   constexpr int NRT = NP / 16;
@@ -799,14 +833,11 @@ __device__ void run_tile(const StepArgs& a, int64_t tile, TileShared<NP, TQ, typ
 
   auto& S = sh.S;
   auto& s_nu = sh.nu;
-  constexpr int NSLOT = TileShared<NP, TQ, T, WV>::NSLOT;
-  double* s_r = sh.r;
+  constexpr int NSLOT = TileShared<NP, TQ, Mode, WV>::NSLOT;
   double* s_p = sh.p;
   int* s_m = sh.m;
   int* s_cnt = sh.cnt;
   int* s_net = sh.net;
-  int* s_list = sh.list;
-  int& s_nlist = sh.nlist;
   int* s_kind = sh.kind;
 
   const int tid = threadIdx.x;
@@ -819,7 +850,7 @@ __device__ void run_tile(const StepArgs& a, int64_t tile, TileShared<NP, TQ, typ
   const RngCache rc{sh.rng, sh.rngb, sh.rfl, &sh.nrfl};
   if (tid < TT) {
     const int64_t j = tb + tid;
-    s_r[tid] = (j < a.K) ? draw_uniform(a.seed, a.iid, a.traj0 + j, 0) : 2.0;
+    sh.r[1][tid] = (j < a.K) ? draw_uniform(a.seed, a.iid, a.traj0 + j, 0) : 2.0;   // read at g = 1
     s_m[tid] = 0;
     s_cnt[tid] = 0;
     s_net[tid] = 0;
@@ -882,6 +913,10 @@ __device__ void run_tile(const StepArgs& a, int64_t tile, TileShared<NP, TQ, typ
   // The accumulators keep C between steps (the identity split starts from C);
   // only column tiles touched by the jump handler are reloaded from LDS.
   unsigned dirty = 0;
+  // channel entries staged per step when the kernel keeps room for them and they fit
+  constexpr int CHPT = stage_channels<Mode, NP>() ? (kChanStage + WV * 64 - 1) / (WV * 64) : 1;
+  const int nch_e = a.nq * NP;
+  const bool ch_on = stage_channels<Mode, NP>() && a.chf != nullptr && nch_e <= kChanStage;
 
   for (int g = 1; g < a.M_run; ++g) {
     const int gsz = a.gs[g];
@@ -937,6 +972,12 @@ __device__ void run_tile(const StepArgs& a, int64_t tile, TileShared<NP, TQ, typ
     for (int k = 0; k < TGPT; ++k) {
       const int f = tid + k * WV * 64;
       tgv[k] = (STAGED && f < NTG) ? step_table(a, f / NP)[static_cast<size_t>(g) * NP + f % NP] : 0.0;
+    }
+    float4 chv[CHPT];
+#pragma unroll
+    for (int k = 0; k < CHPT; ++k) {
+      const int f = tid + k * WV * 64;
+      chv[k] = (ch_on && f < nch_e) ? a.chf[static_cast<size_t>(g) * nch_e + f] : make_float4(0.f, 0.f, 0.f, 0.f);
     }
     if (g > 1) {
       T bnx[QG];
@@ -1060,6 +1101,13 @@ __device__ void run_tile(const StepArgs& a, int64_t tile, TileShared<NP, TQ, typ
         if (f < NTG) sh.tg[f / NP][f % NP] = tgv[k];
       }
     }
+    if (ch_on) {
+#pragma unroll
+      for (int k = 0; k < CHPT; ++k) {
+        const int f = tid + k * WV * 64;
+        if (f < nch_e) sh.chs[f] = chv[k];
+      }
+    }
     __syncthreads();   // every wave has finished reading S
     // ---- 2. C' = d o C and the squared norms (partial sums per wave or row tile).
     // The squares of state-precision amplitudes are exact in FP64 and every sum of
@@ -1115,50 +1163,62 @@ __device__ void run_tile(const StepArgs& a, int64_t tile, TileShared<NP, TQ, typ
         }
       }
     }
-    if (tid == 0) s_nlist = 0;
     __syncthreads();
-    // ---- 3. threshold test
-    if (tid < TT) {
-      const bool valid = tb + tid < a.K;
+    // ---- 3. threshold test.  Every wavefront takes it for all TT trajectories (lane t,
+    // the same FP64 sums in the same order), so each knows the crossing set from a
+    // ballot, without a list or another barrier; the thresholds it reads are not
+    // written this step (the handlers write the other buffer).  Wavefront 0 records
+    // the ground-cluster weight of the trajectories that do not cross and carries
+    // their thresholds over.
+    const double* s_r = sh.r[g & 1];
+    double* s_rn = sh.r[(g + 1) & 1];
+    uint64_t cmask;
+    {
+      bool cross = false;
       double nu = 0.0;
+      const bool valid = lane < TT && tb + lane < a.K;
+      if (lane < TT) {
 #pragma unroll
-      for (int sl = 0; sl < NSLOT; ++sl) nu += s_nu[sl][tid];
-      if (valid) {
-        if (nu <= s_r[tid]) {
-          s_list[atomicAdd(&s_nlist, 1)] = tid;
-        } else {
-          // ground-cluster weight: the (few) lowest rows of this trajectory
-          double gw = 0.0;
+        for (int sl = 0; sl < NSLOT; ++sl) nu += s_nu[sl][lane];
+        cross = valid && nu <= s_r[lane];
+      }
+      cmask = __ballot(cross);
+      if (wave == 0 && lane < TT && !cross) {
+        double gw = 0.0;
+        if (valid)
           for (int row = 0; row < gsz; ++row) {
-            const double re = static_cast<double>(amp<NP, T>(S, tid, 0, row));
-            const double im = static_cast<double>(amp<NP, T>(S, tid, 1, row));
+            const double re = static_cast<double>(amp<NP, T>(S, lane, 0, row));
+            const double im = static_cast<double>(amp<NP, T>(S, lane, 1, row));
             gw += re * re + im * im;
           }
-          s_p[tid] = gw / nu;
-        }
-      } else {
-        s_p[tid] = 0.0;
+        s_p[lane] = valid ? gw / nu : 0.0;
+        s_rn[lane] = s_r[lane];
       }
     }
-    __syncthreads();
-    const int ncross = __builtin_amdgcn_readfirstlane(s_nlist);
+    const int ncross = __popcll(cmask);
     {
-      // 64 / SEG crossings per wavefront, one per segment of SEG lanes
+      // 64 / SEG crossings per wavefront, one per segment of SEG lanes; crossing e is
+      // the trajectory of the e-th set bit of the mask
       constexpr int SEG = seg_width<NP>();
       constexpr int NSEG = kWave / SEG;
       const int seg = (tid & (kWave - 1)) / SEG;
       for (int e0 = wave * NSEG; e0 < ncross; e0 += WV * NSEG) {
         const int e = e0 + seg;
         if (e < ncross) {
-          const int t = s_list[e];
-          finish_crossing<NP, T, STAGED>(a, g, t, tb + t, S, s_r, s_m, s_cnt, s_net, s_p, s_kind, rc, &sh.tg[0][0]);
+          uint64_t mm = cmask;
+          for (int k = 0; k < e; ++k) mm &= mm - 1;
+          const int t = __builtin_ctzll(mm);
+          finish_crossing<NP, T, STAGED>(a, g, t, tb + t, S, s_r, s_rn, s_m, s_cnt, s_net, s_p, s_kind, rc,
+                                         &sh.tg[0][0], ch_on ? sh.chs : nullptr);
         }
       }
     }
     __syncthreads();
     // column tiles whose amplitudes the handler rewrote
     dirty = 0;
-    for (int e = 0; e < ncross; ++e) dirty |= 1u << (__builtin_amdgcn_readfirstlane(s_list[e]) >> 3);
+#pragma unroll
+    for (int q = 0; q < TQ; ++q)
+      if ((cmask >> (8 * q)) & 0xffull) dirty |= 1u << q;
     // ---- 4. per-tile observable sums (wave 0)
     if (wave == 0) {
       const double p = (lane < TT) ? s_p[lane] : 0.0;
@@ -1213,7 +1273,7 @@ template <int NP, int TQ, class Mode>
 __global__ __launch_bounds__((waves_for<NP, Mode>() * 64))
 __attribute__((amdgpu_waves_per_eu(min_waves_per_simd<NP, Mode>()))) void k_trajectories(StepArgs a) {
   constexpr int WV = waves_for<NP, Mode>();
-  __shared__ TileShared<NP, TQ, typename Mode::T, WV> sh;
+  __shared__ TileShared<NP, TQ, Mode, WV> sh;
   run_tile<NP, TQ, Mode, WV>(a, blockIdx.x, sh);
 }
 
@@ -1277,7 +1337,7 @@ __attribute__((amdgpu_waves_per_eu(min_waves_per_simd<NP, BatchMode<NP, Mode>>()
     const StepArgs* __restrict__ args, const BatchItem* __restrict__ items, int n_items, int* counter) {
   using M = BatchMode<NP, Mode>;
   constexpr int WV = waves_for<NP, M>();
-  __shared__ TileShared<NP, TQ, typename M::T, WV> sh;
+  __shared__ TileShared<NP, TQ, M, WV> sh;
   __shared__ int s_item;
   for (;;) {
     if (threadIdx.x == 0) s_item = atomicAdd(counter, 1);
@@ -1429,6 +1489,7 @@ aqt_status enqueue_run(aqt_ctx* ctx, const aqt_run_params* p, const aqt_outputs*
   a.Rcol = ctx->Rcol.as<double>();
   a.ehalf = ctx->ehalf.as<double>();
   a.zdiag = ctx->zdiag.as<double>();
+  a.chf = (prec == AQT_FP32) ? ctx->pk_ch.as<float4>() : nullptr;
   a.E = ctx->E.as<double>();
   a.gs = ctx->gs.as<int>();
   a.partial = partial;

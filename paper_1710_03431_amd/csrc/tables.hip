@@ -164,6 +164,18 @@ inline unsigned blocks_for(int64_t count, int threads = 256) {
 
 // Largest Gamma_b dt_g over all grid points g >= 1 and levels (one workgroup; Gamma >= 0,
 // so the maximum of the bit patterns is the maximum of the values).
+// The jump handler's per-channel numbers in the FP32 state precision, one 16-byte
+// entry per (grid, channel, level): row sum of R, its part below the diagonal, the
+// diagonal, and the dephasing factor z_bb.
+__global__ void k_pack_chan(const double* __restrict__ Rcol, const double* __restrict__ zdiag, int64_t count,
+                            float4* __restrict__ out) {
+  const int64_t idx = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (idx >= count) return;
+  const double* c = Rcol + idx * 4;
+  out[idx] = make_float4(static_cast<float>(c[0]), static_cast<float>(c[1]), static_cast<float>(c[2]),
+                         static_cast<float>(zdiag[idx]));
+}
+
 __global__ void k_max_gdt(const double* __restrict__ Gamma, const double* __restrict__ tlen, int M, int NP,
                           double* __restrict__ out) {
   __shared__ double red[256];
@@ -242,6 +254,7 @@ aqt_status pack_for_precision(aqt_ctx* ctx, int precision) {
   ctx->pk_b.release();
   ctx->pk_dre.release();
   ctx->pk_dim.release();
+  ctx->pk_ch.release();
   if (precision == AQT_FP64) {
     if (ctx->pk_a.reserve(nd * 8) != hipSuccess || ctx->pk_dre.reserve(nv * 8) != hipSuccess ||
         ctx->pk_dim.reserve(nv * 8) != hipSuccess)
@@ -257,6 +270,11 @@ aqt_status pack_for_precision(aqt_ctx* ctx, int precision) {
       if (ctx->pk_a.reserve(nd * 4) != hipSuccess) return ctx->fail(AQT_ENOMEM, "operand allocation failed");
       hipLaunchKernelGGL(k_pack_k4<float>, dim3(blocks_for(nd)), dim3(256), 0, ctx->stream, ctx->dlt.as<double>(),
                          ctx->M, ctx->NP, ctx->pk_a.as<float>());
+      const int64_t nc = nv * ctx->tab_nch;
+      if (ctx->pk_ch.reserve(nc * sizeof(float4)) != hipSuccess)
+        return ctx->fail(AQT_ENOMEM, "operand allocation failed");
+      hipLaunchKernelGGL(k_pack_chan, dim3(blocks_for(nc)), dim3(256), 0, ctx->stream, ctx->Rcol.as<double>(),
+                         ctx->zdiag.as<double>(), nc, ctx->pk_ch.as<float4>());
     } else if (precision == AQT_BF16) {
       if (ctx->pk_a.reserve(nd * 2) != hipSuccess || ctx->pk_b.reserve(nd * 2) != hipSuccess)
         return ctx->fail(AQT_ENOMEM, "operand allocation failed");
