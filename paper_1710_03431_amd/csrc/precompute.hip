@@ -551,12 +551,30 @@ __global__ __launch_bounds__(kEigThreads) void k_polar(double* dlt, int NP, int 
     __syncthreads();
     wg_canonical_range(P, n, nbad, K, ZK, s_perm, Lb, sh);
   }
+  // the factor, into Mm (M is no longer needed)
   for (size_t f = tid; f < nn; f += blockDim.x) {
     const int i = static_cast<int>(f / n), j = static_cast<int>(f - static_cast<size_t>(i) * n);
     double acc = 0.0;
     for (int a = 0; a < n; ++a) acc += T[i * n + a] * U[static_cast<size_t>(a) * n + j];
     for (int q = 0; q < nbad; ++q) acc += Lb[static_cast<size_t>(q) * n + i] * Rb[static_cast<size_t>(q) * n + j];
-    D[static_cast<size_t>(i) * NP + j] = acc - (i == j ? 1.0 : 0.0);
+    Mm[f] = acc;
+  }
+  __syncthreads();
+  // One Newton-Schulz step, O <- O - O (O^T O - I) / 2: the kept directions come from
+  // the eigenvectors of M^T M, so with singular values near tau the factor is orthogonal
+  // only to about eps / tau^2; the step squares that error.
+  for (size_t f = tid; f < nn; f += blockDim.x) {
+    const int i = static_cast<int>(f / n), j = static_cast<int>(f - static_cast<size_t>(i) * n);
+    double acc = 0.0;
+    for (int k = 0; k < n; ++k) acc += Mm[k * n + i] * Mm[k * n + j];
+    P[f] = acc - (i == j ? 1.0 : 0.0);
+  }
+  __syncthreads();
+  for (size_t f = tid; f < nn; f += blockDim.x) {
+    const int i = static_cast<int>(f / n), j = static_cast<int>(f - static_cast<size_t>(i) * n);
+    double acc = 0.0;
+    for (int k = 0; k < n; ++k) acc += Mm[i * n + k] * P[k * n + j];
+    D[static_cast<size_t>(i) * NP + j] = (Mm[f] - 0.5 * acc) - (i == j ? 1.0 : 0.0);
   }
   if (tid == 0) {
     leak[g] = 1.0 - smin;

@@ -193,6 +193,33 @@ def test_dense_lowest_levels_tables():
     np.testing.assert_allclose(got["cinit"], tabs[0].cinit, atol=1e-9)
 
 
+def test_hbm_form_full_rotation_tables():
+    """512 states kept at 128 levels (the most a truncated spectrum keeps): too many for the
+    bisection workspace, so the dense path runs the QR sweeps on the rotations, and at this
+    order the matrix takes the HBM form (one pass over the lower triangle per Householder
+    step, the back transform with the eigenvector columns in registers, columns taken in
+    eigenvalue order)."""
+    inst = W.ring_instance(9, 4242, t_f=500.0, n_grid=64, n_levels=128)
+    # the cut in the middle of the spectrum: little lost at 17 and 33, a whole direction
+    # at 20 and 63 (the polar completion, orthogonal after its Newton-Schulz step)
+    tabs, prev, full = sampled_tables(inst, {1, 2, 17, 20, 33, 63})
+    eng = gpu_tables(inst, method="dense")
+    got = eng.get_tables()
+    check_tables(got, tabs, scale=100.0, prev=prev, full=full)
+    np.testing.assert_allclose(got["cinit"], tabs[0].cinit, atol=1e-9)
+
+
+def test_hbm_form_lowest_levels_tables():
+    """1024 states truncated to 32 levels (the largest dense size): the HBM form of the
+    reduction and back transform behind bisection and inverse iteration."""
+    inst = W.ring_instance(10, 4243, t_f=500.0, n_grid=64, n_levels=32)
+    tabs, prev, full = sampled_tables(inst, {1, 2, 16, 29})
+    eng = gpu_tables(inst, method="dense")
+    got = eng.get_tables()
+    check_tables(got, tabs, scale=100.0, prev=prev, full=full)
+    np.testing.assert_allclose(got["cinit"], tabs[0].cinit, atol=1e-9)
+
+
 def test_iterative_solver_tables_truncated():
     """Chebyshev-filtered subspace iteration (forced on an 8-qubit instance truncated to 16
     levels) against the oracle's dense eigensolver: energies, overlaps, rates."""
