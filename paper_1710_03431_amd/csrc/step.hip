@@ -1277,6 +1277,17 @@ __attribute__((amdgpu_waves_per_eu(min_waves_per_simd<NP, Mode>()))) void k_traj
   run_tile<NP, TQ, Mode, WV>(a, blockIdx.x, sh);
 }
 
+// Compensated (Neumaier) running sum: s + c carries the rounding error of every addition.
+struct CompSum {
+  double s = 0.0, c = 0.0;
+  __device__ void add(double x) {
+    const double t = s + x;
+    c += (fabs(s) >= fabs(x)) ? (s - t) + x : (x - t) + s;
+    s = t;
+  }
+  __device__ double value() const { return s + c; }
+};
+
 __global__ void k_reduce_partials(const double* __restrict__ partial, int64_t tiles, int M, double K,
                                   double* __restrict__ sum, double* __restrict__ sumsq) {
   const int g = blockIdx.x * blockDim.x + threadIdx.x;
@@ -1286,10 +1297,13 @@ __global__ void k_reduce_partials(const double* __restrict__ partial, int64_t ti
     s = K;   // every trajectory starts in the ground state of H(0)
     q = K;
   } else {
+    CompSum cs, cq;
     for (int64_t t = 0; t < tiles; ++t) {
-      s += partial[(t * M + g) * 2];
-      q += partial[(t * M + g) * 2 + 1];
+      cs.add(partial[(t * M + g) * 2]);
+      cq.add(partial[(t * M + g) * 2 + 1]);
     }
+    s = cs.value();
+    q = cq.value();
   }
   if (sum) sum[g] = s;
   if (sumsq) sumsq[g] = q;
@@ -1360,10 +1374,13 @@ __global__ void k_reduce_batch(const StepArgs* __restrict__ args) {
     s = static_cast<double>(a.K);
     q = s;
   } else {
+    CompSum cs, cq;
     for (int64_t t = 0; t < a.tiles; ++t) {
-      s += a.partial[(t * a.M + g) * 2];
-      q += a.partial[(t * a.M + g) * 2 + 1];
+      cs.add(a.partial[(t * a.M + g) * 2]);
+      cq.add(a.partial[(t * a.M + g) * 2 + 1]);
     }
+    s = cs.value();
+    q = cq.value();
   }
   if (a.pgs_sum) a.pgs_sum[g] = s;
   if (a.pgs_sumsq) a.pgs_sumsq[g] = q;
