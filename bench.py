@@ -221,6 +221,9 @@ def bench_batched(args):
         for _ in range(args.warmup):
             b.launch()
         torch.cuda.synchronize()
+        for o in b.outs:   # jump totals accumulate over launches: count the timed ones only
+            o["jump_totals"].zero_()
+        torch.cuda.synchronize()
         starts = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
         ends = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
         for i in range(args.steps):
@@ -230,6 +233,7 @@ def bench_batched(args):
         torch.cuda.synchronize()
         ms = sum(s.elapsed_time(e) for s, e in zip(starts, ends)) / args.steps
         res = b.results()
+        jumps = sum(float(r["jump_totals"].sum()) for r in res) / args.steps
         p = [float(r["pgs_sum"][-1]) / i.n_traj for r, i in zip(res, insts)]
         tiles = sorted(set(b.tiles))
         b.close()
@@ -243,8 +247,10 @@ def bench_batched(args):
             sampled.append({"instance": k, "name": insts[k].name, "P_GS_final": m, "P_GS_final_ame": row["pgs"][-1],
                             "abs_err": abs(m - row["pgs"][-1]), "stderr": math.sqrt(max(v, 0.0) / Kk)})
         results[prec] = {"ms": ms, "value": steps_total / (ms / 1e3), "setup_s": setup_s, "tiles": tiles,
-                         "mean_pgs_final": sum(p) / len(p), "sampled": sampled}
+                         "mean_pgs_final": sum(p) / len(p), "sampled": sampled,
+                         "jumps_per_launch": jumps, "jumps_per_s": jumps / (ms / 1e3)}
         print(f"# {prec}: {ms:.2f} ms/launch, {results[prec]['value']:.4g} traj-steps/s, tiles {tiles}, "
+              f"{jumps:.4g} jumps/launch ({jumps / (ms / 1e3):.3g} jumps/s), "
               f"setup (graph capture + autotune) {setup_s:.1f} s", file=sys.stderr, flush=True)
     head_prec = "bf16" if "bf16" in results else next(iter(results))
     head = results[head_prec]
@@ -263,8 +269,10 @@ def bench_batched(args):
                    "trajectory_steps_per_launch": steps_total, "precision": head_prec},
         # the first eight instances against their stored split-step AME (same grid)
         "error_vs_fp64_ame_same_grid": {p: v["sampled"] for p, v in results.items()},
+        # jump-bound (the small-level groups): the handlers' throughput beside the MFMA roofline
         "paths": {p: {"value": v["value"], "ms_per_step": v["ms"], "tiles": v["tiles"],
-                      "mean_P_GS_final": v["mean_pgs_final"]} for p, v in results.items()},
+                      "mean_P_GS_final": v["mean_pgs_final"], "jumps_per_launch": v["jumps_per_launch"],
+                      "jumps_per_s": v["jumps_per_s"]} for p, v in results.items()},
         "precompute_s": precompute_s,
         "roofline": {"bound": "mfma", "achieved": achieved / 1e12, "peak": PEAK[head_prec] / 1e12,
                      "unit": "TFLOP/s", "frac": achieved / PEAK[head_prec], "traffic": None,

@@ -270,11 +270,13 @@ aqt_status pack_for_precision(aqt_ctx* ctx, int precision) {
       if (ctx->pk_a.reserve(nd * 4) != hipSuccess) return ctx->fail(AQT_ENOMEM, "operand allocation failed");
       hipLaunchKernelGGL(k_pack_k4<float>, dim3(blocks_for(nd)), dim3(256), 0, ctx->stream, ctx->dlt.as<double>(),
                          ctx->M, ctx->NP, ctx->pk_a.as<float>());
-      const int64_t nc = nv * ctx->tab_nch;
-      if (ctx->pk_ch.reserve(nc * sizeof(float4)) != hipSuccess)
-        return ctx->fail(AQT_ENOMEM, "operand allocation failed");
-      hipLaunchKernelGGL(k_pack_chan, dim3(blocks_for(nc)), dim3(256), 0, ctx->stream, ctx->Rcol.as<double>(),
-                         ctx->zdiag.as<double>(), nc, ctx->pk_ch.as<float4>());
+      if (ctx->NP >= 128) {   // the level counts whose FP32 kernels stage the channel entries
+        const int64_t nc = nv * ctx->tab_nch;
+        if (ctx->pk_ch.reserve(nc * sizeof(float4)) != hipSuccess)
+          return ctx->fail(AQT_ENOMEM, "operand allocation failed");
+        hipLaunchKernelGGL(k_pack_chan, dim3(blocks_for(nc)), dim3(256), 0, ctx->stream, ctx->Rcol.as<double>(),
+                           ctx->zdiag.as<double>(), nc, ctx->pk_ch.as<float4>());
+      }
     } else if (precision == AQT_BF16) {
       if (ctx->pk_a.reserve(nd * 2) != hipSuccess || ctx->pk_b.reserve(nd * 2) != hipSuccess)
         return ctx->fail(AQT_ENOMEM, "operand allocation failed");
