@@ -127,34 +127,43 @@ __device__ void wg_tridiagonalize(double* A, int N, int lda, Sh& sh) {
 
 // wg_tridiagonalize for a matrix too large for the caches, where the reduction is
 // bound by HBM bandwidth (same results on exit; the rest of A is overwritten).
-// Only the lower triangle is read.  Each step passes over
-// the lower triangle of the trailing block once: the rank-2 update of the step
-// before, held back until now (its v and w in sh.c / sh.s, which are free until
-// the QR sweep), is applied and written back, and the updated entries feed the
-// symmetric product with this step's vector -- row sums by wavefront reductions,
-// the transposed half accumulated per lane and combined across wavefronts in a
-// fixed order: a third of the traffic of wg_tridiagonalize.
+// Only the lower triangle is read.  The rank-2 updates (v w^T + w v^T) are held back
+// -- up to two, in sh.c / sh.s (free until the QR sweep) and in pend (2 MaxN
+// doubles) -- and written into A every other step, in the pass that forms that
+// step's symmetric product from the updated entries; the steps between read the
+// stale lower triangle and correct the product by the held-back updates (two dot
+// products each).  The product: row sums by wavefront reductions, the transposed
+// half accumulated per lane and combined across wavefronts in a fixed order.  Per
+// two steps one read-write and one read-only pass over the lower triangle: a quarter
+// of the traffic of wg_tridiagonalize (which reads the full matrix for the product
+// and reads and writes it for the update, every step).
 template <class Sh>
-__device__ void wg_tridiagonalize_streamed(double* A, int N, int lda, Sh& sh) {
+__device__ void wg_tridiagonalize_streamed(double* A, int N, int lda, Sh& sh, double* pend) {
   constexpr int NT = (Sh::kMax + kWave - 1) / kWave;   // column slots per lane
   constexpr int NW = kEigThreads / kWave;
   const int tid = threadIdx.x;
   const int lane = tid & (kWave - 1), wave = tid >> 6;
-  double* pv = sh.c;   // held-back update: S -= pv pw^T + pw pv^T
-  double* pw = sh.s;
+  // held-back updates r = 0, 1: the trailing block is A - sum_r (pv_r pw_r^T + pw_r pv_r^T)
+  double* pv0 = sh.c;
+  double* pw0 = sh.s;
+  double* pv1 = pend;
+  double* pw1 = pend + Sh::kMax;
   for (int i = tid; i < N; i += kEigThreads) {
-    pv[i] = 0.0;
-    pw[i] = 0.0;
+    pv0[i] = 0.0;
+    pw0[i] = 0.0;
+    pv1[i] = 0.0;
+    pw1[i] = 0.0;
   }
   __syncthreads();
-  bool pend = false;
+  int npend = 0;   // held-back updates in use (slots 0 .. npend - 1)
   for (int j = 0; j + 2 < N; ++j) {
     const int c0 = j + 1;
-    const double pvj = pv[j], pwj = pw[j];
+    const double pv0j = pv0[j], pw0j = pw0[j], pv1j = pv1[j], pw1j = pw1[j];
     // column j below the diagonal, updated
     double part = 0.0;
     for (int i = c0 + tid; i < N; i += kEigThreads) {
-      const double x = A[static_cast<size_t>(i) * lda + j] - (pv[i] * pwj + pw[i] * pvj);
+      const double x = A[static_cast<size_t>(i) * lda + j] - (pv0[i] * pw0j + pw0[i] * pv0j) -
+                       (pv1[i] * pw1j + pw1[i] * pv1j);
       sh.v[i] = x;
       if (i > c0) part += x * x;
     }
@@ -167,7 +176,7 @@ __device__ void wg_tridiagonalize_streamed(double* A, int N, int lda, Sh& sh) {
     const double bet = refl ? 2.0 / (v0 * v0 + tail) : 0.0;
     __syncthreads();   // every thread has read x0
     if (tid == 0) {
-      sh.d[j] = A[static_cast<size_t>(j) * lda + j] - 2.0 * pvj * pwj;
+      sh.d[j] = A[static_cast<size_t>(j) * lda + j] - 2.0 * (pv0j * pw0j + pv1j * pw1j);
       sh.e[j] = refl ? alpha : x0;
       sh.beta[j] = bet;
       if (refl) sh.v[c0] = v0;
@@ -175,13 +184,14 @@ __device__ void wg_tridiagonalize_streamed(double* A, int N, int lda, Sh& sh) {
     __syncthreads();
     if (refl)
       for (int i = c0 + tid; i < N; i += kEigThreads) A[static_cast<size_t>(j) * lda + i] = sh.v[i];
-    if (!pend && !refl) continue;   // nothing to apply, nothing to multiply
+    const bool flush = npend == 2;   // this pass writes both held-back updates into A
+    if (!flush && !refl) continue;   // nothing to write, nothing to multiply
     double q[NT];
 #pragma unroll
     for (int t = 0; t < NT; ++t) q[t] = 0.0;
     for (int i = c0 + wave; i < N; i += NW) {
       double* row = A + static_cast<size_t>(i) * lda;
-      const double pvi = pv[i], pwi = pw[i];
+      const double pv0i = pv0[i], pw0i = pw0[i], pv1i = pv1[i], pw1i = pw1[i];
       const double vi = refl ? sh.v[i] : 0.0;
       double a[NT];
 #pragma unroll
@@ -195,8 +205,8 @@ __device__ void wg_tridiagonalize_streamed(double* A, int N, int lda, Sh& sh) {
         const int k = c0 + lane + kWave * t;
         if (c0 + kWave * t <= i && k <= i) {
           double x = a[t];
-          if (pend) {
-            x -= pvi * pw[k] + pwi * pv[k];
+          if (flush) {
+            x -= (pv0i * pw0[k] + pw0i * pv0[k]) + (pv1i * pw1[k] + pw1i * pv1[k]);
             row[k] = x;
           }
           if (refl) {
@@ -210,7 +220,7 @@ __device__ void wg_tridiagonalize_streamed(double* A, int N, int lda, Sh& sh) {
         if (lane == 0) sh.w[i] = acc;
       }
     }
-    __syncthreads();   // pass done: row sums in sh.w, old pv / pw no longer read
+    __syncthreads();   // pass done: row sums in sh.w
     if (refl) {
       for (int r = 0; r < NW; ++r) {
         if (wave == r) {
@@ -222,6 +232,23 @@ __device__ void wg_tridiagonalize_streamed(double* A, int N, int lda, Sh& sh) {
         }
         __syncthreads();
       }
+      if (!flush && npend > 0) {
+        // the pass read the stale block: subtract the held-back updates' product with v
+        double d00 = 0.0, d01 = 0.0, d10 = 0.0, d11 = 0.0;
+        for (int i = c0 + tid; i < N; i += kEigThreads) {
+          const double vv = sh.v[i];
+          d00 += pw0[i] * vv;
+          d01 += pv0[i] * vv;
+          d10 += pw1[i] * vv;
+          d11 += pv1[i] * vv;
+        }
+        d00 = block_sum(d00, sh.red);
+        d01 = block_sum(d01, sh.red);
+        d10 = block_sum(d10, sh.red);
+        d11 = block_sum(d11, sh.red);
+        for (int i = c0 + tid; i < N; i += kEigThreads)
+          sh.w[i] -= (pv0[i] * d00 + pw0[i] * d01) + (pv1[i] * d10 + pw1[i] * d11);
+      }
       double pp = 0.0;
       for (int i = c0 + tid; i < N; i += kEigThreads) {
         const double wi = bet * sh.w[i];
@@ -229,27 +256,41 @@ __device__ void wg_tridiagonalize_streamed(double* A, int N, int lda, Sh& sh) {
         pp += sh.v[i] * wi;
       }
       const double Kc = 0.5 * bet * block_sum(pp, sh.red);
+      // the new update goes to slot 0 after a flush (slot 1 cleared), else to slot npend
+      const int slot = flush ? 0 : npend;
+      double* nv = slot ? pv1 : pv0;
+      double* nw = slot ? pw1 : pw0;
       for (int i = c0 + tid; i < N; i += kEigThreads) {
-        pv[i] = sh.v[i];
-        pw[i] = sh.w[i] - Kc * sh.v[i];
+        nv[i] = sh.v[i];
+        nw[i] = sh.w[i] - Kc * sh.v[i];
+        if (flush) {
+          pv1[i] = 0.0;
+          pw1[i] = 0.0;
+        }
       }
+      npend = slot + 1;
     } else {
+      // a flush without a reflection: both slots are written into A
       for (int i = c0 + tid; i < N; i += kEigThreads) {
-        pv[i] = 0.0;
-        pw[i] = 0.0;
+        pv0[i] = 0.0;
+        pw0[i] = 0.0;
+        pv1[i] = 0.0;
+        pw1[i] = 0.0;
       }
+      npend = 0;
     }
-    pend = refl;
     __syncthreads();
   }
   if (tid == 0) {
     if (N >= 2) {
       const int a = N - 2, b = N - 1;
-      sh.d[a] = A[static_cast<size_t>(a) * lda + a] - 2.0 * pv[a] * pw[a];
-      sh.e[a] = A[static_cast<size_t>(b) * lda + a] - (pv[b] * pw[a] + pw[b] * pv[a]);
+      sh.d[a] = A[static_cast<size_t>(a) * lda + a] - 2.0 * (pv0[a] * pw0[a] + pv1[a] * pw1[a]);
+      sh.e[a] = A[static_cast<size_t>(b) * lda + a] - (pv0[b] * pw0[a] + pw0[b] * pv0[a]) -
+                (pv1[b] * pw1[a] + pw1[b] * pv1[a]);
       sh.beta[a] = 0.0;
     }
-    sh.d[N - 1] = A[static_cast<size_t>(N - 1) * lda + N - 1] - 2.0 * pv[N - 1] * pw[N - 1];
+    sh.d[N - 1] = A[static_cast<size_t>(N - 1) * lda + N - 1] -
+                  2.0 * (pv0[N - 1] * pw0[N - 1] + pv1[N - 1] * pw1[N - 1]);
     sh.e[N - 1] = 0.0;
     sh.beta[N - 1] = 0.0;
   }

@@ -83,11 +83,12 @@ __global__ __launch_bounds__(kEigThreads) void k_dense_eig(double* H, double* Z,
   __shared__ EigShared sh;
   __shared__ int s_perm[kEigMaxN];
   __shared__ double s_lo, s_hi;
+  __shared__ double s_pend[STREAMED ? 2 * kEigMaxN : 1];   // second held-back update of the reduction
   const int c = blockIdx.x;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   double* A = H + static_cast<size_t>(c) * N * N;
   double* Zc = Z + static_cast<size_t>(c) * N * N;
-  if (STREAMED) wg_tridiagonalize_streamed(A, N, N, sh);
+  if (STREAMED) wg_tridiagonalize_streamed(A, N, N, sh, s_pend);
   else wg_tridiagonalize(A, N, N, sh);
   if (!partial) {
     const bool ok = wg_band_qr(Zc, N, N, sh);
