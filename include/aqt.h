@@ -252,9 +252,15 @@ AQT_API aqt_status aqt_run_fixed_step(aqt_ctx* ctx, const aqt_run_params* params
  * proportional to 1 / bound: s_g solves F(s_g) = g F(1) / (n_grid - 1), F the trapezoid
  * integral of 1 / bound over the probes, inverted by linear interpolation.  Pass it to
  * aqt_set_grid before aqt_precompute.  AQT_ENUMERIC if the bound is not positive and finite
- * or the grid does not increase (use more probes). */
+ * or the grid does not increase (use more probes).
+ * aqt_bound_grid_points: the step control the paper draws from the bound (the step kept
+ * below it): *n_grid (host) = the fewest points, at least 2, whose bound-following grid keeps
+ * every step t_f (s_g - s_{g-1}) within `fraction` (> 0) of the bound, to the accuracy of
+ * the trapezoid integral: n_grid - 1 = ceil(t_f F(1) / fraction).  AQT_EINVAL if that
+ * exceeds 10^7 points or fraction is not positive and finite. */
 AQT_API aqt_status aqt_step_bound(aqt_ctx* ctx, int n_probe, double* bound);
 AQT_API aqt_status aqt_bound_grid(aqt_ctx* ctx, int n_grid, int n_probe, double* s);
+AQT_API aqt_status aqt_bound_grid_points(aqt_ctx* ctx, double fraction, int n_probe, int32_t* n_grid);
 
 /* ---- Correlated baths -----------------------------------------------------------------
  * Baths with gamma_ab(w) = C_ab gamma(w) (Sec. II eq. ME2-L with a frequency-independent

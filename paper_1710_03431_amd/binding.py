@@ -25,7 +25,7 @@ EXPORTED = ("aqt_create", "aqt_destroy", "aqt_last_error", "aqt_version", "aqt_s
             "aqt_get_dims", "aqt_run", "aqt_grad_pgs", "aqt_set_lamb_shift", "aqt_get_lamb_shift",
             "aqt_set_bath_correlation", "aqt_set_bath_terms", "aqt_set_coupling", "aqt_get_channel_count",
             "aqt_set_grid", "aqt_run_fixed_step", "aqt_run_status", "aqt_run_noalloc",
-            "aqt_step_bound", "aqt_bound_grid",
+            "aqt_step_bound", "aqt_bound_grid", "aqt_bound_grid_points",
             "aqt_batch_create", "aqt_batch_launch", "aqt_batch_tiles",
             "aqt_batch_last_error", "aqt_batch_destroy")
 BATCH_GRAPH, BATCH_AUTOTUNE = 1, 2
@@ -107,6 +107,7 @@ def load_library(path: str = LIB_PATH):
     lib.aqt_run_noalloc.argtypes = [ctx, C.POINTER(RunParams), C.POINTER(Outputs)]
     lib.aqt_step_bound.argtypes = [ctx, C.c_int, dp]
     lib.aqt_bound_grid.argtypes = [ctx, C.c_int, C.c_int, dp]
+    lib.aqt_bound_grid_points.argtypes = [ctx, C.c_double, C.c_int, ip]
     lib.aqt_get_lamb_shift.argtypes = [ctx, dp]
     lib.aqt_batch_create.argtypes = [C.POINTER(C.c_void_p), C.POINTER(C.c_void_p), C.c_int,
                                      C.POINTER(RunParams), C.POINTER(Outputs), C.c_int]
@@ -234,6 +235,13 @@ class Engine:
         out = np.zeros(int(n_grid))
         self._check(self.lib.aqt_bound_grid(self.ctx, int(n_grid), int(n_probe), _dptr(out)))
         return out
+
+    def bound_grid_points(self, fraction: float, n_probe: int = 401) -> int:
+        """Fewest grid points whose bound-following grid keeps every step within `fraction`
+        of the App. B bound (aqt_bound_grid_points)."""
+        v = C.c_int32()
+        self._check(self.lib.aqt_bound_grid_points(self.ctx, float(fraction), int(n_probe), C.byref(v)))
+        return v.value
 
     def channel_count(self) -> int:
         v = C.c_int32()

@@ -534,6 +534,19 @@ aqt_status aqt_bound_grid(aqt_ctx* ctx, int n_grid, int n_probe, double* sg) {
   return AQT_OK;
 }
 
+aqt_status aqt_bound_grid_points(aqt_ctx* ctx, double fraction, int n_probe, int32_t* n_grid) {
+  if (!ctx) return AQT_EINVAL;
+  if (!n_grid) return ctx->fail(AQT_EINVAL, "n_grid must not be null");
+  if (!(fraction > 0.0) || !std::isfinite(fraction)) return ctx->fail(AQT_EINVAL, "fraction must be positive and finite");
+  aqt_status s = bound_checks(ctx, n_probe);
+  if (s != AQT_OK) return s;
+  int M = 0;
+  s = aqt::bound_grid_points(ctx, fraction, n_probe, 1e-8, &M);
+  if (s != AQT_OK) return s;
+  *n_grid = M;
+  return AQT_OK;
+}
+
 aqt_status aqt_get_channel_count(aqt_ctx* ctx, int32_t* n_channels) {
   if (!ctx || !n_channels) return AQT_EINVAL;
   *n_channels = ctx->have_tables ? ctx->tab_nch : ctx->nch();

@@ -127,6 +127,8 @@ aqt_status precompute_tables(aqt_ctx* ctx, int n_grid, int n_levels, double deg_
 // from a scratch precompute) and the grid that equidistributes it.
 aqt_status step_bound(aqt_ctx* ctx, int n_probe, double deg_tol, std::vector<double>& bound);
 aqt_status bound_grid(aqt_ctx* ctx, int n_grid, int n_probe, double deg_tol, double* s_out);
+constexpr int kMaxBoundGridPoints = 10000000;
+aqt_status bound_grid_points(aqt_ctx* ctx, double fraction, int n_probe, double deg_tol, int* n_grid);
 
 // mcwf.hip: fixed-step unraveling.
 aqt_status launch_fixed_step(aqt_ctx* ctx, const aqt_run_params* p, int substeps, const aqt_outputs* o);

@@ -245,14 +245,39 @@ aqt_status step_bound(aqt_ctx* ctx, int P, double deg_tol, std::vector<double>& 
   return AQT_OK;
 }
 
-aqt_status bound_grid(aqt_ctx* ctx, int M, int P, double deg_tol, double* s_out) {
+// F(s_p) = int_0^{s_p} ds / bound(s) by the trapezoid rule on the probes (units 1/ns).
+static aqt_status bound_density_integral(aqt_ctx* ctx, int P, double deg_tol, std::vector<double>& sp,
+                                         std::vector<double>& F) {
   std::vector<double> bound;
   aqt_status s = step_bound(ctx, P, deg_tol, bound);
   if (s != AQT_OK) return s;
-  std::vector<double> sp(P), F(P, 0.0);
+  sp.assign(P, 0.0);
+  F.assign(P, 0.0);
   for (int p = 0; p < P; ++p) sp[p] = static_cast<double>(p) / (P - 1);
   for (int p = 1; p < P; ++p) F[p] = F[p - 1] + 0.5 * (1.0 / bound[p] + 1.0 / bound[p - 1]) * (sp[p] - sp[p - 1]);
   if (!(F[P - 1] > 0.0) || !std::isfinite(F[P - 1])) return ctx->fail(AQT_ENUMERIC, "step bound density not integrable");
+  return AQT_OK;
+}
+
+// Step control from the bound: on the bound-following grid of M points the step into
+// s_g is t_f (s_g - s_{g-1}) ~ t_f F(1) bound(s_g) / (M - 1), so every step stays within
+// `fraction` of the bound when M - 1 >= t_f F(1) / fraction.
+aqt_status bound_grid_points(aqt_ctx* ctx, double fraction, int P, double deg_tol, int* M_out) {
+  std::vector<double> sp, F;
+  aqt_status s = bound_density_integral(ctx, P, deg_tol, sp, F);
+  if (s != AQT_OK) return s;
+  const double steps = std::ceil(ctx->t_f * F[P - 1] / fraction);
+  if (!(steps <= static_cast<double>(kMaxBoundGridPoints - 1)))
+    return ctx->fail(AQT_EINVAL, "the bound asks for more than " + std::to_string(kMaxBoundGridPoints) +
+                                     " grid points at this fraction");
+  *M_out = std::max(2, static_cast<int>(steps) + 1);
+  return AQT_OK;
+}
+
+aqt_status bound_grid(aqt_ctx* ctx, int M, int P, double deg_tol, double* s_out) {
+  std::vector<double> sp, F;
+  aqt_status s = bound_density_integral(ctx, P, deg_tol, sp, F);
+  if (s != AQT_OK) return s;
   // invert F by linear interpolation (targets are non-decreasing, so one forward pass)
   int q = 0;
   for (int g = 0; g < M; ++g) {

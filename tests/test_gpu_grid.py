@@ -134,6 +134,35 @@ def test_library_step_bound_and_grid_match_the_oracle(case):
     assert eng.get_tables(("E",))["E"].shape == (inst.n_grid, inst.levels)
 
 
+@pytest.mark.parametrize("case", ["ring3", "pm1_6q"])
+@pytest.mark.parametrize("fraction", [0.37, 2.5])
+def test_library_bound_grid_points_match_the_oracle(case, fraction):
+    """aqt_bound_grid_points, the step control drawn from the App. B bound (eq. B7):
+    n_grid - 1 = ceil(t_f F(1) / fraction), F(1) the trapezoid integral of 1 / bound over
+    the probes, against the same integral of oracle.spectrum.step_bound; on the grid that
+    aqt_bound_grid returns for that count every step stays within the fraction of the
+    oracle's bound at the step's midpoint (interpolated from the probes, 2% for the
+    linear interpolations), and most steps use more than 90% of it."""
+    insts = {"ring3": W.ring_instance(3, 8, t_f=1.5, eta=0.1, n_grid=61),
+             "pm1_6q": W.pm1_all_to_all(6, 11, t_f=40.0, eta=1e-3, n_grid=61)}
+    inst = insts[case]
+    P = 121
+    from paper_1710_03431_amd.binding import Engine
+    eng = Engine(0)
+    eng.set_instance(inst)
+    M = eng.bound_grid_points(fraction, P)
+    sp = np.linspace(0.0, 1.0, P)
+    b = spectrum.step_bound(inst, sp)
+    F = float(np.sum(0.5 * (1.0 / b[1:] + 1.0 / b[:-1]) * np.diff(sp)))
+    x = inst.t_f * F / fraction
+    want = max(2, int(np.ceil(x)) + 1)
+    assert M == want or (abs(x - round(x)) < 1e-6 and abs(M - want) <= 1), (M, want, x)
+    g = eng.bound_grid(M, P)
+    ratio = inst.t_f * np.diff(g) / (fraction * np.interp(0.5 * (g[1:] + g[:-1]), sp, b))
+    assert ratio.max() <= 1.02, ratio.max()
+    assert np.median(ratio) > 0.9, np.median(ratio)
+
+
 def test_library_bound_grid_argument_errors():
     from paper_1710_03431_amd.binding import AqtError, Engine
     eng = Engine(0)
@@ -148,3 +177,8 @@ def test_library_bound_grid_argument_errors():
         eng.step_bound(2)
     with pytest.raises(AqtError):
         eng.bound_grid(1, 11)
+    for bad in (0.0, -1.0, float("inf"), float("nan")):
+        with pytest.raises(AqtError):
+            eng.bound_grid_points(bad, 11)
+    with pytest.raises(AqtError):
+        eng.bound_grid_points(1e-9, 11)              # more than 10^7 points
