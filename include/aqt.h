@@ -299,11 +299,15 @@ AQT_API aqt_status aqt_set_bath_terms(aqt_ctx* ctx, int n_terms, const double* C
 
 /* Grid points of the anneal (Sec. IV; App. B eq. B7 bounds the step and suggests
  * adapting it to the bound's instantaneous value): s[n_grid] host, s[0] = 0 <
- * s[1] < ... < s[n_grid-1] = 1.  Grid point g sits at t = t_f s_g; the step into it
- * has length t_f (s_g - s_{g-1}) and starts at t_f s_{g-1} (jump record times, the
- * no-jump propagator and the gradient's hat-function weights of the controls use
- * them).  n_grid = 0 or s = NULL restores equidistant points, s_g = g / (n_grid - 1)
- * with steps t_f / (n_grid - 1) starting at (g - 1) t_f / (n_grid - 1).  Applies from
+ * s[1] < ... < s[n_grid-1] = 1.  Grid point g sits at t = t_f s_g.  Its step (the
+ * basis change into g, then the no-jump propagator and jumps with g's tables) has
+ * length (h_g + h_{g+1}) / 2, h_g = t_f (s_g - s_{g-1}), half of each neighbouring
+ * interval, so that every interval is split symmetrically around its basis change (the
+ * last point takes (h_{n_grid-1} + h_1) / 2, so the lengths add up to t_f), and starts
+ * at t_f (s_{g-1} + s_g - s_1) / 2 (jump record times, the no-jump propagator and the
+ * gradient's hat-function weights of the controls use them).  On equidistant points
+ * this is the step t_f / (n_grid - 1) starting at (g - 1) t_f / (n_grid - 1), which is
+ * what n_grid = 0 or s = NULL restores (s_g = g / (n_grid - 1)).  Applies from
  * the next aqt_precompute or aqt_set_tables, whose n_grid must then equal this one
  * (AQT_EINVAL otherwise); loaded tables are invalidated.  AQT_EINVAL for fewer than
  * two points, ends other than 0 and 1, or points that do not increase. */

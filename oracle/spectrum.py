@@ -282,8 +282,16 @@ def table_stream(inst, n_grid: Optional[int] = None, n_levels: Optional[int] = N
         if sg is None:      # equidistant: s_g = g / (M - 1), steps of t_f / (M - 1)
             s, s_prev, t0, dtg = g / (M - 1), (g - 1) / (M - 1), (g - 1) * dt, dt
         else:
+            # The factor of grid point g (its phases and decay) acts between the basis
+            # changes into g and out of g, so it covers half of each neighbouring step:
+            # (h_g + h_{g+1}) / 2, h_g = t_f (s_g - s_{g-1}); the last point takes
+            # (h_{M-1} + h_1) / 2, the half step the first point's factor leaves out,
+            # so the lengths add up to t_f.  A symmetric splitting of each step, which
+            # on equidistant points gives h as above.
             s, s_prev = float(sg[g]), float(sg[g - 1])
-            t0, dtg = inst.t_f * s_prev, inst.t_f * (s - s_prev)
+            s_next = float(sg[g + 1]) if g < M - 1 else 1.0 + float(sg[1])
+            t0 = 0.5 * inst.t_f * (s_prev + s - float(sg[1]))
+            dtg = 0.5 * inst.t_f * (s_next - s_prev)
         need_prev = grids is not None and (g + 1) in grids
         if grids is not None and g not in grids and not need_prev:
             Vprev = None

@@ -204,7 +204,8 @@ aqt_status finish_tables(aqt_ctx* ctx) {
   const int M = ctx->M;
   const int64_t cnt = static_cast<int64_t>(M) * ctx->NP;
   // grid points and steps: s_g = g / (M - 1) with steps t_f / (M - 1) starting at (g - 1) dt,
-  // or the grid of aqt_set_grid with steps t_f (s_g - s_{g-1}) starting at t_f s_{g-1}
+  // or the grid of aqt_set_grid, where the step of grid point g has length (h_g + h_{g+1}) / 2,
+  // h_g = t_f (s_g - s_{g-1}), and starts at t_f (s_{g-1} + s_g - s_1) / 2
   if (!ctx->sgrid.empty() && static_cast<int>(ctx->sgrid.size()) != M)
     return ctx->fail(AQT_EINVAL, "the grid of aqt_set_grid has a different number of points");
   std::vector<double> sg(M), tb(M, 0.0), tl(M, 0.0);
@@ -213,8 +214,14 @@ aqt_status finish_tables(aqt_ctx* ctx) {
       sg[g] = static_cast<double>(g) / (M - 1);
       if (g > 0) tb[g] = (g - 1) * ctx->dt, tl[g] = ctx->dt;
     } else {
+      // grid point g's factor covers half of each neighbouring step (the last point also
+      // the half step the first leaves out): a symmetric splitting of every step
       sg[g] = ctx->sgrid[g];
-      if (g > 0) tb[g] = ctx->t_f * ctx->sgrid[g - 1], tl[g] = ctx->t_f * (ctx->sgrid[g] - ctx->sgrid[g - 1]);
+      if (g > 0) {
+        const double s_next = (g < M - 1) ? ctx->sgrid[g + 1] : 1.0 + ctx->sgrid[1];
+        tb[g] = 0.5 * ctx->t_f * (ctx->sgrid[g - 1] + ctx->sgrid[g] - ctx->sgrid[1]);
+        tl[g] = 0.5 * ctx->t_f * (s_next - ctx->sgrid[g - 1]);
+      }
     }
   }
   if (ctx->sgd.reserve(M * sizeof(double)) != hipSuccess || ctx->tbeg.reserve(M * sizeof(double)) != hipSuccess ||
