@@ -985,12 +985,13 @@ __device__ void run_tile(const StepArgs& a, int64_t tile, TileShared<NP, TQ, Mod
 #pragma unroll
         for (int qq = 0; qq < QG; ++qq) bnx[qq] = S[qq][lc][lane >> 4];
       }
-      // two FP32 wavefronts share each SIMD, and with equal priorities they issue so that
-      // one finishes its share early and leaves the other to run the tail of the GEMM
-      // alone (8% slower); one of each pair at a raised priority keeps both issuing to
+      // two wavefronts share each SIMD, and with equal priorities they issue so that one
+      // finishes its share early and leaves the other to run the tail of the GEMM alone
+      // (8% slower in FP32); one of each pair at a raised priority keeps both issuing to
       // the end.  Raising waves 0-3 (wave 0 starts the step late: it refreshes the Philox
-      // caches) measured 0.6% faster than raising waves 4-7.
-      if (WV == 8 && sizeof(T) == 4 && wave < 4) __builtin_amdgcn_s_setprio(1);
+      // caches) measured 0.6% faster than raising waves 4-7 in FP32, 0.7% in FP64 against
+      // equal priorities.
+      if (WV == 8 && wave < 4) __builtin_amdgcn_s_setprio(1);
       for (int kc = 0; kc < NKC; kc += PF) {
 #pragma unroll
         for (int s2 = 0; s2 < PF; ++s2) {
@@ -1094,7 +1095,7 @@ __device__ void run_tile(const StepArgs& a, int64_t tile, TileShared<NP, TQ, Mod
         }
       }
     }
-    if (WV == 8 && sizeof(T) == 4) __builtin_amdgcn_s_setprio(0);
+    if (WV == 8) __builtin_amdgcn_s_setprio(0);
     // the step tables for this step's handlers (the previous step's handlers are done)
     if constexpr (STAGED) {
 #pragma unroll
