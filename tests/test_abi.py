@@ -57,3 +57,5 @@ def test_struct_layouts_match_c(tmp_path):
 def test_null_context_is_rejected(lib):
     assert lib.aqt_set_bath(None, 1e-4, 1.0, 1.0) == -1
     assert lib.aqt_run(None, None, None) == -1
+    n = ctypes.c_int32(0)
+    assert lib.aqt_bound_grid_points(None, 1.0, 11, ctypes.byref(n)) == -1 and n.value == 0
